@@ -1,0 +1,341 @@
+"""The modified PIC step (oracle, FP64, NumPy).
+
+Fig. 1 of the paper: the analytic fields E1, B1 are added to the internally
+advanced fields E2, B2, the total field is interpolated to the particles and
+used for the particle push, and the particle current drives the internal
+field update of E2, B2 only (Eq. (4)).  The paper evaluates E1, B1 on the
+grid before interpolation; here (as in the HIP path) they are evaluated at
+the particle position, and only E2, B2 are interpolated.
+
+Grid conventions (internal units, periodic in every direction):
+* arrays are indexed [k, j, i] = (z, y, x); 2-D (x, z) grids have ny = 1 and
+  no y derivatives or y motion;
+* Yee staggering (Eqs. (7)-(9) generalised to three dimensions):
+  Ex (i+1/2, j, k), Ey (i, j+1/2, k), Ez (i, j, k+1/2),
+  Bx (i, j+1/2, k+1/2), By (i+1/2, j, k+1/2), Bz (i+1/2, j+1/2, k);
+  J components sit with the E components;
+* particle positions are in cell units relative to the grid origin, one row
+  per axis (x, y, z); the y row is unused on 2-D grids.
+
+Particle shape: quadratic B-spline ("second-order", Sec. II.B: the scaling
+runs used second-order current deposition) for both the gather and the
+charge-conserving deposition.
+"""
+import math
+
+import numpy as np
+
+from . import pulses as _pulses
+
+E_STAGGER = ((0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5))
+B_STAGGER = ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
+_AXIS_OF = {0: 2, 1: 1, 2: 0}   # lab axis -> numpy array axis
+
+
+class Grid:
+    """Internal fields E2, B2 and current J on a periodic Yee grid."""
+
+    def __init__(self, dim, n, dx, dt, x_min, t0=0.0):
+        if dim not in (2, 3):
+            raise ValueError("grid dimension must be 2 or 3")
+        self.dim = dim
+        nx, ny, nz = n
+        if dim == 2:
+            ny = 1
+        self.n = (int(nx), int(ny), int(nz))
+        self.dx = tuple(float(d) for d in dx)
+        self.dt = float(dt)
+        self.x_min = tuple(float(v) for v in x_min)
+        self.t = float(t0)
+        shape = (self.n[2], self.n[1], self.n[0])
+        self.E = [np.zeros(shape) for _ in range(3)]
+        self.B = [np.zeros(shape) for _ in range(3)]
+        self.J = [np.zeros(shape) for _ in range(3)]
+
+    def active(self, axis):
+        return not (self.dim == 2 and axis == 1)
+
+
+class Species:
+    """Macroparticles: positions (cell units), momenta u = gamma beta, weights."""
+
+    def __init__(self, q, m, pos, u, w):
+        self.q = float(q)
+        self.m = float(m)
+        self.pos = np.array(pos, dtype=float, copy=True)
+        self.u = np.array(u, dtype=float, copy=True)
+        self.w = np.array(w, dtype=float, copy=True)
+
+
+# ----------------------------------------------------------------------------
+# Particle shape
+# ----------------------------------------------------------------------------
+
+def tsc(d):
+    """Quadratic B-spline of a node at distance d (cell units)."""
+    a = np.abs(d)
+    return np.where(a <= 0.5, 0.75 - a ** 2,
+                    np.where(a <= 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+def _stencil(xc, stagger):
+    """Nodes and weights of the 3-point quadratic stencil on a staggered lattice.
+
+    A component staggered by ``stagger`` cells has nodes at integer + stagger;
+    returns the three lattice indices around the nearest node and their
+    weights (each of shape (3, N)).
+    """
+    xs = xc - stagger
+    near = np.floor(xs + 0.5)
+    offs = np.arange(-1, 2)[:, None]
+    nodes = near[None, :] + offs
+    return nodes.astype(np.int64), tsc(xs[None, :] - nodes)
+
+
+def gather(grid, pos):
+    """Interpolate E2, B2 to particle positions (quadratic shape, periodic)."""
+    out = []
+    for comps, stag in ((grid.E, E_STAGGER), (grid.B, B_STAGGER)):
+        vals = []
+        for c in range(3):
+            idx, wts = [], []
+            for ax in range(3):
+                if grid.active(ax):
+                    nodes, w = _stencil(pos[ax], stag[c][ax])
+                    idx.append(np.mod(nodes, grid.n[ax]))
+                    wts.append(w)
+                else:
+                    idx.append(np.zeros((1, pos.shape[1]), dtype=np.int64))
+                    wts.append(np.ones((1, pos.shape[1])))
+            acc = np.zeros(pos.shape[1])
+            arr = comps[c]
+            for a in range(idx[0].shape[0]):
+                for b in range(idx[1].shape[0]):
+                    for cc in range(idx[2].shape[0]):
+                        acc += (arr[idx[2][cc], idx[1][b], idx[0][a]]
+                                * wts[0][a] * wts[1][b] * wts[2][cc])
+            vals.append(acc)
+        out.append(np.stack(vals))
+    return out[0], out[1]
+
+
+def lab_positions(grid, pos, y_slice):
+    """Lab coordinates of particles; on (x, z) grids y is the pulse's slice."""
+    X = grid.x_min[0] + pos[0] * grid.dx[0]
+    Z = grid.x_min[2] + pos[2] * grid.dx[2]
+    if grid.dim == 3:
+        Y = grid.x_min[1] + pos[1] * grid.dx[1]
+    else:
+        Y = np.full_like(X, y_slice)
+    return X, Y, Z
+
+
+# ----------------------------------------------------------------------------
+# Push
+# ----------------------------------------------------------------------------
+
+def boris(u, E, B, q_over_m, dt):
+    """Relativistic Boris rotation: u^{n-1/2} -> u^{n+1/2} in fields (E, B).
+
+    Half electric kick, magnetic rotation through t = kappa B / gamma^- with
+    s = 2 t / (1 + |t|^2), half electric kick, with kappa = (q/m) dt / 2.
+    """
+    kappa = 0.5 * q_over_m * dt
+    um = u + kappa * E
+    gm = np.sqrt(1.0 + np.sum(um * um, axis=0))
+    t = kappa * B / gm
+    s = 2.0 * t / (1.0 + np.sum(t * t, axis=0))
+    uprime = um + np.cross(um, t, axis=0)
+    up = um + np.cross(uprime, s, axis=0)
+    return up + kappa * E
+
+
+def gamma_of(u):
+    return np.sqrt(1.0 + np.sum(u * u, axis=0))
+
+
+# ----------------------------------------------------------------------------
+# Charge-conserving deposition (Esirkepov, quadratic shape)
+# ----------------------------------------------------------------------------
+
+def esirkepov(grid, q, w, pos0, pos1, u_half):
+    """Add the current of particles moving pos0 -> pos1 during one step to grid.J.
+
+    The current is built so that the discrete continuity equation
+    (rho^{n+1} - rho^n)/dt + div_h J = 0 holds exactly with rho deposited by
+    the same quadratic shape at the nodes.  Per active axis a:
+        W_a = DS_a * (weighted sum of the other axes' old shape and change),
+        J_a(i + 1/2) - J_a(i - 1/2) = -q w (dx_a / dt) W_a(i);
+    a 2-D grid's out-of-plane current is q w v_y times the time-averaged
+    shape product.  Positions pos0/pos1 are unwrapped cell coordinates.
+    """
+    dt = grid.dt
+    N = pos0.shape[1]
+    win = 6
+    base, S0, DS = [], [], []
+    for ax in range(3):
+        if grid.active(ax):
+            b = np.floor(pos0[ax]).astype(np.int64) - 2
+            nodes = b[:, None] + np.arange(win)[None, :]
+            s0 = tsc(pos0[ax][:, None] - nodes)
+            s1 = tsc(pos1[ax][:, None] - nodes)
+            base.append(b)
+            S0.append(s0)
+            DS.append(s1 - s0)
+        else:
+            base.append(np.zeros(N, dtype=np.int64))
+            S0.append(np.ones((N, 1)))
+            DS.append(np.zeros((N, 1)))
+    qw = q * w
+    sx0, sy0, sz0 = S0
+    dsx, dsy, dsz = DS
+    # Broadcast to (N, wx, wy, wz)
+    X0 = sx0[:, :, None, None]; DX = dsx[:, :, None, None]
+    Y0 = sy0[:, None, :, None]; DY = dsy[:, None, :, None]
+    Z0 = sz0[:, None, None, :]; DZ = dsz[:, None, None, :]
+    Wx = DX * (Y0 * Z0 + 0.5 * DY * Z0 + 0.5 * Y0 * DZ + DY * DZ / 3.0)
+    Wy = DY * (X0 * Z0 + 0.5 * DX * Z0 + 0.5 * X0 * DZ + DX * DZ / 3.0)
+    Wz = DZ * (X0 * Y0 + 0.5 * DX * Y0 + 0.5 * X0 * DY + DX * DY / 3.0)
+    gam = gamma_of(u_half)
+    Jcomp = []
+    for ax, W in ((0, Wx), (1, Wy), (2, Wz)):
+        if grid.active(ax):
+            # cumulative sum along the axis gives J at the half nodes above each node
+            cum = np.cumsum(W, axis=1 + ax)
+            Jcomp.append(-(qw * grid.dx[ax] / dt)[:, None, None, None] * cum)
+        else:
+            v = u_half[ax] / gam
+            shape_avg = (X0 * Y0 * Z0 + 0.5 * DX * Z0 * Y0 + 0.5 * X0 * DZ * Y0
+                         + DX * DZ * Y0 / 3.0)
+            Jcomp.append((qw * v)[:, None, None, None] * shape_avg)
+    ii = (base[0][:, None, None, None] + np.arange(Jcomp[0].shape[1])[None, :, None, None])
+    jj = (base[1][:, None, None, None] + np.arange(Jcomp[0].shape[2])[None, None, :, None])
+    kk = (base[2][:, None, None, None] + np.arange(Jcomp[0].shape[3])[None, None, None, :])
+    ii = np.mod(np.broadcast_to(ii, Jcomp[0].shape), grid.n[0])
+    jj = np.mod(np.broadcast_to(jj, Jcomp[0].shape), grid.n[1])
+    kk = np.mod(np.broadcast_to(kk, Jcomp[0].shape), grid.n[2])
+    for c in range(3):
+        np.add.at(grid.J[c], (kk.ravel(), jj.ravel(), ii.ravel()), Jcomp[c].ravel())
+
+
+# ----------------------------------------------------------------------------
+# Yee update of E2, B2
+# ----------------------------------------------------------------------------
+
+def _dplus(F, grid, ax):
+    if not grid.active(ax):
+        return 0.0
+    return (np.roll(F, -1, axis=_AXIS_OF[ax]) - F) / grid.dx[ax]
+
+
+def _dminus(F, grid, ax):
+    if not grid.active(ax):
+        return 0.0
+    return (F - np.roll(F, 1, axis=_AXIS_OF[ax])) / grid.dx[ax]
+
+
+def _b_half(grid):
+    """B <- B - (dt/2) curl E  (first and third lines of Eqs. (7)-(9))."""
+    Ex, Ey, Ez = grid.E
+    h = 0.5 * grid.dt
+    cx = _dplus(Ez, grid, 1) - _dplus(Ey, grid, 2)
+    cy = _dplus(Ex, grid, 2) - _dplus(Ez, grid, 0)
+    cz = _dplus(Ey, grid, 0) - _dplus(Ex, grid, 1)
+    grid.B[0] = grid.B[0] - h * cx
+    grid.B[1] = grid.B[1] - h * cy
+    grid.B[2] = grid.B[2] - h * cz
+
+
+def _e_full(grid):
+    """E <- E + dt (curl B - J)  (second line of Eqs. (7)-(9), with Eq. (2))."""
+    Bx, By, Bz = grid.B
+    dt = grid.dt
+    cx = _dminus(Bz, grid, 1) - _dminus(By, grid, 2)
+    cy = _dminus(Bx, grid, 2) - _dminus(Bz, grid, 0)
+    cz = _dminus(By, grid, 0) - _dminus(Bx, grid, 1)
+    grid.E[0] = grid.E[0] + dt * (cx - grid.J[0])
+    grid.E[1] = grid.E[1] + dt * (cy - grid.J[1])
+    grid.E[2] = grid.E[2] + dt * (cz - grid.J[2])
+
+
+def yee_step(grid):
+    """One split Yee step of the internal fields only (Eq. (4))."""
+    _b_half(grid)
+    _e_full(grid)
+    _b_half(grid)
+
+
+# ----------------------------------------------------------------------------
+# One full step
+# ----------------------------------------------------------------------------
+
+def push_species(grid, sp, pulse, n_steps_done=None):
+    """Field evaluation and Boris push of one species at time grid.t.
+
+    Returns u^{n+1/2}; positions are not changed.
+    """
+    E2, B2 = gather(grid, sp.pos)
+    if pulse is not None:
+        X, Y, Z = lab_positions(grid, sp.pos, pulse.q_slice)
+        E1, B1 = _pulses.analytic_fields(pulse, grid.t, X, Y, Z)
+        E = E1 + E2
+        B = B1 + B2
+    else:
+        E, B = E2, B2
+    return boris(sp.u, E, B, sp.q / sp.m, grid.dt)
+
+
+def move(grid, pos, u_half):
+    """x^{n+1} = x^n + dt u^{n+1/2}/gamma^{n+1/2} (cell units, unwrapped)."""
+    gam = gamma_of(u_half)
+    new = pos.copy()
+    for ax in range(3):
+        if grid.active(ax):
+            new[ax] = pos[ax] + grid.dt * u_half[ax] / gam / grid.dx[ax]
+    return new
+
+
+def wrap(grid, pos):
+    out = pos.copy()
+    for ax in range(3):
+        if grid.active(ax):
+            out[ax] = np.mod(pos[ax], grid.n[ax])
+    return out
+
+
+def step(grid, species, pulse, field_update=True):
+    """One step of the loop of Fig. 1.
+
+    For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n; Boris push;
+    move; deposit J^{n+1/2}.  Then the Yee update of E2, B2 with J.  J holds
+    the step's current afterwards.  Returns per-species (pos_unwrapped_new,)
+    for diagnostics.
+    """
+    for c in range(3):
+        grid.J[c][...] = 0.0
+    moved = []
+    for sp in species:
+        u_half = push_species(grid, sp, pulse)
+        new = move(grid, sp.pos, u_half)
+        disp = np.abs(new - sp.pos)
+        if np.any(disp >= 1.0):
+            raise ValueError("a particle moved a full cell or more in one step")
+        esirkepov(grid, sp.q, sp.w, sp.pos, new, u_half)
+        sp.u = u_half
+        moved.append(new)
+        sp.pos = wrap(grid, new)
+    if field_update:
+        yee_step(grid)
+    grid.t += grid.dt
+    return moved
+
+
+def gridless_step(t, dt, X, u, q_over_m, pulse):
+    """Test-particle step with no grid: analytic fields only, FP64 lab positions.
+
+    X has shape (3, N) (internal units).  Returns (X^{n+1}, u^{n+1/2}).
+    """
+    E, B = _pulses.analytic_fields(pulse, t, X[0], X[1], X[2])
+    u_new = boris(u, E, B, q_over_m, dt)
+    gam = gamma_of(u_new)
+    return X + dt * u_new / gam, u_new

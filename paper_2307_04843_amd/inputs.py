@@ -1,0 +1,110 @@
+"""Seeded synthetic inputs shared by the HIP path's callers and the oracle.
+
+This module only draws random numbers and lays them out; it holds none of
+the method's arithmetic (no fields, no push, no deposition).  Both sides of
+every parity test start from the arrays produced here.  All values are
+exactly representable in FP32 so that the FP32 and FP64 paths and the oracle
+see bit-identical initial states.
+
+Random numbers come from NumPy's Philox-4x32-10 counter-based generator
+(Salmon et al. 2011), one stream per (seed, species).
+"""
+import math
+
+import numpy as np
+
+ELECTRON_REST_EV = 510998.95
+PROTON_MASS = 1836.15267343
+
+
+def _rng(seed, stream):
+    return np.random.Generator(np.random.Philox(key=int(seed) * 1000003 + int(stream)))
+
+
+def _unit_offsets(rng, n):
+    """FP32 offsets uniformly in [0, 1)."""
+    v = rng.random(n, dtype=np.float64).astype(np.float32)
+    one_minus = np.nextafter(np.float32(1.0), np.float32(0.0))
+    return np.minimum(v, one_minus)
+
+
+def density_uniform(n0):
+    return lambda x, y, z: np.full_like(x, n0)
+
+
+def density_ramp_x(n0, x_start, length):
+    """n = n0 * min(1, (x - x_start)/length) for x >= x_start, else 0 (lambda units)."""
+    return lambda x, y, z: n0 * np.clip((x - x_start) / length, 0.0, 1.0)
+
+
+def density_gauss_channel(n0, radius, y_axis, z_axis):
+    """n = n0 exp(-r_perp^2 / radius^2) about the axis (y_axis, z_axis)."""
+    return lambda x, y, z: n0 * np.exp(-((y - y_axis) ** 2 + (z - z_axis) ** 2) / radius ** 2)
+
+
+def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
+           stream=0, positions_from=None):
+    """Macroparticles filling every cell of a grid, ``ppc`` per cell.
+
+    dim 2 uses axes (x, z); dim 3 uses (x, y, z).  ``dx`` and ``x_min`` are
+    per-axis (x, y, z) in lambda units.  Returns a dict of arrays:
+        cell  int32 linear cell index (x fastest, then y, then z)
+        off   float32 (3, N) offsets in [0, 1) per axis (unused axes zero)
+        u     float32 (3, N) momenta gamma*beta, Maxwellian with temperature T
+        w     float32 (N,) weights n(x_p)/ppc in units of n_c
+    Particles are emitted cell by cell.  ``positions_from`` reuses another
+    species' cells and offsets (co-located ions).
+    """
+    nx, ny, nz = n_cells
+    if dim == 2:
+        ny = 1
+    ncell = nx * ny * nz
+    N = ncell * ppc
+    rng = _rng(seed, stream)
+    if positions_from is None:
+        cell = np.repeat(np.arange(ncell, dtype=np.int64), ppc).astype(np.int32)
+        off = np.zeros((3, N), dtype=np.float32)
+        off[0] = _unit_offsets(rng, N)
+        if dim == 3:
+            off[1] = _unit_offsets(rng, N)
+        off[2] = _unit_offsets(rng, N)
+    else:
+        cell = positions_from["cell"].copy()
+        off = positions_from["off"].copy()
+    sigma = math.sqrt(temperature_ev / (ELECTRON_REST_EV * mass))
+    u = (rng.standard_normal((3, N)) * sigma).astype(np.float32)
+    i = cell.astype(np.int64) % nx
+    j = (cell.astype(np.int64) // nx) % ny
+    k = cell.astype(np.int64) // (nx * ny)
+    xs = x_min[0] + (i + off[0].astype(np.float64)) * dx[0]
+    ys = (x_min[1] + (j + off[1].astype(np.float64)) * dx[1]) if dim == 3 else np.zeros(N)
+    zs = x_min[2] + (k + off[2].astype(np.float64)) * dx[2]
+    w = (density(xs, ys, zs) / ppc).astype(np.float32)
+    return {"cell": cell, "off": off, "u": u, "w": w}
+
+
+def beam(n, gamma0, rel_spread, sigma_perp, sigma_long, x_center, vcell, seed,
+         stream=0, direction=-1.0):
+    """Relativistic electron beam for gridless test-particle runs.
+
+    gamma ~ N(gamma0, (rel_spread*gamma0)^2), moving along x with sign
+    ``direction``, no divergence; transverse N(0, sigma_perp^2) per axis and
+    longitudinal N(x_center, sigma_long^2) (lambda units).  Positions are
+    returned as per-axis int32 virtual cells of size ``vcell`` (lambda) plus
+    FP32 offsets, origin at zero.
+    """
+    rng = _rng(seed, stream)
+    g = gamma0 * (1.0 + rel_spread * rng.standard_normal(n))
+    g = np.maximum(g, 1.0 + 1e-6)
+    ux = direction * np.sqrt(g * g - 1.0)
+    pos = np.stack([x_center + sigma_long * rng.standard_normal(n),
+                    sigma_perp * rng.standard_normal(n),
+                    sigma_perp * rng.standard_normal(n)])
+    scaled = pos / vcell
+    icell = np.floor(scaled).astype(np.int32)
+    off = (scaled - icell).astype(np.float32)
+    one_minus = np.nextafter(np.float32(1.0), np.float32(0.0))
+    off = np.minimum(off, one_minus)
+    u = np.zeros((3, n), dtype=np.float32)
+    u[0] = ux.astype(np.float32)
+    return {"icell": icell, "off": off, "u": u, "w": np.full(n, 1.0 / n, dtype=np.float32)}
