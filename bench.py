@@ -1,0 +1,216 @@
+"""Throughput of the analytic-pulse PIC hot path on one MI355X.
+
+Workload (default): 2-D (x, z) PIC, 4096 x 1024 cells at lambda/20, c dt/dx =
+0.95/sqrt(2), 16 electrons + 16 protons (m = 1836) per cell (134M particles),
+density ramping linearly 0 -> 0.05 n_c over 200 lambda, T = 1 eV; analytic
+Laguerre-Gaussian l=1 p=0 pulse, a0 = 5, w0 = 8 lambda, 30 lambda/c sin^2
+envelope, focus at the box centre, front at x = 0 at t = 0; FP32 particles and
+grid with an FP64 laser phase.  The whole 2000-step run is executed: ``--warmup``
+untimed steps, then ``--steps`` timed steps.
+
+One step = tile sort (every 8 steps) + J clear + fused gather/analytic/Boris/
+move/Esirkepov kernel + Yee update.  ``value`` = particle pushes per second
+over the timed steps, inputs resident in HBM.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+LAMBDA_DX = 0.05
+N_CELLS = (4096, 1, 1024)
+PPC = 16
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def workload_inputs(n_cells=N_CELLS, ppc=PPC, x_min=(0.0, 0.0, -25.6), seed=2):
+    from paper_2307_04843_amd import inputs
+    dx = (LAMBDA_DX,) * 3
+    dens = inputs.density_ramp_x(0.05, 0.0, 200.0)
+    e = inputs.plasma(2, n_cells, dx, x_min, ppc, dens, 1.0, 1.0, seed, stream=0)
+    p = inputs.plasma(2, n_cells, dx, x_min, ppc, dens, 1.0, inputs.PROTON_MASS, seed, stream=1,
+                      positions_from=e)
+    return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
+
+
+def workload_pulse(dt):
+    """LG l=1 p=0 pulse parameters (lambda units) for the 4096 x 1024 box."""
+    dx = LAMBDA_DX
+    c2 = (dt / dx) ** 2
+    kdx = 2 * math.pi * dx
+    vg = 1.0 - (1.0 - c2) * kdx ** 2 / 8.0          # second-order group velocity
+    x_f = N_CELLS[0] * dx / 2
+    tau = 30.0
+    return dict(a0=5.0, tau=tau, x_ref=x_f, t_ref=tau / 2 + x_f / vg, x_f=x_f, w0=8.0, y_c=0.0, z_c=0.0,
+                q_slice=0.0, d_f=3, lg_l=1, lg_p=0, pol=1, dispersion=0, dx_prop=dx, dt_prop=dt)
+
+
+def run_gpu(species, precision, steps, warmup, timing=True):
+    import torch
+    from paper_2307_04843_amd import apt
+    from paper_2307_04843_amd.sim import Simulation
+    dt = 0.95 / math.sqrt(2) * LAMBDA_DX
+    sim = Simulation(2, n=N_CELLS, dx=(LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
+                     precision=precision, species=species)
+    try:
+        sim.set_pulse("lg", **workload_pulse(dt))
+        n_part = sum(int(s["state"]["u"].shape[1]) for s in species)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        if timing:
+            apt.ap_timing_enable(sim.ctx, True)
+            apt.ap_timing_read(sim.ctx, reset=True)
+        t0 = time.perf_counter()
+        done = 0
+        chunk = 250
+        while done < steps:
+            k = min(chunk, steps - done)
+            sim.step(k)
+            done += k
+            if done < steps:
+                torch.cuda.synchronize()   # one sync per chunk: a progress line, negligible cost
+                log("%s: %d/%d steps, %.1f s" % (precision, done, steps, time.perf_counter() - t0))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = apt.ap_timing_read(sim.ctx, reset=True) if timing else None
+        d, st = sim.diag(allow_numeric=True)
+        return dict(wall=wall, n_part=n_part, timing=tm, diag=d, status=st, ncell=sim.ncell)
+    finally:
+        sim.close()
+
+
+def cpu_baseline(budget_s=20.0):
+    """The FP64 oracle on a bounded replica of the same workload (host cores).
+
+    Sample: a 64 x 64-cell periodic replica at the workload's resolution,
+    16 e + 16 p per cell (131072 particles), placed at absolute x in
+    [48, 51.2] lambda about the laser axis with the clock at step 1900, so
+    the LG pulse is present; steps until ~budget_s of CPU time.
+    """
+    import numpy as np
+    from oracle import pic, pulses, units
+    from paper_2307_04843_amd import inputs
+    L = units.LAMBDA
+    n = (64, 1, 64)
+    x_min = (48.0, 0.0, 3.2)
+    dt = 0.95 / math.sqrt(2) * LAMBDA_DX
+    dens = inputs.density_ramp_x(0.05, 0.0, 200.0)
+    e = inputs.plasma(2, n, (LAMBDA_DX,) * 3, x_min, PPC, dens, 1.0, 1.0, 6, stream=0)
+    p = inputs.plasma(2, n, (LAMBDA_DX,) * 3, x_min, PPC, dens, 1.0, inputs.PROTON_MASS, 6, stream=1,
+                      positions_from=e)
+    g = pic.Grid(2, n, (LAMBDA_DX * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=1900 * dt * L)
+    sps = []
+    for q, m, st in ((-1.0, 1.0, e), (1.0, inputs.PROTON_MASS, p)):
+        pos = np.zeros((3, st["cell"].size))
+        pos[0] = st["cell"] % n[0] + st["off"][0]
+        pos[2] = st["cell"] // n[0] + st["off"][2]
+        sps.append(pic.Species(q, m, pos, st["u"].astype(float), st["w"].astype(float)))
+    pp = workload_pulse(dt)
+    P = pulses.Pulse(dict(type="lg", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    N = sum(s.pos.shape[1] for s in sps)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        pic.step(g, sps, P)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    wall = time.perf_counter() - t0
+    return dict(value=N * steps / wall, unit="pushes/s", cores=1, kind="oracle",
+                sample="64x64-cell replica of the 4096x1024 workload at x=48-51.2 lambda, "
+                       "step 1900 clock, %d particles (16 e + 16 p per cell), %d steps, FP64 NumPy, "
+                       "single thread" % (N, steps))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1990)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    log("generating inputs")
+    species = workload_inputs()
+    log("FP32 run: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    r32 = run_gpu(species, "f32", args.steps, args.warmup)
+    tm = r32["timing"]
+    n_part = r32["n_part"]
+    value = n_part * args.steps / r32["wall"]
+    ms_push = tm.ms_push / max(1, tm.n_push)
+    # algorithmic bytes of one launch of the fused kernel: every particle read
+    # (cell 4 + offsets 8 + u 12 + w 4 = 28 B) and written (cell 4 + offsets 8
+    # + u 12 = 24 B), plus the grid share (stage E2, B2: 24 B/cell; J flush 12 B/cell)
+    bytes_launch = n_part * 52 + r32["ncell"] * 36
+    achieved = bytes_launch / (ms_push * 1e-3) / 1e9
+    log("FP32: %.3e pushes/s, push kernel %.3f ms/launch, yee %.3f ms, sort %.3f ms"
+        % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, tm.n_sort)))
+    out = {
+        "metric": "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 MI355X",
+        "value": value,
+        "unit": "pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D PIC 4096x1024 cells lambda/20, 16 e + 16 p per cell (134M), "
+                               "0->0.05 n_c ramp over 200 lambda, analytic LG l=1 p=0 a0=5 w0=8 "
+                               "tau=30, 2000-step run", "particles": n_part, "cells": r32["ncell"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push_deposit_2d", "ms_per_launch": ms_push,
+                     "bytes_per_launch": bytes_launch},
+        "kernels_ms_per_step": {"push_deposit": ms_push, "yee": tm.ms_yee / max(1, tm.n_yee),
+                                "sort": tm.ms_sort / max(1, args.steps),
+                                "other": tm.ms_other / max(1, args.steps)},
+        "numerics": {"n_nonfinite": r32["diag"].n_nonfinite, "n_fast": r32["diag"].n_fast},
+    }
+    if not args.skip_fp64:
+        log("FP64 run: %d steps" % args.fp64_steps)
+        r64 = run_gpu(species, "f64", args.fp64_steps, 0)
+        v64 = n_part * args.fp64_steps / r64["wall"]
+        out["fp64_pushes_per_s"] = v64
+        out["fp32_over_fp64"] = None
+        out["fp64_note"] = ("first %d steps of the same run in the FP64 instantiation; the FP32 "
+                            "rate over the same steps is fp32_first_steps_pushes_per_s" % args.fp64_steps)
+        r32s = run_gpu(species, "f32", args.fp64_steps, 0, timing=False)
+        v32s = n_part * args.fp64_steps / r32s["wall"]
+        out["fp32_first_steps_pushes_per_s"] = v32s
+        out["fp32_over_fp64"] = v32s / v64
+    del species
+    if not args.skip_cpu:
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,281 @@
+/*
+ * apt.h -- C ABI of the MI355X analytic-pulse particle-in-cell hot path.
+ *
+ * The method (Weichman et al., "Analytic pulse technique for computational
+ * electromagnetics", Sec. II, Eqs. (3)-(4) and Fig. 1): the electromagnetic
+ * field is split as E = E1 + E2, B = B1 + B2.  (E1, B1) is a closed-form
+ * vacuum solution -- the laser -- evaluated here at every particle; (E2, B2)
+ * is the plasma response carried on a periodic Yee grid and advanced with the
+ * physical current only.  One step = gather E2, B2 at the particles, add the
+ * analytic E1, B1, relativistic Boris push, move, charge-conserving
+ * (Esirkepov) deposition of J, Yee update of E2, B2.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Units at the API: "lambda units" -- lengths in laser wavelengths,
+ *   times in lambda/c, fields in m c omega/|e| (the paper's a0), densities
+ *   and weights in the critical density n_c, momenta u = gamma*beta.
+ * - Memory: every device buffer is owned by the caller and borrowed by the
+ *   context from ap_init until ap_destroy.  The library never allocates or
+ *   frees device memory.  Host structs are read during the call only.
+ * - Streams: all work is enqueued on the HIP stream given to ap_init (a
+ *   hipStream_t passed as void*; NULL means the null stream).  ap_step and
+ *   ap_set_pulse are asynchronous; ap_gather_diag, ap_backward and
+ *   ap_timing_read synchronise that stream.
+ * - Errors: every call returns an ap_status.  Arguments are validated
+ *   before any state changes; on error nothing is modified and
+ *   ap_last_error() returns a thread-local message.  HIP failures map to
+ *   AP_E_DEVICE with the HIP error text.  No C++ exception crosses the ABI.
+ * - One context must not be used from two threads at once.
+ */
+#ifndef APT_H
+#define APT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ap_status;
+#define AP_OK               0
+#define AP_E_ARG           -1   /* invalid argument or undersized buffer       */
+#define AP_E_STATE         -2   /* call out of order (e.g. step before pulse)  */
+#define AP_E_DEVICE        -3   /* HIP runtime error                           */
+#define AP_E_NOMEM         -4   /* host allocation failed                      */
+#define AP_E_UNSUPPORTED   -5   /* valid but not implemented combination       */
+#define AP_E_NUMERIC       -6   /* non-finite particle state or CFL violation  */
+
+#define AP_MAX_SPECIES      4
+
+/* Arithmetic type of particle and grid arrays. */
+#define AP_F32              0
+#define AP_F64              1
+
+/* Analytic pulse families (Sec. II.A Eq. (15); Sec. III.A Eqs. (20)-(23);
+ * Sec. III.C Eqs. (24)-(26)). */
+#define AP_PULSE_NONE       0
+#define AP_PULSE_PLANE      1   /* pulsed plane wave, Eqs. (15), (17)           */
+#define AP_PULSE_GAUSS      2   /* paraxial Gaussian, Eq. (21), D = d_f          */
+#define AP_PULSE_LG         3   /* Laguerre-Gaussian LG_p^l, d_f = 3             */
+#define AP_PULSE_FF         4   /* Gaussian flying focus, Sec. III.C              */
+#define AP_PULSE_GAUSS_NP   5   /* Gaussian with nonparaxial corrections          */
+
+/* Numerical dispersion constants used for E1, B1 (Sec. II.A). */
+#define AP_DISP_PAPER2      0   /* second-order forms, Eqs. (12)-(14)            */
+#define AP_DISP_EXACT       1   /* exact Yee forms, Eqs. (10)-(11)               */
+#define AP_DISP_VACUUM      2   /* v_phi = v_g = c, B0 = E0                      */
+
+/* ap_step flags */
+#define AP_STEP_CONTINUITY  0x1u  /* track max |(rho1-rho0)/dt + div J| (FP64)  */
+#define AP_STEP_NO_YEE      0x2u  /* keep E2, B2 frozen (J is still deposited)  */
+#define AP_STEP_RECORD      0x4u  /* gridless: keep adjoint checkpoints        */
+
+/* ap_gather_diag masks */
+#define AP_DIAG_PARTICLES   0x1u  /* moments, energies, proxy, NaN count       */
+#define AP_DIAG_FIELDS      0x2u  /* E2, B2 field energy                        */
+
+typedef struct ap_ctx ap_ctx;    /* opaque */
+
+/* Grid and run description.
+ *   dim        0 = gridless test particles (3-D motion, no E2/B2/J),
+ *              2 = (x, z) Cartesian grid, 3 = (x, y, z) grid.
+ *   precision  AP_F32 or AP_F64: type of every real device array.
+ *   n[3]       cells along x, y, z (n[1] ignored for dim 2; unused for 0).
+ *              The grid is periodic: a field component has n nodes per axis.
+ *   tile[3]    particle tile shape in cells (0 = default); the push kernel
+ *              stages each tile's fields plus a halo in LDS.
+ *   dx[3]      cell size per axis (lambda).  For dim 0 it is the size of
+ *              the virtual cells that hold positions as (cell, offset).
+ *   x_min[3]   grid origin (lambda).  Node i of axis a is at
+ *              x_min[a] + i*dx[a]; Yee components are staggered by half
+ *              cells (Ex at i+1/2, Ey at j+1/2, Ez at k+1/2, B dual).
+ *   t0         simulation time at step 0 (lambda/c).
+ *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
+ *              with the smallest dx (the rule stated after Eq. (14)).
+ *   sort_every steps between tile re-sorts (0 = default 8).
+ */
+typedef struct ap_grid_desc {
+    int32_t dim;
+    int32_t precision;
+    int32_t n[3];
+    int32_t tile[3];
+    double  dx[3];
+    double  x_min[3];
+    double  t0;
+    double  dt;
+    int32_t sort_every;
+    int32_t reserved;
+} ap_grid_desc;
+
+/* One particle species: charge in |e|, mass in m_e, count of macroparticles. */
+typedef struct ap_species_desc {
+    double  q;
+    double  m;
+    int64_t n;
+} ap_species_desc;
+
+/* Device arrays of one species, structure of arrays, each with n entries.
+ * A particle's position is (cell, offset): on axis a it is
+ *     x_min[a] + (i_a + off[a]) * dx[a],   0 <= off[a] < 1.
+ *   cell      dim 2/3: linear cell index i + n[0]*(j + n[1]*k) (j = 0 in 2-D)
+ *   icell[3]  dim 0: per-axis virtual cell index (may be negative)
+ *   off[3]    real offsets; dim 2 uses off[0] (x) and off[2] (z)
+ *   u[3]      real momenta gamma*beta (stored at half steps, u^{n-1/2})
+ *   w         real weight: density contribution per cell, in n_c
+ *   id        int32 particle id, carried through re-sorts
+ *   proxy     dim 0 only, optional (NULL): two reals per particle
+ *             (sum and compensation) accumulating the emission proxy.
+ * Unused pointers must be NULL. */
+typedef struct ap_particles {
+    int32_t *cell;
+    int32_t *icell[3];
+    void    *off[3];
+    void    *u[3];
+    void    *w;
+    int32_t *id;
+    void    *proxy;
+} ap_particles;
+
+/* Sizes the caller must allocate (bytes; 256-byte alignment suffices).
+ *   grid_bytes  one block holding Ex,Ey,Ez,Bx,By,Bz,Jx,Jy,Jz, each
+ *               n[0]*n[1]*n[2] reals, x fastest (0 for dim 0).
+ *   work_bytes  library workspace: sort buffers, tile tables, reductions. */
+typedef struct ap_layout {
+    size_t grid_bytes;
+    size_t work_bytes;
+    size_t real_bytes;       /* 4 or 8 */
+    int64_t n_cells;
+    int64_t n_tiles;
+} ap_layout;
+
+typedef struct ap_buffers {
+    void        *grid;       /* grid_bytes, zero-filled by ap_init          */
+    void        *work;       /* work_bytes                                   */
+    ap_particles sp[AP_MAX_SPECIES];
+} ap_buffers;
+
+/* Pulse parameters, lambda units (Sec. II.B lists the run-time set the
+ * paper used: amplitude, frequency, duration, envelope delay and the phase
+ * at a reference position).
+ *   a0           peak field of the envelope (for LG: peak over the mode)
+ *   tau          full zero-to-zero duration of the sin^2 field envelope
+ *   t_ref,x_ref  the envelope peak passes x_ref at t_ref
+ *   phi0         carrier phase at (t_ref, x_ref)
+ *   chirp        fractional linear frequency sweep across tau
+ *   x_f, w0      focal position and waist (Eqs. (21)-(23))
+ *   y_c, z_c     transverse position of the beam axis
+ *   q_slice      lab y sampled by an (x, z) grid
+ *   d_f          focusing dimensionality D of Eq. (21): 2 or 3
+ *   lg_l, lg_p   LG azimuthal and radial index
+ *   pol          0: primary E along y; 1: primary E along z
+ *   beta_f, x0_ff, t0_ff   flying focus: v_f/c, focus at x0_ff at t0_ff
+ *   dispersion   AP_DISP_*; dx_prop, dt_prop: grid spacing along x and
+ *                time step that fix v_phi, v_g, B0/E0 (0 = use the grid's)
+ *   np_order     nonparaxial order (0 or 4) for AP_PULSE_GAUSS_NP */
+typedef struct ap_pulse_params {
+    double  a0, tau, t_ref, x_ref, phi0, chirp;
+    double  x_f, w0, y_c, z_c, q_slice;
+    double  beta_f, x0_ff, t0_ff;
+    double  dx_prop, dt_prop;
+    int32_t d_f, lg_l, lg_p, pol, dispersion, np_order;
+} ap_pulse_params;
+
+/* FP64 diagnostics (reductions of the current state). */
+typedef struct ap_diag {
+    double  t;                          /* lambda/c                        */
+    int64_t step;
+    double  field_energy;               /* sum (E2^2 + B2^2)/2 * cell volume */
+    double  sum_w[AP_MAX_SPECIES];
+    double  kinetic[AP_MAX_SPECIES];    /* m sum w (gamma - 1)              */
+    double  mean_u[AP_MAX_SPECIES][3];  /* weighted means                   */
+    double  mean_u2[AP_MAX_SPECIES][3];
+    double  mean_gamma[AP_MAX_SPECIES];
+    double  proxy_sum[AP_MAX_SPECIES];  /* sum of per-particle proxies      */
+    double  continuity_max;             /* max over checked steps of
+                                           max|(rho1-rho0)/dt + div J|      */
+    double  j_max;                      /* max |J| over the same steps      */
+    int64_t n_nonfinite;                /* particles with non-finite state  */
+    int64_t n_fast;                     /* moves of >= 1 cell in one step   */
+} ap_diag;
+
+/* Accumulated device time of each kernel family since the last reset. */
+typedef struct ap_timing {
+    double  ms_push;        /* fused gather+analytic+Boris+move+deposit      */
+    double  ms_yee;         /* Yee update of E2, B2                          */
+    double  ms_sort;        /* tile count + scan + scatter                   */
+    double  ms_other;       /* J clear, diagnostics                          */
+    int64_t n_push, n_yee, n_sort, n_other;
+    int64_t pushes;         /* particle pushes covered by ms_push            */
+} ap_timing;
+
+/* Sizes of every caller-owned device buffer for this grid and species set.
+ * AP_E_ARG for an invalid description (see ap_init). */
+ap_status ap_query_layout(const ap_grid_desc *grid, const ap_species_desc *species,
+                          int32_t n_species, ap_layout *out);
+
+/* Bind caller-owned buffers and the stream; zero the grid block.
+ * The particle arrays must already hold the initial state (u at t0 - dt/2).
+ * Validation: dim in {0,2,3}; n >= 4 cells per active axis; dx > 0;
+ * dt > 0 and below the Yee limit 1/sqrt(sum 1/dx^2); 1 <= n_species <= 4;
+ * m > 0; every required pointer non-NULL.  Writes *out on success only. */
+ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species,
+                  int32_t n_species, const ap_buffers *buffers, void *hip_stream,
+                  ap_ctx **out);
+
+/* Select the analytic pulse (E1, B1).  Validates the parameters (tau > 0,
+ * w0 > 0 for focused types, d_f in {2,3}, LG needs d_f = 3, beta_f != 1,
+ * finite values) and precomputes its FP64 constants on the host.
+ * AP_PULSE_NONE removes the laser. */
+ap_status ap_set_pulse(ap_ctx *ctx, int32_t pulse_type, const ap_pulse_params *params);
+
+/* Advance n_steps time steps (asynchronous).  Requires ap_set_pulse first. */
+ap_status ap_step(ap_ctx *ctx, int64_t n_steps, uint32_t flags);
+
+/* FP64 reductions of the current state into *out (host), synchronising.
+ * Returns AP_E_NUMERIC (after filling *out) when non-finite particles or
+ * moves of a full cell were detected. */
+ap_status ap_gather_diag(ap_ctx *ctx, uint32_t what, ap_diag *out);
+
+/* Current simulation time (lambda/c) and step count. */
+ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
+
+/* Evaluate the current pulse's E1, B1 at n points, with the same device
+ * function the push uses (test and diagnostic aid; Sec. II.A Fig. 2(a)
+ * style field maps).  xyz: device, 3 arrays of n FP64 lab positions
+ * (x, then y, then z; lambda units).  E, B: device, 3 arrays of n reals
+ * each (context precision, component-major).  t in lambda/c.
+ * Asynchronous on the context stream. */
+ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, void *E, void *B);
+
+/* Gridless adjoint (dim 0): gradient of L = sum_p dL_du[p] . u_p(final)
+ * + dL_dproxy[p] proxy_p with respect to the pulse parameters listed in
+ * param_ids (AP_PARAM_*), over the steps advanced by the last ap_step
+ * call made with AP_STEP_RECORD.  dL_du: device, 3 reals per particle
+ * (component-major, 3 arrays of n); dL_dproxy may be NULL.  Writes
+ * n_params FP64 values to dL_dparams (host).  Synchronises. */
+#define AP_PARAM_A0      0
+#define AP_PARAM_W0      1
+#define AP_PARAM_XF      2
+#define AP_PARAM_BETA_F  3
+#define AP_PARAM_CHIRP   4
+ap_status ap_backward(ap_ctx *ctx, int32_t species, const void *dL_du,
+                      const void *dL_dproxy, const int32_t *param_ids,
+                      int32_t n_params, double *dL_dparams);
+
+/* Per-kernel device timing with HIP events on the context's stream. */
+ap_status ap_timing_enable(ap_ctx *ctx, int32_t enable);
+ap_status ap_timing_read(ap_ctx *ctx, ap_timing *out, int32_t reset);
+
+/* Release the context (does not free caller buffers). NULL is accepted. */
+ap_status ap_destroy(ap_ctx *ctx);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char *ap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APT_H */

@@ -111,11 +111,21 @@ def _lg_peak_norm(l_abs, p):
 
     a0 is the peak field (reading of Sec. II.A: a0 = |e|E0/(m c omega)); at
     focus |F| is (sqrt(2) r/w0)^|l| |L_p^|l|(2 r^2/w0^2)| exp(-r^2/w0^2), whose
-    maximum over r is found here on a dense grid in x = 2 r^2 / w0^2.
+    maximum over r is bracketed on a dense grid in x = 2 r^2 / w0^2 and then
+    refined by a bounded scalar minimisation.
     """
-    x = np.linspace(0.0, 60.0, 600001)
-    prof = x ** (l_abs / 2.0) * np.abs(_laguerre(p, l_abs, x)) * np.exp(-x / 2.0)
-    return 1.0 / prof.max()
+    from scipy.optimize import minimize_scalar
+
+    def prof(x):
+        return x ** (l_abs / 2.0) * np.abs(_laguerre(p, l_abs, np.asarray(x, dtype=float))) * np.exp(-x / 2.0)
+    x = np.linspace(0.0, 60.0, 60001)
+    i = int(np.argmax(prof(x)))
+    lo, hi = x[max(i - 1, 0)], x[min(i + 1, x.size - 1)]
+    if hi <= lo:
+        return 1.0 / float(prof(x[i]))
+    res = minimize_scalar(lambda v: -float(prof(v)), bounds=(lo, hi), method="bounded",
+                          options={"xatol": 1e-13})
+    return 1.0 / max(float(prof(res.x)), float(prof(x[i])))
 
 
 def _envelope(P, t, X):

@@ -1,0 +1,849 @@
+// Host runtime of the C ABI declared in include/apt.h: validation, workspace
+// layout, FP64 pulse constants, per-step kernel sequencing on the caller's
+// stream, diagnostics and per-kernel event timing.
+#include "apt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace apt;
+
+namespace {
+
+thread_local std::string g_err;
+
+ap_status fail(ap_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+const double kTwoPi = 6.283185307179586;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Normalised run description (internal units: c = omega = 1).
+struct RunShape {
+    int dim = 0, prec = 0, nsp = 0;
+    int n[3] = {1, 1, 1};
+    int tile[3] = {1, 1, 1};
+    int ntile[3] = {1, 1, 1};
+    int64_t ncell = 0, ntiles = 0;
+    double dx[3] = {0, 0, 0};
+    double x_min[3] = {0, 0, 0};
+    double dt = 0, t0 = 0;
+    int sort_every = 8;
+    int splits = 1;
+    size_t real = 4;
+    int64_t np[kMaxSpecies] = {0, 0, 0, 0};
+    double q[kMaxSpecies] = {0, 0, 0, 0};
+    double m[kMaxSpecies] = {1, 1, 1, 1};
+};
+
+struct WorkLayout {
+    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, total = 0;
+    size_t count[kMaxSpecies] = {}, start[kMaxSpecies] = {}, rank[kMaxSpecies] = {};
+    size_t alt_cell[kMaxSpecies] = {}, alt_off[kMaxSpecies][3] = {}, alt_u[kMaxSpecies][3] = {};
+    size_t alt_w[kMaxSpecies] = {}, alt_id[kMaxSpecies] = {};
+};
+
+constexpr int kDiagBlocks = 512;
+constexpr int kCounters = 8;   // n_fast, n_bad, res_max, j_max, ...
+
+bool axis_active(int dim, int ax) { return dim == 3 || (dim == 2 && ax != 1) || dim == 0; }
+
+ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t nsp, RunShape *out) {
+    if (!g) return fail(AP_E_ARG, "grid description is NULL");
+    if (!sp) return fail(AP_E_ARG, "species description is NULL");
+    if (g->dim != 0 && g->dim != 2 && g->dim != 3) return fail(AP_E_ARG, "dim must be 0, 2 or 3");
+    if (g->precision != AP_F32 && g->precision != AP_F64) return fail(AP_E_ARG, "precision must be AP_F32 or AP_F64");
+    if (nsp < 1 || nsp > kMaxSpecies) return fail(AP_E_ARG, "n_species must be 1..4");
+    RunShape s;
+    s.dim = g->dim;
+    s.prec = g->precision;
+    s.nsp = nsp;
+    s.real = g->precision == AP_F64 ? 8 : 4;
+    for (int ax = 0; ax < 3; ++ax) {
+        const bool act = axis_active(s.dim, ax);
+        if (act && !finite_pos(g->dx[ax])) return fail(AP_E_ARG, "dx must be finite and > 0 on every active axis");
+        if (!std::isfinite(g->x_min[ax])) return fail(AP_E_ARG, "x_min must be finite");
+        s.dx[ax] = act ? g->dx[ax] * kTwoPi : 1.0;
+        s.x_min[ax] = g->x_min[ax] * kTwoPi;
+        if (s.dim > 0) {
+            if (act) {
+                if (g->n[ax] < 4) return fail(AP_E_ARG, "need at least 4 cells on every active axis");
+                s.n[ax] = g->n[ax];
+            } else {
+                s.n[ax] = 1;
+            }
+        }
+    }
+    if (!std::isfinite(g->t0)) return fail(AP_E_ARG, "t0 must be finite");
+    if (!std::isfinite(g->dt) || g->dt < 0.0) return fail(AP_E_ARG, "dt must be finite and >= 0");
+    s.t0 = g->t0 * kTwoPi;
+    if (s.dim > 0) {
+        s.ncell = (int64_t)s.n[0] * s.n[1] * s.n[2];
+        if (s.ncell >= (int64_t)1 << 31) return fail(AP_E_ARG, "grid too large: cell count must be < 2^31");
+        double inv2 = 0.0, dmin = 1e300;
+        for (int ax = 0; ax < 3; ++ax)
+            if (axis_active(s.dim, ax)) { inv2 += 1.0 / (s.dx[ax] * s.dx[ax]); dmin = std::fmin(dmin, s.dx[ax]); }
+        s.dt = g->dt > 0.0 ? g->dt * kTwoPi : 0.95 / std::sqrt((double)s.dim) * dmin;
+        if (!(s.dt < 1.0 / std::sqrt(inv2))) return fail(AP_E_ARG, "dt exceeds the Yee stability limit");
+        const int def2[3] = {32, 1, 16}, def3[3] = {8, 8, 8};
+        for (int ax = 0; ax < 3; ++ax) {
+            int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : def2[ax]);
+            if (!axis_active(s.dim, ax)) t = 1;
+            if (t > s.n[ax]) t = s.n[ax];
+            if (t > 64) return fail(AP_E_ARG, "tile extent must be <= 64 cells");
+            s.tile[ax] = t;
+            s.ntile[ax] = (s.n[ax] + t - 1) / t;
+        }
+        s.ntiles = (int64_t)s.ntile[0] * s.ntile[1] * s.ntile[2];
+        // LDS of the push kernel: 9 components on the tile plus its halo
+        size_t region = 1;
+        for (int ax = 0; ax < 3; ++ax)
+            if (axis_active(s.dim, ax)) region *= (size_t)(s.tile[ax] + (s.dim == 3 ? 5 : kHaloLo + kHaloHi));
+        if (region * 9 * s.real > 160 * 1024) return fail(AP_E_ARG, "tile too large for LDS (reduce tile extents)");
+    } else {
+        if (!(g->dt > 0.0)) return fail(AP_E_ARG, "gridless runs need dt > 0");
+        s.dt = g->dt * kTwoPi;
+    }
+    if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
+    s.sort_every = g->sort_every > 0 ? g->sort_every : 8;
+    int64_t total = 0;
+    for (int i = 0; i < nsp; ++i) {
+        if (!finite_pos(sp[i].m)) return fail(AP_E_ARG, "species mass must be finite and > 0");
+        if (!std::isfinite(sp[i].q)) return fail(AP_E_ARG, "species charge must be finite");
+        if (sp[i].n < 0 || sp[i].n >= ((int64_t)1 << 31)) return fail(AP_E_ARG, "species count must be in [0, 2^31)");
+        s.np[i] = sp[i].n;
+        s.q[i] = sp[i].q;
+        s.m[i] = sp[i].m;
+        total += sp[i].n;
+    }
+    if (s.dim > 0) {
+        const double avg = (double)total / (double)s.ntiles;
+        double target = (double)total / 4096.0;
+        if (target < 512.0) target = 512.0;
+        if (target > 8192.0) target = 8192.0;
+        int sp_ = (int)std::ceil(avg / target);
+        if (sp_ < 1) sp_ = 1;
+        if (sp_ > 64) sp_ = 64;
+        s.splits = sp_;
+    }
+    *out = s;
+    return AP_OK;
+}
+
+WorkLayout make_layout(const RunShape &s) {
+    WorkLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = align_up(off, 256);
+        off = o + bytes;
+        return o;
+    };
+    L.counters = take(kCounters * 8);
+    L.sums = take((size_t)kDiagVals * 8 * (kMaxSpecies + 1));
+    L.partial = take((size_t)kDiagBlocks * kDiagVals * 8);
+    if (s.dim > 0) {
+        L.rho0 = take((size_t)s.ncell * 8);
+        L.rho1 = take((size_t)s.ncell * 8);
+        for (int i = 0; i < s.nsp; ++i) {
+            const size_t N = (size_t)s.np[i];
+            L.count[i] = take((size_t)s.ntiles * 4);
+            L.start[i] = take((size_t)(s.ntiles + 1) * 4);
+            L.rank[i] = take(N * 4);
+            L.alt_cell[i] = take(N * 4);
+            for (int c = 0; c < 3; ++c) {
+                if (axis_active(s.dim, c)) L.alt_off[i][c] = take(N * s.real);
+                L.alt_u[i][c] = take(N * s.real);
+            }
+            L.alt_w[i] = take(N * s.real);
+            L.alt_id[i] = take(N * 4);
+        }
+    }
+    L.total = align_up(off, 256);
+    return L;
+}
+
+PulseDev default_pulse() {
+    PulseDev P;
+    std::memset(&P, 0, sizeof(P));
+    P.type = PT_NONE;
+    P.tau = 1.0;
+    P.inv_tau = 1.0;
+    P.inv_vg = 1.0;
+    P.v_phi = 1.0;
+    P.b_over_e = 1.0;
+    P.k = 1.0;
+    return P;
+}
+
+struct TimedPair {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ap_ctx {
+    RunShape s;
+    WorkLayout L;
+    ap_buffers buf;
+    hipStream_t stream = nullptr;
+    PulseDev P;
+    int pulse_type = -1;
+    int64_t step = 0;
+    bool sorted_once = false;
+    bool timing = false;
+    std::vector<TimedPair> pending;
+    std::vector<hipEvent_t> pool;
+    double acc_ms[4] = {0, 0, 0, 0};
+    int64_t acc_n[4] = {0, 0, 0, 0};
+    int64_t acc_pushes = 0;
+    int64_t push_since_read = 0;
+
+    unsigned char *work() const { return static_cast<unsigned char *>(buf.work); }
+    template <typename X> X *wp(size_t off) const { return reinterpret_cast<X *>(work() + off); }
+    unsigned long long *counters() const { return wp<unsigned long long>(L.counters); }
+};
+
+namespace {
+
+hipError_t take_event(ap_ctx *c, hipEvent_t *e) {
+    if (!c->pool.empty()) {
+        *e = c->pool.back();
+        c->pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+struct Timer {
+    ap_ctx *c;
+    int kind;
+    hipEvent_t a = nullptr;
+    Timer(ap_ctx *c_, int k) : c(c_), kind(k) {
+        if (c->timing && take_event(c, &a) == hipSuccess) hipEventRecord(a, c->stream);
+    }
+    ~Timer() {
+        if (!c->timing || !a) return;
+        hipEvent_t b;
+        if (take_event(c, &b) != hipSuccess) return;
+        hipEventRecord(b, c->stream);
+        c->pending.push_back({kind, a, b});
+    }
+};
+
+ap_status hip_fail(hipError_t e, const char *where) {
+    return fail(AP_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, where)                         \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return hip_fail(_e, where); \
+    } while (0)
+
+template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags);
+template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
+
+double laguerre_host(int n, int a, double x) {
+    double l0 = 1.0, l1 = 1.0 + a - x;
+    if (n == 0) return l0;
+    for (int m = 1; m < n; ++m) {
+        const double l2 = ((2 * m + 1 + a - x) * l1 - (m + a) * l0) / (m + 1);
+        l0 = l1;
+        l1 = l2;
+    }
+    return l1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ap_last_error(void) { return g_err.c_str(); }
+
+ap_status ap_query_layout(const ap_grid_desc *grid, const ap_species_desc *species, int32_t n_species,
+                          ap_layout *out) {
+    try {
+        if (!out) return fail(AP_E_ARG, "layout output is NULL");
+        RunShape s;
+        const ap_status st = make_shape(grid, species, n_species, &s);
+        if (st != AP_OK) return st;
+        const WorkLayout L = make_layout(s);
+        out->grid_bytes = s.dim > 0 ? (size_t)9 * (size_t)s.ncell * s.real : 0;
+        out->work_bytes = L.total;
+        out->real_bytes = s.real;
+        out->n_cells = s.ncell;
+        out->n_tiles = s.ntiles;
+        return AP_OK;
+    } catch (...) {
+        return fail(AP_E_NOMEM, "host allocation failed");
+    }
+}
+
+ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int32_t n_species,
+                  const ap_buffers *buffers, void *hip_stream, ap_ctx **out) {
+    try {
+        if (!out) return fail(AP_E_ARG, "context output is NULL");
+        if (!buffers) return fail(AP_E_ARG, "buffers are NULL");
+        RunShape s;
+        const ap_status st = make_shape(grid, species, n_species, &s);
+        if (st != AP_OK) return st;
+        if (!buffers->work) return fail(AP_E_ARG, "work buffer is NULL");
+        if (s.dim > 0 && !buffers->grid) return fail(AP_E_ARG, "grid buffer is NULL");
+        for (int i = 0; i < n_species; ++i) {
+            const ap_particles &p = buffers->sp[i];
+            if (s.np[i] == 0) continue;
+            bool okp = p.u[0] && p.u[1] && p.u[2] && p.w;
+            if (s.dim == 0) {
+                okp = okp && p.icell[0] && p.icell[1] && p.icell[2] && p.off[0] && p.off[1] && p.off[2];
+            } else {
+                okp = okp && p.cell && p.off[0] && p.off[2] && p.id && (s.dim == 2 || p.off[1]);
+            }
+            if (!okp) return fail(AP_E_ARG, "species " + std::to_string(i) + ": a required particle array is NULL");
+        }
+        ap_ctx *c = new (std::nothrow) ap_ctx;
+        if (!c) return fail(AP_E_NOMEM, "context allocation failed");
+        c->s = s;
+        c->L = make_layout(s);
+        c->buf = *buffers;
+        c->stream = static_cast<hipStream_t>(hip_stream);
+        c->P = default_pulse();
+        hipError_t e = launch_fill_zero<unsigned long long>(c->counters(), kCounters, c->stream);
+        if (e == hipSuccess && s.dim > 0) {
+            if (s.prec == AP_F64)
+                e = launch_fill_zero<double>(static_cast<double *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
+            else
+                e = launch_fill_zero<float>(static_cast<float *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
+        }
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "ap_init");
+        }
+        *out = c;
+        return AP_OK;
+    } catch (...) {
+        return fail(AP_E_NOMEM, "host allocation failed");
+    }
+}
+
+ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (type < AP_PULSE_NONE || type > AP_PULSE_GAUSS_NP) return fail(AP_E_ARG, "unknown pulse type");
+    PulseDev P = default_pulse();
+    P.type = type;
+    if (type == AP_PULSE_NONE) {
+        c->P = P;
+        c->pulse_type = type;
+        return AP_OK;
+    }
+    if (!prm) return fail(AP_E_ARG, "pulse parameters are NULL");
+    const double vals[] = {prm->a0, prm->tau, prm->t_ref, prm->x_ref, prm->phi0, prm->chirp, prm->x_f,
+                           prm->w0, prm->y_c, prm->z_c, prm->q_slice, prm->beta_f, prm->x0_ff, prm->t0_ff,
+                           prm->dx_prop, prm->dt_prop};
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(AP_E_ARG, "pulse parameters must be finite");
+    if (!(prm->tau > 0.0)) return fail(AP_E_ARG, "tau must be > 0");
+    if (prm->pol != 0 && prm->pol != 1) return fail(AP_E_ARG, "pol must be 0 or 1");
+    if (prm->dispersion < AP_DISP_PAPER2 || prm->dispersion > AP_DISP_VACUUM)
+        return fail(AP_E_ARG, "unknown dispersion mode");
+    const bool focused = type != AP_PULSE_PLANE;
+    if (focused && !(prm->w0 > 0.0)) return fail(AP_E_ARG, "w0 must be > 0");
+    if (focused && prm->d_f != 2 && prm->d_f != 3) return fail(AP_E_ARG, "d_f must be 2 or 3");
+    if (type == AP_PULSE_LG) {
+        if (prm->d_f != 3) return fail(AP_E_ARG, "Laguerre-Gaussian modes need d_f = 3");
+        if (prm->lg_p < 0 || prm->lg_p > 8 || prm->lg_l < -8 || prm->lg_l > 8)
+            return fail(AP_E_ARG, "LG indices must satisfy 0 <= p <= 8, |l| <= 8");
+    }
+    if (type == AP_PULSE_FF && prm->beta_f == 1.0) return fail(AP_E_ARG, "flying focus needs beta_f != 1");
+    if (type == AP_PULSE_GAUSS_NP) return fail(AP_E_UNSUPPORTED, "nonparaxial Gaussian not available in this build");
+    const double L = kTwoPi;
+    // numerical dispersion constants (Sec. II.A, Eqs. (10)-(14)), omega = 1
+    double v_phi = 1.0, v_g = 1.0, boe = 1.0;
+    if (prm->dispersion != AP_DISP_VACUUM) {
+        const double dxp = (prm->dx_prop > 0.0 ? prm->dx_prop * L : c->s.dx[0]);
+        const double dtp = (prm->dt_prop > 0.0 ? prm->dt_prop * L : c->s.dt);
+        if (!(dxp > 0.0) || !(dtp > 0.0) || c->s.dim == 0 && !(prm->dx_prop > 0.0 && prm->dt_prop > 0.0))
+            return fail(AP_E_ARG, "grid dispersion modes need dx_prop and dt_prop");
+        const double cr = dtp / dxp;
+        if (prm->dispersion == AP_DISP_PAPER2) {
+            v_phi = 1.0 - (1.0 - cr * cr) * dxp * dxp / 24.0;
+            v_g = 1.0 - (1.0 - cr * cr) * dxp * dxp / 8.0;
+            boe = 1.0 - dtp * dtp / 8.0;
+        } else {
+            const double sarg = std::sin(0.5 * dtp) / cr;
+            if (!(sarg < 1.0)) return fail(AP_E_ARG, "no propagating Yee mode at this resolution");
+            const double kk = 2.0 / dxp * std::asin(sarg);
+            v_phi = 1.0 / kk;
+            v_g = std::cos(0.5 * kk * dxp) / std::cos(0.5 * dtp);
+            boe = std::cos(0.5 * dtp);
+        }
+    }
+    P.pol = prm->pol;
+    P.d_f = type == AP_PULSE_PLANE ? 3 : prm->d_f;
+    P.lg_l = prm->lg_l;
+    P.lg_p = prm->lg_p;
+    P.np_order = prm->np_order;
+    P.a0 = prm->a0;
+    P.tau = prm->tau * L;
+    P.inv_tau = 1.0 / P.tau;
+    P.half_tau = 0.5 * P.tau;
+    P.t_ref = prm->t_ref * L;
+    P.x_ref = prm->x_ref * L;
+    P.phi0 = prm->phi0;
+    P.b_half = 0.5 * prm->chirp / P.tau;
+    P.k = 1.0 / v_phi;
+    P.inv_vg = 1.0 / v_g;
+    P.v_phi = v_phi;
+    P.b_over_e = boe;
+    P.x_f = prm->x_f * L;
+    P.y_c = prm->y_c * L;
+    P.z_c = prm->z_c * L;
+    P.q_slice = prm->q_slice * L;
+    P.beta_f = prm->beta_f;
+    P.x0_ff = prm->x0_ff * L;
+    P.t0_ff = prm->t0_ff * L;
+    if (focused) {
+        const double w0 = prm->w0 * L;
+        P.w0 = w0;
+        P.inv_w0sq = 1.0 / (w0 * w0);
+        P.x_r = P.k * w0 * w0 / 2.0;
+        double xr = P.x_r;
+        if (type == AP_PULSE_FF) xr *= (1.0 - prm->beta_f);
+        P.inv_xr = 1.0 / xr;
+        P.eps = w0 / P.x_r;
+    }
+    if (type == AP_PULSE_LG) {
+        const int la = prm->lg_l < 0 ? -prm->lg_l : prm->lg_l;
+        // normalise the peak |U| at focus to one (a0 is the peak field)
+        double norm;
+        if (prm->lg_p == 0) {
+            norm = la == 0 ? 1.0 : std::pow(std::exp(1.0) / la, 0.5 * la);
+        } else {
+            auto prof = [&](double x) {
+                return std::pow(x, 0.5 * la) * std::fabs(laguerre_host(prm->lg_p, la, x)) * std::exp(-0.5 * x);
+            };
+            // bracket the maximum on a grid, then golden-section refinement
+            const int ng = 60000;
+            int ib = 0;
+            double best = -1.0;
+            for (int m = 0; m <= ng; ++m) {
+                const double v = prof(60.0 * m / ng);
+                if (v > best) { best = v; ib = m; }
+            }
+            double lo = 60.0 * (ib > 0 ? ib - 1 : 0) / ng, hi = 60.0 * (ib < ng ? ib + 1 : ng) / ng;
+            const double gr = 0.6180339887498949;
+            double x1 = hi - gr * (hi - lo), x2 = lo + gr * (hi - lo);
+            double f1 = prof(x1), f2 = prof(x2);
+            for (int it = 0; it < 200 && hi - lo > 1e-14; ++it) {
+                if (f1 < f2) { lo = x1; x1 = x2; f1 = f2; x2 = lo + gr * (hi - lo); f2 = prof(x2); }
+                else { hi = x2; x2 = x1; f2 = f1; x1 = hi - gr * (hi - lo); f1 = prof(x1); }
+            }
+            double mx = std::fmax(best, prof(0.5 * (lo + hi)));
+            norm = 1.0 / mx;
+        }
+        P.lg_pref = norm * std::pow(std::sqrt(2.0) / P.w0, (double)la);
+    }
+    c->P = P;
+    c->pulse_type = type;
+    return AP_OK;
+}
+
+ap_status ap_step(ap_ctx *c, int64_t n_steps, uint32_t flags) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (n_steps < 0) return fail(AP_E_ARG, "n_steps must be >= 0");
+    if (c->pulse_type < 0) return fail(AP_E_STATE, "ap_set_pulse must be called before ap_step");
+    if (flags & ~(AP_STEP_CONTINUITY | AP_STEP_NO_YEE | AP_STEP_RECORD)) return fail(AP_E_ARG, "unknown step flag");
+    if (c->s.dim == 0 && (flags & (AP_STEP_CONTINUITY | AP_STEP_NO_YEE)))
+        return fail(AP_E_ARG, "grid flags on a gridless run");
+    if (c->s.dim > 0 && (flags & AP_STEP_RECORD)) return fail(AP_E_UNSUPPORTED, "adjoint recording needs dim 0");
+    if (flags & AP_STEP_RECORD) return fail(AP_E_UNSUPPORTED, "adjoint recording not available in this build");
+    try {
+        for (int64_t k = 0; k < n_steps; ++k) {
+            ap_status st;
+            if (c->s.dim == 0)
+                st = c->s.prec == AP_F64 ? step_gridless<double>(c, flags) : step_gridless<float>(c, flags);
+            else
+                st = c->s.prec == AP_F64 ? step_gridded<double>(c, flags) : step_gridded<float>(c, flags);
+            if (st != AP_OK) return st;
+            c->step++;
+        }
+    } catch (...) {
+        return fail(AP_E_NOMEM, "host allocation failed");
+    }
+    return AP_OK;
+}
+
+ap_status ap_get_time(const ap_ctx *c, double *t, int64_t *step) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (t) *t = (c->s.t0 + (double)c->step * c->s.dt) / kTwoPi;
+    if (step) *step = c->step;
+    return AP_OK;
+}
+
+ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (!out) return fail(AP_E_ARG, "diag output is NULL");
+    if (what & ~(AP_DIAG_PARTICLES | AP_DIAG_FIELDS)) return fail(AP_E_ARG, "unknown diag mask");
+    ap_diag d;
+    std::memset(&d, 0, sizeof(d));
+    const RunShape &s = c->s;
+    double *sums = c->wp<double>(c->L.sums);
+    double *partial = c->wp<double>(c->L.partial);
+    double host[(kMaxSpecies + 1) * kDiagVals];
+    std::memset(host, 0, sizeof(host));
+    {
+        Timer tm(c, 3);
+        if (what & AP_DIAG_PARTICLES) {
+            for (int i = 0; i < s.nsp; ++i) {
+                const ap_particles &p = c->buf.sp[i];
+                hipError_t e;
+                if (s.prec == AP_F64) {
+                    DiagArgs<double> a{};
+                    for (int k = 0; k < 3; ++k) { a.u[k] = (const double *)p.u[k]; a.off[k] = (const double *)(axis_active(s.dim, k) ? p.off[k] : nullptr); }
+                    a.w = (const double *)p.w; a.proxy = (const double *)p.proxy; a.n = (int)s.np[i]; a.dim = s.dim;
+                    a.partial = partial; a.blocks = kDiagBlocks;
+                    e = launch_diag_particles<double>(a, c->stream);
+                } else {
+                    DiagArgs<float> a{};
+                    for (int k = 0; k < 3; ++k) { a.u[k] = (const float *)p.u[k]; a.off[k] = (const float *)(axis_active(s.dim, k) ? p.off[k] : nullptr); }
+                    a.w = (const float *)p.w; a.proxy = (const float *)p.proxy; a.n = (int)s.np[i]; a.dim = s.dim;
+                    a.partial = partial; a.blocks = kDiagBlocks;
+                    e = launch_diag_particles<float>(a, c->stream);
+                }
+                if (e != hipSuccess) return hip_fail(e, "ap_gather_diag");
+                HIPCHK(launch_sum_partials(partial, kDiagBlocks, kDiagVals, sums + (size_t)i * kDiagVals, c->stream), "ap_gather_diag");
+            }
+        }
+        if ((what & AP_DIAG_FIELDS) && s.dim > 0) {
+            hipError_t e;
+            if (s.prec == AP_F64) {
+                double *F[6];
+                for (int k = 0; k < 6; ++k) F[k] = static_cast<double *>(c->buf.grid) + (size_t)k * s.ncell;
+                e = launch_diag_fields<double>(F, (size_t)s.ncell, partial, kDiagBlocks, c->stream);
+            } else {
+                float *F[6];
+                for (int k = 0; k < 6; ++k) F[k] = static_cast<float *>(c->buf.grid) + (size_t)k * s.ncell;
+                e = launch_diag_fields<float>(F, (size_t)s.ncell, partial, kDiagBlocks, c->stream);
+            }
+            if (e != hipSuccess) return hip_fail(e, "ap_gather_diag");
+            HIPCHK(launch_sum_partials(partial, kDiagBlocks, 1, sums + (size_t)kMaxSpecies * kDiagVals, c->stream), "ap_gather_diag");
+        }
+    }
+    unsigned long long cnt[kCounters];
+    HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, c->stream), "ap_gather_diag");
+    HIPCHK(hipMemcpyAsync(cnt, c->counters(), sizeof(cnt), hipMemcpyDeviceToHost, c->stream), "ap_gather_diag");
+    HIPCHK(hipStreamSynchronize(c->stream), "ap_gather_diag");
+    d.t = (s.t0 + (double)c->step * s.dt) / kTwoPi;
+    d.step = c->step;
+    int64_t nonfinite = (int64_t)cnt[1];
+    if (what & AP_DIAG_PARTICLES) {
+        for (int i = 0; i < s.nsp; ++i) {
+            const double *v = host + (size_t)i * kDiagVals;
+            const double sw = v[0];
+            d.sum_w[i] = sw;
+            const double inv = sw != 0.0 ? 1.0 / sw : 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d.mean_u[i][k] = v[1 + k] * inv;
+                d.mean_u2[i][k] = v[4 + k] * inv;
+            }
+            d.mean_gamma[i] = v[7] * inv;
+            d.kinetic[i] = c->s.np[i] > 0 ? v[8] * 1.0 : 0.0;
+            d.proxy_sum[i] = v[9];
+            nonfinite += (int64_t)v[10];
+        }
+    }
+    if ((what & AP_DIAG_FIELDS) && s.dim > 0) {
+        double vol = s.dx[0] * s.dx[2] * (s.dim == 3 ? s.dx[1] : 1.0);
+        d.field_energy = 0.5 * host[(size_t)kMaxSpecies * kDiagVals] * vol;
+    }
+    double rmax, jmax;
+    std::memcpy(&rmax, &cnt[2], 8);
+    std::memcpy(&jmax, &cnt[3], 8);
+    d.continuity_max = rmax;
+    d.j_max = jmax;
+    d.n_nonfinite = nonfinite;
+    d.n_fast = (int64_t)cnt[0];
+    *out = d;
+    if (d.n_nonfinite > 0 || d.n_fast > 0)
+        return fail(AP_E_NUMERIC, "non-finite particle state or a move of a full cell detected");
+    return AP_OK;
+}
+
+ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void *E, void *B) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (n < 0 || n >= ((int64_t)1 << 31)) return fail(AP_E_ARG, "n must be in [0, 2^31)");
+    if (!std::isfinite(t)) return fail(AP_E_ARG, "t must be finite");
+    if (n > 0 && (!xyz || !E || !B)) return fail(AP_E_ARG, "NULL buffer");
+    if (c->pulse_type < 0) return fail(AP_E_STATE, "ap_set_pulse must be called before ap_eval_pulse");
+    hipError_t e;
+    // positions arrive in lambda units; the device function works in internal units
+    if (n == 0) return AP_OK;
+    if (c->s.prec == AP_F64)
+        e = launch_eval_pulse<double>(c->P.type, c->P, n, xyz, t * kTwoPi, static_cast<double *>(E),
+                                      static_cast<double *>(B), c->stream);
+    else
+        e = launch_eval_pulse<float>(c->P.type, c->P, n, xyz, t * kTwoPi, static_cast<float *>(E),
+                                     static_cast<float *>(B), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "ap_eval_pulse");
+    return AP_OK;
+}
+
+ap_status ap_backward(ap_ctx *c, int32_t, const void *, const void *, const int32_t *, int32_t, double *) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
+}
+
+ap_status ap_timing_enable(ap_ctx *c, int32_t enable) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    c->timing = enable != 0;
+    return AP_OK;
+}
+
+ap_status ap_timing_read(ap_ctx *c, ap_timing *out, int32_t reset) {
+    if (!c || !out) return fail(AP_E_ARG, "NULL argument");
+    HIPCHK(hipStreamSynchronize(c->stream), "ap_timing_read");
+    for (const TimedPair &tp : c->pending) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, tp.a, tp.b), "ap_timing_read");
+        c->acc_ms[tp.kind] += ms;
+        c->acc_n[tp.kind] += 1;
+        c->pool.push_back(tp.a);
+        c->pool.push_back(tp.b);
+    }
+    c->pending.clear();
+    c->acc_pushes += c->push_since_read;
+    c->push_since_read = 0;
+    out->ms_push = c->acc_ms[0];
+    out->ms_yee = c->acc_ms[1];
+    out->ms_sort = c->acc_ms[2];
+    out->ms_other = c->acc_ms[3];
+    out->n_push = c->acc_n[0];
+    out->n_yee = c->acc_n[1];
+    out->n_sort = c->acc_n[2];
+    out->n_other = c->acc_n[3];
+    out->pushes = c->acc_pushes;
+    if (reset) {
+        for (int k = 0; k < 4; ++k) { c->acc_ms[k] = 0; c->acc_n[k] = 0; }
+        c->acc_pushes = 0;
+    }
+    return AP_OK;
+}
+
+ap_status ap_destroy(ap_ctx *c) {
+    if (!c) return AP_OK;
+    if (c->stream || true) hipStreamSynchronize(c->stream);
+    for (const TimedPair &tp : c->pending) { hipEventDestroy(tp.a); hipEventDestroy(tp.b); }
+    for (hipEvent_t e : c->pool) hipEventDestroy(e);
+    delete c;
+    return AP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t) {
+    const RunShape &s = c->s;
+    Timer tm(c, 0);
+    for (int i = 0; i < s.nsp; ++i) {
+        if (s.np[i] == 0) continue;
+        const ap_particles &p = c->buf.sp[i];
+        GridlessArgs<T> a{};
+        for (int k = 0; k < 3; ++k) {
+            a.icell[k] = p.icell[k];
+            a.off[k] = static_cast<T *>(p.off[k]);
+            a.u[k] = static_cast<T *>(p.u[k]);
+            a.dx[k] = s.dx[k];
+            a.x_min[k] = s.x_min[k];
+        }
+        a.proxy = static_cast<T *>(p.proxy);
+        a.n = (int)s.np[i];
+        a.q_over_m = s.q[i] / s.m[i];
+        a.dt = s.dt;
+        a.t = s.t0 + (double)c->step * s.dt;
+        a.n_bad = c->counters() + 1;
+        a.P = c->P;
+        HIPCHK(launch_gridless<T>(c->P.type, a, c->stream), "gridless push");
+        c->push_since_read += s.np[i];
+    }
+    return AP_OK;
+}
+
+template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
+    const RunShape &s = c->s;
+    const WorkLayout &L = c->L;
+    T *grid = static_cast<T *>(c->buf.grid);
+    const size_t nc = (size_t)s.ncell;
+    T *F[9];
+    for (int k = 0; k < 9; ++k) F[k] = grid + (size_t)k * nc;
+    const FastDiv fnx((uint32_t)s.n[0]);
+    const FastDiv fnxy((uint32_t)(s.n[0] * s.n[1]));
+    const bool do_sort = !c->sorted_once || (c->step % s.sort_every) == 0;
+    bool from_alt = false;
+    if (do_sort) {
+        Timer tm(c, 2);
+        for (int i = 0; i < s.nsp; ++i) {
+            const ap_particles &p = c->buf.sp[i];
+            int32_t *count = c->wp<int32_t>(L.count[i]);
+            int32_t *start = c->wp<int32_t>(L.start[i]);
+            int32_t *rank = c->wp<int32_t>(L.rank[i]);
+            HIPCHK(launch_fill_zero<int32_t>(count, (size_t)s.ntiles, c->stream), "sort");
+            SortArgs sa{};
+            sa.cell = p.cell;
+            sa.ncell = (uint32_t)s.ncell;
+            sa.n = (int)s.np[i];
+            sa.dim = s.dim;
+            sa.fnx = fnx;
+            sa.fnxy = fnxy;
+            sa.ftx = FastDiv((uint32_t)s.tile[0]);
+            sa.fty = FastDiv((uint32_t)s.tile[1]);
+            sa.ftz = FastDiv((uint32_t)s.tile[2]);
+            for (int k = 0; k < 3; ++k) sa.ntile[k] = s.ntile[k];
+            sa.count = count;
+            sa.rank = rank;
+            if (s.np[i] > 0) HIPCHK(launch_tile_count(sa, c->stream), "tile count");
+            HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->stream), "tile scan");
+            ScatterArgs<T> sc{};
+            sc.cell_src = p.cell;
+            sc.cell_dst = c->wp<int32_t>(L.alt_cell[i]);
+            for (int k = 0; k < 3; ++k) {
+                const bool act = axis_active(s.dim, k);
+                sc.off_src[k] = act ? static_cast<const T *>(p.off[k]) : nullptr;
+                sc.off_dst[k] = act ? c->wp<T>(L.alt_off[i][k]) : nullptr;
+                sc.u_src[k] = static_cast<const T *>(p.u[k]);
+                sc.u_dst[k] = c->wp<T>(L.alt_u[i][k]);
+            }
+            sc.w_src = static_cast<const T *>(p.w);
+            sc.w_dst = c->wp<T>(L.alt_w[i]);
+            sc.id_src = p.id;
+            sc.id_dst = c->wp<int32_t>(L.alt_id[i]);
+            sc.rank = rank;
+            sc.start = start;
+            sc.ncell = (uint32_t)s.ncell;
+            sc.n = (int)s.np[i];
+            sc.dim = s.dim;
+            sc.fnx = fnx;
+            sc.fnxy = fnxy;
+            sc.ftx = sa.ftx;
+            sc.fty = sa.fty;
+            sc.ftz = sa.ftz;
+            for (int k = 0; k < 3; ++k) sc.ntile[k] = s.ntile[k];
+            HIPCHK(launch_scatter<T>(sc, c->stream), "tile scatter");
+        }
+        c->sorted_once = true;
+        from_alt = true;
+    }
+    PushArgs<T> a{};
+    a.nsp = s.nsp;
+    for (int i = 0; i < s.nsp; ++i) {
+        const ap_particles &p = c->buf.sp[i];
+        SpeciesIO<T> &io = a.sp[i];
+        for (int k = 0; k < 3; ++k) {
+            const bool act = axis_active(s.dim, k);
+            io.off_out[k] = act ? static_cast<T *>(p.off[k]) : nullptr;
+            io.u_out[k] = static_cast<T *>(p.u[k]);
+            io.off_in[k] = from_alt ? (act ? c->wp<T>(L.alt_off[i][k]) : nullptr) : io.off_out[k];
+            io.u_in[k] = from_alt ? c->wp<T>(L.alt_u[i][k]) : io.u_out[k];
+        }
+        io.cell_out = p.cell;
+        io.w_out = static_cast<T *>(p.w);
+        io.id_out = p.id;
+        io.cell_in = from_alt ? c->wp<int32_t>(L.alt_cell[i]) : p.cell;
+        io.w_in = from_alt ? c->wp<T>(L.alt_w[i]) : io.w_out;
+        io.id_in = from_alt ? c->wp<int32_t>(L.alt_id[i]) : p.id;
+        io.copy_static = from_alt ? 1 : 0;
+        io.tile_start = c->wp<int32_t>(L.start[i]);
+        io.n = (int)s.np[i];
+        io.q_over_m = s.q[i] / s.m[i];
+        io.q = s.q[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        a.E[k] = F[k];
+        a.B[k] = F[3 + k];
+        a.J[k] = F[6 + k];
+        a.n[k] = s.n[k];
+        a.tile[k] = s.tile[k];
+        a.ntile[k] = s.ntile[k];
+        a.dx[k] = s.dx[k];
+        a.x_min[k] = s.x_min[k];
+        a.reg[k] = axis_active(s.dim, k) ? s.tile[k] + kHaloLo + kHaloHi : 1;
+    }
+    a.fnx = fnx;
+    a.fnxy = fnxy;
+    a.fntx = FastDiv((uint32_t)s.ntile[0]);
+    a.fntxy = FastDiv((uint32_t)(s.ntile[0] * s.ntile[1]));
+    a.splits = s.splits;
+    a.n_logical = (int32_t)(s.ntiles * s.splits);
+    a.dt = s.dt;
+    a.t = s.t0 + (double)c->step * s.dt;
+    a.n_fast = c->counters() + 0;
+    a.n_bad = c->counters() + 1;
+    a.P = c->P;
+
+    {
+        Timer tm(c, 3);
+        HIPCHK(launch_fill_zero<T>(F[6], 3 * nc, c->stream), "clear J");
+    }
+    double *rho0 = c->wp<double>(L.rho0), *rho1 = c->wp<double>(L.rho1);
+    auto deposit_rho = [&](double *rho, bool use_in) -> ap_status {
+        HIPCHK(launch_fill_zero<double>(rho, nc, c->stream), "rho");
+        for (int i = 0; i < s.nsp; ++i) {
+            RhoArgs<T> ra{};
+            ra.cell = use_in ? a.sp[i].cell_in : a.sp[i].cell_out;
+            for (int k = 0; k < 3; ++k) ra.off[k] = use_in ? a.sp[i].off_in[k] : a.sp[i].off_out[k];
+            ra.w = use_in ? a.sp[i].w_in : a.sp[i].w_out;
+            ra.n = (int)s.np[i];
+            ra.q = s.q[i];
+            for (int k = 0; k < 3; ++k) ra.nn[k] = s.n[k];
+            ra.fnx = fnx;
+            ra.fnxy = fnxy;
+            ra.dim = s.dim;
+            ra.rho = rho;
+            HIPCHK(launch_rho<T>(ra, c->stream), "rho");
+        }
+        return AP_OK;
+    };
+    if (flags & AP_STEP_CONTINUITY) {
+        Timer tm(c, 3);
+        const ap_status st = deposit_rho(rho0, true);
+        if (st != AP_OK) return st;
+    }
+    {
+        Timer tm(c, 0);
+        hipError_t e = s.dim == 2 ? launch_push_deposit_2d<T>(c->P.type, a, 256, c->stream)
+                                  : launch_push_deposit_3d<T>(c->P.type, a, 256, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "push/deposit");
+        for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
+    }
+    if (flags & AP_STEP_CONTINUITY) {
+        Timer tm(c, 3);
+        const ap_status st = deposit_rho(rho1, false);
+        if (st != AP_OK) return st;
+        T *J[3] = {F[6], F[7], F[8]};
+        HIPCHK(launch_continuity<T>(s.dim, s.n, s.dx, s.dt, rho0, rho1, J, c->counters() + 2, c->counters() + 3,
+                                    c->stream), "continuity");
+    }
+    {
+        Timer tm(c, 1);
+        YeeArgsBase yb;
+        for (int k = 0; k < 3; ++k) { yb.n[k] = s.n[k]; yb.dx[k] = s.dx[k]; }
+        yb.dt = s.dt;
+        HIPCHK(launch_yee<T>(s.dim, F, yb, (flags & AP_STEP_NO_YEE) ? 1 : 0, c->stream), "yee");
+    }
+    return AP_OK;
+}
+
+}  // namespace

@@ -1,0 +1,444 @@
+// Grid-side kernels: Yee update of E2, B2 only, J clear, tile sort,
+// FP64 diagnostics (moments, energies, charge density, continuity residual).
+#include "kernels.h"
+
+namespace apt {
+
+// ---------------------------------------------------------------------------
+// Yee update (Sec. II.A, Eqs. (7)-(9) generalised to 2-D/3-D; Eq. (4): the
+// update acts on the internal fields only, driven by the particle current).
+// Split step: B <- B - (dt/2) curl E; E <- E + dt (curl B - J); B <- B - (dt/2) curl E.
+// Component order in F: Ex Ey Ez Bx By Bz Jx Jy Jz, each nx*ny*nz, x fastest.
+// ---------------------------------------------------------------------------
+struct YeeIdx {
+    int nx, ny, nz;
+    FastDiv fnx, fny;
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_yee_b(T *__restrict__ Ex, T *__restrict__ Ey, T *__restrict__ Ez,
+                                              T *__restrict__ Bx, T *__restrict__ By, T *__restrict__ Bz,
+                                              YeeIdx g, T hx, T hy, T hz, size_t ncell) {
+    // hx = (dt/2)/dx etc.
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t row = g.fnx.div(cc);
+        const int i = (int)(cc - row * g.nx);
+        const int ip = (i + 1 == g.nx) ? -(g.nx - 1) : 1;
+        int j = 0, k, jp = 0;
+        if (DIM == 3) {
+            const uint32_t kk = g.fny.div(row);
+            j = (int)(row - kk * g.ny);
+            k = (int)kk;
+            jp = (j + 1 == g.ny) ? -(g.ny - 1) * g.nx : g.nx;
+        } else {
+            k = (int)row;
+        }
+        const long slab = (long)g.nx * g.ny;
+        const long kp = (k + 1 == g.nz) ? -(long)(g.nz - 1) * slab : slab;
+        const T ex = Ex[c], ey = Ey[c], ez = Ez[c];
+        // curl E at the B locations (forward differences)
+        T cx = -(Ey[c + kp] - ey) * hz;
+        T cy = (Ex[c + kp] - ex) * hz - (Ez[c + ip] - ez) * hx;
+        T cz = (Ey[c + ip] - ey) * hx;
+        if (DIM == 3) {
+            cx += (Ez[c + jp] - ez) * hy;
+            cz -= (Ex[c + jp] - ex) * hy;
+        }
+        Bx[c] -= cx;
+        By[c] -= cy;
+        Bz[c] -= cz;
+        (void)j;
+    }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_yee_e(T *__restrict__ Ex, T *__restrict__ Ey, T *__restrict__ Ez,
+                                              const T *__restrict__ Bx, const T *__restrict__ By,
+                                              const T *__restrict__ Bz, const T *__restrict__ Jx,
+                                              const T *__restrict__ Jy, const T *__restrict__ Jz,
+                                              YeeIdx g, T cx_, T cy_, T cz_, T dt, size_t ncell) {
+    // c*_ = dt/dx etc.
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t row = g.fnx.div(cc);
+        const int i = (int)(cc - row * g.nx);
+        const int im = (i == 0) ? (g.nx - 1) : -1;
+        int k, jm = 0;
+        if (DIM == 3) {
+            const uint32_t kk = g.fny.div(row);
+            const int j = (int)(row - kk * g.ny);
+            k = (int)kk;
+            jm = (j == 0) ? (g.ny - 1) * g.nx : -g.nx;
+        } else {
+            k = (int)row;
+        }
+        const long slab = (long)g.nx * g.ny;
+        const long km = (k == 0) ? (long)(g.nz - 1) * slab : -slab;
+        const T bx = Bx[c], by = By[c], bz = Bz[c];
+        // curl B at the E locations (backward differences)
+        T qx = -(by - By[c + km]) * cz_;
+        T qy = (bx - Bx[c + km]) * cz_ - (bz - Bz[c + im]) * cx_;
+        T qz = (by - By[c + im]) * cx_;
+        if (DIM == 3) {
+            qx += (bz - Bz[c + jm]) * cy_;
+            qz -= (bx - Bx[c + jm]) * cy_;
+        }
+        Ex[c] += qx - dt * Jx[c];
+        Ey[c] += qy - dt * Jy[c];
+        Ez[c] += qz - dt * Jz[c];
+    }
+}
+
+static int grid_blocks(size_t n) {
+    size_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    return (int)(b == 0 ? 1 : b);
+}
+
+template <typename T>
+hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, hipStream_t s) {
+    if (no_yee) return hipSuccess;
+    YeeIdx g;
+    g.nx = a.n[0];
+    g.ny = dim == 3 ? a.n[1] : 1;
+    g.nz = a.n[2];
+    g.fnx = FastDiv((uint32_t)g.nx);
+    g.fny = FastDiv((uint32_t)g.ny);
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    const int blocks = grid_blocks(ncell);
+    const T hx = T(0.5 * a.dt / a.dx[0]), hy = T(0.5 * a.dt / a.dx[1]), hz = T(0.5 * a.dt / a.dx[2]);
+    const T cx = T(a.dt / a.dx[0]), cy = T(a.dt / a.dx[1]), cz = T(a.dt / a.dx[2]);
+    if (dim == 3) {
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+        hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell);
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+    } else {
+        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+        hipLaunchKernelGGL((k_yee_e<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell);
+        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_yee<float>(int, float *const[9], const YeeArgsBase &, int, hipStream_t);
+template hipError_t launch_yee<double>(int, double *const[9], const YeeArgsBase &, int, hipStream_t);
+
+template <typename T> __global__ void k_fill_zero(T *p, size_t n) {
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+        p[c] = T(0);
+}
+template <typename T> hipError_t launch_fill_zero(T *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_zero<T>), dim3(grid_blocks(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+template hipError_t launch_fill_zero<float>(float *, size_t, hipStream_t);
+template hipError_t launch_fill_zero<double>(double *, size_t, hipStream_t);
+template hipError_t launch_fill_zero<int32_t>(int32_t *, size_t, hipStream_t);
+template hipError_t launch_fill_zero<unsigned long long>(unsigned long long *, size_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Tile sort: counting sort of particles by tile id (rank from a wave-
+// aggregated atomic, exclusive scan of the counts, scatter).
+// ---------------------------------------------------------------------------
+AP_D int tile_of(int cell, int dim, const FastDiv &fnx, const FastDiv &fnxy, const FastDiv &ftx,
+                 const FastDiv &fty, const FastDiv &ftz, const int32_t *ntile) {
+    const uint32_t c = (uint32_t)cell;
+    const uint32_t row = fnx.div(c);
+    const uint32_t i = c - row * fnx.d;
+    uint32_t j = 0, k = row;
+    if (dim == 3) {
+        k = fnxy.div(c);
+        j = row - k * (fnxy.d / fnx.d);
+    }
+    const int tx = (int)ftx.div(i), tz = (int)ftz.div(k);
+    const int ty = dim == 3 ? (int)fty.div(j) : 0;
+    return tx + ntile[0] * (ty + ntile[1] * tz);
+}
+
+__global__ __launch_bounds__(256) void k_tile_count(SortArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int key = -1;
+    if (p < a.n) {
+        const int cell = a.cell[p];
+        key = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+    }
+    const int lane = threadIdx.x & 63;
+    unsigned long long active = __ballot(key >= 0);
+    while (active) {
+        const int leader = __ffsll((long long)active) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const unsigned long long match = __ballot(key == lkey) & active;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&a.count[lkey], __popcll(match));
+        base = __shfl(base, leader, 64);
+        if (key == lkey && ((match >> lane) & 1ull)) {
+            const unsigned long long below = match & ((1ull << lane) - 1ull);
+            a.rank[p] = base + __popcll(below);
+        }
+        active &= ~match;
+    }
+}
+
+hipError_t launch_tile_count(const SortArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_count, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Exclusive scan of n counts into start[0..n] by one workgroup of 1024
+// threads, each owning a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *start, int32_t n) {
+    __shared__ int32_t part[1024];
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = t * chunk;
+    const int e = min(n, b + chunk);
+    int sum = 0;
+    for (int i = b; i < e; ++i) sum += count[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int i = b; i < e; ++i) {
+        start[i] = run;
+        run += count[i];
+    }
+    if (t == 1023) start[n] = part[1023];
+}
+
+hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, n_tiles);
+    return hipGetLastError();
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int cell = a.cell_src[p];
+    const int tile = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+    const int d = a.start[tile] + a.rank[p];
+    a.cell_dst[d] = cell;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (a.off_src[c]) a.off_dst[c][d] = a.off_src[c][p];
+        a.u_dst[c][d] = a.u_src[c][p];
+    }
+    a.w_dst[d] = a.w_src[p];
+    a.id_dst[d] = a.id_src[p];
+}
+
+template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_scatter<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_scatter<float>(const ScatterArgs<float> &, hipStream_t);
+template hipError_t launch_scatter<double>(const ScatterArgs<double> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics
+// ---------------------------------------------------------------------------
+template <int NV> AP_D void block_reduce_store(double (&v)[NV], double *out) {
+    __shared__ double red[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const double s = wave_sum(v[m]);
+        if (lane == 0) red[m][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_diag_particles(DiagArgs<T> a) {
+    double v[kDiagVals];
+#pragma unroll
+    for (int m = 0; m < kDiagVals; ++m) v[m] = 0.0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += gridDim.x * blockDim.x) {
+        const double ux = a.u[0][p], uy = a.u[1][p], uz = a.u[2][p];
+        const double w = a.w[p];
+        bool fin = isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(w);
+        for (int c = 0; c < 3; ++c)
+            if (a.off[c]) fin = fin && isfinite((double)a.off[c][p]);
+        if (!fin) { v[10] += 1.0; continue; }
+        const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+        v[0] += w;
+        v[1] += w * ux; v[2] += w * uy; v[3] += w * uz;
+        v[4] += w * ux * ux; v[5] += w * uy * uy; v[6] += w * uz * uz;
+        v[7] += w * g;
+        v[8] += w * (g - 1.0);
+        if (a.proxy) v[9] += (double)a.proxy[2 * p] + (double)a.proxy[2 * p + 1];
+    }
+    block_reduce_store<kDiagVals>(v, a.partial + (size_t)blockIdx.x * kDiagVals);
+}
+
+template <typename T> hipError_t launch_diag_particles(const DiagArgs<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_diag_particles<T>), dim3(a.blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_diag_particles<float>(const DiagArgs<float> &, hipStream_t);
+template hipError_t launch_diag_particles<double>(const DiagArgs<double> &, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_fields(const T *E0, const T *E1, const T *E2, const T *B0,
+                                                     const T *B1, const T *B2, size_t n, double *partial) {
+    double v[1] = {0.0};
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+        const double a0 = E0[c], a1 = E1[c], a2 = E2[c], b0 = B0[c], b1 = B1[c], b2 = B2[c];
+        v[0] += a0 * a0 + a1 * a1 + a2 * a2 + b0 * b0 + b1 * b1 + b2 * b2;
+    }
+    block_reduce_store<1>(v, partial + blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_diag_fields(T *const F[6], size_t ncell, double *partial, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_diag_fields<T>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], ncell, partial);
+    return hipGetLastError();
+}
+template hipError_t launch_diag_fields<float>(float *const[6], size_t, double *, int, hipStream_t);
+template hipError_t launch_diag_fields<double>(double *const[6], size_t, double *, int, hipStream_t);
+
+__global__ void k_sum_partials(const double *partial, int blocks, int nvals, double *out) {
+    const int m = threadIdx.x;
+    if (m >= nvals) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * nvals + m];
+    out[m] = s;
+}
+
+hipError_t launch_sum_partials(const double *partial, int blocks, int nvals, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, blocks, nvals, out);
+    return hipGetLastError();
+}
+
+// Charge density at the nodes, quadratic shape, FP64 atomics.
+template <typename T> __global__ __launch_bounds__(256) void k_rho(RhoArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int cell = a.cell[p];
+    if ((unsigned)cell >= (unsigned)a.nn[0] * (unsigned)a.nn[1] * (unsigned)a.nn[2]) return;
+    const uint32_t row = a.fnx.div((uint32_t)cell);
+    int idx[3];
+    idx[0] = cell - (int)row * a.nn[0];
+    if (a.dim == 3) {
+        const uint32_t k = a.fnxy.div((uint32_t)cell);
+        idx[1] = (int)(row - k * a.nn[1]);
+        idx[2] = (int)k;
+    } else {
+        idx[1] = 0;
+        idx[2] = (int)row;
+    }
+    int base[3];
+    double wt[3][3];
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!a.off[ax] || (a.dim == 2 && ax == 1)) {
+            base[ax] = 0;
+            wt[ax][0] = 1.0; wt[ax][1] = 0.0; wt[ax][2] = 0.0;
+            continue;
+        }
+        const double o = (double)a.off[ax][p];
+        const int nn = o >= 0.5 ? 1 : 0;
+        const double d = o - nn;
+        base[ax] = idx[ax] + nn - 1;
+        wt[ax][0] = 0.5 * (0.5 - d) * (0.5 - d);
+        wt[ax][1] = 0.75 - d * d;
+        wt[ax][2] = 0.5 * (0.5 + d) * (0.5 + d);
+    }
+    const double qw = a.q * (double)a.w[p];
+    const int ny_loop = (a.dim == 3) ? 3 : 1;
+    for (int c = 0; c < 3; ++c) {
+        const int gz = (base[2] + c + a.nn[2]) % a.nn[2];
+        for (int b = 0; b < ny_loop; ++b) {
+            const int gy = (a.dim == 3) ? (base[1] + b + a.nn[1]) % a.nn[1] : 0;
+            for (int m = 0; m < 3; ++m) {
+                const int gx = (base[0] + m + a.nn[0]) % a.nn[0];
+                const size_t g = (size_t)gx + (size_t)a.nn[0] * ((size_t)gy + (size_t)a.nn[1] * gz);
+                atomicAdd(&a.rho[g], qw * wt[0][m] * wt[1][b] * wt[2][c]);
+            }
+        }
+    }
+}
+
+template <typename T> hipError_t launch_rho(const RhoArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_rho<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_rho<float>(const RhoArgs<float> &, hipStream_t);
+template hipError_t launch_rho<double>(const RhoArgs<double> &, hipStream_t);
+
+// max |(rho1 - rho0)/dt + div J| and max |J| (non-negative doubles compare
+// like their bit patterns, so an integer atomicMax orders them).
+template <typename T>
+__global__ __launch_bounds__(256) void k_continuity(YeeIdx g, int dim, double idx, double idy, double idz,
+                                                    double idt, const double *rho0, const double *rho1,
+                                                    const T *Jx, const T *Jy, const T *Jz, size_t ncell,
+                                                    unsigned long long *res_max, unsigned long long *j_max) {
+    double rmax = 0.0, jm = 0.0;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t cc = (uint32_t)c;
+        const uint32_t row = g.fnx.div(cc);
+        const int i = (int)(cc - row * g.nx);
+        const long im = (i == 0) ? (g.nx - 1) : -1;
+        int k;
+        long jmo = 0;
+        if (dim == 3) {
+            const uint32_t kk = g.fny.div(row);
+            const int j = (int)(row - kk * g.ny);
+            k = (int)kk;
+            jmo = (j == 0) ? (long)(g.ny - 1) * g.nx : -(long)g.nx;
+        } else {
+            k = (int)row;
+        }
+        const long slab = (long)g.nx * g.ny;
+        const long km = (k == 0) ? (long)(g.nz - 1) * slab : -slab;
+        double div = ((double)Jx[c] - (double)Jx[c + im]) * idx + ((double)Jz[c] - (double)Jz[c + km]) * idz;
+        if (dim == 3) div += ((double)Jy[c] - (double)Jy[c + jmo]) * idy;
+        const double r = (rho1[c] - rho0[c]) * idt + div;
+        rmax = fmax(rmax, fabs(r));
+        jm = fmax(jm, fmax(fabs((double)Jx[c]), fmax(fabs((double)Jy[c]), fabs((double)Jz[c]))));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+        jm = fmax(jm, __shfl_xor(jm, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(res_max, (unsigned long long)__double_as_longlong(rmax));
+        atomicMax(j_max, (unsigned long long)__double_as_longlong(jm));
+    }
+}
+
+template <typename T>
+hipError_t launch_continuity(int dim, const int32_t n[3], const double dx[3], double dt, const double *rho0,
+                             const double *rho1, T *const J[3], unsigned long long *res_max,
+                             unsigned long long *j_max, hipStream_t s) {
+    YeeIdx g;
+    g.nx = n[0];
+    g.ny = dim == 3 ? n[1] : 1;
+    g.nz = n[2];
+    g.fnx = FastDiv((uint32_t)g.nx);
+    g.fny = FastDiv((uint32_t)g.ny);
+    const size_t ncell = (size_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL((k_continuity<T>), dim3(grid_blocks(ncell)), dim3(256), 0, s, g, dim, 1.0 / dx[0],
+                       1.0 / dx[1], 1.0 / dx[2], 1.0 / dt, rho0, rho1, J[0], J[1], J[2], ncell, res_max, j_max);
+    return hipGetLastError();
+}
+template hipError_t launch_continuity<float>(int, const int32_t[3], const double[3], double, const double *,
+                                             const double *, float *const[3], unsigned long long *,
+                                             unsigned long long *, hipStream_t);
+template hipError_t launch_continuity<double>(int, const int32_t[3], const double[3], double, const double *,
+                                              const double *, double *const[3], unsigned long long *,
+                                              unsigned long long *, hipStream_t);
+
+}  // namespace apt

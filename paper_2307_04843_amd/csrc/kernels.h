@@ -1,0 +1,151 @@
+// Kernel argument structs and launcher declarations shared by the host
+// runtime (apt_host.cpp) and the kernel translation units.
+#pragma once
+
+#include "common.h"
+#include "pulse_dev.h"
+
+namespace apt {
+
+// Tile halo: a particle in tile cell range [X0, X0+TX) may drift kDrift cells
+// out of it between re-sorts and still use the LDS copy.  The quadratic
+// gather needs nodes [c-1, c+2] and the deposit [c-2, c+3] around cell c.
+constexpr int kDrift = 1;
+constexpr int kHaloLo = 2 + kDrift;
+constexpr int kHaloHi = 3 + kDrift;
+
+template <typename T> struct SpeciesIO {
+    // source (read) arrays
+    const int32_t *cell_in;
+    const T *off_in[3];
+    const T *u_in[3];
+    const T *w_in;
+    const int32_t *id_in;
+    // destination (write) arrays
+    int32_t *cell_out;
+    T *off_out[3];
+    T *u_out[3];
+    T *w_out;
+    int32_t *id_out;
+    const int32_t *tile_start;   // [n_tiles + 1]
+    int32_t copy_static;         // write w and id (source != destination)
+    int32_t n;
+    double q_over_m;
+    double q;
+};
+
+template <typename T> struct PushArgs {
+    SpeciesIO<T> sp[kMaxSpecies];
+    int32_t nsp;
+    const T *E[3];
+    const T *B[3];
+    T *J[3];
+    int32_t n[3];                // cells per axis
+    int32_t tile[3];             // tile shape
+    int32_t ntile[3];            // tiles per axis
+    FastDiv fnx, fnxy, fntx, fntxy;
+    int32_t splits;              // workgroups per tile
+    int32_t n_logical;           // n_tiles * splits
+    int32_t reg[3];              // LDS region extent per axis
+    double dx[3];
+    double x_min[3];
+    double dt;
+    double t;                    // time of the positions read (t^n)
+    unsigned long long *n_fast;  // moves >= 1 cell (clamped)
+    unsigned long long *n_bad;   // non-finite / out-of-range particles
+    PulseDev P;
+};
+
+template <typename T> struct GridlessArgs {
+    int32_t *icell[3];
+    T *off[3];
+    T *u[3];
+    T *proxy;                    // 2 per particle or null
+    int32_t n;
+    double q_over_m;
+    double dx[3];                // virtual cell size
+    double x_min[3];
+    double dt;
+    double t;
+    unsigned long long *n_bad;
+    PulseDev P;
+};
+
+struct YeeArgsBase {
+    int32_t n[3];
+    double dx[3];
+    double dt;
+};
+
+// launchers (hipStream_t passed through)
+template <typename T>
+hipError_t launch_push_deposit_2d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);
+template <typename T>
+hipError_t launch_push_deposit_3d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);
+template <typename T>
+hipError_t launch_gridless(int pulse, const GridlessArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_eval_pulse(int pulse, const PulseDev &P, int64_t n, const double *xyz, double t, T *E, T *B,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &g, int no_yee, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_zero(T *p, size_t n, hipStream_t s);
+
+struct SortArgs {
+    const int32_t *cell;
+    uint32_t ncell;              // cells outside [0, ncell) are binned to tile 0
+    int32_t n;
+    int32_t dim;
+    FastDiv fnx, fnxy;           // decompose linear cell
+    FastDiv ftx, fty, ftz;       // cell -> tile
+    int32_t ntile[3];
+    int32_t *count;              // [n_tiles]
+    int32_t *rank;               // [n]
+};
+hipError_t launch_tile_count(const SortArgs &a, hipStream_t s);
+hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, hipStream_t s);
+
+template <typename T> struct ScatterArgs {
+    const int32_t *cell_src; const T *off_src[3]; const T *u_src[3]; const T *w_src; const int32_t *id_src;
+    int32_t *cell_dst; T *off_dst[3]; T *u_dst[3]; T *w_dst; int32_t *id_dst;
+    const int32_t *rank;
+    const int32_t *start;
+    uint32_t ncell;
+    int32_t n, dim;
+    FastDiv fnx, fnxy, ftx, fty, ftz;
+    int32_t ntile[3];
+};
+template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStream_t s);
+
+// diagnostics
+constexpr int kDiagVals = 16;    // per-species partial-sum slots
+template <typename T> struct DiagArgs {
+    const T *u[3];
+    const T *w;
+    const T *proxy;
+    const T *off[3];
+    int32_t n;
+    int32_t dim;
+    double *partial;             // [blocks][kDiagVals]
+    int32_t blocks;
+};
+template <typename T> hipError_t launch_diag_particles(const DiagArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_diag_fields(T *const F[6], size_t ncell, double *partial, int blocks, hipStream_t s);
+hipError_t launch_sum_partials(const double *partial, int blocks, int nvals, double *out, hipStream_t s);
+
+template <typename T> struct RhoArgs {
+    const int32_t *cell; const T *off[3]; const T *w;
+    int32_t n; double q;
+    int32_t nn[3]; FastDiv fnx, fnxy; int32_t dim;
+    double *rho;
+};
+template <typename T> hipError_t launch_rho(const RhoArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_continuity(int dim, const int32_t n[3], const double dx[3], double dt,
+                             const double *rho0, const double *rho1, T *const J[3],
+                             unsigned long long *res_max, unsigned long long *j_max,
+                             hipStream_t s);
+
+}  // namespace apt

@@ -1,0 +1,164 @@
+"""Device buffers for one run, allocated with torch on the caller's stream.
+
+PyTorch is used only for device memory and the stream; every kernel comes
+from libapt.so through the ap_* calls in ``apt``.
+"""
+import numpy as np
+import torch
+
+from . import apt
+
+
+class Simulation:
+    """One context: grid + species buffers sized by ap_query_layout.
+
+    species: list of dicts with keys q, m and a state dict from
+    ``inputs.plasma`` (cell, off, u, w) or ``inputs.beam`` (icell, off, u, w).
+    Lengths and times in lambda units.
+    """
+
+    def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
+                 precision="f32", tile=(0, 0, 0), sort_every=0, species=(), proxy=False,
+                 device="cuda:0", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP path needs a GPU")
+        apt.load()
+        self.dim = dim
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.np_dtype = np.float64 if precision == "f64" else np.float32
+        g = apt.ap_grid_desc()
+        g.dim = dim
+        g.precision = apt.AP_F64 if precision == "f64" else apt.AP_F32
+        for a in range(3):
+            g.n[a] = int(n[a])
+            g.tile[a] = int(tile[a])
+            g.dx[a] = float(dx[a])
+            g.x_min[a] = float(x_min[a])
+        g.t0 = float(t0)
+        g.dt = float(dt)
+        g.sort_every = int(sort_every)
+        self.grid_desc = g
+        self.sp_desc = []
+        for sp in species:
+            d = apt.ap_species_desc()
+            d.q = float(sp["q"])
+            d.m = float(sp["m"])
+            d.n = int(sp["state"]["u"].shape[1])
+            self.sp_desc.append(d)
+        self.layout = apt.ap_query_layout(g, self.sp_desc)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.grid = torch.zeros(max(8, (self.layout.grid_bytes + 7) // 8 * 8), dtype=torch.uint8,
+                                    device=self.device)
+            self.work = torch.zeros(max(256, self.layout.work_bytes), dtype=torch.uint8,
+                                    device=self.device)
+        self.ncell = int(self.layout.n_cells)
+        self.arrays = []
+        bufs = apt.ap_buffers()
+        bufs.grid = self.grid.data_ptr() if self.layout.grid_bytes else None
+        bufs.work = self.work.data_ptr()
+        for i, sp in enumerate(species):
+            st = sp["state"]
+            N = st["u"].shape[1]
+            arr = {}
+            dev = self.device
+            if dim == 0:
+                arr["icell"] = [torch.as_tensor(np.ascontiguousarray(st["icell"][a]), device=dev)
+                                for a in range(3)]
+                arr["off"] = [torch.as_tensor(np.ascontiguousarray(st["off"][a].astype(self.np_dtype)),
+                                              device=dev) for a in range(3)]
+            else:
+                arr["cell"] = torch.as_tensor(np.ascontiguousarray(st["cell"].astype(np.int32)), device=dev)
+                arr["off"] = [torch.as_tensor(np.ascontiguousarray(st["off"][a].astype(self.np_dtype)),
+                                              device=dev) if (dim == 3 or a != 1) else None
+                              for a in range(3)]
+            arr["u"] = [torch.as_tensor(np.ascontiguousarray(st["u"][a].astype(self.np_dtype)), device=dev)
+                        for a in range(3)]
+            arr["w"] = torch.as_tensor(np.ascontiguousarray(st["w"].astype(self.np_dtype)), device=dev)
+            arr["id"] = torch.arange(N, dtype=torch.int32, device=dev)
+            arr["proxy"] = (torch.zeros(2 * N, dtype=self.dtype, device=dev)
+                            if (proxy and dim == 0) else None)
+            p = bufs.sp[i]
+            if dim == 0:
+                for a in range(3):
+                    p.icell[a] = arr["icell"][a].data_ptr()
+            else:
+                p.cell = arr["cell"].data_ptr()
+            for a in range(3):
+                p.off[a] = arr["off"][a].data_ptr() if arr["off"][a] is not None else None
+                p.u[a] = arr["u"][a].data_ptr()
+            p.w = arr["w"].data_ptr()
+            p.id = arr["id"].data_ptr()
+            p.proxy = arr["proxy"].data_ptr() if arr["proxy"] is not None else None
+            self.arrays.append(arr)
+        self.buffers = bufs
+        torch.cuda.synchronize(self.device)
+        self.ctx = apt.ap_init(g, self.sp_desc, bufs, self.stream.cuda_stream)
+
+    # -- fields ------------------------------------------------------------
+    def field_views(self):
+        """(E, B, J) lists of 3 tensors shaped (nz, ny, nx), views of the grid block."""
+        if self.dim == 0:
+            raise ValueError("gridless run has no grid")
+        g = self.grid.view(self.dtype)[: 9 * self.ncell].view(9, self.ncell)
+        nx, ny, nz = self.grid_desc.n[0], (self.grid_desc.n[1] if self.dim == 3 else 1), self.grid_desc.n[2]
+        comps = [g[k].view(nz, ny, nx) for k in range(9)]
+        return comps[0:3], comps[3:6], comps[6:9]
+
+    # -- ap_* wrappers -------------------------------------------------------
+    def set_pulse(self, kind, **params):
+        ptype = apt.PULSE_TYPES[kind]
+        apt.ap_set_pulse(self.ctx, ptype, apt.pulse_params(**params) if ptype != apt.AP_PULSE_NONE else None)
+
+    def eval_pulse(self, xyz, t):
+        """E1, B1 at lab points xyz (3, n) in lambda units, time t; numpy (3, n) arrays."""
+        pts = torch.as_tensor(np.ascontiguousarray(xyz, dtype=np.float64), device=self.device)
+        n = pts.shape[1]
+        E = torch.empty(3 * n, dtype=self.dtype, device=self.device)
+        B = torch.empty(3 * n, dtype=self.dtype, device=self.device)
+        apt.ap_eval_pulse(self.ctx, n, pts.data_ptr(), t, E.data_ptr(), B.data_ptr())
+        torch.cuda.synchronize(self.device)
+        return E.view(3, n).double().cpu().numpy(), B.view(3, n).double().cpu().numpy()
+
+    def step(self, n=1, flags=0):
+        apt.ap_step(self.ctx, n, flags)
+
+    def diag(self, what=apt.AP_DIAG_PARTICLES | apt.AP_DIAG_FIELDS, allow_numeric=False):
+        return apt.ap_gather_diag(self.ctx, what, allow_numeric=allow_numeric)
+
+    def time(self):
+        return apt.ap_get_time(self.ctx)
+
+    def state(self, i):
+        """Host copy of species i, ordered by particle id."""
+        torch.cuda.synchronize(self.device)
+        a = self.arrays[i]
+        ids = a["id"].cpu().numpy()
+        order = np.argsort(ids, kind="stable")
+        out = {"id": ids[order]}
+        if self.dim == 0:
+            out["icell"] = np.stack([a["icell"][k].cpu().numpy()[order] for k in range(3)])
+            out["off"] = np.stack([a["off"][k].cpu().numpy()[order] for k in range(3)])
+        else:
+            out["cell"] = a["cell"].cpu().numpy()[order]
+            out["off"] = np.stack([a["off"][k].cpu().numpy()[order] if a["off"][k] is not None
+                                   else np.zeros(len(ids), dtype=self.np_dtype) for k in range(3)])
+        out["u"] = np.stack([a["u"][k].cpu().numpy()[order] for k in range(3)])
+        out["w"] = a["w"].cpu().numpy()[order]
+        if a["proxy"] is not None:
+            pr = a["proxy"].cpu().numpy().reshape(-1, 2)
+            out["proxy"] = (pr[:, 0].astype(np.float64) + pr[:, 1])[order]
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            torch.cuda.synchronize(self.device)
+            apt.ap_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/apt.h, and validates arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2307_04843_amd import apt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "apt.h")).read()
+    return sorted(set(re.findall(r"^(?:ap_status|const char \*)\s*(ap_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = apt.load()
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(apt.EXPORTED)
+
+
+def _grid(dim=2, n=(64, 1, 32), dx=0.05, prec=apt.AP_F32):
+    g = apt.ap_grid_desc()
+    g.dim = dim
+    g.precision = prec
+    for a in range(3):
+        g.n[a] = n[a]
+        g.dx[a] = dx
+    return g
+
+
+def _sp(n=1000, q=-1.0, m=1.0):
+    s = apt.ap_species_desc()
+    s.q, s.m, s.n = q, m, n
+    return s
+
+
+def test_query_layout_sizes():
+    g = _grid()
+    lay = apt.ap_query_layout(g, [_sp(2048)])
+    assert lay.grid_bytes == 9 * 64 * 32 * 4
+    assert lay.n_cells == 64 * 32
+    assert lay.n_tiles == 2 * 2           # default 32 x 16 tiles
+    assert lay.work_bytes > 2048 * 4 * 8
+    g64 = _grid(prec=apt.AP_F64)
+    assert apt.ap_query_layout(g64, [_sp(2048)]).grid_bytes == 9 * 64 * 32 * 8
+
+
+@pytest.mark.parametrize("mut,msg", [
+    (lambda g: setattr(g, "dim", 1), "dim"),
+    (lambda g: setattr(g, "precision", 7), "precision"),
+    (lambda g: g.n.__setitem__(0, 2), "4 cells"),
+    (lambda g: g.dx.__setitem__(2, -1.0), "dx"),
+    (lambda g: setattr(g, "dt", 0.2), "stability"),
+    (lambda g: setattr(g, "dt", float("nan")), "dt"),
+    (lambda g: (g.n.__setitem__(0, 256), g.tile.__setitem__(0, 100)), "tile"),
+])
+def test_query_layout_rejects_bad_grid(mut, msg):
+    g = _grid()
+    mut(g)
+    with pytest.raises(apt.APTError) as ei:
+        apt.ap_query_layout(g, [_sp()])
+    assert ei.value.status == apt.AP_E_ARG
+    assert msg in apt.last_error()
+
+
+def test_query_layout_rejects_bad_species():
+    with pytest.raises(apt.APTError):
+        apt.ap_query_layout(_grid(), [_sp(m=0.0)])
+    with pytest.raises(apt.APTError):
+        apt.ap_query_layout(_grid(), [_sp(n=-5)])
+    with pytest.raises(apt.APTError):
+        apt.ap_query_layout(_grid(), [_sp()] * 5)
+
+
+def test_gridless_layout_needs_dt():
+    g = _grid(dim=0)
+    with pytest.raises(apt.APTError):
+        apt.ap_query_layout(g, [_sp()])
+    g.dt = 0.01
+    lay = apt.ap_query_layout(g, [_sp()])
+    assert lay.grid_bytes == 0
+
+
+def test_init_rejects_null_buffers_before_device_work():
+    lib = apt.load()
+    g = _grid()
+    sp = (apt.ap_species_desc * 1)(_sp(16))
+    bufs = apt.ap_buffers()
+    ctx = C.c_void_p()
+    st = lib.ap_init(C.byref(g), sp, 1, C.byref(bufs), None, C.byref(ctx))
+    assert st == apt.AP_E_ARG and ctx.value is None
+    assert "NULL" in apt.last_error()
+
+
+def test_calls_on_null_context():
+    lib = apt.load()
+    assert lib.ap_step(None, 1, 0) == apt.AP_E_ARG
+    assert lib.ap_set_pulse(None, 0, None) == apt.AP_E_ARG
+    assert lib.ap_destroy(None) == apt.AP_OK
+    d = apt.ap_diag()
+    assert lib.ap_gather_diag(None, 1, C.byref(d)) == apt.AP_E_ARG
