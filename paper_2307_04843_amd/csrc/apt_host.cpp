@@ -112,7 +112,8 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         size_t region = 1;
         for (int ax = 0; ax < 3; ++ax)
             if (axis_active(s.dim, ax)) region *= (size_t)(s.tile[ax] + (s.dim == 3 ? 5 : kHaloLo + kHaloHi));
-        if (region * 9 * s.real > 160 * 1024) return fail(AP_E_ARG, "tile too large for LDS (reduce tile extents)");
+        if (align_lds(region * 6 * s.real) + region * 3 * 8 > 160 * 1024)
+            return fail(AP_E_ARG, "tile too large for LDS (reduce tile extents)");
     } else {
         if (!(g->dt > 0.0)) return fail(AP_E_ARG, "gridless runs need dt > 0");
         s.dt = g->dt * kTwoPi;
@@ -733,6 +734,11 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sc.rank = rank;
             sc.start = start;
             sc.ncell = (uint32_t)s.ncell;
+            {
+                const double ppc = (double)s.np[i] / (double)s.ncell;
+                int M = (int)std::lround(ppc);
+                sc.interleave = M < 1 ? 1 : (M > 64 ? 64 : M);
+            }
             sc.n = (int)s.np[i];
             sc.dim = s.dim;
             sc.fnx = fnx;

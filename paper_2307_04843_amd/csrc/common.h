@@ -54,6 +54,9 @@ template <typename T> AP_HD Cx<T> operator*(T s, Cx<T> a) { return Cx<T>(s * a.r
 AP_D void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 AP_D void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// LDS sub-buffer offsets are kept 16-byte aligned.
+AP_HD size_t align_lds(size_t bytes) { return (bytes + 15) / 16 * 16; }
+
 template <typename T> AP_D T floor_r(T x);
 template <> AP_D float floor_r<float>(float x) { return floorf(x); }
 template <> AP_D double floor_r<double>(double x) { return floor(x); }

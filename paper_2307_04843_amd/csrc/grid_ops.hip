@@ -222,7 +222,22 @@ template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterAr
     if (p >= a.n) return;
     const int cell = a.cell_src[p];
     const int tile = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
-    const int d = a.start[tile] + a.rank[p];
+    // Place the particle at its tile slot.  Ranks follow the previous order,
+    // which is cell-major (about M particles per cell); a ragged transpose of
+    // the tile's rank sequence with stride M puts consecutive slots in
+    // different cells, so the 64 lanes of a wave update 64 distinct current
+    // nodes in the push kernel's LDS atomics.
+    const int base = a.start[tile];
+    const int cnt = a.start[tile + 1] - base;
+    const int r = a.rank[p];
+    int slot = r;
+    const int M = a.interleave;
+    if (M > 1 && cnt > M) {
+        const int q0 = cnt / M, rem = cnt - q0 * M;
+        const int q = r / M, m = r - q * M;
+        slot = m * q0 + (m < rem ? m : rem) + q;
+    }
+    const int d = base + slot;
     a.cell_dst[d] = cell;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -112,6 +112,7 @@ template <typename T> struct ScatterArgs {
     const int32_t *rank;
     const int32_t *start;
     uint32_t ncell;
+    int32_t interleave;          // mean particles per cell: within-tile ragged transpose stride
     int32_t n, dim;
     FastDiv fnx, fnxy, ftx, fty, ftz;
     int32_t ntile[3];

@@ -38,8 +38,8 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     T *sm = reinterpret_cast<T *>(smem_raw);
     const int RX = a.reg[0], RZ = a.reg[2];
     const int RC = RX * RZ;
-    T *sF = sm;            // Ex Ey Ez Bx By Bz
-    T *sJ = sm + 6 * RC;   // Jx Jy Jz
+    T *sF = sm;                                              // Ex Ey Ez Bx By Bz
+    double *sJ = reinterpret_cast<double *>(smem_raw + align_lds(6 * RC * sizeof(T)));   // Jx Jy Jz (FP64)
 
     // XCD-aware mapping: consecutive hardware block ids go round-robin to
     // the 8 XCDs; give each XCD a contiguous run of logical tiles so that
@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         sF[3 * RC + e] = a.B[0][g];
         sF[4 * RC + e] = a.B[1][g];
         sF[5 * RC + e] = a.B[2][g];
-        sJ[0 * RC + e] = T(0);
-        sJ[1 * RC + e] = T(0);
-        sJ[2 * RC + e] = T(0);
+        sJ[0 * RC + e] = 0.0;
+        sJ[1 * RC + e] = 0.0;
+        sJ[2 * RC + e] = 0.0;
     }
     __syncthreads();
 
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             const T third = T(1.0 / 3.0);
             if (in_lds) {
                 const int x0 = la + bx, z0 = lb + bz;
-                T *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
+                double *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const T cz = S0z[b] + T(0.5) * DSz[b];
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int m = 0; m < 3; ++m) {
                         cum += DSx[m] * cz;
-                        atomic_add(&Jx[(z0 + b) * RX + x0 + m], fx * cum);
+                        atomic_add(&Jx[(z0 + b) * RX + x0 + m], (double)(fx * cum));
                     }
                 }
 #pragma unroll
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
                         cum += DSz[b] * cx;
-                        atomic_add(&Jz[(z0 + b) * RX + x0 + m], fz * cum);
+                        atomic_add(&Jz[(z0 + b) * RX + x0 + m], (double)(fz * cum));
                     }
                 }
 #pragma unroll
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     for (int m = 0; m < 4; ++m) {
                         const T wy = S0x[m] * S0z[b] + T(0.5) * DSx[m] * S0z[b] +
                                      T(0.5) * S0x[m] * DSz[b] + third * DSx[m] * DSz[b];
-                        atomic_add(&Jy[(z0 + b) * RX + x0 + m], fy * wy);
+                        atomic_add(&Jy[(z0 + b) * RX + x0 + m], (double)(fy * wy));
                     }
             } else {
                 int gx[4];
@@ -307,15 +307,16 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         const size_t g = (size_t)gz * nx + gx;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T v = sJ[c * RC + e];
-            if (v != T(0)) atomic_add(&a.J[c][g], v);
+            const double v = sJ[c * RC + e];
+            if (v != 0.0) atomic_add(&a.J[c][g], T(v));
         }
     }
 }
 
 template <typename T, int PT>
 static hipError_t launch2d(const PushArgs<T> &a, int threads, hipStream_t s) {
-    const size_t lds = (size_t)9 * a.reg[0] * a.reg[2] * sizeof(T);
+    const size_t rc = (size_t)a.reg[0] * a.reg[2];
+    const size_t lds = align_lds(6 * rc * sizeof(T)) + 3 * rc * sizeof(double);
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((k_push_deposit_2d<T, PT>), dim3(blocks), dim3(threads), lds, s, a);

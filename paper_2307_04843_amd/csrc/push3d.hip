@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
     const int RXY = RX * RY;
     const int RC = RXY * RZ;
     T *sF = sm;
-    T *sJ = sm + 6 * RC;
+    double *sJ = reinterpret_cast<double *>(smem_raw + align_lds(6 * RC * sizeof(T)));
 
     const int nb = gridDim.x;
     const int bid = blockIdx.x;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
         for (int c = 0; c < 3; ++c) {
             sF[c * RC + e] = a.E[c][g];
             sF[(3 + c) * RC + e] = a.B[c][g];
-            sJ[c * RC + e] = T(0);
+            sJ[c * RC + e] = 0.0;
         }
     }
     __syncthreads();
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
             auto addJ = [&](int comp, int i4, int j4, int k4, T v) {
                 if (in_lds) {
                     atomic_add(&sJ[comp * RC + (loc[2] + base[2] + k4) * RXY + (loc[1] + base[1] + j4) * RX +
-                                   loc[0] + base[0] + i4], v);
+                                   loc[0] + base[0] + i4], (double)v);
                 } else {
                     const int gx = wrap3(idx[0] + base[0] + i4, nx);
                     const int gy = wrap3(idx[1] + base[1] + j4, ny);
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
         const size_t g = (size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const T v = sJ[c * RC + e];
-            if (v != T(0)) atomic_add(&a.J[c][g], v);
+            const double v = sJ[c * RC + e];
+            if (v != 0.0) atomic_add(&a.J[c][g], T(v));
         }
     }
 }
@@ -314,7 +314,8 @@ template <typename T, int PT>
 static hipError_t launch3d(const PushArgs<T> &a0, int threads, hipStream_t s) {
     PushArgs<T> a = a0;
     for (int c = 0; c < 3; ++c) a.reg[c] = a.tile[c] + kLo3 + kHi3;
-    const size_t lds = (size_t)9 * a.reg[0] * a.reg[1] * a.reg[2] * sizeof(T);
+    const size_t rc = (size_t)a.reg[0] * a.reg[1] * a.reg[2];
+    const size_t lds = align_lds(6 * rc * sizeof(T)) + 3 * rc * sizeof(double);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
