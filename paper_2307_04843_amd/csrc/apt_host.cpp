@@ -362,14 +362,20 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         return fail(AP_E_ARG, "unknown dispersion mode");
     const bool focused = type != AP_PULSE_PLANE;
     if (focused && !(prm->w0 > 0.0)) return fail(AP_E_ARG, "w0 must be > 0");
-    if (focused && prm->d_f != 2 && prm->d_f != 3) return fail(AP_E_ARG, "d_f must be 2 or 3");
+    if (focused && type != AP_PULSE_GAUSS_NP && prm->d_f != 2 && prm->d_f != 3)
+        return fail(AP_E_ARG, "d_f must be 2 or 3");
     if (type == AP_PULSE_LG) {
         if (prm->d_f != 3) return fail(AP_E_ARG, "Laguerre-Gaussian modes need d_f = 3");
         if (prm->lg_p < 0 || prm->lg_p > 8 || prm->lg_l < -8 || prm->lg_l > 8)
             return fail(AP_E_ARG, "LG indices must satisfy 0 <= p <= 8, |l| <= 8");
     }
     if (type == AP_PULSE_FF && prm->beta_f == 1.0) return fail(AP_E_ARG, "flying focus needs beta_f != 1");
-    if (type == AP_PULSE_GAUSS_NP) return fail(AP_E_UNSUPPORTED, "nonparaxial Gaussian not available in this build");
+    if (type == AP_PULSE_GAUSS_NP) {
+        if (prm->dispersion != AP_DISP_VACUUM)
+            return fail(AP_E_ARG, "the nonparaxial Gaussian is a vacuum solution: use AP_DISP_VACUUM");
+        if (prm->np_order != 0 && prm->np_order != 2 && prm->np_order != 4)
+            return fail(AP_E_ARG, "np_order must be 0, 2 or 4");
+    }
     const double L = kTwoPi;
     // numerical dispersion constants (Sec. II.A, Eqs. (10)-(14)), omega = 1
     double v_phi = 1.0, v_g = 1.0, boe = 1.0;
@@ -393,7 +399,7 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         }
     }
     P.pol = prm->pol;
-    P.d_f = type == AP_PULSE_PLANE ? 3 : prm->d_f;
+    P.d_f = (type == AP_PULSE_PLANE || type == AP_PULSE_GAUSS_NP) ? 3 : prm->d_f;
     P.lg_l = prm->lg_l;
     P.lg_p = prm->lg_p;
     P.np_order = prm->np_order;
@@ -425,6 +431,9 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         if (type == AP_PULSE_FF) xr *= (1.0 - prm->beta_f);
         P.inv_xr = 1.0 / xr;
         P.eps = w0 / P.x_r;
+        P.inv_w0 = 1.0 / w0;
+        P.np_e2 = prm->np_order >= 2 ? P.eps * P.eps : 0.0;
+        P.np_e4 = prm->np_order >= 4 ? P.eps * P.eps * P.eps * P.eps : 0.0;
     }
     if (type == AP_PULSE_LG) {
         const int la = prm->lg_l < 0 ? -prm->lg_l : prm->lg_l;

@@ -94,6 +94,7 @@ template <typename T> hipError_t launch_gridless(int pulse, const GridlessArgs<T
     case PT_GAUSS: return launch_gl<T, PT_GAUSS>(a, s);
     case PT_LG: return launch_gl<T, PT_LG>(a, s);
     case PT_FF: return launch_gl<T, PT_FF>(a, s);
+    case PT_NP: return launch_gl<T, PT_NP>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -128,6 +129,7 @@ hipError_t launch_eval_pulse(int pulse, const PulseDev &P, int64_t n, const doub
     case PT_GAUSS: return launch_ev<T, PT_GAUSS>(P, n, xyz, t, E, B, s);
     case PT_LG: return launch_ev<T, PT_LG>(P, n, xyz, t, E, B, s);
     case PT_FF: return launch_ev<T, PT_FF>(P, n, xyz, t, E, B, s);
+    case PT_NP: return launch_ev<T, PT_NP>(P, n, xyz, t, E, B, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,6 +21,7 @@
 #pragma once
 
 #include "common.h"
+#include "nonparaxial_gen.h"
 
 namespace apt {
 
@@ -39,7 +40,8 @@ struct PulseDev {
     double beta_f, x0_ff, t0_ff;
     double lg_pref;                        // N (sqrt(2)/w0)^|l|
     double eps;                            // nonparaxial expansion parameter w0/x_R
-    double w0, x_r;
+    double np_e2, np_e4;                   // eps^2, eps^4 weights of the truncated potential
+    double w0, x_r, inv_w0;
 };
 
 // Generalised Laguerre L_n^a(x) and its derivative (-L_{n-1}^{a+1}).
@@ -103,7 +105,7 @@ AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double
             const Cx<T> f(den, -zeta * den);
             const T iw2 = T(P.inv_w0sq);
             T r2, hp, hq;   // r^2 and (1/2) d r^2 / dp, (1/2) d r^2 / dq
-            if (PT == PT_LG || P.d_f == 3) { r2 = p * p + q * q; hp = p; hq = q; }
+            if (PT == PT_LG || PT == PT_NP || P.d_f == 3) { r2 = p * p + q * q; hp = p; hq = q; }
             else if (P.pol == 1)           { r2 = p * p; hp = p; hq = T(0); }
             else                           { r2 = q * q; hp = T(0); hq = q; }
             const T rho2 = r2 * iw2;
@@ -112,7 +114,30 @@ AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double
             T s, c;
             sincospi_r<T>(ang_pi + zeta * den * rho2 * T(0.3183098861837907), &s, &c);
             Cx<T> V(amp * c, amp * s);                   // Gamma exp(-f rho2) e^{i Theta}
-            if constexpr (PT == PT_LG) {
+            if constexpr (PT == PT_NP) {
+                // Gaussian beam beyond the paraxial approximation: fields derived
+                // exactly from the eps^4-truncated vector potential (conjugated
+                // polynomials from nonparaxial_gen.h; explicit i's conjugated here).
+                const NpPoly<T> Q = np_polys<T>(f, rho2, T(1), T(P.np_e2), T(P.np_e4));
+                const T eps = T(P.eps), e2 = eps * eps;
+                const T xi = p * T(P.inv_w0), et = q * T(P.inv_w0);
+                V = f * V;                                   // conj(psi0) Gamma e^{i Theta}
+                const Cx<T> yEp = Q.G + (T(0.25) * e2) * (T(2) * Q.H + (T(4) * xi * xi) * Q.K);
+                const Cx<T> yEq = (e2 * xi * et) * Q.K;
+                const Cx<T> yEx = xi * (Cx<T>(T(0), -eps) * Q.H + (T(0.5) * e2 * eps) * Q.N);
+                const Cx<T> yBq = Q.G + Cx<T>(T(0), T(0.5) * e2) * Q.M;
+                const Cx<T> yBx = Cx<T>(T(0), -eps * et) * Q.H;
+                ep = (yEp * V).re;
+                ex = (yEx * V).re;
+                bx = (yBx * V).re;
+                const T eq = (yEq * V).re;
+                const T bq = (yBq * V).re;
+                E[0] = ex;
+                B[0] = bx;
+                if (P.pol == 0) { E[1] = ep; E[2] = eq; B[2] = bq; }      // p = y, q = z
+                else            { E[2] = ep; E[1] = -eq; B[1] = -bq; }    // p = z, q = -y
+                return true;
+            } else if constexpr (PT == PT_LG) {
                 const int la = P.lg_l >= 0 ? P.lg_l : -P.lg_l;
                 const T sig = P.lg_l >= 0 ? T(1) : T(-1);
                 // f^{|l|+1} (f / conj f)^{p}

@@ -330,6 +330,7 @@ template <typename T> hipError_t launch_push_deposit_2d(int pulse, const PushArg
     case PT_GAUSS: return launch2d<T, PT_GAUSS>(a, threads, s);
     case PT_LG: return launch2d<T, PT_LG>(a, threads, s);
     case PT_FF: return launch2d<T, PT_FF>(a, threads, s);
+    case PT_NP: return launch2d<T, PT_NP>(a, threads, s);
     default: return hipErrorInvalidValue;
     }
 }

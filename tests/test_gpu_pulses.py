@@ -24,6 +24,9 @@ PULSES = {
     "ff_back": dict(type="ff", beta_f=-1.0, x0_ff=100.0, t0_ff=80.0, d_f=3),
     "ff_fwd": dict(type="ff", beta_f=1.5, x0_ff=100.0, t0_ff=80.0, d_f=3),
     "chirp": dict(type="gauss", d_f=3, chirp=0.05),
+    "np4": dict(type="gauss_np", np_order=4, dispersion=units.DISP_VACUUM, w0=2.0),
+    "np4_tight": dict(type="gauss_np", np_order=4, dispersion=units.DISP_VACUUM, w0=0.8, pol=1),
+    "np2": dict(type="gauss_np", np_order=2, dispersion=units.DISP_VACUUM, w0=2.0),
 }
 
 

@@ -544,3 +544,79 @@ def test_oracle_step_conserves_charge_in_gridded_run():
         jmax = max(np.max(np.abs(c)) for c in g.J)
         assert np.max(np.abs(res)) <= 1e-12 * jmax / dx + 1e-300
         pic.yee_step(g)
+
+
+# ---------------------------------------------------------------------------
+# Nonparaxial Gaussian (Lax-Davis series to eps^4)
+# ---------------------------------------------------------------------------
+
+def test_nonparaxial_series_coefficients_solve_recursion():
+    """G2, G4 make (lap_perp + 4i d_zeta + eps^2 d_zeta^2)(psi e^{..}) vanish order by
+    order; checked here on the full psi with finite differences in scaled coordinates:
+    the Helmholtz residual of psi0 (1 + eps^2 G2 + eps^4 G4) scales as eps^6."""
+    from oracle import nonparaxial
+    import sympy as sp
+    F, S = sp.symbols("F S")
+    G2, G4 = nonparaxial.series()
+    g2 = sp.lambdify((F, S), G2, "numpy")
+    g4 = sp.lambdify((F, S), G4, "numpy")
+
+    def psi(xi, eta, zeta, eps):
+        f = 1 / (1 + 1j * zeta)
+        s = xi ** 2 + eta ** 2
+        return (1 + eps ** 2 * g2(f, s) + eps ** 4 * g4(f, s)) * f * np.exp(-f * s)
+
+    def resid(eps, h=2e-3):
+        xi, eta, zeta = 0.4, 0.3, 0.5
+        d2 = lambda fn: (-fn(2 * h) + 16 * fn(h) - 30 * fn(0) + 16 * fn(-h) - fn(-2 * h)) / (12 * h * h)
+        d1 = lambda fn: (-fn(2 * h) + 8 * fn(h) - 8 * fn(-h) + fn(-2 * h)) / (12 * h)
+        lx = d2(lambda o: psi(xi + o, eta, zeta, eps))
+        ly = d2(lambda o: psi(xi, eta + o, zeta, eps))
+        dz = d1(lambda o: psi(xi, eta, zeta + o, eps))
+        dzz = d2(lambda o: psi(xi, eta, zeta + o, eps))
+        return abs(lx + ly + 4j * dz + eps ** 2 * dzz)
+    r1, r2 = resid(0.4), resid(0.2)
+    assert 40 < r1 / r2 < 90, (r1, r2)       # eps^6: ratio 64
+
+
+@pytest.mark.parametrize("order", [0, 2, 4])
+def test_nonparaxial_maxwell_residual_order(order):
+    """Fields derived exactly from the truncated potential: div B and Faraday hold
+    to the FD error.  Truncating psi after eps^order leaves a Helmholtz residual
+    ~ eps^(order+2) / w0^2 ~ eps^(order+4) in field units, so Ampere's residual
+    scales as eps^(order+4) and Gauss's (one more transverse derivative) as
+    eps^(order+5): halving eps divides them by 2^(order+4) and 2^(order+5).  A
+    wrong eps^4 coefficient would leave the order-2 scaling."""
+    res = []
+    for w0 in (0.5, 1.0):
+        P = pulses.Pulse(dict(type="gauss_np", a0=1.0, tau=4000.0, t_ref=0.0, x_ref=0.0, x_f=0.0,
+                              w0=w0, np_order=order, dispersion=units.DISP_VACUUM))
+        # near the envelope peak: t = 0 at x = 0
+        pt = (0.3 * P.x_r, 0.45 * P.w0, -0.3 * P.w0)
+        r = _maxwell_residuals(P, pt[0], pt[1], pt[2], 0.3 * P.x_r, 0.004 * P.w0)
+        res.append(np.array(r))
+    for i in (1, 2):
+        assert res[0][i] < 1e-6, res        # div B, Faraday: exact up to FD error
+    for i, extra in ((0, 5), (3, 4)):
+        expect = 2.0 ** (order + extra)
+        ratio = res[0][i] / res[1][i]
+        assert 0.7 * expect < ratio < 1.4 * expect, (i, ratio, res)
+
+
+def test_nonparaxial_tends_to_paraxial():
+    """As eps -> 0 the nonparaxial beam becomes the paraxial Gaussian of Eq. (21):
+    the difference in E_p, B_q relative to a0 shrinks proportionally to eps."""
+    diffs = []
+    for w0 in (2.0, 4.0):
+        base = dict(a0=1.0, tau=4000.0, t_ref=0.0, x_ref=0.0, x_f=0.0, w0=w0,
+                    dispersion=units.DISP_VACUUM, pol=0)
+        Pn = pulses.Pulse(dict(type="gauss_np", np_order=4, **base))
+        Pg = pulses.Pulse(dict(type="gauss", d_f=3, **base))
+        X = np.linspace(-0.5, 0.5, 41) * Pg.x_r
+        Y = 0.5 * Pg.w0 * np.ones_like(X)
+        Z = -0.3 * Pg.w0 * np.ones_like(X)
+        En, Bn = pulses.analytic_fields(Pn, 0.0, X, Y, Z)
+        Eg, Bg = pulses.analytic_fields(Pg, 0.0, X, Y, Z)
+        diffs.append(max(np.abs(En[1] - Eg[1]).max(), np.abs(Bn[2] - Bg[2]).max(),
+                         np.abs(En[0] - Eg[0]).max()))
+    assert diffs[1] < 0.6 * diffs[0] and diffs[0] < 0.2, diffs
