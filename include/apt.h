@@ -148,6 +148,7 @@ typedef struct ap_layout {
     size_t real_bytes;       /* 4 or 8 */
     int64_t n_cells;
     int64_t n_tiles;
+    size_t ckpt_slot_bytes;  /* dim 0: bytes of one adjoint checkpoint slot */
 } ap_layout;
 
 typedef struct ap_buffers {
@@ -249,12 +250,25 @@ ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
  * Asynchronous on the context stream. */
 ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, void *E, void *B);
 
-/* Gridless adjoint (dim 0): gradient of L = sum_p dL_du[p] . u_p(final)
- * + dL_dproxy[p] proxy_p with respect to the pulse parameters listed in
- * param_ids (AP_PARAM_*), over the steps advanced by the last ap_step
- * call made with AP_STEP_RECORD.  dL_du: device, 3 reals per particle
- * (component-major, 3 arrays of n); dL_dproxy may be NULL.  Writes
- * n_params FP64 values to dL_dparams (host).  Synchronises. */
+/* Adjoint checkpoint storage (gridless runs).  dev: caller-owned device
+ * buffer of `bytes`; segment K: steps between stored states.  Recording n
+ * steps needs ceil(n/K) + K slots of ap_layout.ckpt_slot_bytes (outer
+ * checkpoints plus the replay buffer of one segment).  AP_E_UNSUPPORTED for
+ * gridded runs. */
+ap_status ap_set_checkpoints(ap_ctx *ctx, void *dev, size_t bytes, int32_t segment);
+
+/* Gradient of a particle observable with respect to pulse parameters over
+ * the steps of the last ap_step call made with AP_STEP_RECORD (gridless
+ * runs; the state must not have been advanced since).  The observable is
+ *     L = sum_p dL_du[p] . u_p(final) + dL_dproxy[p] * proxy_p(final),
+ * i.e. the caller passes the cotangents of the final momenta (device,
+ * component-major, 3 arrays of n reals of the context precision) and,
+ * optionally, of the emission proxies (device, n reals, or NULL).  The
+ * reverse sweep replays each segment from its checkpoint and runs the
+ * hand-written adjoint of the analytic field, Boris push, move and proxy.
+ * param_ids (host): AP_PARAM_* values, each at most once; the focal position
+ * is x_f (x0_ff for the flying focus).  Writes n_params FP64 derivatives to
+ * dL_dparams (host) in lambda units.  Synchronises the stream. */
 #define AP_PARAM_A0      0
 #define AP_PARAM_W0      1
 #define AP_PARAM_XF      2

@@ -102,7 +102,7 @@ def _field_functions():
     E = [sp.I * (A + sp.diff(divA, x)), sp.I * sp.diff(divA, y), sp.I * sp.diff(divA, z)]
     B = [sp.Integer(0) * A, sp.diff(A, z), -sp.diff(A, y)]
     carrier = sp.exp(-sp.I * z) / sp.I
-    out = [sp.lambdify((x, y, z, w0, e2w, e4w), sp.expand(comp * carrier), "numpy") for comp in E + B]
+    out = [sp.lambdify((x, y, z, w0, e2w, e4w), sp.expand(comp * carrier), "numpy", cse=True) for comp in E + B]
     return out
 
 

@@ -330,12 +330,26 @@ def step(grid, species, pulse, field_update=True):
     return moved
 
 
-def gridless_step(t, dt, X, u, q_over_m, pulse):
+def emission_proxy(u0, u1, E, B, dt):
+    """Radiated-power proxy of one step (Lienard form with the 2 r_e/3 factor dropped):
+    gamma^2 [ |E + beta x B|^2 - (beta . E)^2 ] dt, with u_bar = (u0 + u1)/2."""
+    ub = 0.5 * (u0 + u1)
+    g = gamma_of(ub)
+    beta = ub / g
+    F = E + np.cross(beta, B, axis=0)
+    return g ** 2 * (np.sum(F * F, axis=0) - np.sum(beta * E, axis=0) ** 2) * dt
+
+
+def gridless_step(t, dt, X, u, q_over_m, pulse, with_proxy=False):
     """Test-particle step with no grid: analytic fields only, FP64 lab positions.
 
-    X has shape (3, N) (internal units).  Returns (X^{n+1}, u^{n+1/2}).
+    X has shape (3, N) (internal units).  Returns (X^{n+1}, u^{n+1/2}) and, with
+    ``with_proxy``, the step's emission-proxy increment.
     """
     E, B = _pulses.analytic_fields(pulse, t, X[0], X[1], X[2])
     u_new = boris(u, E, B, q_over_m, dt)
     gam = gamma_of(u_new)
-    return X + dt * u_new / gam, u_new
+    X_new = X + dt * u_new / gam
+    if with_proxy:
+        return X_new, u_new, emission_proxy(u, u_new, E, B, dt)
+    return X_new, u_new

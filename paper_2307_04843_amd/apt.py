@@ -25,7 +25,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
-            "ap_get_time", "ap_eval_pulse", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
+            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
             "ap_last_error")
 
 
@@ -47,7 +47,7 @@ class ap_particles(C.Structure):
 
 class ap_layout(C.Structure):
     _fields_ = [("grid_bytes", C.c_size_t), ("work_bytes", C.c_size_t), ("real_bytes", C.c_size_t),
-                ("n_cells", C.c_int64), ("n_tiles", C.c_int64)]
+                ("n_cells", C.c_int64), ("n_tiles", C.c_int64), ("ckpt_slot_bytes", C.c_size_t)]
 
 
 class ap_buffers(C.Structure):
@@ -108,6 +108,7 @@ def load():
         "ap_get_time": (C.c_int32, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
         "ap_eval_pulse": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p,
                                       C.c_void_p]),
+        "ap_set_checkpoints": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
         "ap_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(C.c_int32),
                                     C.c_int32, P(C.c_double)]),
         "ap_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -176,6 +177,11 @@ def ap_get_time(ctx):
 def ap_eval_pulse(ctx, n, xyz_ptr, t, e_ptr, b_ptr):
     _check(load().ap_eval_pulse(ctx, int(n), C.c_void_p(xyz_ptr), float(t), C.c_void_p(e_ptr),
                                 C.c_void_p(b_ptr)), "ap_eval_pulse")
+
+
+def ap_set_checkpoints(ctx, dev_ptr, nbytes, segment):
+    _check(load().ap_set_checkpoints(ctx, C.c_void_p(dev_ptr), int(nbytes), int(segment)),
+           "ap_set_checkpoints")
 
 
 def ap_backward(ctx, species, dl_du_ptr, dl_dproxy_ptr, param_ids):

@@ -1,0 +1,102 @@
+"""Differentiable gridless runs: torch.autograd.Function over ap_step/ap_backward.
+
+``GridlessRun`` owns a gridless Simulation, its initial particle state and a
+checkpoint buffer.  ``APTRun.apply(params, run)`` resets the particles to the
+initial state, applies the pulse parameters ``params`` (float64 tensor, in the
+order of ``run.param_names``, lambda units), advances ``run.n_steps`` steps with
+checkpoint recording and returns the final momenta u (3, N) and the emission
+proxies (N,).  Its backward calls the library's hand-written adjoint
+(ap_backward) and returns dL/dparams.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import apt
+from .sim import Simulation
+
+PARAM_IDS = {"a0": apt.AP_PARAM_A0, "w0": apt.AP_PARAM_W0, "x_f": apt.AP_PARAM_XF,
+             "beta_f": apt.AP_PARAM_BETA_F, "chirp": apt.AP_PARAM_CHIRP}
+
+
+class GridlessRun:
+    def __init__(self, state, pulse_kind, pulse_params, param_names, n_steps, dt, t0=0.0,
+                 vcell=1.0, precision="f32", q=-1.0, m=1.0, segment=None, proxy=True):
+        self.sim = Simulation(0, dx=(vcell,) * 3, x_min=(0.0, 0.0, 0.0), t0=t0, dt=dt, precision=precision,
+                              species=[dict(q=q, m=m, state=state)], proxy=proxy)
+        self.kind = pulse_kind
+        self.base = dict(pulse_params)
+        self.param_names = list(param_names)
+        for nm in self.param_names:
+            if nm not in PARAM_IDS:
+                raise ValueError("unknown parameter %r" % nm)
+        self.n_steps = int(n_steps)
+        self.segment = int(segment or max(1, int(math.sqrt(self.n_steps))))
+        nseg = -(-self.n_steps // self.segment)
+        slot = int(self.sim.layout.ckpt_slot_bytes)
+        self.ckpt = torch.empty(max(2, nseg + self.segment) * slot, dtype=torch.uint8, device=self.sim.device)
+        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        a = self.sim.arrays[0]
+        self._init = {k: [t.clone() for t in a[k]] for k in ("icell", "off", "u")}
+        self._t0 = t0
+
+    def _reset(self):
+        a = self.sim.arrays[0]
+        for k in ("icell", "off", "u"):
+            for dst, src in zip(a[k], self._init[k]):
+                dst.copy_(src)
+        if a["proxy"] is not None:
+            a["proxy"].zero_()
+        # rewind the clock: a fresh context keeps the library state simple
+        apt.ap_destroy(self.sim.ctx)
+        self.sim.ctx = apt.ap_init(self.sim.grid_desc, self.sim.sp_desc, self.sim.buffers,
+                                   self.sim.stream.cuda_stream)
+        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+
+    def forward(self, values):
+        self._reset()
+        prm = dict(self.base)
+        for nm, v in zip(self.param_names, values):
+            prm["x0_ff" if (nm == "x_f" and self.kind == "ff") else nm] = float(v)
+        self.sim.set_pulse(self.kind, **prm)
+        self.sim.step(self.n_steps, flags=apt.AP_STEP_RECORD)
+        a = self.sim.arrays[0]
+        u = torch.stack([t.clone() for t in a["u"]])
+        if a["proxy"] is not None:
+            pr = a["proxy"].view(-1, 2)
+            proxy = pr[:, 0].double() + pr[:, 1].double()
+        else:
+            proxy = torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
+        return u, proxy
+
+    def backward(self, grad_u, grad_proxy):
+        dt = self.sim.dtype
+        gu = (grad_u if grad_u is not None else torch.zeros((3, self.sim.sp_desc[0].n), device=self.sim.device))
+        gu = gu.to(device=self.sim.device, dtype=dt).contiguous()
+        gp_ptr = None
+        gp = None
+        if grad_proxy is not None:
+            gp = grad_proxy.to(device=self.sim.device, dtype=dt).contiguous()
+            gp_ptr = gp.data_ptr()
+        ids = [PARAM_IDS[nm] for nm in self.param_names]
+        torch.cuda.synchronize(self.sim.device)
+        return apt.ap_backward(self.sim.ctx, 0, gu.data_ptr(), gp_ptr, ids)
+
+    def close(self):
+        self.sim.close()
+
+
+class APTRun(torch.autograd.Function):
+    """params (float64, CPU) -> (u_final (3, N), proxy (N,)) through the HIP path."""
+
+    @staticmethod
+    def forward(ctx, params, run):
+        ctx.run = run
+        u, proxy = run.forward(params.detach().cpu().double().tolist())
+        return u, proxy
+
+    @staticmethod
+    def backward(ctx, grad_u, grad_proxy):
+        g = ctx.run.backward(grad_u, grad_proxy)
+        return torch.tensor(g, dtype=torch.float64), None

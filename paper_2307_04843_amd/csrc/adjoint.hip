@@ -1,0 +1,238 @@
+// Adjoint of the gridless step (analytic field + Boris push + move + emission
+// proxy) for gradients of particle observables with respect to the pulse
+// parameters.
+//
+// Forward step n (per particle):  E, B = field(x^n, t^n; theta)
+//     u^{n+1/2} = Boris(u^{n-1/2}, E, B),   x^{n+1} = x^n + dt u^{n+1/2}/gamma,
+//     proxy += P(u^{n-1/2}, u^{n+1/2}, E, B).
+// Reverse step n, with lx = dL/dx^{n+1}, lu = dL/du^{n+1/2}, lp = dL/dproxy:
+//     lu1 = lu + dt (lx - v (v . lx))/gamma + lp dP/du1
+//     lu0 = J_u^T lu1 + lp dP/du0,  lE = J_E^T lu1 + lp dP/dE,  lB = J_B^T lu1 + lp dP/dB
+//     lx <- lx + (dE/dx)^T lE + (dB/dx)^T lB,   g_theta += (dE/dtheta)^T lE + (dB/dtheta)^T lB
+//     lu <- lu0.
+// The Jacobians come from forward-mode dual numbers: 8 tangents through the
+// same generic pulse code the forward kernels use (slots: x, y, z, a0, w0,
+// focal position, beta_f, chirp), 9 through the Boris rotation and 12
+// through the proxy.  Adjoint state and gradient partials are FP64.
+#include "kernels.h"
+
+namespace apt {
+
+constexpr int kAdjN = 8;
+
+template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev &P) {
+    using D8 = Dual<T, kAdjN>;
+    using I8 = DualD<T, kAdjN>;
+    PulseVar<D8> V;
+    V.a0 = D8::var(T(P.a0), 3);
+    const double w0 = P.w0 > 0.0 ? P.w0 : 1.0;
+    auto wd = [&](double v, double dv) {
+        D8 r(v);
+        r.d[4] = T(dv);
+        return r;
+    };
+    V.inv_xr = wd(P.inv_xr, -2.0 * P.inv_xr / w0);
+    if (P.type == PT_FF) V.inv_xr.d[6] = T(P.inv_xr / (1.0 - P.beta_f));
+    V.inv_w0sq = wd(P.inv_w0sq, -2.0 * P.inv_w0sq / w0);
+    V.inv_w0 = wd(P.inv_w0, -P.inv_w0 / w0);
+    V.eps = wd(P.eps, -P.eps / w0);
+    V.np_e2 = wd(P.np_e2, -2.0 * P.np_e2 / w0);
+    V.np_e4 = wd(P.np_e4, -4.0 * P.np_e4 / w0);
+    const int la = P.lg_l < 0 ? -P.lg_l : P.lg_l;
+    V.lg_pref = wd(P.lg_pref, -la * P.lg_pref / w0);
+    V.v_phi = D8(P.v_phi);
+    V.b_over_e = D8(P.b_over_e);
+    I8 xf(P.x_f);
+    xf.d[5] = T(1);
+    V.x_f = xf;
+    I8 x0(P.x0_ff);
+    x0.d[5] = T(1);
+    V.x0_ff = x0;
+    I8 bf(P.beta_f);
+    bf.d[6] = T(1);
+    V.beta_f = bf;
+    I8 bh(P.b_half);
+    bh.d[7] = T(0.5 / P.tau);
+    V.b_half = bh;
+    return V;
+}
+
+template <typename R>
+AP_D void boris_g(const R u0[3], const R E[3], const R B[3], R kap, R u1[3]) {
+    const R umx = u0[0] + kap * E[0], umy = u0[1] + kap * E[1], umz = u0[2] + kap * E[2];
+    const R ig = rsqrt_r(R(1.0) + umx * umx + umy * umy + umz * umz);
+    const R tx = kap * B[0] * ig, ty = kap * B[1] * ig, tz = kap * B[2] * ig;
+    const R sf = R(2.0) / (R(1.0) + tx * tx + ty * ty + tz * tz);
+    const R upx = umx + (umy * tz - umz * ty);
+    const R upy = umy + (umz * tx - umx * tz);
+    const R upz = umz + (umx * ty - umy * tx);
+    u1[0] = umx + sf * (upy * tz - upz * ty) + kap * E[0];
+    u1[1] = umy + sf * (upz * tx - upx * tz) + kap * E[1];
+    u1[2] = umz + sf * (upx * ty - upy * tx) + kap * E[2];
+}
+
+template <typename R>
+AP_D R proxy_g(const R u0[3], const R u1[3], const R E[3], const R B[3], R dt) {
+    const R bx = R(0.5) * (u0[0] + u1[0]), by = R(0.5) * (u0[1] + u1[1]), bz = R(0.5) * (u0[2] + u1[2]);
+    const R gb = sqrt_r(R(1.0) + bx * bx + by * by + bz * bz);
+    const R igb = R(1.0) / gb;
+    const R vx = bx * igb, vy = by * igb, vz = bz * igb;
+    const R fx = E[0] + (vy * B[2] - vz * B[1]);
+    const R fy = E[1] + (vz * B[0] - vx * B[2]);
+    const R fz = E[2] + (vx * B[1] - vy * B[0]);
+    const R ve = vx * E[0] + vy * E[1] + vz * E[2];
+    return gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
+}
+
+template <typename T, int PT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (p < a.n) {
+        using D8 = Dual<T, kAdjN>;
+        using I8 = DualD<T, kAdjN>;
+        I8 Xd[3];
+        T u0v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Xd[c] = I8(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
+            Xd[c].d[c] = T(1);
+            u0v[c] = a.u[c][p];
+        }
+        const PulseVar<D8> W = adjoint_vars<T>(a.P);
+        D8 E8[3], B8[3];
+        analytic_field_g<PT, D8, I8>(a.P, W, a.t, Xd[0], Xd[1], Xd[2], E8, B8);
+
+        // Boris Jacobian: tangents over (u0, E, B)
+        using D9 = Dual<T, 9>;
+        D9 uu[3], ee[3], bb[3], u1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uu[c] = D9::var(u0v[c], c);
+            ee[c] = D9::var(E8[c].v, 3 + c);
+            bb[c] = D9::var(B8[c].v, 6 + c);
+        }
+        boris_g<D9>(uu, ee, bb, D9(0.5 * a.q_over_m * a.dt), u1);
+
+        double lx[3], lu1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lx[c] = a.lam[c][p];
+            lu1[c] = a.lam[3 + c][p];
+        }
+        // move: x^{n+1} = x^n + dt u1/gamma1
+        {
+            const double v1[3] = {(double)u1[0].v, (double)u1[1].v, (double)u1[2].v};
+            const double g1 = sqrt(1.0 + v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2]);
+            const double vv[3] = {v1[0] / g1, v1[1] / g1, v1[2] / g1};
+            const double vl = vv[0] * lx[0] + vv[1] * lx[1] + vv[2] * lx[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lu1[c] += a.dt * (lx[c] - vv[c] * vl) / g1;
+        }
+        double lu0[3] = {0.0, 0.0, 0.0}, lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
+        if (a.lam_proxy) {
+            const double lp = (double)a.lam_proxy[p];
+            if (lp != 0.0) {
+                using D12 = Dual<T, 12>;
+                D12 q0[3], q1[3], qe[3], qb[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    q0[c] = D12::var(u0v[c], c);
+                    q1[c] = D12::var(u1[c].v, 3 + c);
+                    qe[c] = D12::var(E8[c].v, 6 + c);
+                    qb[c] = D12::var(B8[c].v, 9 + c);
+                }
+                const D12 P12 = proxy_g<D12>(q0, q1, qe, qb, D12(a.dt));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    lu0[c] += lp * (double)P12.d[c];
+                    lu1[c] += lp * (double)P12.d[3 + c];
+                    lE[c] += lp * (double)P12.d[6 + c];
+                    lB[c] += lp * (double)P12.d[9 + c];
+                }
+            }
+        }
+        // Boris adjoint
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lu0[c] += lu1[r] * (double)u1[r].d[c];
+                lE[c] += lu1[r] * (double)u1[r].d[3 + c];
+                lB[c] += lu1[r] * (double)u1[r].d[6 + c];
+            }
+        }
+        // field adjoint
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = lx[c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[c] + lB[k] * (double)B8[k].d[c];
+            a.lam[c][p] = acc;
+            a.lam[3 + c][p] = lu0[c];
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[3 + j] + lB[k] * (double)B8[k].d[3 + j];
+            g[j] = acc;
+        }
+    }
+    // per-block FP64 sum, accumulated into this block's slot (no atomics)
+    __shared__ double red[5][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const double s = wave_sum(g[j]);
+        if (lane == 0) red[j][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
+        a.partial[(size_t)blockIdx.x * 5 + threadIdx.x] += s;
+    }
+}
+
+template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_adjoint_step<T, PT>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s) {
+    switch (pulse) {
+    case PT_PLANE: return launch_adj<T, PT_PLANE>(a, s);
+    case PT_GAUSS: return launch_adj<T, PT_GAUSS>(a, s);
+    case PT_LG: return launch_adj<T, PT_LG>(a, s);
+    case PT_FF: return launch_adj<T, PT_FF>(a, s);
+    case PT_NP: return launch_adj<T, PT_NP>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_adjoint_step<float>(int, const AdjointArgs<float> &, hipStream_t);
+template hipError_t launch_adjoint_step<double>(int, const AdjointArgs<double> &, hipStream_t);
+
+// lam[0..2] = 0, lam[3..5] = dL/du (as FP64), partial = 0
+template <typename T>
+__global__ void k_adjoint_init(double *lam0, double *lam1, double *lam2, double *lam3, double *lam4, double *lam5,
+                               const T *dl_du, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    lam0[p] = 0.0;
+    lam1[p] = 0.0;
+    lam2[p] = 0.0;
+    lam3[p] = (double)dl_du[p];
+    lam4[p] = (double)dl_du[n + p];
+    lam5[p] = (double)dl_du[2 * n + p];
+}
+template <typename T> hipError_t launch_adjoint_init(double *const lam[6], const T *dl_du, int n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_adjoint_init<T>), dim3((n + 255) / 256), dim3(256), 0, s, lam[0], lam[1], lam[2], lam[3],
+                       lam[4], lam[5], dl_du, n);
+    return hipGetLastError();
+}
+template hipError_t launch_adjoint_init<float>(double *const[6], const float *, int, hipStream_t);
+template hipError_t launch_adjoint_init<double>(double *const[6], const double *, int, hipStream_t);
+
+}  // namespace apt

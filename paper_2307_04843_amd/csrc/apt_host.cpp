@@ -51,6 +51,10 @@ struct RunShape {
 
 struct WorkLayout {
     size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, total = 0;
+    size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
+    int adj_blocks = 0;
+    size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
+    size_t slot_off[kMaxSpecies] = {};     // species block offsets inside a slot
     size_t count[kMaxSpecies] = {}, start[kMaxSpecies] = {}, rank[kMaxSpecies] = {};
     size_t alt_cell[kMaxSpecies] = {}, alt_off[kMaxSpecies][3] = {}, alt_u[kMaxSpecies][3] = {};
     size_t alt_w[kMaxSpecies] = {}, alt_id[kMaxSpecies] = {};
@@ -172,6 +176,20 @@ WorkLayout make_layout(const RunShape &s) {
             L.alt_id[i] = take(N * 4);
         }
     }
+    if (s.dim == 0) {
+        int64_t nmax = 0;
+        for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
+        for (int c = 0; c < 6; ++c) L.lam[c] = take((size_t)nmax * 8);
+        L.adj_blocks = (int)((nmax + 255) / 256);
+        if (L.adj_blocks < 1) L.adj_blocks = 1;
+        L.adj_partial = take((size_t)L.adj_blocks * 5 * 8);
+        size_t so = 0;
+        for (int i = 0; i < s.nsp; ++i) {
+            L.slot_off[i] = so;
+            so += align_up((size_t)s.np[i] * (12 + 6 * s.real), 256);
+        }
+        L.slot_bytes = so;
+    }
     L.total = align_up(off, 256);
     return L;
 }
@@ -212,6 +230,11 @@ struct ap_ctx {
     int64_t acc_n[4] = {0, 0, 0, 0};
     int64_t acc_pushes = 0;
     int64_t push_since_read = 0;
+    // adjoint checkpoints (gridless)
+    unsigned char *ckpt = nullptr;
+    size_t ckpt_bytes = 0;
+    int64_t segment = 0;
+    int64_t rec_n = 0, rec_step0 = 0;
 
     unsigned char *work() const { return static_cast<unsigned char *>(buf.work); }
     template <typename X> X *wp(size_t off) const { return reinterpret_cast<X *>(work() + off); }
@@ -257,6 +280,9 @@ ap_status hip_fail(hipError_t e, const char *where) {
 
 template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags);
 template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
+template <typename T>
+ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                        double *out);
 
 double laguerre_host(int n, int a, double x) {
     double l0 = 1.0, l1 = 1.0 + a - x;
@@ -288,6 +314,7 @@ ap_status ap_query_layout(const ap_grid_desc *grid, const ap_species_desc *speci
         out->real_bytes = s.real;
         out->n_cells = s.ncell;
         out->n_tiles = s.ntiles;
+        out->ckpt_slot_bytes = L.slot_bytes;
         return AP_OK;
     } catch (...) {
         return fail(AP_E_NOMEM, "host allocation failed");
@@ -479,7 +506,18 @@ ap_status ap_step(ap_ctx *c, int64_t n_steps, uint32_t flags) {
     if (c->s.dim == 0 && (flags & (AP_STEP_CONTINUITY | AP_STEP_NO_YEE)))
         return fail(AP_E_ARG, "grid flags on a gridless run");
     if (c->s.dim > 0 && (flags & AP_STEP_RECORD)) return fail(AP_E_UNSUPPORTED, "adjoint recording needs dim 0");
-    if (flags & AP_STEP_RECORD) return fail(AP_E_UNSUPPORTED, "adjoint recording not available in this build");
+    if (flags & AP_STEP_RECORD) {
+        if (!c->ckpt) return fail(AP_E_STATE, "ap_set_checkpoints must be called before recording");
+        const int64_t nseg = (n_steps + c->segment - 1) / c->segment;
+        const int64_t need = nseg + c->segment;
+        if ((size_t)need * c->L.slot_bytes > c->ckpt_bytes)
+            return fail(AP_E_ARG, "checkpoint buffer too small: need " + std::to_string(need) + " slots of " +
+                                      std::to_string(c->L.slot_bytes) + " bytes");
+        c->rec_n = n_steps;
+        c->rec_step0 = c->step;
+    } else {
+        c->rec_n = 0;   // any unrecorded step invalidates the recording
+    }
     try {
         for (int64_t k = 0; k < n_steps; ++k) {
             ap_status st;
@@ -611,9 +649,39 @@ ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void 
     return AP_OK;
 }
 
-ap_status ap_backward(ap_ctx *c, int32_t, const void *, const void *, const int32_t *, int32_t, double *) {
+ap_status ap_set_checkpoints(ap_ctx *c, void *dev, size_t bytes, int32_t segment) {
     if (!c) return fail(AP_E_ARG, "context is NULL");
-    return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
+    if (c->s.dim != 0) return fail(AP_E_UNSUPPORTED, "checkpoints are for gridless runs");
+    if (segment < 1) return fail(AP_E_ARG, "segment must be >= 1");
+    if (!dev || bytes < 2 * c->L.slot_bytes) return fail(AP_E_ARG, "checkpoint buffer NULL or smaller than two slots");
+    c->ckpt = static_cast<unsigned char *>(dev);
+    c->ckpt_bytes = bytes;
+    c->segment = segment;
+    c->rec_n = 0;
+    return AP_OK;
+}
+
+ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void *dl_dproxy,
+                      const int32_t *param_ids, int32_t n_params, double *out) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (c->s.dim != 0) return fail(AP_E_UNSUPPORTED, "the adjoint covers gridless runs");
+    if (c->rec_n <= 0) return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
+    if (c->step != c->rec_step0 + c->rec_n) return fail(AP_E_STATE, "the state moved past the recorded window");
+    if (species < 0 || species >= c->s.nsp) return fail(AP_E_ARG, "species index out of range");
+    if (!dl_du || !out || (n_params > 0 && !param_ids)) return fail(AP_E_ARG, "NULL argument");
+    if (n_params < 0 || n_params > 5) return fail(AP_E_ARG, "n_params must be 0..5");
+    for (int k = 0; k < n_params; ++k) {
+        if (param_ids[k] < AP_PARAM_A0 || param_ids[k] > AP_PARAM_CHIRP) return fail(AP_E_ARG, "unknown parameter id");
+        for (int j = 0; j < k; ++j)
+            if (param_ids[j] == param_ids[k]) return fail(AP_E_ARG, "repeated parameter id");
+    }
+    if (c->P.type == PT_NONE) return fail(AP_E_STATE, "no pulse set");
+    try {
+        return c->s.prec == AP_F64 ? backward_impl<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
+                                   : backward_impl<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
+    } catch (...) {
+        return fail(AP_E_NOMEM, "host allocation failed");
+    }
 }
 
 ap_status ap_timing_enable(ap_ctx *c, int32_t enable) {
@@ -654,7 +722,7 @@ ap_status ap_timing_read(ap_ctx *c, ap_timing *out, int32_t reset) {
 
 ap_status ap_destroy(ap_ctx *c) {
     if (!c) return AP_OK;
-    if (c->stream || true) hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->stream);
     for (const TimedPair &tp : c->pending) { hipEventDestroy(tp.a); hipEventDestroy(tp.b); }
     for (hipEvent_t e : c->pool) hipEventDestroy(e);
     delete c;
@@ -665,30 +733,144 @@ ap_status ap_destroy(ap_ctx *c) {
 
 namespace {
 
-template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t) {
+// Gridless arguments for species i reading from and writing to the given state.
+template <typename T>
+GridlessArgs<T> gridless_args(ap_ctx *c, int i, int32_t *const icell[3], T *const off[3], T *const u[3],
+                              int32_t *const icell_out[3], T *const off_out[3], T *const u_out[3], T *proxy,
+                              double t) {
     const RunShape &s = c->s;
+    GridlessArgs<T> a{};
+    for (int k = 0; k < 3; ++k) {
+        a.icell[k] = icell[k];
+        a.off[k] = off[k];
+        a.u[k] = u[k];
+        a.icell_out[k] = icell_out[k];
+        a.off_out[k] = off_out[k];
+        a.u_out[k] = u_out[k];
+        a.dx[k] = s.dx[k];
+        a.x_min[k] = s.x_min[k];
+    }
+    a.proxy = proxy;
+    a.n = (int)s.np[i];
+    a.q_over_m = s.q[i] / s.m[i];
+    a.dt = s.dt;
+    a.t = t;
+    a.n_bad = c->counters() + 1;
+    a.P = c->P;
+    return a;
+}
+
+// Pointers of species i inside checkpoint slot k.
+template <typename T> void slot_ptrs(ap_ctx *c, int64_t k, int i, int32_t *icell[3], T *off[3], T *u[3]) {
+    const size_t N = (size_t)c->s.np[i];
+    unsigned char *base = c->ckpt + (size_t)k * c->L.slot_bytes + c->L.slot_off[i];
+    for (int a = 0; a < 3; ++a) icell[a] = reinterpret_cast<int32_t *>(base) + a * N;
+    T *r = reinterpret_cast<T *>(base + 12 * N);
+    for (int a = 0; a < 3; ++a) {
+        off[a] = r + a * N;
+        u[a] = r + (3 + a) * N;
+    }
+}
+
+template <typename T> ap_status copy_state_to_slot(ap_ctx *c, int64_t k) {
+    for (int i = 0; i < c->s.nsp; ++i) {
+        const size_t N = (size_t)c->s.np[i];
+        if (N == 0) continue;
+        int32_t *ic[3];
+        T *off[3], *u[3];
+        slot_ptrs<T>(c, k, i, ic, off, u);
+        const ap_particles &p = c->buf.sp[i];
+        for (int a = 0; a < 3; ++a) {
+            HIPCHK(hipMemcpyAsync(ic[a], p.icell[a], N * 4, hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+            HIPCHK(hipMemcpyAsync(off[a], p.off[a], N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+            HIPCHK(hipMemcpyAsync(u[a], p.u[a], N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint");
+        }
+    }
+    return AP_OK;
+}
+
+template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags) {
+    const RunShape &s = c->s;
+    if (flags & AP_STEP_RECORD) {
+        const int64_t k = c->step - c->rec_step0;
+        if (k % c->segment == 0) {
+            const ap_status st = copy_state_to_slot<T>(c, k / c->segment);
+            if (st != AP_OK) return st;
+        }
+    }
     Timer tm(c, 0);
     for (int i = 0; i < s.nsp; ++i) {
         if (s.np[i] == 0) continue;
         const ap_particles &p = c->buf.sp[i];
-        GridlessArgs<T> a{};
-        for (int k = 0; k < 3; ++k) {
-            a.icell[k] = p.icell[k];
-            a.off[k] = static_cast<T *>(p.off[k]);
-            a.u[k] = static_cast<T *>(p.u[k]);
-            a.dx[k] = s.dx[k];
-            a.x_min[k] = s.x_min[k];
-        }
-        a.proxy = static_cast<T *>(p.proxy);
-        a.n = (int)s.np[i];
-        a.q_over_m = s.q[i] / s.m[i];
-        a.dt = s.dt;
-        a.t = s.t0 + (double)c->step * s.dt;
-        a.n_bad = c->counters() + 1;
-        a.P = c->P;
+        T *off[3] = {static_cast<T *>(p.off[0]), static_cast<T *>(p.off[1]), static_cast<T *>(p.off[2])};
+        T *u[3] = {static_cast<T *>(p.u[0]), static_cast<T *>(p.u[1]), static_cast<T *>(p.u[2])};
+        GridlessArgs<T> a = gridless_args<T>(c, i, p.icell, off, u, p.icell, off, u, static_cast<T *>(p.proxy),
+                                             s.t0 + (double)c->step * s.dt);
         HIPCHK(launch_gridless<T>(c->P.type, a, c->stream), "gridless push");
         c->push_since_read += s.np[i];
     }
+    return AP_OK;
+}
+
+template <typename T>
+ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                        double *out) {
+    const RunShape &s = c->s;
+    const WorkLayout &L = c->L;
+    const int n = (int)s.np[sp];
+    double *lam[6];
+    for (int k = 0; k < 6; ++k) lam[k] = c->wp<double>(L.lam[k]);
+    double *partial = c->wp<double>(L.adj_partial);
+    HIPCHK(launch_fill_zero<double>(partial, (size_t)L.adj_blocks * 5, c->stream), "backward");
+    HIPCHK(launch_adjoint_init<T>(lam, static_cast<const T *>(dl_du), n, c->stream), "backward");
+    const int64_t K = c->segment;
+    const int64_t nseg = (c->rec_n + K - 1) / K;
+    const int64_t inner0 = nseg;   // first inner slot
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * K;
+        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+        // replay the segment forward from its checkpoint into the inner slots
+        for (int64_t j = 0; j + 1 < len; ++j) {
+            int32_t *ic_i[3], *ic_o[3];
+            T *of_i[3], *u_i[3], *of_o[3], *u_o[3];
+            if (j == 0) slot_ptrs<T>(c, seg, sp, ic_i, of_i, u_i);
+            else slot_ptrs<T>(c, inner0 + j, sp, ic_i, of_i, u_i);
+            slot_ptrs<T>(c, inner0 + j + 1, sp, ic_o, of_o, u_o);
+            const double t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
+            GridlessArgs<T> a = gridless_args<T>(c, sp, ic_i, of_i, u_i, ic_o, of_o, u_o, nullptr, t);
+            HIPCHK(launch_gridless<T>(c->P.type, a, c->stream), "backward replay");
+        }
+        for (int64_t j = len - 1; j >= 0; --j) {
+            int32_t *ic[3];
+            T *of[3], *u[3];
+            slot_ptrs<T>(c, j == 0 ? seg : inner0 + j, sp, ic, of, u);
+            AdjointArgs<T> a{};
+            for (int k = 0; k < 3; ++k) {
+                a.icell[k] = ic[k];
+                a.off[k] = of[k];
+                a.u[k] = u[k];
+                a.dx[k] = s.dx[k];
+                a.x_min[k] = s.x_min[k];
+            }
+            for (int k = 0; k < 6; ++k) a.lam[k] = lam[k];
+            a.lam_proxy = static_cast<const T *>(dl_dproxy);
+            a.partial = partial;
+            a.n = n;
+            a.q_over_m = s.q[sp] / s.m[sp];
+            a.dt = s.dt;
+            a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
+            a.P = c->P;
+            HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+        }
+    }
+    double *sums = c->wp<double>(L.sums);
+    HIPCHK(launch_sum_partials(partial, L.adj_blocks, 5, sums, c->stream), "backward");
+    double host[5];
+    HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, c->stream), "backward");
+    HIPCHK(hipStreamSynchronize(c->stream), "backward");
+    // internal -> lambda units for the length parameters (w0, focal position)
+    const double unit[5] = {1.0, kTwoPi, kTwoPi, 1.0, 1.0};
+    for (int k = 0; k < np_; ++k) out[k] = host[ids[k]] * unit[ids[k]];
     return AP_OK;
 }
 

@@ -22,6 +22,12 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_gridless(
     T ux = a.u[0][p], uy = a.u[1][p], uz = a.u[2][p];
     if (!ok) {
         atomicAdd(a.n_bad, 1ull);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a.icell_out[c][p] = ic[c];
+            a.off_out[c][p] = of[c];
+        }
+        a.u_out[0][p] = ux; a.u_out[1][p] = uy; a.u_out[2][p] = uz;
         return;
     }
     const double X = a.x_min[0] + ((double)ic[0] + (double)of[0]) * a.dx[0];
@@ -73,12 +79,12 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_gridless(
         int sh = (int)fl;
         no -= fl;
         if (no >= T(1)) { no -= T(1); sh += 1; }
-        a.icell[c][p] = ic[c] + sh;
-        a.off[c][p] = no;
+        a.icell_out[c][p] = ic[c] + sh;
+        a.off_out[c][p] = no;
     }
-    a.u[0][p] = ux;
-    a.u[1][p] = uy;
-    a.u[2][p] = uz;
+    a.u_out[0][p] = ux;
+    a.u_out[1][p] = uy;
+    a.u_out[2][p] = uz;
 }
 
 template <typename T, int PT> static hipError_t launch_gl(const GridlessArgs<T> &a, hipStream_t s) {

@@ -57,9 +57,12 @@ template <typename T> struct PushArgs {
 };
 
 template <typename T> struct GridlessArgs {
-    int32_t *icell[3];
-    T *off[3];
-    T *u[3];
+    const int32_t *icell[3];     // source state
+    const T *off[3];
+    const T *u[3];
+    int32_t *icell_out[3];       // destination state (may alias the source)
+    T *off_out[3];
+    T *u_out[3];
     T *proxy;                    // 2 per particle or null
     int32_t n;
     double q_over_m;
@@ -70,6 +73,24 @@ template <typename T> struct GridlessArgs {
     unsigned long long *n_bad;
     PulseDev P;
 };
+
+template <typename T> struct AdjointArgs {
+    const int32_t *icell[3];     // state x^n, u^{n-1/2} of the step being reversed
+    const T *off[3];
+    const T *u[3];
+    double *lam[6];              // dL/dx (lab, internal units), dL/du (in: step n+1, out: step n)
+    const T *lam_proxy;          // dL/dproxy per particle or null
+    double *partial;             // [blocks][5] gradient partials (a0, w0, focus, beta_f, chirp)
+    int32_t n;
+    double q_over_m;
+    double dx[3];
+    double x_min[3];
+    double dt;
+    double t;
+    PulseDev P;
+};
+template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_adjoint_init(double *const lam[6], const T *dl_du, int n, hipStream_t s);
 
 struct YeeArgsBase {
     int32_t n[3];

@@ -21,6 +21,7 @@
 #pragma once
 
 #include "common.h"
+#include "dual.h"
 #include "nonparaxial_gen.h"
 
 namespace apt {
@@ -62,76 +63,107 @@ template <typename T> AP_D void laguerre(int n, int a, T x, T *L, T *dL) {
     *dL = (n - 1 == 0) ? T(-1) : -m1;
 }
 
-// Field at lab point (X, Y, Z), time t.  Output in lab components.
-// Returns false (fields zero) outside the envelope support.
-template <int PT, typename T>
-AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double Z,
-                         T E[3], T B[3]) {
-    E[0] = E[1] = E[2] = T(0);
-    B[0] = B[1] = B[2] = T(0);
+// Differentiable pulse parameters.  R is the working number type (float,
+// double or a dual number); I the matching FP64-island type.  For the plain
+// forward kernels these are the PulseDev values; the adjoint seeds tangents.
+template <typename R> struct PulseVar {
+    using I = typename NumTraits<R>::island;
+    R a0, inv_xr, inv_w0sq, inv_w0, eps, np_e2, np_e4, lg_pref, v_phi, b_over_e;
+    I x_f, x0_ff, beta_f, b_half;
+};
+
+template <typename R> AP_D PulseVar<R> plain_vars(const PulseDev &P) {
+    PulseVar<R> V;
+    V.a0 = R(P.a0);
+    V.inv_xr = R(P.inv_xr);
+    V.inv_w0sq = R(P.inv_w0sq);
+    V.inv_w0 = R(P.inv_w0);
+    V.eps = R(P.eps);
+    V.np_e2 = R(P.np_e2);
+    V.np_e4 = R(P.np_e4);
+    V.lg_pref = R(P.lg_pref);
+    V.v_phi = R(P.v_phi);
+    V.b_over_e = R(P.b_over_e);
+    V.x_f = typename PulseVar<R>::I(P.x_f);
+    V.x0_ff = typename PulseVar<R>::I(P.x0_ff);
+    V.beta_f = typename PulseVar<R>::I(P.beta_f);
+    V.b_half = typename PulseVar<R>::I(P.b_half);
+    return V;
+}
+
+// Field at lab point (X, Y, Z) (FP64 island numbers), time t.  Output in lab
+// components.  Returns false (fields zero) outside the envelope support.
+template <int PT, typename R, typename I>
+AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, const I &X, const I &Y,
+                           const I &Z, R E[3], R B[3]) {
+    using NT = NumTraits<R>;
+    E[0] = E[1] = E[2] = R(0.0);
+    B[0] = B[1] = B[2] = R(0.0);
     if constexpr (PT == PT_NONE) {
         return false;
     } else {
-        // envelope argument: eta = (t - t_ref) - (x - x_ref)/v_g + tau/2  (FP64)
-        const double eta = (t - P.t_ref) - (X - P.x_ref) * P.inv_vg + P.half_tau;
-        if (!(eta > 0.0 && eta < P.tau)) return false;
-        T se, ce;
-        sincospi_r<T>(T(eta * P.inv_tau), &se, &ce);
-        const T gam = T(P.a0) * se * se;
+        // envelope argument: eta = (t - t_ref) - (x - x_ref)/v_g + tau/2  (FP64 island)
+        const I xr = island_shift(X, P.x_ref);
+        const I eta = island_shift(island_scale(xr, -P.inv_vg), -((t - P.t_ref) + P.half_tau));
+        const double eta_v = ival(eta);
+        if (!(eta_v > 0.0 && eta_v < P.tau)) return false;
+        R se, ce;
+        sincospi_r(NT::from_island(island_scale(eta, P.inv_tau)), &se, &ce);
+        const R gam = W.a0 * se * se;
         // carrier + chirp phase, FP64, reduced to revolutions
-        const double de = eta - P.half_tau;
-        const double theta = (t - P.t_ref) - P.k * (X - P.x_ref) + P.phi0 + P.b_half * de * de;
-        double rev = theta * 0.15915494309189535;   // 1/(2 pi)
-        rev -= rint(rev);
-        const T ang_pi = T(2.0 * rev);               // Theta / pi in [-1, 1]
+        const I de = island_shift(eta, P.half_tau);
+        const I theta = island_shift(island_scale(xr, -P.k), -((t - P.t_ref) + P.phi0)) + W.b_half * de * de;
+        I rev = island_scale(theta, 0.15915494309189535);   // 1/(2 pi)
+        rev = island_shift(rev, rint(ival(rev)));
+        const R ang_pi = NT::from_island(island_scale(rev, 2.0));   // Theta / pi in [-1, 1]
 
-        T ep, ex, bx;   // pulse-frame E_p, E_x, B_x; B_q = (B0/E0) E_p
+        R ep, ex, bx;   // pulse-frame E_p, E_x, B_x; B_q = (B0/E0) E_p
         if constexpr (PT == PT_PLANE) {
-            T s, c;
-            sincospi_r<T>(ang_pi, &s, &c);
+            R s, c;
+            sincospi_r(ang_pi, &s, &c);
             ep = gam * c;
-            ex = T(0);
-            bx = T(0);
+            ex = R(0.0);
+            bx = R(0.0);
         } else {
             // pulse-frame transverse coordinates
-            T p, q;
-            if (P.pol == 0) { p = T(Y - P.y_c); q = T(Z - P.z_c); }
-            else            { p = T(Z - P.z_c); q = T(-(Y - P.y_c)); }
-            double s_d;
-            if constexpr (PT == PT_FF) s_d = P.x0_ff + P.beta_f * (t - P.t0_ff) - X;
-            else                       s_d = P.x_f - X;
-            const T zeta = T(s_d * P.inv_xr);
-            const T den = T(1) / (T(1) + zeta * zeta);          // |f|^2 = (w0/w)^2
-            const Cx<T> f(den, -zeta * den);
-            const T iw2 = T(P.inv_w0sq);
-            T r2, hp, hq;   // r^2 and (1/2) d r^2 / dp, (1/2) d r^2 / dq
+            R p, q;
+            if (P.pol == 0) { p = NT::from_island(island_shift(Y, P.y_c)); q = NT::from_island(island_shift(Z, P.z_c)); }
+            else            { p = NT::from_island(island_shift(Z, P.z_c)); q = -NT::from_island(island_shift(Y, P.y_c)); }
+            I s_d;
+            if constexpr (PT == PT_FF) s_d = W.x0_ff + island_scale(W.beta_f, t - P.t0_ff) - X;
+            else                       s_d = W.x_f - X;
+            const R zeta = NT::from_island(s_d) * W.inv_xr;
+            const R den = R(1.0) / (R(1.0) + zeta * zeta);          // |f|^2 = (w0/w)^2
+            const Cx<R> f(den, -zeta * den);
+            const R iw2 = W.inv_w0sq;
+            R r2, hp, hq;   // r^2 and (1/2) d r^2 / dp, (1/2) d r^2 / dq
             if (PT == PT_LG || PT == PT_NP || P.d_f == 3) { r2 = p * p + q * q; hp = p; hq = q; }
-            else if (P.pol == 1)           { r2 = p * p; hp = p; hq = T(0); }
-            else                           { r2 = q * q; hp = T(0); hq = q; }
-            const T rho2 = r2 * iw2;
+            else if (P.pol == 1)                          { r2 = p * p; hp = p; hq = R(0.0); }
+            else                                          { r2 = q * q; hp = R(0.0); hq = q; }
+            const R rho2 = r2 * iw2;
             // exp(-f rho2) = exp(-den rho2) * exp(i zeta den rho2)
-            const T amp = gam * exp_r<T>(-den * rho2);
-            T s, c;
-            sincospi_r<T>(ang_pi + zeta * den * rho2 * T(0.3183098861837907), &s, &c);
-            Cx<T> V(amp * c, amp * s);                   // Gamma exp(-f rho2) e^{i Theta}
+            const R amp = gam * exp_r(-(den * rho2));
+            R s, c;
+            sincospi_r(ang_pi + zeta * den * rho2 * R(0.3183098861837907), &s, &c);
+            Cx<R> V(amp * c, amp * s);                   // Gamma exp(-f rho2) e^{i Theta}
             if constexpr (PT == PT_NP) {
                 // Gaussian beam beyond the paraxial approximation: fields derived
                 // exactly from the eps^4-truncated vector potential (conjugated
                 // polynomials from nonparaxial_gen.h; explicit i's conjugated here).
-                const NpPoly<T> Q = np_polys<T>(f, rho2, T(1), T(P.np_e2), T(P.np_e4));
-                const T eps = T(P.eps), e2 = eps * eps;
-                const T xi = p * T(P.inv_w0), et = q * T(P.inv_w0);
+                const NpPoly<R> Q = np_polys<R>(f, rho2, R(1.0), W.np_e2, W.np_e4);
+                const R eps = W.eps, e2 = eps * eps;
+                const R xi = p * W.inv_w0, et = q * W.inv_w0;
                 V = f * V;                                   // conj(psi0) Gamma e^{i Theta}
-                const Cx<T> yEp = Q.G + (T(0.25) * e2) * (T(2) * Q.H + (T(4) * xi * xi) * Q.K);
-                const Cx<T> yEq = (e2 * xi * et) * Q.K;
-                const Cx<T> yEx = xi * (Cx<T>(T(0), -eps) * Q.H + (T(0.5) * e2 * eps) * Q.N);
-                const Cx<T> yBq = Q.G + Cx<T>(T(0), T(0.5) * e2) * Q.M;
-                const Cx<T> yBx = Cx<T>(T(0), -eps * et) * Q.H;
+                const Cx<R> yEp = Q.G + (R(0.25) * e2) * (R(2.0) * Q.H + (R(4.0) * xi * xi) * Q.K);
+                const Cx<R> yEq = (e2 * xi * et) * Q.K;
+                const Cx<R> yEx = xi * (Cx<R>(R(0.0), -eps) * Q.H + (R(0.5) * e2 * eps) * Q.N);
+                const Cx<R> yBq = Q.G + Cx<R>(R(0.0), R(0.5) * e2) * Q.M;
+                const Cx<R> yBx = Cx<R>(R(0.0), -(eps * et)) * Q.H;
                 ep = (yEp * V).re;
                 ex = (yEx * V).re;
                 bx = (yBx * V).re;
-                const T eq = (yEq * V).re;
-                const T bq = (yBq * V).re;
+                const R eq = (yEq * V).re;
+                const R bq = (yBq * V).re;
                 E[0] = ex;
                 B[0] = bx;
                 if (P.pol == 0) { E[1] = ep; E[2] = eq; B[2] = bq; }      // p = y, q = z
@@ -139,58 +171,64 @@ AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double
                 return true;
             } else if constexpr (PT == PT_LG) {
                 const int la = P.lg_l >= 0 ? P.lg_l : -P.lg_l;
-                const T sig = P.lg_l >= 0 ? T(1) : T(-1);
+                const R sig = P.lg_l >= 0 ? R(1.0) : R(-1.0);
                 // f^{|l|+1} (f / conj f)^{p}
-                Cx<T> fp = f;
+                Cx<R> fp = f;
                 for (int m = 0; m < la; ++m) fp = fp * f;
                 if (P.lg_p > 0) {
-                    const Cx<T> ratio = (T(1) / den) * (f * f);
+                    const Cx<R> ratio = (R(1.0) / den) * (f * f);
                     for (int m = 0; m < P.lg_p; ++m) fp = fp * ratio;
                 }
-                V = T(P.lg_pref) * (fp * V);
-                const Cx<T> pq(p, sig * q);
-                Cx<T> pw(T(1), T(0)), pwm1(T(1), T(0));
+                V = W.lg_pref * (fp * V);
+                const Cx<R> pq(p, sig * q);
+                Cx<R> pw(R(1.0), R(0.0)), pwm1(R(1.0), R(0.0));
                 for (int m = 0; m < la; ++m) { pwm1 = pw; pw = pw * pq; }
-                T Lg, dLg;
-                laguerre<T>(P.lg_p, la, T(2) * rho2 * den, &Lg, &dLg);
-                const T la_t = T(la);
+                R Lg, dLg;
+                laguerre<R>(P.lg_p, la, R(2.0) * rho2 * den, &Lg, &dLg);
+                const R la_t = R(double(la));
                 // U/V-factor A = pq^|l| L; dA/dp and dA/dq including the Gaussian factor
-                const Cx<T> A = Lg * pw;
-                const Cx<T> g2p = (T(-2) * iw2 * p) * f;   // d/dp of (-f r^2/w0^2)
-                const Cx<T> g2q = (T(-2) * iw2 * q) * f;
-                const T lp = T(4) * p * den * iw2 * dLg;
-                const T lq = T(4) * q * den * iw2 * dLg;
-                const Cx<T> Ap = (la_t * Lg) * pwm1 + lp * pw + g2p * A;
-                const Cx<T> Aq = Cx<T>(T(0), sig * la_t * Lg) * pwm1 + lq * pw + g2q * A;
-                const Cx<T> eV = A * V, pV = Ap * V, qV = Aq * V;
+                const Cx<R> A = Lg * pw;
+                const Cx<R> g2p = (R(-2.0) * iw2 * p) * f;   // d/dp of (-f r^2/w0^2)
+                const Cx<R> g2q = (R(-2.0) * iw2 * q) * f;
+                const R lp = R(4.0) * p * den * iw2 * dLg;
+                const R lq = R(4.0) * q * den * iw2 * dLg;
+                const Cx<R> Ap = (la_t * Lg) * pwm1 + lp * pw + g2p * A;
+                const Cx<R> Aq = Cx<R>(R(0.0), sig * la_t * Lg) * pwm1 + lq * pw + g2q * A;
+                const Cx<R> eV = A * V, pV = Ap * V, qV = Aq * V;
                 ep = eV.re;
-                ex = T(P.v_phi) * pV.im;            // Re{-i z} = Im z
-                bx = T(P.b_over_e) * qV.im;
+                ex = W.v_phi * pV.im;            // Re{-i z} = Im z
+                bx = W.b_over_e * qV.im;
             } else {
-                Cx<T> fV;
                 if (P.d_f == 3) {
                     V = f * V;
                 } else {
                     // principal sqrt(f) for Re f > 0, in the form without cancellation
                     // near focus: sr = sqrt((|f| + Re f)/2), si = Im f / (2 sr)
-                    const T mod = sqrt_r<T>(den);      // |f| = sqrt(den)
-                    const T sr = sqrt_r<T>(T(0.5) * (mod + f.re));
-                    const T si = f.im / (T(2) * sr);
-                    V = Cx<T>(sr, si) * V;
+                    const R mod = sqrt_r(den);      // |f| = sqrt(den)
+                    const R sr = sqrt_r(R(0.5) * (mod + f.re));
+                    const R si = f.im / (R(2.0) * sr);
+                    V = Cx<R>(sr, si) * V;
                 }
-                fV = f * V;
+                const Cx<R> fV = f * V;
                 ep = V.re;
-                ex = T(P.v_phi) * (T(-2) * iw2 * hp) * fV.im;
-                bx = T(P.b_over_e) * (T(-2) * iw2 * hq) * fV.im;
+                ex = W.v_phi * (R(-2.0) * iw2 * hp) * fV.im;
+                bx = W.b_over_e * (R(-2.0) * iw2 * hq) * fV.im;
             }
         }
-        const T bq = T(P.b_over_e) * ep;
+        const R bq = W.b_over_e * ep;
         E[0] = ex;
         B[0] = bx;
         if (P.pol == 0) { E[1] = ep; B[2] = bq; }          // p = y, q = z
         else            { E[2] = ep; B[1] = -bq; }         // p = z, q = -y
         return true;
     }
+}
+
+// Plain (non-differentiated) evaluation used by the forward kernels.
+template <int PT, typename T>
+AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double Z, T E[3], T B[3]) {
+    const PulseVar<T> W = plain_vars<T>(P);
+    return analytic_field_g<PT, T, double>(P, W, t, X, Y, Z, E, B);
 }
 
 }  // namespace apt

@@ -1,0 +1,135 @@
+"""Adjoint (ap_backward through APTRun) vs reference gradients.
+
+Workload: a replica of the head-on collision run -- electrons with gamma =
+2000 (5% spread), transverse sigma = 1 lambda, meeting a tightly focused
+eps^4 nonparaxial Gaussian pulse (w0 = 2 lambda, a0 = 20, tau = 20 lambda/c)
+at its focus, dt = 0.01 lambda/c; 2000 steps around the collision (t = 90
+... 110 lambda/c) instead of 20000, and 64 electrons.  Observable: mean
+final p_perp^2 (plus the mean emission proxy in the second test).
+
+References: (1) the FP64 oracle's Richardson-extrapolated central difference;
+(2) central differences of the HIP FP64 forward itself.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import grad as ograd
+from oracle import units
+from paper_2307_04843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+T0, DT, NSTEPS = 90.0, 0.01, 2000
+
+
+def _beam(n=32, seed=3):
+    b = inputs.beam(n, 2000.0, 0.05, 1.0, 1.0, 10.0, 1.0, seed=seed)
+    return b
+
+
+def _pulse():
+    return dict(a0=20.0, tau=20.0, t_ref=100.0, x_ref=0.0, x_f=0.0, w0=2.0, np_order=4,
+                dispersion=units.DISP_VACUUM, pol=0)
+
+
+def _run(precision, names, kind="gauss_np", pulse=None, beam=None, segment=None):
+    from paper_2307_04843_amd.autograd import GridlessRun
+    return GridlessRun(beam if beam is not None else _beam(), kind, pulse or _pulse(), names, NSTEPS, DT, t0=T0,
+                       precision=precision, segment=segment)
+
+
+def _obs_grad(run, values, proxy_weight=0.0):
+    from paper_2307_04843_amd.autograd import APTRun
+    p = torch.tensor(values, dtype=torch.float64, requires_grad=True)
+    u, proxy = APTRun.apply(p, run)
+    N = u.shape[1]
+    L = ((u[1].double() ** 2 + u[2].double() ** 2).sum() + proxy_weight * proxy.sum()) / N
+    L.backward()
+    return float(L), p.grad.numpy().copy(), u.detach().double().cpu().numpy(), proxy.detach().cpu().numpy()
+
+
+def _oracle_grad(names, values, u_final, proxy_weight, kind="gauss_np", pulse=None, beam=None, rel_h=2e-3):
+    b = beam if beam is not None else _beam()
+    X0 = b["icell"].astype(float) + b["off"].astype(float)
+    u0 = b["u"].astype(float)
+    N = u0.shape[1]
+    wu = np.zeros_like(u0)
+    wu[1] = 2 * u_final[1] / N
+    wu[2] = 2 * u_final[2] / N
+    wp = np.full(N, proxy_weight / N)
+    prm = dict(type=kind, **(pulse or _pulse()))
+    out = []
+    for nm, v in zip(names, values):
+        key = "x0_ff" if (nm == "x_f" and kind == "ff") else nm
+        prm[key] = v
+    for nm in names:
+        key = "x0_ff" if (nm == "x_f" and kind == "ff") else nm
+        g, d1, d2 = ograd.gradient(prm, key, X0, u0, -1.0, T0, DT, NSTEPS, wu, wp, rel_h=rel_h)
+        out.append(g)
+    return np.array(out)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_fp64_matches_oracle_and_fd():
+    names = ["a0", "w0", "x_f"]
+    vals = [20.0, 2.0, 0.0]
+    run = _run("f64", names)
+    try:
+        L, g, u_final, _ = _obs_grad(run, vals)
+        # central differences of the HIP FP64 forward (Richardson)
+        fd = []
+        for k, nm in enumerate(names):
+            h = 2e-3 * max(1.0, abs(vals[k]))
+
+            def Lof(v):
+                vv = list(vals)
+                vv[k] = v
+                u, _ = run.forward(vv)
+                u = u.double().cpu().numpy()
+                return float(((u[1] ** 2 + u[2] ** 2).sum()) / u.shape[1])
+            d1 = (Lof(vals[k] + h) - Lof(vals[k] - h)) / (2 * h)
+            d2 = (Lof(vals[k] + h / 2) - Lof(vals[k] - h / 2)) / h
+            fd.append((4 * d2 - d1) / 3)
+        fd = np.array(fd)
+    finally:
+        run.close()
+    go = _oracle_grad(names, vals, u_final, 0.0)
+    assert np.all(np.abs(go) > 1e-6), go
+    assert np.allclose(g, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max()), (g, fd)
+    assert np.allclose(g, go, rtol=1e-6, atol=1e-9 * np.abs(go).max()), (g, go)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_fp32_with_proxy_matches_oracle():
+    names = ["a0", "w0", "x_f"]
+    vals = [20.0, 2.0, 0.0]
+    run = _run("f32", names)
+    try:
+        L, g, u_final, _ = _obs_grad(run, vals, proxy_weight=1e-12)
+    finally:
+        run.close()
+    go = _oracle_grad(names, vals, u_final, 1e-12)
+    rel = np.abs(g - go) / np.abs(go)
+    assert np.all(rel < 1e-3), (g, go, rel)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("beta_f", [-1.0, 1.5])
+def test_adjoint_flying_focus_beta_and_chirp(beta_f):
+    """Flying focus (the 3-D flying-focus workload's pulse, gridless here): gradients
+    with respect to the focal velocity and the chirp, FP64 path vs the oracle."""
+    pulse = dict(a0=2.0, tau=30.0, t_ref=100.0, x_ref=0.0, x_f=0.0, w0=4.0, d_f=3, pol=0,
+                 beta_f=beta_f, x0_ff=0.0, t0_ff=100.0, chirp=0.05, dispersion=units.DISP_VACUUM)
+    b = inputs.beam(64, 1.5, 0.05, 2.0, 1.0, 0.0, 1.0, seed=4, direction=1.0)
+    names = ["beta_f", "chirp", "a0"]
+    vals = [beta_f, 0.05, 2.0]
+    run = _run("f64", names, kind="ff", pulse=pulse, beam=b)
+    try:
+        L, g, u_final, _ = _obs_grad(run, vals, proxy_weight=1e-2)
+    finally:
+        run.close()
+    # the chirp enters through a phase of O(1) rad at chirp = 0.05: the difference
+    # step must be small against 0.05 for the extrapolation to converge
+    go = _oracle_grad(names, vals, u_final, 1e-2, kind="ff", pulse=pulse, beam=b, rel_h=2e-4)
+    assert np.allclose(g, go, rtol=1e-6, atol=1e-9 * np.abs(go).max()), (g, go)

@@ -620,3 +620,49 @@ def test_nonparaxial_tends_to_paraxial():
         diffs.append(max(np.abs(En[1] - Eg[1]).max(), np.abs(Bn[2] - Bg[2]).max(),
                          np.abs(En[0] - Eg[0]).max()))
     assert diffs[1] < 0.6 * diffs[0] and diffs[0] < 0.2, diffs
+
+
+# ---------------------------------------------------------------------------
+# Emission proxy and reference gradients
+# ---------------------------------------------------------------------------
+
+def test_emission_proxy_relativistic_larmor_cases():
+    """The proxy is the Lienard power gamma^2 [F^2 - (beta . F)^2] with F = E + beta x B
+    (constant dropped): at rest it is |E|^2 dt; for force along the velocity it is
+    E^2 dt (the gamma^6 a^2 law); for force across it, gamma^2 E^2 dt (gamma^4 a^2)."""
+    dt = 0.1
+    E = np.array([[0.0], [3.0], [0.0]])
+    zero = np.zeros((3, 1))
+    assert np.allclose(pic.emission_proxy(zero, zero, E, zero, dt), 9.0 * dt)
+    u = np.array([[0.0], [4.0], [0.0]])      # along E
+    assert np.allclose(pic.emission_proxy(u, u, E, zero, dt), 9.0 * dt)
+    u = np.array([[4.0], [0.0], [0.0]])      # across E
+    g2 = 1 + 16.0
+    assert np.allclose(pic.emission_proxy(u, u, E, zero, dt), g2 * 9.0 * dt)
+    # a pure magnetic force across the velocity: F = beta x B
+    B = np.array([[0.0], [0.0], [2.0]])
+    beta = 4.0 / np.sqrt(g2)
+    assert np.allclose(pic.emission_proxy(u, u, zero, B, dt), g2 * (beta * 2.0) ** 2 * dt)
+
+
+def test_reference_gradient_converges_at_fourth_order():
+    """The Richardson-extrapolated central difference of the FP64 trajectory: the two
+    central differences it combines differ by O(h^2); shrinking h by 4 shrinks that
+    gap ~16x, and the extrapolated values agree far below the gap."""
+    from oracle import grad
+    from paper_2307_04843_amd import inputs
+    beam = inputs.beam(8, 20.0, 0.05, 0.5, 0.3, 0.2, 1.0, seed=5)
+    X0 = beam["icell"].astype(float) + beam["off"].astype(float)
+    u0 = beam["u"].astype(float)
+    prm = dict(type="gauss", a0=4.0, tau=6.0, t_ref=3.0, x_ref=0.0, x_f=0.1, w0=1.5, d_f=3, pol=0,
+               dispersion=units.DISP_VACUUM)
+    wu = np.zeros_like(u0)
+    wu[1] = 1.0
+    wu[2] = 0.5
+    wp = np.ones(8) * 0.1
+    args = (X0, u0, -1.0, 1.0, 0.02, 150, wu, wp)
+    g1, a1, b1 = grad.gradient(prm, "w0", *args, rel_h=4e-3)
+    g2, a2, b2 = grad.gradient(prm, "w0", *args, rel_h=1e-3)
+    gap1, gap2 = abs(a1 - b1), abs(a2 - b2)
+    assert 10.0 < gap1 / gap2 < 22.0, (gap1, gap2)
+    assert abs(g1 - g2) < 0.05 * gap2 + 1e-9 * abs(g2)
