@@ -20,10 +20,11 @@ namespace apt {
 
 constexpr int kAdjN = 8;
 
-template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev &P) {
+template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev &P, double t) {
     using D8 = Dual<T, kAdjN>;
     using I8 = DualD<T, kAdjN>;
     PulseVar<D8> V;
+    fill_step_constants(P, t, V);
     V.a0 = D8::var(T(P.a0), 3);
     const double w0 = P.w0 > 0.0 ? P.w0 : 1.0;
     auto wd = [&](double v, double dv) {
@@ -42,15 +43,11 @@ template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev 
     V.lg_pref = wd(P.lg_pref, -la * P.lg_pref / w0);
     V.v_phi = D8(P.v_phi);
     V.b_over_e = D8(P.b_over_e);
-    I8 xf(P.x_f);
-    xf.d[5] = T(1);
-    V.x_f = xf;
-    I8 x0(P.x0_ff);
-    x0.d[5] = T(1);
-    V.x0_ff = x0;
-    I8 bf(P.beta_f);
-    bf.d[6] = T(1);
-    V.beta_f = bf;
+    // s0 = x_f, or x0_ff + beta_f (t - t0_ff) for the flying focus
+    I8 s0(P.type == PT_FF ? P.x0_ff + P.beta_f * (t - P.t0_ff) : P.x_f);
+    s0.d[5] = T(1);
+    if (P.type == PT_FF) s0.d[6] = T(t - P.t0_ff);
+    V.s0 = s0;
     I8 bh(P.b_half);
     bh.d[7] = T(0.5 / P.tau);
     V.b_half = bh;
@@ -98,9 +95,9 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_adjoint_s
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
         }
-        const PulseVar<D8> W = adjoint_vars<T>(a.P);
+        const PulseVar<D8> W = adjoint_vars<T>(a.P, a.t);
         D8 E8[3], B8[3];
-        analytic_field_g<PT, D8, I8>(a.P, W, a.t, Xd[0], Xd[1], Xd[2], E8, B8);
+        analytic_field_g<PT, D8, I8>(W, Xd[0], Xd[1], Xd[2], E8, B8);
 
         // Boris Jacobian: tangents over (u0, E, B)
         using D9 = Dual<T, 9>;

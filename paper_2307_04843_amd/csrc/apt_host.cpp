@@ -640,11 +640,11 @@ ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void 
     // positions arrive in lambda units; the device function works in internal units
     if (n == 0) return AP_OK;
     if (c->s.prec == AP_F64)
-        e = launch_eval_pulse<double>(c->P.type, c->P, n, xyz, t * kTwoPi, static_cast<double *>(E),
-                                      static_cast<double *>(B), c->stream);
+        e = launch_eval_pulse<double>(c->P.type, plain_vars<double>(c->P, t * kTwoPi), n, xyz,
+                                      static_cast<double *>(E), static_cast<double *>(B), c->stream);
     else
-        e = launch_eval_pulse<float>(c->P.type, c->P, n, xyz, t * kTwoPi, static_cast<float *>(E),
-                                     static_cast<float *>(B), c->stream);
+        e = launch_eval_pulse<float>(c->P.type, plain_vars<float>(c->P, t * kTwoPi), n, xyz,
+                                     static_cast<float *>(E), static_cast<float *>(B), c->stream);
     if (e != hipSuccess) return hip_fail(e, "ap_eval_pulse");
     return AP_OK;
 }
@@ -756,7 +756,7 @@ GridlessArgs<T> gridless_args(ap_ctx *c, int i, int32_t *const icell[3], T *cons
     a.dt = s.dt;
     a.t = t;
     a.n_bad = c->counters() + 1;
-    a.P = c->P;
+    a.W = plain_vars<T>(c->P, t);
     return a;
 }
 
@@ -988,7 +988,9 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     a.t = s.t0 + (double)c->step * s.dt;
     a.n_fast = c->counters() + 0;
     a.n_bad = c->counters() + 1;
-    a.P = c->P;
+    a.q_slice = c->P.q_slice;
+    a.pulse = c->P.type;
+    a.W = plain_vars<T>(c->P, a.t);
 
     {
         Timer tm(c, 3);

@@ -65,17 +65,48 @@ template <typename T> AP_D T sqrt_r(T x);
 template <> AP_D float sqrt_r<float>(float x) { return sqrtf(x); }
 template <> AP_D double sqrt_r<double>(double x) { return sqrt(x); }
 
+// FP32: the hardware reciprocal square root, reciprocal and base-2 exponential
+// (about 1 ulp); FP64: the correctly rounded library forms.
 template <typename T> AP_D T rsqrt_r(T x);
-template <> AP_D float rsqrt_r<float>(float x) { return rsqrtf(x); }
+template <> AP_D float rsqrt_r<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <> AP_D double rsqrt_r<double>(double x) { return rsqrt(x); }
 
+template <typename T> AP_D T rcp_r(T x);
+template <> AP_D float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> AP_D double rcp_r<double>(double x) { return 1.0 / x; }
+
 template <typename T> AP_D T exp_r(T x);
-template <> AP_D float exp_r<float>(float x) { return expf(x); }
+template <> AP_D float exp_r<float>(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 template <> AP_D double exp_r<double>(double x) { return exp(x); }
 
 // sin(pi x), cos(pi x)
 template <typename T> AP_D void sincospi_r(T x, T *s, T *c);
-template <> AP_D void sincospi_r<float>(float x, float *s, float *c) { sincospif(x, s, c); }
+// FP32 sin(pi x), cos(pi x) for moderate |x| (here |x| <= ~2): reduce by
+// quarter turns q = rint(2x), r = x - q/2 in [-1/4, 1/4] (exact), then the
+// Taylor series of sin(pi r) to r^9 and cos(pi r) to r^10 (truncation below
+// 1e-9 on the reduced range), then rotate by q quarter turns.
+template <> AP_D void sincospi_r<float>(float x, float *s, float *c) {
+    const float q = rintf(2.0f * x);
+    const float r = fmaf(-0.5f, q, x);
+    const float r2 = r * r;
+    float ps = 0.08214588661112823f;                  // pi^9/9!
+    ps = fmaf(ps, r2, -0.5992645293207921f);          // -pi^7/7!
+    ps = fmaf(ps, r2, 2.5501640398773455f);           // pi^5/5!
+    ps = fmaf(ps, r2, -5.16771278004997f);            // -pi^3/3!
+    ps = fmaf(ps, r2, 3.141592653589793f);            // pi
+    const float sr = ps * r;
+    float pc = -0.025806891390014062f;                // -pi^10/10!
+    pc = fmaf(pc, r2, 0.2353306303588932f);           // pi^8/8!
+    pc = fmaf(pc, r2, -1.3352627688545893f);          // -pi^6/6!
+    pc = fmaf(pc, r2, 4.058712126416768f);            // pi^4/4!
+    pc = fmaf(pc, r2, -4.934802200544679f);           // -pi^2/2!
+    const float cr = fmaf(pc, r2, 1.0f);
+    const int k = (int)q & 3;
+    const float ss = (k & 1) ? cr : sr;
+    const float cc = (k & 1) ? sr : cr;
+    *s = (k & 2) ? -ss : ss;
+    *c = ((k + 1) & 2) ? -cc : cc;
+}
 template <> AP_D void sincospi_r<double>(double x, double *s, double *c) { sincospi(x, s, c); }
 
 template <typename T> AP_D void sincos_r(T x, T *s, T *c);

@@ -96,6 +96,13 @@ template <typename T, int N> AP_D Dual<T, N> rsqrt_r(Dual<T, N> a) {
     for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * h;
     return r;
 }
+template <typename T, int N> AP_D Dual<T, N> rcp_r(Dual<T, N> a) {
+    Dual<T, N> r; r.v = rcp_r<T>(a.v);
+    const T h = -r.v * r.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * h;
+    return r;
+}
 template <typename T, int N> AP_D Dual<T, N> exp_r(Dual<T, N> a) {
     Dual<T, N> r; r.v = exp_r<T>(a.v);
 #pragma unroll

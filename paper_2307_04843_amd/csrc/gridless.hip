@@ -34,7 +34,7 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_gridless(
     const double Y = a.x_min[1] + ((double)ic[1] + (double)of[1]) * a.dx[1];
     const double Z = a.x_min[2] + ((double)ic[2] + (double)of[2]) * a.dx[2];
     T E[3], B[3];
-    analytic_field<PT, T>(a.P, a.t, X, Y, Z, E, B);
+    analytic_field<PT, T>(a.W, X, Y, Z, E, B);
 
     const T kap = T(0.5 * a.q_over_m * a.dt);
     const T u0x = ux, u0y = uy, u0z = uz;
@@ -106,12 +106,12 @@ template <typename T> hipError_t launch_gridless(int pulse, const GridlessArgs<T
 }
 // E1, B1 at arbitrary lab points (internal units), component-major outputs.
 template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_eval_pulse(PulseDev P, int64_t n, const double *xyz, double t, T *E, T *B) {
+__global__ __launch_bounds__(256) void k_eval_pulse(PulseVar<T> W, int64_t n, const double *xyz, T *E, T *B) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     T e[3], b[3];
     const double L = 6.283185307179586;   // positions arrive in lambda units
-    analytic_field<PT, T>(P, t, xyz[i] * L, xyz[n + i] * L, xyz[2 * n + i] * L, e, b);
+    analytic_field<PT, T>(W, xyz[i] * L, xyz[n + i] * L, xyz[2 * n + i] * L, e, b);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         E[c * n + i] = e[c];
@@ -120,28 +120,28 @@ __global__ __launch_bounds__(256) void k_eval_pulse(PulseDev P, int64_t n, const
 }
 
 template <typename T, int PT>
-static hipError_t launch_ev(const PulseDev &P, int64_t n, const double *xyz, double t, T *E, T *B, hipStream_t s) {
+static hipError_t launch_ev(const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_eval_pulse<T, PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, n, xyz, t, E, B);
+    hipLaunchKernelGGL((k_eval_pulse<T, PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, xyz, E, B);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_eval_pulse(int pulse, const PulseDev &P, int64_t n, const double *xyz, double t, T *E, T *B,
+hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B,
                              hipStream_t s) {
     switch (pulse) {
-    case PT_NONE: return launch_ev<T, PT_NONE>(P, n, xyz, t, E, B, s);
-    case PT_PLANE: return launch_ev<T, PT_PLANE>(P, n, xyz, t, E, B, s);
-    case PT_GAUSS: return launch_ev<T, PT_GAUSS>(P, n, xyz, t, E, B, s);
-    case PT_LG: return launch_ev<T, PT_LG>(P, n, xyz, t, E, B, s);
-    case PT_FF: return launch_ev<T, PT_FF>(P, n, xyz, t, E, B, s);
-    case PT_NP: return launch_ev<T, PT_NP>(P, n, xyz, t, E, B, s);
+    case PT_NONE: return launch_ev<T, PT_NONE>(W, n, xyz, E, B, s);
+    case PT_PLANE: return launch_ev<T, PT_PLANE>(W, n, xyz, E, B, s);
+    case PT_GAUSS: return launch_ev<T, PT_GAUSS>(W, n, xyz, E, B, s);
+    case PT_LG: return launch_ev<T, PT_LG>(W, n, xyz, E, B, s);
+    case PT_FF: return launch_ev<T, PT_FF>(W, n, xyz, E, B, s);
+    case PT_NP: return launch_ev<T, PT_NP>(W, n, xyz, E, B, s);
     default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_eval_pulse<float>(int, const PulseDev &, int64_t, const double *, double, float *, float *,
+template hipError_t launch_eval_pulse<float>(int, const PulseVar<float> &, int64_t, const double *, float *, float *,
                                              hipStream_t);
-template hipError_t launch_eval_pulse<double>(int, const PulseDev &, int64_t, const double *, double, double *,
+template hipError_t launch_eval_pulse<double>(int, const PulseVar<double> &, int64_t, const double *, double *,
                                               double *, hipStream_t);
 
 template hipError_t launch_gridless<float>(int, const GridlessArgs<float> &, hipStream_t);

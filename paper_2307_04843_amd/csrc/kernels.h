@@ -53,7 +53,9 @@ template <typename T> struct PushArgs {
     double t;                    // time of the positions read (t^n)
     unsigned long long *n_fast;  // moves >= 1 cell (clamped)
     unsigned long long *n_bad;   // non-finite / out-of-range particles
-    PulseDev P;
+    double q_slice;              // lab y sampled by an (x, z) grid
+    int32_t pulse;               // PulseType
+    PulseVar<T> W;               // pulse constants of this step
 };
 
 template <typename T> struct GridlessArgs {
@@ -71,7 +73,7 @@ template <typename T> struct GridlessArgs {
     double dt;
     double t;
     unsigned long long *n_bad;
-    PulseDev P;
+    PulseVar<T> W;
 };
 
 template <typename T> struct AdjointArgs {
@@ -106,7 +108,7 @@ hipError_t launch_push_deposit_3d(int pulse, const PushArgs<T> &a, int threads, 
 template <typename T>
 hipError_t launch_gridless(int pulse, const GridlessArgs<T> &a, hipStream_t s);
 template <typename T>
-hipError_t launch_eval_pulse(int pulse, const PulseDev &P, int64_t n, const double *xyz, double t, T *E, T *B,
+hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B,
                              hipStream_t s);
 template <typename T>
 hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &g, int no_yee, hipStream_t s);

@@ -63,17 +63,45 @@ template <typename T> AP_D void laguerre(int n, int a, T x, T *L, T *dL) {
     *dL = (n - 1 == 0) ? T(-1) : -m1;
 }
 
-// Differentiable pulse parameters.  R is the working number type (float,
-// double or a dual number); I the matching FP64-island type.  For the plain
-// forward kernels these are the PulseDev values; the adjoint seeds tangents.
+// Pulse constants of one time step.  R is the working number type (float,
+// double or a dual number); I the matching FP64-island type.  The host builds
+// the plain version per step in FP64 (so the kernels hold few live scalars);
+// the adjoint builds a dual version with tangents on the parameters.
+//     eta   = eta0 - X / v_g                      (envelope argument)
+//     theta = th0 - k X + b_half (eta - tau/2)^2  (carrier + chirp phase)
+//     s     = s0 - X                              (distance to focus)
 template <typename R> struct PulseVar {
     using I = typename NumTraits<R>::island;
+    double eta0, inv_vg, th0, k;
+    double tau, inv_tau, half_tau;
+    double y_c, z_c;
+    I s0, b_half;
     R a0, inv_xr, inv_w0sq, inv_w0, eps, np_e2, np_e4, lg_pref, v_phi, b_over_e;
-    I x_f, x0_ff, beta_f, b_half;
+    int32_t pol, d_f, lg_l, lg_p;
 };
 
-template <typename R> AP_D PulseVar<R> plain_vars(const PulseDev &P) {
+template <typename R> AP_HD void fill_step_constants(const PulseDev &P, double t, PulseVar<R> &V) {
+    V.eta0 = (t - P.t_ref) + P.half_tau + P.x_ref * P.inv_vg;
+    V.inv_vg = P.inv_vg;
+    V.th0 = (t - P.t_ref) + P.phi0 + P.k * P.x_ref;
+    V.k = P.k;
+    V.tau = P.tau;
+    V.inv_tau = P.inv_tau;
+    V.half_tau = P.half_tau;
+    V.y_c = P.y_c;
+    V.z_c = P.z_c;
+    V.pol = P.pol;
+    V.d_f = P.d_f;
+    V.lg_l = P.lg_l;
+    V.lg_p = P.lg_p;
+}
+
+// Plain constants of the step at time t (host or device).
+template <typename R> AP_HD PulseVar<R> plain_vars(const PulseDev &P, double t) {
     PulseVar<R> V;
+    fill_step_constants(P, t, V);
+    V.s0 = P.type == PT_FF ? P.x0_ff + P.beta_f * (t - P.t0_ff) : P.x_f;
+    V.b_half = P.b_half;
     V.a0 = R(P.a0);
     V.inv_xr = R(P.inv_xr);
     V.inv_w0sq = R(P.inv_w0sq);
@@ -84,35 +112,29 @@ template <typename R> AP_D PulseVar<R> plain_vars(const PulseDev &P) {
     V.lg_pref = R(P.lg_pref);
     V.v_phi = R(P.v_phi);
     V.b_over_e = R(P.b_over_e);
-    V.x_f = typename PulseVar<R>::I(P.x_f);
-    V.x0_ff = typename PulseVar<R>::I(P.x0_ff);
-    V.beta_f = typename PulseVar<R>::I(P.beta_f);
-    V.b_half = typename PulseVar<R>::I(P.b_half);
     return V;
 }
 
 // Field at lab point (X, Y, Z) (FP64 island numbers), time t.  Output in lab
 // components.  Returns false (fields zero) outside the envelope support.
 template <int PT, typename R, typename I>
-AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, const I &X, const I &Y,
-                           const I &Z, R E[3], R B[3]) {
+AP_D bool analytic_field_g(const PulseVar<R> &W, const I &X, const I &Y, const I &Z, R E[3], R B[3]) {
     using NT = NumTraits<R>;
     E[0] = E[1] = E[2] = R(0.0);
     B[0] = B[1] = B[2] = R(0.0);
     if constexpr (PT == PT_NONE) {
         return false;
     } else {
-        // envelope argument: eta = (t - t_ref) - (x - x_ref)/v_g + tau/2  (FP64 island)
-        const I xr = island_shift(X, P.x_ref);
-        const I eta = island_shift(island_scale(xr, -P.inv_vg), -((t - P.t_ref) + P.half_tau));
+        // envelope argument eta = eta0 - X/v_g (FP64 island)
+        const I eta = island_shift(island_scale(X, -W.inv_vg), -W.eta0);
         const double eta_v = ival(eta);
-        if (!(eta_v > 0.0 && eta_v < P.tau)) return false;
+        if (!(eta_v > 0.0 && eta_v < W.tau)) return false;
         R se, ce;
-        sincospi_r(NT::from_island(island_scale(eta, P.inv_tau)), &se, &ce);
+        sincospi_r(NT::from_island(island_scale(eta, W.inv_tau)), &se, &ce);
         const R gam = W.a0 * se * se;
         // carrier + chirp phase, FP64, reduced to revolutions
-        const I de = island_shift(eta, P.half_tau);
-        const I theta = island_shift(island_scale(xr, -P.k), -((t - P.t_ref) + P.phi0)) + W.b_half * de * de;
+        const I de = island_shift(eta, W.half_tau);
+        const I theta = island_shift(island_scale(X, -W.k), -W.th0) + W.b_half * de * de;
         I rev = island_scale(theta, 0.15915494309189535);   // 1/(2 pi)
         rev = island_shift(rev, rint(ival(rev)));
         const R ang_pi = NT::from_island(island_scale(rev, 2.0));   // Theta / pi in [-1, 1]
@@ -127,18 +149,16 @@ AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, co
         } else {
             // pulse-frame transverse coordinates
             R p, q;
-            if (P.pol == 0) { p = NT::from_island(island_shift(Y, P.y_c)); q = NT::from_island(island_shift(Z, P.z_c)); }
-            else            { p = NT::from_island(island_shift(Z, P.z_c)); q = -NT::from_island(island_shift(Y, P.y_c)); }
-            I s_d;
-            if constexpr (PT == PT_FF) s_d = W.x0_ff + island_scale(W.beta_f, t - P.t0_ff) - X;
-            else                       s_d = W.x_f - X;
+            if (W.pol == 0) { p = NT::from_island(island_shift(Y, W.y_c)); q = NT::from_island(island_shift(Z, W.z_c)); }
+            else            { p = NT::from_island(island_shift(Z, W.z_c)); q = -NT::from_island(island_shift(Y, W.y_c)); }
+            const I s_d = W.s0 - X;
             const R zeta = NT::from_island(s_d) * W.inv_xr;
-            const R den = R(1.0) / (R(1.0) + zeta * zeta);          // |f|^2 = (w0/w)^2
+            const R den = rcp_r(R(1.0) + zeta * zeta);          // |f|^2 = (w0/w)^2
             const Cx<R> f(den, -zeta * den);
             const R iw2 = W.inv_w0sq;
             R r2, hp, hq;   // r^2 and (1/2) d r^2 / dp, (1/2) d r^2 / dq
-            if (PT == PT_LG || PT == PT_NP || P.d_f == 3) { r2 = p * p + q * q; hp = p; hq = q; }
-            else if (P.pol == 1)                          { r2 = p * p; hp = p; hq = R(0.0); }
+            if (PT == PT_LG || PT == PT_NP || W.d_f == 3) { r2 = p * p + q * q; hp = p; hq = q; }
+            else if (W.pol == 1)                          { r2 = p * p; hp = p; hq = R(0.0); }
             else                                          { r2 = q * q; hp = R(0.0); hq = q; }
             const R rho2 = r2 * iw2;
             // exp(-f rho2) = exp(-den rho2) * exp(i zeta den rho2)
@@ -166,25 +186,25 @@ AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, co
                 const R bq = (yBq * V).re;
                 E[0] = ex;
                 B[0] = bx;
-                if (P.pol == 0) { E[1] = ep; E[2] = eq; B[2] = bq; }      // p = y, q = z
+                if (W.pol == 0) { E[1] = ep; E[2] = eq; B[2] = bq; }      // p = y, q = z
                 else            { E[2] = ep; E[1] = -eq; B[1] = -bq; }    // p = z, q = -y
                 return true;
             } else if constexpr (PT == PT_LG) {
-                const int la = P.lg_l >= 0 ? P.lg_l : -P.lg_l;
-                const R sig = P.lg_l >= 0 ? R(1.0) : R(-1.0);
+                const int la = W.lg_l >= 0 ? W.lg_l : -W.lg_l;
+                const R sig = W.lg_l >= 0 ? R(1.0) : R(-1.0);
                 // f^{|l|+1} (f / conj f)^{p}
                 Cx<R> fp = f;
                 for (int m = 0; m < la; ++m) fp = fp * f;
-                if (P.lg_p > 0) {
-                    const Cx<R> ratio = (R(1.0) / den) * (f * f);
-                    for (int m = 0; m < P.lg_p; ++m) fp = fp * ratio;
+                if (W.lg_p > 0) {
+                    const Cx<R> ratio = rcp_r(den) * (f * f);
+                    for (int m = 0; m < W.lg_p; ++m) fp = fp * ratio;
                 }
                 V = W.lg_pref * (fp * V);
                 const Cx<R> pq(p, sig * q);
                 Cx<R> pw(R(1.0), R(0.0)), pwm1(R(1.0), R(0.0));
                 for (int m = 0; m < la; ++m) { pwm1 = pw; pw = pw * pq; }
                 R Lg, dLg;
-                laguerre<R>(P.lg_p, la, R(2.0) * rho2 * den, &Lg, &dLg);
+                laguerre<R>(W.lg_p, la, R(2.0) * rho2 * den, &Lg, &dLg);
                 const R la_t = R(double(la));
                 // U/V-factor A = pq^|l| L; dA/dp and dA/dq including the Gaussian factor
                 const Cx<R> A = Lg * pw;
@@ -199,14 +219,14 @@ AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, co
                 ex = W.v_phi * pV.im;            // Re{-i z} = Im z
                 bx = W.b_over_e * qV.im;
             } else {
-                if (P.d_f == 3) {
+                if (W.d_f == 3) {
                     V = f * V;
                 } else {
                     // principal sqrt(f) for Re f > 0, in the form without cancellation
                     // near focus: sr = sqrt((|f| + Re f)/2), si = Im f / (2 sr)
                     const R mod = sqrt_r(den);      // |f| = sqrt(den)
                     const R sr = sqrt_r(R(0.5) * (mod + f.re));
-                    const R si = f.im / (R(2.0) * sr);
+                    const R si = R(0.5) * f.im * rcp_r(sr);
                     V = Cx<R>(sr, si) * V;
                 }
                 const Cx<R> fV = f * V;
@@ -218,7 +238,7 @@ AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, co
         const R bq = W.b_over_e * ep;
         E[0] = ex;
         B[0] = bx;
-        if (P.pol == 0) { E[1] = ep; B[2] = bq; }          // p = y, q = z
+        if (W.pol == 0) { E[1] = ep; B[2] = bq; }          // p = y, q = z
         else            { E[2] = ep; B[1] = -bq; }         // p = z, q = -y
         return true;
     }
@@ -226,9 +246,8 @@ AP_D bool analytic_field_g(const PulseDev &P, const PulseVar<R> &W, double t, co
 
 // Plain (non-differentiated) evaluation used by the forward kernels.
 template <int PT, typename T>
-AP_D bool analytic_field(const PulseDev &P, double t, double X, double Y, double Z, T E[3], T B[3]) {
-    const PulseVar<T> W = plain_vars<T>(P);
-    return analytic_field_g<PT, T, double>(P, W, t, X, Y, Z, E, B);
+AP_D bool analytic_field(const PulseVar<T> &W, double X, double Y, double Z, T E[3], T B[3]) {
+    return analytic_field_g<PT, T, double>(W, X, Y, Z, E, B);
 }
 
 }  // namespace apt

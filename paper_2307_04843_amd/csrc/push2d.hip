@@ -32,14 +32,17 @@ template <typename T> AP_D void place4(int o, const T w[3], T out[4]) {
 
 AP_D int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <typename T, int PT>
+template <typename T, int PT, bool INPLACE>
 __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     const int RX = a.reg[0], RZ = a.reg[2];
     const int RC = RX * RZ;
     T *sF = sm;                                              // Ex Ey Ez Bx By Bz
-    double *sJ = reinterpret_cast<double *>(smem_raw + align_lds(6 * RC * sizeof(T)));   // Jx Jy Jz (FP64)
+    // The current tile accumulates in FP64 for both working types: ds_add_f64
+    // measured several times faster than ds_add_f32 for this access pattern.
+    using A = double;
+    A *sJ = reinterpret_cast<A *>(smem_raw + align_lds(6 * RC * sizeof(T)));   // Jx Jy Jz
 
     // XCD-aware mapping: consecutive hardware block ids go round-robin to
     // the 8 XCDs; give each XCD a contiguous run of logical tiles so that
@@ -68,9 +71,9 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         sF[3 * RC + e] = a.B[0][g];
         sF[4 * RC + e] = a.B[1][g];
         sF[5 * RC + e] = a.B[2][g];
-        sJ[0 * RC + e] = 0.0;
-        sJ[1 * RC + e] = 0.0;
-        sJ[2 * RC + e] = 0.0;
+        sJ[0 * RC + e] = A(0);
+        sJ[1 * RC + e] = A(0);
+        sJ[2 * RC + e] = A(0);
     }
     __syncthreads();
 
@@ -81,6 +84,15 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 
     for (int s = 0; s < a.nsp; ++s) {
         const SpeciesIO<T> &S = a.sp[s];
+        // in-place steps read and write the same arrays (fewer live pointers)
+        const int32_t *cell_in = INPLACE ? S.cell_out : S.cell_in;
+        const T *off_in0 = INPLACE ? S.off_out[0] : S.off_in[0];
+        const T *off_in1 = INPLACE ? S.off_out[1] : S.off_in[1];
+        const T *off_in2 = INPLACE ? S.off_out[2] : S.off_in[2];
+        const T *u_in0 = INPLACE ? S.u_out[0] : S.u_in[0];
+        const T *u_in1 = INPLACE ? S.u_out[1] : S.u_in[1];
+        const T *u_in2 = INPLACE ? S.u_out[2] : S.u_in[2];
+        const T *w_in = INPLACE ? S.w_out : S.w_in;
         const int beg = S.tile_start[tile];
         const int cnt = S.tile_start[tile + 1] - beg;
         const int pb = beg + (int)(((long long)cnt * split) / a.splits);
@@ -90,11 +102,11 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         const T cjz = T(-S.q * a.dx[2] / a.dt);
         const T cjy = T(S.q);
         for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
-            const int cell = S.cell_in[p];
-            const T offx = S.off_in[0][p];
-            const T offz = S.off_in[2][p];
-            T ux = S.u_in[0][p], uy = S.u_in[1][p], uz = S.u_in[2][p];
-            const T w = S.w_in[p];
+            const int cell = cell_in[p];
+            const T offx = off_in0[p];
+            const T offz = off_in2[p];
+            T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
+            const T w = w_in[p];
             const bool ok = (unsigned)cell < ncell && offx >= T(0) && offx < T(1) &&
                             offz >= T(0) && offz < T(1);
             if (!ok) {
@@ -103,7 +115,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                 S.off_out[0][p] = offx;
                 S.off_out[2][p] = offz;
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
-                if (S.copy_static) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+                if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
                 continue;
             }
             const int k = (int)a.fnx.div((unsigned)cell);
@@ -171,7 +183,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             T e1[3], b1[3];
             const double X = a.x_min[0] + ((double)i + (double)offx) * a.dx[0];
             const double Z = a.x_min[2] + ((double)k + (double)offz) * a.dx[2];
-            analytic_field<PT, T>(a.P, a.t, X, a.P.q_slice, Z, e1, b1);
+            analytic_field<PT, T>(a.W, X, a.q_slice, Z, e1, b1);
             const T Ex = e1[0] + e2[0], Ey = e1[1] + e2[1], Ez = e1[2] + e2[2];
             const T Bx = b1[0] + b2[0], By = b1[1] + b2[1], Bz = b1[2] + b2[2];
 
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             const T third = T(1.0 / 3.0);
             if (in_lds) {
                 const int x0 = la + bx, z0 = lb + bz;
-                double *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
+                A *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const T cz = S0z[b] + T(0.5) * DSz[b];
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int m = 0; m < 3; ++m) {
                         cum += DSx[m] * cz;
-                        atomic_add(&Jx[(z0 + b) * RX + x0 + m], (double)(fx * cum));
+                        atomic_add(&Jx[(z0 + b) * RX + x0 + m], A(fx * cum));
                     }
                 }
 #pragma unroll
@@ -237,7 +249,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
                         cum += DSz[b] * cx;
-                        atomic_add(&Jz[(z0 + b) * RX + x0 + m], (double)(fz * cum));
+                        atomic_add(&Jz[(z0 + b) * RX + x0 + m], A(fz * cum));
                     }
                 }
 #pragma unroll
@@ -246,7 +258,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     for (int m = 0; m < 4; ++m) {
                         const T wy = S0x[m] * S0z[b] + T(0.5) * DSx[m] * S0z[b] +
                                      T(0.5) * S0x[m] * DSz[b] + third * DSx[m] * DSz[b];
-                        atomic_add(&Jy[(z0 + b) * RX + x0 + m], (double)(fy * wy));
+                        atomic_add(&Jy[(z0 + b) * RX + x0 + m], A(fy * wy));
                     }
             } else {
                 int gx[4];
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             S.u_out[0][p] = ux;
             S.u_out[1][p] = uy;
             S.u_out[2][p] = uz;
-            if (S.copy_static) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+            if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
         }
     }
     __syncthreads();
@@ -307,8 +319,8 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         const size_t g = (size_t)gz * nx + gx;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double v = sJ[c * RC + e];
-            if (v != 0.0) atomic_add(&a.J[c][g], T(v));
+            const A v = sJ[c * RC + e];
+            if (v != A(0)) atomic_add(&a.J[c][g], T(v));
         }
     }
 }
@@ -319,7 +331,10 @@ static hipError_t launch2d(const PushArgs<T> &a, int threads, hipStream_t s) {
     const size_t lds = align_lds(6 * rc * sizeof(T)) + 3 * rc * sizeof(double);
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_push_deposit_2d<T, PT>), dim3(blocks), dim3(threads), lds, s, a);
+    if (a.sp[0].copy_static == 0)
+        hipLaunchKernelGGL((k_push_deposit_2d<T, PT, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_push_deposit_2d<T, PT, false>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

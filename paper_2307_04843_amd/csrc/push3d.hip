@@ -27,7 +27,7 @@ template <typename T> AP_D void place4w(int o, const T w[3], T out[4]) {
 
 AP_D int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <typename T, int PT>
+template <typename T, int PT, bool INPLACE>
 __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
@@ -78,6 +78,15 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
     // Ex(h,n,n) Ey(n,h,n) Ez(n,n,h) Bx(n,h,h) By(h,n,h) Bz(h,h,n)
     for (int s = 0; s < a.nsp; ++s) {
         const SpeciesIO<T> &S = a.sp[s];
+        // in-place steps read and write the same arrays (fewer live pointers)
+        const int32_t *cell_in = INPLACE ? S.cell_out : S.cell_in;
+        const T *off_in0 = INPLACE ? S.off_out[0] : S.off_in[0];
+        const T *off_in1 = INPLACE ? S.off_out[1] : S.off_in[1];
+        const T *off_in2 = INPLACE ? S.off_out[2] : S.off_in[2];
+        const T *u_in0 = INPLACE ? S.u_out[0] : S.u_in[0];
+        const T *u_in1 = INPLACE ? S.u_out[1] : S.u_in[1];
+        const T *u_in2 = INPLACE ? S.u_out[2] : S.u_in[2];
+        const T *w_in = INPLACE ? S.w_out : S.w_in;
         const int beg = S.tile_start[tile];
         const int cnt = S.tile_start[tile + 1] - beg;
         const int pb = beg + (int)(((long long)cnt * split) / a.splits);
@@ -85,23 +94,23 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
         const T kap = T(0.5 * S.q_over_m * a.dt);
         const T cj[3] = {T(-S.q * a.dx[0] / a.dt), T(-S.q * a.dx[1] / a.dt), T(-S.q * a.dx[2] / a.dt)};
         for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
-            const int cell = S.cell_in[p];
+            const int cell = cell_in[p];
             T off[3];
             bool ok = (unsigned)cell < ncell;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                off[c] = S.off_in[c][p];
+                off[c] = (c == 0 ? off_in0 : (c == 1 ? off_in1 : off_in2))[p];
                 ok = ok && off[c] >= T(0) && off[c] < T(1);
             }
-            T ux = S.u_in[0][p], uy = S.u_in[1][p], uz = S.u_in[2][p];
-            const T w = S.w_in[p];
+            T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
+            const T w = w_in[p];
             if (!ok) {
                 atomicAdd(a.n_bad, 1ull);
                 S.cell_out[p] = cell;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) S.off_out[c][p] = off[c];
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
-                if (S.copy_static) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+                if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
                 continue;
             }
             const int row = (int)a.fnx.div((unsigned)cell);
@@ -177,7 +186,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
             const double X = a.x_min[0] + ((double)idx[0] + (double)off[0]) * a.dx[0];
             const double Y = a.x_min[1] + ((double)idx[1] + (double)off[1]) * a.dx[1];
             const double Z = a.x_min[2] + ((double)idx[2] + (double)off[2]) * a.dx[2];
-            analytic_field<PT, T>(a.P, a.t, X, Y, Z, e1, b1);
+            analytic_field<PT, T>(a.W, X, Y, Z, e1, b1);
             const T Ex = e1[0] + e2[0], Ey = e1[1] + e2[1], Ez = e1[2] + e2[2];
             const T Bx = b1[0] + b2[0], By = b1[1] + b2[1], Bz = b1[2] + b2[2];
 
@@ -288,7 +297,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
             S.u_out[0][p] = ux;
             S.u_out[1][p] = uy;
             S.u_out[2][p] = uz;
-            if (S.copy_static) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+            if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
         }
     }
     __syncthreads();
@@ -312,6 +321,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
 
 template <typename T, int PT>
 static hipError_t launch3d(const PushArgs<T> &a0, int threads, hipStream_t s) {
+    const bool inplace = a0.sp[0].copy_static == 0;
     PushArgs<T> a = a0;
     for (int c = 0; c < 3; ++c) a.reg[c] = a.tile[c] + kLo3 + kHi3;
     const size_t rc = (size_t)a.reg[0] * a.reg[1] * a.reg[2];
@@ -319,7 +329,10 @@ static hipError_t launch3d(const PushArgs<T> &a0, int threads, hipStream_t s) {
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_push_deposit_3d<T, PT>), dim3(blocks), dim3(threads), lds, s, a);
+    if (inplace)
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, true>), dim3(blocks), dim3(threads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, false>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
