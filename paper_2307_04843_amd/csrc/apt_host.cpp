@@ -102,7 +102,7 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
             if (axis_active(s.dim, ax)) { inv2 += 1.0 / (s.dx[ax] * s.dx[ax]); dmin = std::fmin(dmin, s.dx[ax]); }
         s.dt = g->dt > 0.0 ? g->dt * kTwoPi : 0.95 / std::sqrt((double)s.dim) * dmin;
         if (!(s.dt < 1.0 / std::sqrt(inv2))) return fail(AP_E_ARG, "dt exceeds the Yee stability limit");
-        const int def2[3] = {32, 1, 16}, def3[3] = {8, 8, 8};
+        const int def2[3] = {16, 1, 8}, def3[3] = {8, 8, 4};
         for (int ax = 0; ax < 3; ++ax) {
             int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : def2[ax]);
             if (!axis_active(s.dim, ax)) t = 1;
@@ -926,9 +926,14 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sc.start = start;
             sc.ncell = (uint32_t)s.ncell;
             {
+                // The first sort starts from the caller's order (typically cell
+                // by cell) and interleaves it; later sorts start from an
+                // interleaved order, which ranks within a tile preserve, so
+                // they keep it (and write their slots contiguously).
                 const double ppc = (double)s.np[i] / (double)s.ncell;
                 int M = (int)std::lround(ppc);
-                sc.interleave = M < 1 ? 1 : (M > 64 ? 64 : M);
+                M = M < 1 ? 1 : (M > 64 ? 64 : M);
+                sc.interleave = c->sorted_once ? 1 : M;
             }
             sc.n = (int)s.np[i];
             sc.dim = s.dim;

@@ -222,11 +222,12 @@ template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterAr
     if (p >= a.n) return;
     const int cell = a.cell_src[p];
     const int tile = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
-    // Place the particle at its tile slot.  Ranks follow the previous order,
-    // which is cell-major (about M particles per cell); a ragged transpose of
-    // the tile's rank sequence with stride M puts consecutive slots in
-    // different cells, so the 64 lanes of a wave update 64 distinct current
-    // nodes in the push kernel's LDS atomics.
+    // Place the particle at its tile slot.  Ranks follow the previous order
+    // (a wave's lanes rank in lane order).  When that order is cell-major
+    // (about M particles per cell), a ragged transpose of the tile's rank
+    // sequence with stride M puts consecutive slots in different cells, so the
+    // 64 lanes of a wave update distinct current nodes in the push kernel's
+    // LDS atomics; M = 1 keeps the previous order.
     const int base = a.start[tile];
     const int cnt = a.start[tile + 1] - base;
     const int r = a.rank[p];

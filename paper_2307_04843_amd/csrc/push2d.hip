@@ -32,6 +32,46 @@ template <typename T> AP_D void place4(int o, const T w[3], T out[4]) {
 
 AP_D int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Esirkepov deposition of one particle into the LDS current tile on a WX x WZ
+// node window (rows of RX nodes; window origin x0, z0).  A 3-node axis is
+// exact when the stencil keeps its nearest node on that axis: the fourth
+// weight is then zero before and after the move, and so is every current
+// term that involves it.
+template <int WX, int WZ, typename T>
+AP_D void deposit_window(double *sJ, int RC, int RX, int x0, int z0, const T S0x[4], const T DSx[4],
+                         const T S0z[4], const T DSz[4], T fx, T fy, T fz) {
+    double *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
+    const T third = T(1.0 / 3.0);
+#pragma unroll
+    for (int b = 0; b < WZ; ++b) {
+        const T cz = S0z[b] + T(0.5) * DSz[b];
+        T cum = T(0);
+#pragma unroll
+        for (int m = 0; m < WX - 1; ++m) {
+            cum += DSx[m] * cz;
+            atomic_add(&Jx[(z0 + b) * RX + x0 + m], (double)(fx * cum));
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < WX; ++m) {
+        const T cx = S0x[m] + T(0.5) * DSx[m];
+        T cum = T(0);
+#pragma unroll
+        for (int b = 0; b < WZ - 1; ++b) {
+            cum += DSz[b] * cx;
+            atomic_add(&Jz[(z0 + b) * RX + x0 + m], (double)(fz * cum));
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < WZ; ++b)
+#pragma unroll
+        for (int m = 0; m < WX; ++m) {
+            const T wy = S0x[m] * S0z[b] + T(0.5) * DSx[m] * S0z[b] + T(0.5) * S0x[m] * DSz[b] +
+                         third * DSx[m] * DSz[b];
+            atomic_add(&Jy[(z0 + b) * RX + x0 + m], (double)(fy * wy));
+        }
+}
+
 template <typename T, int PT, bool INPLACE>
 __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -230,36 +270,13 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             const T fx = cjx * w, fz = cjz * w, fy = cjy * w * uy * ign;
             const T third = T(1.0 / 3.0);
             if (in_lds) {
+                // window width per axis, uniform over the wave
+                const bool wx4 = __any(nxn != n1x), wz4 = __any(nzn != n1z);
                 const int x0 = la + bx, z0 = lb + bz;
-                A *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const T cz = S0z[b] + T(0.5) * DSz[b];
-                    T cum = T(0);
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) {
-                        cum += DSx[m] * cz;
-                        atomic_add(&Jx[(z0 + b) * RX + x0 + m], A(fx * cum));
-                    }
-                }
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const T cx = S0x[m] + T(0.5) * DSx[m];
-                    T cum = T(0);
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        cum += DSz[b] * cx;
-                        atomic_add(&Jz[(z0 + b) * RX + x0 + m], A(fz * cum));
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const T wy = S0x[m] * S0z[b] + T(0.5) * DSx[m] * S0z[b] +
-                                     T(0.5) * S0x[m] * DSz[b] + third * DSx[m] * DSz[b];
-                        atomic_add(&Jy[(z0 + b) * RX + x0 + m], A(fy * wy));
-                    }
+                if (wx4 && wz4) deposit_window<4, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
+                else if (wx4) deposit_window<4, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
+                else if (wz4) deposit_window<3, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
+                else deposit_window<3, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
             } else {
                 int gx[4];
                 size_t gz[4];

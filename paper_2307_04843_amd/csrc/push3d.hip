@@ -27,6 +27,58 @@ template <typename T> AP_D void place4w(int o, const T w[3], T out[4]) {
 
 AP_D int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Esirkepov deposition of one particle into the LDS current tile on a W^3 node
+// window with origin (o0, o1, o2).  W = 3 is exact when no axis changes its
+// nearest node during the move (the fourth weight is zero before and after).
+template <int W, typename T>
+AP_D void deposit_window3(double *sJ, int RC, int RXY, int RX, int o0, int o1, int o2, const T (&S0)[3][4],
+                          const T (&DS)[3][4], const T (&fj)[3]) {
+    const T third = T(1.0 / 3.0);
+    auto at = [&](int comp, int i4, int j4, int k4) {
+        return sJ + comp * RC + (o2 + k4) * RXY + (o1 + j4) * RX + o0 + i4;
+    };
+    // Jx: cumulative along x of Wx = DSx (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3)
+#pragma unroll
+    for (int k4 = 0; k4 < W; ++k4)
+#pragma unroll
+        for (int j4 = 0; j4 < W; ++j4) {
+            const T cyz = S0[1][j4] * S0[2][k4] + T(0.5) * DS[1][j4] * S0[2][k4] +
+                          T(0.5) * S0[1][j4] * DS[2][k4] + third * DS[1][j4] * DS[2][k4];
+            T cum = T(0);
+#pragma unroll
+            for (int i4 = 0; i4 < W - 1; ++i4) {
+                cum += DS[0][i4] * cyz;
+                atomic_add(at(0, i4, j4, k4), (double)(fj[0] * cum));
+            }
+        }
+#pragma unroll
+    for (int k4 = 0; k4 < W; ++k4)
+#pragma unroll
+        for (int i4 = 0; i4 < W; ++i4) {
+            const T cxz = S0[0][i4] * S0[2][k4] + T(0.5) * DS[0][i4] * S0[2][k4] +
+                          T(0.5) * S0[0][i4] * DS[2][k4] + third * DS[0][i4] * DS[2][k4];
+            T cum = T(0);
+#pragma unroll
+            for (int j4 = 0; j4 < W - 1; ++j4) {
+                cum += DS[1][j4] * cxz;
+                atomic_add(at(1, i4, j4, k4), (double)(fj[1] * cum));
+            }
+        }
+#pragma unroll
+    for (int j4 = 0; j4 < W; ++j4)
+#pragma unroll
+        for (int i4 = 0; i4 < W; ++i4) {
+            const T cxy = S0[0][i4] * S0[1][j4] + T(0.5) * DS[0][i4] * S0[1][j4] +
+                          T(0.5) * S0[0][i4] * DS[1][j4] + third * DS[0][i4] * DS[1][j4];
+            T cum = T(0);
+#pragma unroll
+            for (int k4 = 0; k4 < W - 1; ++k4) {
+                cum += DS[2][k4] * cxy;
+                atomic_add(at(2, i4, j4, k4), (double)(fj[2] * cum));
+            }
+        }
+}
+
 template <typename T, int PT, bool INPLACE>
 __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -222,9 +274,11 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
             // Esirkepov on the 4x4x4 window relative to the old cell
             T S0[3][4], DS[3][4];
             int base[3];
+            bool moved_node = false;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int n1 = sh[c] + (nof[c] >= T(0.5) ? 1 : 0);
+                moved_node = moved_node || (n1 != nod[c]);
                 T w1[3];
                 tsc3w(nof[c] - T(n1 - sh[c]), w1);
                 base[c] = min(nod[c], n1) - 1;
@@ -234,59 +288,60 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) DS[c][m] = s1[m] - S0[c][m];
             }
-            const T third = T(1.0 / 3.0);
             const T fj[3] = {cj[0] * w, cj[1] * w, cj[2] * w};
-            auto addJ = [&](int comp, int i4, int j4, int k4, T v) {
-                if (in_lds) {
-                    atomic_add(&sJ[comp * RC + (loc[2] + base[2] + k4) * RXY + (loc[1] + base[1] + j4) * RX +
-                                   loc[0] + base[0] + i4], (double)v);
-                } else {
+            if (in_lds) {
+                // window width uniform over the wave
+                const int o0 = loc[0] + base[0], o1 = loc[1] + base[1], o2 = loc[2] + base[2];
+                if (__any(moved_node)) deposit_window3<4>(sJ, RC, RXY, RX, o0, o1, o2, S0, DS, fj);
+                else deposit_window3<3>(sJ, RC, RXY, RX, o0, o1, o2, S0, DS, fj);
+            } else {
+                const T third = T(1.0 / 3.0);
+                auto addJ = [&](int comp, int i4, int j4, int k4, T v) {
                     const int gx = wrap3(idx[0] + base[0] + i4, nx);
                     const int gy = wrap3(idx[1] + base[1] + j4, ny);
                     const int gz = wrap3(idx[2] + base[2] + k4, nz);
                     atomic_add(&a.J[comp][(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)], v);
-                }
-            };
-            // Jx: cumulative along x of Wx = DSx (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3)
+                };
 #pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4)
+                for (int k4 = 0; k4 < 4; ++k4)
 #pragma unroll
-                for (int j4 = 0; j4 < 4; ++j4) {
-                    const T cyz = S0[1][j4] * S0[2][k4] + T(0.5) * DS[1][j4] * S0[2][k4] +
-                                  T(0.5) * S0[1][j4] * DS[2][k4] + third * DS[1][j4] * DS[2][k4];
-                    T cum = T(0);
+                    for (int j4 = 0; j4 < 4; ++j4) {
+                        const T cyz = S0[1][j4] * S0[2][k4] + T(0.5) * DS[1][j4] * S0[2][k4] +
+                                      T(0.5) * S0[1][j4] * DS[2][k4] + third * DS[1][j4] * DS[2][k4];
+                        T cum = T(0);
 #pragma unroll
-                    for (int i4 = 0; i4 < 3; ++i4) {
-                        cum += DS[0][i4] * cyz;
-                        addJ(0, i4, j4, k4, fj[0] * cum);
+                        for (int i4 = 0; i4 < 3; ++i4) {
+                            cum += DS[0][i4] * cyz;
+                            addJ(0, i4, j4, k4, fj[0] * cum);
+                        }
                     }
-                }
 #pragma unroll
-            for (int k4 = 0; k4 < 4; ++k4)
+                for (int k4 = 0; k4 < 4; ++k4)
 #pragma unroll
-                for (int i4 = 0; i4 < 4; ++i4) {
-                    const T cxz = S0[0][i4] * S0[2][k4] + T(0.5) * DS[0][i4] * S0[2][k4] +
-                                  T(0.5) * S0[0][i4] * DS[2][k4] + third * DS[0][i4] * DS[2][k4];
-                    T cum = T(0);
+                    for (int i4 = 0; i4 < 4; ++i4) {
+                        const T cxz = S0[0][i4] * S0[2][k4] + T(0.5) * DS[0][i4] * S0[2][k4] +
+                                      T(0.5) * S0[0][i4] * DS[2][k4] + third * DS[0][i4] * DS[2][k4];
+                        T cum = T(0);
 #pragma unroll
-                    for (int j4 = 0; j4 < 3; ++j4) {
-                        cum += DS[1][j4] * cxz;
-                        addJ(1, i4, j4, k4, fj[1] * cum);
+                        for (int j4 = 0; j4 < 3; ++j4) {
+                            cum += DS[1][j4] * cxz;
+                            addJ(1, i4, j4, k4, fj[1] * cum);
+                        }
                     }
-                }
 #pragma unroll
-            for (int j4 = 0; j4 < 4; ++j4)
+                for (int j4 = 0; j4 < 4; ++j4)
 #pragma unroll
-                for (int i4 = 0; i4 < 4; ++i4) {
-                    const T cxy = S0[0][i4] * S0[1][j4] + T(0.5) * DS[0][i4] * S0[1][j4] +
-                                  T(0.5) * S0[0][i4] * DS[1][j4] + third * DS[0][i4] * DS[1][j4];
-                    T cum = T(0);
+                    for (int i4 = 0; i4 < 4; ++i4) {
+                        const T cxy = S0[0][i4] * S0[1][j4] + T(0.5) * DS[0][i4] * S0[1][j4] +
+                                      T(0.5) * S0[0][i4] * DS[1][j4] + third * DS[0][i4] * DS[1][j4];
+                        T cum = T(0);
 #pragma unroll
-                    for (int k4 = 0; k4 < 3; ++k4) {
-                        cum += DS[2][k4] * cxy;
-                        addJ(2, i4, j4, k4, fj[2] * cum);
+                        for (int k4 = 0; k4 < 3; ++k4) {
+                            cum += DS[2][k4] * cxy;
+                            addJ(2, i4, j4, k4, fj[2] * cum);
+                        }
                     }
-                }
+            }
 
             int ni[3];
 #pragma unroll

@@ -128,3 +128,20 @@ def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0):
     else:
         sim.set_pulse("none")
     return sim
+
+
+def force_scale(g, sps, P):
+    """|q/m| dt (|E_tot| + |Gamma F|) per particle at the step's start (oracle fields).
+
+    The local laser amplitude |Gamma F| enters because the carrier phase is
+    only defined to the precision of its FP64 terms (~1e-13 rad at 10^3 rad):
+    at a zero crossing of the carrier the instantaneous field is small but its
+    rounding error is set by the amplitude."""
+    out = []
+    for sp in sps:
+        E2, _ = pic.gather(g, sp.pos)
+        X, Y, Z = pic.lab_positions(g, sp.pos, P.q_slice)
+        E1, _ = pulses.analytic_fields(P, g.t, X, Y, Z)
+        amp = pulses._envelope(P, g.t, X)[0] * np.abs(pulses._profile(P, g.t, X, Y, Z)[0])
+        out.append(abs(sp.q / sp.m) * g.dt * (np.linalg.norm(E1 + E2, axis=0) + amp))
+    return out

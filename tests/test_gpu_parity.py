@@ -21,29 +21,12 @@ pytestmark = pytest.mark.gpu
 L = units.LAMBDA
 
 
-def _force_scale(g, sps, P):
-    """|q/m| dt (|E_tot| + |Gamma F|) per particle at the step's start (oracle fields).
-
-    The local laser amplitude |Gamma F| enters because the carrier phase is
-    only defined to the precision of its FP64 terms (~1e-13 rad at 10^3 rad):
-    at a zero crossing of the carrier the instantaneous field is small but its
-    rounding error is set by the amplitude."""
-    out = []
-    for sp in sps:
-        E2, _ = pic.gather(g, sp.pos)
-        X, Y, Z = pic.lab_positions(g, sp.pos, P.q_slice)
-        E1, _ = pulses.analytic_fields(P, g.t, X, Y, Z)
-        amp = pulses._envelope(P, g.t, X)[0] * np.abs(pulses._profile(P, g.t, X, Y, Z)[0])
-        out.append(abs(sp.q / sp.m) * g.dt * (np.linalg.norm(E1 + E2, axis=0) + amp))
-    return out
-
-
 def _run_one_step(case, precision, tile=(0, 0, 0)):
     sim = cases.sim_from_case(case, precision=precision, tile=tile)
     try:
         g, sps, P = cases.oracle_state(case)
         u_old = [sp.u.copy() for sp in sps]
-        fscale = _force_scale(g, sps, P)
+        fscale = cases.force_scale(g, sps, P)
         pic.step(g, sps, P)
         sim.step(1)
         out = [sim.state(i) for i in range(len(sps))]
@@ -57,15 +40,17 @@ def _run_one_step(case, precision, tile=(0, 0, 0)):
 
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
 @pytest.mark.parametrize("pulse", ["cfg2", "cfg1"])
-def test_one_step_2d_parity(precision, tol, pulse):
+@pytest.mark.parametrize("tile", [(0, 0, 0), (32, 1, 16)])
+def test_one_step_2d_parity(precision, tol, pulse, tile):
     """One full step (gather + LG/Gaussian field + Boris + move + Esirkepov + Yee) on a
-    70x40 grid (several 32x16 tiles plus ragged tails), electrons and protons."""
+    70x40 grid (several tiles, default 16x8 or 32x16, plus ragged tails), electrons and
+    protons."""
     if pulse == "cfg1":
         case = cases.make_case(n=(70, 1, 40), x_min=(0.0, 0.0, 0.0), t0_steps=150, pulse="cfg1",
                                u_scale=50.0, seed=3)
     else:
         case = cases.make_case(seed=2, u_scale=20.0)
-    g, sps, u_old, fscale, out, gf, d = _run_one_step(case, precision)
+    g, sps, u_old, fscale, out, gf, d = _run_one_step(case, precision, tile)
     n = case["n"]
     for sp, u0, fs, st in zip(sps, u_old, fscale, out):
         scale = np.maximum(np.maximum(np.linalg.norm(sp.u, axis=0), np.linalg.norm(u0, axis=0)), fs)
@@ -197,9 +182,11 @@ def _gauss_pulse_3d(dxl, dt, box):
 
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
 @pytest.mark.parametrize("kind", ["gauss", "ff"])
-def test_one_step_3d_parity(precision, tol, kind):
+@pytest.mark.parametrize("tile", [(0, 0, 0), (8, 8, 8)])
+def test_one_step_3d_parity(precision, tol, kind, tile):
     """3-D step (27-point gather per component, 4x4x4 Esirkepov window) on a 20x18x14
-    grid with 8x8x8 tiles (ragged tails on every axis), electrons and protons."""
+    grid with 8x8x4 (default) or 8x8x8 tiles (ragged tails on every axis), electrons
+    and protons."""
     dxl = 0.0625
     n = (20, 18, 14)
     dt = units.default_dt(dxl, 3)
@@ -207,7 +194,7 @@ def test_one_step_3d_parity(precision, tol, kind):
     pp = (_ff_pulse_3d if kind == "ff" else _gauss_pulse_3d)(dxl, dt, box)
     case = cases.make_case(dim=3, n=n, dxl=dxl, x_min=(0.0, 0.0, 0.0), t0_steps=int(10.0 / dt),
                            ppc=2, pulse=pp, u_scale=30.0, seed=21)
-    g, sps, u_old, fscale, out, gf, d = _run_one_step(case, precision)
+    g, sps, u_old, fscale, out, gf, d = _run_one_step(case, precision, tile)
     for sp, u0, fs, st in zip(sps, u_old, fscale, out):
         scale = np.maximum(np.maximum(np.linalg.norm(sp.u, axis=0), np.linalg.norm(u0, axis=0)), fs)
         rel = np.linalg.norm(st["u"].astype(float) - sp.u, axis=0) / scale
