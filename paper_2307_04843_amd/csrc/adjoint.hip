@@ -10,30 +10,41 @@
 //     lu0 = J_u^T lu1 + lp dP/du0,  lE = J_E^T lu1 + lp dP/dE,  lB = J_B^T lu1 + lp dP/dB
 //     lx <- lx + (dE/dx)^T lE + (dB/dx)^T lB,   g_theta += (dE/dtheta)^T lE + (dB/dtheta)^T lB
 //     lu <- lu0.
-// The Jacobians come from forward-mode dual numbers: 8 tangents through the
-// same generic pulse code the forward kernels use (slots: x, y, z, a0, w0,
-// focal position, beta_f, chirp), 9 through the Boris rotation and 12
-// through the proxy.  Adjoint state and gradient partials are FP64.
+// The field Jacobians come from forward-mode dual numbers through the same
+// generic pulse code the forward kernels use, with NT tangents: x, y, z and
+// one per requested parameter among w0, focal position, beta_f and chirp.
+// The amplitude needs no tangent: every pulse field is proportional to a0,
+// so dF/da0 = F / a0 (evaluated at a0 = 1 when a0 = 0).  9 tangents run
+// through the Boris rotation and 12 through the proxy.  Adjoint state and
+// gradient partials are FP64.
 #include "kernels.h"
 
 namespace apt {
 
-constexpr int kAdjN = 8;
+// Tangent k >= 3 carries parameter slot[k - 3]: set it to dv where that is `param`.
+template <int NT, typename T> AP_D void seed_tangent(T (&d)[NT], const int32_t (&slot)[4], int param, double dv) {
+#pragma unroll
+    for (int k = 0; k < NT - 3; ++k)
+        if (slot[k] == param) d[3 + k] = T(dv);
+}
 
-template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev &P, double t) {
-    using D8 = Dual<T, kAdjN>;
-    using I8 = DualD<T, kAdjN>;
-    PulseVar<D8> V;
+// Per-step pulse variables as duals; the amplitude is a0_eff (a0, or 1 when
+// a0 = 0), without a tangent.
+template <typename T, int NT>
+AP_D PulseVar<Dual<T, NT>> adjoint_vars(const PulseDev &P, double t, const int32_t (&slot)[4], double a0_eff) {
+    using DN = Dual<T, NT>;
+    using IN = DualD<T, NT>;
+    PulseVar<DN> V;
     fill_step_constants(P, t, V);
-    V.a0 = D8::var(T(P.a0), 3);
+    V.a0 = DN(T(a0_eff));
     const double w0 = P.w0 > 0.0 ? P.w0 : 1.0;
     auto wd = [&](double v, double dv) {
-        D8 r(v);
-        r.d[4] = T(dv);
+        DN r(v);
+        seed_tangent(r.d, slot, 1, dv);
         return r;
     };
     V.inv_xr = wd(P.inv_xr, -2.0 * P.inv_xr / w0);
-    if (P.type == PT_FF) V.inv_xr.d[6] = T(P.inv_xr / (1.0 - P.beta_f));
+    if (P.type == PT_FF) seed_tangent(V.inv_xr.d, slot, 3, P.inv_xr / (1.0 - P.beta_f));
     V.inv_w0sq = wd(P.inv_w0sq, -2.0 * P.inv_w0sq / w0);
     V.inv_w0 = wd(P.inv_w0, -P.inv_w0 / w0);
     V.eps = wd(P.eps, -P.eps / w0);
@@ -41,15 +52,15 @@ template <typename T> AP_D PulseVar<Dual<T, kAdjN>> adjoint_vars(const PulseDev 
     V.np_e4 = wd(P.np_e4, -4.0 * P.np_e4 / w0);
     const int la = P.lg_l < 0 ? -P.lg_l : P.lg_l;
     V.lg_pref = wd(P.lg_pref, -la * P.lg_pref / w0);
-    V.v_phi = D8(P.v_phi);
-    V.b_over_e = D8(P.b_over_e);
+    V.v_phi = DN(P.v_phi);
+    V.b_over_e = DN(P.b_over_e);
     // s0 = x_f, or x0_ff + beta_f (t - t0_ff) for the flying focus
-    I8 s0(P.type == PT_FF ? P.x0_ff + P.beta_f * (t - P.t0_ff) : P.x_f);
-    s0.d[5] = T(1);
-    if (P.type == PT_FF) s0.d[6] = T(t - P.t0_ff);
+    IN s0(P.type == PT_FF ? P.x0_ff + P.beta_f * (t - P.t0_ff) : P.x_f);
+    seed_tangent(s0.d, slot, 2, 1.0);
+    if (P.type == PT_FF) seed_tangent(s0.d, slot, 3, t - P.t0_ff);
     V.s0 = s0;
-    I8 bh(P.b_half);
-    bh.d[7] = T(0.5 / P.tau);
+    IN bh(P.b_half);
+    seed_tangent(bh.d, slot, 4, 0.5 / P.tau);
     V.b_half = bh;
     return V;
 }
@@ -81,23 +92,39 @@ AP_D R proxy_g(const R u0[3], const R u1[3], const R E[3], const R B[3], R dt) {
     return gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
 }
 
-template <typename T, int PT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<T> a) {
+template <typename T, int PT, int NT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<T> a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (p < a.n) {
-        using D8 = Dual<T, kAdjN>;
-        using I8 = DualD<T, kAdjN>;
-        I8 Xd[3];
+        using DN = Dual<T, NT>;
+        using IN = DualD<T, NT>;
+        IN Xd[3];
         T u0v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Xd[c] = I8(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
+            Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
         }
-        const PulseVar<D8> W = adjoint_vars<T>(a.P, a.t);
-        D8 E8[3], B8[3];
-        analytic_field_g<PT, D8, I8>(W, Xd[0], Xd[1], Xd[2], E8, B8);
+        const double a0_eff = a.P.a0 != 0.0 ? a.P.a0 : 1.0;
+        const PulseVar<DN> W = adjoint_vars<T, NT>(a.P, a.t, a.slot, a0_eff);
+        DN E8[3], B8[3];
+        analytic_field_g<PT, DN, IN>(W, Xd[0], Xd[1], Xd[2], E8, B8);
+        // fields per unit amplitude (dF/da0), then at the actual amplitude
+        T Fu[6];
+        const T ascale = T(a.P.a0 / a0_eff), ia0 = T(1.0 / a0_eff);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fu[c] = E8[c].v * ia0;
+            Fu[3 + c] = B8[c].v * ia0;
+            E8[c].v *= ascale;
+            B8[c].v *= ascale;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                E8[c].d[k] *= ascale;
+                B8[c].d[k] *= ascale;
+            }
+        }
 
         // Boris Jacobian: tangents over (u0, E, B)
         using D9 = Dual<T, 9>;
@@ -168,11 +195,15 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_adjoint_s
             a.lam[3 + c][p] = lu0[c];
         }
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
+        for (int k = 0; k < 3; ++k) g[0] += lE[k] * (double)Fu[k] + lB[k] * (double)Fu[3 + k];
+#pragma unroll
+        for (int j = 0; j < NT - 3; ++j) {
             double acc = 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[3 + j] + lB[k] * (double)B8[k].d[3 + j];
-            g[j] = acc;
+#pragma unroll
+            for (int q = 1; q < 5; ++q)
+                if (a.slot[j] == q) g[q] = acc;
         }
     }
     // per-block FP64 sum, accumulated into this block's slot (no atomics)
@@ -193,7 +224,12 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_adjoint_s
 
 template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_adjoint_step<T, PT>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    int np = 0;
+    for (int k = 0; k < 4; ++k) np += a.slot[k] >= 0 ? 1 : 0;
+    const dim3 grid((a.n + 255) / 256), block(256);
+    // parameter tangents padded to 2 or 4 (unused slots are -1 and stay zero)
+    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<T, PT, 5>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_adjoint_step<T, PT, 7>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

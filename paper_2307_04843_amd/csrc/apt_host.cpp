@@ -821,6 +821,11 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     double *lam[6];
     for (int k = 0; k < 6; ++k) lam[k] = c->wp<double>(L.lam[k]);
     double *partial = c->wp<double>(L.adj_partial);
+    // tangent slots of the requested parameters (the amplitude needs none)
+    int32_t slot[4] = {-1, -1, -1, -1};
+    int nslot = 0;
+    for (int k = 0; k < np_; ++k)
+        if (ids[k] != AP_PARAM_A0) slot[nslot++] = ids[k];
     HIPCHK(launch_fill_zero<double>(partial, (size_t)L.adj_blocks * 5, c->stream), "backward");
     HIPCHK(launch_adjoint_init<T>(lam, static_cast<const T *>(dl_du), n, c->stream), "backward");
     const int64_t K = c->segment;
@@ -855,6 +860,7 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
             for (int k = 0; k < 6; ++k) a.lam[k] = lam[k];
             a.lam_proxy = static_cast<const T *>(dl_dproxy);
             a.partial = partial;
+            for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
             a.n = n;
             a.q_over_m = s.q[sp] / s.m[sp];
             a.dt = s.dt;

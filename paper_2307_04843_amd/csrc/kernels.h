@@ -83,6 +83,7 @@ template <typename T> struct AdjointArgs {
     double *lam[6];              // dL/dx (lab, internal units), dL/du (in: step n+1, out: step n)
     const T *lam_proxy;          // dL/dproxy per particle or null
     double *partial;             // [blocks][5] gradient partials (a0, w0, focus, beta_f, chirp)
+    int32_t slot[4];             // parameter id carried by tangent 3 + k (-1: unused)
     int32_t n;
     double q_over_m;
     double dx[3];
