@@ -92,7 +92,7 @@ AP_D R proxy_g(const R u0[3], const R u1[3], const R E[3], const R B[3], R dt) {
     return gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
 }
 
-template <typename T, int PT, int NT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<T> a) {
+template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (p < a.n) {
@@ -222,14 +222,25 @@ template <typename T, int PT, int NT> __global__ __launch_bounds__(256) void k_a
     }
 }
 
+// FP32: two waves per SIMD (the compiler keeps the dual-number working set
+// in 256 registers with a few spills), measured faster than one wave without
+// spills.  FP64 needs twice the registers and runs best at one wave.
+template <int PT, int NT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step(AdjointArgs<float> a) {
+    adjoint_step_body<float, PT, NT>(a);
+}
+template <int PT, int NT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
+    adjoint_step_body<double, PT, NT>(a);
+}
+
 template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     int np = 0;
     for (int k = 0; k < 4; ++k) np += a.slot[k] >= 0 ? 1 : 0;
     const dim3 grid((a.n + 255) / 256), block(256);
     // parameter tangents padded to 2 or 4 (unused slots are -1 and stay zero)
-    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<T, PT, 5>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_adjoint_step<T, PT, 7>), grid, block, 0, s, a);
+    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<PT, 5>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_adjoint_step<PT, 7>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

@@ -9,6 +9,10 @@
 
 namespace apt {
 
+// Underlying scalar of a number type (the type itself for float and double;
+// dual numbers specialise it): constants multiply through it at scalar cost.
+template <typename R> struct ScalarOf { using type = R; };
+
 constexpr int kMaxSpecies = 4;
 constexpr int kWave = 64;
 

@@ -11,6 +11,7 @@
 namespace apt {
 
 template <typename T, int N> struct Dual {
+    using scalar = T;
     T v;
     T d[N];
     AP_HD Dual() : v(T(0)) {
@@ -77,6 +78,14 @@ AP_DUAL_T AP_HD Dual<T, N> operator/(const Dual<T, N> &a, const Dual<T, N> &b) {
     for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * ib;
     return r;
 }
+// scalar (non-deduced) times dual: no product rule work on a constant
+AP_DUAL_T AP_HD Dual<T, N> operator*(typename Dual<T, N>::scalar s, const Dual<T, N> &a) {
+    Dual<T, N> r; r.v = s * a.v;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i];
+    return r;
+}
+AP_DUAL_T AP_HD Dual<T, N> operator*(const Dual<T, N> &a, typename Dual<T, N>::scalar s) { return s * a; }
 AP_DUAL_T AP_HD Dual<T, N> &operator+=(Dual<T, N> &a, const Dual<T, N> &b) { a = a + b; return a; }
 AP_DUAL_T AP_HD Dual<T, N> &operator-=(Dual<T, N> &a, const Dual<T, N> &b) { a = a - b; return a; }
 AP_DUAL_T AP_HD bool operator>=(const Dual<T, N> &a, const Dual<T, N> &b) { return a.v >= b.v; }
@@ -120,6 +129,8 @@ template <typename T, int N> AP_D void sincospi_r(Dual<T, N> a, Dual<T, N> *s, D
         c->d[i] = -pi * sv * a.d[i];
     }
 }
+
+template <typename T, int N> struct ScalarOf<Dual<T, N>> { using type = T; };
 
 // ---- FP64-island helpers
 AP_DUAL_T AP_HD DualD<T, N> operator+(const DualD<T, N> &a, const DualD<T, N> &b) {

@@ -170,7 +170,7 @@ AP_D bool analytic_field_g(const PulseVar<R> &W, const I &X, const I &Y, const I
                 // Gaussian beam beyond the paraxial approximation: fields derived
                 // exactly from the eps^4-truncated vector potential (conjugated
                 // polynomials from nonparaxial_gen.h; explicit i's conjugated here).
-                const NpPoly<R> Q = np_polys<R>(f, rho2, R(1.0), W.np_e2, W.np_e4);
+                const NpPoly<R> Q = np_polys<R>(f, rho2, W.np_e2, W.np_e4);
                 const R eps = W.eps, e2 = eps * eps;
                 const R xi = p * W.inv_w0, et = q * W.inv_w0;
                 V = f * V;                                   // conj(psi0) Gamma e^{i Theta}
