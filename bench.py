@@ -12,6 +12,15 @@ One step = tile sort (every 8 steps) + J clear + fused gather/analytic/Boris/
 move/Esirkepov kernel + Yee update.  ``value`` = particle pushes per second
 over the timed steps, inputs resident in HBM.
 
+Second leg (``adjoint``): the gridless head-on collision -- 2^24 electrons,
+gamma = 2000 with 5% spread, transverse sigma = 1 lambda, against the eps^4
+nonparaxial Gaussian (a0 = 20, w0 = 2 lambda, tau = 20 lambda/c, focus at the
+origin), dt = 0.01 lambda/c -- over the ``--adj-steps`` steps around the
+collision (t = 90 ... 110 lambda/c for 2000 steps), forward with checkpoint
+recording plus ap_backward for d<p_perp^2>/d(a0, w0, x_f), in FP32 and FP64.
+Adjoint pushes/s = N x steps / wall time of the backward pass (replay
+included).
+
 Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
 """
 import argparse
@@ -134,6 +143,88 @@ def cpu_baseline(budget_s=20.0):
                        "single thread" % (N, steps))
 
 
+ADJ_N = 1 << 24
+ADJ_T0 = 90.0
+ADJ_DT = 0.01
+
+
+def adjoint_beam(n=ADJ_N):
+    from paper_2307_04843_amd import inputs
+    return inputs.beam(n, 2000.0, 0.05, 1.0, 1.0, 10.0, 1.0, seed=3)
+
+
+def adjoint_pulse():
+    return dict(a0=20.0, tau=20.0, t_ref=100.0, x_ref=0.0, x_f=0.0, w0=2.0, np_order=4,
+                dispersion=2, pol=0)
+
+
+def run_adjoint(beam, precision, steps):
+    """Forward (recording) + backward of the collision run; wall times and gradient."""
+    import torch
+    from paper_2307_04843_amd.autograd import APTRun, GridlessRun
+    names = ["a0", "w0", "x_f"]
+    vals = [20.0, 2.0, 0.0]
+    run = GridlessRun(beam, "gauss_np", adjoint_pulse(), names, steps, ADJ_DT, t0=ADJ_T0, precision=precision)
+    try:
+        n = int(beam["u"].shape[1])
+        p = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, _ = APTRun.apply(p, run)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        obs = (u[1].double() ** 2 + u[2].double() ** 2).sum() / n
+        obs.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return dict(forward_s=t1 - t0, backward_s=t2 - t1, grad=p.grad.tolist(), observable=float(obs),
+                    forward_pushes_per_s=n * steps / (t1 - t0), adjoint_pushes_per_s=n * steps / (t2 - t1),
+                    segment=run.segment, checkpoint_gb=run.ckpt.numel() / 1e9)
+    finally:
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
+
+def _cpu_gridless_chunk(args):
+    """Oracle gridless steps on one chunk of the sample, timed after a warm-up
+    step (the oracle derives its eps^4 field functions on first use).
+    Returns (pushes, seconds)."""
+    X0, u0, steps = args
+    from oracle import grad as ograd
+    prm = dict(type="gauss_np", **adjoint_pulse())
+    t_start = 99.0   # pulse and beam overlap: the expensive part of the run
+    ograd.run_gridless(prm, X0[:, :64], u0[:, :64], -1.0, t_start, ADJ_DT, 1)
+    t0 = time.perf_counter()
+    ograd.run_gridless(prm, X0, u0, -1.0, t_start, ADJ_DT, steps)
+    return X0.shape[1] * steps, time.perf_counter() - t0
+
+
+def cpu_gridless_baseline(budget_s=8.0):
+    """The FP64 oracle's gridless step (eps^4 field + Boris + move) on the host:
+    one process, then one process per available core (at most 16; the run is
+    embarrassingly parallel over particles)."""
+    import multiprocessing as mp
+    b = adjoint_beam(1 << 13)
+    X0 = (b["icell"].astype(float) + b["off"].astype(float))
+    u0 = b["u"].astype(float)
+    n1, w1 = _cpu_gridless_chunk((X0, u0, 1))
+    steps = max(1, int(budget_s / 2 / w1))
+    n1, w1 = _cpu_gridless_chunk((X0, u0, steps))
+    single = n1 / w1
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 16))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_cpu_gridless_chunk, [(X0, u0, steps)] * cores)
+    multi = sum(r[0] for r in res) / max(r[1] for r in res)
+    return dict(value=single, unit="pushes/s", cores=1, kind="oracle", all_core_value=multi,
+                all_core_cores=cores,
+                sample="8192 electrons of the collision beam from t = 99 lambda/c (inside the eps^4 "
+                       "pulse), %d steps, FP64 NumPy; all-core: %d spawned processes on the same "
+                       "sample, throughput = total pushes / slowest worker" % (steps, cores))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +234,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--skip-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -206,9 +299,31 @@ def main():
         out["fp32_first_steps_pushes_per_s"] = v32s
         out["fp32_over_fp64"] = v32s / v64
     del species
+    if not args.skip_adjoint:
+        beam = adjoint_beam()
+        adj = {"workload": "gridless head-on collision: 2^24 electrons, gamma 2000 (5%% spread), "
+                           "sigma_perp 1 lambda, eps^4 nonparaxial Gaussian a0=20 w0=2 tau=20, "
+                           "dt=0.01, steps %d of the 20000-step run (t=%.0f..%.0f), observable "
+                           "<p_perp^2>, gradient wrt (a0, w0, x_f)"
+                           % (args.adj_steps, ADJ_T0, ADJ_T0 + ADJ_DT * args.adj_steps),
+               "particles": ADJ_N, "steps": args.adj_steps}
+        for prec in ("f32", "f64"):
+            log("adjoint leg %s: %d steps" % (prec, args.adj_steps))
+            adj[prec] = run_adjoint(beam, prec, args.adj_steps)
+        g32, g64 = adj["f32"]["grad"], adj["f64"]["grad"]
+        adj["grad_rel_diff_f32_vs_f64"] = [abs(a - b) / max(abs(b), 1e-300) for a, b in zip(g32, g64)]
+        gnorm = math.sqrt(sum(b * b for b in g64))
+        adj["grad_diff_over_norm_f32_vs_f64"] = [abs(a - b) / max(gnorm, 1e-300) for a, b in zip(g32, g64)]
+        adj["f32_over_f64_forward"] = adj["f32"]["forward_pushes_per_s"] / adj["f64"]["forward_pushes_per_s"]
+        adj["f32_over_f64_adjoint"] = adj["f32"]["adjoint_pushes_per_s"] / adj["f64"]["adjoint_pushes_per_s"]
+        out["adjoint"] = adj
+        del beam
     if not args.skip_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        if not args.skip_adjoint:
+            log("CPU oracle baseline, gridless")
+            out["cpu_baseline_gridless"] = cpu_gridless_baseline()
     print(json.dumps(out), flush=True)
 
 
