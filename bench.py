@@ -66,13 +66,13 @@ def workload_pulse(dt):
                 q_slice=0.0, d_f=3, lg_l=1, lg_p=0, pol=1, dispersion=0, dx_prop=dx, dt_prop=dt)
 
 
-def run_gpu(species, precision, steps, warmup, timing=True):
+def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0):
     import torch
     from paper_2307_04843_amd import apt
     from paper_2307_04843_amd.sim import Simulation
     dt = 0.95 / math.sqrt(2) * LAMBDA_DX
     sim = Simulation(2, n=N_CELLS, dx=(LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
-                     precision=precision, species=species)
+                     precision=precision, species=species, sort_every=sort_every)
     try:
         sim.set_pulse("lg", **workload_pulse(dt))
         n_part = sum(int(s["state"]["u"].shape[1]) for s in species)
@@ -225,31 +225,37 @@ def cpu_gridless_baseline(budget_s=8.0):
                        "sample, throughput = total pushes / slowest worker" % (steps, cores))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1990)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fp64-steps", type=int, default=100)
-    ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--adj-steps", type=int, default=2000)
-    ap.add_argument("--skip-adjoint", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
+METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 MI355X"
 
+# HBM traffic of k_push_deposit_2d on this workload, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the same counters read for
+# a plain copy of known size in the same run; per launch, averaged over the
+# launches of the profiled steps.  Valid only for the kernel sources whose
+# digest is recorded here (None once the sources change).
+MEASURED_TRAFFIC = None
+
+
+PUSH2D_SOURCES = ("push2d.hip", "kernels.h", "common.h", "pulse_dev.h", "dual.h", "nonparaxial_gen.h",
+                  "apt_host.cpp")
+
+
+def sources_digest(names=PUSH2D_SOURCES):
+    """SHA-256 over the sources that define the 2-D push kernel and its launch."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2307_04843_amd", "csrc")
+    h = hashlib.sha256()
+    for nm in names:
+        h.update(nm.encode())
+        with open(os.path.join(d, nm), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pic_leg(args):
     log("generating inputs")
     species = workload_inputs()
     log("FP32 run: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    r32 = run_gpu(species, "f32", args.steps, args.warmup)
+    r32 = run_gpu(species, "f32", args.steps, args.warmup, sort_every=args.sort_every)
     tm = r32["timing"]
     n_part = r32["n_part"]
     value = n_part * args.steps / r32["wall"]
@@ -259,10 +265,19 @@ def main():
     # + u 12 = 24 B), plus the grid share (stage E2, B2: 24 B/cell; J flush 12 B/cell)
     bytes_launch = n_part * 52 + r32["ncell"] * 36
     achieved = bytes_launch / (ms_push * 1e-3) / 1e9
+    traffic = None
+    traffic_note = "no counter measurement for the current kernel sources"
+    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_digest():
+        tb = MEASURED_TRAFFIC["fetch_bytes_per_launch"] + MEASURED_TRAFFIC["write_bytes_per_launch"]
+        traffic = tb / (ms_push * 1e-3) / 1e9
+        traffic_note = ("HBM bytes per launch %.4g (fetch %.4g + write %.4g) from rocprofv3 FETCH_SIZE/"
+                        "WRITE_SIZE, %s, over the current launch time" % (
+                            tb, MEASURED_TRAFFIC["fetch_bytes_per_launch"],
+                            MEASURED_TRAFFIC["write_bytes_per_launch"], MEASURED_TRAFFIC["note"]))
     log("FP32: %.3e pushes/s, push kernel %.3f ms/launch, yee %.3f ms, sort %.3f ms"
         % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, tm.n_sort)))
     out = {
-        "metric": "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 MI355X",
+        "metric": METRIC,
         "value": value,
         "unit": "pushes/s",
         "n_gpus": 1,
@@ -278,13 +293,14 @@ def main():
                                "0->0.05 n_c ramp over 200 lambda, analytic LG l=1 p=0 a0=5 w0=8 "
                                "tau=30, 2000-step run", "particles": n_part, "cells": r32["ncell"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "kernel": "k_push_deposit_2d", "ms_per_launch": ms_push,
                      "bytes_per_launch": bytes_launch},
         "kernels_ms_per_step": {"push_deposit": ms_push, "yee": tm.ms_yee / max(1, tm.n_yee),
                                 "sort": tm.ms_sort / max(1, args.steps),
                                 "other": tm.ms_other / max(1, args.steps)},
-        "numerics": {"n_nonfinite": r32["diag"].n_nonfinite, "n_fast": r32["diag"].n_fast},
+        "numerics": {"n_nonfinite": r32["diag"].n_nonfinite, "n_fast": r32["diag"].n_fast,
+                     "offtile_fraction": r32["diag"].n_offtile / float(n_part * (args.steps + args.warmup))},
     }
     if not args.skip_fp64:
         log("FP64 run: %d steps" % args.fp64_steps)
@@ -299,25 +315,71 @@ def main():
         out["fp32_first_steps_pushes_per_s"] = v32s
         out["fp32_over_fp64"] = v32s / v64
     del species
+    return out
+
+
+def adjoint_leg(args):
+    beam = adjoint_beam()
+    adj = {"workload": "gridless head-on collision: 2^24 electrons, gamma 2000 (5%% spread), "
+                       "sigma_perp 1 lambda, eps^4 nonparaxial Gaussian a0=20 w0=2 tau=20, "
+                       "dt=0.01, steps %d of the 20000-step run (t=%.0f..%.0f), observable "
+                       "<p_perp^2>, gradient wrt (a0, w0, x_f)"
+                       % (args.adj_steps, ADJ_T0, ADJ_T0 + ADJ_DT * args.adj_steps),
+           "particles": ADJ_N, "steps": args.adj_steps}
+    for prec in ("f32", "f64"):
+        log("adjoint leg %s: %d steps" % (prec, args.adj_steps))
+        adj[prec] = run_adjoint(beam, prec, args.adj_steps)
+    g32, g64 = adj["f32"]["grad"], adj["f64"]["grad"]
+    adj["grad_rel_diff_f32_vs_f64"] = [abs(a - b) / max(abs(b), 1e-300) for a, b in zip(g32, g64)]
+    gnorm = math.sqrt(sum(b * b for b in g64))
+    adj["grad_diff_over_norm_f32_vs_f64"] = [abs(a - b) / max(gnorm, 1e-300) for a, b in zip(g32, g64)]
+    adj["f32_over_f64_forward"] = adj["f32"]["forward_pushes_per_s"] / adj["f64"]["forward_pushes_per_s"]
+    adj["f32_over_f64_adjoint"] = adj["f32"]["adjoint_pushes_per_s"] / adj["f64"]["adjoint_pushes_per_s"]
+    return adj
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1990)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--skip-pic", action="store_true", help="skip the 2-D PIC leg (profiling runs)")
+    ap.add_argument("--sort-every", type=int, default=0, help="tile re-sort interval (0: library default)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy a device buffer of this size (a known-size kernel for "
+                         "scaling HBM counters in profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
+        del src, dst
+    if args.skip_pic:
+        out = {"metric": METRIC, "value": None, "unit": "pushes/s", "n_gpus": 1, "steps": 0,
+               "warmup": 0, "note": "PIC leg skipped (profiling run)"}
+    else:
+        out = pic_leg(args)
     if not args.skip_adjoint:
-        beam = adjoint_beam()
-        adj = {"workload": "gridless head-on collision: 2^24 electrons, gamma 2000 (5%% spread), "
-                           "sigma_perp 1 lambda, eps^4 nonparaxial Gaussian a0=20 w0=2 tau=20, "
-                           "dt=0.01, steps %d of the 20000-step run (t=%.0f..%.0f), observable "
-                           "<p_perp^2>, gradient wrt (a0, w0, x_f)"
-                           % (args.adj_steps, ADJ_T0, ADJ_T0 + ADJ_DT * args.adj_steps),
-               "particles": ADJ_N, "steps": args.adj_steps}
-        for prec in ("f32", "f64"):
-            log("adjoint leg %s: %d steps" % (prec, args.adj_steps))
-            adj[prec] = run_adjoint(beam, prec, args.adj_steps)
-        g32, g64 = adj["f32"]["grad"], adj["f64"]["grad"]
-        adj["grad_rel_diff_f32_vs_f64"] = [abs(a - b) / max(abs(b), 1e-300) for a, b in zip(g32, g64)]
-        gnorm = math.sqrt(sum(b * b for b in g64))
-        adj["grad_diff_over_norm_f32_vs_f64"] = [abs(a - b) / max(gnorm, 1e-300) for a, b in zip(g32, g64)]
-        adj["f32_over_f64_forward"] = adj["f32"]["forward_pushes_per_s"] / adj["f64"]["forward_pushes_per_s"]
-        adj["f32_over_f64_adjoint"] = adj["f32"]["adjoint_pushes_per_s"] / adj["f64"]["adjoint_pushes_per_s"]
-        out["adjoint"] = adj
-        del beam
+        out["adjoint"] = adjoint_leg(args)
     if not args.skip_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)

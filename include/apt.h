@@ -94,7 +94,7 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *   t0         simulation time at step 0 (lambda/c).
  *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
  *              with the smallest dx (the rule stated after Eq. (14)).
- *   sort_every steps between tile re-sorts (0 = default 8).
+ *   sort_every steps between tile re-sorts (0 = default: 12 in 2-D, 8 in 3-D).
  */
 typedef struct ap_grid_desc {
     int32_t dim;
@@ -199,6 +199,9 @@ typedef struct ap_diag {
     double  j_max;                      /* max |J| over the same steps      */
     int64_t n_nonfinite;                /* particles with non-finite state  */
     int64_t n_fast;                     /* moves of >= 1 cell in one step   */
+    int64_t n_offtile;                  /* pushes whose stencil left the LDS-staged
+                                           tile region (served from global memory
+                                           instead; a measure of sort staleness) */
 } ap_diag;
 
 /* Accumulated device time of each kernel family since the last reset. */

@@ -70,7 +70,8 @@ class ap_diag(C.Structure):
                 ("mean_u", (C.c_double * 3) * 4), ("mean_u2", (C.c_double * 3) * 4),
                 ("mean_gamma", C.c_double * 4), ("proxy_sum", C.c_double * 4),
                 ("continuity_max", C.c_double), ("j_max", C.c_double),
-                ("n_nonfinite", C.c_int64), ("n_fast", C.c_int64)]
+                ("n_nonfinite", C.c_int64), ("n_fast", C.c_int64),
+                ("n_offtile", C.c_int64)]
 
 
 class ap_timing(C.Structure):

@@ -61,7 +61,7 @@ struct WorkLayout {
 };
 
 constexpr int kDiagBlocks = 512;
-constexpr int kCounters = 8;   // n_fast, n_bad, res_max, j_max, ...
+constexpr int kCounters = 8;   // n_fast, n_bad, res_max, j_max, n_offtile, ...
 
 bool axis_active(int dim, int ax) { return dim == 3 || (dim == 2 && ax != 1) || dim == 0; }
 
@@ -123,7 +123,8 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
-    s.sort_every = g->sort_every > 0 ? g->sort_every : 8;
+    // default re-sort interval: 2-D tiles carry a two-cell drift margin, 3-D none
+    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 8 : 12);
     int64_t total = 0;
     for (int i = 0; i < nsp; ++i) {
         if (!finite_pos(sp[i].m)) return fail(AP_E_ARG, "species mass must be finite and > 0");
@@ -624,6 +625,7 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
     d.j_max = jmax;
     d.n_nonfinite = nonfinite;
     d.n_fast = (int64_t)cnt[0];
+    d.n_offtile = (int64_t)cnt[4];
     *out = d;
     if (d.n_nonfinite > 0 || d.n_fast > 0)
         return fail(AP_E_NUMERIC, "non-finite particle state or a move of a full cell detected");
@@ -999,6 +1001,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     a.t = s.t0 + (double)c->step * s.dt;
     a.n_fast = c->counters() + 0;
     a.n_bad = c->counters() + 1;
+    a.n_offtile = c->counters() + 4;
     a.q_slice = c->P.q_slice;
     a.pulse = c->P.type;
     a.W = plain_vars<T>(c->P, a.t);

@@ -118,6 +118,13 @@ template <> AP_D void sincos_r<float>(float x, float *s, float *c) { sincosf(x, 
 template <> AP_D void sincos_r<double>(double x, double *s, double *c) { sincos(x, s, c); }
 
 // Block-wide sum of doubles (blockDim.x a multiple of 64, <= 1024).
+// Add the number of lanes of the wave with pred set to *counter (one atomic).
+AP_D void wave_count(unsigned long long *counter, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (m != 0ull && (int)(threadIdx.x & 63) == __ffsll((long long)__ballot(1)) - 1)
+        atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
 AP_D double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;

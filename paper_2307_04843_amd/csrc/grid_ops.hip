@@ -325,16 +325,31 @@ hipError_t launch_diag_fields(T *const F[6], size_t ncell, double *partial, int 
 template hipError_t launch_diag_fields<float>(float *const[6], size_t, double *, int, hipStream_t);
 template hipError_t launch_diag_fields<double>(double *const[6], size_t, double *, int, hipStream_t);
 
-__global__ void k_sum_partials(const double *partial, int blocks, int nvals, double *out) {
-    const int m = threadIdx.x;
-    if (m >= nvals) return;
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * nvals + m];
-    out[m] = s;
+// out[m] = sum over rows b of partial[b][m], m < nvals <= 16: one workgroup,
+// each thread sums a strided set of rows for every m, then a fixed-order
+// tree in LDS (deterministic for a given row count).
+__global__ __launch_bounds__(1024) void k_sum_partials(const double *partial, int blocks, int nvals, double *out) {
+    __shared__ double red[16][1024 / 64];
+    double s[16];
+    for (int m = 0; m < 16; ++m) s[m] = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += blockDim.x)
+        for (int m = 0; m < nvals && m < 16; ++m) s[m] += partial[(size_t)b * nvals + m];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int m = 0; m < nvals && m < 16; ++m) {
+        const double w = wave_sum(s[m]);
+        if (lane == 0) red[m][wid] = w;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nvals && threadIdx.x < 16) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
 }
 
 hipError_t launch_sum_partials(const double *partial, int blocks, int nvals, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, partial, blocks, nvals, out);
+    if (nvals > 16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, blocks, nvals, out);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace apt {
 // Tile halo: a particle in tile cell range [X0, X0+TX) may drift kDrift cells
 // out of it between re-sorts and still use the LDS copy.  The quadratic
 // gather needs nodes [c-1, c+2] and the deposit [c-2, c+3] around cell c.
-constexpr int kDrift = 1;
+constexpr int kDrift = 2;
 constexpr int kHaloLo = 2 + kDrift;
 constexpr int kHaloHi = 3 + kDrift;
 
@@ -53,6 +53,7 @@ template <typename T> struct PushArgs {
     double t;                    // time of the positions read (t^n)
     unsigned long long *n_fast;  // moves >= 1 cell (clamped)
     unsigned long long *n_bad;   // non-finite / out-of-range particles
+    unsigned long long *n_offtile;   // pushes that left the staged region (global-memory path)
     double q_slice;              // lab y sampled by an (x, z) grid
     int32_t pulse;               // PulseType
     PulseVar<T> W;               // pulse constants of this step

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             if (dk < -half_nz) dk += nz; else if (dk >= nz - half_nz) dk -= nz;
             const int la = di + kHaloLo, lb = dk + kHaloLo;
             const bool in_lds = la >= 2 && la <= RX - 4 && lb >= 2 && lb <= RZ - 4;
+            wave_count(a.n_offtile, !in_lds);
 
             // ---- gather E2, B2 (quadratic shape at each staggered location)
             const int nxn = offx >= T(0.5) ? 1 : 0;

@@ -181,6 +181,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
                 loc[c] = d + kLo3;
                 in_lds = in_lds && loc[c] >= 2 && loc[c] <= reg[c] - 4;
             }
+            wave_count(a.n_offtile, !in_lds);
             // weights: node (n) and half-node (h) per axis
             int nod[3];
             T wn[3][3], wh[3][3];
