@@ -129,6 +129,60 @@ def test_pin2_time_step_rule():
     assert abs(units.default_dt(2.0, 3) - 2 * 0.95 / math.sqrt(3)) < 1e-15
 
 
+def _plane_yee_residual(mode, dxl, tau, half_window, b_over_e=None):
+    """Max one-step residual (E, B) of the sampled PLANE pulse under the split
+    Yee step of Eqs. (7)-(9) in 1-D (E_y on nodes, B_z on half nodes, both at
+    integer times; B half step, E full step, B half step), over a window of
+    +-half_window lambda about the envelope peak.  Residual = (discrete step -
+    analytic value at t + dt) / dt."""
+    dt_l = 0.95 / math.sqrt(2) * dxl
+    P = pulses.Pulse(dict(type="plane", a0=1.0, tau=tau, t_ref=0.0, x_ref=0.0, pol=0,
+                          dispersion=mode, dx_prop=dxl, dt=dt_l))
+    if b_over_e is not None:
+        P.b_over_e = b_over_e
+    dx, dt = dxl * L, dt_l * L
+    t = (tau + 3.0) * L
+    xc = P.v_g * t                      # envelope peak (t_ref = x_ref = 0)
+    n0 = int((xc - half_window * L) / dx)
+    x = (n0 + np.arange(int(2 * half_window / dxl))) * dx
+    xh = x + dx / 2
+    z = np.zeros_like(x)
+    E0 = pulses.analytic_fields(P, t, x, z, z)[0][1]
+    B0 = pulses.analytic_fields(P, t, xh, z, z)[1][2]
+    E1 = pulses.analytic_fields(P, t + dt, x, z, z)[0][1]
+    B1 = pulses.analytic_fields(P, t + dt, xh, z, z)[1][2]
+    # dB_z/dt = -dE_y/dx, dE_y/dt = -dB_z/dx (internal units)
+    Bh = B0 - 0.5 * dt * (np.roll(E0, -1) - E0) / dx
+    En = E0 - dt * (Bh - np.roll(Bh, 1)) / dx
+    Bn = Bh - 0.5 * dt * (np.roll(En, -1) - En) / dx
+    return max(np.abs((En - E1) / dt)[3:-3].max(), np.abs((Bn - B1) / dt)[3:-3].max())
+
+
+def test_pin3_plane_pulse_discrete_yee_residual():
+    """Sec. II.A: with the second-order constants of Eqs. (12)-(14) the sampled
+    plane pulse satisfies the discrete Yee equations to O((omega dx)^4) where
+    the envelope is flat (near the peak of a long pulse), against O((omega dx)^2)
+    with vacuum constants; on a short pulse the envelope edges leave an
+    O((omega dx)^2) residual that is still far below the vacuum one.  A wrong
+    phase velocity, group velocity or B0/E0 (planted below: B0/E0 = 1) drops
+    the peak to second order."""
+    d = (0.05, 0.025)
+    p2 = [_plane_yee_residual(units.DISP_PAPER2, x, 400.0, 2.0) for x in d]
+    vac = [_plane_yee_residual(units.DISP_VACUUM, x, 400.0, 2.0) for x in d]
+    ex = [_plane_yee_residual(units.DISP_EXACT, x, 400.0, 2.0) for x in d]
+    assert p2[0] / p2[1] > 12.0, p2                      # fourth order at the peak
+    assert 3.0 < vac[0] / vac[1] < 5.0, vac              # second order
+    assert p2[0] < vac[0] / 100.0
+    assert ex[0] < p2[0] / 10.0                          # exact constants: envelope terms only
+    bad = [_plane_yee_residual(units.DISP_PAPER2, x, 400.0, 2.0, b_over_e=1.0) for x in d]
+    assert bad[0] / bad[1] < 5.0 and bad[0] > 10.0 * p2[0], bad
+    # short pulse (tau = 20 lambda/c), whole pulse: second order, much below vacuum
+    p2s = [_plane_yee_residual(units.DISP_PAPER2, x, 20.0, 12.0) for x in d]
+    vacs = [_plane_yee_residual(units.DISP_VACUUM, x, 20.0, 12.0) for x in d]
+    assert 3.0 < p2s[0] / p2s[1] < 5.0, p2s
+    assert p2s[0] < vacs[0] / 10.0, (p2s, vacs)
+
+
 # ---------------------------------------------------------------------------
 # Analytic pulses (Eqs. (15), (17), (20)-(26))
 # ---------------------------------------------------------------------------
