@@ -94,7 +94,7 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *   t0         simulation time at step 0 (lambda/c).
  *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
  *              with the smallest dx (the rule stated after Eq. (14)).
- *   sort_every steps between tile re-sorts (0 = default: 12 in 2-D, 8 in 3-D).
+ *   sort_every steps between tile re-sorts (0 = default: 12 in 2-D, 2 in 3-D).
  */
 typedef struct ap_grid_desc {
     int32_t dim;

@@ -102,7 +102,7 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
             if (axis_active(s.dim, ax)) { inv2 += 1.0 / (s.dx[ax] * s.dx[ax]); dmin = std::fmin(dmin, s.dx[ax]); }
         s.dt = g->dt > 0.0 ? g->dt * kTwoPi : 0.95 / std::sqrt((double)s.dim) * dmin;
         if (!(s.dt < 1.0 / std::sqrt(inv2))) return fail(AP_E_ARG, "dt exceeds the Yee stability limit");
-        const int def2[3] = {16, 1, 8}, def3[3] = {8, 8, 4};
+        const int def2[3] = {16, 1, 8}, def3[3] = {8, 4, 4};
         for (int ax = 0; ax < 3; ++ax) {
             int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : def2[ax]);
             if (!axis_active(s.dim, ax)) t = 1;
@@ -123,8 +123,9 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
-    // default re-sort interval: 2-D tiles carry a two-cell drift margin, 3-D none
-    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 8 : 12);
+    // default re-sort interval: 2-D tiles carry a two-cell drift margin, 3-D
+    // tiles none (LDS budget), so 3-D re-sorts every other step
+    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 2 : 12);
     int64_t total = 0;
     for (int i = 0; i < nsp; ++i) {
         if (!finite_pos(sp[i].m)) return fail(AP_E_ARG, "species mass must be finite and > 0");

@@ -148,9 +148,14 @@ AP_D bool analytic_field_g(const PulseVar<R> &W, const I &X, const I &Y, const I
             bx = R(0.0);
         } else {
             // pulse-frame transverse coordinates
-            R p, q;
-            if (W.pol == 0) { p = NT::from_island(island_shift(Y, W.y_c)); q = NT::from_island(island_shift(Z, W.z_c)); }
-            else            { p = NT::from_island(island_shift(Z, W.z_c)); q = -NT::from_island(island_shift(Y, W.y_c)); }
+            // (both offsets first, then a per-value select: selecting between the
+            // Y and Z operands themselves would make the compiler address them
+            // through scratch memory in the dual-number instantiations)
+            const R dy = NT::from_island(island_shift(Y, W.y_c));
+            const R dz = NT::from_island(island_shift(Z, W.z_c));
+            const bool pol0 = W.pol == 0;
+            const R p = pol0 ? dy : dz;
+            const R q = pol0 ? dz : -dy;
             const I s_d = W.s0 - X;
             const R zeta = NT::from_island(s_d) * W.inv_xr;
             const R den = rcp_r(R(1.0) + zeta * zeta);          // |f|^2 = (w0/w)^2

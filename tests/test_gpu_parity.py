@@ -185,7 +185,7 @@ def _gauss_pulse_3d(dxl, dt, box):
 @pytest.mark.parametrize("tile", [(0, 0, 0), (8, 8, 8)])
 def test_one_step_3d_parity(precision, tol, kind, tile):
     """3-D step (27-point gather per component, 4x4x4 Esirkepov window) on a 20x18x14
-    grid with 8x8x4 (default) or 8x8x8 tiles (ragged tails on every axis), electrons
+    grid with 8x4x4 (default) or 8x8x8 tiles (ragged tails on every axis), electrons
     and protons."""
     dxl = 0.0625
     n = (20, 18, 14)
