@@ -9,6 +9,11 @@
 
 namespace apt {
 
+// Two-lane vector of a scalar type (LDS pairs).
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
 // Underlying scalar of a number type (the type itself for float and double;
 // dual numbers specialise it): constants multiply through it at scalar cost.
 template <typename R> struct ScalarOf { using type = R; };

@@ -78,7 +78,12 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     T *sm = reinterpret_cast<T *>(smem_raw);
     const int RX = a.reg[0], RZ = a.reg[2];
     const int RC = RX * RZ;
-    T *sF = sm;                                              // Ex Ey Ez Bx By Bz
+    // Staged fields: components that share a stencil window are stored as
+    // pairs, (Ex, Bz) on (half, node) and (Ez, Bx) on (node, half), so one
+    // LDS read serves both; Ey (node, node) and By (half, half) alone.
+    using T2 = typename Vec2<T>::type;
+    T2 *sP = reinterpret_cast<T2 *>(smem_raw);               // [2][RC] pairs
+    T *sS = reinterpret_cast<T *>(sP + 2 * RC);              // [2][RC] Ey, By
     // The current tile accumulates in FP64 for both working types: ds_add_f64
     // measured several times faster than ds_add_f32 for this access pattern.
     using A = double;
@@ -105,12 +110,13 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         const int gx = ((ox + lx) % nx + nx) % nx;
         const int gz = ((oz + lz) % nz + nz) % nz;
         const size_t g = (size_t)gz * nx + gx;
-        sF[0 * RC + e] = a.E[0][g];
-        sF[1 * RC + e] = a.E[1][g];
-        sF[2 * RC + e] = a.E[2][g];
-        sF[3 * RC + e] = a.B[0][g];
-        sF[4 * RC + e] = a.B[1][g];
-        sF[5 * RC + e] = a.B[2][g];
+        T2 p0, p1;
+        p0.x = a.E[0][g]; p0.y = a.B[2][g];
+        p1.x = a.E[2][g]; p1.y = a.B[0][g];
+        sP[e] = p0;
+        sP[RC + e] = p1;
+        sS[e] = a.E[1][g];
+        sS[RC + e] = a.B[1][g];
         sJ[0 * RC + e] = A(0);
         sJ[1 * RC + e] = A(0);
         sJ[2 * RC + e] = A(0);
@@ -178,8 +184,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             T e2[3], b2[3];
             if (in_lds) {
                 const int xn = la + nxn - 1, xh = la - 1, zn = lb + nzn - 1, zh = lb - 1;
-                auto G = [&](int comp, int bx, const T *wx, int bz, const T *wz) {
-                    const T *F = sF + comp * RC;
+                auto G = [&](const T *F, int bx, const T *wx, int bz, const T *wz) {
                     T acc = T(0);
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
@@ -188,12 +193,22 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     }
                     return acc;
                 };
-                e2[0] = G(0, xh, wxh, zn, wzn);
-                e2[1] = G(1, xn, wxn, zn, wzn);
-                e2[2] = G(2, xn, wxn, zh, wzh);
-                b2[0] = G(3, xn, wxn, zh, wzh);
-                b2[1] = G(4, xh, wxh, zh, wzh);
-                b2[2] = G(5, xh, wxh, zn, wzn);
+                auto G2 = [&](const T2 *F, int bx, const T *wx, int bz, const T *wz, T &o0, T &o1) {
+                    T a0 = T(0), a1 = T(0);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const T2 *row = F + (bz + b) * RX + bx;
+                        const T2 r0 = row[0], r1 = row[1], r2 = row[2];
+                        a0 += wz[b] * (wx[0] * r0.x + wx[1] * r1.x + wx[2] * r2.x);
+                        a1 += wz[b] * (wx[0] * r0.y + wx[1] * r1.y + wx[2] * r2.y);
+                    }
+                    o0 = a0;
+                    o1 = a1;
+                };
+                G2(sP, xh, wxh, zn, wzn, e2[0], b2[2]);
+                G2(sP + RC, xn, wxn, zh, wzh, e2[2], b2[0]);
+                e2[1] = G(sS, xn, wxn, zn, wzn);
+                b2[1] = G(sS + RC, xh, wxh, zh, wzh);
             } else {
                 int gxn[3], gxh[3];
                 size_t gzn[3], gzh[3];
