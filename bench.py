@@ -232,7 +232,17 @@ METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 
 # a plain copy of known size in the same run; per launch, averaged over the
 # launches of the profiled steps.  Valid only for the kernel sources whose
 # digest is recorded here (None once the sources change).
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {
+    "sources_sha256": "005a637ff3662fdf43c65ae2da741c3a20b8407f756f5354573d3ee51f9bf411",
+    "fetch_bytes_per_launch": 4.09989e9,
+    "write_bytes_per_launch": 3.98755e9,
+    # SQ_INSTS_VALU x 64 / particles, same runs: VALU lane-ops issued per push
+    "valu_lane_ops_per_push": 600.5,
+    "note": "average over the 2000 launches of the default run (calibration copy factors "
+            "0.500 fetch, 1.000 write), profiles/push_deposit_2d_lg_4096x1024_f32.md",
+}
+# Non-packed FP32 VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.
+VALU_PEAK_T_LANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 PUSH2D_SOURCES = ("push2d.hip", "kernels.h", "common.h", "pulse_dev.h", "dual.h", "nonparaxial_gen.h",
@@ -267,6 +277,7 @@ def pic_leg(args):
     achieved = bytes_launch / (ms_push * 1e-3) / 1e9
     traffic = None
     traffic_note = "no counter measurement for the current kernel sources"
+    roofline_valu = None
     if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_digest():
         tb = MEASURED_TRAFFIC["fetch_bytes_per_launch"] + MEASURED_TRAFFIC["write_bytes_per_launch"]
         traffic = tb / (ms_push * 1e-3) / 1e9
@@ -274,6 +285,12 @@ def pic_leg(args):
                         "WRITE_SIZE, %s, over the current launch time" % (
                             tb, MEASURED_TRAFFIC["fetch_bytes_per_launch"],
                             MEASURED_TRAFFIC["write_bytes_per_launch"], MEASURED_TRAFFIC["note"]))
+        ops = MEASURED_TRAFFIC["valu_lane_ops_per_push"] * n_part / (ms_push * 1e-3) / 1e12
+        roofline_valu = {"bound": "alu", "achieved": ops, "peak": VALU_PEAK_T_LANE_OPS,
+                         "unit": "T VALU lane-ops/s", "frac": ops / VALU_PEAK_T_LANE_OPS,
+                         "per_push": MEASURED_TRAFFIC["valu_lane_ops_per_push"],
+                         "note": "VALU lane-ops issued per push counted by rocprofv3 (SQ_INSTS_VALU), "
+                                 "non-packed FP32 issue peak"}
     log("FP32: %.3e pushes/s, push kernel %.3f ms/launch, yee %.3f ms, sort %.3f ms"
         % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, tm.n_sort)))
     out = {
@@ -296,6 +313,7 @@ def pic_leg(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
                      "kernel": "k_push_deposit_2d", "ms_per_launch": ms_push,
                      "bytes_per_launch": bytes_launch},
+        "roofline_valu": roofline_valu,
         "kernels_ms_per_step": {"push_deposit": ms_push, "yee": tm.ms_yee / max(1, tm.n_yee),
                                 "sort": tm.ms_sort / max(1, args.steps),
                                 "other": tm.ms_other / max(1, args.steps)},
