@@ -50,7 +50,7 @@ struct RunShape {
 };
 
 struct WorkLayout {
-    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, total = 0;
+    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, total = 0;
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -164,6 +164,8 @@ WorkLayout make_layout(const RunShape &s) {
     if (s.dim > 0) {
         L.rho0 = take((size_t)s.ncell * 8);
         L.rho1 = take((size_t)s.ncell * 8);
+        // FP64 accumulator of the step's current (FP32 runs; FP64 runs use J)
+        if (s.prec == AP_F32) L.jacc = take((size_t)s.ncell * 3 * 8);
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
             L.count[i] = take((size_t)s.ntiles * 4);
@@ -985,6 +987,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         a.E[k] = F[k];
         a.B[k] = F[3 + k];
         a.J[k] = F[6 + k];
+        a.Jacc[k] = s.prec == AP_F32 ? c->wp<double>(L.jacc) + (size_t)k * nc : reinterpret_cast<double *>(F[6 + k]);
         a.n[k] = s.n[k];
         a.tile[k] = s.tile[k];
         a.ntile[k] = s.ntile[k];
@@ -1009,7 +1012,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
 
     {
         Timer tm(c, 3);
-        HIPCHK(launch_fill_zero<T>(F[6], 3 * nc, c->stream), "clear J");
+        HIPCHK(launch_fill_zero<double>(a.Jacc[0], 3 * nc, c->stream), "clear J");
     }
     double *rho0 = c->wp<double>(L.rho0), *rho1 = c->wp<double>(L.rho1);
     auto deposit_rho = [&](double *rho, bool use_in) -> ap_status {
@@ -1041,6 +1044,11 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
                                   : launch_push_deposit_3d<T>(c->P.type, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
+    }
+    if (s.prec == AP_F32) {
+        // one rounding of the FP64 sum per node keeps continuity at FP32 round-off
+        Timer tm(c, 3);
+        HIPCHK(launch_round_current<T>(a.Jacc[0], F[6], 3 * nc, c->stream), "round J");
     }
     if (flags & AP_STEP_CONTINUITY) {
         Timer tm(c, 3);

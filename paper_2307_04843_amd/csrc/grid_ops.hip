@@ -137,6 +137,18 @@ template hipError_t launch_fill_zero<double>(double *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<int32_t>(int32_t *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<unsigned long long>(unsigned long long *, size_t, hipStream_t);
 
+template <typename T> __global__ void k_round_current(const double *jacc, T *J, size_t n) {
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+        J[c] = T(jacc[c]);
+}
+template <typename T> hipError_t launch_round_current(const double *jacc, T *J, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_round_current<T>), dim3(grid_blocks(n)), dim3(256), 0, s, jacc, J, n);
+    return hipGetLastError();
+}
+template hipError_t launch_round_current<float>(const double *, float *, size_t, hipStream_t);
+template hipError_t launch_round_current<double>(const double *, double *, size_t, hipStream_t);
+
 // ---------------------------------------------------------------------------
 // Tile sort: counting sort of particles by tile id (rank from a wave-
 // aggregated atomic, exclusive scan of the counts, scatter).

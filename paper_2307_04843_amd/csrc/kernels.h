@@ -40,6 +40,7 @@ template <typename T> struct PushArgs {
     const T *E[3];
     const T *B[3];
     T *J[3];
+    double *Jacc[3];             // FP64 accumulator of this step's current (J itself in FP64 runs)
     int32_t n[3];                // cells per axis
     int32_t tile[3];             // tile shape
     int32_t ntile[3];            // tiles per axis
@@ -116,6 +117,8 @@ template <typename T>
 hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &g, int no_yee, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_zero(T *p, size_t n, hipStream_t s);
+// J = (T) Jacc over n values: the step's current rounded once to the working type.
+template <typename T> hipError_t launch_round_current(const double *jacc, T *J, size_t n, hipStream_t s);
 
 struct SortArgs {
     const int32_t *cell;

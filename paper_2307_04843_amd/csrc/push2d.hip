@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int m = 0; m < 3; ++m) {
                         cum += DSx[m] * cz;
-                        atomic_add(&a.J[0][gz[b] + gx[m]], fx * cum);
+                        atomic_add(&a.Jacc[0][gz[b] + gx[m]], (double)(fx * cum));
                     }
                 }
 #pragma unroll
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
                         cum += DSz[b] * cx;
-                        atomic_add(&a.J[2][gz[b] + gx[m]], fz * cum);
+                        atomic_add(&a.Jacc[2][gz[b] + gx[m]], (double)(fz * cum));
                     }
                 }
 #pragma unroll
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     for (int m = 0; m < 4; ++m) {
                         const T wy = S0x[m] * S0z[b] + T(0.5) * DSx[m] * S0z[b] +
                                      T(0.5) * S0x[m] * DSz[b] + third * DSx[m] * DSz[b];
-                        atomic_add(&a.J[1][gz[b] + gx[m]], fy * wy);
+                        atomic_add(&a.Jacc[1][gz[b] + gx[m]], (double)(fy * wy));
                     }
             }
 
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const A v = sJ[c * RC + e];
-            if (v != A(0)) atomic_add(&a.J[c][g], T(v));
+            if (v != A(0)) atomic_add(&a.Jacc[c][g], (double)v);
         }
     }
 }

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
                     const int gx = wrap3(idx[0] + base[0] + i4, nx);
                     const int gy = wrap3(idx[1] + base[1] + j4, ny);
                     const int gz = wrap3(idx[2] + base[2] + k4, nz);
-                    atomic_add(&a.J[comp][(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)], v);
+                    atomic_add(&a.Jacc[comp][(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)], (double)v);
                 };
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4)
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double v = sJ[c * RC + e];
-            if (v != 0.0) atomic_add(&a.J[c][g], T(v));
+            if (v != 0.0) atomic_add(&a.Jacc[c][g], v);
         }
     }
 }

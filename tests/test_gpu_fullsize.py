@@ -1,0 +1,116 @@
+"""Parity at the benchmark's full size, in the benchmark's launch configuration.
+
+The 2-D LG run of ``bench.py`` (4096 x 1024 cells at lambda/20, 16 electrons +
+16 protons per cell = 134M particles, density ramp, LG l=1 p=0 a0=5, default
+tiles and re-sort schedule) is advanced to step 395 (t = 13.3 lambda/c, the
+pulse inside the ramp).  Two single steps are then checked: step 395 (an
+in-place push) and step 396 (re-sort, then push from the sorted copy).  For
+each, the oracle recomputes the push of sampled particles one by one from
+the GPU's state and fields at the start of the step.  Half the sample lies in
+the pulse (x < 13.3 lambda, |z| < 10.6 lambda), half is uniform.  The
+continuity residual of the whole grid is checked too; it holds at any size.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import bench
+from oracle import pic, pulses, units
+from paper_2307_04843_amd import apt
+from paper_2307_04843_amd.sim import Simulation
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+L = units.LAMBDA
+N_SAMPLE = 1000   # per species, per half (pulse region / uniform)
+
+
+def _sample_ids(n_part, seed):
+    """Particle ids: half with their initial cell in the pulse region, half uniform.
+    Ids follow the generator's cell-by-cell order (id // ppc = initial cell)."""
+    nx, _, nz = bench.N_CELLS
+    rng = np.random.default_rng(seed)
+    cx = rng.integers(0, 266, N_SAMPLE)
+    cz = rng.integers(300, 724, N_SAMPLE)
+    pulse = (cz * nx + cx) * bench.PPC + rng.integers(0, bench.PPC, N_SAMPLE)
+    uniform = rng.choice(n_part, N_SAMPLE, replace=False)
+    return np.unique(np.concatenate([pulse, uniform]).astype(np.int64))
+
+
+def _select(sim, i, ids):
+    """Host copy of the particles with the given ids, ordered by id."""
+    a = sim.arrays[i]
+    idt = torch.as_tensor(ids, device=sim.device, dtype=a["id"].dtype)
+    k = torch.isin(a["id"], idt).nonzero().squeeze(1)
+    k = k[torch.argsort(a["id"][k])]
+    nk = int(k.numel())
+    off = [a["off"][c][k].cpu().numpy() if a["off"][c] is not None else np.zeros(nk, np.float32)
+           for c in range(3)]
+    return {"id": a["id"][k].cpu().numpy(), "cell": a["cell"][k].cpu().numpy(),
+            "off": np.stack(off), "u": np.stack([a["u"][c][k].cpu().numpy() for c in range(3)]),
+            "w": a["w"][k].cpu().numpy()}
+
+
+def _positions(st):
+    nx = bench.N_CELLS[0]
+    cell = st["cell"].astype(np.int64)
+    pos = np.zeros((3, cell.size))
+    pos[0] = (cell % nx) + st["off"][0].astype(float)
+    pos[2] = (cell // nx) + st["off"][2].astype(float)
+    return pos
+
+
+def _check_one_step(sim, species, ids, P, dt):
+    E, B, _ = sim.field_views()
+    fields = [t.double().cpu().numpy() for t in E + B]
+    t_n, _ = sim.time()
+    pre = [_select(sim, i, ids[i]) for i in range(len(species))]
+    sim.step(1, flags=apt.AP_STEP_CONTINUITY)
+    post = [_select(sim, i, ids[i]) for i in range(len(species))]
+    g = pic.Grid(2, bench.N_CELLS, (bench.LAMBDA_DX * L,) * 3, dt * L, (0.0, 0.0, -25.6 * L), t0=t_n * L)
+    for k in range(3):
+        g.E[k][...] = fields[k]
+        g.B[k][...] = fields[3 + k]
+    worst_u, worst_x = 0.0, 0.0
+    for sp_desc, a, b in zip(species, pre, post):
+        assert np.array_equal(a["id"], b["id"])
+        sp = pic.Species(sp_desc["q"], sp_desc["m"], _positions(a), a["u"].astype(float), a["w"].astype(float))
+        fs = cases.force_scale(g, [sp], P)[0]
+        u_half = pic.push_species(g, sp, P)
+        x_new = pic.move(g, sp.pos, u_half)
+        scale = np.maximum(np.maximum(np.linalg.norm(u_half, axis=0), np.linalg.norm(sp.u, axis=0)), fs)
+        du = np.linalg.norm(b["u"].astype(float) - u_half, axis=0) / scale
+        worst_u = max(worst_u, float(du.max()))
+        pos = _positions(b)
+        for ax, n in ((0, bench.N_CELLS[0]), (2, bench.N_CELLS[2])):
+            worst_x = max(worst_x, float(np.abs(cases.periodic_diff(pos[ax], x_new[ax], n)).max()))
+    return worst_u, worst_x
+
+
+@pytest.mark.timeout(900)
+def test_full_size_lg_run_sampled_pushes_and_continuity():
+    species = bench.workload_inputs()
+    n_part = [int(s["state"]["u"].shape[1]) for s in species]
+    dt = 0.95 / math.sqrt(2) * bench.LAMBDA_DX
+    pp = bench.workload_pulse(dt)
+    P = pulses.Pulse(dict(type="lg", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    ids = [_sample_ids(n, seed=20 + i) for i, n in enumerate(n_part)]
+    sim = Simulation(2, n=bench.N_CELLS, dx=(bench.LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
+                     precision="f32", species=species)
+    del species[0]["state"], species[1]["state"]
+    try:
+        sim.set_pulse("lg", **pp)
+        sim.step(395)
+        results = [_check_one_step(sim, species, ids, P, dt) for _ in range(2)]   # in-place, then re-sort
+        d, _ = sim.diag()
+    finally:
+        sim.close()
+    for worst_u, worst_x in results:
+        assert worst_u <= 1e-6, results
+        assert worst_x <= 1e-6, results
+    dxi = bench.LAMBDA_DX * L
+    assert d.j_max > 0
+    assert d.continuity_max <= 1e-6 * d.j_max / dxi, (d.continuity_max, d.j_max / dxi)
