@@ -114,3 +114,73 @@ def test_full_size_lg_run_sampled_pushes_and_continuity():
     dxi = bench.LAMBDA_DX * L
     assert d.j_max > 0
     assert d.continuity_max <= 1e-6 * d.j_max / dxi, (d.continuity_max, d.j_max / dxi)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_collision_sampled_step_and_fp32_fp64_gradients():
+    """The gridless collision of the adjoint leg at full size (2^24 electrons,
+    eps^4 pulse a0 = 20, w0 = 2).  (1) After 900 steps (t = 99 lambda/c, beam
+    inside the pulse) one step of 4000 sampled electrons is recomputed by the
+    oracle: momenta <= 1e-6 relative, positions <= 1e-6 lambda.  (2) The FP32
+    and FP64 adjoints over the 200 steps t = 99 ... 101 give the same gradient
+    of <p_perp^2> wrt (a0, w0) to 1e-4 relative; x_f's gradient, which nearly
+    cancels on the symmetric beam, agrees to 1e-4 of the gradient norm."""
+    from paper_2307_04843_amd.autograd import APTRun, GridlessRun
+    beam = bench.adjoint_beam()
+    n = int(beam["u"].shape[1])
+    prm = bench.adjoint_pulse()
+    sim = Simulation(0, dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=bench.ADJ_T0, dt=bench.ADJ_DT,
+                     precision="f32", species=[dict(q=-1.0, m=1.0, state=beam)])
+    ids = np.sort(np.random.default_rng(31).choice(n, 4000, replace=False))
+    try:
+        sim.set_pulse("gauss_np", **prm)
+        sim.step(900)
+        t_n, _ = sim.time()
+        pre = _select_gridless(sim, ids)
+        sim.step(1)
+        post = _select_gridless(sim, ids)
+        beam_t = {k: [t.clone() for t in sim.arrays[0][k]] for k in ("icell", "off", "u")}
+    finally:
+        sim.close()
+    P = pulses.Pulse(dict(type="gauss_np", **prm))
+    X = (pre["icell"].astype(float) + pre["off"].astype(float)) * L
+    u0 = pre["u"].astype(float)
+    X1, u1 = pic.gridless_step(t_n * L, bench.ADJ_DT * L, X, u0, -1.0, P)
+    scale = np.maximum(np.maximum(np.linalg.norm(u1, axis=0), np.linalg.norm(u0, axis=0)),
+                       np.linalg.norm(u1 - u0, axis=0))
+    assert (np.linalg.norm(post["u"].astype(float) - u1, axis=0) / scale).max() <= 1e-6
+    Xg = (post["icell"].astype(float) + post["off"].astype(float)) * L
+    assert np.abs(Xg - X1).max() / L <= 1e-6
+
+    # gradients over t = 99 ... 101 from the state reached above
+    state = {"icell": np.stack([t.cpu().numpy() for t in beam_t["icell"]]),
+             "off": np.stack([t.cpu().numpy() for t in beam_t["off"]]),
+             "u": np.stack([t.cpu().numpy() for t in beam_t["u"]]), "w": beam["w"]}
+    del beam_t, beam
+    grads = {}
+    for prec in ("f32", "f64"):
+        run = GridlessRun(state, "gauss_np", prm, ["a0", "w0", "x_f"], 200, bench.ADJ_DT, t0=t_n,
+                          precision=prec)
+        try:
+            p = torch.tensor([prm["a0"], prm["w0"], prm["x_f"]], dtype=torch.float64, requires_grad=True)
+            u, _ = APTRun.apply(p, run)
+            ((u[1].double() ** 2 + u[2].double() ** 2).sum() / n).backward()
+            grads[prec] = p.grad.numpy().copy()
+        finally:
+            run.close()
+            del run
+            torch.cuda.empty_cache()
+    g32, g64 = grads["f32"], grads["f64"]
+    assert np.all(np.abs(g32[:2] - g64[:2]) <= 1e-4 * np.abs(g64[:2])), (g32, g64)
+    assert abs(g32[2] - g64[2]) <= 1e-4 * np.linalg.norm(g64), (g32, g64)
+
+
+def _select_gridless(sim, ids):
+    a = sim.arrays[0]
+    idt = torch.as_tensor(ids, device=sim.device, dtype=a["id"].dtype)
+    k = torch.isin(a["id"], idt).nonzero().squeeze(1)
+    k = k[torch.argsort(a["id"][k])]
+    return {"id": a["id"][k].cpu().numpy(),
+            "icell": np.stack([a["icell"][c][k].cpu().numpy() for c in range(3)]),
+            "off": np.stack([a["off"][c][k].cpu().numpy() for c in range(3)]),
+            "u": np.stack([a["u"][c][k].cpu().numpy() for c in range(3)])}
