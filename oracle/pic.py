@@ -4,8 +4,10 @@ Fig. 1 of the paper: the analytic fields E1, B1 are added to the internally
 advanced fields E2, B2, the total field is interpolated to the particles and
 used for the particle push, and the particle current drives the internal
 field update of E2, B2 only (Eq. (4)).  The paper evaluates E1, B1 on the
-grid before interpolation; here (as in the HIP path) they are evaluated at
-the particle position, and only E2, B2 are interpolated.
+grid before interpolation (``pulse_on_grid=True`` here: each component is
+sampled at its own staggered node and added to E2, B2 before the gather);
+the default evaluates them at the particle position, and only E2, B2 are
+interpolated.
 
 Grid conventions (internal units, periodic in every direction):
 * arrays are indexed [k, j, i] = (z, y, x); 2-D (x, z) grids have ny = 1 and
@@ -269,11 +271,47 @@ def yee_step(grid):
 # One full step
 # ----------------------------------------------------------------------------
 
-def push_species(grid, sp, pulse, n_steps_done=None):
+def sample_pulse(grid, pulse):
+    """E1, B1 sampled on the grid at time grid.t: each component at its own
+    staggered node (the literal loop of Fig. 1).  On (x, z) grids the lab y
+    of every node is the pulse's slice.  Returns (E1[3], B1[3]) shaped like
+    grid.E."""
+    nx, ny, nz = grid.n
+    ii = np.arange(nx)[None, None, :]
+    jj = np.arange(ny)[None, :, None]
+    kk = np.arange(nz)[:, None, None]
+    shape = (nz, ny, nx)
+    out = []
+    for stag, which in ((E_STAGGER, 0), (B_STAGGER, 1)):
+        comps = []
+        for c in range(3):
+            X = np.broadcast_to(grid.x_min[0] + (ii + stag[c][0]) * grid.dx[0], shape)
+            Z = np.broadcast_to(grid.x_min[2] + (kk + stag[c][2]) * grid.dx[2], shape)
+            if grid.dim == 3:
+                Y = np.broadcast_to(grid.x_min[1] + (jj + stag[c][1]) * grid.dx[1], shape)
+            else:
+                Y = np.full(shape, pulse.q_slice)
+            F = _pulses.analytic_fields(pulse, grid.t, X, Y, Z)[which]
+            comps.append(np.array(F[c], dtype=float))
+        out.append(comps)
+    return out[0], out[1]
+
+
+def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False):
     """Field evaluation and Boris push of one species at time grid.t.
 
     Returns u^{n+1/2}; positions are not changed.
     """
+    if pulse is not None and pulse_on_grid:
+        E1g, B1g = sample_pulse(grid, pulse)
+        saved = grid.E, grid.B
+        grid.E = [a + b for a, b in zip(saved[0], E1g)]
+        grid.B = [a + b for a, b in zip(saved[1], B1g)]
+        try:
+            E, B = gather(grid, sp.pos)
+        finally:
+            grid.E, grid.B = saved
+        return boris(sp.u, E, B, sp.q / sp.m, grid.dt)
     E2, B2 = gather(grid, sp.pos)
     if pulse is not None:
         X, Y, Z = lab_positions(grid, sp.pos, pulse.q_slice)
@@ -303,10 +341,11 @@ def wrap(grid, pos):
     return out
 
 
-def step(grid, species, pulse, field_update=True):
+def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
     """One step of the loop of Fig. 1.
 
-    For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n; Boris push;
+    For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n (E1, B1 at the
+    particle, or sampled on the grid with ``pulse_on_grid``); Boris push;
     move; deposit J^{n+1/2}.  Then the Yee update of E2, B2 with J.  J holds
     the step's current afterwards.  Returns per-species (pos_unwrapped_new,)
     for diagnostics.
@@ -315,7 +354,7 @@ def step(grid, species, pulse, field_update=True):
         grid.J[c][...] = 0.0
     moved = []
     for sp in species:
-        u_half = push_species(grid, sp, pulse)
+        u_half = push_species(grid, sp, pulse, pulse_on_grid=pulse_on_grid)
         new = move(grid, sp.pos, u_half)
         disp = np.abs(new - sp.pos)
         if np.any(disp >= 1.0):

@@ -33,6 +33,9 @@ converted here with the factor 2*pi of ``units``:
     dx_prop, dt cell size along x and time step, lambda units (fix the
                 numerical v_phi, v_g, B0/E0 of Eqs. (10)-(14))
     np_order    0 or 4: order in eps = w0/x_R of the nonparaxial Gaussian
+    envelope    'sin2' (default) or 'sgauss': super-Gaussian of order
+                sg_order whose intensity full width at half maximum is
+                fwhm (lambda/c), centred in the support [0, tau]
 """
 import math
 
@@ -83,6 +86,18 @@ class Pulse:
         # the sweep across the envelope is chirp * omega.
         self.b = self.chirp * self.omega / self.tau
         self.lg_norm = _lg_peak_norm(abs(self.lg_l), self.lg_p) if self.kind == "lg" else 1.0
+        # Temporal envelope: sin^2, or the super-Gaussian the paper's runs use
+        # (Sec. II.B), exp(-((eta - tau/2)/tau_g)^(2g)); tau_g is fixed by the
+        # intensity FWHM: Gamma^2 = 1/2 at (eta - tau/2)/tau_g = (ln 2 / 2)^(1/2g).
+        self.envelope = prm.get("envelope", "sin2")
+        if self.envelope not in ("sin2", "sgauss"):
+            raise ValueError("unknown envelope %r" % (self.envelope,))
+        self.sg_order = int(prm.get("sg_order", 4))
+        self.fwhm = float(prm.get("fwhm", 0.0)) * L
+        if self.envelope == "sgauss":
+            if self.sg_order < 1 or not self.fwhm > 0.0:
+                raise ValueError("the super-Gaussian envelope needs sg_order >= 1 and fwhm > 0")
+            self.tau_g = self.fwhm / (2.0 * (math.log(2.0) / 2.0) ** (1.0 / (2 * self.sg_order)))
         if self.kind == "lg" and self.d_f != 3:
             raise ValueError("Laguerre-Gaussian modes need d_f = 3")
 
@@ -129,7 +144,7 @@ def _lg_peak_norm(l_abs, p):
 
 
 def _envelope(P, t, X):
-    """sin^2 envelope Gamma and chirp phase Phi of Eq. (15).
+    """Envelope Gamma (sin^2 or super-Gaussian) and chirp phase Phi of Eq. (15).
 
     eta = (t - t_ref) - (x - x_ref)/v_g + tau/2 is the envelope argument
     t - x/v_g shifted so that the support is 0 <= eta <= tau and the peak
@@ -137,7 +152,11 @@ def _envelope(P, t, X):
     """
     eta = (t - P.t_ref) - (X - P.x_ref) / P.v_g + P.tau / 2.0
     inside = (eta >= 0.0) & (eta <= P.tau)
-    gam = np.where(inside, P.a0 * np.sin(math.pi * eta / P.tau) ** 2, 0.0)
+    if P.envelope == "sgauss":
+        prof = np.exp(-((eta - P.tau / 2.0) / P.tau_g) ** (2 * P.sg_order))
+    else:
+        prof = np.sin(math.pi * eta / P.tau) ** 2
+    gam = np.where(inside, P.a0 * prof, 0.0)
     phi = 0.5 * P.b * (eta - P.tau / 2.0) ** 2
     return gam, phi
 

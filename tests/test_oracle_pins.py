@@ -123,13 +123,55 @@ def test_pin2_dispersion_constants():
     assert vac[:3] == (1.0, 1.0, 1.0)
 
 
+def test_super_gaussian_envelope_shape():
+    """Super-Gaussian envelope (the profile of the paper's runs, Sec. II.B):
+    the intensity FWHM equals the requested one for several orders; order 1
+    is the Gaussian exp(-(eta - tau/2)^2 / tau_g^2) with tau_g = FWHM /
+    sqrt(2 ln 2); the peak sits at tau/2 and the support is [0, tau]."""
+    for g in (1, 2, 4, 8):
+        P = pulses.Pulse(dict(type="plane", a0=2.0, tau=200.0, envelope="sgauss", sg_order=g, fwhm=30.0,
+                              dispersion=units.DISP_VACUUM))
+        eta = np.linspace(0.0, P.tau, 400001)
+        X = -(eta - P.tau / 2.0)            # t = t_ref = x_ref = 0, v_g = 1
+        gam, _ = pulses._envelope(P, 0.0, X)
+        inten = (gam / P.a0) ** 2
+        above = eta[inten >= 0.5]
+        assert abs((above[-1] - above[0]) / L - 30.0) < 2e-3, (g, (above[-1] - above[0]) / L)
+        assert abs(gam.max() - 2.0) < 1e-12
+        assert abs(0.5 * (above[0] + above[-1]) - P.tau / 2.0) < 1e-3 * L
+        if g == 1:
+            tg = 30.0 * L / math.sqrt(2.0 * math.log(2.0))
+            ref = 2.0 * np.exp(-((eta - P.tau / 2.0) / tg) ** 2)
+            assert np.allclose(gam, ref, rtol=0, atol=1e-12)
+    P = pulses.Pulse(dict(type="plane", a0=1.0, tau=50.0, envelope="sgauss", sg_order=4, fwhm=30.0,
+                          dispersion=units.DISP_VACUUM))
+    gam, _ = pulses._envelope(P, 0.0, np.array([P.tau / 2.0 + 1e-9, -P.tau / 2.0 - 1e-9]))
+    assert np.all(gam == 0.0)
+
+
+def test_super_gaussian_plane_pulse_discrete_yee_orders():
+    """Sec. II.B: with a fourth-order super-Gaussian, the error of the analytic
+    plane pulse against the Yee update is fourth order in omega dx at the peak
+    (flat top) and second order on the rising edge.  Measured here as the
+    one-step split-Yee residual of the sampled pulse (second-order constants of
+    Eqs. (12)-(14)), at the peak and on the edge of a pulse of FWHM 100
+    lambda/c."""
+    sg = dict(envelope="sgauss", sg_order=4, fwhm=100.0)
+    d = (0.05, 0.025)
+    peak = [_plane_yee_residual(units.DISP_PAPER2, x, 160.0, 2.0, **sg) for x in d]
+    edge = [_plane_yee_residual(units.DISP_PAPER2, x, 160.0, 2.0, window_at=-55.0, **sg) for x in d]
+    assert peak[0] / peak[1] > 12.0, peak                # fourth order at the flat top
+    assert 3.0 < edge[0] / edge[1] < 5.0, edge           # second order on the edge
+    assert edge[1] > 5.0 * peak[1]                       # and the gap widens with resolution
+
+
 def test_pin2_time_step_rule():
     """c dt/dx = 0.95/sqrt(D) (stated after Eq. (14))."""
     assert abs(units.default_dt(1.0, 2) - 0.95 / math.sqrt(2)) < 1e-15
     assert abs(units.default_dt(2.0, 3) - 2 * 0.95 / math.sqrt(3)) < 1e-15
 
 
-def _plane_yee_residual(mode, dxl, tau, half_window, b_over_e=None):
+def _plane_yee_residual(mode, dxl, tau, half_window, b_over_e=None, window_at=0.0, **extra):
     """Max one-step residual (E, B) of the sampled PLANE pulse under the split
     Yee step of Eqs. (7)-(9) in 1-D (E_y on nodes, B_z on half nodes, both at
     integer times; B half step, E full step, B half step), over a window of
@@ -137,12 +179,12 @@ def _plane_yee_residual(mode, dxl, tau, half_window, b_over_e=None):
     analytic value at t + dt) / dt."""
     dt_l = 0.95 / math.sqrt(2) * dxl
     P = pulses.Pulse(dict(type="plane", a0=1.0, tau=tau, t_ref=0.0, x_ref=0.0, pol=0,
-                          dispersion=mode, dx_prop=dxl, dt=dt_l))
+                          dispersion=mode, dx_prop=dxl, dt=dt_l, **extra))
     if b_over_e is not None:
         P.b_over_e = b_over_e
     dx, dt = dxl * L, dt_l * L
     t = (tau + 3.0) * L
-    xc = P.v_g * t                      # envelope peak (t_ref = x_ref = 0)
+    xc = P.v_g * (t - window_at * L)    # envelope peak (t_ref = x_ref = 0), shifted by window_at
     n0 = int((xc - half_window * L) / dx)
     x = (n0 + np.arange(int(2 * half_window / dxl))) * dx
     xh = x + dx / 2
@@ -720,3 +762,44 @@ def test_reference_gradient_converges_at_fourth_order():
     gap1, gap2 = abs(a1 - b1), abs(a2 - b2)
     assert 10.0 < gap1 / gap2 < 22.0, (gap1, gap2)
     assert abs(g1 - g2) < 0.05 * gap2 + 1e-9 * abs(g2)
+
+
+def test_grid_sampled_pulse_converges_to_particle_evaluation():
+    """The paper's literal loop (Fig. 1) samples E1, B1 on the Yee grid, each
+    component at its own staggered node, and interpolates the sum with the
+    particle shape.  The interpolated sampled field must approach the field
+    evaluated at the particle at second order in dx (quadratic B-spline
+    smoothing of a smooth field): halving dx divides the difference by ~4.
+    Sampling a component at the wrong stagger leaves a first-order error."""
+    P = pulses.Pulse(dict(type="gauss", a0=2.0, tau=30.0, t_ref=0.0, x_ref=3.2, x_f=3.2, w0=2.0, d_f=2, pol=1,
+                          dispersion=units.DISP_VACUUM))
+    errs = []
+    for dxl in (0.05, 0.025):
+        n = int(round(6.4 / dxl))
+        g = pic.Grid(2, (n, 1, n), (dxl * L,) * 3, 0.5 * dxl * L, (0.0, 0.0, -3.2 * L), t0=0.0)
+        E1g, B1g = pic.sample_pulse(g, P)
+        g.E, g.B = E1g, B1g
+        rng = np.random.default_rng(5)
+        pos = np.zeros((3, 400))
+        pos[0] = rng.uniform(0.3, 0.7, 400) * n
+        pos[2] = rng.uniform(0.3, 0.7, 400) * n
+        Eg, Bg = pic.gather(g, pos)
+        X, Y, Z = pic.lab_positions(g, pos, P.q_slice)
+        Ep, Bp = pulses.analytic_fields(P, g.t, X, Y, Z)
+        errs.append(max(np.abs(Eg - Ep).max(), np.abs(Bg - Bp).max()) / P.a0)
+    assert 3.2 < errs[0] / errs[1] < 4.8, errs
+    kdx = 2 * math.pi * 0.025
+    assert errs[1] < 1.2 * kdx ** 2 / 8      # the B-spline smoothing of a carrier, (k dx)^2 / 8
+    # a planted stagger error (E_x sampled on the nodes) is first order
+    dxl = 0.05
+    n = int(round(6.4 / dxl))
+    g = pic.Grid(2, (n, 1, n), (dxl * L,) * 3, 0.5 * dxl * L, (0.0, 0.0, -3.2 * L), t0=0.0)
+    E1g, B1g = pic.sample_pulse(g, P)
+    ii = np.arange(n)[None, None, :]
+    kk = np.arange(n)[:, None, None]
+    Xn = np.broadcast_to(g.x_min[0] + ii * g.dx[0], E1g[0].shape)
+    Zn = np.broadcast_to(g.x_min[2] + kk * g.dx[2], E1g[0].shape)
+    E1g[0] = np.array(pulses.analytic_fields(P, g.t, Xn, np.zeros_like(Xn), Zn)[0][0])
+    g.E, g.B = E1g, B1g
+    Eg, _ = pic.gather(g, pos)
+    assert np.abs(Eg - Ep).max() / P.a0 > 10 * errs[0]
