@@ -72,6 +72,20 @@ typedef int32_t ap_status;
 #define AP_STEP_NO_YEE      0x2u  /* keep E2, B2 frozen (J is still deposited)  */
 #define AP_STEP_RECORD      0x4u  /* gridless: keep adjoint checkpoints        */
 
+/* ap_grid_desc options */
+#define AP_GRID_PULSE_ON_GRID 0x1  /* allow AP_SAMPLE_GRID (reserves workspace)  */
+
+/* Temporal envelopes (Sec. II.A sin^2 form; Sec. II.B super-Gaussian runs). */
+#define AP_ENV_SIN2         0   /* a0 sin^2(pi eta / tau) on [0, tau]           */
+#define AP_ENV_SGAUSS       1   /* a0 exp(-((eta - tau/2)/tau_g)^(2g)) on [0, tau],
+                                   tau_g from the intensity FWHM              */
+
+/* Where E1, B1 are evaluated (Fig. 1). */
+#define AP_SAMPLE_PARTICLES 0   /* at every particle (default)                  */
+#define AP_SAMPLE_GRID      1   /* at the staggered Yee nodes, added to E2, B2
+                                   before the gather (gridded runs with
+                                   AP_GRID_PULSE_ON_GRID)                      */
+
 /* ap_gather_diag masks */
 #define AP_DIAG_PARTICLES   0x1u  /* moments, energies, proxy, NaN count       */
 #define AP_DIAG_FIELDS      0x2u  /* E2, B2 field energy                        */
@@ -95,6 +109,9 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
  *              with the smallest dx (the rule stated after Eq. (14)).
  *   sort_every steps between tile re-sorts (0 = default: 12 in 2-D, 2 in 3-D).
+ *   options    AP_GRID_* bits (0 = none).  AP_GRID_PULSE_ON_GRID reserves
+ *              the workspace for the grid-sampled pulse (AP_SAMPLE_GRID):
+ *              6 more reals per cell.
  */
 typedef struct ap_grid_desc {
     int32_t dim;
@@ -106,7 +123,7 @@ typedef struct ap_grid_desc {
     double  t0;
     double  dt;
     int32_t sort_every;
-    int32_t reserved;
+    int32_t options;
 } ap_grid_desc;
 
 /* One particle species: charge in |e|, mass in m_e, count of macroparticles. */
@@ -174,13 +191,19 @@ typedef struct ap_buffers {
  *   beta_f, x0_ff, t0_ff   flying focus: v_f/c, focus at x0_ff at t0_ff
  *   dispersion   AP_DISP_*; dx_prop, dt_prop: grid spacing along x and
  *                time step that fix v_phi, v_g, B0/E0 (0 = use the grid's)
- *   np_order     nonparaxial order (0 or 4) for AP_PULSE_GAUSS_NP */
+ *   np_order     nonparaxial order (0 or 4) for AP_PULSE_GAUSS_NP
+ *   envelope     AP_ENV_*; sg_order g >= 1 and fwhm (intensity full width at
+ *                half maximum, lambda/c) for AP_ENV_SGAUSS, centred in the
+ *                support [0, tau] (the reading of the paper's super-Gaussian)
+ *   sampling     AP_SAMPLE_* */
 typedef struct ap_pulse_params {
     double  a0, tau, t_ref, x_ref, phi0, chirp;
     double  x_f, w0, y_c, z_c, q_slice;
     double  beta_f, x0_ff, t0_ff;
     double  dx_prop, dt_prop;
     int32_t d_f, lg_l, lg_p, pol, dispersion, np_order;
+    int32_t envelope, sg_order, sampling, reserved;
+    double  fwhm;
 } ap_pulse_params;
 
 /* FP64 diagnostics (reductions of the current state). */

@@ -20,6 +20,11 @@ AP_DISP_PAPER2, AP_DISP_EXACT, AP_DISP_VACUUM = 0, 1, 2
 AP_STEP_CONTINUITY, AP_STEP_NO_YEE, AP_STEP_RECORD = 0x1, 0x2, 0x4
 AP_DIAG_PARTICLES, AP_DIAG_FIELDS = 0x1, 0x2
 AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5)
+AP_GRID_PULSE_ON_GRID = 0x1
+AP_ENV_SIN2, AP_ENV_SGAUSS = 0, 1
+AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID = 0, 1
+ENVELOPES = {"sin2": AP_ENV_SIN2, "sgauss": AP_ENV_SGAUSS}
+SAMPLINGS = {"particles": AP_SAMPLE_PARTICLES, "grid": AP_SAMPLE_GRID}
 
 PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE_GAUSS,
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
@@ -33,7 +38,7 @@ class ap_grid_desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("n", C.c_int32 * 3),
                 ("tile", C.c_int32 * 3), ("dx", C.c_double * 3), ("x_min", C.c_double * 3),
                 ("t0", C.c_double), ("dt", C.c_double), ("sort_every", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("options", C.c_int32)]
 
 
 class ap_species_desc(C.Structure):
@@ -61,7 +66,9 @@ class ap_pulse_params(C.Structure):
                 ("beta_f", C.c_double), ("x0_ff", C.c_double), ("t0_ff", C.c_double),
                 ("dx_prop", C.c_double), ("dt_prop", C.c_double),
                 ("d_f", C.c_int32), ("lg_l", C.c_int32), ("lg_p", C.c_int32), ("pol", C.c_int32),
-                ("dispersion", C.c_int32), ("np_order", C.c_int32)]
+                ("dispersion", C.c_int32), ("np_order", C.c_int32),
+                ("envelope", C.c_int32), ("sg_order", C.c_int32), ("sampling", C.c_int32),
+                ("reserved", C.c_int32), ("fwhm", C.c_double)]
 
 
 class ap_diag(C.Structure):
@@ -214,8 +221,13 @@ def pulse_params(**kw):
     p = ap_pulse_params()
     defaults = dict(a0=1.0, tau=10.0, t_ref=0.0, x_ref=0.0, phi0=0.0, chirp=0.0, x_f=0.0, w0=5.0,
                     y_c=0.0, z_c=0.0, q_slice=0.0, beta_f=0.0, x0_ff=0.0, t0_ff=0.0, dx_prop=0.0,
-                    dt_prop=0.0, d_f=3, lg_l=0, lg_p=0, pol=0, dispersion=AP_DISP_PAPER2, np_order=4)
+                    dt_prop=0.0, d_f=3, lg_l=0, lg_p=0, pol=0, dispersion=AP_DISP_PAPER2, np_order=4,
+                    envelope=AP_ENV_SIN2, sg_order=4, sampling=AP_SAMPLE_PARTICLES, fwhm=0.0)
     defaults.update(kw)
+    if isinstance(defaults["envelope"], str):
+        defaults["envelope"] = ENVELOPES[defaults["envelope"]]
+    if isinstance(defaults["sampling"], str):
+        defaults["sampling"] = SAMPLINGS[defaults["sampling"]]
     for k, v in defaults.items():
         setattr(p, k, v)
     return p

@@ -43,6 +43,7 @@ struct RunShape {
     double dt = 0, t0 = 0;
     int sort_every = 8;
     int splits = 1;
+    int options = 0;
     size_t real = 4;
     int64_t np[kMaxSpecies] = {0, 0, 0, 0};
     double q[kMaxSpecies] = {0, 0, 0, 0};
@@ -50,7 +51,7 @@ struct RunShape {
 };
 
 struct WorkLayout {
-    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, total = 0;
+    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, total = 0;
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -123,6 +124,10 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
+    if (g->options & ~AP_GRID_PULSE_ON_GRID) return fail(AP_E_ARG, "unknown grid option bits");
+    if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
+        return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
+    s.options = g->options;
     // default re-sort interval: 2-D tiles carry a two-cell drift margin, 3-D
     // tiles none (LDS budget), so 3-D re-sorts every other step
     s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 2 : 12);
@@ -166,6 +171,8 @@ WorkLayout make_layout(const RunShape &s) {
         L.rho1 = take((size_t)s.ncell * 8);
         // FP64 accumulator of the step's current (FP32 runs; FP64 runs use J)
         if (s.prec == AP_F32) L.jacc = take((size_t)s.ncell * 3 * 8);
+        // E2 + E1 and B2 + B1 with E1, B1 sampled on the grid (AP_SAMPLE_GRID)
+        if (s.options & AP_GRID_PULSE_ON_GRID) L.esamp = take((size_t)s.ncell * 6 * s.real);
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
             L.count[i] = take((size_t)s.ntiles * 4);
@@ -401,6 +408,16 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
             return fail(AP_E_ARG, "LG indices must satisfy 0 <= p <= 8, |l| <= 8");
     }
     if (type == AP_PULSE_FF && prm->beta_f == 1.0) return fail(AP_E_ARG, "flying focus needs beta_f != 1");
+    if (prm->envelope != AP_ENV_SIN2 && prm->envelope != AP_ENV_SGAUSS)
+        return fail(AP_E_ARG, "unknown envelope");
+    if (prm->envelope == AP_ENV_SGAUSS) {
+        if (prm->sg_order < 1 || prm->sg_order > 32) return fail(AP_E_ARG, "sg_order must be 1..32");
+        if (!std::isfinite(prm->fwhm) || !(prm->fwhm > 0.0)) return fail(AP_E_ARG, "fwhm must be > 0");
+    }
+    if (prm->sampling != AP_SAMPLE_PARTICLES && prm->sampling != AP_SAMPLE_GRID)
+        return fail(AP_E_ARG, "unknown sampling mode");
+    if (prm->sampling == AP_SAMPLE_GRID && !(c->s.dim > 0 && (c->s.options & AP_GRID_PULSE_ON_GRID)))
+        return fail(AP_E_STATE, "grid sampling needs a gridded run created with AP_GRID_PULSE_ON_GRID");
     if (type == AP_PULSE_GAUSS_NP) {
         if (prm->dispersion != AP_DISP_VACUUM)
             return fail(AP_E_ARG, "the nonparaxial Gaussian is a vacuum solution: use AP_DISP_VACUUM");
@@ -434,6 +451,14 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
     P.lg_l = prm->lg_l;
     P.lg_p = prm->lg_p;
     P.np_order = prm->np_order;
+    P.envelope = prm->envelope;
+    P.sg_order = prm->envelope == AP_ENV_SGAUSS ? prm->sg_order : 1;
+    // super-Gaussian: intensity exp(-2 x^(2g)) is 1/2 at x = (ln 2 / 2)^(1/(2g)),
+    // so tau_g = FWHM / (2 (ln 2 / 2)^(1/(2g)))
+    P.inv_tau_g = prm->envelope == AP_ENV_SGAUSS
+                      ? 2.0 * std::pow(0.5 * std::log(2.0), 0.5 / prm->sg_order) / (prm->fwhm * L)
+                      : 0.0;
+    P.sampling = prm->sampling;
     P.a0 = prm->a0;
     P.tau = prm->tau * L;
     P.inv_tau = 1.0 / P.tau;
@@ -1009,6 +1034,32 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     a.q_slice = c->P.q_slice;
     a.pulse = c->P.type;
     a.W = plain_vars<T>(c->P, a.t);
+    // grid-sampled pulse: the push gathers E2 + E1 and B2 + B1 from the
+    // workspace and evaluates nothing per particle
+    const bool on_grid = c->P.sampling == AP_SAMPLE_GRID && c->P.type != PT_NONE;
+    if (on_grid) {
+        Timer tm(c, 3);
+        SampleArgs<T> sa{};
+        T *S = c->wp<T>(L.esamp);
+        for (int k = 0; k < 6; ++k) {
+            sa.F[k] = F[k];
+            sa.S[k] = S + (size_t)k * nc;
+        }
+        for (int k = 0; k < 3; ++k) {
+            sa.n[k] = s.n[k];
+            sa.dx[k] = s.dx[k];
+            sa.x_min[k] = s.x_min[k];
+            a.E[k] = sa.S[k];
+            a.B[k] = sa.S[3 + k];
+        }
+        sa.dim = s.dim;
+        sa.fnx = fnx;
+        sa.fnxy = fnxy;
+        sa.q_slice = c->P.q_slice;
+        sa.W = a.W;
+        HIPCHK(launch_sample_pulse<T>(c->P.type, sa, c->stream), "sample pulse");
+    }
+    const int push_pulse = on_grid ? (int)PT_NONE : c->P.type;
 
     {
         Timer tm(c, 3);
@@ -1040,8 +1091,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     }
     {
         Timer tm(c, 0);
-        hipError_t e = s.dim == 2 ? launch_push_deposit_2d<T>(c->P.type, a, 256, c->stream)
-                                  : launch_push_deposit_3d<T>(c->P.type, a, 256, c->stream);
+        hipError_t e = s.dim == 2 ? launch_push_deposit_2d<T>(push_pulse, a, 256, c->stream)
+                                  : launch_push_deposit_3d<T>(push_pulse, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
     }

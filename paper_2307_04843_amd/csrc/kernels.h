@@ -78,6 +78,20 @@ template <typename T> struct GridlessArgs {
     PulseVar<T> W;
 };
 
+// Grid-sampled pulse: S[c] = F[c] + (E1, B1)[c] at component c's staggered node.
+template <typename T> struct SampleArgs {
+    const T *F[6];               // E2x E2y E2z B2x B2y B2z
+    T *S[6];                     // sums, same layout
+    int32_t n[3];
+    int32_t dim;
+    FastDiv fnx, fnxy;
+    double dx[3];
+    double x_min[3];
+    double q_slice;              // lab y of an (x, z) grid
+    PulseVar<T> W;               // pulse constants of this step
+};
+template <typename T> hipError_t launch_sample_pulse(int pulse, const SampleArgs<T> &a, hipStream_t s);
+
 template <typename T> struct AdjointArgs {
     const int32_t *icell[3];     // state x^n, u^{n-1/2} of the step being reversed
     const T *off[3];

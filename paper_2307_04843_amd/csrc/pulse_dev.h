@@ -43,6 +43,9 @@ struct PulseDev {
     double eps;                            // nonparaxial expansion parameter w0/x_R
     double np_e2, np_e4;                   // eps^2, eps^4 weights of the truncated potential
     double w0, x_r, inv_w0;
+    int32_t envelope, sg_order;            // AP_ENV_*, super-Gaussian order g
+    double inv_tau_g;                      // 1/tau_g of the super-Gaussian
+    int32_t sampling;                      // AP_SAMPLE_* (host sequencing only)
 };
 
 // Generalised Laguerre L_n^a(x) and its derivative (-L_{n-1}^{a+1}).
@@ -78,6 +81,8 @@ template <typename R> struct PulseVar {
     I s0, b_half;
     R a0, inv_xr, inv_w0sq, inv_w0, eps, np_e2, np_e4, lg_pref, v_phi, b_over_e;
     int32_t pol, d_f, lg_l, lg_p;
+    int32_t envelope, sg_order;
+    double inv_tau_g;
 };
 
 template <typename R> AP_HD void fill_step_constants(const PulseDev &P, double t, PulseVar<R> &V) {
@@ -94,6 +99,9 @@ template <typename R> AP_HD void fill_step_constants(const PulseDev &P, double t
     V.d_f = P.d_f;
     V.lg_l = P.lg_l;
     V.lg_p = P.lg_p;
+    V.envelope = P.envelope;
+    V.sg_order = P.sg_order;
+    V.inv_tau_g = P.inv_tau_g;
 }
 
 // Plain constants of the step at time t (host or device).
@@ -129,9 +137,19 @@ AP_D bool analytic_field_g(const PulseVar<R> &W, const I &X, const I &Y, const I
         const I eta = island_shift(island_scale(X, -W.inv_vg), -W.eta0);
         const double eta_v = ival(eta);
         if (!(eta_v > 0.0 && eta_v < W.tau)) return false;
-        R se, ce;
-        sincospi_r(NT::from_island(island_scale(eta, W.inv_tau)), &se, &ce);
-        const R gam = W.a0 * se * se;
+        R gam;
+        if (W.envelope == 1) {
+            // super-Gaussian exp(-x^(2g)), x = (eta - tau/2) / tau_g
+            const R xg = NT::from_island(island_scale(island_shift(eta, W.half_tau), W.inv_tau_g));
+            const R x2 = xg * xg;
+            R pw = x2;
+            for (int m = 1; m < W.sg_order; ++m) pw = pw * x2;
+            gam = W.a0 * exp_r(-pw);
+        } else {
+            R se, ce;
+            sincospi_r(NT::from_island(island_scale(eta, W.inv_tau)), &se, &ce);
+            gam = W.a0 * se * se;
+        }
         // carrier + chirp phase, FP64, reduced to revolutions
         const I de = island_shift(eta, W.half_tau);
         const I theta = island_shift(island_scale(X, -W.k), -W.th0) + W.b_half * de * de;

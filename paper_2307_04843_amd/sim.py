@@ -19,7 +19,7 @@ class Simulation:
 
     def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
                  precision="f32", tile=(0, 0, 0), sort_every=0, species=(), proxy=False,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, pulse_on_grid=False):
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP path needs a GPU")
         apt.load()
@@ -38,6 +38,7 @@ class Simulation:
         g.t0 = float(t0)
         g.dt = float(dt)
         g.sort_every = int(sort_every)
+        g.options = apt.AP_GRID_PULSE_ON_GRID if pulse_on_grid else 0
         self.grid_desc = g
         self.sp_desc = []
         for sp in species:

@@ -112,11 +112,11 @@ def periodic_diff(a, b, n):
     return d - n * np.round(d / n)
 
 
-def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0):
+def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0, pulse_on_grid=False):
     from paper_2307_04843_amd.sim import Simulation
     sim = Simulation(case["dim"], n=case["n"], dx=case["dx"], x_min=case["x_min"], t0=case["t0"],
                      dt=case["dt"], precision=precision, tile=tile, sort_every=sort_every,
-                     species=case["species"])
+                     species=case["species"], pulse_on_grid=pulse_on_grid)
     E, B, _ = sim.field_views()
     import torch
     for k in range(3):
@@ -124,6 +124,8 @@ def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0):
         B[k].copy_(torch.as_tensor(case["fields"][3 + k]).to(B[k].dtype))
     if case["pulse"] is not None:
         pp = {k: v for k, v in case["pulse"].items() if k not in ("type", "dt")}
+        if pulse_on_grid:
+            pp["sampling"] = "grid"
         sim.set_pulse(case["pulse"]["type"], **pp)
     else:
         sim.set_pulse("none")

@@ -60,6 +60,7 @@ def test_query_layout_sizes():
     (lambda g: setattr(g, "dt", 0.2), "stability"),
     (lambda g: setattr(g, "dt", float("nan")), "dt"),
     (lambda g: (g.n.__setitem__(0, 256), g.tile.__setitem__(0, 100)), "tile"),
+    (lambda g: setattr(g, "options", 0x8), "option"),
 ])
 def test_query_layout_rejects_bad_grid(mut, msg):
     g = _grid()
@@ -106,3 +107,25 @@ def test_calls_on_null_context():
     assert lib.ap_destroy(None) == apt.AP_OK
     d = apt.ap_diag()
     assert lib.ap_gather_diag(None, 1, C.byref(d)) == apt.AP_E_ARG
+
+
+def test_pulse_on_grid_option_reserves_workspace():
+    g = _grid()
+    base = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
+    g.options = apt.AP_GRID_PULSE_ON_GRID
+    more = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
+    assert more >= base + 6 * 64 * 32 * 4
+    g0 = _grid(dim=0)
+    g0.dt = 0.01
+    g0.options = apt.AP_GRID_PULSE_ON_GRID
+    with pytest.raises(apt.APTError):
+        apt.ap_query_layout(g0, [_sp()])
+
+
+def test_pulse_params_struct_matches_header():
+    """ap_pulse_params in the binding has the header's layout: 16 doubles, 10
+    int32 (d_f ... reserved), then fwhm."""
+    assert C.sizeof(apt.ap_pulse_params) == 16 * 8 + 10 * 4 + 8
+    assert apt.ap_pulse_params.fwhm.offset == 16 * 8 + 10 * 4
+    p = apt.pulse_params(envelope="sgauss", sampling="grid", fwhm=30.0)
+    assert (p.envelope, p.sampling, p.fwhm) == (apt.AP_ENV_SGAUSS, apt.AP_SAMPLE_GRID, 30.0)

@@ -133,3 +133,21 @@ def test_adjoint_flying_focus_beta_and_chirp(beta_f):
     # step must be small against 0.05 for the extrapolation to converge
     go = _oracle_grad(names, vals, u_final, 1e-2, kind="ff", pulse=pulse, beam=b, rel_h=2e-4)
     assert np.allclose(g, go, rtol=1e-6, atol=1e-9 * np.abs(go).max()), (g, go)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_super_gaussian_envelope_fp64():
+    """The collision replica with a super-Gaussian envelope (order 2, intensity
+    FWHM 12 lambda/c): the FP64 adjoint gradient wrt (a0, w0, x_f) matches the
+    oracle's reference gradient."""
+    pulse = dict(_pulse(), tau=30.0, envelope="sgauss", sg_order=2, fwhm=12.0)
+    names = ["a0", "w0", "x_f"]
+    vals = [20.0, 2.0, 0.0]
+    run = _run("f64", names, pulse=pulse)
+    try:
+        L, g, u_final, _ = _obs_grad(run, vals)
+    finally:
+        run.close()
+    go = _oracle_grad(names, vals, u_final, 0.0, pulse=pulse)
+    assert np.all(np.abs(go) > 1e-6), go
+    assert np.allclose(g, go, rtol=1e-6, atol=1e-9 * np.abs(go).max()), (g, go)

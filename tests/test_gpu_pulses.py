@@ -27,6 +27,10 @@ PULSES = {
     "np4": dict(type="gauss_np", np_order=4, dispersion=units.DISP_VACUUM, w0=2.0),
     "np4_tight": dict(type="gauss_np", np_order=4, dispersion=units.DISP_VACUUM, w0=0.8, pol=1),
     "np2": dict(type="gauss_np", np_order=2, dispersion=units.DISP_VACUUM, w0=2.0),
+    "sg4_plane": dict(type="plane", envelope="sgauss", sg_order=4, fwhm=20.0),
+    "sg2_lg10": dict(type="lg", lg_l=1, lg_p=0, pol=1, envelope="sgauss", sg_order=2, fwhm=15.0),
+    "sg1_ff": dict(type="ff", beta_f=-1.0, x0_ff=100.0, t0_ff=80.0, d_f=3, envelope="sgauss", sg_order=1,
+                   fwhm=12.0),
 }
 
 
