@@ -49,3 +49,55 @@ def gradient(prm, name, X0, u0, q_over_m, t0, dt, n_steps, wu, wp, rel_h=1e-3):
     d1 = (Lof(base + h) - Lof(base - h)) / (2 * h)
     d2 = (Lof(base + h / 2) - Lof(base - h / 2)) / h
     return (4 * d2 - d1) / 3, d1, d2
+
+
+# ----------------------------------------------------------------------------
+# Gridded runs, frozen-grid reading: E2, B2 are the fields a nominal
+# self-consistent run produced at the start of each step, taken as an external
+# field; the gradient is that of the particles pushed through them.
+# ----------------------------------------------------------------------------
+
+def record_gridded_run(grid, species, prm, n_steps, pulse_on_grid=False):
+    """Nominal run of the full loop (pic.step) from the given state.  Returns
+    [(E2, B2, t)] at the start of every step; grid and species end at the
+    final state."""
+    P = pulses.Pulse(prm)
+    recs = []
+    for _ in range(n_steps):
+        recs.append(([e.copy() for e in grid.E], [b.copy() for b in grid.B], grid.t))
+        pic.step(grid, species, P, pulse_on_grid=pulse_on_grid)
+    return recs
+
+
+def frozen_run(prm, grid, recs, sp0, pulse_on_grid=False):
+    """One species pushed through the recorded fields (no deposit, no field
+    update).  ``grid`` supplies the geometry; returns the final (pos, u)."""
+    P = pulses.Pulse(prm)
+    sp = pic.Species(sp0.q, sp0.m, sp0.pos, sp0.u, sp0.w)
+    saved = grid.E, grid.B, grid.t
+    try:
+        for E, B, t in recs:
+            grid.E, grid.B, grid.t = E, B, t
+            u_half = pic.push_species(grid, sp, P, pulse_on_grid=pulse_on_grid)
+            new = pic.move(grid, sp.pos, u_half)
+            sp.u = u_half
+            sp.pos = pic.wrap(grid, new)
+    finally:
+        grid.E, grid.B, grid.t = saved
+    return sp.pos, sp.u
+
+
+def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-5, pulse_on_grid=False):
+    """dL/d(prm[name]), L = sum wu . u_final, through the recorded fields:
+    Richardson-extrapolated central differences as in ``gradient``."""
+    base = float(prm[name])
+    h = rel_h * max(abs(base), 1.0)
+
+    def Lof(v):
+        q = dict(prm)
+        q[name] = v
+        return float(np.sum(wu * frozen_run(q, grid, recs, sp0, pulse_on_grid)[1]))
+
+    d1 = (Lof(base + h) - Lof(base - h)) / (2 * h)
+    d2 = (Lof(base + h / 2) - Lof(base - h / 2)) / h
+    return (4 * d2 - d1) / 3, d1, d2

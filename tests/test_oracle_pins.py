@@ -803,3 +803,27 @@ def test_grid_sampled_pulse_converges_to_particle_evaluation():
     g.E, g.B = E1g, B1g
     Eg, _ = pic.gather(g, pos)
     assert np.abs(Eg - Ep).max() / P.a0 > 10 * errs[0]
+
+
+def test_frozen_grid_reference_replays_and_converges():
+    """Frozen-grid reading of the adjoint of gridded runs: replaying one species
+    through the recorded E2, B2 at the nominal parameters reproduces the
+    self-consistent run exactly, and the difference quotient settles as h
+    shrinks.  Steps of 1e-3 a0 and more are not usable: a particle that crosses
+    the periodic boundary jumps to another lab position of the (non-periodic)
+    pulse, so L has jumps; the reference therefore works at h = 1e-5 a0."""
+    from oracle import grad as ograd
+    from tests import cases
+    case = cases.make_case(n=(24, 1, 16), seed=4, u_scale=10.0, ppc=2)
+    g, sps, _ = cases.oracle_state(case)
+    prm = dict(case["pulse"])
+    sp0 = pic.Species(sps[0].q, sps[0].m, sps[0].pos, sps[0].u, sps[0].w)
+    recs = ograd.record_gridded_run(g, sps, prm, 12)
+    pos, u = ograd.frozen_run(prm, g, recs, sp0)
+    assert np.array_equal(u, sps[0].u)
+    assert np.array_equal(pos, sps[0].pos)
+    wu = np.zeros_like(u)
+    wu[2] = u[2] / u.shape[1]
+    est = [ograd.frozen_gradient(prm, "a0", g, recs, sp0, wu, rel_h=h)[0] for h in (1e-4, 1e-5)]
+    assert est[1] != 0.0
+    assert abs(est[0] - est[1]) <= 1e-8 * abs(est[1]), est
