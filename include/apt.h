@@ -70,7 +70,7 @@ typedef int32_t ap_status;
 /* ap_step flags */
 #define AP_STEP_CONTINUITY  0x1u  /* track max |(rho1-rho0)/dt + div J| (FP64)  */
 #define AP_STEP_NO_YEE      0x2u  /* keep E2, B2 frozen (J is still deposited)  */
-#define AP_STEP_RECORD      0x4u  /* gridless: keep adjoint checkpoints        */
+#define AP_STEP_RECORD      0x4u  /* keep adjoint checkpoints (ap_backward)    */
 
 /* ap_grid_desc options */
 #define AP_GRID_PULSE_ON_GRID 0x1  /* allow AP_SAMPLE_GRID (reserves workspace)  */
@@ -276,16 +276,24 @@ ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
  * Asynchronous on the context stream. */
 ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, void *E, void *B);
 
-/* Adjoint checkpoint storage (gridless runs).  dev: caller-owned device
- * buffer of `bytes`; segment K: steps between stored states.  Recording n
- * steps needs ceil(n/K) + K slots of ap_layout.ckpt_slot_bytes (outer
- * checkpoints plus the replay buffer of one segment).  AP_E_UNSUPPORTED for
- * gridded runs. */
+/* Adjoint checkpoint storage.  dev: caller-owned device buffer of `bytes`;
+ * segment K: steps between stored states.  Recording n steps needs
+ * ap_checkpoint_bytes(ctx, n, K) bytes (AP_E_ARG at the recording ap_step
+ * call if the buffer is smaller).  Gridless runs: ceil(n/K) + K slots of
+ * ap_layout.ckpt_slot_bytes (outer checkpoints plus the replay buffer of one
+ * segment).  Gridded runs: the whole state (every species, E2, B2) every K
+ * steps, a copy of the final state, K replay slots (E2, B2 and one
+ * species), and the FP64 adjoint state of the largest species.  The buffer
+ * must stay allocated and untouched until the last ap_backward call. */
 ap_status ap_set_checkpoints(ap_ctx *ctx, void *dev, size_t bytes, int32_t segment);
 
+/* Checkpoint bytes for recording n_steps >= 1 steps with segment K >= 1
+ * (written to *bytes, host). */
+ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segment, size_t *bytes);
+
 /* Gradient of a particle observable with respect to pulse parameters over
- * the steps of the last ap_step call made with AP_STEP_RECORD (gridless
- * runs; the state must not have been advanced since).  The observable is
+ * the steps of the last ap_step call made with AP_STEP_RECORD (the state
+ * must not have been advanced, nor the pulse changed, since).  The observable is
  *     L = sum_p dL_du[p] . u_p(final) + dL_dproxy[p] * proxy_p(final),
  * i.e. the caller passes the cotangents of the final momenta (device,
  * component-major, 3 arrays of n reals of the context precision) and,
@@ -294,7 +302,19 @@ ap_status ap_set_checkpoints(ap_ctx *ctx, void *dev, size_t bytes, int32_t segme
  * hand-written adjoint of the analytic field, Boris push, move and proxy.
  * param_ids (host): AP_PARAM_* values, each at most once; the focal position
  * is x_f (x0_ff for the flying focus).  Writes n_params FP64 derivatives to
- * dL_dparams (host) in lambda units.  Synchronises the stream. */
+ * dL_dparams (host) in lambda units.  Synchronises the stream.
+ *
+ * Gridded runs (dim 2, 3) take the frozen-grid reading: the E2, B2 that each
+ * push gathered are a recorded external field, so the gradient follows the
+ * parameters through the particles' own analytic fields and through the
+ * position dependence of the gather, not through the plasma's response on
+ * the grid.  There dL_du is indexed by particle id (the species' ids must be
+ * a permutation of 0..n-1, else AP_E_ARG), dL_dproxy must be NULL, and the
+ * pulse must be evaluated per particle (AP_SAMPLE_PARTICLES, else
+ * AP_E_UNSUPPORTED).  The reverse sweep replays each segment with the full
+ * loop (push, deposit, field update), then restores the final state; the
+ * next step re-sorts.  A replayed step reproduces the recorded one up to the
+ * summation order of the current deposit. */
 #define AP_PARAM_A0      0
 #define AP_PARAM_W0      1
 #define AP_PARAM_XF      2

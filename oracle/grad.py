@@ -87,9 +87,15 @@ def frozen_run(prm, grid, recs, sp0, pulse_on_grid=False):
     return sp.pos, sp.u
 
 
-def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-5, pulse_on_grid=False):
+def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-6, pulse_on_grid=False):
     """dL/d(prm[name]), L = sum wu . u_final, through the recorded fields:
-    Richardson-extrapolated central differences as in ``gradient``."""
+    Richardson-extrapolated central differences as in ``gradient``.
+
+    L has jumps: a particle that crosses the periodic boundary one step
+    earlier or later samples the (non-periodic) pulse a box length away.  On
+    small boxes they lie within 1e-4 relative of the nominal parameters, so
+    the step is kept small; at 1e-6 the round-off of L stays near 1e-10
+    relative."""
     base = float(prm[name])
     h = rel_h * max(abs(base), 1.0)
 

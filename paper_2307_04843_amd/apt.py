@@ -30,7 +30,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
-            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
+            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
             "ap_last_error")
 
 
@@ -117,6 +117,7 @@ def load():
         "ap_eval_pulse": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p,
                                       C.c_void_p]),
         "ap_set_checkpoints": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
+        "ap_checkpoint_bytes": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, P(C.c_size_t)]),
         "ap_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(C.c_int32),
                                     C.c_int32, P(C.c_double)]),
         "ap_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -190,6 +191,12 @@ def ap_eval_pulse(ctx, n, xyz_ptr, t, e_ptr, b_ptr):
 def ap_set_checkpoints(ctx, dev_ptr, nbytes, segment):
     _check(load().ap_set_checkpoints(ctx, C.c_void_p(dev_ptr), int(nbytes), int(segment)),
            "ap_set_checkpoints")
+
+
+def ap_checkpoint_bytes(ctx, n_steps, segment):
+    out = C.c_size_t(0)
+    _check(load().ap_checkpoint_bytes(ctx, int(n_steps), int(segment), C.byref(out)), "ap_checkpoint_bytes")
+    return int(out.value)
 
 
 def ap_backward(ctx, species, dl_du_ptr, dl_dproxy_ptr, param_ids):

@@ -1,4 +1,4 @@
-"""Differentiable gridless runs: torch.autograd.Function over ap_step/ap_backward.
+"""Differentiable runs: torch.autograd.Function over ap_step/ap_backward.
 
 ``GridlessRun`` owns a gridless Simulation, its initial particle state and a
 checkpoint buffer.  ``APTRun.apply(params, run)`` resets the particles to the
@@ -7,6 +7,11 @@ order of ``run.param_names``, lambda units), advances ``run.n_steps`` steps with
 checkpoint recording and returns the final momenta u (3, N) and the emission
 proxies (N,).  Its backward calls the library's hand-written adjoint
 (ap_backward) and returns dL/dparams.
+
+``GriddedRun`` does the same for a gridded run (dim 2 or 3, every species,
+full loop) and one species' final momenta, ordered by particle id, in the
+frozen-grid reading: the gradient treats the E2, B2 each push gathered as a
+recorded external field.  Its proxy output is identically zero.
 """
 import math
 
@@ -87,8 +92,83 @@ class GridlessRun:
         self.sim.close()
 
 
+class GriddedRun:
+    """species: Simulation species list (plasma states with cell, off, u, w).
+    fields: optional initial E2, B2 (6 arrays shaped (nz, ny, nx)), else zero.
+    The gradient is of species ``species_index``'s final momenta."""
+
+    def __init__(self, dim, n, dx, x_min, species, pulse_kind, pulse_params, param_names, n_steps, t0=0.0,
+                 dt=0.0, precision="f32", fields=None, species_index=0, segment=None, tile=(0, 0, 0),
+                 sort_every=0):
+        self.sim = Simulation(dim, n=n, dx=dx, x_min=x_min, t0=t0, dt=dt, precision=precision, tile=tile,
+                              sort_every=sort_every, species=species)
+        self.kind = pulse_kind
+        self.base = dict(pulse_params)
+        self.param_names = list(param_names)
+        for nm in self.param_names:
+            if nm not in PARAM_IDS:
+                raise ValueError("unknown parameter %r" % nm)
+        self.n_steps = int(n_steps)
+        self.sp = int(species_index)
+        self.segment = int(segment or max(1, int(math.sqrt(self.n_steps))))
+        nbytes = apt.ap_checkpoint_bytes(self.sim.ctx, self.n_steps, self.segment)
+        self.ckpt = torch.empty(nbytes, dtype=torch.uint8, device=self.sim.device)
+        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        self._fields = None if fields is None else [torch.as_tensor(np.asarray(f)) for f in fields]
+        self._init = []
+        for a in self.sim.arrays:
+            self._init.append({"cell": a["cell"].clone(), "off": [t.clone() if t is not None else None
+                                                                   for t in a["off"]],
+                               "u": [t.clone() for t in a["u"]], "w": a["w"].clone(), "id": a["id"].clone()})
+
+    def _reset(self):
+        for a, ini in zip(self.sim.arrays, self._init):
+            a["cell"].copy_(ini["cell"])
+            a["w"].copy_(ini["w"])
+            a["id"].copy_(ini["id"])
+            for k in range(3):
+                if a["off"][k] is not None:
+                    a["off"][k].copy_(ini["off"][k])
+                a["u"][k].copy_(ini["u"][k])
+        # a fresh context rewinds the clock and zeroes the grid
+        apt.ap_destroy(self.sim.ctx)
+        self.sim.ctx = apt.ap_init(self.sim.grid_desc, self.sim.sp_desc, self.sim.buffers,
+                                   self.sim.stream.cuda_stream)
+        if self._fields is not None:
+            E, B, _ = self.sim.field_views()
+            for k in range(3):
+                E[k].copy_(self._fields[k].to(E[k].dtype))
+                B[k].copy_(self._fields[3 + k].to(B[k].dtype))
+        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+
+    def forward(self, values):
+        self._reset()
+        prm = dict(self.base)
+        for nm, v in zip(self.param_names, values):
+            prm["x0_ff" if (nm == "x_f" and self.kind == "ff") else nm] = float(v)
+        self.sim.set_pulse(self.kind, **prm)
+        self.sim.step(self.n_steps, flags=apt.AP_STEP_RECORD)
+        a = self.sim.arrays[self.sp]
+        u = torch.stack(a["u"])
+        out = torch.empty_like(u)
+        out[:, a["id"].long()] = u
+        return out, torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
+
+    def backward(self, grad_u, grad_proxy=None):
+        n = self.sim.sp_desc[self.sp].n
+        gu = grad_u if grad_u is not None else torch.zeros((3, n), device=self.sim.device)
+        gu = gu.to(device=self.sim.device, dtype=self.sim.dtype).contiguous()
+        ids = [PARAM_IDS[nm] for nm in self.param_names]
+        torch.cuda.synchronize(self.sim.device)
+        return apt.ap_backward(self.sim.ctx, self.sp, gu.data_ptr(), None, ids)
+
+    def close(self):
+        self.sim.close()
+
+
 class APTRun(torch.autograd.Function):
-    """params (float64, CPU) -> (u_final (3, N), proxy (N,)) through the HIP path."""
+    """params (float64, CPU) -> (u_final (3, N), proxy (N,)) through the HIP path
+    (``run``: a GridlessRun or a GriddedRun)."""
 
     @staticmethod
     def forward(ctx, params, run):

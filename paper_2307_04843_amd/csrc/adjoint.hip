@@ -1,6 +1,10 @@
 // Adjoint of the gridless step (analytic field + Boris push + move + emission
 // proxy) for gradients of particle observables with respect to the pulse
-// parameters.
+// parameters.  The same reverse step serves gridded runs in the frozen-grid
+// reading: the E2, B2 each push gathered are a recorded external field, so
+// E = E1(x; theta) + gather(E2)(x) and dE/dx gains the gradient of the
+// quadratic-shape gather; the adjoint state is indexed by particle id, since
+// re-sorts permute the particle arrays between steps.
 //
 // Forward step n (per particle):  E, B = field(x^n, t^n; theta)
 //     u^{n+1/2} = Boris(u^{n-1/2}, E, B),   x^{n+1} = x^n + dt u^{n+1/2}/gamma,
@@ -92,17 +96,107 @@ AP_D R proxy_g(const R u0[3], const R u1[3], const R E[3], const R B[3], R dt) {
     return gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
 }
 
-template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
+// Quadratic B-spline weights of nodes -1, 0, +1 at offset d and their d-derivatives.
+template <typename T> AP_D void tsc3_d(T d, T w[3], T dw[3]) {
+    const T lo = T(0.5) - d, hi = T(0.5) + d;
+    w[0] = T(0.5) * lo * lo;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * hi * hi;
+    dw[0] = -lo;
+    dw[1] = T(-2) * d;
+    dw[2] = hi;
+}
+
+// Three-node stencil of one axis for a component on nodes or half a cell up.
+template <typename T> struct AxisStencil {
+    int idx[3];
+    T w[3], dw[3];
+};
+template <typename T> AP_D void axis_stencil(int i, T off, bool half, int n, AxisStencil<T> &st) {
+    int c;
+    T d;
+    if (half) {
+        c = i;
+        d = off - T(0.5);
+    } else {
+        const int up = off >= T(0.5) ? 1 : 0;
+        c = i + up;
+        d = off - T(up);
+    }
+    tsc3_d(d, st.w, st.dw);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int v = c - 1 + m;
+        st.idx[m] = v < 0 ? v + n : (v >= n ? v - n : v);
+    }
+}
+
+// Gathered value and its gradient in cell units (x, y, z; y only in 3-D).
+template <typename T, int GD>
+AP_D void gather_grad(const T *F, const AxisStencil<T> &sx, const AxisStencil<T> &sy, const AxisStencil<T> &sz,
+                      int nx, int ny, T &v, T (&gr)[3]) {
+    v = T(0);
+    gr[0] = gr[1] = gr[2] = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        T pv = T(0), px = T(0), py = T(0);
+#pragma unroll
+        for (int q = 0; q < (GD == 3 ? 3 : 1); ++q) {
+            const T *row = F + ((size_t)sz.idx[b] * ny + (GD == 3 ? sy.idx[q] : 0)) * nx;
+            T r = T(0), rd = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const T f = row[sx.idx[m]];
+                r += sx.w[m] * f;
+                rd += sx.dw[m] * f;
+            }
+            const T wy = GD == 3 ? sy.w[q] : T(1);
+            pv += wy * r;
+            px += wy * rd;
+            if (GD == 3) py += sy.dw[q] * r;
+        }
+        v += sz.w[b] * pv;
+        gr[0] += sz.w[b] * px;
+        gr[1] += sz.w[b] * py;
+        gr[2] += sz.dw[b] * pv;
+    }
+}
+
+template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (p < a.n) {
+    int lid = p;          // index of the particle's adjoint state
+    bool ok = p < a.n;
+    int ic[3] = {0, 0, 0};
+    T ov[3] = {T(0), T(0), T(0)};
+    if (GD > 0 && ok) {
+        // grid state: linear cell + offsets on the active axes; particles the
+        // push skipped (invalid cell or offset) keep their adjoint state
+        const int cell = a.G.cell[p];
+        lid = a.G.id[p];
+        ov[0] = a.off[0][p];
+        ov[2] = a.off[2][p];
+        if (GD == 3) ov[1] = a.off[1][p];
+        const int nx = a.G.n[0], nxy = a.G.n[0] * a.G.n[1];
+        ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
+             ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)lid < (unsigned)a.n;
+        const int k = (int)a.G.fnxy.div((unsigned)cell);
+        const int r = cell - k * nxy;
+        const int j = (int)a.G.fnx.div((unsigned)r);
+        ic[0] = r - j * nx;
+        ic[1] = j;
+        ic[2] = k;
+    }
+    if (ok) {
         using DN = Dual<T, NT>;
         using IN = DualD<T, NT>;
         IN Xd[3];
         T u0v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
+            if (GD == 0) Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
+            else if (GD == 2 && c == 1) Xd[c] = IN(a.G.q_slice);
+            else Xd[c] = IN(a.x_min[c] + ((double)ic[c] + (double)ov[c]) * a.dx[c]);
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
         }
@@ -125,6 +219,33 @@ template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_bod
                 B8[c].d[k] *= ascale;
             }
         }
+        if (GD > 0) {
+            // recorded E2, B2: E_c sits half a cell up on axis c, B_c on
+            // nodes along c and half a cell up on the other axes
+            AxisStencil<T> sn[3], sh[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                if (GD == 2 && ax == 1) continue;
+                axis_stencil(ic[ax], ov[ax], false, a.G.n[ax], sn[ax]);
+                axis_stencil(ic[ax], ov[ax], true, a.G.n[ax], sh[ax]);
+            }
+            const T idx_[3] = {T(1.0 / a.dx[0]), T(1.0 / a.dx[1]), T(1.0 / a.dx[2])};
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int c = f % 3;
+                const bool isE = f < 3;
+                const AxisStencil<T> &sx = (c == 0) == isE ? sh[0] : sn[0];
+                const AxisStencil<T> &sy = (c == 1) == isE ? sh[1] : sn[1];
+                const AxisStencil<T> &sz = (c == 2) == isE ? sh[2] : sn[2];
+                T v, gr[3];
+                gather_grad<T, GD>(a.G.F[f], sx, sy, sz, a.G.n[0], a.G.n[1], v, gr);
+                DN &F8 = isE ? E8[c] : B8[c];
+                F8.v += v;
+                F8.d[0] += gr[0] * idx_[0];
+                if (GD == 3) F8.d[1] += gr[1] * idx_[1];
+                F8.d[2] += gr[2] * idx_[2];
+            }
+        }
 
         // Boris Jacobian: tangents over (u0, E, B)
         using D9 = Dual<T, 9>;
@@ -140,8 +261,8 @@ template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_bod
         double lx[3], lu1[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            lx[c] = a.lam[c][p];
-            lu1[c] = a.lam[3 + c][p];
+            lx[c] = a.lam[c][lid];
+            lu1[c] = a.lam[3 + c][lid];
         }
         // move: x^{n+1} = x^n + dt u1/gamma1
         {
@@ -153,7 +274,7 @@ template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_bod
             for (int c = 0; c < 3; ++c) lu1[c] += a.dt * (lx[c] - vv[c] * vl) / g1;
         }
         double lu0[3] = {0.0, 0.0, 0.0}, lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
-        if (a.lam_proxy) {
+        if (GD == 0 && a.lam_proxy) {
             const double lp = (double)a.lam_proxy[p];
             if (lp != 0.0) {
                 using D12 = Dual<T, 12>;
@@ -191,8 +312,9 @@ template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_bod
             double acc = lx[c];
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[c] + lB[k] * (double)B8[k].d[c];
-            a.lam[c][p] = acc;
-            a.lam[3 + c][p] = lu0[c];
+            // an (x, z) grid does not move y: its adjoint stays zero
+            if (!(GD == 2 && c == 1)) a.lam[c][lid] = acc;
+            a.lam[3 + c][lid] = lu0[c];
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[0] += lE[k] * (double)Fu[k] + lB[k] * (double)Fu[3 + k];
@@ -225,22 +347,31 @@ template <typename T, int PT, int NT> AP_D __forceinline__ void adjoint_step_bod
 // FP32: two waves per SIMD (the compiler keeps the dual-number working set
 // in 256 registers with a few spills), measured faster than one wave without
 // spills.  FP64 needs twice the registers and runs best at one wave.
-template <int PT, int NT>
+template <int PT, int NT, int GD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step(AdjointArgs<float> a) {
-    adjoint_step_body<float, PT, NT>(a);
+    adjoint_step_body<float, PT, NT, GD>(a);
 }
-template <int PT, int NT> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
-    adjoint_step_body<double, PT, NT>(a);
+template <int PT, int NT, int GD> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
+    adjoint_step_body<double, PT, NT, GD>(a);
+}
+
+template <typename T, int PT, int GD> static void launch_adj_gd(const AdjointArgs<T> &a, int np, hipStream_t s) {
+    const dim3 grid((a.n + 255) / 256), block(256);
+    // parameter tangents padded to 2 or 4 (unused slots are -1 and stay zero)
+    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD>), grid, block, 0, s, a);
 }
 
 template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     int np = 0;
     for (int k = 0; k < 4; ++k) np += a.slot[k] >= 0 ? 1 : 0;
-    const dim3 grid((a.n + 255) / 256), block(256);
-    // parameter tangents padded to 2 or 4 (unused slots are -1 and stay zero)
-    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<PT, 5>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_adjoint_step<PT, 7>), grid, block, 0, s, a);
+    switch (a.dim) {
+    case 0: launch_adj_gd<T, PT, 0>(a, np, s); break;
+    case 2: launch_adj_gd<T, PT, 2>(a, np, s); break;
+    case 3: launch_adj_gd<T, PT, 3>(a, np, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -277,6 +408,20 @@ template <typename T> hipError_t launch_adjoint_init(double *const lam[6], const
     return hipGetLastError();
 }
 template hipError_t launch_adjoint_init<float>(double *const[6], const float *, int, hipStream_t);
+
+__global__ void k_check_ids(const int32_t *id, int n, int32_t *seen, unsigned long long *bad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int v = id[p];
+    bool b = v < 0 || v >= n;
+    if (!b) b = atomicAdd(&seen[v], 1) != 0;
+    if (b) atomicAdd(bad, 1ull);
+}
+hipError_t launch_check_ids(const int32_t *id, int n, int32_t *seen, unsigned long long *bad, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_ids, dim3((n + 255) / 256), dim3(256), 0, s, id, n, seen, bad);
+    return hipGetLastError();
+}
 template hipError_t launch_adjoint_init<double>(double *const[6], const double *, int, hipStream_t);
 
 }  // namespace apt

@@ -205,6 +205,67 @@ WorkLayout make_layout(const RunShape &s) {
     return L;
 }
 
+// Checkpoint buffer of a gridded run (frozen-grid adjoint):
+//   [adjoint state: 6 x n_max FP64][gradient partials]
+//   [final-state slot][ceil(n/K) checkpoint slots][K replay slots]
+// A checkpoint slot holds every species (cell, id, offsets, u, w) and E2, B2;
+// a replay slot holds E2, B2 and the species being differentiated (no w).
+struct GridCkpt {
+    size_t lam[6] = {}, partial = 0, fixed = 0;
+    int blocks = 0;
+    size_t outer = 0, inner = 0;
+    size_t sp_off[kMaxSpecies] = {};   // species blocks inside a checkpoint slot
+    size_t fields = 0;                 // E2, B2 inside a checkpoint slot (at 0 in a replay slot)
+    size_t inner_sp = 0;               // species block inside a replay slot
+};
+
+size_t sp_block_bytes(const RunShape &s, int i, bool with_w) {
+    const size_t N = (size_t)s.np[i];
+    const size_t nact = s.dim == 3 ? 3 : 2;
+    return align_up(N * 8 + N * s.real * (nact + 3 + (with_w ? 1 : 0)), 256);
+}
+
+GridCkpt grid_ckpt(const RunShape &s) {
+    GridCkpt G;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = align_up(off, 256);
+        off = o + bytes;
+        return o;
+    };
+    int64_t nmax = 0;
+    for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
+    for (int c = 0; c < 6; ++c) G.lam[c] = take((size_t)nmax * 8);
+    G.blocks = (int)((nmax + 255) / 256);
+    if (G.blocks < 1) G.blocks = 1;
+    G.partial = take((size_t)G.blocks * 5 * 8);
+    G.fixed = align_up(off, 256);
+    const size_t fbytes = align_up((size_t)6 * (size_t)s.ncell * s.real, 256);
+    size_t so = 0, mx = 0;
+    for (int i = 0; i < s.nsp; ++i) {
+        G.sp_off[i] = so;
+        so += sp_block_bytes(s, i, true);
+        const size_t b = sp_block_bytes(s, i, false);
+        mx = b > mx ? b : mx;
+    }
+    G.fields = so;
+    G.outer = so + fbytes;
+    G.inner_sp = fbytes;
+    G.inner = fbytes + mx;
+    return G;
+}
+
+// Bytes of checkpoint storage for recording n steps with segment K.
+size_t ckpt_need(const RunShape &s, const WorkLayout &L, int64_t n, int64_t K) {
+    const int64_t nseg = n > 0 ? (n + K - 1) / K : 1;
+    if (s.dim == 0) {
+        const int64_t slots = nseg + K > 2 ? nseg + K : 2;
+        return (size_t)slots * L.slot_bytes;
+    }
+    const GridCkpt G = grid_ckpt(s);
+    return G.fixed + (size_t)(1 + nseg) * G.outer + (size_t)K * G.inner;
+}
+
 PulseDev default_pulse() {
     PulseDev P;
     std::memset(&P, 0, sizeof(P));
@@ -234,6 +295,7 @@ struct ap_ctx {
     int pulse_type = -1;
     int64_t step = 0;
     bool sorted_once = false;
+    bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
     bool timing = false;
     std::vector<TimedPair> pending;
     std::vector<hipEvent_t> pool;
@@ -294,6 +356,8 @@ template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
 template <typename T>
 ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
                         double *out);
+template <typename T>
+ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const int32_t *ids, int np_, double *out);
 
 double laguerre_host(int n, int a, double x) {
     double l0 = 1.0, l1 = 1.0 + a - x;
@@ -524,6 +588,7 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
     }
     c->P = P;
     c->pulse_type = type;
+    c->rec_n = 0;   // a recording holds for the pulse it was made with
     return AP_OK;
 }
 
@@ -534,14 +599,11 @@ ap_status ap_step(ap_ctx *c, int64_t n_steps, uint32_t flags) {
     if (flags & ~(AP_STEP_CONTINUITY | AP_STEP_NO_YEE | AP_STEP_RECORD)) return fail(AP_E_ARG, "unknown step flag");
     if (c->s.dim == 0 && (flags & (AP_STEP_CONTINUITY | AP_STEP_NO_YEE)))
         return fail(AP_E_ARG, "grid flags on a gridless run");
-    if (c->s.dim > 0 && (flags & AP_STEP_RECORD)) return fail(AP_E_UNSUPPORTED, "adjoint recording needs dim 0");
     if (flags & AP_STEP_RECORD) {
         if (!c->ckpt) return fail(AP_E_STATE, "ap_set_checkpoints must be called before recording");
-        const int64_t nseg = (n_steps + c->segment - 1) / c->segment;
-        const int64_t need = nseg + c->segment;
-        if ((size_t)need * c->L.slot_bytes > c->ckpt_bytes)
-            return fail(AP_E_ARG, "checkpoint buffer too small: need " + std::to_string(need) + " slots of " +
-                                      std::to_string(c->L.slot_bytes) + " bytes");
+        const size_t need = ckpt_need(c->s, c->L, n_steps, c->segment);
+        if (need > c->ckpt_bytes)
+            return fail(AP_E_ARG, "checkpoint buffer too small: need " + std::to_string(need) + " bytes");
         c->rec_n = n_steps;
         c->rec_step0 = c->step;
     } else {
@@ -681,9 +743,9 @@ ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void 
 
 ap_status ap_set_checkpoints(ap_ctx *c, void *dev, size_t bytes, int32_t segment) {
     if (!c) return fail(AP_E_ARG, "context is NULL");
-    if (c->s.dim != 0) return fail(AP_E_UNSUPPORTED, "checkpoints are for gridless runs");
     if (segment < 1) return fail(AP_E_ARG, "segment must be >= 1");
-    if (!dev || bytes < 2 * c->L.slot_bytes) return fail(AP_E_ARG, "checkpoint buffer NULL or smaller than two slots");
+    if (!dev || bytes < ckpt_need(c->s, c->L, 1, 1))
+        return fail(AP_E_ARG, "checkpoint buffer NULL or smaller than one recorded step needs");
     c->ckpt = static_cast<unsigned char *>(dev);
     c->ckpt_bytes = bytes;
     c->segment = segment;
@@ -691,10 +753,19 @@ ap_status ap_set_checkpoints(ap_ctx *c, void *dev, size_t bytes, int32_t segment
     return AP_OK;
 }
 
+ap_status ap_checkpoint_bytes(const ap_ctx *c, int64_t n_steps, int32_t segment, size_t *bytes) {
+    if (!c || !bytes) return fail(AP_E_ARG, "NULL argument");
+    if (n_steps < 1 || segment < 1) return fail(AP_E_ARG, "n_steps and segment must be >= 1");
+    *bytes = ckpt_need(c->s, c->L, n_steps, segment);
+    return AP_OK;
+}
+
 ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void *dl_dproxy,
                       const int32_t *param_ids, int32_t n_params, double *out) {
     if (!c) return fail(AP_E_ARG, "context is NULL");
-    if (c->s.dim != 0) return fail(AP_E_UNSUPPORTED, "the adjoint covers gridless runs");
+    if (c->s.dim > 0 && dl_dproxy) return fail(AP_E_ARG, "gridded runs carry no emission proxy");
+    if (c->s.dim > 0 && c->P.sampling == AP_SAMPLE_GRID)
+        return fail(AP_E_UNSUPPORTED, "the adjoint of gridded runs needs the pulse evaluated per particle");
     if (c->rec_n <= 0) return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
     if (c->step != c->rec_step0 + c->rec_n) return fail(AP_E_STATE, "the state moved past the recorded window");
     if (species < 0 || species >= c->s.nsp) return fail(AP_E_ARG, "species index out of range");
@@ -707,6 +778,9 @@ ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void 
     }
     if (c->P.type == PT_NONE) return fail(AP_E_STATE, "no pulse set");
     try {
+        if (c->s.dim > 0)
+            return c->s.prec == AP_F64 ? backward_grid<double>(c, species, dl_du, param_ids, n_params, out)
+                                       : backward_grid<float>(c, species, dl_du, param_ids, n_params, out);
         return c->s.prec == AP_F64 ? backward_impl<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
                                    : backward_impl<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
     } catch (...) {
@@ -896,6 +970,7 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
             a.dt = s.dt;
             a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
             a.P = c->P;
+            a.dim = 0;
             HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
         }
     }
@@ -910,6 +985,198 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     return AP_OK;
 }
 
+// ---- gridded checkpoints
+
+template <typename T> struct SpBlock {
+    int32_t *cell, *id;
+    T *off[3], *u[3], *w;
+};
+
+// Species i's arrays inside a slot block that starts at base.
+template <typename T> SpBlock<T> sp_block(unsigned char *base, const RunShape &s, int i, bool with_w) {
+    SpBlock<T> b{};
+    const size_t N = (size_t)s.np[i];
+    b.cell = reinterpret_cast<int32_t *>(base);
+    b.id = b.cell + N;
+    T *r = reinterpret_cast<T *>(base + 8 * N);
+    for (int a = 0; a < 3; ++a) {
+        b.off[a] = axis_active(s.dim, a) ? r : nullptr;
+        if (b.off[a]) r += N;
+    }
+    for (int a = 0; a < 3; ++a) {
+        b.u[a] = r;
+        r += N;
+    }
+    b.w = with_w ? r : nullptr;
+    return b;
+}
+
+template <typename T> SpBlock<T> live_block(ap_ctx *c, int i) {
+    const ap_particles &p = c->buf.sp[i];
+    SpBlock<T> b{};
+    b.cell = p.cell;
+    b.id = p.id;
+    for (int a = 0; a < 3; ++a) {
+        b.off[a] = axis_active(c->s.dim, a) ? static_cast<T *>(p.off[a]) : nullptr;
+        b.u[a] = static_cast<T *>(p.u[a]);
+    }
+    b.w = static_cast<T *>(p.w);
+    return b;
+}
+
+template <typename T> ap_status copy_block(ap_ctx *c, const SpBlock<T> &dst, const SpBlock<T> &src, size_t N, bool w) {
+    if (N == 0) return AP_OK;
+    HIPCHK(hipMemcpyAsync(dst.cell, src.cell, N * 4, hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    HIPCHK(hipMemcpyAsync(dst.id, src.id, N * 4, hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    for (int a = 0; a < 3; ++a) {
+        if (dst.off[a]) HIPCHK(hipMemcpyAsync(dst.off[a], src.off[a], N * sizeof(T), hipMemcpyDeviceToDevice, c->stream),
+                               "checkpoint copy");
+        HIPCHK(hipMemcpyAsync(dst.u[a], src.u[a], N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    }
+    if (w) HIPCHK(hipMemcpyAsync(dst.w, src.w, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    return AP_OK;
+}
+
+unsigned char *ckpt_final(ap_ctx *c) { return c->ckpt + grid_ckpt(c->s).fixed; }
+unsigned char *ckpt_outer(ap_ctx *c, int64_t k) {
+    const GridCkpt G = grid_ckpt(c->s);
+    return c->ckpt + G.fixed + (size_t)(1 + k) * G.outer;
+}
+unsigned char *ckpt_inner(ap_ctx *c, int64_t j) {
+    const GridCkpt G = grid_ckpt(c->s);
+    const int64_t nseg = (c->rec_n + c->segment - 1) / c->segment;
+    return c->ckpt + G.fixed + (size_t)(1 + nseg) * G.outer + (size_t)j * G.inner;
+}
+
+// Whole state (every species, E2, B2) to a checkpoint slot or back.
+template <typename T> ap_status save_ckpt(ap_ctx *c, unsigned char *slot, bool restore = false) {
+    const RunShape &s = c->s;
+    const GridCkpt G = grid_ckpt(s);
+    for (int i = 0; i < s.nsp; ++i) {
+        const SpBlock<T> live = live_block<T>(c, i), blk = sp_block<T>(slot + G.sp_off[i], s, i, true);
+        const ap_status st = restore ? copy_block<T>(c, live, blk, (size_t)s.np[i], true)
+                                     : copy_block<T>(c, blk, live, (size_t)s.np[i], true);
+        if (st != AP_OK) return st;
+    }
+    unsigned char *grid = static_cast<unsigned char *>(c->buf.grid);
+    const size_t fb = (size_t)6 * (size_t)s.ncell * sizeof(T);
+    HIPCHK(hipMemcpyAsync(restore ? grid : slot + G.fields, restore ? slot + G.fields : grid, fb,
+                          hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    return AP_OK;
+}
+
+// Replay slot: E2, B2 and species sp at the start of a step.
+template <typename T> ap_status save_replay(ap_ctx *c, unsigned char *slot, int sp) {
+    const RunShape &s = c->s;
+    const GridCkpt G = grid_ckpt(s);
+    HIPCHK(hipMemcpyAsync(slot, c->buf.grid, (size_t)6 * (size_t)s.ncell * sizeof(T), hipMemcpyDeviceToDevice,
+                          c->stream), "replay copy");
+    return copy_block<T>(c, sp_block<T>(slot + G.inner_sp, s, sp, false), live_block<T>(c, sp), (size_t)s.np[sp],
+                         false);
+}
+
+// Reverse sweep of a recorded gridded run (frozen-grid reading).  Each
+// segment is restored from its checkpoint and replayed with the full loop
+// (push, deposit, field update), storing E2, B2 and the species at the start
+// of every step; the adjoint steps then run backwards over those slots.  The
+// state after the last recorded step is put back at the end.
+template <typename T>
+ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const int32_t *ids, int np_, double *out) {
+    const RunShape &s = c->s;
+    const GridCkpt G = grid_ckpt(s);
+    const int n = (int)s.np[sp];
+    unsigned long long *cnt = c->counters();
+    unsigned long long saved[kCounters];
+    {
+        // the adjoint state is indexed by particle id: ids must be 0..n-1, each once
+        int32_t *seen = c->wp<int32_t>(c->L.rank[sp]);
+        HIPCHK(launch_fill_zero<int32_t>(seen, (size_t)n, c->stream), "backward");
+        HIPCHK(hipMemcpyAsync(saved, cnt, sizeof(saved), hipMemcpyDeviceToHost, c->stream), "backward");
+        HIPCHK(launch_fill_zero<unsigned long long>(cnt + 5, 1, c->stream), "backward");
+        HIPCHK(launch_check_ids(c->buf.sp[sp].id, n, seen, cnt + 5, c->stream), "backward");
+        unsigned long long bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, cnt + 5, sizeof(bad), hipMemcpyDeviceToHost, c->stream), "backward");
+        HIPCHK(hipStreamSynchronize(c->stream), "backward");
+        if (bad != 0) return fail(AP_E_ARG, "particle ids of the species are not a permutation of 0..n-1");
+    }
+    double *lam[6];
+    for (int k = 0; k < 6; ++k) lam[k] = reinterpret_cast<double *>(c->ckpt + G.lam[k]);
+    double *partial = reinterpret_cast<double *>(c->ckpt + G.partial);
+    int32_t slot[4] = {-1, -1, -1, -1};
+    int nslot = 0;
+    for (int k = 0; k < np_; ++k)
+        if (ids[k] != AP_PARAM_A0) slot[nslot++] = ids[k];
+    ap_status st = save_ckpt<T>(c, ckpt_final(c));
+    if (st != AP_OK) return st;
+    HIPCHK(launch_fill_zero<double>(partial, (size_t)G.blocks * 5, c->stream), "backward");
+    HIPCHK(launch_adjoint_init<T>(lam, static_cast<const T *>(dl_du), n, c->stream), "backward");
+    const int64_t K = c->segment;
+    const int64_t nseg = (c->rec_n + K - 1) / K;
+    const FastDiv fnx((uint32_t)s.n[0]), fnxy((uint32_t)(s.n[0] * s.n[1]));
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * K;
+        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+        st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
+        if (st != AP_OK) return st;
+        c->step = c->rec_step0 + s0;
+        c->need_sort = true;
+        for (int64_t j = 0; j < len; ++j) {
+            st = save_replay<T>(c, ckpt_inner(c, j), sp);
+            if (st != AP_OK) return st;
+            if (j + 1 < len) {
+                st = step_gridded<T>(c, 0);
+                if (st != AP_OK) return st;
+                c->step++;
+            }
+        }
+        for (int64_t j = len - 1; j >= 0; --j) {
+            unsigned char *slot_j = ckpt_inner(c, j);
+            const SpBlock<T> b = sp_block<T>(slot_j + G.inner_sp, s, sp, false);
+            const T *F = reinterpret_cast<const T *>(slot_j);
+            AdjointArgs<T> a{};
+            for (int k = 0; k < 3; ++k) {
+                a.off[k] = b.off[k];
+                a.u[k] = b.u[k];
+                a.dx[k] = s.dx[k];
+                a.x_min[k] = s.x_min[k];
+                a.G.n[k] = s.n[k];
+            }
+            for (int k = 0; k < 6; ++k) {
+                a.lam[k] = lam[k];
+                a.G.F[k] = F + (size_t)k * (size_t)s.ncell;
+            }
+            a.G.cell = b.cell;
+            a.G.id = b.id;
+            a.G.fnx = fnx;
+            a.G.fnxy = fnxy;
+            a.G.q_slice = c->P.q_slice;
+            a.dim = s.dim;
+            a.lam_proxy = nullptr;
+            a.partial = partial;
+            for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
+            a.n = n;
+            a.q_over_m = s.q[sp] / s.m[sp];
+            a.dt = s.dt;
+            a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
+            a.P = c->P;
+            HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+        }
+    }
+    st = save_ckpt<T>(c, ckpt_final(c), true);
+    if (st != AP_OK) return st;
+    c->step = c->rec_step0 + c->rec_n;
+    c->need_sort = true;
+    HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
+    double *sums = c->wp<double>(c->L.sums);
+    HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
+    double host[5];
+    HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, c->stream), "backward");
+    HIPCHK(hipStreamSynchronize(c->stream), "backward");
+    const double unit[5] = {1.0, kTwoPi, kTwoPi, 1.0, 1.0};
+    for (int k = 0; k < np_; ++k) out[k] = host[ids[k]] * unit[ids[k]];
+    return AP_OK;
+}
+
 template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     const RunShape &s = c->s;
     const WorkLayout &L = c->L;
@@ -919,7 +1186,14 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     for (int k = 0; k < 9; ++k) F[k] = grid + (size_t)k * nc;
     const FastDiv fnx((uint32_t)s.n[0]);
     const FastDiv fnxy((uint32_t)(s.n[0] * s.n[1]));
-    const bool do_sort = !c->sorted_once || (c->step % s.sort_every) == 0;
+    if (flags & AP_STEP_RECORD) {
+        const int64_t k = c->step - c->rec_step0;
+        if (k % c->segment == 0) {
+            const ap_status st = save_ckpt<T>(c, ckpt_outer(c, k / c->segment));
+            if (st != AP_OK) return st;
+        }
+    }
+    const bool do_sort = !c->sorted_once || c->need_sort || (c->step % s.sort_every) == 0;
     bool from_alt = false;
     if (do_sort) {
         Timer tm(c, 2);
@@ -982,6 +1256,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             HIPCHK(launch_scatter<T>(sc, c->stream), "tile scatter");
         }
         c->sorted_once = true;
+        c->need_sort = false;
         from_alt = true;
     }
     PushArgs<T> a{};

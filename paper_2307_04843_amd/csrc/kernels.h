@@ -92,8 +92,19 @@ template <typename T> struct SampleArgs {
 };
 template <typename T> hipError_t launch_sample_pulse(int pulse, const SampleArgs<T> &a, hipStream_t s);
 
+// Gridded runs, frozen-grid reading: the E2, B2 the push gathered at step n
+// are a recorded external field; their position dependence enters dL/dx.
+template <typename T> struct AdjointGrid {
+    const int32_t *cell;         // linear cell of each particle (x fastest)
+    const int32_t *id;           // particle id: index of its adjoint state
+    const T *F[6];               // E2x E2y E2z B2x B2y B2z at the start of step n
+    int32_t n[3];
+    FastDiv fnx, fnxy;
+    double q_slice;              // lab y of an (x, z) grid
+};
+
 template <typename T> struct AdjointArgs {
-    const int32_t *icell[3];     // state x^n, u^{n-1/2} of the step being reversed
+    const int32_t *icell[3];     // state x^n, u^{n-1/2} of the step being reversed (gridless)
     const T *off[3];
     const T *u[3];
     double *lam[6];              // dL/dx (lab, internal units), dL/du (in: step n+1, out: step n)
@@ -107,8 +118,13 @@ template <typename T> struct AdjointArgs {
     double dt;
     double t;
     PulseDev P;
+    int32_t dim;                 // 0 (gridless), 2 or 3 (grid: G is used, icell is not)
+    AdjointGrid<T> G;
 };
 template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s);
+// Checks that id[0..n) is a permutation of 0..n-1: seen[] (n ints, zeroed by
+// the caller) counts each id; *bad counts ids out of range or repeated.
+hipError_t launch_check_ids(const int32_t *id, int n, int32_t *seen, unsigned long long *bad, hipStream_t s);
 template <typename T> hipError_t launch_adjoint_init(double *const lam[6], const T *dl_du, int n, hipStream_t s);
 
 struct YeeArgsBase {
