@@ -297,6 +297,28 @@ def sample_pulse(grid, pulse):
     return out[0], out[1]
 
 
+def sample_current(grid, pulse, t):
+    """Analytic current J1 (Sec. IV) on the grid at time t, each component at
+    the node of the matching E component (where the Yee update uses J).
+    Returns J1[3] shaped like grid.J."""
+    nx, ny, nz = grid.n
+    ii = np.arange(nx)[None, None, :]
+    jj = np.arange(ny)[None, :, None]
+    kk = np.arange(nz)[:, None, None]
+    shape = (nz, ny, nx)
+    out = []
+    for c in range(3):
+        stag = E_STAGGER[c]
+        X = np.broadcast_to(grid.x_min[0] + (ii + stag[0]) * grid.dx[0], shape)
+        Z = np.broadcast_to(grid.x_min[2] + (kk + stag[2]) * grid.dx[2], shape)
+        if grid.dim == 3:
+            Y = np.broadcast_to(grid.x_min[1] + (jj + stag[1]) * grid.dx[1], shape)
+        else:
+            Y = np.full(shape, pulse.q_slice)
+        out.append(np.array(_pulses.analytic_current(pulse, t, X, Y, Z)[c], dtype=float))
+    return out
+
+
 def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False):
     """Field evaluation and Boris push of one species at time grid.t.
 
@@ -346,8 +368,9 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
 
     For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n (E1, B1 at the
     particle, or sampled on the grid with ``pulse_on_grid``); Boris push;
-    move; deposit J^{n+1/2}.  Then the Yee update of E2, B2 with J.  J holds
-    the step's current afterwards.  Returns per-species (pos_unwrapped_new,)
+    move; deposit J^{n+1/2}.  With an analytic current (Sec. IV) J1 at
+    t^{n+1/2} is subtracted: E2, B2 are driven by J - J1.  Then the Yee update
+    of E2, B2.  J holds the Yee source (J, or J - J1) afterwards.  Returns per-species (pos_unwrapped_new,)
     for diagnostics.
     """
     for c in range(3):
@@ -363,6 +386,10 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
         sp.u = u_half
         moved.append(new)
         sp.pos = wrap(grid, new)
+    if pulse is not None and pulse.current:
+        J1 = sample_current(grid, pulse, grid.t + 0.5 * grid.dt)
+        for c in range(3):
+            grid.J[c] -= J1[c]
     if field_update:
         yee_step(grid)
     grid.t += grid.dt

@@ -29,13 +29,18 @@ converted here with the factor 2*pi of ``units``:
     pol         0 (p = y) or 1 (p = z)
     beta_f, x0_ff, t0_ff   flying focus: focal velocity / c, focus at x0_ff
                            at time t0_ff (Sec. III.C)
-    dispersion  units.DISP_PAPER2 | DISP_EXACT | DISP_VACUUM
+    dispersion  units.DISP_PAPER2 | DISP_EXACT | DISP_VACUUM | DISP_PLASMA
     dx_prop, dt cell size along x and time step, lambda units (fix the
                 numerical v_phi, v_g, B0/E0 of Eqs. (10)-(14))
     np_order    0 or 4: order in eps = w0/x_R of the nonparaxial Gaussian
     envelope    'sin2' (default) or 'sgauss': super-Gaussian of order
                 sg_order whose intensity full width at half maximum is
                 fwhm (lambda/c), centred in the support [0, tau]
+    wp2, zeta   DISP_PLASMA (Sec. IV): omega_p^2/omega^2 of the density the
+                analytic current J1 represents, and the factor zeta of the
+                plasma's discrete response (default 1)
+    fd          DISP_PLASMA: keep the lowest-order finite-duration
+                corrections of B1 and J1 (default True)
 """
 import math
 
@@ -78,7 +83,13 @@ class Pulse:
         dt = float(prm.get("dt", 0.0)) * L
         if mode != units.DISP_VACUUM and dt <= 0.0:
             raise ValueError("grid dispersion modes need dx_prop and dt")
-        self.v_phi, self.v_g, self.b_over_e, self.k = units.dispersion(mode, dx, dt)
+        self.wp2 = float(prm.get("wp2", 0.0))
+        self.zeta = float(prm.get("zeta", 1.0))
+        self.fd = bool(prm.get("fd", True))
+        self.current = mode == units.DISP_PLASMA
+        if self.current and self.kind == "gauss_np":
+            raise ValueError("the nonparaxial Gaussian is a vacuum field")
+        self.v_phi, self.v_g, self.b_over_e, self.k = units.dispersion(mode, dx, dt, self.wp2, self.zeta)
         self.omega = 1.0
         # Rayleigh range x_R = k w0^2 / 2 with k = omega / v_phi (Eq. (23)).
         self.x_r = self.k * self.w0 ** 2 / 2.0
@@ -159,6 +170,45 @@ def _envelope(P, t, X):
     gam = np.where(inside, P.a0 * prof, 0.0)
     phi = 0.5 * P.b * (eta - P.tau / 2.0) ** 2
     return gam, phi
+
+
+def _envelope_rates(P, t, X):
+    """Time derivatives at fixed x of the envelope and the chirp phase, as
+    Gamma'/Gamma, Gamma''/Gamma, Phi', Phi'' (zero outside the support)."""
+    eta = (t - P.t_ref) - (X - P.x_ref) / P.v_g + P.tau / 2.0
+    inside = (eta > 0.0) & (eta < P.tau)
+    if P.envelope == "sgauss":
+        g = P.sg_order
+        x = (eta - P.tau / 2.0) / P.tau_g
+        g1 = -2.0 * g * x ** (2 * g - 1) / P.tau_g
+        g2 = g1 * g1 - 2.0 * g * (2 * g - 1) * x ** (2 * g - 2) / P.tau_g ** 2
+    else:
+        a = math.pi / P.tau
+        sn = np.where(inside, np.sin(a * eta), 1.0)
+        cs = np.cos(a * eta)
+        g1 = 2.0 * a * cs / sn
+        g2 = 2.0 * a * a * (cs * cs - sn * sn) / (sn * sn)
+    p1 = P.b * (eta - P.tau / 2.0)
+    p2 = np.full_like(eta, P.b)
+    zero = np.zeros_like(eta)
+    return (np.where(inside, g1, zero), np.where(inside, g2, zero), np.where(inside, p1, zero),
+            np.where(inside, p2, zero))
+
+
+def fd_factor(P, t, X, delta):
+    """Lowest-order finite-duration correction (Sec. IV) as a complex factor
+    A exp(i psi) on Gamma exp(i(Theta + Phi)), for a field whose spectrum is
+    the envelope's times 1 + delta sum_n (i/omega)^n d^n/dt^n:
+        A   = 1 - delta Gamma''/(w^2 Gamma) + (delta Gamma'/(w Gamma))^2 / 2
+                - delta Phi'/w + delta Phi'^2 / w^2,
+        psi = delta Gamma'/(w Gamma) - delta Phi''/w^2 - 2 delta (Gamma'/Gamma) Phi'/w^2.
+    delta = 1 - v_phi/v_g gives B1 (the B_z form of Sec. IV), delta = 1 the
+    integral of E1 that J1 carries."""
+    g1, g2, p1, p2 = _envelope_rates(P, t, X)
+    w = P.omega
+    amp = 1.0 - delta * g2 / w ** 2 + 0.5 * (delta * g1 / w) ** 2 - delta * p1 / w + delta * p1 ** 2 / w ** 2
+    psi = delta * g1 / w - delta * p2 / w ** 2 - 2.0 * delta * g1 * p1 / w ** 2
+    return amp * np.exp(1j * psi)
 
 
 def _carrier(P, t, X):
@@ -265,10 +315,39 @@ def analytic_fields(P, t, X, Y, Z):
     carrier = gam * np.exp(1j * (theta + phi))
     e_p = np.real(F * carrier)
     e_x = np.real(-1j * (P.v_phi / P.omega) * Fp * carrier)
-    b_q = P.b_over_e * e_p
-    b_x = np.real(-1j * (1.0 / P.omega) * P.b_over_e * Fq * carrier)
+    # B1: Eq. (17) in vacuum; with an analytic current the finite-duration
+    # correction of Sec. IV (delta = 1 - v_phi/v_g), unless switched off
+    cb = carrier * fd_factor(P, t, X, 1.0 - P.v_phi / P.v_g) if (P.current and P.fd) else carrier
+    b_q = P.b_over_e * np.real(F * cb)
+    b_x = np.real(-1j * (1.0 / P.omega) * P.b_over_e * Fq * cb)
     zero = np.zeros_like(e_p)
     return to_lab(P, (e_x, e_p, zero), (b_x, zero, b_q))
+
+
+def analytic_current(P, t, X, Y, Z):
+    """Analytic current J1 of Sec. IV at lab points and time t (internal units,
+    dJ1/dt = omega_p^2 zeta E1 with 4 pi absorbed): each component of E1 =
+    Re{G Gamma e^{i(Theta + Phi)}} gives
+        J1 = (wp2 zeta / omega) Re{-i G Gamma e^{i(Theta + Phi)} C},
+    C the finite-duration factor with delta = 1 (1 with ``fd`` off).  The
+    transverse factor G is held fixed over the integral (slowly varying).
+    Returns J (3,) + X.shape, lab components; zero without DISP_PLASMA."""
+    X = np.asarray(X, dtype=float)
+    Y = np.broadcast_to(np.asarray(Y, dtype=float), X.shape)
+    Z = np.broadcast_to(np.asarray(Z, dtype=float), X.shape)
+    if not P.current:
+        return np.zeros((3,) + X.shape)
+    gam, phi = _envelope(P, t, X)
+    theta = _carrier(P, t, X)
+    F, Fp, Fq = _profile(P, t, X, Y, Z)
+    carrier = gam * np.exp(1j * (theta + phi))
+    if P.fd:
+        carrier = carrier * fd_factor(P, t, X, 1.0)
+    pre = P.wp2 * P.zeta / P.omega
+    j_p = pre * np.real(-1j * F * carrier)
+    j_x = pre * np.real(-1j * (-1j * (P.v_phi / P.omega) * Fp) * carrier)
+    zero = np.zeros_like(j_p)
+    return to_lab(P, (j_x, j_p, zero), (zero, zero, zero))[0]
 
 
 def to_lab(P, e_xpq, b_xpq):

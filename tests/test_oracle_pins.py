@@ -827,3 +827,125 @@ def test_frozen_grid_reference_replays_and_converges():
     est = [ograd.frozen_gradient(prm, "a0", g, recs, sp0, wu, rel_h=h)[0] for h in (1e-5, 1e-6, 1e-7)]
     assert est[1] != 0.0
     assert max(abs(est[0] - est[1]), abs(est[2] - est[1])) <= 1e-8 * abs(est[1]), est
+
+
+# ---------------------------------------------------------------------------
+# Analytic current J1 (Sec. IV)
+# ---------------------------------------------------------------------------
+
+def test_plasma_dispersion_constants():
+    """Sec. IV: with no plasma the constants are the exact Yee ones; v_g
+    equals d omega/d k of the dispersion relation solved numerically for
+    omega(k); towards the continuum v_phi -> 1/sqrt(1 - wp2 zeta),
+    v_g, B0/E0 -> sqrt(1 - wp2 zeta), at second order."""
+    from scipy.optimize import brentq
+    dx = 0.05 * L
+    dt = 0.95 / math.sqrt(2) * dx
+    a = units.dispersion(units.DISP_EXACT, dx, dt)
+    b = units.dispersion(units.DISP_PLASMA, dx, dt, 0.0, 1.0)
+    assert max(abs(x - y) for x, y in zip(a, b)) <= 1e-15
+    wp2, zeta = 0.05, 0.9
+    vphi, vg, boe, k = units.dispersion(units.DISP_PLASMA, dx, dt, wp2, zeta)
+
+    def omega_of(kk):
+        def f(w):
+            h = w * dt / 2
+            return math.sin(h) ** 2 - (wp2 / w ** 2) * h * math.sin(h) * zeta - (dt / dx) ** 2 * math.sin(kk * dx / 2) ** 2
+        return brentq(f, 0.3, 2.0, xtol=1e-15)
+    assert abs(omega_of(k) - 1.0) < 1e-12
+    h = 1e-5
+    assert abs((omega_of(k + h) - omega_of(k - h)) / (2 * h) - vg) < 1e-8
+    # Faraday's law at integer times: B0/E0 = (dt/dx) sin(k dx/2) cos(w dt/2) / sin(w dt/2)
+    assert abs(boe - (dt / dx) * math.sin(k * dx / 2) * math.cos(dt / 2) / math.sin(dt / 2)) < 1e-14
+    errs = []
+    for dxl in (0.02, 0.01):
+        d = dxl * L
+        v = units.dispersion(units.DISP_PLASMA, d, 0.95 / math.sqrt(2) * d, wp2, zeta)
+        r = math.sqrt(1 - wp2 * zeta)
+        errs.append(np.array([v[0] - 1 / r, v[1] - r, v[2] - r]))
+    assert np.all(np.abs(errs[0]) / np.abs(errs[1]) > 3.9) and np.all(np.abs(errs[1]) < 3e-4)
+
+
+def _plasma_yee_residual(dxl, fwhm, fd=True, use_j=True, delta_sign=1.0, sg_order=1, window=None, wp2=0.05):
+    """Max one-step residual of the sampled PLANE pulse with J1 under the split
+    Yee step (as in the vacuum pin; E is advanced with -J1 at the half step),
+    over the pulse (or +-window lambda about its peak)."""
+    tau = 6.0 * fwhm
+    half_window = window if window is not None else tau / 2 + 1.0
+    dt_l = 0.95 / math.sqrt(2) * dxl
+    P = pulses.Pulse(dict(type="plane", a0=1.0, tau=tau, t_ref=0.0, x_ref=0.0, pol=0,
+                          dispersion=units.DISP_PLASMA, dx_prop=dxl, dt=dt_l, wp2=wp2, zeta=1.0, fd=fd,
+                          envelope="sgauss", sg_order=sg_order, fwhm=fwhm))
+    if delta_sign != 1.0:    # planted error: the finite-duration terms with the opposite sign
+        P.v_g = P.v_phi / (1.0 + (1.0 - P.v_phi / P.v_g))
+    dx, dt = dxl * L, dt_l * L
+    t = (tau + 3.0) * L
+    n0 = int((P.v_g * t - half_window * L) / dx)
+    x = (n0 + np.arange(int(2 * half_window / dxl))) * dx
+    xh = x + dx / 2
+    z = np.zeros_like(x)
+    E0 = pulses.analytic_fields(P, t, x, z, z)[0][1]
+    B0 = pulses.analytic_fields(P, t, xh, z, z)[1][2]
+    E1 = pulses.analytic_fields(P, t + dt, x, z, z)[0][1]
+    B1 = pulses.analytic_fields(P, t + dt, xh, z, z)[1][2]
+    J = pulses.analytic_current(P, t + dt / 2, x, z, z)[1] if use_j else 0.0
+    Bh = B0 - 0.5 * dt * (np.roll(E0, -1) - E0) / dx
+    En = E0 - dt * (Bh - np.roll(Bh, 1)) / dx - dt * J
+    Bn = Bh - 0.5 * dt * (np.roll(En, -1) - En) / dx
+    return max(np.abs((En - E1) / dt)[3:-3].max(), np.abs((Bn - B1) / dt)[3:-3].max())
+
+
+def test_analytic_current_satisfies_discrete_yee():
+    """Sec. IV: E1, B1 with the plasma constants and J1 at the half step form a
+    solution of the Yee equations with source J1.  Near the peak of a long
+    pulse the residual is ~1e-5 of the one without J1.  Over a Gaussian pulse
+    the finite-duration corrections of B1 and J1 leave only the numerical
+    residual, which falls at second order in dx; without them, or with
+    their sign flipped, the physical-dispersion residual does not converge."""
+    with_j = _plasma_yee_residual(0.05, 70.0, window=2.0)
+    without = _plasma_yee_residual(0.05, 70.0, window=2.0, use_j=False)
+    assert with_j < 1e-4 * without, (with_j, without)
+    fd = [_plasma_yee_residual(d, 10.0) for d in (0.05, 0.025)]
+    nofd = [_plasma_yee_residual(d, 10.0, fd=False) for d in (0.05, 0.025)]
+    flip = [_plasma_yee_residual(d, 10.0, delta_sign=-1.0) for d in (0.05, 0.025)]
+    assert fd[0] / fd[1] > 3.5, fd
+    assert nofd[1] > 0.7 * nofd[0] and fd[1] < nofd[1] / 8.0, (fd, nofd)
+    assert flip[1] > 0.7 * flip[0] and fd[1] < flip[1] / 8.0, (fd, flip)
+    # the residual of a longer pulse is proportionally smaller (first order in bandwidth)
+    assert 1.8 < _plasma_yee_residual(0.05, 5.0) / fd[0] < 2.2
+
+
+def test_analytic_current_linear_response():
+    """Sec. IV, Fig. 9: a cold electron plasma driven by a weak pulse carries
+    the current J1 that the analytic term removes, so the internally advanced
+    field E2 stays at the level of the mismatch between the particles'
+    discrete response and J1.  160 x 4 cells at lambda/20, 8 electrons per
+    cell at n = 0.05 n_c, immobile ions, a0 = 0.01 Gaussian (FWHM 4 lambda/c)
+    sampled on the grid; after 300 steps max|E2| is > 8x below the run
+    whose pulse carries no analytic current, and the finite-duration
+    corrections lower it further."""
+    from paper_2307_04843_amd import inputs
+
+    def run(mode, fd=True):
+        dxl, wp2 = 0.05, 0.05
+        n = (160, 1, 4)
+        dtl = 0.95 / math.sqrt(2) * dxl
+        st = inputs.plasma(2, n, (dxl,) * 3, (0.0, 0.0, 0.0), 8, inputs.density_uniform(wp2), 1e-6, 1.0, 5)
+        g = pic.Grid(2, n, (dxl * L,) * 3, dtl * L, (0.0, 0.0, 0.0), t0=0.0)
+        cell = st["cell"].astype(np.int64)
+        pos = np.zeros((3, cell.size))
+        pos[0] = cell % n[0] + st["off"][0]
+        pos[2] = cell // n[0] + st["off"][2]
+        sp = pic.Species(-1.0, 1.0, pos, st["u"].astype(float), st["w"].astype(float))
+        P = pulses.Pulse(dict(type="plane", a0=0.01, tau=24.0, t_ref=14.0, x_ref=0.0, pol=1, dispersion=mode,
+                              dx_prop=dxl, dt=dtl, wp2=wp2 if mode == units.DISP_PLASMA else 0.0, fd=fd,
+                              envelope="sgauss", sg_order=1, fwhm=4.0))
+        for _ in range(300):
+            pic.step(g, [sp], P, pulse_on_grid=True)
+        return max(np.abs(e).max() for e in g.E)
+
+    e_j1 = run(units.DISP_PLASMA)
+    e_nofd = run(units.DISP_PLASMA, fd=False)
+    e_vac = run(units.DISP_EXACT)
+    assert e_j1 < e_vac / 8.0, (e_j1, e_vac)
+    assert e_j1 < e_nofd, (e_j1, e_nofd)
