@@ -21,6 +21,16 @@ recording plus ap_backward for d<p_perp^2>/d(a0, w0, x_f), in FP32 and FP64.
 Adjoint pushes/s = N x steps / wall time of the backward pass (replay
 included).
 
+Third leg (``three_d``): 3-D PIC, 512 x 256 x 256 cells at lambda/16, c dt/dx
+= 0.95/sqrt(3), 8 electrons per cell (268M) in 0.001 n_c with immobile ions,
+T = 1 eV, flying-focus pulse (beta_f = -1, a0 = 2, w0 = 4 lambda, tau = 150
+lambda/c, 5% chirp), FP32: steps 1800 ... 1900 of the 4000-step run (the box
+inside the pulse, the moving focus crossing it), then the frozen-grid adjoint
+of d<p_perp^2>/d(beta_f, chirp) over a 32-step window (segments of 8).
+
+Fourth leg (``small``): the 128 x 64 Gaussian run (32768 electrons, 200 steps)
+in FP64 and FP32; launch-bound, reported for completeness.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
 """
 import argparse
@@ -66,15 +76,148 @@ def workload_pulse(dt):
                 q_slice=0.0, d_f=3, lg_l=1, lg_p=0, pol=1, dispersion=0, dx_prop=dx, dt_prop=dt)
 
 
-def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0):
+N3 = (512, 256, 256)
+DX3 = 0.0625
+PPC3 = 8
+T0_STEP3 = 1800
+
+
+def workload3d_inputs(seed=4):
+    from paper_2307_04843_amd import inputs
+    e = inputs.plasma(3, N3, (DX3,) * 3, (0.0, -8.0, -8.0), PPC3, inputs.density_uniform(0.001), 1.0, 1.0,
+                      seed, stream=0)
+    return [dict(q=-1.0, m=1.0, state=e)]
+
+
+def workload3d_pulse(dt):
+    """Flying focus for the 512 x 256 x 256 box: front at x = 0 at t = 0, focus
+    moving backwards at c through the box centre at step 1850."""
+    c2 = (dt / DX3) ** 2
+    kdx = 2 * math.pi * DX3
+    vg = 1.0 - (1.0 - c2) * kdx ** 2 / 8.0
+    xc = N3[0] * DX3 / 2
+    tau = 150.0
+    return dict(a0=2.0, tau=tau, x_ref=xc, t_ref=tau / 2 + xc / vg, x_f=0.0, w0=4.0, y_c=0.0, z_c=0.0, d_f=3,
+                pol=0, beta_f=-1.0, x0_ff=xc, t0_ff=(T0_STEP3 + 50) * dt, chirp=0.05, dispersion=0,
+                dx_prop=DX3, dt_prop=dt)
+
+
+def three_d_leg(args):
+    import torch
+    from paper_2307_04843_amd import apt
+    from paper_2307_04843_amd.autograd import APTRun, GriddedRun
+    from paper_2307_04843_amd.sim import Simulation
+    log("3-D: generating inputs")
+    species = workload3d_inputs()
+    n = int(species[0]["state"]["u"].shape[1])
+    dt = 0.95 / math.sqrt(3) * DX3
+    t0 = T0_STEP3 * dt
+    pp = workload3d_pulse(dt)
+    geo = dict(n=N3, dx=(DX3,) * 3, x_min=(0.0, -8.0, -8.0), t0=t0, dt=dt)
+    out = {"workload": "3-D PIC 512x256x256 cells lambda/16, 8 e per cell (268M), 0.001 n_c, immobile "
+                       "ions, flying focus beta_f=-1 a0=2 w0=4 tau=150 chirp 5%%, steps %d..%d of the "
+                       "4000-step run" % (T0_STEP3, T0_STEP3 + args.steps3d), "particles": n,
+           "steps": args.steps3d, "warmup": 5}
+    sim = Simulation(3, precision="f32", species=species, **geo)
+    try:
+        sim.set_pulse("ff", **pp)
+        sim.step(5)
+        torch.cuda.synchronize()
+        apt.ap_timing_enable(sim.ctx, True)
+        apt.ap_timing_read(sim.ctx, reset=True)
+        w0 = time.perf_counter()
+        sim.step(args.steps3d)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        tm = apt.ap_timing_read(sim.ctx, reset=True)
+        d, _ = sim.diag(allow_numeric=True)
+        ms_push = tm.ms_push / max(1, tm.n_push)
+        # particle bytes (read 32, write 28) + grid share (stage 24, flush 12 per cell)
+        bl = n * 60 + sim.ncell * 36
+        out.update({"pushes_per_s": n * args.steps3d / wall, "ms_per_step": wall * 1e3 / args.steps3d,
+                    "push_ms_per_launch": ms_push, "hbm_gbs_algorithmic": bl / (ms_push * 1e-3) / 1e9,
+                    "hbm_frac": bl / (ms_push * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "yee_ms": tm.ms_yee / max(1, tm.n_yee), "sort_ms_per_step": tm.ms_sort / args.steps3d,
+                    "n_nonfinite": d.n_nonfinite, "n_fast": d.n_fast,
+                    "offtile_fraction": d.n_offtile / float(n * (args.steps3d + 5))})
+        log("3-D: %.3e pushes/s, push %.3f ms/launch" % (out["pushes_per_s"], ms_push))
+    finally:
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    if args.adj3d_steps > 0:
+        names = ["beta_f", "chirp"]
+        K = 8
+        log("3-D adjoint: %d-step window, segments of %d" % (args.adj3d_steps, K))
+        run = GriddedRun(3, N3, (DX3,) * 3, (0.0, -8.0, -8.0), species, "ff", pp, names, args.adj3d_steps,
+                         t0=t0, dt=dt, precision="f32", segment=K)
+        try:
+            p = torch.tensor([pp["beta_f"], pp["chirp"]], dtype=torch.float64, requires_grad=True)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            u, _ = APTRun.apply(p, run)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            obs = (u[1].double() ** 2 + u[2].double() ** 2).sum() / n
+            obs.backward()
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            out["adjoint"] = {"window_steps": args.adj3d_steps, "segment": K, "params": names,
+                              "grad": p.grad.tolist(), "observable": float(obs.detach()),
+                              "forward_pushes_per_s": n * args.adj3d_steps / (b - a),
+                              "adjoint_pushes_per_s": n * args.adj3d_steps / (c - b),
+                              "checkpoint_gb": run.ckpt.numel() / 1e9,
+                              "note": "frozen-grid reading; backward = segment replays with the full "
+                                      "loop + reverse steps"}
+            log("3-D adjoint: %.3e pushes/s" % out["adjoint"]["adjoint_pushes_per_s"])
+        finally:
+            run.close()
+            del run
+            torch.cuda.empty_cache()
+    del species
+    return out
+
+
+def small_leg():
+    """The 128 x 64 Gaussian run: 32768 electrons, 200 steps, FP64 and FP32."""
+    import torch
+    from paper_2307_04843_amd import inputs
+    from paper_2307_04843_amd.sim import Simulation
+    dx = 0.05
+    dt = 0.95 / math.sqrt(2) * dx
+    e = inputs.plasma(2, (128, 1, 64), (dx,) * 3, (0.0, 0.0, 0.0), 4, inputs.density_uniform(0.01), 1.0, 1.0,
+                      1, stream=0)
+    c2 = (dt / dx) ** 2
+    vg = 1.0 - (1.0 - c2) * (2 * math.pi * dx) ** 2 / 8.0
+    pp = dict(a0=1.0, tau=10.0, x_ref=3.2, t_ref=5.0 + 3.2 / vg, x_f=3.2, w0=5.0, y_c=0.0, z_c=1.6,
+              q_slice=0.0, d_f=2, pol=1, dispersion=0, dx_prop=dx, dt_prop=dt)
+    out = {"workload": "2-D PIC 128x64 cells lambda/20, 4 e per cell (32768), 0.01 n_c, immobile ions, "
+                       "Gaussian D_f=2 a0=1 w0=5 tau=10, 200 steps", "particles": 32768, "steps": 200}
+    for prec in ("f64", "f32"):
+        sim = Simulation(2, n=(128, 1, 64), dx=(dx,) * 3, x_min=(0.0, 0.0, 0.0), t0=0.0, dt=dt, precision=prec,
+                         species=[dict(q=-1.0, m=1.0, state=e)])
+        try:
+            sim.set_pulse("gauss", **pp)
+            sim.step(5)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            sim.step(200)
+            torch.cuda.synchronize()
+            out[prec + "_pushes_per_s"] = 32768 * 200 / (time.perf_counter() - a)
+        finally:
+            sim.close()
+    return out
+
+
+def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_grid=False):
     import torch
     from paper_2307_04843_amd import apt
     from paper_2307_04843_amd.sim import Simulation
     dt = 0.95 / math.sqrt(2) * LAMBDA_DX
     sim = Simulation(2, n=N_CELLS, dx=(LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
-                     precision=precision, species=species, sort_every=sort_every)
+                     precision=precision, species=species, sort_every=sort_every, pulse_on_grid=on_grid)
     try:
-        sim.set_pulse("lg", **workload_pulse(dt))
+        sim.set_pulse("lg", **workload_pulse(dt), sampling="grid" if on_grid else "particles")
         n_part = sum(int(s["state"]["u"].shape[1]) for s in species)
         sim.step(warmup)
         torch.cuda.synchronize()
@@ -332,6 +475,16 @@ def pic_leg(args):
         v32s = n_part * args.fp64_steps / r32s["wall"]
         out["fp32_first_steps_pushes_per_s"] = v32s
         out["fp32_over_fp64"] = v32s / v64
+        log("grid-sampled pulse: %d steps" % args.fp64_steps)
+        rg = run_gpu(species, "f32", args.fp64_steps, 0, on_grid=True)
+        tg = rg["timing"]
+        out["grid_sampled"] = {
+            "pushes_per_s": n_part * args.fp64_steps / rg["wall"],
+            "note": "first %d steps with E1, B1 sampled on the grid (Fig. 1 loop, AP_SAMPLE_GRID): "
+                    "sampling kernel + push without per-particle pulse evaluation; compare "
+                    "fp32_first_steps_pushes_per_s" % args.fp64_steps,
+            "push_ms_per_launch": tg.ms_push / max(1, tg.n_push),
+            "sample_and_round_ms_per_step": tg.ms_other / max(1, args.fp64_steps)}
     del species
     return out
 
@@ -369,6 +522,10 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--skip-pic", action="store_true", help="skip the 2-D PIC leg (profiling runs)")
     ap.add_argument("--sort-every", type=int, default=0, help="tile re-sort interval (0: library default)")
+    ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 3-D leg")
+    ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
+    ap.add_argument("--skip-3d", action="store_true")
+    ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a device buffer of this size (a known-size kernel for "
                          "scaling HBM counters in profiling runs)")
@@ -398,6 +555,10 @@ def main():
         out = pic_leg(args)
     if not args.skip_adjoint:
         out["adjoint"] = adjoint_leg(args)
+    if not args.skip_3d:
+        out["three_d"] = three_d_leg(args)
+    if not args.skip_small:
+        out["small"] = small_leg()
     if not args.skip_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
