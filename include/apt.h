@@ -66,6 +66,8 @@ typedef int32_t ap_status;
 #define AP_DISP_PAPER2      0   /* second-order forms, Eqs. (12)-(14)            */
 #define AP_DISP_EXACT       1   /* exact Yee forms, Eqs. (10)-(11)               */
 #define AP_DISP_VACUUM      2   /* v_phi = v_g = c, B0 = E0                      */
+#define AP_DISP_PLASMA      3   /* exact Yee forms with the analytic current J1
+                                   of a linear plasma response (Sec. IV)        */
 
 /* ap_step flags */
 #define AP_STEP_CONTINUITY  0x1u  /* track max |(rho1-rho0)/dt + div J| (FP64)  */
@@ -195,15 +197,27 @@ typedef struct ap_buffers {
  *   envelope     AP_ENV_*; sg_order g >= 1 and fwhm (intensity full width at
  *                half maximum, lambda/c) for AP_ENV_SGAUSS, centred in the
  *                support [0, tau] (the reading of the paper's super-Gaussian)
- *   sampling     AP_SAMPLE_* */
+ *   sampling     AP_SAMPLE_*
+ *   wp2, zeta, no_fd   AP_DISP_PLASMA only (Sec. IV): the pulse propagates
+ *                in a plasma whose linear response is the analytic current
+ *                J1, dJ1/dt = wp2 zeta E1 (wp2 = omega_p^2/omega^2 of the
+ *                density J1 stands for, e.g. n_e/n_c for electrons; zeta the
+ *                factor of the plasma's discrete response, 0 meaning 1).
+ *                v_phi, v_g and B0/E0 solve the Yee relation with that
+ *                current; every step the grid's Yee update is driven by
+ *                J - J1 (J1 at t^{n+1/2} on the E nodes).  B1 and J1 keep
+ *                the lowest-order finite-duration corrections unless
+ *                no_fd != 0.  Needs a gridded run, AP_SAMPLE_GRID and a
+ *                pulse type other than AP_PULSE_GAUSS_NP. */
 typedef struct ap_pulse_params {
     double  a0, tau, t_ref, x_ref, phi0, chirp;
     double  x_f, w0, y_c, z_c, q_slice;
     double  beta_f, x0_ff, t0_ff;
     double  dx_prop, dt_prop;
     int32_t d_f, lg_l, lg_p, pol, dispersion, np_order;
-    int32_t envelope, sg_order, sampling, reserved;
+    int32_t envelope, sg_order, sampling, no_fd;
     double  fwhm;
+    double  wp2, zeta;
 } ap_pulse_params;
 
 /* FP64 diagnostics (reductions of the current state). */

@@ -16,7 +16,7 @@ AP_OK, AP_E_ARG, AP_E_STATE, AP_E_DEVICE, AP_E_NOMEM, AP_E_UNSUPPORTED, AP_E_NUM
 AP_MAX_SPECIES = 4
 AP_F32, AP_F64 = 0, 1
 AP_PULSE_NONE, AP_PULSE_PLANE, AP_PULSE_GAUSS, AP_PULSE_LG, AP_PULSE_FF, AP_PULSE_GAUSS_NP = range(6)
-AP_DISP_PAPER2, AP_DISP_EXACT, AP_DISP_VACUUM = 0, 1, 2
+AP_DISP_PAPER2, AP_DISP_EXACT, AP_DISP_VACUUM, AP_DISP_PLASMA = 0, 1, 2, 3
 AP_STEP_CONTINUITY, AP_STEP_NO_YEE, AP_STEP_RECORD = 0x1, 0x2, 0x4
 AP_DIAG_PARTICLES, AP_DIAG_FIELDS = 0x1, 0x2
 AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5)
@@ -68,7 +68,7 @@ class ap_pulse_params(C.Structure):
                 ("d_f", C.c_int32), ("lg_l", C.c_int32), ("lg_p", C.c_int32), ("pol", C.c_int32),
                 ("dispersion", C.c_int32), ("np_order", C.c_int32),
                 ("envelope", C.c_int32), ("sg_order", C.c_int32), ("sampling", C.c_int32),
-                ("reserved", C.c_int32), ("fwhm", C.c_double)]
+                ("no_fd", C.c_int32), ("fwhm", C.c_double), ("wp2", C.c_double), ("zeta", C.c_double)]
 
 
 class ap_diag(C.Structure):
@@ -229,7 +229,11 @@ def pulse_params(**kw):
     defaults = dict(a0=1.0, tau=10.0, t_ref=0.0, x_ref=0.0, phi0=0.0, chirp=0.0, x_f=0.0, w0=5.0,
                     y_c=0.0, z_c=0.0, q_slice=0.0, beta_f=0.0, x0_ff=0.0, t0_ff=0.0, dx_prop=0.0,
                     dt_prop=0.0, d_f=3, lg_l=0, lg_p=0, pol=0, dispersion=AP_DISP_PAPER2, np_order=4,
-                    envelope=AP_ENV_SIN2, sg_order=4, sampling=AP_SAMPLE_PARTICLES, fwhm=0.0)
+                    envelope=AP_ENV_SIN2, sg_order=4, sampling=AP_SAMPLE_PARTICLES, fwhm=0.0, wp2=0.0,
+                    zeta=0.0, no_fd=0)
+    if "fd" in kw:
+        kw = dict(kw)
+        kw["no_fd"] = 0 if kw.pop("fd") else 1
     defaults.update(kw)
     if isinstance(defaults["envelope"], str):
         defaults["envelope"] = ENVELOPES[defaults["envelope"]]

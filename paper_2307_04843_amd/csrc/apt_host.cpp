@@ -455,13 +455,21 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
     if (!prm) return fail(AP_E_ARG, "pulse parameters are NULL");
     const double vals[] = {prm->a0, prm->tau, prm->t_ref, prm->x_ref, prm->phi0, prm->chirp, prm->x_f,
                            prm->w0, prm->y_c, prm->z_c, prm->q_slice, prm->beta_f, prm->x0_ff, prm->t0_ff,
-                           prm->dx_prop, prm->dt_prop};
+                           prm->dx_prop, prm->dt_prop, prm->wp2, prm->zeta};
     for (double v : vals)
         if (!std::isfinite(v)) return fail(AP_E_ARG, "pulse parameters must be finite");
     if (!(prm->tau > 0.0)) return fail(AP_E_ARG, "tau must be > 0");
     if (prm->pol != 0 && prm->pol != 1) return fail(AP_E_ARG, "pol must be 0 or 1");
-    if (prm->dispersion < AP_DISP_PAPER2 || prm->dispersion > AP_DISP_VACUUM)
+    if (prm->dispersion < AP_DISP_PAPER2 || prm->dispersion > AP_DISP_PLASMA)
         return fail(AP_E_ARG, "unknown dispersion mode");
+    const bool plasma = prm->dispersion == AP_DISP_PLASMA;
+    if (plasma) {
+        if (type == AP_PULSE_GAUSS_NP) return fail(AP_E_ARG, "the nonparaxial Gaussian is a vacuum solution");
+        if (c->s.dim == 0) return fail(AP_E_ARG, "an analytic current needs a grid");
+        if (prm->sampling != AP_SAMPLE_GRID)
+            return fail(AP_E_UNSUPPORTED, "an analytic current needs the pulse sampled on the grid (AP_SAMPLE_GRID)");
+        if (prm->wp2 < 0.0 || prm->zeta < 0.0) return fail(AP_E_ARG, "wp2 and zeta must be >= 0");
+    }
     const bool focused = type != AP_PULSE_PLANE;
     if (focused && !(prm->w0 > 0.0)) return fail(AP_E_ARG, "w0 must be > 0");
     if (focused && type != AP_PULSE_GAUSS_NP && prm->d_f != 2 && prm->d_f != 3)
@@ -497,7 +505,23 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         if (!(dxp > 0.0) || !(dtp > 0.0) || c->s.dim == 0 && !(prm->dx_prop > 0.0 && prm->dt_prop > 0.0))
             return fail(AP_E_ARG, "grid dispersion modes need dx_prop and dt_prop");
         const double cr = dtp / dxp;
-        if (prm->dispersion == AP_DISP_PAPER2) {
+        if (plasma) {
+            // Sec. IV: sin^2(dt/2) - wp2 zeta (dt/2) sin(dt/2) = (dt/dx)^2 sin^2(k dx/2), omega = 1
+            const double zeta = prm->zeta > 0.0 ? prm->zeta : 1.0;
+            const double h = 0.5 * dtp, sh = std::sin(h), ch = std::cos(h);
+            const double lhs = sh * sh - prm->wp2 * zeta * h * sh;
+            if (!(lhs > 0.0) || !(std::sqrt(lhs) / cr < 1.0))
+                return fail(AP_E_ARG, "no propagating Yee mode for this plasma density");
+            const double kk = 2.0 / dxp * std::asin(std::sqrt(lhs) / cr);
+            v_phi = 1.0 / kk;
+            const double dlhs = sh * ch * dtp - prm->wp2 * zeta * h * (h * ch - sh);
+            v_g = cr * cr * std::sin(0.5 * kk * dxp) * std::cos(0.5 * kk * dxp) * dxp / dlhs;
+            boe = ch * std::sqrt(1.0 - prm->wp2 * zeta * h / sh);
+            P.current = 1;
+            P.fd = prm->no_fd ? 0 : 1;
+            P.wp2z = prm->wp2 * zeta;
+            P.fd_delta = 1.0 - v_phi / v_g;
+        } else if (prm->dispersion == AP_DISP_PAPER2) {
             v_phi = 1.0 - (1.0 - cr * cr) * dxp * dxp / 24.0;
             v_g = 1.0 - (1.0 - cr * cr) * dxp * dxp / 8.0;
             boe = 1.0 - dtp * dtp / 8.0;
@@ -731,11 +755,12 @@ ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void 
     hipError_t e;
     // positions arrive in lambda units; the device function works in internal units
     if (n == 0) return AP_OK;
+    const double fd_delta = (c->P.current && c->P.fd) ? c->P.fd_delta : 0.0;
     if (c->s.prec == AP_F64)
-        e = launch_eval_pulse<double>(c->P.type, plain_vars<double>(c->P, t * kTwoPi), n, xyz,
+        e = launch_eval_pulse<double>(c->P.type, plain_vars<double>(c->P, t * kTwoPi), fd_delta, n, xyz,
                                       static_cast<double *>(E), static_cast<double *>(B), c->stream);
     else
-        e = launch_eval_pulse<float>(c->P.type, plain_vars<float>(c->P, t * kTwoPi), n, xyz,
+        e = launch_eval_pulse<float>(c->P.type, plain_vars<float>(c->P, t * kTwoPi), fd_delta, n, xyz,
                                      static_cast<float *>(E), static_cast<float *>(B), c->stream);
     if (e != hipSuccess) return hip_fail(e, "ap_eval_pulse");
     return AP_OK;
@@ -1332,6 +1357,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         sa.fnxy = fnxy;
         sa.q_slice = c->P.q_slice;
         sa.W = a.W;
+        sa.fd_b = (c->P.current && c->P.fd) ? 1 : 0;
+        sa.fd_delta = c->P.fd_delta;
         HIPCHK(launch_sample_pulse<T>(c->P.type, sa, c->stream), "sample pulse");
     }
     const int push_pulse = on_grid ? (int)PT_NONE : c->P.type;
@@ -1383,6 +1410,25 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         T *J[3] = {F[6], F[7], F[8]};
         HIPCHK(launch_continuity<T>(s.dim, s.n, s.dx, s.dt, rho0, rho1, J, c->counters() + 2, c->counters() + 3,
                                     c->stream), "continuity");
+    }
+    if (c->P.current) {
+        // Sec. IV: E2, B2 are driven by J - J1, J1 at t^{n+1/2}
+        Timer tm(c, 3);
+        CurrentArgs<T> ca{};
+        for (int k = 0; k < 3; ++k) {
+            ca.J[k] = F[6 + k];
+            ca.n[k] = s.n[k];
+            ca.dx[k] = s.dx[k];
+            ca.x_min[k] = s.x_min[k];
+        }
+        ca.dim = s.dim;
+        ca.fnx = fnx;
+        ca.fnxy = fnxy;
+        ca.q_slice = c->P.q_slice;
+        ca.W = plain_vars<T>(c->P, a.t + 0.5 * s.dt);
+        ca.wp2z = c->P.wp2z;
+        ca.fd = c->P.fd;
+        HIPCHK(launch_analytic_current<T>(c->P.type, ca, c->stream), "analytic current");
     }
     {
         Timer tm(c, 1);

@@ -3,6 +3,7 @@
 // (E2 = B2 = 0), so particles are independent: one thread per particle.
 // Positions are per-axis (virtual cell, FP32 offset); the FP64 position
 // x_min + (i + off) dx feeds the analytic phase.
+#include "current_dev.h"
 #include "kernels.h"
 
 namespace apt {
@@ -104,14 +105,18 @@ template <typename T> hipError_t launch_gridless(int pulse, const GridlessArgs<T
     default: return hipErrorInvalidValue;
     }
 }
-// E1, B1 at arbitrary lab points (internal units), component-major outputs.
+// E1, B1 at arbitrary lab points (internal units), component-major outputs;
+// fd_delta != 0: B1 with the finite-duration correction of an analytic current.
 template <typename T, int PT>
-__global__ __launch_bounds__(256) void k_eval_pulse(PulseVar<T> W, int64_t n, const double *xyz, T *E, T *B) {
+__global__ __launch_bounds__(256) void k_eval_pulse(PulseVar<T> W, double fd_delta, int64_t n, const double *xyz,
+                                                    T *E, T *B) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     T e[3], b[3];
     const double L = 6.283185307179586;   // positions arrive in lambda units
-    analytic_field<PT, T>(W, xyz[i] * L, xyz[n + i] * L, xyz[2 * n + i] * L, e, b);
+    const double X = xyz[i] * L, Y = xyz[n + i] * L, Z = xyz[2 * n + i] * L;
+    if (fd_delta != 0.0) field_fd<PT, T>(W, quadrature_vars(W), T(fd_delta), X, Y, Z, e, b);
+    else analytic_field<PT, T>(W, X, Y, Z, e, b);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         E[c * n + i] = e[c];
@@ -120,29 +125,31 @@ __global__ __launch_bounds__(256) void k_eval_pulse(PulseVar<T> W, int64_t n, co
 }
 
 template <typename T, int PT>
-static hipError_t launch_ev(const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B, hipStream_t s) {
+static hipError_t launch_ev(const PulseVar<T> &W, double fd_delta, int64_t n, const double *xyz, T *E, T *B,
+                            hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_eval_pulse<T, PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, n, xyz, E, B);
+    hipLaunchKernelGGL((k_eval_pulse<T, PT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, W, fd_delta, n,
+                       xyz, E, B);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B,
-                             hipStream_t s) {
+hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, double fd_delta, int64_t n, const double *xyz, T *E,
+                             T *B, hipStream_t s) {
     switch (pulse) {
-    case PT_NONE: return launch_ev<T, PT_NONE>(W, n, xyz, E, B, s);
-    case PT_PLANE: return launch_ev<T, PT_PLANE>(W, n, xyz, E, B, s);
-    case PT_GAUSS: return launch_ev<T, PT_GAUSS>(W, n, xyz, E, B, s);
-    case PT_LG: return launch_ev<T, PT_LG>(W, n, xyz, E, B, s);
-    case PT_FF: return launch_ev<T, PT_FF>(W, n, xyz, E, B, s);
-    case PT_NP: return launch_ev<T, PT_NP>(W, n, xyz, E, B, s);
+    case PT_NONE: return launch_ev<T, PT_NONE>(W, 0.0, n, xyz, E, B, s);
+    case PT_PLANE: return launch_ev<T, PT_PLANE>(W, fd_delta, n, xyz, E, B, s);
+    case PT_GAUSS: return launch_ev<T, PT_GAUSS>(W, fd_delta, n, xyz, E, B, s);
+    case PT_LG: return launch_ev<T, PT_LG>(W, fd_delta, n, xyz, E, B, s);
+    case PT_FF: return launch_ev<T, PT_FF>(W, fd_delta, n, xyz, E, B, s);
+    case PT_NP: return launch_ev<T, PT_NP>(W, 0.0, n, xyz, E, B, s);
     default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_eval_pulse<float>(int, const PulseVar<float> &, int64_t, const double *, float *, float *,
-                                             hipStream_t);
-template hipError_t launch_eval_pulse<double>(int, const PulseVar<double> &, int64_t, const double *, double *,
-                                              double *, hipStream_t);
+template hipError_t launch_eval_pulse<float>(int, const PulseVar<float> &, double, int64_t, const double *, float *,
+                                             float *, hipStream_t);
+template hipError_t launch_eval_pulse<double>(int, const PulseVar<double> &, double, int64_t, const double *,
+                                              double *, double *, hipStream_t);
 
 template hipError_t launch_gridless<float>(int, const GridlessArgs<float> &, hipStream_t);
 template hipError_t launch_gridless<double>(int, const GridlessArgs<double> &, hipStream_t);

@@ -89,8 +89,25 @@ template <typename T> struct SampleArgs {
     double x_min[3];
     double q_slice;              // lab y of an (x, z) grid
     PulseVar<T> W;               // pulse constants of this step
+    int32_t fd_b;                // B1 with the finite-duration correction of an analytic current
+    double fd_delta;             // its factor 1 - v_phi/v_g
 };
 template <typename T> hipError_t launch_sample_pulse(int pulse, const SampleArgs<T> &a, hipStream_t s);
+
+// Analytic current (Sec. IV): J[c] -= J1_c at component c's E node, t^{n+1/2}.
+template <typename T> struct CurrentArgs {
+    T *J[3];
+    int32_t n[3];
+    int32_t dim;
+    FastDiv fnx, fnxy;
+    double dx[3];
+    double x_min[3];
+    double q_slice;
+    PulseVar<T> W;               // pulse constants at t^{n+1/2}
+    double wp2z;                 // omega_p^2 zeta / omega
+    int32_t fd;                  // finite-duration correction kept
+};
+template <typename T> hipError_t launch_analytic_current(int pulse, const CurrentArgs<T> &a, hipStream_t s);
 
 // Gridded runs, frozen-grid reading: the E2, B2 the push gathered at step n
 // are a recorded external field; their position dependence enters dL/dx.
@@ -140,9 +157,10 @@ template <typename T>
 hipError_t launch_push_deposit_3d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);
 template <typename T>
 hipError_t launch_gridless(int pulse, const GridlessArgs<T> &a, hipStream_t s);
+// fd_delta != 0: B1 with the finite-duration correction of an analytic current.
 template <typename T>
-hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, int64_t n, const double *xyz, T *E, T *B,
-                             hipStream_t s);
+hipError_t launch_eval_pulse(int pulse, const PulseVar<T> &W, double fd_delta, int64_t n, const double *xyz, T *E,
+                             T *B, hipStream_t s);
 template <typename T>
 hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &g, int no_yee, hipStream_t s);
 template <typename T>

@@ -46,6 +46,9 @@ struct PulseDev {
     int32_t envelope, sg_order;            // AP_ENV_*, super-Gaussian order g
     double inv_tau_g;                      // 1/tau_g of the super-Gaussian
     int32_t sampling;                      // AP_SAMPLE_* (host sequencing only)
+    int32_t current, fd;                   // analytic current J1 on; finite-duration terms kept
+    double wp2z;                           // omega_p^2 zeta / omega of J1
+    double fd_delta;                       // 1 - v_phi / v_g (B1's finite-duration factor)
 };
 
 // Generalised Laguerre L_n^a(x) and its derivative (-L_{n-1}^{a+1}).

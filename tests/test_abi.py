@@ -124,8 +124,11 @@ def test_pulse_on_grid_option_reserves_workspace():
 
 def test_pulse_params_struct_matches_header():
     """ap_pulse_params in the binding has the header's layout: 16 doubles, 10
-    int32 (d_f ... reserved), then fwhm."""
-    assert C.sizeof(apt.ap_pulse_params) == 16 * 8 + 10 * 4 + 8
+    int32 (d_f ... no_fd), then fwhm, wp2, zeta."""
+    assert C.sizeof(apt.ap_pulse_params) == 16 * 8 + 10 * 4 + 3 * 8
     assert apt.ap_pulse_params.fwhm.offset == 16 * 8 + 10 * 4
+    assert apt.ap_pulse_params.zeta.offset == 16 * 8 + 10 * 4 + 16
     p = apt.pulse_params(envelope="sgauss", sampling="grid", fwhm=30.0)
     assert (p.envelope, p.sampling, p.fwhm) == (apt.AP_ENV_SGAUSS, apt.AP_SAMPLE_GRID, 30.0)
+    q = apt.pulse_params(dispersion=apt.AP_DISP_PLASMA, wp2=0.05, fd=False)
+    assert (q.wp2, q.zeta, q.no_fd) == (0.05, 0.0, 1)
