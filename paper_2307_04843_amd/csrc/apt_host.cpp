@@ -51,7 +51,7 @@ struct RunShape {
 };
 
 struct WorkLayout {
-    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, total = 0;
+    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, total = 0;
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -128,9 +128,11 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
     s.options = g->options;
-    // default re-sort interval: 2-D tiles carry a two-cell drift margin, 3-D
-    // tiles none (LDS budget), so 3-D re-sorts every other step
-    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 2 : 12);
+    // default re-sort interval: 2-D tiles carry a two-cell drift margin; 3-D
+    // tiles none (LDS budget), so 3-D re-sorts every step (a push that leaves
+    // the staged region takes the global path, which measured costlier than
+    // the sort)
+    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 1 : 12);
     int64_t total = 0;
     for (int i = 0; i < nsp; ++i) {
         if (!finite_pos(sp[i].m)) return fail(AP_E_ARG, "species mass must be finite and > 0");
@@ -173,6 +175,7 @@ WorkLayout make_layout(const RunShape &s) {
         if (s.prec == AP_F32) L.jacc = take((size_t)s.ncell * 3 * 8);
         // E2 + E1 and B2 + B1 with E1, B1 sampled on the grid (AP_SAMPLE_GRID)
         if (s.options & AP_GRID_PULSE_ON_GRID) L.esamp = take((size_t)s.ncell * 6 * s.real);
+        L.scan_part = take((size_t)2 * scan_part_len((int32_t)s.ntiles) * 4);
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
             L.count[i] = take((size_t)s.ntiles * 4);
@@ -1242,7 +1245,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sa.count = count;
             sa.rank = rank;
             if (s.np[i] > 0) HIPCHK(launch_tile_count(sa, c->stream), "tile count");
-            HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->stream), "tile scan");
+            HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(L.scan_part), c->stream), "tile scan");
             ScatterArgs<T> sc{};
             sc.cell_src = p.cell;
             sc.cell_dst = c->wp<int32_t>(L.alt_cell[i]);

@@ -1,5 +1,7 @@
 // Grid-side kernels: Yee update of E2, B2 only, J clear, tile sort,
 // FP64 diagnostics (moments, energies, charge density, continuity residual).
+#include <climits>
+
 #include "kernels.h"
 
 namespace apt {
@@ -168,28 +170,68 @@ AP_D int tile_of(int cell, int dim, const FastDiv &fnx, const FastDiv &fnxy, con
     return tx + ntile[0] * (ty + ntile[1] * tz);
 }
 
+// Tile histogram and each particle's rank within its tile.  Lanes of a wave
+// with equal tiles are grouped (ballot); the block's four waves then combine
+// their groups per tile in LDS, so that one global atomic per (block, tile)
+// hands out the block's slots (sorted input puts a block in one to three
+// tiles).  Tiles more than kAggSlots above the block's smallest take a global
+// atomic per wave group.  Within a block the ranks follow wave then lane order.
+constexpr int kAggSlots = 32;
+
 __global__ __launch_bounds__(256) void k_tile_count(SortArgs a) {
+    __shared__ int s_cnt[4][kAggSlots];
+    __shared__ int s_base[kAggSlots];
+    __shared__ int s_min[4];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int key = -1;
     if (p < a.n) {
         const int cell = a.cell[p];
         key = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
     }
-    const int lane = threadIdx.x & 63;
+    int km = key >= 0 ? key : INT_MAX;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) km = min(km, __shfl_xor(km, off, 64));
+    if (lane == 0) s_min[wid] = km;
+    for (int e = threadIdx.x; e < 4 * kAggSlots; e += blockDim.x) s_cnt[e / kAggSlots][e % kAggSlots] = 0;
+    __syncthreads();
+    const int key0 = min(min(s_min[0], s_min[1]), min(s_min[2], s_min[3]));
+    int slot = -1, local = 0;
     unsigned long long active = __ballot(key >= 0);
     while (active) {
         const int leader = __ffsll((long long)active) - 1;
         const int lkey = __shfl(key, leader, 64);
         const unsigned long long match = __ballot(key == lkey) & active;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&a.count[lkey], __popcll(match));
-        base = __shfl(base, leader, 64);
-        if (key == lkey && ((match >> lane) & 1ull)) {
-            const unsigned long long below = match & ((1ull << lane) - 1ull);
-            a.rank[p] = base + __popcll(below);
+        const bool mine = key == lkey && ((match >> lane) & 1ull);
+        const int below = __popcll(match & ((1ull << lane) - 1ull));
+        const int sl = lkey - key0;
+        if (sl < kAggSlots) {
+            if (lane == leader) s_cnt[wid][sl] = __popcll(match);
+            if (mine) {
+                slot = sl;
+                local = below;
+            }
+        } else {
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&a.count[lkey], __popcll(match));
+            base = __shfl(base, leader, 64);
+            if (mine) a.rank[p] = base + below;
         }
         active &= ~match;
     }
+    __syncthreads();
+    if (threadIdx.x < kAggSlots) {
+        const int sl = threadIdx.x;
+        int run = 0;
+        for (int w = 0; w < 4; ++w) {
+            const int c = s_cnt[w][sl];
+            s_cnt[w][sl] = run;
+            run += c;
+        }
+        s_base[sl] = run > 0 ? atomicAdd(&a.count[key0 + sl], run) : 0;
+    }
+    __syncthreads();
+    if (slot >= 0) a.rank[p] = s_base[slot] + s_cnt[wid][slot] + local;
 }
 
 hipError_t launch_tile_count(const SortArgs &a, hipStream_t s) {
@@ -199,7 +241,7 @@ hipError_t launch_tile_count(const SortArgs &a, hipStream_t s) {
 }
 
 // Exclusive scan of n counts into start[0..n] by one workgroup of 1024
-// threads, each owning a contiguous chunk.
+// threads, each owning a contiguous chunk (the top level of launch_scan).
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *start, int32_t n) {
     __shared__ int32_t part[1024];
     const int t = threadIdx.x;
@@ -224,8 +266,82 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *count, int32_t *st
     if (t == 1023) start[n] = part[1023];
 }
 
-hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, n_tiles);
+// Two-level scan for many tiles: each block of 1024 threads owns kScanChunk
+// consecutive counts (4 per thread).
+constexpr int kScanChunk = 4096;
+
+// Exclusive scan of one int per thread over a 1024-thread block; returns the
+// block total through *total.
+AP_D int block_exclusive_scan(int v, int *sh, int *total) {
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int w = 0; w < 16; ++w) {
+            const int c = sh[w];
+            sh[w] = run;
+            run += c;
+        }
+        sh[16] = run;
+    }
+    __syncthreads();
+    const int out = sh[wid] + x - v;
+    *total = sh[16];
+    return out;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_part(const int32_t *count, int32_t n, int32_t *part) {
+    __shared__ int sh[17];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * 4;
+    int v = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (base + m < n) v += count[base + m];
+    int total;
+    block_exclusive_scan(v, sh, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_final(const int32_t *count, int32_t n, const int32_t *part_start,
+                                                     int32_t *start) {
+    __shared__ int sh[17];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * 4;
+    int c[4], v = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        c[m] = base + m < n ? count[base + m] : 0;
+        v += c[m];
+    }
+    int total;
+    int run = part_start[blockIdx.x] + block_exclusive_scan(v, sh, &total);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (base + m < n) start[base + m] = run;
+        run += c[m];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[n] = part_start[gridDim.x];
+}
+
+int32_t scan_part_len(int32_t n_tiles) { return (n_tiles + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, int32_t *part, hipStream_t s) {
+    if (n_tiles <= kScanChunk) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, count, start, n_tiles);
+        return hipGetLastError();
+    }
+    // part: [nb] block totals, then [nb + 1] their exclusive scan
+    const int nb = (n_tiles + kScanChunk - 1) / kScanChunk;
+    int32_t *part_start = part + nb;
+    hipLaunchKernelGGL(k_scan_part, dim3(nb), dim3(1024), 0, s, count, n_tiles, part);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, part, part_start, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n_tiles, part_start, start);
     return hipGetLastError();
 }
 

@@ -180,7 +180,10 @@ struct SortArgs {
     int32_t *rank;               // [n]
 };
 hipError_t launch_tile_count(const SortArgs &a, hipStream_t s);
-hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, hipStream_t s);
+// start[0..n_tiles] = exclusive scan of count (start[n_tiles] = total).
+// part: scratch of 2 * scan_part_len(n_tiles) ints.
+int32_t scan_part_len(int32_t n_tiles);
+hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, int32_t *part, hipStream_t s);
 
 template <typename T> struct ScatterArgs {
     const int32_t *cell_src; const T *off_src[3]; const T *u_src[3]; const T *w_src; const int32_t *id_src;

@@ -36,12 +36,16 @@ AP_D int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 // node window (rows of RX nodes; window origin x0, z0).  A 3-node axis is
 // exact when the stencil keeps its nearest node on that axis: the fourth
 // weight is then zero before and after the move, and so is every current
-// term that involves it.
+// term that involves it.  In a 4-node window the lanes that kept their node
+// skip those zero terms (fewer active lanes per LDS atomic).
 template <int WX, int WZ, typename T>
 AP_D void deposit_window(double *sJ, int RC, int RX, int x0, int z0, const T S0x[4], const T DSx[4],
                          const T S0z[4], const T DSz[4], T fx, T fy, T fz) {
     double *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
     const T third = T(1.0 / 3.0);
+    auto atomic_add = [](double *p, double v) {
+        if ((WX == 3 && WZ == 3) || v != 0.0) apt::atomic_add(p, v);
+    };
 #pragma unroll
     for (int b = 0; b < WZ; ++b) {
         const T cz = S0z[b] + T(0.5) * DSz[b];

@@ -322,3 +322,34 @@ def test_one_step_pulse_sampled_on_grid_parity(precision, tol, dim):
         assert np.abs(gf[6 + k] - g.J[k]).max() <= ftol * jmax, ("J", k)
         assert np.abs(gf[k] - g.E[k]).max() <= ftol * fmax, ("E", k)
         assert np.abs(gf[3 + k] - g.B[k]).max() <= ftol * fmax, ("B", k)
+
+
+def test_many_tiles_sorted_steps_fp64():
+    """More tiles than one scan block covers (512 x 160 cells in 4 x 4 tiles:
+    5120 tiles, the two-level tile scan), re-sorted every step: two FP64 steps
+    vs the oracle, every particle (1 electron + 1 proton per cell)."""
+    case = cases.make_case(n=(512, 1, 160), x_min=(0.0, 0.0, 0.0), t0_steps=150, pulse="cfg1", ppc=1,
+                           u_scale=20.0, seed=41)
+    sim = cases.sim_from_case(case, precision="f64", tile=(4, 1, 4), sort_every=1)
+    try:
+        g, sps, P = cases.oracle_state(case)
+        for _ in range(2):
+            pic.step(g, sps, P)
+        sim.step(2)
+        out = [sim.state(i) for i in range(len(sps))]
+        E, B, J = sim.field_views()
+        gf = [t.double().cpu().numpy() for t in E + B + J]
+    finally:
+        sim.close()
+    for sp, st in zip(sps, out):
+        scale = np.maximum(np.linalg.norm(sp.u, axis=0), 1e-3)
+        assert (np.linalg.norm(st["u"].astype(float) - sp.u, axis=0) / scale).max() <= 1e-10
+        pos = cases.gpu_positions(case, st)
+        for ax in (0, 2):
+            assert np.abs(cases.periodic_diff(pos[ax], sp.pos[ax], case["n"][ax])).max() <= 1e-10
+    fmax = max(np.abs(c).max() for c in g.E + g.B)
+    jmax = max(np.abs(c).max() for c in g.J)
+    for k in range(3):
+        assert np.abs(gf[k] - g.E[k]).max() <= 1e-10 * fmax
+        assert np.abs(gf[3 + k] - g.B[k]).max() <= 1e-10 * fmax
+        assert np.abs(gf[6 + k] - g.J[k]).max() <= 1e-10 * jmax
