@@ -110,7 +110,7 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *   t0         simulation time at step 0 (lambda/c).
  *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
  *              with the smallest dx (the rule stated after Eq. (14)).
- *   sort_every steps between tile re-sorts (0 = default: 12 in 2-D, 1 in 3-D).
+ *   sort_every steps between tile re-sorts (0 = default: 8 in 2-D, 1 in 3-D).
  *   options    AP_GRID_* bits (0 = none).  AP_GRID_PULSE_ON_GRID reserves
  *              the workspace for the grid-sampled pulse (AP_SAMPLE_GRID):
  *              6 more reals per cell.

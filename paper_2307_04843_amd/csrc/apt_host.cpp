@@ -132,7 +132,7 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
     // tiles none (LDS budget), so 3-D re-sorts every step (a push that leaves
     // the staged region takes the global path, which measured costlier than
     // the sort)
-    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 1 : 12);
+    s.sort_every = g->sort_every > 0 ? g->sort_every : (s.dim == 3 ? 1 : 8);
     int64_t total = 0;
     for (int i = 0; i < nsp; ++i) {
         if (!finite_pos(sp[i].m)) return fail(AP_E_ARG, "species mass must be finite and > 0");

@@ -2,9 +2,10 @@
 
 The 2-D LG run of ``bench.py`` (4096 x 1024 cells at lambda/20, 16 electrons +
 16 protons per cell = 134M particles, density ramp, LG l=1 p=0 a0=5, default
-tiles and re-sort schedule) is advanced to step 395 (t = 13.3 lambda/c, the
-pulse inside the ramp).  Two single steps are then checked: step 395 (an
-in-place push) and step 396 (re-sort, then push from the sorted copy).  For
+tiles and re-sort schedule, a re-sort every 8 steps) is advanced to step 399
+(t = 13.4 lambda/c, the pulse inside the ramp).  Two single steps are then
+checked: step 399 (an in-place push) and step 400 (re-sort, then push from
+the sorted copy).  For
 each, the oracle recomputes the push of sampled particles one by one from
 the GPU's state and fields at the start of the step.  Half the sample lies in
 the pulse (x < 13.3 lambda, |z| < 10.6 lambda), half is uniform.  The
@@ -103,7 +104,7 @@ def test_full_size_lg_run_sampled_pushes_and_continuity():
     del species[0]["state"], species[1]["state"]
     try:
         sim.set_pulse("lg", **pp)
-        sim.step(395)
+        sim.step(399)
         results = [_check_one_step(sim, species, ids, P, dt) for _ in range(2)]   # in-place, then re-sort
         d, _ = sim.diag()
     finally:
