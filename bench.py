@@ -31,6 +31,12 @@ of d<p_perp^2>/d(beta_f, chirp) over a 32-step window (segments of 8).
 Fourth leg (``small``): the 128 x 64 Gaussian run (32768 electrons, 200 steps)
 in FP64 and FP32; launch-bound, reported for completeness.
 
+Optional leg (``--with-large3d``, off by default: about three minutes of host
+input generation): 3-D PIC, 1024 x 512 x 512 cells at lambda/16, 2 electrons
++ 2 protons per cell (1.07e9 particles) in n = 0.01 exp(-r^2/(20 lambda)^2)
+n_c, Gaussian D_f = 3 pulse (a0 = 3, w0 = 10 lambda, tau = 30 lambda/c,
+focus at the box centre), FP32, steps 450 ... 550 of the 1000-step run.
+
 Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
 """
 import argparse
@@ -175,6 +181,93 @@ def three_d_leg(args):
             del run
             torch.cuda.empty_cache()
     del species
+    return out
+
+
+N5 = (1024, 512, 512)
+X5_MIN = (0.0, -16.0, -16.0)
+
+
+def large3d_inputs(seed=5, slab=32):
+    """Electrons + protons of the 1024 x 512 x 512 channel, generated slab by
+    slab of `slab` z-planes (each slab its own seeded stream) straight into
+    device tensors."""
+    import numpy as np
+    import torch
+    from paper_2307_04843_amd import inputs
+    nx, ny, nz = N5
+    ppc = 2
+    n = nx * ny * nz * ppc
+    dens = inputs.density_gauss_channel(0.01, 20.0, 0.0, 0.0)
+    dev = torch.device("cuda")
+    e = {"cell": torch.empty(n, dtype=torch.int32, device=dev),
+         "off": torch.empty((3, n), dtype=torch.float32, device=dev),
+         "u": torch.empty((3, n), dtype=torch.float32, device=dev),
+         "w": torch.empty(n, dtype=torch.float32, device=dev)}
+    up = torch.empty((3, n), dtype=torch.float32, device=dev)
+    per = nx * ny * slab * ppc
+    for k0 in range(0, nz, slab):
+        xm = (X5_MIN[0], X5_MIN[1], X5_MIN[2] + k0 * DX3)
+        s_e = inputs.plasma(3, (nx, ny, slab), (DX3,) * 3, xm, ppc, dens, 1.0, 1.0, seed, stream=2 * k0)
+        s_p = inputs.plasma(3, (nx, ny, slab), (DX3,) * 3, xm, ppc, dens, 1.0, inputs.PROTON_MASS, seed,
+                            stream=2 * k0 + 1, positions_from=s_e)
+        a, b = (k0 // slab) * per, (k0 // slab + 1) * per
+        e["cell"][a:b] = torch.from_numpy(s_e["cell"] + np.int32(k0 * nx * ny)).to(dev)
+        e["off"][:, a:b] = torch.from_numpy(s_e["off"]).to(dev)
+        e["u"][:, a:b] = torch.from_numpy(s_e["u"]).to(dev)
+        e["w"][a:b] = torch.from_numpy(s_e["w"]).to(dev)
+        up[:, a:b] = torch.from_numpy(s_p["u"]).to(dev)
+        del s_e, s_p
+        log("large 3-D inputs: %d/%d z-planes" % (k0 + slab, nz))
+    p = {"cell": e["cell"].clone(), "off": e["off"].clone(), "u": up, "w": e["w"].clone()}
+    return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
+
+
+def large3d_leg(args):
+    import torch
+    from paper_2307_04843_amd import apt
+    from paper_2307_04843_amd.sim import Simulation
+    species = large3d_inputs()
+    n = sum(int(s["state"]["u"].shape[1]) for s in species)
+    dt = 0.95 / math.sqrt(3) * DX3
+    c2 = (dt / DX3) ** 2
+    vg = 1.0 - (1.0 - c2) * (2 * math.pi * DX3) ** 2 / 8.0
+    xc = N5[0] * DX3 / 2
+    pp = dict(a0=3.0, tau=30.0, x_ref=xc, t_ref=15.0 + xc / vg, x_f=xc, w0=10.0, y_c=0.0, z_c=0.0, d_f=3, pol=0,
+              dispersion=0, dx_prop=DX3, dt_prop=dt)
+    steps, t_step0 = 100, 450
+    out = {"workload": "3-D PIC 1024x512x512 cells lambda/16, 2 e + 2 p per cell (1.07e9), n = 0.01 "
+                       "exp(-r^2/(20 lambda)^2), Gaussian D_f=3 a0=3 w0=10 tau=30, steps %d..%d of the "
+                       "1000-step run" % (t_step0, t_step0 + steps), "particles": n, "steps": steps, "warmup": 3}
+    sim = Simulation(3, n=N5, dx=(DX3,) * 3, x_min=X5_MIN, t0=t_step0 * dt, dt=dt, precision="f32",
+                     species=species)
+    try:
+        sim.set_pulse("gauss", **pp)
+        sim.step(3)
+        torch.cuda.synchronize()
+        apt.ap_timing_enable(sim.ctx, True)
+        apt.ap_timing_read(sim.ctx, reset=True)
+        a = time.perf_counter()
+        for k in range(0, steps, 25):
+            sim.step(25)
+            torch.cuda.synchronize()
+            log("large 3-D: %d/%d steps" % (k + 25, steps))
+        wall = time.perf_counter() - a
+        tm = apt.ap_timing_read(sim.ctx, reset=True)
+        d, _ = sim.diag(allow_numeric=True)
+        ms_push = tm.ms_push / max(1, tm.n_push)
+        bl = n * 60 + sim.ncell * 36
+        out.update({"pushes_per_s": n * steps / wall, "ms_per_step": wall * 1e3 / steps,
+                    "push_ms_per_launch": ms_push, "hbm_gbs_algorithmic": bl / (ms_push * 1e-3) / 1e9,
+                    "hbm_frac": bl / (ms_push * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "yee_ms": tm.ms_yee / max(1, tm.n_yee), "sort_ms_per_step": tm.ms_sort / steps,
+                    "n_nonfinite": d.n_nonfinite, "n_fast": d.n_fast,
+                    "offtile_fraction": d.n_offtile / float(n * (steps + 3))})
+        log("large 3-D: %.3e pushes/s, push %.3f ms/launch" % (out["pushes_per_s"], ms_push))
+    finally:
+        sim.close()
+        del sim, species
+        torch.cuda.empty_cache()
     return out
 
 
@@ -526,6 +619,8 @@ def main():
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
+    ap.add_argument("--with-large3d", action="store_true",
+                    help="add the 1024x512x512 3-D leg (about three minutes of input generation)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a device buffer of this size (a known-size kernel for "
                          "scaling HBM counters in profiling runs)")
@@ -559,6 +654,8 @@ def main():
         out["three_d"] = three_d_leg(args)
     if not args.skip_small:
         out["small"] = small_leg()
+    if args.with_large3d:
+        out["large3d"] = large3d_leg(args)
     if not args.skip_cpu:
         log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)

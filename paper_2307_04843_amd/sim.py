@@ -9,12 +9,21 @@ import torch
 from . import apt
 
 
+def _dev(x, np_dtype, dev):
+    """Device tensor of a host array (converted to np_dtype) or of a tensor."""
+    if isinstance(x, torch.Tensor):
+        return x.to(device=dev, dtype=torch.from_numpy(np.zeros(0, np_dtype)).dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x.astype(np_dtype)), device=dev)
+
+
 class Simulation:
     """One context: grid + species buffers sized by ap_query_layout.
 
     species: list of dicts with keys q, m and a state dict from
-    ``inputs.plasma`` (cell, off, u, w) or ``inputs.beam`` (icell, off, u, w).
-    Lengths and times in lambda units.
+    ``inputs.plasma`` (cell, off, u, w) or ``inputs.beam`` (icell, off, u, w);
+    the arrays may be numpy arrays or torch tensors (a device tensor of the
+    working type is used in place: the run updates it).  Lengths and times in
+    lambda units.
     """
 
     def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
@@ -65,18 +74,14 @@ class Simulation:
             arr = {}
             dev = self.device
             if dim == 0:
-                arr["icell"] = [torch.as_tensor(np.ascontiguousarray(st["icell"][a]), device=dev)
-                                for a in range(3)]
-                arr["off"] = [torch.as_tensor(np.ascontiguousarray(st["off"][a].astype(self.np_dtype)),
-                                              device=dev) for a in range(3)]
+                arr["icell"] = [_dev(st["icell"][a], np.int32, dev) for a in range(3)]
+                arr["off"] = [_dev(st["off"][a], self.np_dtype, dev) for a in range(3)]
             else:
-                arr["cell"] = torch.as_tensor(np.ascontiguousarray(st["cell"].astype(np.int32)), device=dev)
-                arr["off"] = [torch.as_tensor(np.ascontiguousarray(st["off"][a].astype(self.np_dtype)),
-                                              device=dev) if (dim == 3 or a != 1) else None
+                arr["cell"] = _dev(st["cell"], np.int32, dev)
+                arr["off"] = [_dev(st["off"][a], self.np_dtype, dev) if (dim == 3 or a != 1) else None
                               for a in range(3)]
-            arr["u"] = [torch.as_tensor(np.ascontiguousarray(st["u"][a].astype(self.np_dtype)), device=dev)
-                        for a in range(3)]
-            arr["w"] = torch.as_tensor(np.ascontiguousarray(st["w"].astype(self.np_dtype)), device=dev)
+            arr["u"] = [_dev(st["u"][a], self.np_dtype, dev) for a in range(3)]
+            arr["w"] = _dev(st["w"], self.np_dtype, dev)
             arr["id"] = torch.arange(N, dtype=torch.int32, device=dev)
             arr["proxy"] = (torch.zeros(2 * N, dtype=self.dtype, device=dev)
                             if (proxy and dim == 0) else None)
