@@ -21,7 +21,7 @@ def rho(grid, species):
                 idx.append(np.mod(nodes, grid.n[ax]))
                 wts.append(w)
             else:
-                idx.append(np.zeros((1, N), dtype=np.int64))
+                idx.append(np.floor(sp.pos[ax]).astype(np.int64)[None, :] % grid.n[ax])
                 wts.append(np.ones((1, N)))
         for a in range(idx[0].shape[0]):
             for b in range(idx[1].shape[0]):

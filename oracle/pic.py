@@ -35,14 +35,21 @@ _AXIS_OF = {0: 2, 1: 1, 2: 0}   # lab axis -> numpy array axis
 
 
 class Grid:
-    """Internal fields E2, B2 and current J on a periodic Yee grid."""
+    """Internal fields E2, B2 and current J on a periodic Yee grid.
+
+    dim 3: (x, y, z); dim 2: (x, z), the lab y of every node being the
+    pulse's slice; dim 1: rows of independent 1-D grids along x (the
+    reduced-dimensionality series of Sec. III.B), row k at lab z = x_min[2] +
+    k dx[2] and lab y = the pulse's slice.  An inactive axis has no
+    derivative, no motion and no stagger; a particle's coordinate on it is
+    the (integer) index of its row."""
 
     def __init__(self, dim, n, dx, dt, x_min, t0=0.0):
-        if dim not in (2, 3):
-            raise ValueError("grid dimension must be 2 or 3")
+        if dim not in (1, 2, 3):
+            raise ValueError("grid dimension must be 1, 2 or 3")
         self.dim = dim
         nx, ny, nz = n
-        if dim == 2:
+        if dim in (1, 2):
             ny = 1
         self.n = (int(nx), int(ny), int(nz))
         self.dx = tuple(float(d) for d in dx)
@@ -55,7 +62,7 @@ class Grid:
         self.J = [np.zeros(shape) for _ in range(3)]
 
     def active(self, axis):
-        return not (self.dim == 2 and axis == 1)
+        return self.dim == 3 or (self.dim == 2 and axis != 1) or axis == 0
 
 
 class Species:
@@ -107,7 +114,7 @@ def gather(grid, pos):
                     idx.append(np.mod(nodes, grid.n[ax]))
                     wts.append(w)
                 else:
-                    idx.append(np.zeros((1, pos.shape[1]), dtype=np.int64))
+                    idx.append(np.floor(pos[ax]).astype(np.int64)[None, :] % grid.n[ax])
                     wts.append(np.ones((1, pos.shape[1])))
             acc = np.zeros(pos.shape[1])
             arr = comps[c]
@@ -185,7 +192,7 @@ def esirkepov(grid, q, w, pos0, pos1, u_half):
             S0.append(s0)
             DS.append(s1 - s0)
         else:
-            base.append(np.zeros(N, dtype=np.int64))
+            base.append(np.floor(pos0[ax]).astype(np.int64))
             S0.append(np.ones((N, 1)))
             DS.append(np.zeros((N, 1)))
     qw = q * w
@@ -286,7 +293,7 @@ def sample_pulse(grid, pulse):
         comps = []
         for c in range(3):
             X = np.broadcast_to(grid.x_min[0] + (ii + stag[c][0]) * grid.dx[0], shape)
-            Z = np.broadcast_to(grid.x_min[2] + (kk + stag[c][2]) * grid.dx[2], shape)
+            Z = np.broadcast_to(grid.x_min[2] + (kk + (stag[c][2] if grid.active(2) else 0.0)) * grid.dx[2], shape)
             if grid.dim == 3:
                 Y = np.broadcast_to(grid.x_min[1] + (jj + stag[c][1]) * grid.dx[1], shape)
             else:
@@ -310,7 +317,7 @@ def sample_current(grid, pulse, t):
     for c in range(3):
         stag = E_STAGGER[c]
         X = np.broadcast_to(grid.x_min[0] + (ii + stag[0]) * grid.dx[0], shape)
-        Z = np.broadcast_to(grid.x_min[2] + (kk + stag[2]) * grid.dx[2], shape)
+        Z = np.broadcast_to(grid.x_min[2] + (kk + (stag[2] if grid.active(2) else 0.0)) * grid.dx[2], shape)
         if grid.dim == 3:
             Y = np.broadcast_to(grid.x_min[1] + (jj + stag[1]) * grid.dx[1], shape)
         else:

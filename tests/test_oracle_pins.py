@@ -567,10 +567,11 @@ def test_pin10_gather_linear_field_exact():
     assert np.allclose(B[2], -1.0 * pos[0] + 0.5 * (pos[2] - 0.0), atol=1e-12)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim", [1, 2, 3])
 def test_pin9_esirkepov_continuity_and_sum_rules(dim):
     """The deposited current satisfies the discrete continuity equation to
-    round-off, and sum_nodes J_a = sum q w v_a (first-moment sum rule)."""
+    round-off, and sum_nodes J_a = sum q w v_a (first-moment sum rule).  In
+    1-D the particles sit on 8 independent rows."""
     rng = np.random.default_rng(4 + dim)
     n = (10, 7, 8) if dim == 3 else (10, 1, 8)
     g = pic.Grid(dim, n, (0.3, 0.35, 0.25), 0.1, (0.0, 0.0, 0.0))
@@ -579,9 +580,12 @@ def test_pin9_esirkepov_continuity_and_sum_rules(dim):
     for ax in range(3):
         if g.active(ax):
             pos0[ax] = rng.uniform(0, n[ax], N)
+    if dim == 1:
+        pos0[2] = rng.integers(0, n[2], N)
     disp = rng.uniform(-0.95, 0.95, (3, N))
-    if dim == 2:
-        disp[1] = 0.0
+    for ax in range(3):
+        if not g.active(ax):
+            disp[ax] = 0.0
     pos1 = pos0 + disp
     u = rng.standard_normal((3, N))
     w = rng.uniform(0.5, 1.5, N)
@@ -949,3 +953,103 @@ def test_analytic_current_linear_response():
     e_vac = run(units.DISP_EXACT)
     assert e_j1 < e_vac / 8.0, (e_j1, e_vac)
     assert e_j1 < e_nofd, (e_j1, e_nofd)
+
+
+def test_pin1_yee_1d_rows_eigenmode_and_independence():
+    """1-D rows (Sec. III.B series): each row carries the exact discrete plane
+    wave of the 1-D Yee relation sin(w dt/2)/dt = sin(k dx/2)/dx with
+    B0 = cos(w dt/2) E0, to round-off over 400 steps; rows with different
+    amplitudes do not couple (no derivative across rows)."""
+    nx, nrows = 64, 3
+    dx = 0.3
+    dt = 0.95 * dx
+    m = 5
+    k = 2 * math.pi * m / (nx * dx)
+    omega = 2.0 / dt * math.asin(dt / dx * math.sin(k * dx / 2))
+    g = pic.Grid(1, (nx, 1, nrows), (dx, dx, 7.0), dt, (0.0, 0.0, 0.0))
+    xi = np.arange(nx) * dx
+    amp = np.array([1.0, -0.5, 0.0])[:, None, None]
+    g.E[2][:] = amp * np.cos(k * xi)[None, None, :]
+    g.B[1][:] = -amp * (math.cos(omega * dt / 2) * np.cos(k * (xi + dx / 2)))[None, None, :]
+    for _ in range(400):
+        pic.yee_step(g)
+    T = 400 * dt
+    ez = amp[:, 0, 0][:, None] * np.cos(k * xi - omega * T)[None, :]
+    by = -amp[:, 0, 0][:, None] * math.cos(omega * dt / 2) * np.cos(k * (xi + dx / 2) - omega * T)[None, :]
+    assert np.max(np.abs(g.E[2][:, 0, :] - ez)) < 1e-11
+    assert np.max(np.abs(g.B[1][:, 0, :] - by)) < 1e-11
+    assert np.max(np.abs(g.E[2][2])) == 0.0
+
+
+def test_1d_rows_step_equals_separate_runs():
+    """A step of particles spread over rows equals each row stepped as its own
+    one-row grid placed at that row's lab z (sample_pulse and the pulse see
+    the row's position; deposit, gather and Yee stay inside the row)."""
+    from tests import cases
+    dxl = 0.05
+    nx, nrows = 48, 3
+    dtl = units.default_dt(dxl, 1)
+    pp = dict(type="gauss", a0=2.0, tau=20.0, x_ref=1.2, t_ref=10.0, x_f=1.2, w0=1.5, y_c=0.0, z_c=0.4,
+              q_slice=0.1, d_f=3, pol=1, dispersion=units.DISP_PAPER2, dx_prop=dxl, dt=dtl)
+    P = pulses.Pulse(pp)
+    rng = np.random.default_rng(9)
+    N = 600
+    pos = np.zeros((3, N))
+    pos[0] = rng.uniform(0, nx, N)
+    pos[2] = rng.integers(0, nrows, N)
+    u = rng.standard_normal((3, N)) * 0.05
+    w = rng.uniform(0.5, 1.5, N)
+    xmin = (0.0, 0.0, -0.3)
+    dz = 0.35 * L
+    g = pic.Grid(1, (nx, 1, nrows), (dxl * L, dxl * L, dz), dtl * L, tuple(v * L for v in xmin), t0=10.0 * L)
+    for c in range(3):
+        g.E[c][:] = rng.standard_normal(g.E[c].shape) * 0.05
+        g.B[c][:] = rng.standard_normal(g.B[c].shape) * 0.05
+    E0 = [e.copy() for e in g.E]
+    B0 = [b.copy() for b in g.B]
+    sp = pic.Species(-1.0, 1.0, pos, u, w)
+    pic.step(g, [sp], P)
+    for r in range(nrows):
+        sel = pos[2] == r
+        gr = pic.Grid(1, (nx, 1, 1), (dxl * L, dxl * L, dz), dtl * L, (xmin[0] * L, 0.0, xmin[2] * L + r * dz),
+                      t0=10.0 * L)
+        for c in range(3):
+            gr.E[c][0] = E0[c][r]
+            gr.B[c][0] = B0[c][r]
+        p_r = pos[:, sel].copy()
+        p_r[2] = 0.0
+        spr = pic.Species(-1.0, 1.0, p_r, u[:, sel], w[sel])
+        pic.step(gr, [spr], P)
+        assert np.allclose(spr.u, sp.u[:, sel], rtol=0, atol=1e-13)
+        assert np.allclose(spr.pos[0], sp.pos[0, sel], rtol=0, atol=1e-12)
+        for c in range(3):
+            assert np.allclose(gr.E[c][0], g.E[c][r], rtol=0, atol=1e-13)
+            assert np.allclose(gr.J[c][0], g.J[c][r], rtol=0, atol=1e-13)
+    assert max(np.abs(g.J[c]).max() for c in range(3)) > 0
+
+
+def test_1d_row_test_particle_equals_gridless_plane_wave():
+    """1D-3V: a zero-weight electron on a 1-D row driven by a PLANE pulse
+    (no transverse dependence) moves exactly as the gridless test particle:
+    the same u (all three components) at every step as the pulse passes,
+    and the same x after 300 steps."""
+    dxl = 0.05
+    dtl = units.default_dt(dxl, 1)
+    pp = dict(type="plane", a0=1.0, tau=10.0, x_ref=0.0, t_ref=6.0, pol=0, dispersion=units.DISP_PAPER2,
+              dx_prop=dxl, dt=dtl)
+    P = pulses.Pulse(pp)
+    g = pic.Grid(1, (64, 1, 1), (dxl * L,) * 3, dtl * L, (0.0, 0.0, 0.0), t0=0.0)
+    sp = pic.Species(-1.0, 1.0, np.array([[10.3], [0.0], [0.0]]), np.zeros((3, 1)), np.zeros(1))
+    X = np.array([[10.3 * dxl * L], [P.q_slice], [0.0]])
+    u = np.zeros((3, 1))
+    umax = 0.0
+    for n in range(300):
+        t = g.t
+        pic.step(g, [sp], P)
+        X, u = pic.gridless_step(t, g.dt, X, u, -1.0, P)
+        umax = max(umax, float(np.abs(u).max()))
+        assert np.allclose(sp.u, u, rtol=0, atol=1e-12)
+    assert umax > 0.5
+    xg = (sp.pos[0] + 64 * np.round((X[0] / (dxl * L) - sp.pos[0]) / 64)) * dxl * L
+    assert abs(float(xg[0] - X[0, 0])) < 1e-10 * L
+    assert max(np.abs(e).max() for e in g.E) == 0.0
