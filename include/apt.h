@@ -96,9 +96,15 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
 
 /* Grid and run description.
  *   dim        0 = gridless test particles (3-D motion, no E2/B2/J),
+ *              1 = rows of independent 1-D grids along x (1D-3V: three
+ *              velocity components, motion, fields and current along x
+ *              only; the reduced-dimensionality series of Sec. III.B),
  *              2 = (x, z) Cartesian grid, 3 = (x, y, z) grid.
  *   precision  AP_F32 or AP_F64: type of every real device array.
- *   n[3]       cells along x, y, z (n[1] ignored for dim 2; unused for 0).
+ *   n[3]       cells along x, y, z (n[1] ignored for dims 1, 2; unused for 0).
+ *              dim 1: n[2] >= 1 rows; row k lies at lab z = x_min[2] +
+ *              k*dx[2] (dx[2] >= 0) and at the pulse's y slice; particles
+ *              keep their row (cell = k*n[0] + i, an x offset only).
  *              The grid is periodic: a field component has n nodes per axis.
  *   tile[3]    particle tile shape in cells (0 = default); the push kernel
  *              stages each tile's fields plus a halo in LDS.
@@ -110,7 +116,8 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *   t0         simulation time at step 0 (lambda/c).
  *   dt         time step (lambda/c); 0 selects c dt/dx = 0.95/sqrt(D)
  *              with the smallest dx (the rule stated after Eq. (14)).
- *   sort_every steps between tile re-sorts (0 = default: 8 in 2-D, 1 in 3-D).
+ *   sort_every steps between tile re-sorts (0 = default: 8 in 1-D and 2-D,
+ *              1 in 3-D).
  *   options    AP_GRID_* bits (0 = none).  AP_GRID_PULSE_ON_GRID reserves
  *              the workspace for the grid-sampled pulse (AP_SAMPLE_GRID):
  *              6 more reals per cell.

@@ -175,7 +175,7 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
         const int cell = a.G.cell[p];
         lid = a.G.id[p];
         ov[0] = a.off[0][p];
-        ov[2] = a.off[2][p];
+        if (GD >= 2) ov[2] = a.off[2][p];
         if (GD == 3) ov[1] = a.off[1][p];
         const int nx = a.G.n[0], nxy = a.G.n[0] * a.G.n[1];
         ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
@@ -195,7 +195,7 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (GD == 0) Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
-            else if (GD == 2 && c == 1) Xd[c] = IN(a.G.q_slice);
+            else if (GD <= 2 && c == 1) Xd[c] = IN(a.G.q_slice);
             else Xd[c] = IN(a.x_min[c] + ((double)ic[c] + (double)ov[c]) * a.dx[c]);
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
@@ -225,7 +225,18 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
             AxisStencil<T> sn[3], sh[3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                if (GD == 2 && ax == 1) continue;
+                if (GD <= 2 && ax == 1) continue;
+                if (GD == 1 && ax == 2) {
+                    // 1-D rows: the particle's own row, weight one, no gradient
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        sn[2].idx[m] = ic[2];
+                        sn[2].w[m] = T(m == 0 ? 1 : 0);
+                        sn[2].dw[m] = T(0);
+                    }
+                    sh[2] = sn[2];
+                    continue;
+                }
                 axis_stencil(ic[ax], ov[ax], false, a.G.n[ax], sn[ax]);
                 axis_stencil(ic[ax], ov[ax], true, a.G.n[ax], sh[ax]);
             }
@@ -243,7 +254,7 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
                 F8.v += v;
                 F8.d[0] += gr[0] * idx_[0];
                 if (GD == 3) F8.d[1] += gr[1] * idx_[1];
-                F8.d[2] += gr[2] * idx_[2];
+                if (GD >= 2) F8.d[2] += gr[2] * idx_[2];
             }
         }
 
@@ -312,8 +323,8 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
             double acc = lx[c];
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[c] + lB[k] * (double)B8[k].d[c];
-            // an (x, z) grid does not move y: its adjoint stays zero
-            if (!(GD == 2 && c == 1)) a.lam[c][lid] = acc;
+            // an (x, z) grid does not move y, 1-D rows move x only: those adjoints stay zero
+            if (GD == 0 || GD == 3 || c == 0 || (GD == 2 && c == 2)) a.lam[c][lid] = acc;
             a.lam[3 + c][lid] = lu0[c];
         }
 #pragma unroll
@@ -368,6 +379,7 @@ template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> 
     for (int k = 0; k < 4; ++k) np += a.slot[k] >= 0 ? 1 : 0;
     switch (a.dim) {
     case 0: launch_adj_gd<T, PT, 0>(a, np, s); break;
+    case 1: launch_adj_gd<T, PT, 1>(a, np, s); break;
     case 2: launch_adj_gd<T, PT, 2>(a, np, s); break;
     case 3: launch_adj_gd<T, PT, 3>(a, np, s); break;
     default: return hipErrorInvalidValue;

@@ -64,12 +64,14 @@ struct WorkLayout {
 constexpr int kDiagBlocks = 512;
 constexpr int kCounters = 8;   // n_fast, n_bad, res_max, j_max, n_offtile, ...
 
-bool axis_active(int dim, int ax) { return dim == 3 || (dim == 2 && ax != 1) || dim == 0; }
+// Axes with dynamics (derivatives, motion, stagger).  dim 1: rows of
+// independent lines along x; the z index is the row.
+bool axis_active(int dim, int ax) { return dim == 3 || dim == 0 || (dim == 2 && ax != 1) || ax == 0; }
 
 ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t nsp, RunShape *out) {
     if (!g) return fail(AP_E_ARG, "grid description is NULL");
     if (!sp) return fail(AP_E_ARG, "species description is NULL");
-    if (g->dim != 0 && g->dim != 2 && g->dim != 3) return fail(AP_E_ARG, "dim must be 0, 2 or 3");
+    if (g->dim < 0 || g->dim > 3) return fail(AP_E_ARG, "dim must be 0, 1, 2 or 3");
     if (g->precision != AP_F32 && g->precision != AP_F64) return fail(AP_E_ARG, "precision must be AP_F32 or AP_F64");
     if (nsp < 1 || nsp > kMaxSpecies) return fail(AP_E_ARG, "n_species must be 1..4");
     RunShape s;
@@ -87,6 +89,12 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
             if (act) {
                 if (g->n[ax] < 4) return fail(AP_E_ARG, "need at least 4 cells on every active axis");
                 s.n[ax] = g->n[ax];
+            } else if (s.dim == 1 && ax == 2) {
+                // rows of a 1-D run: row k sits at lab z = x_min[2] + k dx[2]
+                if (g->n[2] < 1) return fail(AP_E_ARG, "a 1-D run needs n[2] >= 1 rows");
+                if (!std::isfinite(g->dx[2]) || g->dx[2] < 0.0) return fail(AP_E_ARG, "row spacing dx[2] must be >= 0");
+                s.n[2] = g->n[2];
+                s.dx[2] = g->dx[2] * kTwoPi;
             } else {
                 s.n[ax] = 1;
             }
@@ -103,9 +111,9 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
             if (axis_active(s.dim, ax)) { inv2 += 1.0 / (s.dx[ax] * s.dx[ax]); dmin = std::fmin(dmin, s.dx[ax]); }
         s.dt = g->dt > 0.0 ? g->dt * kTwoPi : 0.95 / std::sqrt((double)s.dim) * dmin;
         if (!(s.dt < 1.0 / std::sqrt(inv2))) return fail(AP_E_ARG, "dt exceeds the Yee stability limit");
-        const int def2[3] = {16, 1, 8}, def3[3] = {8, 4, 4};
+        const int def1[3] = {32, 1, 1}, def2[3] = {16, 1, 8}, def3[3] = {8, 4, 4};
         for (int ax = 0; ax < 3; ++ax) {
-            int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : def2[ax]);
+            int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : (s.dim == 2 ? def2[ax] : def1[ax]));
             if (!axis_active(s.dim, ax)) t = 1;
             if (t > s.n[ax]) t = s.n[ax];
             if (t > 64) return fail(AP_E_ARG, "tile extent must be <= 64 cells");
@@ -416,7 +424,7 @@ ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int3
             if (s.dim == 0) {
                 okp = okp && p.icell[0] && p.icell[1] && p.icell[2] && p.off[0] && p.off[1] && p.off[2];
             } else {
-                okp = okp && p.cell && p.off[0] && p.off[2] && p.id && (s.dim == 2 || p.off[1]);
+                okp = okp && p.cell && p.off[0] && p.id && (s.dim == 1 || p.off[2]) && (s.dim != 3 || p.off[1]);
             }
             if (!okp) return fail(AP_E_ARG, "species " + std::to_string(i) + ": a required particle array is NULL");
         }
@@ -732,7 +740,8 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
         }
     }
     if ((what & AP_DIAG_FIELDS) && s.dim > 0) {
-        double vol = s.dx[0] * s.dx[2] * (s.dim == 3 ? s.dx[1] : 1.0);
+        // per unit transverse length (2-D) or area (1-D)
+        double vol = s.dx[0] * (s.dim >= 2 ? s.dx[2] : 1.0) * (s.dim == 3 ? s.dx[1] : 1.0);
         d.field_energy = 0.5 * host[(size_t)kMaxSpecies * kDiagVals] * vol;
     }
     double rmax, jmax;
@@ -1396,7 +1405,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     }
     {
         Timer tm(c, 0);
-        hipError_t e = s.dim == 2 ? launch_push_deposit_2d<T>(push_pulse, a, 256, c->stream)
+        hipError_t e = s.dim == 1   ? launch_push_deposit_1d<T>(push_pulse, a, 256, c->stream)
+                       : s.dim == 2 ? launch_push_deposit_2d<T>(push_pulse, a, 256, c->stream)
                                   : launch_push_deposit_3d<T>(push_pulse, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];

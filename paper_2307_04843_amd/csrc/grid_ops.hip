@@ -109,8 +109,11 @@ hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, 
     g.fny = FastDiv((uint32_t)g.ny);
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     const int blocks = grid_blocks(ncell);
-    const T hx = T(0.5 * a.dt / a.dx[0]), hy = T(0.5 * a.dt / a.dx[1]), hz = T(0.5 * a.dt / a.dx[2]);
-    const T cx = T(a.dt / a.dx[0]), cy = T(a.dt / a.dx[1]), cz = T(a.dt / a.dx[2]);
+    // 1-D rows: the (x, z) kernels with no z derivative, so rows do not couple
+    const T hx = T(0.5 * a.dt / a.dx[0]), hy = T(0.5 * a.dt / a.dx[1]);
+    const T hz = dim == 1 ? T(0) : T(0.5 * a.dt / a.dx[2]);
+    const T cx = T(a.dt / a.dx[0]), cy = T(a.dt / a.dx[1]);
+    const T cz = dim == 1 ? T(0) : T(a.dt / a.dx[2]);
     if (dim == 3) {
         hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
         hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell);
@@ -501,8 +504,8 @@ template <typename T> __global__ __launch_bounds__(256) void k_rho(RhoArgs<T> a)
     int base[3];
     double wt[3][3];
     for (int ax = 0; ax < 3; ++ax) {
-        if (!a.off[ax] || (a.dim == 2 && ax == 1)) {
-            base[ax] = 0;
+        if (!a.off[ax] || (a.dim <= 2 && ax == 1) || (a.dim == 1 && ax == 2)) {
+            base[ax] = idx[ax];   // inactive axis: the node of the particle's own row
             wt[ax][0] = 1.0; wt[ax][1] = 0.0; wt[ax][2] = 0.0;
             continue;
         }
@@ -590,7 +593,8 @@ hipError_t launch_continuity(int dim, const int32_t n[3], const double dx[3], do
     g.fny = FastDiv((uint32_t)g.ny);
     const size_t ncell = (size_t)g.nx * g.ny * g.nz;
     hipLaunchKernelGGL((k_continuity<T>), dim3(grid_blocks(ncell)), dim3(256), 0, s, g, dim, 1.0 / dx[0],
-                       1.0 / dx[1], 1.0 / dx[2], 1.0 / dt, rho0, rho1, J[0], J[1], J[2], ncell, res_max, j_max);
+                       1.0 / dx[1], dim == 1 ? 0.0 : 1.0 / dx[2], 1.0 / dt, rho0, rho1, J[0], J[1], J[2], ncell,
+                       res_max, j_max);
     return hipGetLastError();
 }
 template hipError_t launch_continuity<float>(int, const int32_t[3], const double[3], double, const double *,

@@ -152,6 +152,8 @@ struct YeeArgsBase {
 
 // launchers (hipStream_t passed through)
 template <typename T>
+hipError_t launch_push_deposit_1d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);
+template <typename T>
 hipError_t launch_push_deposit_2d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);
 template <typename T>
 hipError_t launch_push_deposit_3d(int pulse, const PushArgs<T> &a, int threads, hipStream_t s);

@@ -23,7 +23,8 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_sample_pu
         }
         // node and half-node coordinates per axis (lab, internal units)
         const double xn = a.x_min[0] + (double)i * a.dx[0], xh = xn + 0.5 * a.dx[0];
-        const double zn = a.x_min[2] + (double)k * a.dx[2], zh = zn + 0.5 * a.dx[2];
+        // 1-D rows: no stagger across rows (every component sits at the row's z)
+        const double zn = a.x_min[2] + (double)k * a.dx[2], zh = a.dim == 1 ? zn : zn + 0.5 * a.dx[2];
         const double yn = a.dim == 3 ? a.x_min[1] + (double)j * a.dx[1] : a.q_slice;
         const double yh = a.dim == 3 ? yn + 0.5 * a.dx[1] : a.q_slice;
         T e[3], b[3], out[6];
@@ -36,14 +37,14 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_sample_pu
         // Ex (h, n, n), Bz (h, h, n): in 2-D both at (xh, zn)
         ev(xh, yn, zn);
         out[0] = e[0];
-        if (a.dim == 2) out[5] = b[2];
+        if (a.dim < 3) out[5] = b[2];
         // Ey (n, h, n)
         ev(xn, yh, zn);
         out[1] = e[1];
         // Ez (n, n, h), Bx (n, h, h): in 2-D both at (xn, zh)
         ev(xn, yn, zh);
         out[2] = e[2];
-        if (a.dim == 2) out[3] = b[0];
+        if (a.dim < 3) out[3] = b[0];
         // By (h, n, h)
         ev(xh, yn, zh);
         out[4] = b[1];
@@ -94,7 +95,8 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_analytic_
             j = (int)(row - (uint32_t)k * a.n[1]);
         }
         const double xn = a.x_min[0] + (double)i * a.dx[0], xh = xn + 0.5 * a.dx[0];
-        const double zn = a.x_min[2] + (double)k * a.dx[2], zh = zn + 0.5 * a.dx[2];
+        // 1-D rows: no stagger across rows (every component sits at the row's z)
+        const double zn = a.x_min[2] + (double)k * a.dx[2], zh = a.dim == 1 ? zn : zn + 0.5 * a.dx[2];
         const double yn = a.dim == 3 ? a.x_min[1] + (double)j * a.dx[1] : a.q_slice;
         const double yh = a.dim == 3 ? yn + 0.5 * a.dx[1] : a.q_slice;
         T j1[3];

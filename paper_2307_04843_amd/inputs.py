@@ -46,7 +46,8 @@ def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
            stream=0, positions_from=None):
     """Macroparticles filling every cell of a grid, ``ppc`` per cell.
 
-    dim 2 uses axes (x, z); dim 3 uses (x, y, z).  ``dx`` and ``x_min`` are
+    dim 2 uses axes (x, z); dim 3 uses (x, y, z); dim 1 fills rows of 1-D
+    lines along x, row k at z = x_min[2] + k dx[2] (no z offset).  ``dx`` and ``x_min`` are
     per-axis (x, y, z) in lambda units.  Returns a dict of arrays:
         cell  int32 linear cell index (x fastest, then y, then z)
         off   float32 (3, N) offsets in [0, 1) per axis (unused axes zero)
@@ -56,7 +57,7 @@ def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
     species' cells and offsets (co-located ions).
     """
     nx, ny, nz = n_cells
-    if dim == 2:
+    if dim in (1, 2):
         ny = 1
     ncell = nx * ny * nz
     N = ncell * ppc
@@ -67,7 +68,8 @@ def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
         off[0] = _unit_offsets(rng, N)
         if dim == 3:
             off[1] = _unit_offsets(rng, N)
-        off[2] = _unit_offsets(rng, N)
+        if dim >= 2:
+            off[2] = _unit_offsets(rng, N)
     else:
         cell = positions_from["cell"].copy()
         off = positions_from["off"].copy()

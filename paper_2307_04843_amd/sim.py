@@ -78,8 +78,8 @@ class Simulation:
                 arr["off"] = [_dev(st["off"][a], self.np_dtype, dev) for a in range(3)]
             else:
                 arr["cell"] = _dev(st["cell"], np.int32, dev)
-                arr["off"] = [_dev(st["off"][a], self.np_dtype, dev) if (dim == 3 or a != 1) else None
-                              for a in range(3)]
+                act = (True, dim == 3, dim >= 2)   # 1-D rows carry an x offset only
+                arr["off"] = [_dev(st["off"][a], self.np_dtype, dev) if act[a] else None for a in range(3)]
             arr["u"] = [_dev(st["u"][a], self.np_dtype, dev) for a in range(3)]
             arr["w"] = _dev(st["w"], self.np_dtype, dev)
             arr["id"] = torch.arange(N, dtype=torch.int32, device=dev)

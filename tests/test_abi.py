@@ -53,7 +53,9 @@ def test_query_layout_sizes():
 
 
 @pytest.mark.parametrize("mut,msg", [
-    (lambda g: setattr(g, "dim", 1), "dim"),
+    (lambda g: setattr(g, "dim", 4), "dim"),
+    (lambda g: (setattr(g, "dim", 1), g.n.__setitem__(2, 0)), "rows"),
+    (lambda g: (setattr(g, "dim", 1), g.dx.__setitem__(2, -0.5)), "row spacing"),
     (lambda g: setattr(g, "precision", 7), "precision"),
     (lambda g: g.n.__setitem__(0, 2), "4 cells"),
     (lambda g: g.dx.__setitem__(2, -1.0), "dx"),
@@ -132,3 +134,15 @@ def test_pulse_params_struct_matches_header():
     assert (p.envelope, p.sampling, p.fwhm) == (apt.AP_ENV_SGAUSS, apt.AP_SAMPLE_GRID, 30.0)
     q = apt.pulse_params(dispersion=apt.AP_DISP_PLASMA, wp2=0.05, fd=False)
     assert (q.wp2, q.zeta, q.no_fd) == (0.05, 0.0, 1)
+
+
+def test_rows1d_layout():
+    """dim 1: rows of 1-D lines; tiles along x only, one tile row per grid row."""
+    g = _grid()
+    g.dim = 1
+    g.n[0], g.n[1], g.n[2] = 100, 7, 3
+    g.dx[2] = 0.0
+    lay = apt.ap_query_layout(g, [_sp()])
+    assert lay.n_cells == 300
+    assert lay.n_tiles == 4 * 3                  # default 32-cell tiles
+    assert lay.grid_bytes == 9 * 300 * lay.real_bytes
