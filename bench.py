@@ -31,6 +31,12 @@ of d<p_perp^2>/d(beta_f, chirp) over a 32-step window (segments of 8).
 Fourth leg (``small``): the 128 x 64 Gaussian run (32768 electrons, 200 steps)
 in FP64 and FP32; launch-bound, reported for completeness.
 
+Fifth leg (``rows1d``): the reduced-dimensionality series of Sec. III.B as one
+run of 30 independent 1-D rows (z = 0 ... 2.9 lambda, 0.1 lambda apart), 4096
+cells at lambda/20 each, 64 electrons per cell (7.9M) in 0.01 n_c, Gaussian
+D_f = 3 pulse (a0 = 5, w0 = 2.5 lambda, tau = 10 lambda/c) on the rows' axis
+side, FP32, 500 steps.
+
 Optional leg (``--with-large3d``, off by default: about three minutes of host
 input generation): 3-D PIC, 1024 x 512 x 512 cells at lambda/16, 2 electrons
 + 2 protons per cell (1.07e9 particles) in n = 0.01 exp(-r^2/(20 lambda)^2)
@@ -271,6 +277,43 @@ def large3d_leg(args):
     return out
 
 
+def rows1d_leg():
+    import torch
+    from paper_2307_04843_amd import apt, inputs
+    from paper_2307_04843_amd.sim import Simulation
+    dx = 0.05
+    n = (4096, 1, 30)
+    dt = 0.95 * dx
+    e = inputs.plasma(1, n, (dx, dx, 0.1), (0.0, 0.0, 0.0), 64, inputs.density_uniform(0.01), 1.0, 1.0, 7)
+    npart = int(e["u"].shape[1])
+    vg = 1.0 - (1.0 - (dt / dx) ** 2) * (2 * math.pi * dx) ** 2 / 8.0
+    pp = dict(a0=5.0, tau=10.0, x_ref=102.4, t_ref=5.0 + 102.4 / vg, x_f=102.4, w0=2.5, y_c=0.0, z_c=0.0, d_f=3,
+              pol=0, dispersion=0, dx_prop=dx, dt_prop=dt)
+    out = {"workload": "30 rows of 1-D PIC, 4096 cells lambda/20 each, rows 0.1 lambda apart, 64 e per cell "
+                       "(7.9M), 0.01 n_c, Gaussian D_f=3 a0=5 w0=2.5 tau=10, 500 steps", "particles": npart,
+           "steps": 500}
+    sim = Simulation(1, n=n, dx=(dx, dx, 0.1), x_min=(0.0, 0.0, 0.0), t0=100.0, dt=dt, precision="f32",
+                     species=[dict(q=-1.0, m=1.0, state=e)])
+    try:
+        sim.set_pulse("gauss", **pp)
+        sim.step(5)
+        torch.cuda.synchronize()
+        apt.ap_timing_enable(sim.ctx, True)
+        apt.ap_timing_read(sim.ctx, reset=True)
+        a = time.perf_counter()
+        sim.step(500)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - a
+        tm = apt.ap_timing_read(sim.ctx, reset=True)
+        d, _ = sim.diag(allow_numeric=True)
+        out.update({"pushes_per_s": npart * 500 / wall, "ms_per_step": wall * 2.0,
+                    "push_ms_per_launch": tm.ms_push / max(1, tm.n_push),
+                    "n_nonfinite": d.n_nonfinite, "n_fast": d.n_fast})
+    finally:
+        sim.close()
+    return out
+
+
 def small_leg():
     """The 128 x 64 Gaussian run: 32768 electrons, 200 steps, FP64 and FP32."""
     import torch
@@ -469,11 +512,14 @@ METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 
 # launches of the profiled steps.  Valid only for the kernel sources whose
 # digest is recorded here (None once the sources change).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "005a637ff3662fdf43c65ae2da741c3a20b8407f756f5354573d3ee51f9bf411",
-    "fetch_bytes_per_launch": 4.09989e9,
-    "write_bytes_per_launch": 3.98755e9,
+    "sources_sha256": "1042969b0b4e3ad42c9a975f7a140c750449ff9997e2ef5ae2c4cb6683e50f35",
+    "fetch_bytes_per_launch": 4.12217e9,
+    "write_bytes_per_launch": 3.87950e9,
     # SQ_INSTS_VALU x 64 / particles, same runs: VALU lane-ops issued per push
-    "valu_lane_ops_per_push": 600.5,
+    "valu_lane_ops_per_push": 591.1,
+    # SQ_LDS_IDX_ACTIVE / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs), and the bank-conflict share of it
+    "lds_busy_frac": 0.818,
+    "lds_bank_conflict_frac": 0.380,
     "note": "average over the 2000 launches of the default run (calibration copy factors "
             "0.500 fetch, 1.000 write), profiles/push_deposit_2d_lg_4096x1024_f32.md",
 }
@@ -514,6 +560,7 @@ def pic_leg(args):
     traffic = None
     traffic_note = "no counter measurement for the current kernel sources"
     roofline_valu = None
+    roofline_lds = None
     if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_digest():
         tb = MEASURED_TRAFFIC["fetch_bytes_per_launch"] + MEASURED_TRAFFIC["write_bytes_per_launch"]
         traffic = tb / (ms_push * 1e-3) / 1e9
@@ -527,6 +574,11 @@ def pic_leg(args):
                          "per_push": MEASURED_TRAFFIC["valu_lane_ops_per_push"],
                          "note": "VALU lane-ops issued per push counted by rocprofv3 (SQ_INSTS_VALU), "
                                  "non-packed FP32 issue peak"}
+        roofline_lds = {"bound": "lds", "busy_frac": MEASURED_TRAFFIC["lds_busy_frac"],
+                        "bank_conflict_frac_of_busy": MEASURED_TRAFFIC["lds_bank_conflict_frac"],
+                        "note": "share of the kernel's cycles in which the LDS pipe is busy "
+                                "(rocprofv3 SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, first 200 steps): "
+                                "the kernel's first bound"}
     log("FP32: %.3e pushes/s, push kernel %.3f ms/launch, yee %.3f ms, sort %.3f ms"
         % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, tm.n_sort)))
     out = {
@@ -550,6 +602,7 @@ def pic_leg(args):
                      "kernel": "k_push_deposit_2d", "ms_per_launch": ms_push,
                      "bytes_per_launch": bytes_launch},
         "roofline_valu": roofline_valu,
+        "roofline_lds": roofline_lds,
         "kernels_ms_per_step": {"push_deposit": ms_push, "yee": tm.ms_yee / max(1, tm.n_yee),
                                 "sort": tm.ms_sort / max(1, args.steps),
                                 "other": tm.ms_other / max(1, args.steps)},
@@ -619,6 +672,7 @@ def main():
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
+    ap.add_argument("--skip-rows1d", action="store_true")
     ap.add_argument("--with-large3d", action="store_true",
                     help="add the 1024x512x512 3-D leg (about three minutes of input generation)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -654,6 +708,8 @@ def main():
         out["three_d"] = three_d_leg(args)
     if not args.skip_small:
         out["small"] = small_leg()
+    if not args.skip_rows1d:
+        out["rows1d"] = rows1d_leg()
     if args.with_large3d:
         out["large3d"] = large3d_leg(args)
     if not args.skip_cpu:
