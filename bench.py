@@ -456,7 +456,7 @@ def run_adjoint(beam, precision, steps):
         obs.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return dict(forward_s=t1 - t0, backward_s=t2 - t1, grad=p.grad.tolist(), observable=float(obs),
+        return dict(forward_s=t1 - t0, backward_s=t2 - t1, grad=p.grad.tolist(), observable=float(obs.detach()),
                     forward_pushes_per_s=n * steps / (t1 - t0), adjoint_pushes_per_s=n * steps / (t2 - t1),
                     segment=run.segment, checkpoint_gb=run.ckpt.numel() / 1e9)
     finally:

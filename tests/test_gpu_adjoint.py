@@ -46,7 +46,7 @@ def _obs_grad(run, values, proxy_weight=0.0):
     N = u.shape[1]
     L = ((u[1].double() ** 2 + u[2].double() ** 2).sum() + proxy_weight * proxy.sum()) / N
     L.backward()
-    return float(L), p.grad.numpy().copy(), u.detach().double().cpu().numpy(), proxy.detach().cpu().numpy()
+    return float(L.detach()), p.grad.numpy().copy(), u.detach().double().cpu().numpy(), proxy.detach().cpu().numpy()
 
 
 def _oracle_grad(names, values, u_final, proxy_weight, kind="gauss_np", pulse=None, beam=None, rel_h=2e-3):
