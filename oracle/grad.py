@@ -69,26 +69,29 @@ def record_gridded_run(grid, species, prm, n_steps, pulse_on_grid=False):
     return recs
 
 
-def frozen_run(prm, grid, recs, sp0, pulse_on_grid=False):
+def frozen_run(prm, grid, recs, sp0, pulse_on_grid=False, with_proxy=False):
     """One species pushed through the recorded fields (no deposit, no field
-    update).  ``grid`` supplies the geometry; returns the final (pos, u)."""
+    update).  ``grid`` supplies the geometry; returns the final (pos, u), and
+    the emission proxy accumulated from zero with ``with_proxy``."""
     P = pulses.Pulse(prm)
     sp = pic.Species(sp0.q, sp0.m, sp0.pos, sp0.u, sp0.w)
+    proxy = np.zeros(sp.u.shape[1])
     saved = grid.E, grid.B, grid.t
     try:
         for E, B, t in recs:
             grid.E, grid.B, grid.t = E, B, t
-            u_half = pic.push_species(grid, sp, P, pulse_on_grid=pulse_on_grid)
+            u_half, Ep, Bp = pic.push_species(grid, sp, P, pulse_on_grid=pulse_on_grid, with_fields=True)
+            proxy = proxy + pic.emission_proxy(sp.u, u_half, Ep, Bp, grid.dt)
             new = pic.move(grid, sp.pos, u_half)
             sp.u = u_half
             sp.pos = pic.wrap(grid, new)
     finally:
         grid.E, grid.B, grid.t = saved
-    return sp.pos, sp.u
+    return (sp.pos, sp.u, proxy) if with_proxy else (sp.pos, sp.u)
 
 
-def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-6, pulse_on_grid=False):
-    """dL/d(prm[name]), L = sum wu . u_final, through the recorded fields:
+def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-6, pulse_on_grid=False, wp=None):
+    """dL/d(prm[name]), L = sum wu . u_final (+ sum wp proxy_final), through the recorded fields:
     Richardson-extrapolated central differences as in ``gradient``.
 
     L has jumps: a particle that crosses the periodic boundary one step
@@ -102,7 +105,10 @@ def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-6, pulse_on_grid=Fa
     def Lof(v):
         q = dict(prm)
         q[name] = v
-        return float(np.sum(wu * frozen_run(q, grid, recs, sp0, pulse_on_grid)[1]))
+        if wp is None:
+            return float(np.sum(wu * frozen_run(q, grid, recs, sp0, pulse_on_grid)[1]))
+        _, u, pr = frozen_run(q, grid, recs, sp0, pulse_on_grid, with_proxy=True)
+        return float(np.sum(wu * u) + np.sum(wp * pr))
 
     d1 = (Lof(base + h) - Lof(base - h)) / (2 * h)
     d2 = (Lof(base + h / 2) - Lof(base - h / 2)) / h

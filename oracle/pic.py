@@ -66,14 +66,16 @@ class Grid:
 
 
 class Species:
-    """Macroparticles: positions (cell units), momenta u = gamma beta, weights."""
+    """Macroparticles: positions (cell units), momenta u = gamma beta, weights;
+    ``proxy`` (per particle, or None) accumulates the emission proxy."""
 
-    def __init__(self, q, m, pos, u, w):
+    def __init__(self, q, m, pos, u, w, proxy=None):
         self.q = float(q)
         self.m = float(m)
         self.pos = np.array(pos, dtype=float, copy=True)
         self.u = np.array(u, dtype=float, copy=True)
         self.w = np.array(w, dtype=float, copy=True)
+        self.proxy = None if proxy is None else np.array(proxy, dtype=float, copy=True)
 
 
 # ----------------------------------------------------------------------------
@@ -326,10 +328,11 @@ def sample_current(grid, pulse, t):
     return out
 
 
-def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False):
+def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False, with_fields=False):
     """Field evaluation and Boris push of one species at time grid.t.
 
-    Returns u^{n+1/2}; positions are not changed.
+    Returns u^{n+1/2} (and the total E, B at the particles with
+    ``with_fields``); positions are not changed.
     """
     if pulse is not None and pulse_on_grid:
         E1g, B1g = sample_pulse(grid, pulse)
@@ -340,7 +343,8 @@ def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False):
             E, B = gather(grid, sp.pos)
         finally:
             grid.E, grid.B = saved
-        return boris(sp.u, E, B, sp.q / sp.m, grid.dt)
+        u1 = boris(sp.u, E, B, sp.q / sp.m, grid.dt)
+        return (u1, E, B) if with_fields else u1
     E2, B2 = gather(grid, sp.pos)
     if pulse is not None:
         X, Y, Z = lab_positions(grid, sp.pos, pulse.q_slice)
@@ -349,7 +353,8 @@ def push_species(grid, sp, pulse, n_steps_done=None, pulse_on_grid=False):
         B = B1 + B2
     else:
         E, B = E2, B2
-    return boris(sp.u, E, B, sp.q / sp.m, grid.dt)
+    u1 = boris(sp.u, E, B, sp.q / sp.m, grid.dt)
+    return (u1, E, B) if with_fields else u1
 
 
 def move(grid, pos, u_half):
@@ -374,8 +379,9 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
     """One step of the loop of Fig. 1.
 
     For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n (E1, B1 at the
-    particle, or sampled on the grid with ``pulse_on_grid``); Boris push;
-    move; deposit J^{n+1/2}.  With an analytic current (Sec. IV) J1 at
+    particle, or sampled on the grid with ``pulse_on_grid``); Boris push
+    (plus the emission proxy of the step for species that carry one); move;
+    deposit J^{n+1/2}.  With an analytic current (Sec. IV) J1 at
     t^{n+1/2} is subtracted: E2, B2 are driven by J - J1.  Then the Yee update
     of E2, B2.  J holds the Yee source (J, or J - J1) afterwards.  Returns per-species (pos_unwrapped_new,)
     for diagnostics.
@@ -384,7 +390,9 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
         grid.J[c][...] = 0.0
     moved = []
     for sp in species:
-        u_half = push_species(grid, sp, pulse, pulse_on_grid=pulse_on_grid)
+        u_half, E, B = push_species(grid, sp, pulse, pulse_on_grid=pulse_on_grid, with_fields=True)
+        if sp.proxy is not None:
+            sp.proxy = sp.proxy + emission_proxy(sp.u, u_half, E, B, grid.dt)
         new = move(grid, sp.pos, u_half)
         disp = np.abs(new - sp.pos)
         if np.any(disp >= 1.0):

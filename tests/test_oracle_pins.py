@@ -1032,24 +1032,29 @@ def test_1d_row_test_particle_equals_gridless_plane_wave():
     """1D-3V: a zero-weight electron on a 1-D row driven by a PLANE pulse
     (no transverse dependence) moves exactly as the gridless test particle:
     the same u (all three components) at every step as the pulse passes,
-    and the same x after 300 steps."""
+    the same x after 300 steps and the same emission proxy."""
     dxl = 0.05
     dtl = units.default_dt(dxl, 1)
     pp = dict(type="plane", a0=1.0, tau=10.0, x_ref=0.0, t_ref=6.0, pol=0, dispersion=units.DISP_PAPER2,
               dx_prop=dxl, dt=dtl)
     P = pulses.Pulse(pp)
     g = pic.Grid(1, (64, 1, 1), (dxl * L,) * 3, dtl * L, (0.0, 0.0, 0.0), t0=0.0)
-    sp = pic.Species(-1.0, 1.0, np.array([[10.3], [0.0], [0.0]]), np.zeros((3, 1)), np.zeros(1))
+    sp = pic.Species(-1.0, 1.0, np.array([[10.3], [0.0], [0.0]]), np.zeros((3, 1)), np.zeros(1),
+                     proxy=np.zeros(1))
     X = np.array([[10.3 * dxl * L], [P.q_slice], [0.0]])
     u = np.zeros((3, 1))
+    proxy = np.zeros(1)
     umax = 0.0
     for n in range(300):
         t = g.t
         pic.step(g, [sp], P)
-        X, u = pic.gridless_step(t, g.dt, X, u, -1.0, P)
+        X, u, dp = pic.gridless_step(t, g.dt, X, u, -1.0, P, with_proxy=True)
+        proxy = proxy + dp
         umax = max(umax, float(np.abs(u).max()))
         assert np.allclose(sp.u, u, rtol=0, atol=1e-12)
     assert umax > 0.5
+    # the emission proxy accumulated on the grid equals the gridless one
+    assert proxy[0] > 0 and abs(sp.proxy[0] - proxy[0]) <= 1e-12 * proxy[0]
     xg = (sp.pos[0] + 64 * np.round((X[0] / (dxl * L) - sp.pos[0]) / 64)) * dxl * L
     assert abs(float(xg[0] - X[0, 0])) < 1e-10 * L
     assert max(np.abs(e).max() for e in g.E) == 0.0
