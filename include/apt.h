@@ -76,6 +76,8 @@ typedef int32_t ap_status;
 
 /* ap_grid_desc options */
 #define AP_GRID_PULSE_ON_GRID 0x1  /* allow AP_SAMPLE_GRID (reserves workspace)  */
+#define AP_GRID_PROXY         0x2  /* gridded species may carry an emission
+                                      proxy (reserves its re-sort workspace)  */
 
 /* Temporal envelopes (Sec. II.A sin^2 form; Sec. II.B super-Gaussian runs). */
 #define AP_ENV_SIN2         0   /* a0 sin^2(pi eta / tau) on [0, tau]           */
@@ -151,8 +153,10 @@ typedef struct ap_species_desc {
  *   u[3]      real momenta gamma*beta (stored at half steps, u^{n-1/2})
  *   w         real weight: density contribution per cell, in n_c
  *   id        int32 particle id, carried through re-sorts
- *   proxy     dim 0 only, optional (NULL): two reals per particle
- *             (sum and compensation) accumulating the emission proxy.
+ *   proxy     optional (NULL): two reals per particle, interleaved
+ *             (sum s, compensation c; the proxy is s - c), accumulating
+ *             the emission proxy; gridded runs need AP_GRID_PROXY and
+ *             re-sort it with the particle.
  * Unused pointers must be NULL. */
 typedef struct ap_particles {
     int32_t *cell;
@@ -325,12 +329,13 @@ ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segmen
  * is x_f (x0_ff for the flying focus).  Writes n_params FP64 derivatives to
  * dL_dparams (host) in lambda units.  Synchronises the stream.
  *
- * Gridded runs (dim 2, 3) take the frozen-grid reading: the E2, B2 that each
- * push gathered are a recorded external field, so the gradient follows the
- * parameters through the particles' own analytic fields and through the
+ * Gridded runs (dim 1, 2, 3) take the frozen-grid reading: the E2, B2 that
+ * each push gathered are a recorded external field, so the gradient follows
+ * the parameters through the particles' own analytic fields and through the
  * position dependence of the gather, not through the plasma's response on
- * the grid.  There dL_du is indexed by particle id (the species' ids must be
- * a permutation of 0..n-1, else AP_E_ARG), dL_dproxy must be NULL, and the
+ * the grid.  There dL_du and dL_dproxy are indexed by particle id (the
+ * species' ids must be a permutation of 0..n-1, else AP_E_ARG), dL_dproxy
+ * needs a species that carries a proxy (else AP_E_ARG), and the
  * pulse must be evaluated per particle (AP_SAMPLE_PARTICLES, else
  * AP_E_UNSUPPORTED).  The reverse sweep replays each segment with the full
  * loop (push, deposit, field update), then restores the final state; the

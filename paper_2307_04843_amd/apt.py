@@ -21,6 +21,7 @@ AP_STEP_CONTINUITY, AP_STEP_NO_YEE, AP_STEP_RECORD = 0x1, 0x2, 0x4
 AP_DIAG_PARTICLES, AP_DIAG_FIELDS = 0x1, 0x2
 AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5)
 AP_GRID_PULSE_ON_GRID = 0x1
+AP_GRID_PROXY = 0x2
 AP_ENV_SIN2, AP_ENV_SGAUSS = 0, 1
 AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID = 0, 1
 ENVELOPES = {"sin2": AP_ENV_SIN2, "sgauss": AP_ENV_SGAUSS}

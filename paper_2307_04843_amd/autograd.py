@@ -8,10 +8,11 @@ checkpoint recording and returns the final momenta u (3, N) and the emission
 proxies (N,).  Its backward calls the library's hand-written adjoint
 (ap_backward) and returns dL/dparams.
 
-``GriddedRun`` does the same for a gridded run (dim 2 or 3, every species,
-full loop) and one species' final momenta, ordered by particle id, in the
-frozen-grid reading: the gradient treats the E2, B2 each push gathered as a
-recorded external field.  Its proxy output is identically zero.
+``GriddedRun`` does the same for a gridded run (dim 1, 2 or 3, every species,
+full loop) and one species' final momenta and proxies, ordered by particle id,
+in the frozen-grid reading: the gradient treats the E2, B2 each push gathered
+as a recorded external field.  Without ``proxy=True`` its proxy output is
+identically zero.
 """
 import math
 
@@ -70,7 +71,7 @@ class GridlessRun:
         u = torch.stack([t.clone() for t in a["u"]])
         if a["proxy"] is not None:
             pr = a["proxy"].view(-1, 2)
-            proxy = pr[:, 0].double() + pr[:, 1].double()
+            proxy = pr[:, 0].double() - pr[:, 1].double()   # sum minus its compensation
         else:
             proxy = torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
         return u, proxy
@@ -99,9 +100,10 @@ class GriddedRun:
 
     def __init__(self, dim, n, dx, x_min, species, pulse_kind, pulse_params, param_names, n_steps, t0=0.0,
                  dt=0.0, precision="f32", fields=None, species_index=0, segment=None, tile=(0, 0, 0),
-                 sort_every=0):
+                 sort_every=0, proxy=False):
         self.sim = Simulation(dim, n=n, dx=dx, x_min=x_min, t0=t0, dt=dt, precision=precision, tile=tile,
-                              sort_every=sort_every, species=species)
+                              sort_every=sort_every, species=species, proxy=proxy)
+        self.proxy = bool(proxy)
         self.kind = pulse_kind
         self.base = dict(pulse_params)
         self.param_names = list(param_names)
@@ -130,6 +132,8 @@ class GriddedRun:
                 if a["off"][k] is not None:
                     a["off"][k].copy_(ini["off"][k])
                 a["u"][k].copy_(ini["u"][k])
+            if a["proxy"] is not None:
+                a["proxy"].zero_()
         # a fresh context rewinds the clock and zeroes the grid
         apt.ap_destroy(self.sim.ctx)
         self.sim.ctx = apt.ap_init(self.sim.grid_desc, self.sim.sp_desc, self.sim.buffers,
@@ -151,16 +155,24 @@ class GriddedRun:
         a = self.sim.arrays[self.sp]
         u = torch.stack(a["u"])
         out = torch.empty_like(u)
-        out[:, a["id"].long()] = u
-        return out, torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
+        idx = a["id"].long()
+        out[:, idx] = u
+        proxy = torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
+        if a["proxy"] is not None:
+            pr = a["proxy"].view(-1, 2)
+            proxy[idx] = pr[:, 0].double() - pr[:, 1].double()   # sum minus its compensation
+        return out, proxy
 
     def backward(self, grad_u, grad_proxy=None):
         n = self.sim.sp_desc[self.sp].n
         gu = grad_u if grad_u is not None else torch.zeros((3, n), device=self.sim.device)
         gu = gu.to(device=self.sim.device, dtype=self.sim.dtype).contiguous()
+        gp = None
+        if self.proxy and grad_proxy is not None:
+            gp = grad_proxy.to(device=self.sim.device, dtype=self.sim.dtype).contiguous()   # by particle id
         ids = [PARAM_IDS[nm] for nm in self.param_names]
         torch.cuda.synchronize(self.sim.device)
-        return apt.ap_backward(self.sim.ctx, self.sp, gu.data_ptr(), None, ids)
+        return apt.ap_backward(self.sim.ctx, self.sp, gu.data_ptr(), gp.data_ptr() if gp is not None else None, ids)
 
     def close(self):
         self.sim.close()

@@ -241,21 +241,23 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
                 axis_stencil(ic[ax], ov[ax], true, a.G.n[ax], sh[ax]);
             }
             const T idx_[3] = {T(1.0 / a.dx[0]), T(1.0 / a.dx[1]), T(1.0 / a.dx[2])};
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const int c = f % 3;
-                const bool isE = f < 3;
-                const AxisStencil<T> &sx = (c == 0) == isE ? sh[0] : sn[0];
-                const AxisStencil<T> &sy = (c == 1) == isE ? sh[1] : sn[1];
-                const AxisStencil<T> &sz = (c == 2) == isE ? sh[2] : sn[2];
+            // each field with its own stencils, written out so that no stencil
+            // is selected at run time (that selection put them in scratch memory)
+            auto add = [&](DN &F8, const T *F, const AxisStencil<T> &sx, const AxisStencil<T> &sy,
+                           const AxisStencil<T> &sz) {
                 T v, gr[3];
-                gather_grad<T, GD>(a.G.F[f], sx, sy, sz, a.G.n[0], a.G.n[1], v, gr);
-                DN &F8 = isE ? E8[c] : B8[c];
+                gather_grad<T, GD>(F, sx, sy, sz, a.G.n[0], a.G.n[1], v, gr);
                 F8.v += v;
                 F8.d[0] += gr[0] * idx_[0];
                 if (GD == 3) F8.d[1] += gr[1] * idx_[1];
                 if (GD >= 2) F8.d[2] += gr[2] * idx_[2];
-            }
+            };
+            add(E8[0], a.G.F[0], sh[0], sn[1], sn[2]);
+            add(E8[1], a.G.F[1], sn[0], sh[1], sn[2]);
+            add(E8[2], a.G.F[2], sn[0], sn[1], sh[2]);
+            add(B8[0], a.G.F[3], sn[0], sh[1], sh[2]);
+            add(B8[1], a.G.F[4], sh[0], sn[1], sh[2]);
+            add(B8[2], a.G.F[5], sh[0], sh[1], sn[2]);
         }
 
         // Boris Jacobian: tangents over (u0, E, B)
@@ -285,8 +287,8 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
             for (int c = 0; c < 3; ++c) lu1[c] += a.dt * (lx[c] - vv[c] * vl) / g1;
         }
         double lu0[3] = {0.0, 0.0, 0.0}, lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
-        if (GD == 0 && a.lam_proxy) {
-            const double lp = (double)a.lam_proxy[p];
+        if (a.lam_proxy) {
+            const double lp = (double)a.lam_proxy[lid];
             if (lp != 0.0) {
                 using D12 = Dual<T, 12>;
                 D12 q0[3], q1[3], qe[3], qb[3];

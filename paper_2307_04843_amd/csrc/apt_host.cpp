@@ -48,6 +48,7 @@ struct RunShape {
     int64_t np[kMaxSpecies] = {0, 0, 0, 0};
     double q[kMaxSpecies] = {0, 0, 0, 0};
     double m[kMaxSpecies] = {1, 1, 1, 1};
+    bool has_proxy[kMaxSpecies] = {false, false, false, false};   // gridded: species carries a proxy
 };
 
 struct WorkLayout {
@@ -58,7 +59,7 @@ struct WorkLayout {
     size_t slot_off[kMaxSpecies] = {};     // species block offsets inside a slot
     size_t count[kMaxSpecies] = {}, start[kMaxSpecies] = {}, rank[kMaxSpecies] = {};
     size_t alt_cell[kMaxSpecies] = {}, alt_off[kMaxSpecies][3] = {}, alt_u[kMaxSpecies][3] = {};
-    size_t alt_w[kMaxSpecies] = {}, alt_id[kMaxSpecies] = {};
+    size_t alt_w[kMaxSpecies] = {}, alt_id[kMaxSpecies] = {}, alt_proxy[kMaxSpecies] = {};
 };
 
 constexpr int kDiagBlocks = 512;
@@ -132,9 +133,11 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
-    if (g->options & ~AP_GRID_PULSE_ON_GRID) return fail(AP_E_ARG, "unknown grid option bits");
+    if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY)) return fail(AP_E_ARG, "unknown grid option bits");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
+    if ((g->options & AP_GRID_PROXY) && s.dim == 0)
+        return fail(AP_E_ARG, "AP_GRID_PROXY needs a grid (gridless runs always accept a proxy)");
     s.options = g->options;
     // default re-sort interval: 2-D tiles carry a two-cell drift margin; 3-D
     // tiles none (LDS budget), so 3-D re-sorts every step (a push that leaves
@@ -196,6 +199,8 @@ WorkLayout make_layout(const RunShape &s) {
             }
             L.alt_w[i] = take(N * s.real);
             L.alt_id[i] = take(N * 4);
+            // the proxy's (sum, compensation) pair follows its particle through re-sorts
+            if (s.options & AP_GRID_PROXY) L.alt_proxy[i] = take(N * 2 * s.real);
         }
     }
     if (s.dim == 0) {
@@ -219,8 +224,10 @@ WorkLayout make_layout(const RunShape &s) {
 // Checkpoint buffer of a gridded run (frozen-grid adjoint):
 //   [adjoint state: 6 x n_max FP64][gradient partials]
 //   [final-state slot][ceil(n/K) checkpoint slots][K replay slots]
-// A checkpoint slot holds every species (cell, id, offsets, u, w) and E2, B2;
-// a replay slot holds E2, B2 and the species being differentiated (no w).
+// A checkpoint slot holds every species (cell, id, offsets, u, w, and the
+// proxy pair of a species that carries one) and E2, B2; a replay slot holds
+// E2, B2 and the species being differentiated (no w, no proxy: the proxy
+// enters no step, so its adjoint is constant).
 struct GridCkpt {
     size_t lam[6] = {}, partial = 0, fixed = 0;
     int blocks = 0;
@@ -233,7 +240,8 @@ struct GridCkpt {
 size_t sp_block_bytes(const RunShape &s, int i, bool with_w) {
     const size_t N = (size_t)s.np[i];
     const size_t nact = s.dim == 3 ? 3 : 2;
-    return align_up(N * 8 + N * s.real * (nact + 3 + (with_w ? 1 : 0)), 256);
+    const size_t npr = (with_w && s.has_proxy[i]) ? 2 : 0;
+    return align_up(N * 8 + N * s.real * (nact + 3 + (with_w ? 1 : 0) + npr), 256);
 }
 
 GridCkpt grid_ckpt(const RunShape &s) {
@@ -368,7 +376,8 @@ template <typename T>
 ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
                         double *out);
 template <typename T>
-ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const int32_t *ids, int np_, double *out);
+ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                        double *out);
 
 double laguerre_host(int n, int a, double x) {
     double l0 = 1.0, l1 = 1.0 + a - x;
@@ -427,6 +436,12 @@ ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int3
                 okp = okp && p.cell && p.off[0] && p.id && (s.dim == 1 || p.off[2]) && (s.dim != 3 || p.off[1]);
             }
             if (!okp) return fail(AP_E_ARG, "species " + std::to_string(i) + ": a required particle array is NULL");
+        }
+        for (int i = 0; i < n_species; ++i) {
+            if (s.dim == 0 || !buffers->sp[i].proxy) continue;
+            if (!(s.options & AP_GRID_PROXY))
+                return fail(AP_E_ARG, "species " + std::to_string(i) + ": a gridded proxy needs AP_GRID_PROXY");
+            s.has_proxy[i] = s.np[i] > 0;
         }
         ap_ctx *c = new (std::nothrow) ap_ctx;
         if (!c) return fail(AP_E_NOMEM, "context allocation failed");
@@ -800,7 +815,8 @@ ap_status ap_checkpoint_bytes(const ap_ctx *c, int64_t n_steps, int32_t segment,
 ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void *dl_dproxy,
                       const int32_t *param_ids, int32_t n_params, double *out) {
     if (!c) return fail(AP_E_ARG, "context is NULL");
-    if (c->s.dim > 0 && dl_dproxy) return fail(AP_E_ARG, "gridded runs carry no emission proxy");
+    if (c->s.dim > 0 && dl_dproxy && (species < 0 || species >= c->s.nsp || !c->s.has_proxy[species]))
+        return fail(AP_E_ARG, "the species carries no emission proxy");
     if (c->s.dim > 0 && c->P.sampling == AP_SAMPLE_GRID)
         return fail(AP_E_UNSUPPORTED, "the adjoint of gridded runs needs the pulse evaluated per particle");
     if (c->rec_n <= 0) return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
@@ -816,8 +832,8 @@ ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void 
     if (c->P.type == PT_NONE) return fail(AP_E_STATE, "no pulse set");
     try {
         if (c->s.dim > 0)
-            return c->s.prec == AP_F64 ? backward_grid<double>(c, species, dl_du, param_ids, n_params, out)
-                                       : backward_grid<float>(c, species, dl_du, param_ids, n_params, out);
+            return c->s.prec == AP_F64 ? backward_grid<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
+                                       : backward_grid<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
         return c->s.prec == AP_F64 ? backward_impl<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
                                    : backward_impl<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
     } catch (...) {
@@ -1026,7 +1042,7 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
 
 template <typename T> struct SpBlock {
     int32_t *cell, *id;
-    T *off[3], *u[3], *w;
+    T *off[3], *u[3], *w, *proxy;
 };
 
 // Species i's arrays inside a slot block that starts at base.
@@ -1045,6 +1061,8 @@ template <typename T> SpBlock<T> sp_block(unsigned char *base, const RunShape &s
         r += N;
     }
     b.w = with_w ? r : nullptr;
+    if (b.w) r += N;
+    b.proxy = (with_w && s.has_proxy[i]) ? r : nullptr;
     return b;
 }
 
@@ -1058,6 +1076,7 @@ template <typename T> SpBlock<T> live_block(ap_ctx *c, int i) {
         b.u[a] = static_cast<T *>(p.u[a]);
     }
     b.w = static_cast<T *>(p.w);
+    b.proxy = c->s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
     return b;
 }
 
@@ -1071,6 +1090,9 @@ template <typename T> ap_status copy_block(ap_ctx *c, const SpBlock<T> &dst, con
         HIPCHK(hipMemcpyAsync(dst.u[a], src.u[a], N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
     }
     if (w) HIPCHK(hipMemcpyAsync(dst.w, src.w, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
+    if (w && dst.proxy && src.proxy)
+        HIPCHK(hipMemcpyAsync(dst.proxy, src.proxy, 2 * N * sizeof(T), hipMemcpyDeviceToDevice, c->stream),
+               "checkpoint copy");
     return AP_OK;
 }
 
@@ -1118,7 +1140,8 @@ template <typename T> ap_status save_replay(ap_ctx *c, unsigned char *slot, int 
 // of every step; the adjoint steps then run backwards over those slots.  The
 // state after the last recorded step is put back at the end.
 template <typename T>
-ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const int32_t *ids, int np_, double *out) {
+ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                        double *out) {
     const RunShape &s = c->s;
     const GridCkpt G = grid_ckpt(s);
     const int n = (int)s.np[sp];
@@ -1188,7 +1211,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const int32_t *ids
             a.G.fnxy = fnxy;
             a.G.q_slice = c->P.q_slice;
             a.dim = s.dim;
-            a.lam_proxy = nullptr;
+            a.lam_proxy = static_cast<const T *>(dl_dproxy);   // by particle id, like dl_du
             a.partial = partial;
             for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
             a.n = n;
@@ -1269,6 +1292,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sc.w_dst = c->wp<T>(L.alt_w[i]);
             sc.id_src = p.id;
             sc.id_dst = c->wp<int32_t>(L.alt_id[i]);
+            sc.proxy_src = s.has_proxy[i] ? static_cast<const T *>(p.proxy) : nullptr;
+            sc.proxy_dst = s.has_proxy[i] ? c->wp<T>(L.alt_proxy[i]) : nullptr;
             sc.rank = rank;
             sc.start = start;
             sc.ncell = (uint32_t)s.ncell;
@@ -1315,6 +1340,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         io.w_in = from_alt ? c->wp<T>(L.alt_w[i]) : io.w_out;
         io.id_in = from_alt ? c->wp<int32_t>(L.alt_id[i]) : p.id;
         io.copy_static = from_alt ? 1 : 0;
+        io.proxy_out = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
+        io.proxy_in = s.has_proxy[i] && from_alt ? c->wp<T>(L.alt_proxy[i]) : io.proxy_out;
         io.tile_start = c->wp<int32_t>(L.start[i]);
         io.n = (int)s.np[i];
         io.q_over_m = s.q[i] / s.m[i];

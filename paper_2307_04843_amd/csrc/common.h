@@ -135,4 +135,28 @@ AP_D double wave_sum(double v) {
     return v;
 }
 
+// Emission proxy of one push (Lienard power without its 2 r_e/3 constant):
+// gamma^2 [ |E + beta x B|^2 - (beta . E)^2 ] dt with u_bar = (u0 + u1)/2,
+// added to a compensated pair (sum, compensation) read from src[0..1] and
+// written to dst[0..1].
+template <typename T>
+AP_D void proxy_accumulate(const T *src, T *dst, const T u0[3], const T u1[3], const T E[3], const T B[3], T dt) {
+    const T bx = T(0.5) * (u0[0] + u1[0]), by = T(0.5) * (u0[1] + u1[1]), bz = T(0.5) * (u0[2] + u1[2]);
+    const T gb = sqrt_r<T>(T(1) + bx * bx + by * by + bz * bz);
+    const T igb = T(1) / gb;
+    const T vx = bx * igb, vy = by * igb, vz = bz * igb;
+    const T fx = E[0] + (vy * B[2] - vz * B[1]);
+    const T fy = E[1] + (vz * B[0] - vx * B[2]);
+    const T fz = E[2] + (vx * B[1] - vy * B[0]);
+    const T ve = vx * E[0] + vy * E[1] + vz * E[2];
+    const T inc = gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
+    const T s = src[0];
+    T cmp = src[1];
+    const T y = inc - cmp;
+    const T tsum = s + y;
+    cmp = (tsum - s) - y;
+    dst[0] = tsum;
+    dst[1] = cmp;
+}
+
 }  // namespace apt

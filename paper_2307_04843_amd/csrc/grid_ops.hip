@@ -378,6 +378,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterAr
     }
     a.w_dst[d] = a.w_src[p];
     a.id_dst[d] = a.id_src[p];
+    if (a.proxy_src) {
+        a.proxy_dst[2 * d] = a.proxy_src[2 * p];
+        a.proxy_dst[2 * d + 1] = a.proxy_src[2 * p + 1];
+    }
 }
 
 template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStream_t s) {
@@ -425,7 +429,8 @@ template <typename T> __global__ __launch_bounds__(256) void k_diag_particles(Di
         v[4] += w * ux * ux; v[5] += w * uy * uy; v[6] += w * uz * uz;
         v[7] += w * g;
         v[8] += w * (g - 1.0);
-        if (a.proxy) v[9] += (double)a.proxy[2 * p] + (double)a.proxy[2 * p + 1];
+        // compensated pair: the sum carries the compensation's error with the opposite sign
+        if (a.proxy) v[9] += (double)a.proxy[2 * p] - (double)a.proxy[2 * p + 1];
     }
     block_reduce_store<kDiagVals>(v, a.partial + (size_t)blockIdx.x * kDiagVals);
 }

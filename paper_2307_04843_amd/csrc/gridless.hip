@@ -51,23 +51,8 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_gridless(
     uz = umz + sf * (upx * ty - upy * tx) + kap * E[2];
 
     if (a.proxy) {
-        // Lienard-type radiated-power proxy with u_bar = (u^{n-1/2} + u^{n+1/2})/2:
-        // gamma^2 [ |E + beta x B|^2 - (beta . E)^2 ] dt, summed with compensation.
-        const T bx_ = T(0.5) * (u0x + ux), by_ = T(0.5) * (u0y + uy), bz_ = T(0.5) * (u0z + uz);
-        const T gb = sqrt_r<T>(T(1) + bx_ * bx_ + by_ * by_ + bz_ * bz_);
-        const T igb = T(1) / gb;
-        const T vx = bx_ * igb, vy = by_ * igb, vz = bz_ * igb;
-        const T fx = E[0] + (vy * B[2] - vz * B[1]);
-        const T fy = E[1] + (vz * B[0] - vx * B[2]);
-        const T fz = E[2] + (vx * B[1] - vy * B[0]);
-        const T ve = vx * E[0] + vy * E[1] + vz * E[2];
-        const T inc = gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * T(a.dt);
-        T s = a.proxy[2 * p], cmp = a.proxy[2 * p + 1];
-        const T y = inc - cmp;
-        const T tsum = s + y;
-        cmp = (tsum - s) - y;
-        a.proxy[2 * p] = tsum;
-        a.proxy[2 * p + 1] = cmp;
+        const T u0[3] = {u0x, u0y, u0z}, u1[3] = {ux, uy, uz};
+        proxy_accumulate<T>(a.proxy + 2 * p, a.proxy + 2 * p, u0, u1, E, B, T(a.dt));
     }
 
     const T ign = rsqrt_r<T>(T(1) + ux * ux + uy * uy + uz * uz);

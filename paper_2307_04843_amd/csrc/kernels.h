@@ -27,6 +27,8 @@ template <typename T> struct SpeciesIO {
     T *u_out[3];
     T *w_out;
     int32_t *id_out;
+    const T *proxy_in;           // emission proxy (sum, compensation) per particle, or null
+    T *proxy_out;
     const int32_t *tile_start;   // [n_tiles + 1]
     int32_t copy_static;         // write w and id (source != destination)
     int32_t n;
@@ -190,6 +192,7 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, in
 template <typename T> struct ScatterArgs {
     const int32_t *cell_src; const T *off_src[3]; const T *u_src[3]; const T *w_src; const int32_t *id_src;
     int32_t *cell_dst; T *off_dst[3]; T *u_dst[3]; T *w_dst; int32_t *id_dst;
+    const T *proxy_src; T *proxy_dst;   // 2 per particle, or null
     const int32_t *rank;
     const int32_t *start;
     uint32_t ncell;

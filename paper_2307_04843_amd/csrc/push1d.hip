@@ -31,7 +31,7 @@ template <typename T> AP_D void place4_1d(int o, const T w[3], T out[4]) {
 
 AP_D int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-template <typename T, int PT, bool INPLACE>
+template <typename T, int PT, bool INPLACE, bool PROXY>
 __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int RX = a.reg[0];
@@ -96,6 +96,10 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
                 S.off_out[0][p] = offx;
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
                 if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+                if (PROXY && !INPLACE && S.proxy_out) {
+                    S.proxy_out[2 * p] = S.proxy_in[2 * p];
+                    S.proxy_out[2 * p + 1] = S.proxy_in[2 * p + 1];
+                }
                 continue;
             }
             const int i = cell - prow * nx;
@@ -145,6 +149,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
             const T Bx = b1[0] + f[3], By = b1[1] + f[4], Bz = b1[2] + f[5];
 
             // ---- relativistic Boris push
+            const T u0x = ux, u0y = uy, u0z = uz;
             const T umx = ux + kap * Ex, umy = uy + kap * Ey, umz = uz + kap * Ez;
             const T ig = rsqrt_r<T>(T(1) + umx * umx + umy * umy + umz * umz);
             const T tx_ = kap * Bx * ig, ty_ = kap * By * ig, tz_ = kap * Bz * ig;
@@ -155,6 +160,14 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
             ux = umx + sf * (upy * tz_ - upz * ty_) + kap * Ex;
             uy = umy + sf * (upz * tx_ - upx * tz_) + kap * Ey;
             uz = umz + sf * (upx * ty_ - upy * tx_) + kap * Ez;
+            if constexpr (PROXY) {
+                if (S.proxy_out) {
+                    const T uv0[3] = {u0x, u0y, u0z}, uv1[3] = {ux, uy, uz};
+                    const T Ev[3] = {Ex, Ey, Ez}, Bv[3] = {Bx, By, Bz};
+                    proxy_accumulate<T>((INPLACE ? S.proxy_out : S.proxy_in) + 2 * p, S.proxy_out + 2 * p, uv0, uv1,
+                                        Ev, Bv, T(a.dt));
+                }
+            }
 
             // ---- move along x
             const T ign = rsqrt_r<T>(T(1) + ux * ux + uy * uy + uz * uz);
@@ -242,10 +255,17 @@ static hipError_t launch1d(const PushArgs<T> &a, int threads, hipStream_t s) {
     const size_t lds = align_lds(6 * rx * sizeof(T)) + 3 * rx * sizeof(double);
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
-    if (a.sp[0].copy_static == 0)
-        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, true>), dim3(blocks), dim3(threads), lds, s, a);
+    bool proxy = false;
+    for (int k = 0; k < a.nsp; ++k) proxy = proxy || a.sp[k].proxy_out != nullptr;
+    const bool inplace = a.sp[0].copy_static == 0;
+    if (inplace && !proxy)
+        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, true, false>), dim3(blocks), dim3(threads), lds, s, a);
+    else if (!proxy)
+        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, false, false>), dim3(blocks), dim3(threads), lds, s, a);
+    else if (inplace)
+        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, true, true>), dim3(blocks), dim3(threads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, false>), dim3(blocks), dim3(threads), lds, s, a);
+        hipLaunchKernelGGL((k_push_deposit_1d<T, PT, false, true>), dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 

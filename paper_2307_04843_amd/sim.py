@@ -47,7 +47,8 @@ class Simulation:
         g.t0 = float(t0)
         g.dt = float(dt)
         g.sort_every = int(sort_every)
-        g.options = apt.AP_GRID_PULSE_ON_GRID if pulse_on_grid else 0
+        g.options = ((apt.AP_GRID_PULSE_ON_GRID if pulse_on_grid else 0)
+                     | (apt.AP_GRID_PROXY if (proxy and dim > 0) else 0))
         self.grid_desc = g
         self.sp_desc = []
         for sp in species:
@@ -84,7 +85,7 @@ class Simulation:
             arr["w"] = _dev(st["w"], self.np_dtype, dev)
             arr["id"] = torch.arange(N, dtype=torch.int32, device=dev)
             arr["proxy"] = (torch.zeros(2 * N, dtype=self.dtype, device=dev)
-                            if (proxy and dim == 0) else None)
+                            if proxy else None)
             p = bufs.sp[i]
             if dim == 0:
                 for a in range(3):
@@ -154,7 +155,7 @@ class Simulation:
         out["w"] = a["w"].cpu().numpy()[order]
         if a["proxy"] is not None:
             pr = a["proxy"].cpu().numpy().reshape(-1, 2)
-            out["proxy"] = (pr[:, 0].astype(np.float64) + pr[:, 1])[order]
+            out["proxy"] = (pr[:, 0].astype(np.float64) - pr[:, 1])[order]   # sum minus its compensation
         return out
 
     def close(self):

@@ -69,8 +69,9 @@ def make_case(dim=2, n=(70, 1, 40), dxl=0.05, x_min=(48.0, 0.0, 4.8), t0_steps=1
     return dict(dim=dim, n=n, dx=dx, x_min=x_min, t0=t0, dt=dt, species=sp, fields=fields, pulse=pp)
 
 
-def oracle_state(case):
-    """Oracle Grid, Species list and Pulse for a case (internal units)."""
+def oracle_state(case, proxy=False):
+    """Oracle Grid, Species list and Pulse for a case (internal units); with
+    ``proxy`` every species accumulates the emission proxy from zero."""
     dim = case["dim"]
     n = case["n"]
     g = pic.Grid(dim, n, tuple(d * L for d in case["dx"]), case["dt"] * L,
@@ -88,7 +89,8 @@ def oracle_state(case):
         if dim == 3:
             pos[1] = ((cell // nx) % ny) + st["off"][1].astype(float)
         pos[2] = (cell // (nx * ny)) + st["off"][2].astype(float)
-        sps.append(pic.Species(sp["q"], sp["m"], pos, st["u"].astype(float), st["w"].astype(float)))
+        sps.append(pic.Species(sp["q"], sp["m"], pos, st["u"].astype(float), st["w"].astype(float),
+                               proxy=np.zeros(cell.size) if proxy else None))
     P = pulses.Pulse(case["pulse"]) if case["pulse"] is not None else None
     return g, sps, P
 
@@ -112,11 +114,11 @@ def periodic_diff(a, b, n):
     return d - n * np.round(d / n)
 
 
-def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0, pulse_on_grid=False):
+def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0, pulse_on_grid=False, proxy=False):
     from paper_2307_04843_amd.sim import Simulation
     sim = Simulation(case["dim"], n=case["n"], dx=case["dx"], x_min=case["x_min"], t0=case["t0"],
                      dt=case["dt"], precision=precision, tile=tile, sort_every=sort_every,
-                     species=case["species"], pulse_on_grid=pulse_on_grid)
+                     species=case["species"], pulse_on_grid=pulse_on_grid, proxy=proxy)
     E, B, _ = sim.field_views()
     import torch
     for k in range(3):

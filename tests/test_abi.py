@@ -124,6 +124,21 @@ def test_pulse_on_grid_option_reserves_workspace():
         apt.ap_query_layout(g0, [_sp()])
 
 
+def test_proxy_option_reserves_workspace():
+    """AP_GRID_PROXY reserves the re-sort copy of each species' (sum,
+    compensation) pairs; gridless runs reject the bit (they always take one)."""
+    g = _grid()
+    base = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
+    g.options = apt.AP_GRID_PROXY
+    more = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
+    assert more >= base + 2 * 2048 * 4
+    g0 = _grid(dim=0)
+    g0.dt = 0.01
+    g0.options = apt.AP_GRID_PROXY
+    with pytest.raises(apt.APTError, match="AP_GRID_PROXY"):
+        apt.ap_query_layout(g0, [_sp()])
+
+
 def test_pulse_params_struct_matches_header():
     """ap_pulse_params in the binding has the header's layout: 16 doubles, 10
     int32 (d_f ... no_fd), then fwhm, wp2, zeta."""
