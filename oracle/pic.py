@@ -22,12 +22,20 @@ Grid conventions (internal units, periodic in every direction):
 Particle shape: quadratic B-spline ("second-order", Sec. II.B: the scaling
 runs used second-order current deposition) for both the gather and the
 charge-conserving deposition.
+
+Open x ends (1-D rows, ``Grid(..., open_x=True)``): the traditional
+comparison runs of Fig. demo launch the pulse through an incoming-wave
+boundary at x_min (App. B) and let it leave through x_max.  E nodes 0 and
+nx - 1 are the boundary nodes; the B nodes at nx - 1/2 lie outside and are
+held at zero.  Particles stay periodic: the runs keep plasma away from the
+ends.
 """
 import math
 
 import numpy as np
 
 from . import pulses as _pulses
+from . import units as _units
 
 E_STAGGER = ((0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5))
 B_STAGGER = ((0.0, 0.5, 0.5), (0.5, 0.0, 0.5), (0.5, 0.5, 0.0))
@@ -42,12 +50,16 @@ class Grid:
     reduced-dimensionality series of Sec. III.B), row k at lab z = x_min[2] +
     k dx[2] and lab y = the pulse's slice.  An inactive axis has no
     derivative, no motion and no stagger; a particle's coordinate on it is
-    the (integer) index of its row."""
+    the (integer) index of its row.  ``open_x`` (dim 1 only): the x ends are
+    incoming/outgoing-wave boundaries for E2, B2 (App. B)."""
 
-    def __init__(self, dim, n, dx, dt, x_min, t0=0.0):
+    def __init__(self, dim, n, dx, dt, x_min, t0=0.0, open_x=False):
         if dim not in (1, 2, 3):
             raise ValueError("grid dimension must be 1, 2 or 3")
+        if open_x and dim != 1:
+            raise ValueError("open x boundaries are built for 1-D rows only")
         self.dim = dim
+        self.open_x = bool(open_x)
         nx, ny, nz = n
         if dim in (1, 2):
             ny = 1
@@ -255,25 +267,77 @@ def _b_half(grid):
     grid.B[0] = grid.B[0] - h * cx
     grid.B[1] = grid.B[1] - h * cy
     grid.B[2] = grid.B[2] - h * cz
+    if grid.open_x:
+        # the transverse B nodes at nx - 1/2 lie outside the open domain
+        grid.B[1][..., -1] = 0.0
+        grid.B[2][..., -1] = 0.0
 
 
-def _e_full(grid):
-    """E <- E + dt (curl B - J)  (second line of Eqs. (7)-(9), with Eq. (2))."""
+def _e_full(grid, source=None):
+    """E <- E + dt (curl B - J)  (second line of Eqs. (7)-(9), with Eq. (2)).
+
+    Open x ends: the transverse E at the boundary nodes follows App. B.  At
+    x_min Ampere's law with the B node half a cell outside, together with
+    the incoming-wave condition averaged over the step (E_y + B_z = 2 S_y,
+    E_z - B_y = 2 S_z), is solved for the new boundary E; at x_max the same
+    with no incoming wave (E_y - B_z = 0, E_z + B_y = 0).  With
+    r = dx/(c dt) this gives
+        x_min: (1 + r) E_y' = 4 S_y - 2 B_z(1/2) + (r - 1) E_y
+               (1 + r) E_z' = 4 S_z + 2 B_y(1/2) + (r - 1) E_z
+        x_max: (1 + r) E_y' = 2 B_z(nx - 3/2) + (r - 1) E_y
+               (1 + r) E_z' = -2 B_y(nx - 3/2) + (r - 1) E_z
+    (B at the half step, as in the bulk update; J is not applied at the
+    boundary nodes).  ``source`` is (S_y, S_z) per row at t^{n+1/2}, or None."""
     Bx, By, Bz = grid.B
     dt = grid.dt
+    if grid.open_x:
+        old_y = grid.E[1][..., [0, -1]].copy()
+        old_z = grid.E[2][..., [0, -1]].copy()
     cx = _dminus(Bz, grid, 1) - _dminus(By, grid, 2)
     cy = _dminus(Bx, grid, 2) - _dminus(Bz, grid, 0)
     cz = _dminus(By, grid, 0) - _dminus(Bx, grid, 1)
     grid.E[0] = grid.E[0] + dt * (cx - grid.J[0])
     grid.E[1] = grid.E[1] + dt * (cy - grid.J[1])
     grid.E[2] = grid.E[2] + dt * (cz - grid.J[2])
+    if grid.open_x:
+        r = grid.dx[0] / dt
+        sy, sz = (0.0, 0.0) if source is None else (source[0][:, None], source[1][:, None])
+        grid.E[1][..., 0] = (4.0 * sy - 2.0 * Bz[..., 0] + (r - 1.0) * old_y[..., 0]) / (1.0 + r)
+        grid.E[2][..., 0] = (4.0 * sz + 2.0 * By[..., 0] + (r - 1.0) * old_z[..., 0]) / (1.0 + r)
+        grid.E[1][..., -1] = (2.0 * Bz[..., -2] + (r - 1.0) * old_y[..., 1]) / (1.0 + r)
+        grid.E[2][..., -1] = (-2.0 * By[..., -2] + (r - 1.0) * old_z[..., 1]) / (1.0 + r)
 
 
-def yee_step(grid):
-    """One split Yee step of the internal fields only (Eq. (4))."""
+def yee_step(grid, source=None):
+    """One split Yee step of the internal fields only (Eq. (4)); ``source``
+    drives the incoming-wave boundary of an open-x grid."""
     _b_half(grid)
-    _e_full(grid)
+    _e_full(grid, source)
     _b_half(grid)
+
+
+def incoming_wave_s0(dx, dt):
+    """S0/E0 of the incoming-wave boundary (App. B, the exact first form):
+    the source amplitude that launches a plane wave of amplitude E0 into the
+    Yee bulk, k being the vacuum Yee wavenumber of omega = 1 (Eq. (10)).
+    dx, dt internal units (c = omega = 1)."""
+    k = _units.dispersion(_units.DISP_EXACT, dx, dt)[3]
+    r = dx / dt
+    h = 0.5 * dt
+    return 0.5 * (math.cos(h) + r * math.sin(h) * math.cos(0.5 * k * dx) / math.sin(0.5 * k * dx))
+
+
+def boundary_source(grid, pulse, t):
+    """(S_y, S_z) per row at time t for a pulse launched through the x_min
+    boundary: S0/E0 times the pulse's transverse E at (x_min, row) (App. B;
+    the source carries the pulse's own envelope and phase at the boundary)."""
+    nz = grid.n[2]
+    X = np.full(nz, grid.x_min[0])
+    Y = np.full(nz, pulse.q_slice)
+    Z = grid.x_min[2] + np.arange(nz) * grid.dx[2]
+    E1 = _pulses.analytic_fields(pulse, t, X, Y, Z)[0]
+    s0 = incoming_wave_s0(grid.dx[0], grid.dt)
+    return s0 * np.asarray(E1[1], dtype=float), s0 * np.asarray(E1[2], dtype=float)
 
 
 # ----------------------------------------------------------------------------
@@ -375,8 +439,13 @@ def wrap(grid, pos):
     return out
 
 
-def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
+def step(grid, species, pulse, field_update=True, pulse_on_grid=False, launch=False):
     """One step of the loop of Fig. 1.
+
+    ``launch`` (an open-x grid and a plane pulse): the traditional run the
+    paper compares with.  The pulse is not evaluated analytically anywhere;
+    it enters through the incoming-wave boundary at x_min, and the particles
+    feel E2, B2 alone.
 
     For each species: E = E1 + E2, B = B1 + B2 at x^n, t^n (E1, B1 at the
     particle, or sampled on the grid with ``pulse_on_grid``); Boris push
@@ -386,11 +455,14 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
     of E2, B2.  J holds the Yee source (J, or J - J1) afterwards.  Returns per-species (pos_unwrapped_new,)
     for diagnostics.
     """
+    if launch and not (grid.open_x and pulse is not None and pulse.kind == "plane" and not pulse.current):
+        raise ValueError("launching through the boundary needs an open-x grid and a plane pulse")
     for c in range(3):
         grid.J[c][...] = 0.0
     moved = []
     for sp in species:
-        u_half, E, B = push_species(grid, sp, pulse, pulse_on_grid=pulse_on_grid, with_fields=True)
+        u_half, E, B = push_species(grid, sp, None if launch else pulse, pulse_on_grid=pulse_on_grid,
+                                    with_fields=True)
         if sp.proxy is not None:
             sp.proxy = sp.proxy + emission_proxy(sp.u, u_half, E, B, grid.dt)
         new = move(grid, sp.pos, u_half)
@@ -406,7 +478,7 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False):
         for c in range(3):
             grid.J[c] -= J1[c]
     if field_update:
-        yee_step(grid)
+        yee_step(grid, boundary_source(grid, pulse, grid.t + 0.5 * grid.dt) if launch else None)
     grid.t += grid.dt
     return moved
 

@@ -1058,3 +1058,84 @@ def test_1d_row_test_particle_equals_gridless_plane_wave():
     xg = (sp.pos[0] + 64 * np.round((X[0] / (dxl * L) - sp.pos[0]) / 64)) * dxl * L
     assert abs(float(xg[0] - X[0, 0])) < 1e-10 * L
     assert max(np.abs(e).max() for e in g.E) == 0.0
+
+
+# ---- open x ends and the incoming-wave launch (App. B, Fig. demo)
+
+def test_incoming_wave_s0_second_order_form():
+    """App. B: the exact S0/E0 and its printed second-order form
+    1 - (1 + (c dt/dx)^2)(omega dx/c)^2/16 differ at fourth order."""
+    diffs = []
+    for ppl in (15.0, 30.0, 60.0, 120.0):
+        dx = L / ppl
+        dt = 0.95 * dx
+        s0 = pic.incoming_wave_s0(dx, dt)
+        approx = 1.0 - (1.0 + (dt / dx) ** 2) * dx ** 2 / 16.0
+        assert 0.0 < 1.0 - s0 < 0.2 * dx ** 2
+        diffs.append(abs(s0 - approx))
+    for a, b in zip(diffs, diffs[1:]):
+        assert 14.0 < a / b < 18.0, diffs
+    # the continuum limit launches the wave with S = E
+    assert abs(pic.incoming_wave_s0(1e-4, 0.9e-4) - 1.0) < 1e-8
+
+
+def _launch_vs_apt(ppl, corrected=True, tau=66.0, fwhm=30.0, extra=0.0):
+    """Fig. demo (a, b, e) in vacuum, 1-D: a plane super-Gaussian pulse (g = 4,
+    intensity FWHM 30 lambda/c, the paper's 100 fs at 1 um) launched through
+    the x_min boundary into an open 78-lambda line, against the APT field of
+    the same pulse (E2 = 0 in vacuum, so the APT total is E1).  Returns the
+    cycle-averaged difference <E_A - E_I> at the pulse centre and on the
+    leading edge (where <E_A> is 10% of its peak), in units of a0, when the
+    front is 6 lambda from x_max, and the grid; ``extra`` > 0 runs on longer
+    and returns the grid alone (None, None, grid)."""
+    dxl = 1.0 / ppl
+    dtl = 0.95 * dxl
+    Ld = tau + 12.0
+    nx = int(round(Ld / dxl)) + 1
+    grid = pic.Grid(1, (nx, 1, 1), (dxl * L,) * 3, dtl * L, (0.0, 0.0, 0.0), t0=0.0, open_x=True)
+    P = pulses.Pulse(dict(type="plane", a0=1.0, tau=tau, x_ref=0.0, t_ref=tau / 2, pol=0,
+                          dispersion=units.DISP_PAPER2, dx_prop=dxl, dt=dtl, envelope="sgauss", sg_order=4,
+                          fwhm=fwhm))
+    s0 = pic.incoming_wave_s0(grid.dx[0], grid.dt)
+    for _ in range(int((tau + 6.0 + extra) / dtl)):
+        sy, sz = pic.boundary_source(grid, P, grid.t + 0.5 * grid.dt)
+        pic.yee_step(grid, (sy, sz) if corrected else (sy / s0, sz / s0))
+        grid.t += grid.dt
+    if extra > 0.0:
+        return None, None, grid
+    x = np.arange(nx) * grid.dx[0]
+    EA = pulses.analytic_fields(P, grid.t, x, np.zeros(nx), np.zeros(nx))[0][1]
+    ED = EA - grid.E[1][0, 0]
+
+    def cyc(F):
+        # <F>(x) = (2 int_{x - 1/2}^{x + 1/2} F^2 dx')^{1/2}, lambda = 1
+        return np.sqrt(2.0 * np.convolve(F * F, np.ones(int(ppl)) / ppl, mode="same"))
+
+    eA, eD = cyc(EA), cyc(ED)
+    ic = int(round(P.v_g * (grid.t - P.t_ref) / grid.dx[0]))
+    lead = np.nonzero((np.arange(nx) > ic) & (eA < 0.1 * eA.max()))[0][0]
+    return eD[ic], eD[lead], grid
+
+
+def test_boundary_launch_matches_apt_fourth_order_peak_second_order_edge():
+    """Fig. demo(e): with the App. B amplitude the boundary-launched pulse and
+    the APT pulse (second-order v_phi, v_g, B0/E0 of Eqs. (12)-(14)) differ
+    at fourth order in omega dx/c at the pulse centre and at second order on
+    its rising edge.  Without the S0 correction the centre differs at second
+    order (the amplitude error of the boundary)."""
+    res = {p: _launch_vs_apt(p)[:2] for p in (15, 30, 60)}
+    for a, b in ((15, 30), (30, 60)):
+        assert 12.0 < res[a][0] / res[b][0] < 20.0, res
+        assert 3.0 < res[a][1] / res[b][1] < 5.5, res
+    assert res[30][0] < 3e-4 and res[30][1] < 2e-4
+    raw = {p: _launch_vs_apt(p, corrected=False)[0] for p in (30, 60)}
+    assert 3.5 < raw[30] / raw[60] < 4.5
+    assert raw[30] > 20.0 * res[30][0]
+
+
+def test_open_boundary_lets_the_pulse_leave():
+    """A short pulse launched at x_min crosses the line and leaves through
+    x_max: what remains is below 1e-6 of the amplitude."""
+    _, _, grid = _launch_vs_apt(30, tau=20.0, fwhm=6.0, extra=60.0)
+    assert grid.t > 85.0 * L
+    assert max(np.abs(grid.E[1]).max(), np.abs(grid.B[2]).max(), np.abs(grid.E[2]).max()) < 1e-6
