@@ -78,6 +78,15 @@ typedef int32_t ap_status;
 #define AP_GRID_PULSE_ON_GRID 0x1  /* allow AP_SAMPLE_GRID (reserves workspace)  */
 #define AP_GRID_PROXY         0x2  /* gridded species may carry an emission
                                       proxy (reserves its re-sort workspace)  */
+#define AP_GRID_OPEN_X        0x4  /* dim 1 only: the x ends of every row are
+                                      incoming/outgoing-wave boundaries for E2,
+                                      B2 (App. B, first order, normal
+                                      incidence).  E nodes 0 and n[0]-1 are the
+                                      boundary nodes; the transverse B nodes at
+                                      n[0]-1/2 lie outside and are held at 0;
+                                      J is not applied at the boundary nodes.
+                                      Particles stay periodic in x: keep plasma
+                                      away from the ends.                      */
 
 /* Temporal envelopes (Sec. II.A sin^2 form; Sec. II.B super-Gaussian runs). */
 #define AP_ENV_SIN2         0   /* a0 sin^2(pi eta / tau) on [0, tau]           */
@@ -89,6 +98,14 @@ typedef int32_t ap_status;
 #define AP_SAMPLE_GRID      1   /* at the staggered Yee nodes, added to E2, B2
                                    before the gather (gridded runs with
                                    AP_GRID_PULSE_ON_GRID)                      */
+#define AP_SAMPLE_BOUNDARY  2   /* nowhere: the traditional run of Fig. demo.
+                                   A PLANE pulse (no analytic current) enters
+                                   through the x_min boundary of an
+                                   AP_GRID_OPEN_X run: the source is S0/E0 of
+                                   App. B (exact form, vacuum Yee wavenumber
+                                   along x) times the pulse's transverse E at
+                                   (x_min, row) at t^{n+1/2}; the particles
+                                   feel E2, B2 alone                          */
 
 /* ap_gather_diag masks */
 #define AP_DIAG_PARTICLES   0x1u  /* moments, energies, proxy, NaN count       */

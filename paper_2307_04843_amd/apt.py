@@ -22,10 +22,11 @@ AP_DIAG_PARTICLES, AP_DIAG_FIELDS = 0x1, 0x2
 AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5)
 AP_GRID_PULSE_ON_GRID = 0x1
 AP_GRID_PROXY = 0x2
+AP_GRID_OPEN_X = 0x4
 AP_ENV_SIN2, AP_ENV_SGAUSS = 0, 1
-AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID = 0, 1
+AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID, AP_SAMPLE_BOUNDARY = 0, 1, 2
 ENVELOPES = {"sin2": AP_ENV_SIN2, "sgauss": AP_ENV_SGAUSS}
-SAMPLINGS = {"particles": AP_SAMPLE_PARTICLES, "grid": AP_SAMPLE_GRID}
+SAMPLINGS = {"particles": AP_SAMPLE_PARTICLES, "grid": AP_SAMPLE_GRID, "boundary": AP_SAMPLE_BOUNDARY}
 
 PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE_GAUSS,
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}

@@ -82,7 +82,9 @@ class GridlessRun:
         gu = gu.to(device=self.sim.device, dtype=dt).contiguous()
         gp_ptr = None
         gp = None
-        if grad_proxy is not None:
+        # a proxy cotangent that is zero everywhere is left out: the adjoint
+        # then runs the kernel without the proxy term
+        if grad_proxy is not None and grad_proxy.numel() > 0 and bool(grad_proxy.abs().max() > 0):
             gp = grad_proxy.to(device=self.sim.device, dtype=dt).contiguous()
             gp_ptr = gp.data_ptr()
         ids = [PARAM_IDS[nm] for nm in self.param_names]
@@ -168,7 +170,7 @@ class GriddedRun:
         gu = grad_u if grad_u is not None else torch.zeros((3, n), device=self.sim.device)
         gu = gu.to(device=self.sim.device, dtype=self.sim.dtype).contiguous()
         gp = None
-        if self.proxy and grad_proxy is not None:
+        if self.proxy and grad_proxy is not None and grad_proxy.numel() > 0 and bool(grad_proxy.abs().max() > 0):
             gp = grad_proxy.to(device=self.sim.device, dtype=self.sim.dtype).contiguous()   # by particle id
         ids = [PARAM_IDS[nm] for nm in self.param_names]
         torch.cuda.synchronize(self.sim.device)

@@ -162,7 +162,7 @@ AP_D void gather_grad(const T *F, const AxisStencil<T> &sx, const AxisStencil<T>
     }
 }
 
-template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
+template <typename T, int PT, int NT, int GD, bool PX> AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int lid = p;          // index of the particle's adjoint state
@@ -287,7 +287,7 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
             for (int c = 0; c < 3; ++c) lu1[c] += a.dt * (lx[c] - vv[c] * vl) / g1;
         }
         double lu0[3] = {0.0, 0.0, 0.0}, lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
-        if (a.lam_proxy) {
+        if (PX && a.lam_proxy) {
             const double lp = (double)a.lam_proxy[lid];
             if (lp != 0.0) {
                 using D12 = Dual<T, 12>;
@@ -359,20 +359,28 @@ template <typename T, int PT, int NT, int GD> AP_D __forceinline__ void adjoint_
 
 // FP32: two waves per SIMD (the compiler keeps the dual-number working set
 // in 256 registers with a few spills), measured faster than one wave without
-// spills.  FP64 needs twice the registers and runs best at one wave.
-template <int PT, int NT, int GD>
+// spills.  FP64 needs twice the registers and runs best at one wave.  The
+// proxy term (PX) is a kernel of its own: its 12-tangent Jacobian would
+// otherwise raise the register demand of every launch.
+template <int PT, int NT, int GD, bool PX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step(AdjointArgs<float> a) {
-    adjoint_step_body<float, PT, NT, GD>(a);
+    adjoint_step_body<float, PT, NT, GD, PX>(a);
 }
-template <int PT, int NT, int GD> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
-    adjoint_step_body<double, PT, NT, GD>(a);
+template <int PT, int NT, int GD, bool PX> __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
+    adjoint_step_body<double, PT, NT, GD, PX>(a);
 }
 
 template <typename T, int PT, int GD> static void launch_adj_gd(const AdjointArgs<T> &a, int np, hipStream_t s) {
     const dim3 grid((a.n + 255) / 256), block(256);
     // parameter tangents padded to 2 or 4 (unused slots are -1 and stay zero)
-    if (np <= 2) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD>), grid, block, 0, s, a);
+    const bool px = a.lam_proxy != nullptr;
+    if (np <= 2) {
+        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, false>), grid, block, 0, s, a);
+    } else {
+        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, false>), grid, block, 0, s, a);
+    }
 }
 
 template <typename T, int PT> static hipError_t launch_adj(const AdjointArgs<T> &a, hipStream_t s) {

@@ -52,7 +52,8 @@ struct RunShape {
 };
 
 struct WorkLayout {
-    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, total = 0;
+    size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, bsrc = 0,
+           total = 0;
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -133,7 +134,9 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
-    if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY)) return fail(AP_E_ARG, "unknown grid option bits");
+    if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY | AP_GRID_OPEN_X))
+        return fail(AP_E_ARG, "unknown grid option bits");
+    if ((g->options & AP_GRID_OPEN_X) && s.dim != 1) return fail(AP_E_ARG, "AP_GRID_OPEN_X is built for 1-D rows only");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
     if ((g->options & AP_GRID_PROXY) && s.dim == 0)
@@ -187,6 +190,8 @@ WorkLayout make_layout(const RunShape &s) {
         // E2 + E1 and B2 + B1 with E1, B1 sampled on the grid (AP_SAMPLE_GRID)
         if (s.options & AP_GRID_PULSE_ON_GRID) L.esamp = take((size_t)s.ncell * 6 * s.real);
         L.scan_part = take((size_t)2 * scan_part_len((int32_t)s.ntiles) * 4);
+        // boundary source S_y, S_z per row (incoming-wave x_min of open rows)
+        if (s.options & AP_GRID_OPEN_X) L.bsrc = take((size_t)s.n[2] * 2 * s.real);
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
             L.count[i] = take((size_t)s.ntiles * 4);
@@ -312,6 +317,7 @@ struct ap_ctx {
     hipStream_t stream = nullptr;
     PulseDev P;
     int pulse_type = -1;
+    double s0 = 1.0;             // S0/E0 of the incoming-wave boundary (AP_SAMPLE_BOUNDARY)
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
@@ -512,8 +518,14 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         if (prm->sg_order < 1 || prm->sg_order > 32) return fail(AP_E_ARG, "sg_order must be 1..32");
         if (!std::isfinite(prm->fwhm) || !(prm->fwhm > 0.0)) return fail(AP_E_ARG, "fwhm must be > 0");
     }
-    if (prm->sampling != AP_SAMPLE_PARTICLES && prm->sampling != AP_SAMPLE_GRID)
+    if (prm->sampling != AP_SAMPLE_PARTICLES && prm->sampling != AP_SAMPLE_GRID &&
+        prm->sampling != AP_SAMPLE_BOUNDARY)
         return fail(AP_E_ARG, "unknown sampling mode");
+    if (prm->sampling == AP_SAMPLE_BOUNDARY) {
+        if (!(c->s.options & AP_GRID_OPEN_X))
+            return fail(AP_E_STATE, "launching through the boundary needs a run created with AP_GRID_OPEN_X");
+        if (type != AP_PULSE_PLANE) return fail(AP_E_ARG, "only a PLANE pulse is launched through the boundary");
+    }
     if (prm->sampling == AP_SAMPLE_GRID && !(c->s.dim > 0 && (c->s.options & AP_GRID_PULSE_ON_GRID)))
         return fail(AP_E_STATE, "grid sampling needs a gridded run created with AP_GRID_PULSE_ON_GRID");
     if (type == AP_PULSE_GAUSS_NP) {
@@ -636,7 +648,17 @@ ap_status ap_set_pulse(ap_ctx *c, int32_t type, const ap_pulse_params *prm) {
         }
         P.lg_pref = norm * std::pow(std::sqrt(2.0) / P.w0, (double)la);
     }
+    double s0 = 1.0;
+    if (prm->sampling == AP_SAMPLE_BOUNDARY) {
+        // App. B, exact form: S0/E0 = [cos(dt/2) + r sin(dt/2) cos(k dx/2)/sin(k dx/2)]/2,
+        // r = dx/dt, k the vacuum Yee wavenumber along x: sin(k dx/2) = r sin(dt/2)
+        const double dx = c->s.dx[0], dt = c->s.dt, r = dx / dt, h = 0.5 * dt;
+        const double sk = r * std::sin(h);
+        if (!(sk > 0.0 && sk < 1.0)) return fail(AP_E_ARG, "no propagating Yee mode along x for this dx, dt");
+        s0 = 0.5 * (std::cos(h) + r * std::sin(h) * std::cos(std::asin(sk)) / sk);
+    }
     c->P = P;
+    c->s0 = s0;
     c->pulse_type = type;
     c->rec_n = 0;   // a recording holds for the pulse it was made with
     return AP_OK;
@@ -817,7 +839,7 @@ ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void 
     if (!c) return fail(AP_E_ARG, "context is NULL");
     if (c->s.dim > 0 && dl_dproxy && (species < 0 || species >= c->s.nsp || !c->s.has_proxy[species]))
         return fail(AP_E_ARG, "the species carries no emission proxy");
-    if (c->s.dim > 0 && c->P.sampling == AP_SAMPLE_GRID)
+    if (c->s.dim > 0 && c->P.sampling != AP_SAMPLE_PARTICLES)
         return fail(AP_E_UNSUPPORTED, "the adjoint of gridded runs needs the pulse evaluated per particle");
     if (c->rec_n <= 0) return fail(AP_E_STATE, "no recorded forward run (step with AP_STEP_RECORD first)");
     if (c->step != c->rec_step0 + c->rec_n) return fail(AP_E_STATE, "the state moved past the recorded window");
@@ -1400,7 +1422,9 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         sa.fd_delta = c->P.fd_delta;
         HIPCHK(launch_sample_pulse<T>(c->P.type, sa, c->stream), "sample pulse");
     }
-    const int push_pulse = on_grid ? (int)PT_NONE : c->P.type;
+    // launched through the x_min boundary: no analytic field anywhere
+    const bool launch = c->P.sampling == AP_SAMPLE_BOUNDARY && c->P.type != PT_NONE;
+    const int push_pulse = (on_grid || launch) ? (int)PT_NONE : c->P.type;
 
     {
         Timer tm(c, 3);
@@ -1475,6 +1499,22 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         YeeArgsBase yb;
         for (int k = 0; k < 3; ++k) { yb.n[k] = s.n[k]; yb.dx[k] = s.dx[k]; }
         yb.dt = s.dt;
+        yb.open_x = (s.options & AP_GRID_OPEN_X) ? 1 : 0;
+        yb.src = nullptr;
+        if (launch && !(flags & AP_STEP_NO_YEE)) {
+            BoundaryArgs<T> ba{};
+            ba.S = c->wp<T>(L.bsrc);
+            ba.rows = s.n[2];
+            for (int k = 0; k < 3; ++k) {
+                ba.x_min[k] = s.x_min[k];
+                ba.dx[k] = s.dx[k];
+            }
+            ba.q_slice = c->P.q_slice;
+            ba.s0 = c->s0;
+            ba.W = plain_vars<T>(c->P, a.t + 0.5 * s.dt);
+            HIPCHK(launch_boundary_source<T>(c->P.type, ba, c->stream), "boundary source");
+            yb.src = ba.S;
+        }
         HIPCHK(launch_yee<T>(s.dim, F, yb, (flags & AP_STEP_NO_YEE) ? 1 : 0, c->stream), "yee");
     }
     return AP_OK;

@@ -20,7 +20,7 @@ struct YeeIdx {
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_yee_b(T *__restrict__ Ex, T *__restrict__ Ey, T *__restrict__ Ez,
                                               T *__restrict__ Bx, T *__restrict__ By, T *__restrict__ Bz,
-                                              YeeIdx g, T hx, T hy, T hz, size_t ncell) {
+                                              YeeIdx g, T hx, T hy, T hz, size_t ncell, int open_x) {
     // hx = (dt/2)/dx etc.
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
         const uint32_t cc = (uint32_t)c;
@@ -48,8 +48,10 @@ __global__ __launch_bounds__(256) void k_yee_b(T *__restrict__ Ex, T *__restrict
             cz -= (Ex[c + jp] - ex) * hy;
         }
         Bx[c] -= cx;
-        By[c] -= cy;
-        Bz[c] -= cz;
+        // open x ends: the transverse B nodes at nx - 1/2 lie outside the domain
+        const bool ghost = DIM == 2 && open_x && i == g.nx - 1;
+        By[c] = ghost ? T(0) : By[c] - cy;
+        Bz[c] = ghost ? T(0) : Bz[c] - cz;
         (void)j;
     }
 }
@@ -59,8 +61,9 @@ __global__ __launch_bounds__(256) void k_yee_e(T *__restrict__ Ex, T *__restrict
                                               const T *__restrict__ Bx, const T *__restrict__ By,
                                               const T *__restrict__ Bz, const T *__restrict__ Jx,
                                               const T *__restrict__ Jy, const T *__restrict__ Jz,
-                                              YeeIdx g, T cx_, T cy_, T cz_, T dt, size_t ncell) {
-    // c*_ = dt/dx etc.
+                                              YeeIdx g, T cx_, T cy_, T cz_, T dt, size_t ncell,
+                                              int open_x, const T *__restrict__ src, T r) {
+    // c*_ = dt/dx etc.; r = dx/dt
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
         const uint32_t cc = (uint32_t)c;
         const uint32_t row = g.fnx.div(cc);
@@ -86,9 +89,26 @@ __global__ __launch_bounds__(256) void k_yee_e(T *__restrict__ Ex, T *__restrict
             qx += (bz - Bz[c + jm]) * cy_;
             qz -= (bx - Bx[c + jm]) * cy_;
         }
+        const T ey = Ey[c], ez = Ez[c];
+        T ny = ey + (qy - dt * Jy[c]), nz = ez + (qz - dt * Jz[c]);
+        if (DIM == 2 && open_x && (i == 0 || i == g.nx - 1)) {
+            // App. B: Ampere's law with the outside B node and the step-averaged
+            // incoming-wave condition (x_min: E_y + B_z = 2 S_y, E_z - B_y = 2 S_z;
+            // x_max: no incoming wave), solved for the new boundary E; J is not
+            // applied at the boundary nodes
+            const T ir = T(1) / (T(1) + r), rm = r - T(1);
+            if (i == 0) {
+                const T sy = src ? src[2 * k] : T(0), sz = src ? src[2 * k + 1] : T(0);
+                ny = (T(4) * sy - T(2) * bz + rm * ey) * ir;
+                nz = (T(4) * sz + T(2) * by + rm * ez) * ir;
+            } else {
+                ny = (T(2) * Bz[c - 1] + rm * ey) * ir;
+                nz = (rm * ez - T(2) * By[c - 1]) * ir;
+            }
+        }
         Ex[c] += qx - dt * Jx[c];
-        Ey[c] += qy - dt * Jy[c];
-        Ez[c] += qz - dt * Jz[c];
+        Ey[c] = ny;
+        Ez[c] = nz;
     }
 }
 
@@ -115,13 +135,16 @@ hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, 
     const T cx = T(a.dt / a.dx[0]), cy = T(a.dt / a.dx[1]);
     const T cz = dim == 1 ? T(0) : T(a.dt / a.dx[2]);
     if (dim == 3) {
-        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
-        hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell);
-        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, 0);
+        hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, 0, (const T *)nullptr, T(1));
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, 0);
     } else {
-        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
-        hipLaunchKernelGGL((k_yee_e<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell);
-        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell);
+        const int ox = dim == 1 && a.open_x ? 1 : 0;
+        const T *src = static_cast<const T *>(a.src);
+        const T r = T(a.dx[0] / a.dt);
+        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);
+        hipLaunchKernelGGL((k_yee_e<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, ox, src, r);
+        hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);
     }
     return hipGetLastError();
 }

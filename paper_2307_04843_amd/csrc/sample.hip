@@ -4,6 +4,7 @@
 // particle shape.  One thread per cell writes the six sums.  With an
 // analytic current (Sec. IV) B1 carries its finite-duration correction, and
 // k_analytic_current subtracts J1 at the half step from the deposited J.
+// k_boundary_source drives the incoming-wave boundary of open-x rows.
 #include <algorithm>
 
 #include "current_dev.h"
@@ -128,5 +129,25 @@ template <typename T> hipError_t launch_analytic_current(int pulse, const Curren
 }
 template hipError_t launch_analytic_current<float>(int, const CurrentArgs<float> &, hipStream_t);
 template hipError_t launch_analytic_current<double>(int, const CurrentArgs<double> &, hipStream_t);
+
+// Incoming-wave boundary source (App. B): one thread per row evaluates the
+// pulse at (x_min, row) at the half step; S = (S0/E0) E1_{y,z}.
+template <typename T, int PT> __global__ __launch_bounds__(64) void k_boundary_source(BoundaryArgs<T> a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.rows) return;
+    T e[3], b[3];
+    analytic_field<PT, T>(a.W, a.x_min[0], a.q_slice, a.x_min[2] + (double)r * a.dx[2], e, b);
+    a.S[2 * r] = T(a.s0) * e[1];
+    a.S[2 * r + 1] = T(a.s0) * e[2];
+}
+
+template <typename T> hipError_t launch_boundary_source(int pulse, const BoundaryArgs<T> &a, hipStream_t s) {
+    if (pulse != PT_PLANE) return hipErrorInvalidValue;   // the S0 amplitude is a plane-wave result
+    if (a.rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_boundary_source<T, PT_PLANE>), dim3((unsigned)((a.rows + 63) / 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+template hipError_t launch_boundary_source<float>(int, const BoundaryArgs<float> &, hipStream_t);
+template hipError_t launch_boundary_source<double>(int, const BoundaryArgs<double> &, hipStream_t);
 
 }  // namespace apt

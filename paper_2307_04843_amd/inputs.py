@@ -37,6 +37,11 @@ def density_ramp_x(n0, x_start, length):
     return lambda x, y, z: n0 * np.clip((x - x_start) / length, 0.0, 1.0)
 
 
+def density_slab_x(n0, x0, x1):
+    """n = n0 for x0 <= x < x1, else 0 (lambda units)."""
+    return lambda x, y, z: np.where((x >= x0) & (x < x1), n0, 0.0)
+
+
 def density_gauss_channel(n0, radius, y_axis, z_axis):
     """n = n0 exp(-r_perp^2 / radius^2) about the axis (y_axis, z_axis)."""
     return lambda x, y, z: n0 * np.exp(-((y - y_axis) ** 2 + (z - z_axis) ** 2) / radius ** 2)

@@ -23,12 +23,15 @@ class Simulation:
     ``inputs.plasma`` (cell, off, u, w) or ``inputs.beam`` (icell, off, u, w);
     the arrays may be numpy arrays or torch tensors (a device tensor of the
     working type is used in place: the run updates it).  Lengths and times in
-    lambda units.
+    lambda units.  ``proxy``: every species carries an emission proxy;
+    ``pulse_on_grid``: the pulse may be sampled on the grid; ``open_x`` (1-D
+    rows): incoming/outgoing-wave x ends, for pulses launched through x_min
+    (``set_pulse(..., sampling="boundary")``).
     """
 
     def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
                  precision="f32", tile=(0, 0, 0), sort_every=0, species=(), proxy=False,
-                 device="cuda:0", stream=None, pulse_on_grid=False):
+                 device="cuda:0", stream=None, pulse_on_grid=False, open_x=False):
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP path needs a GPU")
         apt.load()
@@ -48,7 +51,8 @@ class Simulation:
         g.dt = float(dt)
         g.sort_every = int(sort_every)
         g.options = ((apt.AP_GRID_PULSE_ON_GRID if pulse_on_grid else 0)
-                     | (apt.AP_GRID_PROXY if (proxy and dim > 0) else 0))
+                     | (apt.AP_GRID_PROXY if (proxy and dim > 0) else 0)
+                     | (apt.AP_GRID_OPEN_X if open_x else 0))
         self.grid_desc = g
         self.sp_desc = []
         for sp in species:

@@ -139,6 +139,19 @@ def test_proxy_option_reserves_workspace():
         apt.ap_query_layout(g0, [_sp()])
 
 
+def test_open_x_option_rows_only():
+    """AP_GRID_OPEN_X is built for 1-D rows: other dims reject it; rows take it
+    and reserve the per-row boundary source."""
+    g = _grid()
+    g.options = apt.AP_GRID_OPEN_X
+    with pytest.raises(apt.APTError, match="1-D rows"):
+        apt.ap_query_layout(g, [_sp()])
+    g1 = _grid(dim=1)
+    base = apt.ap_query_layout(g1, [_sp()]).work_bytes
+    g1.options = apt.AP_GRID_OPEN_X
+    assert apt.ap_query_layout(g1, [_sp()]).work_bytes >= base
+
+
 def test_pulse_params_struct_matches_header():
     """ap_pulse_params in the binding has the header's layout: 16 doubles, 10
     int32 (d_f ... no_fd), then fwhm, wp2, zeta."""
