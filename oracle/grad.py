@@ -6,6 +6,10 @@ to a pulse parameter is taken here by central differences of the FP64
 trajectory, Richardson-extrapolated: with D(h) = (L(th + h) - L(th - h))/(2h),
     g = (4 D(h/2) - D(h)) / 3,
 whose error is O(h^4) plus FP64 rounding ~ eps |L| / h.
+
+Gridded runs have two references: the frozen-grid one (one species pushed
+through the E2, B2 a nominal run recorded) and the fully coupled one (the
+whole loop, every species, rerun at each perturbed parameter).
 """
 import numpy as np
 
@@ -108,6 +112,55 @@ def frozen_gradient(prm, name, grid, recs, sp0, wu, rel_h=1e-6, pulse_on_grid=Fa
         if wp is None:
             return float(np.sum(wu * frozen_run(q, grid, recs, sp0, pulse_on_grid)[1]))
         _, u, pr = frozen_run(q, grid, recs, sp0, pulse_on_grid, with_proxy=True)
+        return float(np.sum(wu * u) + np.sum(wp * pr))
+
+    d1 = (Lof(base + h) - Lof(base - h)) / (2 * h)
+    d2 = (Lof(base + h / 2) - Lof(base - h / 2)) / h
+    return (4 * d2 - d1) / 3, d1, d2
+
+
+# ----------------------------------------------------------------------------
+# Gridded runs, fully coupled: the parameters act on every species through
+# E1, B1 and, through the deposited current and the Yee update, on E2, B2.
+# ----------------------------------------------------------------------------
+
+def _clone(grid, species):
+    g = pic.Grid(grid.dim, grid.n, grid.dx, grid.dt, grid.x_min, t0=grid.t, open_x=grid.open_x)
+    g.E = [e.copy() for e in grid.E]
+    g.B = [b.copy() for b in grid.B]
+    sps = [pic.Species(sp.q, sp.m, sp.pos, sp.u, sp.w, proxy=None if sp.proxy is None else sp.proxy)
+           for sp in species]
+    return g, sps
+
+
+def coupled_run(prm, grid, species, n_steps, sp_index=0, with_proxy=False):
+    """The full loop (pic.step: push, deposit, Yee) for n_steps from copies of
+    ``grid`` and ``species`` (left unchanged).  Returns the final u of species
+    ``sp_index`` and, with ``with_proxy``, its emission proxy accumulated from
+    zero."""
+    P = pulses.Pulse(prm)
+    g, sps = _clone(grid, species)
+    if with_proxy:
+        sps[sp_index].proxy = np.zeros(sps[sp_index].u.shape[1])
+    for _ in range(n_steps):
+        pic.step(g, sps, P)
+    sp = sps[sp_index]
+    return (sp.u, sp.proxy) if with_proxy else sp.u
+
+
+def coupled_gradient(prm, name, grid, species, n_steps, wu, sp_index=0, rel_h=1e-6, wp=None):
+    """dL/d(prm[name]) through the whole self-consistent run, L = sum wu . u_final
+    (+ sum wp proxy_final) of species ``sp_index``: Richardson-extrapolated
+    central differences as in ``frozen_gradient`` (the same jumps apply)."""
+    base = float(prm[name])
+    h = rel_h * max(abs(base), 1.0)
+
+    def Lof(v):
+        q = dict(prm)
+        q[name] = v
+        if wp is None:
+            return float(np.sum(wu * coupled_run(q, grid, species, n_steps, sp_index)))
+        u, pr = coupled_run(q, grid, species, n_steps, sp_index, with_proxy=True)
         return float(np.sum(wu * u) + np.sum(wp * pr))
 
     d1 = (Lof(base + h) - Lof(base - h)) / (2 * h)

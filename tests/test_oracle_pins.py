@@ -833,6 +833,44 @@ def test_frozen_grid_reference_replays_and_converges():
     assert max(abs(est[0] - est[1]), abs(est[2] - est[1])) <= 1e-8 * abs(est[1]), est
 
 
+def test_coupled_reference_reduces_to_frozen_and_converges():
+    """Fully coupled reference: with weightless particles the grid does not
+    depend on the parameters, so the coupled gradient equals the frozen-grid
+    one; with the plasma's weights it differs (the response through deposit
+    and Yee update) and the difference quotient settles as h shrinks."""
+    from oracle import grad as ograd
+    from tests import cases
+    case = cases.make_case(n=(24, 1, 16), seed=4, u_scale=10.0, ppc=2)
+    prm = dict(case["pulse"])
+    names = ("a0", "w0", "x_f")
+    g, sps, _ = cases.oracle_state(case)
+    u = ograd.coupled_run(prm, g, sps, 12)
+    wu = np.zeros_like(u)
+    wu[2] = u[2] / u.shape[1]
+    # weightless: coupled == frozen
+    g0, sps0, _ = cases.oracle_state(case)
+    for sp in sps0:
+        sp.w = np.zeros_like(sp.w)
+    sp00 = pic.Species(sps0[0].q, sps0[0].m, sps0[0].pos, sps0[0].u, sps0[0].w)
+    gz, spz, _ = cases.oracle_state(case)
+    for sp in spz:
+        sp.w = np.zeros_like(sp.w)
+    recs0 = ograd.record_gridded_run(gz, spz, prm, 12)
+    for nm in names:
+        c = ograd.coupled_gradient(prm, nm, g0, sps0, 12, wu)[0]
+        f = ograd.frozen_gradient(prm, nm, g0, recs0, sp00, wu)[0]
+        assert abs(c - f) <= 1e-9 * max(abs(f), 1e-3), (nm, c, f)
+    # weighted: the coupling is visible, and the quotient converges
+    sp0 = pic.Species(sps[0].q, sps[0].m, sps[0].pos, sps[0].u, sps[0].w)
+    g2, sps2, _ = cases.oracle_state(case)
+    recs = ograd.record_gridded_run(g2, sps2, prm, 12)
+    cpl = np.array([ograd.coupled_gradient(prm, nm, g, sps, 12, wu)[0] for nm in names])
+    frz = np.array([ograd.frozen_gradient(prm, nm, g, recs, sp0, wu)[0] for nm in names])
+    fine = np.array([ograd.coupled_gradient(prm, nm, g, sps, 12, wu, rel_h=1e-7)[0] for nm in names])
+    assert np.linalg.norm(cpl - frz) > 1e-2 * np.linalg.norm(cpl)
+    assert np.all(np.abs(fine - cpl) <= 1e-6 * np.linalg.norm(cpl)), (cpl, fine)
+
+
 # ---------------------------------------------------------------------------
 # Analytic current J1 (Sec. IV)
 # ---------------------------------------------------------------------------
