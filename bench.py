@@ -160,32 +160,35 @@ def three_d_leg(args):
     if args.adj3d_steps > 0:
         names = ["beta_f", "chirp"]
         K = 8
-        log("3-D adjoint: %d-step window, segments of %d" % (args.adj3d_steps, K))
-        run = GriddedRun(3, N3, (DX3,) * 3, (0.0, -8.0, -8.0), species, "ff", pp, names, args.adj3d_steps,
-                         t0=t0, dt=dt, precision="f32", segment=K)
-        try:
-            p = torch.tensor([pp["beta_f"], pp["chirp"]], dtype=torch.float64, requires_grad=True)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            u, _ = APTRun.apply(p, run)
-            torch.cuda.synchronize()
-            b = time.perf_counter()
-            obs = (u[1].double() ** 2 + u[2].double() ** 2).sum() / n
-            obs.backward()
-            torch.cuda.synchronize()
-            c = time.perf_counter()
-            out["adjoint"] = {"window_steps": args.adj3d_steps, "segment": K, "params": names,
-                              "grad": p.grad.tolist(), "observable": float(obs.detach()),
-                              "forward_pushes_per_s": n * args.adj3d_steps / (b - a),
-                              "adjoint_pushes_per_s": n * args.adj3d_steps / (c - b),
-                              "checkpoint_gb": run.ckpt.numel() / 1e9,
-                              "note": "frozen-grid reading; backward = segment replays with the full "
-                                      "loop + reverse steps"}
-            log("3-D adjoint: %.3e pushes/s" % out["adjoint"]["adjoint_pushes_per_s"])
-        finally:
-            run.close()
-            del run
-            torch.cuda.empty_cache()
+        for coupled in (False, True) if not args.skip_coupled else (False,):
+            key = "adjoint_coupled" if coupled else "adjoint"
+            log("3-D %s: %d-step window, segments of %d" % (key, args.adj3d_steps, K))
+            run = GriddedRun(3, N3, (DX3,) * 3, (0.0, -8.0, -8.0), species, "ff", pp, names, args.adj3d_steps,
+                             t0=t0, dt=dt, precision="f32", segment=K, coupled=coupled)
+            try:
+                p = torch.tensor([pp["beta_f"], pp["chirp"]], dtype=torch.float64, requires_grad=True)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                u, _ = APTRun.apply(p, run)
+                torch.cuda.synchronize()
+                b = time.perf_counter()
+                obs = (u[1].double() ** 2 + u[2].double() ** 2).sum() / n
+                obs.backward()
+                torch.cuda.synchronize()
+                c = time.perf_counter()
+                note = ("fully coupled: every species' push, current, the Yee update and the gather "
+                        "differentiated; backward = segment replays + transposed Yee + reverse steps" if coupled
+                        else "frozen-grid reading; backward = segment replays with the full loop + reverse steps")
+                out[key] = {"window_steps": args.adj3d_steps, "segment": K, "params": names,
+                            "grad": p.grad.tolist(), "observable": float(obs.detach()),
+                            "forward_pushes_per_s": n * args.adj3d_steps / (b - a),
+                            "adjoint_pushes_per_s": n * args.adj3d_steps / (c - b),
+                            "checkpoint_gb": run.ckpt.numel() / 1e9, "note": note}
+                log("3-D %s: %.3e pushes/s" % (key, out[key]["adjoint_pushes_per_s"]))
+            finally:
+                run.close()
+                del run
+                torch.cuda.empty_cache()
     del species
     return out
 
@@ -670,6 +673,7 @@ def main():
     ap.add_argument("--sort-every", type=int, default=0, help="tile re-sort interval (0: library default)")
     ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 3-D leg")
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
+    ap.add_argument("--skip-coupled", action="store_true", help="3-D leg: frozen-grid adjoint only")
     ap.add_argument("--skip-3d", action="store_true")
     ap.add_argument("--skip-small", action="store_true")
     ap.add_argument("--skip-rows1d", action="store_true")

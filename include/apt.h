@@ -329,6 +329,23 @@ ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, voi
  * must stay allocated and untouched until the last ap_backward call. */
 ap_status ap_set_checkpoints(ap_ctx *ctx, void *dev, size_t bytes, int32_t segment);
 
+/* Reading of the adjoint of gridded runs (ap_backward).
+ *   AP_ADJ_FROZEN   (default) the E2, B2 each push gathered are a recorded
+ *                   external field: one species is differentiated.
+ *   AP_ADJ_COUPLED  the whole loop is differentiated: every species' push,
+ *                   its charge-conserving current (positions before and
+ *                   after the step, and the out-of-plane velocity), the Yee
+ *                   update (transposed, periodic grids only) and the gather
+ *                   of E2, B2; the parameters reach the observed species
+ *                   also through the plasma's response.  Every species'
+ *                   ids must be a permutation of 0..n-1.
+ * Setting the mode drops the checkpoint buffer and any recording (the
+ * layout depends on it): call before ap_set_checkpoints.  AP_E_ARG for an
+ * unknown mode or a gridless run, AP_E_UNSUPPORTED with AP_GRID_OPEN_X. */
+#define AP_ADJ_FROZEN   0
+#define AP_ADJ_COUPLED  1
+ap_status ap_set_adjoint_mode(ap_ctx *ctx, int32_t mode);
+
 /* Checkpoint bytes for recording n_steps >= 1 steps with segment K >= 1
  * (written to *bytes, host). */
 ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segment, size_t *bytes);

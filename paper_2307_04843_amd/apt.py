@@ -23,6 +23,7 @@ AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5
 AP_GRID_PULSE_ON_GRID = 0x1
 AP_GRID_PROXY = 0x2
 AP_GRID_OPEN_X = 0x4
+AP_ADJ_FROZEN, AP_ADJ_COUPLED = 0, 1
 AP_ENV_SIN2, AP_ENV_SGAUSS = 0, 1
 AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID, AP_SAMPLE_BOUNDARY = 0, 1, 2
 ENVELOPES = {"sin2": AP_ENV_SIN2, "sgauss": AP_ENV_SGAUSS}
@@ -32,7 +33,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
-            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
+            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_set_adjoint_mode", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
             "ap_last_error")
 
 
@@ -120,6 +121,7 @@ def load():
                                       C.c_void_p]),
         "ap_set_checkpoints": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
         "ap_checkpoint_bytes": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, P(C.c_size_t)]),
+        "ap_set_adjoint_mode": (C.c_int32, [C.c_void_p, C.c_int32]),
         "ap_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(C.c_int32),
                                     C.c_int32, P(C.c_double)]),
         "ap_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -193,6 +195,10 @@ def ap_eval_pulse(ctx, n, xyz_ptr, t, e_ptr, b_ptr):
 def ap_set_checkpoints(ctx, dev_ptr, nbytes, segment):
     _check(load().ap_set_checkpoints(ctx, C.c_void_p(dev_ptr), int(nbytes), int(segment)),
            "ap_set_checkpoints")
+
+
+def ap_set_adjoint_mode(ctx, mode):
+    _check(load().ap_set_adjoint_mode(ctx, int(mode)), "ap_set_adjoint_mode")
 
 
 def ap_checkpoint_bytes(ctx, n_steps, segment):

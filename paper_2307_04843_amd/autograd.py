@@ -9,10 +9,11 @@ proxies (N,).  Its backward calls the library's hand-written adjoint
 (ap_backward) and returns dL/dparams.
 
 ``GriddedRun`` does the same for a gridded run (dim 1, 2 or 3, every species,
-full loop) and one species' final momenta and proxies, ordered by particle id,
-in the frozen-grid reading: the gradient treats the E2, B2 each push gathered
-as a recorded external field.  Without ``proxy=True`` its proxy output is
-identically zero.
+full loop) and one species' final momenta and proxies, ordered by particle id.
+By default in the frozen-grid reading (the gradient treats the E2, B2 each
+push gathered as a recorded external field); with ``coupled=True`` through
+the whole loop (every species' current, the Yee update and the gather).
+Without ``proxy=True`` its proxy output is identically zero.
 """
 import math
 
@@ -92,7 +93,10 @@ class GridlessRun:
         return apt.ap_backward(self.sim.ctx, 0, gu.data_ptr(), gp_ptr, ids)
 
     def close(self):
+        # an autograd graph may still hold this run: release its device memory now
         self.sim.close()
+        self.ckpt = None
+        self._init = None
 
 
 class GriddedRun:
@@ -102,10 +106,12 @@ class GriddedRun:
 
     def __init__(self, dim, n, dx, x_min, species, pulse_kind, pulse_params, param_names, n_steps, t0=0.0,
                  dt=0.0, precision="f32", fields=None, species_index=0, segment=None, tile=(0, 0, 0),
-                 sort_every=0, proxy=False):
+                 sort_every=0, proxy=False, coupled=False):
         self.sim = Simulation(dim, n=n, dx=dx, x_min=x_min, t0=t0, dt=dt, precision=precision, tile=tile,
                               sort_every=sort_every, species=species, proxy=proxy)
         self.proxy = bool(proxy)
+        self.mode = apt.AP_ADJ_COUPLED if coupled else apt.AP_ADJ_FROZEN
+        apt.ap_set_adjoint_mode(self.sim.ctx, self.mode)
         self.kind = pulse_kind
         self.base = dict(pulse_params)
         self.param_names = list(param_names)
@@ -140,6 +146,7 @@ class GriddedRun:
         apt.ap_destroy(self.sim.ctx)
         self.sim.ctx = apt.ap_init(self.sim.grid_desc, self.sim.sp_desc, self.sim.buffers,
                                    self.sim.stream.cuda_stream)
+        apt.ap_set_adjoint_mode(self.sim.ctx, self.mode)
         if self._fields is not None:
             E, B, _ = self.sim.field_views()
             for k in range(3):
@@ -177,7 +184,10 @@ class GriddedRun:
         return apt.ap_backward(self.sim.ctx, self.sp, gu.data_ptr(), gp.data_ptr() if gp is not None else None, ids)
 
     def close(self):
+        # an autograd graph may still hold this run: release its device memory now
         self.sim.close()
+        self.ckpt = None
+        self._init = None
 
 
 class APTRun(torch.autograd.Function):

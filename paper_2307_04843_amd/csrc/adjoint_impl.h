@@ -1,0 +1,590 @@
+// Adjoint of the gridless step (analytic field + Boris push + move + emission
+// proxy) for gradients of particle observables with respect to the pulse
+// parameters.  The same reverse step serves gridded runs in the frozen-grid
+// reading: the E2, B2 each push gathered are a recorded external field, so
+// E = E1(x; theta) + gather(E2)(x) and dE/dx gains the gradient of the
+// quadratic-shape gather; the adjoint state is indexed by particle id, since
+// re-sorts permute the particle arrays between steps.
+//
+// Forward step n (per particle):  E, B = field(x^n, t^n; theta)
+//     u^{n+1/2} = Boris(u^{n-1/2}, E, B),   x^{n+1} = x^n + dt u^{n+1/2}/gamma,
+//     proxy += P(u^{n-1/2}, u^{n+1/2}, E, B).
+// Reverse step n, with lx = dL/dx^{n+1}, lu = dL/du^{n+1/2}, lp = dL/dproxy:
+//     lu1 = lu + dt (lx - v (v . lx))/gamma + lp dP/du1
+//     lu0 = J_u^T lu1 + lp dP/du0,  lE = J_E^T lu1 + lp dP/dE,  lB = J_B^T lu1 + lp dP/dB
+//     lx <- lx + (dE/dx)^T lE + (dB/dx)^T lB,   g_theta += (dE/dtheta)^T lE + (dB/dtheta)^T lB
+//     lu <- lu0.
+// The field Jacobians come from forward-mode dual numbers through the same
+// generic pulse code the forward kernels use, with NT tangents: x, y, z and
+// one per requested parameter among w0, focal position, beta_f and chirp.
+// The amplitude needs no tangent: every pulse field is proportional to a0,
+// so dF/da0 = F / a0 (evaluated at a0 = 1 when a0 = 0).  9 tangents run
+// through the Boris rotation and 12 through the proxy.  Adjoint state and
+// gradient partials are FP64.
+//
+// Fully coupled reading of gridded runs (CPL): the particles also drive E2,
+// B2 through their current J(x^n, x^{n+1}, u^{n+1/2}), and the gather reads
+// E2^n, B2^n.  With lJ = dL/dJ^{n+1/2} on the E nodes (from the reverse Yee
+// step, outside this kernel), each particle adds
+//     lx^{n+1} += (dJ/dx^{n+1})^T lJ,   lx^n += (dJ/dx^n)^T lJ,
+//     lu1 += (dv/du1)^T (dJ/dv)^T lJ   (out-of-plane components only),
+// and scatters its field adjoint back through the gather weights,
+//     lE2^n[node] += S(node) lE,   lB2^n[node] += S(node) lB.
+#pragma once
+#include "kernels.h"
+
+namespace apt {
+
+// Tangent k >= 3 carries parameter slot[k - 3]: set it to dv where that is `param`.
+template <int NT, typename T> AP_D void seed_tangent(T (&d)[NT], const int32_t (&slot)[4], int param, double dv) {
+#pragma unroll
+    for (int k = 0; k < NT - 3; ++k)
+        if (slot[k] == param) d[3 + k] = T(dv);
+}
+
+// Per-step pulse variables as duals; the amplitude is a0_eff (a0, or 1 when
+// a0 = 0), without a tangent.
+template <typename T, int NT>
+AP_D PulseVar<Dual<T, NT>> adjoint_vars(const PulseDev &P, double t, const int32_t (&slot)[4], double a0_eff) {
+    using DN = Dual<T, NT>;
+    using IN = DualD<T, NT>;
+    PulseVar<DN> V;
+    fill_step_constants(P, t, V);
+    V.a0 = DN(T(a0_eff));
+    const double w0 = P.w0 > 0.0 ? P.w0 : 1.0;
+    auto wd = [&](double v, double dv) {
+        DN r(v);
+        seed_tangent(r.d, slot, 1, dv);
+        return r;
+    };
+    V.inv_xr = wd(P.inv_xr, -2.0 * P.inv_xr / w0);
+    if (P.type == PT_FF) seed_tangent(V.inv_xr.d, slot, 3, P.inv_xr / (1.0 - P.beta_f));
+    V.inv_w0sq = wd(P.inv_w0sq, -2.0 * P.inv_w0sq / w0);
+    V.inv_w0 = wd(P.inv_w0, -P.inv_w0 / w0);
+    V.eps = wd(P.eps, -P.eps / w0);
+    V.np_e2 = wd(P.np_e2, -2.0 * P.np_e2 / w0);
+    V.np_e4 = wd(P.np_e4, -4.0 * P.np_e4 / w0);
+    const int la = P.lg_l < 0 ? -P.lg_l : P.lg_l;
+    V.lg_pref = wd(P.lg_pref, -la * P.lg_pref / w0);
+    V.v_phi = DN(P.v_phi);
+    V.b_over_e = DN(P.b_over_e);
+    // s0 = x_f, or x0_ff + beta_f (t - t0_ff) for the flying focus
+    IN s0(P.type == PT_FF ? P.x0_ff + P.beta_f * (t - P.t0_ff) : P.x_f);
+    seed_tangent(s0.d, slot, 2, 1.0);
+    if (P.type == PT_FF) seed_tangent(s0.d, slot, 3, t - P.t0_ff);
+    V.s0 = s0;
+    IN bh(P.b_half);
+    seed_tangent(bh.d, slot, 4, 0.5 / P.tau);
+    V.b_half = bh;
+    return V;
+}
+
+template <typename R>
+AP_D void boris_g(const R u0[3], const R E[3], const R B[3], R kap, R u1[3]) {
+    const R umx = u0[0] + kap * E[0], umy = u0[1] + kap * E[1], umz = u0[2] + kap * E[2];
+    const R ig = rsqrt_r(R(1.0) + umx * umx + umy * umy + umz * umz);
+    const R tx = kap * B[0] * ig, ty = kap * B[1] * ig, tz = kap * B[2] * ig;
+    const R sf = R(2.0) / (R(1.0) + tx * tx + ty * ty + tz * tz);
+    const R upx = umx + (umy * tz - umz * ty);
+    const R upy = umy + (umz * tx - umx * tz);
+    const R upz = umz + (umx * ty - umy * tx);
+    u1[0] = umx + sf * (upy * tz - upz * ty) + kap * E[0];
+    u1[1] = umy + sf * (upz * tx - upx * tz) + kap * E[1];
+    u1[2] = umz + sf * (upx * ty - upy * tx) + kap * E[2];
+}
+
+template <typename R>
+AP_D R proxy_g(const R u0[3], const R u1[3], const R E[3], const R B[3], R dt) {
+    const R bx = R(0.5) * (u0[0] + u1[0]), by = R(0.5) * (u0[1] + u1[1]), bz = R(0.5) * (u0[2] + u1[2]);
+    const R gb = sqrt_r(R(1.0) + bx * bx + by * by + bz * bz);
+    const R igb = R(1.0) / gb;
+    const R vx = bx * igb, vy = by * igb, vz = bz * igb;
+    const R fx = E[0] + (vy * B[2] - vz * B[1]);
+    const R fy = E[1] + (vz * B[0] - vx * B[2]);
+    const R fz = E[2] + (vx * B[1] - vy * B[0]);
+    const R ve = vx * E[0] + vy * E[1] + vz * E[2];
+    return gb * gb * (fx * fx + fy * fy + fz * fz - ve * ve) * dt;
+}
+
+// Quadratic B-spline weights of nodes -1, 0, +1 at offset d and their d-derivatives.
+template <typename T> AP_D void tsc3_d(T d, T w[3], T dw[3]) {
+    const T lo = T(0.5) - d, hi = T(0.5) + d;
+    w[0] = T(0.5) * lo * lo;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * hi * hi;
+    dw[0] = -lo;
+    dw[1] = T(-2) * d;
+    dw[2] = hi;
+}
+
+// Three-node stencil of one axis for a component on nodes or half a cell up.
+template <typename T> struct AxisStencil {
+    int idx[3];
+    T w[3], dw[3];
+};
+template <typename T> AP_D void axis_stencil(int i, T off, bool half, int n, AxisStencil<T> &st) {
+    int c;
+    T d;
+    if (half) {
+        c = i;
+        d = off - T(0.5);
+    } else {
+        const int up = off >= T(0.5) ? 1 : 0;
+        c = i + up;
+        d = off - T(up);
+    }
+    tsc3_d(d, st.w, st.dw);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int v = c - 1 + m;
+        st.idx[m] = v < 0 ? v + n : (v >= n ? v - n : v);
+    }
+}
+
+// Gathered value and its gradient in cell units (x, y, z; y only in 3-D).
+template <typename T, int GD>
+AP_D void gather_grad(const T *F, const AxisStencil<T> &sx, const AxisStencil<T> &sy, const AxisStencil<T> &sz,
+                      int nx, int ny, T &v, T (&gr)[3]) {
+    v = T(0);
+    gr[0] = gr[1] = gr[2] = T(0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        T pv = T(0), px = T(0), py = T(0);
+#pragma unroll
+        for (int q = 0; q < (GD == 3 ? 3 : 1); ++q) {
+            const T *row = F + ((size_t)sz.idx[b] * ny + (GD == 3 ? sy.idx[q] : 0)) * nx;
+            T r = T(0), rd = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const T f = row[sx.idx[m]];
+                r += sx.w[m] * f;
+                rd += sx.dw[m] * f;
+            }
+            const T wy = GD == 3 ? sy.w[q] : T(1);
+            pv += wy * r;
+            px += wy * rd;
+            if (GD == 3) py += sy.dw[q] * r;
+        }
+        v += sz.w[b] * pv;
+        gr[0] += sz.w[b] * px;
+        gr[1] += sz.w[b] * py;
+        gr[2] += sz.dw[b] * pv;
+    }
+}
+
+// Quadratic B-spline of a node at distance d (cell units) and its d-derivative.
+template <typename T> AP_D void tsc_vd(T d, T &v, T &dv) {
+    const T ad = fabs(d);
+    if (ad <= T(0.5)) {
+        v = T(0.75) - d * d;
+        dv = T(-2) * d;
+    } else if (ad <= T(1.5)) {
+        const T e = T(1.5) - ad;
+        v = T(0.5) * e * e;
+        dv = d > T(0) ? -e : e;
+    } else {
+        v = T(0);
+        dv = T(0);
+    }
+}
+
+AP_D __forceinline__ int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Adjoint of one particle's charge-conserving current.  The current is that
+// of the forward deposit: per active axis A, J_A(m + 1/2) = -q w (dx_A/dt)
+// sum_{m' <= m} W_A(m') with W_A the shape-change weights, and the current
+// along an axis without motion is q w v S_avg.  With lJ = -dt lE~ (lE~ the
+// E adjoint after the first half of the reverse Yee step, read from lE_t)
+//     G = sum over the 5-node window of lJ . J
+// is differentiated in x^n, x^{n+1} (cell units, forward-mode tangents) and
+// in v (out-of-plane components).  ov: offsets at x^n; dl: the step's
+// displacement in cells; returns the cell-unit gradients and dG/dv.
+template <typename T, int GD>
+AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const int ic[3], const T ov[3],
+                          const T dl[3], const T v[3], double qw, double dt, const double dx[3], double gx0[3],
+                          double gx1[3], double gv[3]) {
+    constexpr int NA = GD == 3 ? 3 : (GD == 2 ? 2 : 1);
+    using D = Dual<T, 2 * NA>;
+    const int ax[3] = {0, GD == 3 ? 1 : 2, 2};
+    T s0v[NA][5], s0d[NA][5], s1v[NA][5], s1d[NA][5];
+    int cb[NA];
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+        const int A = ax[s];
+        const int up = ov[A] >= T(0.5) ? 1 : 0;
+        cb[s] = ic[A] + up - 2;
+        const T x0 = ov[A] - T(up), x1 = x0 + dl[A];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            tsc_vd(x0 - T(m - 2), s0v[s][m], s0d[s][m]);
+            tsc_vd(x1 - T(m - 2), s1v[s][m], s1d[s][m]);
+        }
+    }
+    auto S0 = [&](int s, int m) {
+        D r(s0v[s][m]);
+        r.d[s] = s0d[s][m];
+        return r;
+    };
+    auto S1 = [&](int s, int m) {
+        D r(s1v[s][m]);
+        r.d[NA + s] = s1d[s][m];
+        return r;
+    };
+    const int nx = n[0], ny = n[1], nz = n[2];
+    D G(0.0);
+    if constexpr (GD == 1) {
+        // a row: x moves; y and z carry q w v times the mean shape
+        const double *ex = lE_t[0] + (size_t)ic[2] * nx;
+        const double *ey = lE_t[1] + (size_t)ic[2] * nx;
+        const double *ez = lE_t[2] + (size_t)ic[2] * nx;
+        double suf = 0.0;
+        D Gy(0.0), Gz(0.0);
+#pragma unroll
+        for (int m = 4; m >= 0; --m) {
+            const int i = wrap_idx(cb[0] + m, nx);
+            suf += ex[i];
+            G += (S1(0, m) - S0(0, m)) * T(qw * dx[0] * suf);
+            const D mean = T(0.5) * (S0(0, m) + S1(0, m));
+            Gy += mean * T(ey[i]);
+            Gz += mean * T(ez[i]);
+        }
+        const double cy = -dt * qw;
+        G += Gy * T(cy * (double)v[1]) + Gz * T(cy * (double)v[2]);
+        gv[1] = cy * (double)Gy.v;
+        gv[2] = cy * (double)Gz.v;
+    } else if constexpr (GD == 2) {
+        // J_x: suffix sums of lE~_x along x, per z
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const size_t row = (size_t)wrap_idx(cb[1] + k, nz) * nx;
+            const D zm = T(0.5) * (S0(1, k) + S1(1, k));
+            double suf = 0.0;
+#pragma unroll
+            for (int m = 4; m >= 0; --m) {
+                suf += lE_t[0][row + wrap_idx(cb[0] + m, nx)];
+                G += (S1(0, m) - S0(0, m)) * zm * T(qw * dx[0] * suf);
+            }
+        }
+        // J_z: suffix sums along z, per x; J_y: q w v_y times the mean shape product
+        D Gy(0.0);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const int i = wrap_idx(cb[0] + m, nx);
+            const D x0 = S0(0, m), x1 = S1(0, m);
+            const D xm = T(0.5) * (x0 + x1);
+            double suf = 0.0;
+#pragma unroll
+            for (int k = 4; k >= 0; --k) {
+                const size_t c = (size_t)wrap_idx(cb[1] + k, nz) * nx + i;
+                suf += lE_t[2][c];
+                const D z0 = S0(1, k), z1 = S1(1, k);
+                G += (z1 - z0) * xm * T(qw * dx[2] * suf);
+                const D sa = T(1.0 / 3.0) * (x0 * z0 + x1 * z1) + T(1.0 / 6.0) * (x1 * z0 + x0 * z1);
+                Gy += sa * T(lE_t[1][c]);
+            }
+        }
+        const double cy = -dt * qw;
+        G += Gy * T(cy * (double)v[1]);
+        gv[1] = cy * (double)Gy.v;
+    } else {
+        // 3-D: W_A = DS_A (1/3 P0 Q0 + 1/6 P1 Q0 + 1/6 P0 Q1 + 1/3 P1 Q1) over the other two axes
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int s1 = s == 0 ? 1 : 0, s2 = s == 2 ? 1 : 2;   // the two other slots
+            const double coef = qw * dx[ax[s]];
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const D p0 = S0(s1, b), p1 = S1(s1, b), q0 = S0(s2, c), q1 = S1(s2, c);
+                    const D tr = T(1.0 / 3.0) * (p0 * q0 + p1 * q1) + T(1.0 / 6.0) * (p1 * q0 + p0 * q1);
+                    int id3[3];
+                    id3[s1] = wrap_idx(cb[s1] + b, s1 == 0 ? nx : (s1 == 1 ? ny : nz));
+                    id3[s2] = wrap_idx(cb[s2] + c, s2 == 0 ? nx : (s2 == 1 ? ny : nz));
+                    double suf = 0.0;
+#pragma unroll
+                    for (int m = 4; m >= 0; --m) {
+                        id3[s] = wrap_idx(cb[s] + m, s == 0 ? nx : (s == 1 ? ny : nz));
+                        suf += lE_t[s][((size_t)id3[2] * ny + id3[1]) * nx + id3[0]];
+                        G += (S1(s, m) - S0(s, m)) * tr * T(coef * suf);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+        gx0[ax[s]] = (double)G.d[s];
+        gx1[ax[s]] = (double)G.d[NA + s];
+    }
+}
+
+// The gather's adjoint: val spread to the nodes of the stencil with the
+// gather's weights (FP64 atomics).
+template <typename T, int GD>
+AP_D void scatter_adjoint(double *F, const AxisStencil<T> &sx, const AxisStencil<T> &sy, const AxisStencil<T> &sz,
+                          int nx, int ny, double val) {
+#pragma unroll
+    for (int b = 0; b < (GD == 1 ? 1 : 3); ++b) {
+#pragma unroll
+        for (int q = 0; q < (GD == 3 ? 3 : 1); ++q) {
+            const double wzy = (double)sz.w[b] * (GD == 3 ? (double)sy.w[q] : 1.0) * val;
+            double *row = F + ((size_t)sz.idx[b] * ny + (GD == 3 ? sy.idx[q] : 0)) * nx;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) atomicAdd(row + sx.idx[m], (double)sx.w[m] * wzy);
+        }
+    }
+}
+
+template <typename T, int GD> AP_D void grid_stencils(const int ic[3], const T ov[3], const int32_t n[3],
+                                                     AxisStencil<T> sn[3], AxisStencil<T> sh[3]) {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (GD <= 2 && ax == 1) continue;
+        if (GD == 1 && ax == 2) {
+            // 1-D rows: the particle's own row, weight one, no gradient
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                sn[2].idx[m] = ic[2];
+                sn[2].w[m] = T(m == 0 ? 1 : 0);
+                sn[2].dw[m] = T(0);
+            }
+            sh[2] = sn[2];
+            continue;
+        }
+        axis_stencil(ic[ax], ov[ax], false, n[ax], sn[ax]);
+        axis_stencil(ic[ax], ov[ax], true, n[ax], sh[ax]);
+    }
+}
+
+template <typename T, int PT, int NT, int GD, bool PX, bool CPL>
+AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int lid = p;          // index of the particle's adjoint state
+    bool ok = p < a.n;
+    int ic[3] = {0, 0, 0};
+    T ov[3] = {T(0), T(0), T(0)};
+    if (GD > 0 && ok) {
+        // grid state: linear cell + offsets on the active axes; particles the
+        // push skipped (invalid cell or offset) keep their adjoint state
+        const int cell = a.G.cell[p];
+        lid = a.G.id[p];
+        ov[0] = a.off[0][p];
+        if (GD >= 2) ov[2] = a.off[2][p];
+        if (GD == 3) ov[1] = a.off[1][p];
+        const int nx = a.G.n[0], nxy = a.G.n[0] * a.G.n[1];
+        ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
+             ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)lid < (unsigned)a.n;
+        const int k = (int)a.G.fnxy.div((unsigned)cell);
+        const int r = cell - k * nxy;
+        const int j = (int)a.G.fnx.div((unsigned)r);
+        ic[0] = r - j * nx;
+        ic[1] = j;
+        ic[2] = k;
+    }
+    if (ok) {
+        using DN = Dual<T, NT>;
+        using IN = DualD<T, NT>;
+        IN Xd[3];
+        T u0v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (GD == 0) Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
+            else if (GD <= 2 && c == 1) Xd[c] = IN(a.G.q_slice);
+            else Xd[c] = IN(a.x_min[c] + ((double)ic[c] + (double)ov[c]) * a.dx[c]);
+            Xd[c].d[c] = T(1);
+            u0v[c] = a.u[c][p];
+        }
+        const double a0_eff = a.P.a0 != 0.0 ? a.P.a0 : 1.0;
+        const PulseVar<DN> W = adjoint_vars<T, NT>(a.P, a.t, a.slot, a0_eff);
+        DN E8[3], B8[3];
+        analytic_field_g<PT, DN, IN>(W, Xd[0], Xd[1], Xd[2], E8, B8);
+        // fields per unit amplitude (dF/da0), then at the actual amplitude
+        T Fu[6];
+        const T ascale = T(a.P.a0 / a0_eff), ia0 = T(1.0 / a0_eff);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Fu[c] = E8[c].v * ia0;
+            Fu[3 + c] = B8[c].v * ia0;
+            E8[c].v *= ascale;
+            B8[c].v *= ascale;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+                E8[c].d[k] *= ascale;
+                B8[c].d[k] *= ascale;
+            }
+        }
+        if (GD > 0) {
+            // recorded E2, B2: E_c sits half a cell up on axis c, B_c on
+            // nodes along c and half a cell up on the other axes
+            AxisStencil<T> sn[3], sh[3];
+            grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
+            const T idx_[3] = {T(1.0 / a.dx[0]), T(1.0 / a.dx[1]), T(1.0 / a.dx[2])};
+            // each field with its own stencils, written out so that no stencil
+            // is selected at run time (that selection put them in scratch memory)
+            auto add = [&](DN &F8, const T *F, const AxisStencil<T> &sx, const AxisStencil<T> &sy,
+                           const AxisStencil<T> &sz) {
+                T v, gr[3];
+                gather_grad<T, GD>(F, sx, sy, sz, a.G.n[0], a.G.n[1], v, gr);
+                F8.v += v;
+                F8.d[0] += gr[0] * idx_[0];
+                if (GD == 3) F8.d[1] += gr[1] * idx_[1];
+                if (GD >= 2) F8.d[2] += gr[2] * idx_[2];
+            };
+            add(E8[0], a.G.F[0], sh[0], sn[1], sn[2]);
+            add(E8[1], a.G.F[1], sn[0], sh[1], sn[2]);
+            add(E8[2], a.G.F[2], sn[0], sn[1], sh[2]);
+            add(B8[0], a.G.F[3], sn[0], sh[1], sh[2]);
+            add(B8[1], a.G.F[4], sh[0], sn[1], sh[2]);
+            add(B8[2], a.G.F[5], sh[0], sh[1], sn[2]);
+        }
+
+        // Boris Jacobian: tangents over (u0, E, B)
+        using D9 = Dual<T, 9>;
+        D9 uu[3], ee[3], bb[3], u1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            uu[c] = D9::var(u0v[c], c);
+            ee[c] = D9::var(E8[c].v, 3 + c);
+            bb[c] = D9::var(B8[c].v, 6 + c);
+        }
+        boris_g<D9>(uu, ee, bb, D9(0.5 * a.q_over_m * a.dt), u1);
+
+        double lx[3], lu1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lx[c] = a.lam[c][lid];
+            lu1[c] = a.lam[3 + c][lid];
+        }
+        // deposit (coupled reading): x^{n+1} and v from u1 as the forward move takes them
+        double gx0[3] = {0.0, 0.0, 0.0}, gv[3] = {0.0, 0.0, 0.0};
+        if constexpr (CPL && GD > 0) {
+            const T ig = rsqrt_r<T>(T(1) + u1[0].v * u1[0].v + u1[1].v * u1[1].v + u1[2].v * u1[2].v);
+            const T vt[3] = {u1[0].v * ig, u1[1].v * ig, u1[2].v * ig};
+            T dl[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
+                    const T d = vt[c] * T(a.dt / a.dx[c]);
+                    dl[c] = fabs(d) < T(1) ? d : T(0);   // the forward push holds a too-fast move
+                }
+            }
+            double gx1[3] = {0.0, 0.0, 0.0};
+            deposit_adjoint<T, GD>(a.lJ, a.G.n, ic, ov, dl, vt, a.q * (double)a.w[p], a.dt, a.dx, gx0, gx1, gv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
+                    lx[c] += gx1[c] / a.dx[c];
+                    gx0[c] /= a.dx[c];
+                }
+            }
+        }
+        // move: x^{n+1} = x^n + dt u1/gamma1 (and v of the out-of-plane current)
+        {
+            const double v1[3] = {(double)u1[0].v, (double)u1[1].v, (double)u1[2].v};
+            const double g1 = sqrt(1.0 + v1[0] * v1[0] + v1[1] * v1[1] + v1[2] * v1[2]);
+            const double vv[3] = {v1[0] / g1, v1[1] / g1, v1[2] / g1};
+            const double vl = vv[0] * lx[0] + vv[1] * lx[1] + vv[2] * lx[2];
+            const double vg = vv[0] * gv[0] + vv[1] * gv[1] + vv[2] * gv[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lu1[c] += (a.dt * (lx[c] - vv[c] * vl) + (gv[c] - vv[c] * vg)) / g1;
+        }
+        double lu0[3] = {0.0, 0.0, 0.0}, lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
+        if (PX && a.lam_proxy) {
+            const double lp = (double)a.lam_proxy[lid];
+            if (lp != 0.0) {
+                using D12 = Dual<T, 12>;
+                D12 q0[3], q1[3], qe[3], qb[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    q0[c] = D12::var(u0v[c], c);
+                    q1[c] = D12::var(u1[c].v, 3 + c);
+                    qe[c] = D12::var(E8[c].v, 6 + c);
+                    qb[c] = D12::var(B8[c].v, 9 + c);
+                }
+                const D12 P12 = proxy_g<D12>(q0, q1, qe, qb, D12(a.dt));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    lu0[c] += lp * (double)P12.d[c];
+                    lu1[c] += lp * (double)P12.d[3 + c];
+                    lE[c] += lp * (double)P12.d[6 + c];
+                    lB[c] += lp * (double)P12.d[9 + c];
+                }
+            }
+        }
+        // Boris adjoint
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lu0[c] += lu1[r] * (double)u1[r].d[c];
+                lE[c] += lu1[r] * (double)u1[r].d[3 + c];
+                lB[c] += lu1[r] * (double)u1[r].d[6 + c];
+            }
+        }
+        if constexpr (CPL && GD > 0) {
+            // the gather's adjoint into the grid adjoints of E2^n, B2^n
+            AxisStencil<T> sn[3], sh[3];
+            grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
+            const int nx = a.G.n[0], ny = a.G.n[1];
+            scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
+            scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
+            scatter_adjoint<T, GD>(a.lEg[2], sn[0], sn[1], sh[2], nx, ny, lE[2]);
+            scatter_adjoint<T, GD>(a.lBg[0], sn[0], sh[1], sh[2], nx, ny, lB[0]);
+            scatter_adjoint<T, GD>(a.lBg[1], sh[0], sn[1], sh[2], nx, ny, lB[1]);
+            scatter_adjoint<T, GD>(a.lBg[2], sh[0], sh[1], sn[2], nx, ny, lB[2]);
+        }
+        // field adjoint
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = lx[c] + gx0[c];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[c] + lB[k] * (double)B8[k].d[c];
+            // an (x, z) grid does not move y, 1-D rows move x only: those adjoints stay zero
+            if (GD == 0 || GD == 3 || c == 0 || (GD == 2 && c == 2)) a.lam[c][lid] = acc;
+            a.lam[3 + c][lid] = lu0[c];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[0] += lE[k] * (double)Fu[k] + lB[k] * (double)Fu[3 + k];
+#pragma unroll
+        for (int j = 0; j < NT - 3; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[3 + j] + lB[k] * (double)B8[k].d[3 + j];
+#pragma unroll
+            for (int q = 1; q < 5; ++q)
+                if (a.slot[j] == q) g[q] = acc;
+        }
+    }
+    // per-block FP64 sum, accumulated into this block's slot (no atomics)
+    __shared__ double red[5][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const double s = wave_sum(g[j]);
+        if (lane == 0) red[j][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
+        a.partial[(size_t)blockIdx.x * 5 + threadIdx.x] += s;
+    }
+}
+
+// FP32: two waves per SIMD (the compiler keeps the dual-number working set
+// in 256 registers with a few spills), measured faster than one wave without
+// spills.  FP64 needs twice the registers and runs best at one wave.  The
+// proxy term (PX) is a kernel of its own: its 12-tangent Jacobian would
+// otherwise raise the register demand of every launch.
+template <int PT, int NT, int GD, bool PX, bool CPL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step(AdjointArgs<float> a) {
+    adjoint_step_body<float, PT, NT, GD, PX, CPL>(a);
+}
+template <int PT, int NT, int GD, bool PX, bool CPL>
+__global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
+    adjoint_step_body<double, PT, NT, GD, PX, CPL>(a);
+}
+
+}  // namespace apt

@@ -49,6 +49,7 @@ struct RunShape {
     double q[kMaxSpecies] = {0, 0, 0, 0};
     double m[kMaxSpecies] = {1, 1, 1, 1};
     bool has_proxy[kMaxSpecies] = {false, false, false, false};   // gridded: species carries a proxy
+    int adj_mode = AP_ADJ_FROZEN;   // reading of the gridded adjoint (fixes the checkpoint layout)
 };
 
 struct WorkLayout {
@@ -235,17 +236,20 @@ WorkLayout make_layout(const RunShape &s) {
 // enters no step, so its adjoint is constant).
 struct GridCkpt {
     size_t lam[6] = {}, partial = 0, fixed = 0;
+    size_t lam_sp[kMaxSpecies][6] = {};   // coupled: adjoint state of every species
+    size_t lgrid = 0;                     // coupled: FP64 adjoints lE, lB, lJt (3 x ncell each)
     int blocks = 0;
     size_t outer = 0, inner = 0;
     size_t sp_off[kMaxSpecies] = {};   // species blocks inside a checkpoint slot
     size_t fields = 0;                 // E2, B2 inside a checkpoint slot (at 0 in a replay slot)
-    size_t inner_sp = 0;               // species block inside a replay slot
+    size_t inner_sp = 0;               // frozen: the differentiated species' block inside a replay slot
+    size_t inner_off[kMaxSpecies] = {};   // coupled: every species' block (with w) inside a replay slot
 };
 
-size_t sp_block_bytes(const RunShape &s, int i, bool with_w) {
+size_t sp_block_bytes(const RunShape &s, int i, bool with_w, bool with_proxy) {
     const size_t N = (size_t)s.np[i];
     const size_t nact = s.dim == 3 ? 3 : 2;
-    const size_t npr = (with_w && s.has_proxy[i]) ? 2 : 0;
+    const size_t npr = (with_proxy && s.has_proxy[i]) ? 2 : 0;
     return align_up(N * 8 + N * s.real * (nact + 3 + (with_w ? 1 : 0) + npr), 256);
 }
 
@@ -259,23 +263,32 @@ GridCkpt grid_ckpt(const RunShape &s) {
     };
     int64_t nmax = 0;
     for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
-    for (int c = 0; c < 6; ++c) G.lam[c] = take((size_t)nmax * 8);
+    const bool cpl = s.adj_mode == AP_ADJ_COUPLED;
+    if (cpl) {
+        for (int i = 0; i < s.nsp; ++i)
+            for (int c = 0; c < 6; ++c) G.lam_sp[i][c] = take((size_t)s.np[i] * 8);
+        G.lgrid = take((size_t)9 * (size_t)s.ncell * 8);
+    } else {
+        for (int c = 0; c < 6; ++c) G.lam[c] = take((size_t)nmax * 8);
+    }
     G.blocks = (int)((nmax + 255) / 256);
     if (G.blocks < 1) G.blocks = 1;
     G.partial = take((size_t)G.blocks * 5 * 8);
     G.fixed = align_up(off, 256);
     const size_t fbytes = align_up((size_t)6 * (size_t)s.ncell * s.real, 256);
-    size_t so = 0, mx = 0;
+    size_t so = 0, mx = 0, io = fbytes;
     for (int i = 0; i < s.nsp; ++i) {
         G.sp_off[i] = so;
-        so += sp_block_bytes(s, i, true);
-        const size_t b = sp_block_bytes(s, i, false);
+        so += sp_block_bytes(s, i, true, true);
+        const size_t b = sp_block_bytes(s, i, false, false);
         mx = b > mx ? b : mx;
+        G.inner_off[i] = io;
+        io += sp_block_bytes(s, i, true, false);
     }
     G.fields = so;
     G.outer = so + fbytes;
     G.inner_sp = fbytes;
-    G.inner = fbytes + mx;
+    G.inner = cpl ? io : fbytes + mx;
     return G;
 }
 
@@ -384,6 +397,9 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
 template <typename T>
 ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
                         double *out);
+template <typename T>
+ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                           double *out);
 
 double laguerre_host(int n, int a, double x) {
     double l0 = 1.0, l1 = 1.0 + a - x;
@@ -827,6 +843,21 @@ ap_status ap_set_checkpoints(ap_ctx *c, void *dev, size_t bytes, int32_t segment
     return AP_OK;
 }
 
+ap_status ap_set_adjoint_mode(ap_ctx *c, int32_t mode) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (mode != AP_ADJ_FROZEN && mode != AP_ADJ_COUPLED) return fail(AP_E_ARG, "unknown adjoint mode");
+    if (mode == AP_ADJ_COUPLED && c->s.dim == 0) return fail(AP_E_ARG, "the coupled reading needs a grid");
+    if (mode == AP_ADJ_COUPLED && (c->s.options & AP_GRID_OPEN_X))
+        return fail(AP_E_UNSUPPORTED, "the coupled adjoint is built for periodic grids");
+    c->s.adj_mode = mode;
+    // the checkpoint layout depends on the mode: a buffer must be set again
+    c->ckpt = nullptr;
+    c->ckpt_bytes = 0;
+    c->segment = 0;
+    c->rec_n = 0;
+    return AP_OK;
+}
+
 ap_status ap_checkpoint_bytes(const ap_ctx *c, int64_t n_steps, int32_t segment, size_t *bytes) {
     if (!c || !bytes) return fail(AP_E_ARG, "NULL argument");
     if (n_steps < 1 || segment < 1) return fail(AP_E_ARG, "n_steps and segment must be >= 1");
@@ -853,6 +884,10 @@ ap_status ap_backward(ap_ctx *c, int32_t species, const void *dl_du, const void 
     }
     if (c->P.type == PT_NONE) return fail(AP_E_STATE, "no pulse set");
     try {
+        if (c->s.dim > 0 && c->s.adj_mode == AP_ADJ_COUPLED)
+            return c->s.prec == AP_F64
+                       ? backward_coupled<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
+                       : backward_coupled<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
         if (c->s.dim > 0)
             return c->s.prec == AP_F64 ? backward_grid<double>(c, species, dl_du, dl_dproxy, param_ids, n_params, out)
                                        : backward_grid<float>(c, species, dl_du, dl_dproxy, param_ids, n_params, out);
@@ -1068,7 +1103,8 @@ template <typename T> struct SpBlock {
 };
 
 // Species i's arrays inside a slot block that starts at base.
-template <typename T> SpBlock<T> sp_block(unsigned char *base, const RunShape &s, int i, bool with_w) {
+template <typename T>
+SpBlock<T> sp_block(unsigned char *base, const RunShape &s, int i, bool with_w, bool with_proxy) {
     SpBlock<T> b{};
     const size_t N = (size_t)s.np[i];
     b.cell = reinterpret_cast<int32_t *>(base);
@@ -1084,7 +1120,7 @@ template <typename T> SpBlock<T> sp_block(unsigned char *base, const RunShape &s
     }
     b.w = with_w ? r : nullptr;
     if (b.w) r += N;
-    b.proxy = (with_w && s.has_proxy[i]) ? r : nullptr;
+    b.proxy = (with_proxy && s.has_proxy[i]) ? r : nullptr;
     return b;
 }
 
@@ -1134,7 +1170,7 @@ template <typename T> ap_status save_ckpt(ap_ctx *c, unsigned char *slot, bool r
     const RunShape &s = c->s;
     const GridCkpt G = grid_ckpt(s);
     for (int i = 0; i < s.nsp; ++i) {
-        const SpBlock<T> live = live_block<T>(c, i), blk = sp_block<T>(slot + G.sp_off[i], s, i, true);
+        const SpBlock<T> live = live_block<T>(c, i), blk = sp_block<T>(slot + G.sp_off[i], s, i, true, true);
         const ap_status st = restore ? copy_block<T>(c, live, blk, (size_t)s.np[i], true)
                                      : copy_block<T>(c, blk, live, (size_t)s.np[i], true);
         if (st != AP_OK) return st;
@@ -1152,8 +1188,19 @@ template <typename T> ap_status save_replay(ap_ctx *c, unsigned char *slot, int 
     const GridCkpt G = grid_ckpt(s);
     HIPCHK(hipMemcpyAsync(slot, c->buf.grid, (size_t)6 * (size_t)s.ncell * sizeof(T), hipMemcpyDeviceToDevice,
                           c->stream), "replay copy");
-    return copy_block<T>(c, sp_block<T>(slot + G.inner_sp, s, sp, false), live_block<T>(c, sp), (size_t)s.np[sp],
-                         false);
+    if (s.adj_mode == AP_ADJ_COUPLED) {
+        // every species, with weights (they scale the current)
+        for (int i = 0; i < s.nsp; ++i) {
+            SpBlock<T> live = live_block<T>(c, i);
+            live.proxy = nullptr;
+            const ap_status st =
+                copy_block<T>(c, sp_block<T>(slot + G.inner_off[i], s, i, true, false), live, (size_t)s.np[i], true);
+            if (st != AP_OK) return st;
+        }
+        return AP_OK;
+    }
+    return copy_block<T>(c, sp_block<T>(slot + G.inner_sp, s, sp, false, false), live_block<T>(c, sp),
+                         (size_t)s.np[sp], false);
 }
 
 // Reverse sweep of a recorded gridded run (frozen-grid reading).  Each
@@ -1213,7 +1260,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
         }
         for (int64_t j = len - 1; j >= 0; --j) {
             unsigned char *slot_j = ckpt_inner(c, j);
-            const SpBlock<T> b = sp_block<T>(slot_j + G.inner_sp, s, sp, false);
+            const SpBlock<T> b = sp_block<T>(slot_j + G.inner_sp, s, sp, false, false);
             const T *F = reinterpret_cast<const T *>(slot_j);
             AdjointArgs<T> a{};
             for (int k = 0; k < 3; ++k) {
@@ -1242,6 +1289,137 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
             a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
             a.P = c->P;
             HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+        }
+    }
+    st = save_ckpt<T>(c, ckpt_final(c), true);
+    if (st != AP_OK) return st;
+    c->step = c->rec_step0 + c->rec_n;
+    c->need_sort = true;
+    HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
+    double *sums = c->wp<double>(c->L.sums);
+    HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
+    double host[5];
+    HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, c->stream), "backward");
+    HIPCHK(hipStreamSynchronize(c->stream), "backward");
+    const double unit[5] = {1.0, kTwoPi, kTwoPi, 1.0, 1.0};
+    for (int k = 0; k < np_; ++k) out[k] = host[ids[k]] * unit[ids[k]];
+    return AP_OK;
+}
+
+// Reverse sweep in the fully coupled reading: every species' adjoint state and
+// the FP64 grid adjoints of E2, B2 run backwards together.  Per reverse step:
+// the transposed Yee step (leaving dL/dJ = -dt lJt), then for each species
+// the particle adjoint, which reads lJt through its current and adds its
+// gather's adjoint to lE, lB.  Replay slots hold every species with weights.
+template <typename T>
+ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
+                           double *out) {
+    const RunShape &s = c->s;
+    const GridCkpt G = grid_ckpt(s);
+    const size_t nc = (size_t)s.ncell;
+    unsigned long long *cnt = c->counters();
+    unsigned long long saved[kCounters];
+    HIPCHK(hipMemcpyAsync(saved, cnt, sizeof(saved), hipMemcpyDeviceToHost, c->stream), "backward");
+    for (int i = 0; i < s.nsp; ++i) {
+        // each adjoint state is indexed by particle id: ids must be 0..n-1, each once
+        if (s.np[i] == 0) continue;
+        int32_t *seen = c->wp<int32_t>(c->L.rank[i]);
+        HIPCHK(launch_fill_zero<int32_t>(seen, (size_t)s.np[i], c->stream), "backward");
+        HIPCHK(launch_fill_zero<unsigned long long>(cnt + 5, 1, c->stream), "backward");
+        HIPCHK(launch_check_ids(c->buf.sp[i].id, (int)s.np[i], seen, cnt + 5, c->stream), "backward");
+        unsigned long long bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, cnt + 5, sizeof(bad), hipMemcpyDeviceToHost, c->stream), "backward");
+        HIPCHK(hipStreamSynchronize(c->stream), "backward");
+        if (bad != 0) {
+            HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
+            return fail(AP_E_ARG, "particle ids of species " + std::to_string(i) + " are not a permutation of 0..n-1");
+        }
+    }
+    double *lam[kMaxSpecies][6];
+    for (int i = 0; i < s.nsp; ++i)
+        for (int k = 0; k < 6; ++k) lam[i][k] = reinterpret_cast<double *>(c->ckpt + G.lam_sp[i][k]);
+    double *lE = reinterpret_cast<double *>(c->ckpt + G.lgrid), *lB = lE + 3 * nc, *lJt = lE + 6 * nc;
+    double *partial = reinterpret_cast<double *>(c->ckpt + G.partial);
+    int32_t slot[4] = {-1, -1, -1, -1};
+    int nslot = 0;
+    for (int k = 0; k < np_; ++k)
+        if (ids[k] != AP_PARAM_A0) slot[nslot++] = ids[k];
+    ap_status st = save_ckpt<T>(c, ckpt_final(c));
+    if (st != AP_OK) return st;
+    HIPCHK(launch_fill_zero<double>(partial, (size_t)G.blocks * 5, c->stream), "backward");
+    HIPCHK(launch_fill_zero<double>(lE, 9 * nc, c->stream), "backward");
+    for (int i = 0; i < s.nsp; ++i) {
+        if (i == sp) {
+            HIPCHK(launch_adjoint_init<T>(lam[i], static_cast<const T *>(dl_du), (int)s.np[i], c->stream), "backward");
+        } else {
+            for (int k = 0; k < 6; ++k) HIPCHK(launch_fill_zero<double>(lam[i][k], (size_t)s.np[i], c->stream), "backward");
+        }
+    }
+    YeeArgsBase yb{};
+    for (int k = 0; k < 3; ++k) {
+        yb.n[k] = s.n[k];
+        yb.dx[k] = s.dx[k];
+    }
+    yb.dt = s.dt;
+    const int64_t K = c->segment;
+    const int64_t nseg = (c->rec_n + K - 1) / K;
+    const FastDiv fnx((uint32_t)s.n[0]), fnxy((uint32_t)(s.n[0] * s.n[1]));
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = seg * K;
+        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+        st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
+        if (st != AP_OK) return st;
+        c->step = c->rec_step0 + s0;
+        c->need_sort = true;
+        for (int64_t j = 0; j < len; ++j) {
+            st = save_replay<T>(c, ckpt_inner(c, j), sp);
+            if (st != AP_OK) return st;
+            if (j + 1 < len) {
+                st = step_gridded<T>(c, 0);
+                if (st != AP_OK) return st;
+                c->step++;
+            }
+        }
+        for (int64_t j = len - 1; j >= 0; --j) {
+            unsigned char *slot_j = ckpt_inner(c, j);
+            const T *F = reinterpret_cast<const T *>(slot_j);
+            HIPCHK(launch_yee_adjoint(s.dim, lE, lB, lJt, yb, c->stream), "backward yee");
+            for (int i = 0; i < s.nsp; ++i) {
+                if (s.np[i] == 0) continue;
+                const SpBlock<T> b = sp_block<T>(slot_j + G.inner_off[i], s, i, true, false);
+                AdjointArgs<T> a{};
+                for (int k = 0; k < 3; ++k) {
+                    a.off[k] = b.off[k];
+                    a.u[k] = b.u[k];
+                    a.dx[k] = s.dx[k];
+                    a.x_min[k] = s.x_min[k];
+                    a.G.n[k] = s.n[k];
+                    a.lJ[k] = lJt + (size_t)k * nc;
+                    a.lEg[k] = lE + (size_t)k * nc;
+                    a.lBg[k] = lB + (size_t)k * nc;
+                }
+                for (int k = 0; k < 6; ++k) {
+                    a.lam[k] = lam[i][k];
+                    a.G.F[k] = F + (size_t)k * nc;
+                }
+                a.G.cell = b.cell;
+                a.G.id = b.id;
+                a.G.fnx = fnx;
+                a.G.fnxy = fnxy;
+                a.G.q_slice = c->P.q_slice;
+                a.w = b.w;
+                a.q = s.q[i];
+                a.dim = s.dim;
+                a.lam_proxy = i == sp ? static_cast<const T *>(dl_dproxy) : nullptr;
+                a.partial = partial;
+                for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
+                a.n = (int)s.np[i];
+                a.q_over_m = s.q[i] / s.m[i];
+                a.dt = s.dt;
+                a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
+                a.P = c->P;
+                HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+            }
         }
     }
     st = save_ckpt<T>(c, ckpt_final(c), true);

@@ -151,6 +151,42 @@ hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, 
 template hipError_t launch_yee<float>(int, float *const[9], const YeeArgsBase &, int, hipStream_t);
 template hipError_t launch_yee<double>(int, double *const[9], const YeeArgsBase &, int, hipStream_t);
 
+// Reverse of the split Yee step (B half, E full, B half) for the adjoints
+// (lE, lB) of (E, B).  The discrete curls are transposes of each other
+// (C_B = C_E^T on a periodic Yee grid), so the transposed step is
+//     lE <- lE - (dt/2) C_B lB;   lJt = lE;   lB <- lB + dt C_E lE;   lE <- lE - (dt/2) C_B lB
+// with dL/dJ^{n+1/2} = -dt lJt.  The forward kernels run it with negated
+// coefficients (k_yee_e adds c C_B B - dt J: here c = -(dt/2)/dx and no J;
+// k_yee_b subtracts h C_E E: here h = -dt/dx).
+hipError_t launch_yee_adjoint(int dim, double *lE, double *lB, double *lJt, const YeeArgsBase &a, hipStream_t s) {
+    YeeIdx g;
+    g.nx = a.n[0];
+    g.ny = dim == 3 ? a.n[1] : 1;
+    g.nz = a.n[2];
+    g.fnx = FastDiv((uint32_t)g.nx);
+    g.fny = FastDiv((uint32_t)g.ny);
+    const size_t nc = (size_t)g.nx * g.ny * g.nz;
+    const int blocks = grid_blocks(nc);
+    double *E0 = lE, *E1 = lE + nc, *E2 = lE + 2 * nc, *B0 = lB, *B1 = lB + nc, *B2 = lB + 2 * nc;
+    const double ex = -0.5 * a.dt / a.dx[0], ey = -0.5 * a.dt / a.dx[1], ez = dim == 1 ? 0.0 : -0.5 * a.dt / a.dx[2];
+    const double bx = -a.dt / a.dx[0], by = -a.dt / a.dx[1], bz = dim == 1 ? 0.0 : -a.dt / a.dx[2];
+    if (dim == 3) {
+        hipLaunchKernelGGL((k_yee_e<double, 3>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, lJt, lJt + nc, lJt + 2 * nc, g, ex, ey, ez, 0.0, nc, 0, (const double *)nullptr, 1.0);
+    } else {
+        hipLaunchKernelGGL((k_yee_e<double, 2>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, lJt, lJt + nc, lJt + 2 * nc, g, ex, ey, ez, 0.0, nc, 0, (const double *)nullptr, 1.0);
+    }
+    hipError_t e = hipMemcpyAsync(lJt, lE, 3 * nc * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    if (dim == 3) {
+        hipLaunchKernelGGL((k_yee_b<double, 3>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, g, bx, by, bz, nc, 0);
+        hipLaunchKernelGGL((k_yee_e<double, 3>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, lJt, lJt + nc, lJt + 2 * nc, g, ex, ey, ez, 0.0, nc, 0, (const double *)nullptr, 1.0);
+    } else {
+        hipLaunchKernelGGL((k_yee_b<double, 2>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, g, bx, by, bz, nc, 0);
+        hipLaunchKernelGGL((k_yee_e<double, 2>), dim3(blocks), dim3(256), 0, s, E0, E1, E2, B0, B1, B2, lJt, lJt + nc, lJt + 2 * nc, g, ex, ey, ez, 0.0, nc, 0, (const double *)nullptr, 1.0);
+    }
+    return hipGetLastError();
+}
+
 template <typename T> __global__ void k_fill_zero(T *p, size_t n) {
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
         p[c] = T(0);

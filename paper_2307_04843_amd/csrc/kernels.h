@@ -137,10 +137,18 @@ template <typename T> struct AdjointArgs {
     double dt;
     double t;
     PulseDev P;
-    int32_t dim;                 // 0 (gridless), 2 or 3 (grid: G is used, icell is not)
+    int32_t dim;                 // 0 (gridless), 1, 2 or 3 (grid: G is used, icell is not)
     AdjointGrid<T> G;
+    // fully coupled reading of gridded runs (lJ[0] != null): the deposit and
+    // the gather are differentiated as well
+    const T *w;                  // particle weights, same order as off/u
+    double q;                    // species charge
+    const double *lJ[3];         // E adjoint after the first half of the reverse Yee step (E nodes)
+    double *lEg[3], *lBg[3];     // grid adjoints of E2^n, B2^n: the gather's adjoint is added here
 };
 template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_adjoint_step_coupled(int pulse, const AdjointArgs<T> &a, hipStream_t s);
+
 // Checks that id[0..n) is a permutation of 0..n-1: seen[] (n ints, zeroed by
 // the caller) counts each id; *bad counts ids out of range or repeated.
 hipError_t launch_check_ids(const int32_t *id, int n, int32_t *seen, unsigned long long *bad, hipStream_t s);
@@ -165,6 +173,10 @@ template <typename T> struct BoundaryArgs {
     PulseVar<T> W;               // pulse constants at t^{n+1/2}
 };
 template <typename T> hipError_t launch_boundary_source(int pulse, const BoundaryArgs<T> &a, hipStream_t s);
+// Reverse split Yee step on FP64 adjoints (lE, lB: 3 x ncell each): from the
+// adjoints of E^{n+1}, B^{n+1} to those of E^n, B^n, leaving in lJt the E
+// adjoint after its first half (dL/dJ^{n+1/2} = -dt lJt).  Periodic grids.
+hipError_t launch_yee_adjoint(int dim, double *lE, double *lB, double *lJt, const YeeArgsBase &a, hipStream_t s);
 
 // launchers (hipStream_t passed through)
 template <typename T>

@@ -163,10 +163,14 @@ class Simulation:
         return out
 
     def close(self):
+        """Destroy the context and drop the device buffers (state() and the
+        field views are unavailable afterwards)."""
         if getattr(self, "ctx", None):
             torch.cuda.synchronize(self.device)
             apt.ap_destroy(self.ctx)
             self.ctx = None
+            self.grid = self.work = None
+            self.arrays = []
 
     def __del__(self):
         try:
