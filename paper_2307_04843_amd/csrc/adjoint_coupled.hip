@@ -9,12 +9,24 @@ namespace apt {
 template <typename T, int PT, int GD> static void launch_cpl_gd(const AdjointArgs<T> &a, int np, hipStream_t s) {
     const dim3 grid((a.n + 255) / 256), block(256);
     const bool px = a.lam_proxy != nullptr;
+    // 2-D and 3-D stage the gather's adjoint in LDS
+    const size_t sh = GD >= 2 ? (size_t)kAdjLdsDoubles * sizeof(double) : 0;
+    if constexpr (GD == 3) {
+        if (np <= 2) {
+            if (px) hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 5, true, T>), grid, block, sh, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 5, false, T>), grid, block, sh, s, a);
+        } else {
+            if (px) hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 7, true, T>), grid, block, sh, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 7, false, T>), grid, block, sh, s, a);
+        }
+        return;
+    }
     if (np <= 2) {
-        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, false, true>), grid, block, 0, s, a);
+        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, true, true>), grid, block, sh, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, false, true>), grid, block, sh, s, a);
     } else {
-        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, false, true>), grid, block, 0, s, a);
+        if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, true, true>), grid, block, sh, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, false, true>), grid, block, sh, s, a);
     }
 }
 

@@ -204,118 +204,168 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
                           const T dl[3], const T v[3], double qw, double dt, const double dx[3], double gx0[3],
                           double gx1[3], double gv[3]) {
     constexpr int NA = GD == 3 ? 3 : (GD == 2 ? 2 : 1);
-    using D = Dual<T, 2 * NA>;
     const int ax[3] = {0, GD == 3 ? 1 : 2, 2};
-    T s0v[NA][5], s0d[NA][5], s1v[NA][5], s1d[NA][5];
+    // per active slot: window start (node c - 2, unwrapped) and the positions
+    // before / after the step relative to the window centre c
+    T x0[NA], x1[NA];
     int cb[NA];
 #pragma unroll
     for (int s = 0; s < NA; ++s) {
         const int A = ax[s];
         const int up = ov[A] >= T(0.5) ? 1 : 0;
         cb[s] = ic[A] + up - 2;
-        const T x0 = ov[A] - T(up), x1 = x0 + dl[A];
-#pragma unroll
-        for (int m = 0; m < 5; ++m) {
-            tsc_vd(x0 - T(m - 2), s0v[s][m], s0d[s][m]);
-            tsc_vd(x1 - T(m - 2), s1v[s][m], s1d[s][m]);
-        }
+        x0[s] = ov[A] - T(up);
+        x1[s] = x0[s] + dl[A];
     }
-    auto S0 = [&](int s, int m) {
-        D r(s0v[s][m]);
-        r.d[s] = s0d[s][m];
-        return r;
-    };
-    auto S1 = [&](int s, int m) {
-        D r(s1v[s][m]);
-        r.d[NA + s] = s1d[s][m];
-        return r;
-    };
     const int nx = n[0], ny = n[1], nz = n[2];
-    D G(0.0);
+    // shapes of window node m (0..4) on slot s, and their derivatives in x0, x1
+    auto shp = [&](int s, int m, T &a0, T &d0, T &a1, T &d1) {
+        tsc_vd(x0[s] - T(m - 2), a0, d0);
+        tsc_vd(x1[s] - T(m - 2), a1, d1);
+    };
+    const double T3 = 1.0 / 3.0, T6 = 1.0 / 6.0;
     if constexpr (GD == 1) {
-        // a row: x moves; y and z carry q w v times the mean shape
+        // a row: J_x from the x shapes; y and z carry q w v times the mean shape
         const double *ex = lE_t[0] + (size_t)ic[2] * nx;
         const double *ey = lE_t[1] + (size_t)ic[2] * nx;
         const double *ez = lE_t[2] + (size_t)ic[2] * nx;
-        double suf = 0.0;
-        D Gy(0.0), Gz(0.0);
+        double suf = 0.0, g0 = 0.0, g1 = 0.0, sy = 0.0, sz = 0.0, y0 = 0.0, y1 = 0.0, z0 = 0.0, z1 = 0.0;
 #pragma unroll
         for (int m = 4; m >= 0; --m) {
+            T a0, d0, a1, d1;
+            shp(0, m, a0, d0, a1, d1);
             const int i = wrap_idx(cb[0] + m, nx);
             suf += ex[i];
-            G += (S1(0, m) - S0(0, m)) * T(qw * dx[0] * suf);
-            const D mean = T(0.5) * (S0(0, m) + S1(0, m));
-            Gy += mean * T(ey[i]);
-            Gz += mean * T(ez[i]);
+            g0 -= (double)d0 * suf;
+            g1 += (double)d1 * suf;
+            const double mean = 0.5 * ((double)a0 + (double)a1);
+            sy += mean * ey[i];
+            sz += mean * ez[i];
+            y0 += 0.5 * (double)d0 * ey[i];
+            y1 += 0.5 * (double)d1 * ey[i];
+            z0 += 0.5 * (double)d0 * ez[i];
+            z1 += 0.5 * (double)d1 * ez[i];
         }
-        const double cy = -dt * qw;
-        G += Gy * T(cy * (double)v[1]) + Gz * T(cy * (double)v[2]);
-        gv[1] = cy * (double)Gy.v;
-        gv[2] = cy * (double)Gz.v;
+        const double cj = qw * dx[0], cy = -dt * qw;
+        gx0[0] = cj * g0 + cy * ((double)v[1] * y0 + (double)v[2] * z0);
+        gx1[0] = cj * g1 + cy * ((double)v[1] * y1 + (double)v[2] * z1);
+        gv[1] = cy * sy;
+        gv[2] = cy * sz;
     } else if constexpr (GD == 2) {
-        // J_x: suffix sums of lE~_x along x, per z
-#pragma unroll
+        double g[4] = {0.0, 0.0, 0.0, 0.0};   // d/d(x0, z0, x1, z1)
+        const double cx = qw * dx[0], cz = qw * dx[2], cy = -dt * qw * (double)v[1];
+        double sy = 0.0;
+        // J_x: per z node, suffix sums of lE~_x along x
+#pragma unroll 1
         for (int k = 0; k < 5; ++k) {
-            const size_t row = (size_t)wrap_idx(cb[1] + k, nz) * nx;
-            const D zm = T(0.5) * (S0(1, k) + S1(1, k));
-            double suf = 0.0;
+            T za0, zd0, za1, zd1;
+            shp(1, k, za0, zd0, za1, zd1);
+            const double *row = lE_t[0] + (size_t)wrap_idx(cb[1] + k, nz) * nx;
+            double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
 #pragma unroll
             for (int m = 4; m >= 0; --m) {
-                suf += lE_t[0][row + wrap_idx(cb[0] + m, nx)];
-                G += (S1(0, m) - S0(0, m)) * zm * T(qw * dx[0] * suf);
+                T xa0, xd0, xa1, xd1;
+                shp(0, m, xa0, xd0, xa1, xd1);
+                suf += row[wrap_idx(cb[0] + m, nx)];
+                av += (double)(xa1 - xa0) * suf;
+                a0 -= (double)xd0 * suf;
+                a1 += (double)xd1 * suf;
             }
+            const double zm = 0.5 * ((double)za0 + (double)za1);
+            g[0] += cx * zm * a0;
+            g[2] += cx * zm * a1;
+            g[1] += cx * 0.5 * (double)zd0 * av;
+            g[3] += cx * 0.5 * (double)zd1 * av;
         }
-        // J_z: suffix sums along z, per x; J_y: q w v_y times the mean shape product
-        D Gy(0.0);
-#pragma unroll
+        // J_z: per x node, suffix sums along z; J_y: q w v_y times the mean shape product
+#pragma unroll 1
         for (int m = 0; m < 5; ++m) {
+            T xa0, xd0, xa1, xd1;
+            shp(0, m, xa0, xd0, xa1, xd1);
             const int i = wrap_idx(cb[0] + m, nx);
-            const D x0 = S0(0, m), x1 = S1(0, m);
-            const D xm = T(0.5) * (x0 + x1);
-            double suf = 0.0;
+            double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
+            double p0 = 0.0, p1 = 0.0, r0 = 0.0, r1 = 0.0;   // sums over z for J_y
 #pragma unroll
             for (int k = 4; k >= 0; --k) {
+                T za0, zd0, za1, zd1;
+                shp(1, k, za0, zd0, za1, zd1);
                 const size_t c = (size_t)wrap_idx(cb[1] + k, nz) * nx + i;
                 suf += lE_t[2][c];
-                const D z0 = S0(1, k), z1 = S1(1, k);
-                G += (z1 - z0) * xm * T(qw * dx[2] * suf);
-                const D sa = T(1.0 / 3.0) * (x0 * z0 + x1 * z1) + T(1.0 / 6.0) * (x1 * z0 + x0 * z1);
-                Gy += sa * T(lE_t[1][c]);
+                av += (double)(za1 - za0) * suf;
+                a0 -= (double)zd0 * suf;
+                a1 += (double)zd1 * suf;
+                const double ly = lE_t[1][c];
+                p0 += ly * (T3 * (double)za0 + T6 * (double)za1);   // pairs with X0
+                p1 += ly * (T6 * (double)za0 + T3 * (double)za1);   // pairs with X1
+                r0 += ly * (double)zd0;
+                r1 += ly * (double)zd1;
             }
+            const double xm = 0.5 * ((double)xa0 + (double)xa1);
+            g[1] += cz * xm * a0;
+            g[3] += cz * xm * a1;
+            g[0] += cz * 0.5 * (double)xd0 * av;
+            g[2] += cz * 0.5 * (double)xd1 * av;
+            sy += (double)xa0 * p0 + (double)xa1 * p1;
+            g[0] += cy * (double)xd0 * p0;
+            g[2] += cy * (double)xd1 * p1;
+            g[1] += cy * r0 * (T3 * (double)xa0 + T6 * (double)xa1);
+            g[3] += cy * r1 * (T6 * (double)xa0 + T3 * (double)xa1);
         }
-        const double cy = -dt * qw;
-        G += Gy * T(cy * (double)v[1]);
-        gv[1] = cy * (double)Gy.v;
+        gx0[0] = g[0];
+        gx0[2] = g[1];
+        gx1[0] = g[2];
+        gx1[2] = g[3];
+        gv[1] = -dt * qw * sy;
     } else {
-        // 3-D: W_A = DS_A (1/3 P0 Q0 + 1/6 P1 Q0 + 1/6 P0 Q1 + 1/3 P1 Q1) over the other two axes
+        // 3-D: W_A = DS_A tr(P, Q), tr = 1/3 (P0 Q0 + P1 Q1) + 1/6 (P1 Q0 + P0 Q1) over the
+        // other two axes; per (b, c) the suffix-weighted sum along A carries the
+        // two A tangents, tr the four others
+        double gd[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const int s1 = s == 0 ? 1 : 0, s2 = s == 2 ? 1 : 2;   // the two other slots
-            const double coef = qw * dx[ax[s]];
-#pragma unroll
+            const int s1 = s == 0 ? 1 : 0, s2 = s == 2 ? 1 : 2;   // the two other axes
+            const int n_s = s == 0 ? nx : (s == 1 ? ny : nz);
+            const int n_1 = s1 == 0 ? nx : (s1 == 1 ? ny : nz);
+            const int n_2 = s2 == 0 ? nx : (s2 == 1 ? ny : nz);
+            const double coef = qw * dx[s];
+#pragma unroll 1
             for (int b = 0; b < 5; ++b) {
-#pragma unroll
+                T p0, dp0, p1, dp1;
+                shp(s1, b, p0, dp0, p1, dp1);
+                const int i1 = wrap_idx(cb[s1] + b, n_1);
+#pragma unroll 1
                 for (int c = 0; c < 5; ++c) {
-                    const D p0 = S0(s1, b), p1 = S1(s1, b), q0 = S0(s2, c), q1 = S1(s2, c);
-                    const D tr = T(1.0 / 3.0) * (p0 * q0 + p1 * q1) + T(1.0 / 6.0) * (p1 * q0 + p0 * q1);
+                    T q0, dq0, q1, dq1;
+                    shp(s2, c, q0, dq0, q1, dq1);
+                    const double tr = T3 * ((double)p0 * q0 + (double)p1 * q1) + T6 * ((double)p1 * q0 + (double)p0 * q1);
                     int id3[3];
-                    id3[s1] = wrap_idx(cb[s1] + b, s1 == 0 ? nx : (s1 == 1 ? ny : nz));
-                    id3[s2] = wrap_idx(cb[s2] + c, s2 == 0 ? nx : (s2 == 1 ? ny : nz));
-                    double suf = 0.0;
+                    id3[s1] = i1;
+                    id3[s2] = wrap_idx(cb[s2] + c, n_2);
+                    double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
 #pragma unroll
                     for (int m = 4; m >= 0; --m) {
-                        id3[s] = wrap_idx(cb[s] + m, s == 0 ? nx : (s == 1 ? ny : nz));
+                        T sa0, sd0, sa1, sd1;
+                        shp(s, m, sa0, sd0, sa1, sd1);
+                        id3[s] = wrap_idx(cb[s] + m, n_s);
                         suf += lE_t[s][((size_t)id3[2] * ny + id3[1]) * nx + id3[0]];
-                        G += (S1(s, m) - S0(s, m)) * tr * T(coef * suf);
+                        av += (double)(sa1 - sa0) * suf;
+                        a0 -= (double)sd0 * suf;
+                        a1 += (double)sd1 * suf;
                     }
+                    gd[s] += coef * tr * a0;
+                    gd[3 + s] += coef * tr * a1;
+                    gd[s1] += coef * av * (double)dp0 * (T3 * (double)q0 + T6 * (double)q1);
+                    gd[3 + s1] += coef * av * (double)dp1 * (T3 * (double)q1 + T6 * (double)q0);
+                    gd[s2] += coef * av * (double)dq0 * (T3 * (double)p0 + T6 * (double)p1);
+                    gd[3 + s2] += coef * av * (double)dq1 * (T3 * (double)p1 + T6 * (double)p0);
                 }
             }
         }
-    }
 #pragma unroll
-    for (int s = 0; s < NA; ++s) {
-        gx0[ax[s]] = (double)G.d[s];
-        gx1[ax[s]] = (double)G.d[NA + s];
+        for (int k = 0; k < 3; ++k) {
+            gx0[k] = gd[k];
+            gx1[k] = gd[3 + k];
+        }
     }
 }
 
@@ -332,6 +382,35 @@ AP_D void scatter_adjoint(double *F, const AxisStencil<T> &sx, const AxisStencil
             double *row = F + ((size_t)sz.idx[b] * ny + (GD == 3 ? sy.idx[q] : 0)) * nx;
 #pragma unroll
             for (int m = 0; m < 3; ++m) atomicAdd(row + sx.idx[m], (double)sx.w[m] * wzy);
+        }
+    }
+}
+
+// LDS staging of the gather's adjoint (coupled 2-D/3-D): a block's particles
+// are nearly tile-sorted, so their stencils cover a small box of nodes; the
+// block accumulates there and flushes each node once.
+constexpr int kAdjLdsDoubles = 6144;   // 48 KiB: six components of up to 1024 nodes
+struct AdjRegion {
+    int lo[3], ext[3], n[3];
+    AP_D int local(int ax, int idx) const {
+        int l = idx - lo[ax];
+        if (l < 0) l += n[ax];
+        else if (l >= n[ax]) l -= n[ax];
+        return l;
+    }
+};
+template <typename T, int GD>
+AP_D void scatter_adjoint_lds(double *L, int comp, const AdjRegion &R, const AxisStencil<T> &sx,
+                              const AxisStencil<T> &sy, const AxisStencil<T> &sz, double val) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int q = 0; q < (GD == 3 ? 3 : 1); ++q) {
+            const double wzy = (double)sz.w[b] * (GD == 3 ? (double)sy.w[q] : 1.0) * val;
+            const int l2 = R.local(2, sz.idx[b]), l1 = GD == 3 ? R.local(1, sy.idx[q]) : 0;
+            double *row = L + (((size_t)comp * R.ext[2] + l2) * R.ext[1] + l1) * R.ext[0];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) atomicAdd(row + R.local(0, sx.idx[m]), (double)sx.w[m] * wzy);
         }
     }
 }
@@ -383,6 +462,49 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
         ic[1] = j;
         ic[2] = k;
     }
+    // coupled 2-D/3-D: the block's bounding box of cells fixes its LDS region
+    AdjRegion R{};
+    bool use_lds = false;
+    int vol = 0;
+    double *lds_adj = nullptr;
+    if constexpr (CPL && GD >= 2) {
+        extern __shared__ double adj_dyn[];
+        lds_adj = adj_dyn;
+        __shared__ int bbox[6];
+        if (threadIdx.x < 3) {
+            bbox[threadIdx.x] = 0x7fffffff;
+            bbox[3 + threadIdx.x] = -0x7fffffff;
+        }
+        __syncthreads();
+        if (ok) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                atomicMin(&bbox[ax], ic[ax]);
+                atomicMax(&bbox[3 + ax], ic[ax]);
+            }
+        }
+        __syncthreads();
+        bool fits = true;
+        vol = 6;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            R.n[ax] = a.G.n[ax];
+            if (GD == 2 && ax == 1) {
+                R.lo[1] = 0;
+                R.ext[1] = 1;
+                continue;
+            }
+            // stencil nodes reach one below the lowest cell and two above the highest
+            R.lo[ax] = bbox[ax] - 1;
+            R.ext[ax] = bbox[3 + ax] - bbox[ax] + 4;
+            fits = fits && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
+            vol *= R.ext[ax];
+        }
+        use_lds = fits && vol <= kAdjLdsDoubles;
+        if (use_lds)
+            for (int i = threadIdx.x; i < vol; i += blockDim.x) lds_adj[i] = 0.0;
+        __syncthreads();
+    }
     if (ok) {
         using DN = Dual<T, NT>;
         using IN = DualD<T, NT>;
@@ -395,6 +517,46 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             else Xd[c] = IN(a.x_min[c] + ((double)ic[c] + (double)ov[c]) * a.dx[c]);
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
+        }
+        // coupled reading: the current's adjoint first, from a value-only pass
+        // (push and move as the forward step takes them), so that its working
+        // set does not overlap the dual-number one below
+        double gx0[3] = {0.0, 0.0, 0.0}, gx1[3] = {0.0, 0.0, 0.0}, gv[3] = {0.0, 0.0, 0.0};
+        if constexpr (CPL && GD > 0) {
+            T ev[3], bv[3];
+            analytic_field<PT, T>(plain_vars<T>(a.P, a.t), Xd[0].v, Xd[1].v, Xd[2].v, ev, bv);
+            {
+                AxisStencil<T> sn[3], sh[3];
+                grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
+                T gr[3], gvv;
+                const int nx = a.G.n[0], ny = a.G.n[1];
+                gather_grad<T, GD>(a.G.F[0], sh[0], sn[1], sn[2], nx, ny, gvv, gr); ev[0] += gvv;
+                gather_grad<T, GD>(a.G.F[1], sn[0], sh[1], sn[2], nx, ny, gvv, gr); ev[1] += gvv;
+                gather_grad<T, GD>(a.G.F[2], sn[0], sn[1], sh[2], nx, ny, gvv, gr); ev[2] += gvv;
+                gather_grad<T, GD>(a.G.F[3], sn[0], sh[1], sh[2], nx, ny, gvv, gr); bv[0] += gvv;
+                gather_grad<T, GD>(a.G.F[4], sh[0], sn[1], sh[2], nx, ny, gvv, gr); bv[1] += gvv;
+                gather_grad<T, GD>(a.G.F[5], sh[0], sh[1], sn[2], nx, ny, gvv, gr); bv[2] += gvv;
+            }
+            T u1p[3];
+            boris_g<T>(u0v, ev, bv, T(0.5 * a.q_over_m * a.dt), u1p);
+            const T ig = rsqrt_r<T>(T(1) + u1p[0] * u1p[0] + u1p[1] * u1p[1] + u1p[2] * u1p[2]);
+            const T vt[3] = {u1p[0] * ig, u1p[1] * ig, u1p[2] * ig};
+            T dl[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
+                    const T d = vt[c] * T(a.dt / a.dx[c]);
+                    dl[c] = fabs(d) < T(1) ? d : T(0);   // the forward push holds a too-fast move
+                }
+            }
+            deposit_adjoint<T, GD>(a.lJ, a.G.n, ic, ov, dl, vt, a.q * (double)a.w[p], a.dt, a.dx, gx0, gx1, gv);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
+                    gx1[c] /= a.dx[c];
+                    gx0[c] /= a.dx[c];
+                }
+            }
         }
         const double a0_eff = a.P.a0 != 0.0 ? a.P.a0 : 1.0;
         const PulseVar<DN> W = adjoint_vars<T, NT>(a.P, a.t, a.slot, a0_eff);
@@ -457,29 +619,9 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             lx[c] = a.lam[c][lid];
             lu1[c] = a.lam[3 + c][lid];
         }
-        // deposit (coupled reading): x^{n+1} and v from u1 as the forward move takes them
-        double gx0[3] = {0.0, 0.0, 0.0}, gv[3] = {0.0, 0.0, 0.0};
-        if constexpr (CPL && GD > 0) {
-            const T ig = rsqrt_r<T>(T(1) + u1[0].v * u1[0].v + u1[1].v * u1[1].v + u1[2].v * u1[2].v);
-            const T vt[3] = {u1[0].v * ig, u1[1].v * ig, u1[2].v * ig};
-            T dl[3] = {T(0), T(0), T(0)};
+        // the current depends on x^{n+1}
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
-                    const T d = vt[c] * T(a.dt / a.dx[c]);
-                    dl[c] = fabs(d) < T(1) ? d : T(0);   // the forward push holds a too-fast move
-                }
-            }
-            double gx1[3] = {0.0, 0.0, 0.0};
-            deposit_adjoint<T, GD>(a.lJ, a.G.n, ic, ov, dl, vt, a.q * (double)a.w[p], a.dt, a.dx, gx0, gx1, gv);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
-                    lx[c] += gx1[c] / a.dx[c];
-                    gx0[c] /= a.dx[c];
-                }
-            }
-        }
+        for (int c = 0; c < 3; ++c) lx[c] += gx1[c];
         // move: x^{n+1} = x^n + dt u1/gamma1 (and v of the out-of-plane current)
         {
             const double v1[3] = {(double)u1[0].v, (double)u1[1].v, (double)u1[2].v};
@@ -528,12 +670,21 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             AxisStencil<T> sn[3], sh[3];
             grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
             const int nx = a.G.n[0], ny = a.G.n[1];
+            if (GD >= 2 && use_lds) {
+                scatter_adjoint_lds<T, GD>(lds_adj, 0, R, sh[0], sn[1], sn[2], lE[0]);
+                scatter_adjoint_lds<T, GD>(lds_adj, 1, R, sn[0], sh[1], sn[2], lE[1]);
+                scatter_adjoint_lds<T, GD>(lds_adj, 2, R, sn[0], sn[1], sh[2], lE[2]);
+                scatter_adjoint_lds<T, GD>(lds_adj, 3, R, sn[0], sh[1], sh[2], lB[0]);
+                scatter_adjoint_lds<T, GD>(lds_adj, 4, R, sh[0], sn[1], sh[2], lB[1]);
+                scatter_adjoint_lds<T, GD>(lds_adj, 5, R, sh[0], sh[1], sn[2], lB[2]);
+            } else {
             scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
             scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
             scatter_adjoint<T, GD>(a.lEg[2], sn[0], sn[1], sh[2], nx, ny, lE[2]);
             scatter_adjoint<T, GD>(a.lBg[0], sn[0], sh[1], sh[2], nx, ny, lB[0]);
             scatter_adjoint<T, GD>(a.lBg[1], sh[0], sn[1], sh[2], nx, ny, lB[1]);
             scatter_adjoint<T, GD>(a.lBg[2], sh[0], sh[1], sn[2], nx, ny, lB[2]);
+            }
         }
         // field adjoint
 #pragma unroll
@@ -555,6 +706,27 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
 #pragma unroll
             for (int q = 1; q < 5; ++q)
                 if (a.slot[j] == q) g[q] = acc;
+        }
+    }
+    if constexpr (CPL && GD >= 2) {
+        if (use_lds) {
+            // flush: each node of the region once (zero sums skipped)
+            __syncthreads();
+            const int per = R.ext[0] * R.ext[1] * R.ext[2];
+            for (int i = threadIdx.x; i < vol; i += blockDim.x) {
+                const double v = lds_adj[i];
+                if (v == 0.0) continue;
+                const int comp = i / per;
+                int r = i - comp * per;
+                const int l2 = r / (R.ext[0] * R.ext[1]);
+                r -= l2 * R.ext[0] * R.ext[1];
+                const int l1 = r / R.ext[0], l0 = r - l1 * R.ext[0];
+                int g[3] = {R.lo[0] + l0, R.lo[1] + l1, R.lo[2] + l2};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) g[ax] = wrap_idx(g[ax], R.n[ax]);
+                const size_t node = ((size_t)g[2] * R.n[1] + g[1]) * R.n[0] + g[0];
+                atomicAdd(comp < 3 ? a.lEg[comp] + node : a.lBg[comp - 3] + node, v);
+            }
         }
     }
     // per-block FP64 sum, accumulated into this block's slot (no atomics)
@@ -585,6 +757,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <int PT, int NT, int GD, bool PX, bool CPL>
 __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
     adjoint_step_body<double, PT, NT, GD, PX, CPL>(a);
+}
+// The coupled 3-D step carries the current's and the gather's adjoints as
+// well: one wave per SIMD, so that its working set stays in registers.
+template <int PT, int NT, bool PX, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_step_cpl3(
+    AdjointArgs<T> a) {
+    adjoint_step_body<T, PT, NT, 3, PX, true>(a);
 }
 
 }  // namespace apt
