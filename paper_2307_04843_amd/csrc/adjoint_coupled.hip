@@ -7,7 +7,8 @@
 namespace apt {
 
 template <typename T, int PT, int GD> static void launch_cpl_gd(const AdjointArgs<T> &a, int np, hipStream_t s) {
-    const dim3 grid((a.n + 255) / 256), block(256);
+    const int per_block = 256 * (GD >= 2 ? kAdjPpt : 1);
+    const dim3 grid((a.n + per_block - 1) / per_block), block(256);
     const bool px = a.lam_proxy != nullptr;
     // 2-D and 3-D stage the gather's adjoint in LDS
     const size_t sh = GD >= 2 ? (size_t)kAdjLdsDoubles * sizeof(double) : 0;

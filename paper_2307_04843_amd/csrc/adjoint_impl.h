@@ -389,7 +389,8 @@ AP_D void scatter_adjoint(double *F, const AxisStencil<T> &sx, const AxisStencil
 // LDS staging of the gather's adjoint (coupled 2-D/3-D): a block's particles
 // are nearly tile-sorted, so their stencils cover a small box of nodes; the
 // block accumulates there and flushes each node once.
-constexpr int kAdjLdsDoubles = 6144;   // 48 KiB: six components of up to 1024 nodes
+constexpr int kAdjLdsDoubles = 8192;   // 64 KiB: six components of up to 1365 nodes
+constexpr int kAdjPpt = 1;             // particles per thread in those blocks (4 measured slower)
 struct AdjRegion {
     int lo[3], ext[3], n[3];
     AP_D int local(int ax, int idx) const {
@@ -438,30 +439,35 @@ template <typename T, int GD> AP_D void grid_stencils(const int ic[3], const T o
 
 template <typename T, int PT, int NT, int GD, bool PX, bool CPL>
 AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // particles per thread: the coupled 2-D/3-D blocks take a tile's worth, so
+    // that their LDS region is flushed once for more particles
+    constexpr int PPT = (CPL && GD >= 2) ? kAdjPpt : 1;
+    const int base = blockIdx.x * blockDim.x * PPT + threadIdx.x;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    int lid = p;          // index of the particle's adjoint state
-    bool ok = p < a.n;
-    int ic[3] = {0, 0, 0};
-    T ov[3] = {T(0), T(0), T(0)};
-    if (GD > 0 && ok) {
-        // grid state: linear cell + offsets on the active axes; particles the
-        // push skipped (invalid cell or offset) keep their adjoint state
-        const int cell = a.G.cell[p];
-        lid = a.G.id[p];
-        ov[0] = a.off[0][p];
-        if (GD >= 2) ov[2] = a.off[2][p];
-        if (GD == 3) ov[1] = a.off[1][p];
-        const int nx = a.G.n[0], nxy = a.G.n[0] * a.G.n[1];
-        ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
-             ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)lid < (unsigned)a.n;
-        const int k = (int)a.G.fnxy.div((unsigned)cell);
-        const int r = cell - k * nxy;
-        const int j = (int)a.G.fnx.div((unsigned)r);
-        ic[0] = r - j * nx;
-        ic[1] = j;
-        ic[2] = k;
-    }
+    auto load = [&](int p, int &lid, bool &ok, int ic[3], T ov[3]) {
+        lid = p;          // index of the particle's adjoint state
+        ok = p < a.n;
+        ic[0] = ic[1] = ic[2] = 0;
+        ov[0] = ov[1] = ov[2] = T(0);
+        if (GD > 0 && ok) {
+            // grid state: linear cell + offsets on the active axes; particles the
+            // push skipped (invalid cell or offset) keep their adjoint state
+            const int cell = a.G.cell[p];
+            lid = a.G.id[p];
+            ov[0] = a.off[0][p];
+            if (GD >= 2) ov[2] = a.off[2][p];
+            if (GD == 3) ov[1] = a.off[1][p];
+            const int nx = a.G.n[0], nxy = a.G.n[0] * a.G.n[1];
+            ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
+                 ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)lid < (unsigned)a.n;
+            const int k = (int)a.G.fnxy.div((unsigned)cell);
+            const int r = cell - k * nxy;
+            const int j = (int)a.G.fnx.div((unsigned)r);
+            ic[0] = r - j * nx;
+            ic[1] = j;
+            ic[2] = k;
+        }
+    };
     // coupled 2-D/3-D: the block's bounding box of cells fixes its LDS region
     AdjRegion R{};
     bool use_lds = false;
@@ -476,11 +482,17 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             bbox[3 + threadIdx.x] = -0x7fffffff;
         }
         __syncthreads();
-        if (ok) {
+        for (int kk = 0; kk < PPT; ++kk) {
+            int lid, ic[3];
+            bool ok;
+            T ov[3];
+            load(base + kk * (int)blockDim.x, lid, ok, ic, ov);
+            if (ok) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                atomicMin(&bbox[ax], ic[ax]);
-                atomicMax(&bbox[3 + ax], ic[ax]);
+                for (int ax = 0; ax < 3; ++ax) {
+                    atomicMin(&bbox[ax], ic[ax]);
+                    atomicMax(&bbox[3 + ax], ic[ax]);
+                }
             }
         }
         __syncthreads();
@@ -505,6 +517,12 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             for (int i = threadIdx.x; i < vol; i += blockDim.x) lds_adj[i] = 0.0;
         __syncthreads();
     }
+    for (int kk = 0; kk < PPT; ++kk) {
+    const int p = base + kk * (int)blockDim.x;
+    int lid, ic[3];
+    bool ok;
+    T ov[3];
+    load(p, lid, ok, ic, ov);
     if (ok) {
         using DN = Dual<T, NT>;
         using IN = DualD<T, NT>;
@@ -705,9 +723,10 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             for (int k = 0; k < 3; ++k) acc += lE[k] * (double)E8[k].d[3 + j] + lB[k] * (double)B8[k].d[3 + j];
 #pragma unroll
             for (int q = 1; q < 5; ++q)
-                if (a.slot[j] == q) g[q] = acc;
+                if (a.slot[j] == q) g[q] += acc;
         }
     }
+    }   // particles of this thread
     if constexpr (CPL && GD >= 2) {
         if (use_lds) {
             // flush: each node of the region once (zero sums skipped)
