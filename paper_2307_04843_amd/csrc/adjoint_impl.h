@@ -199,8 +199,25 @@ AP_D __forceinline__ int wrap_idx(int i, int n) { return i < 0 ? i + n : (i >= n
 // is differentiated in x^n, x^{n+1} (cell units, forward-mode tangents) and
 // in v (out-of-plane components).  ov: offsets at x^n; dl: the step's
 // displacement in cells; returns the cell-unit gradients and dG/dv.
-template <typename T, int GD>
-AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const int ic[3], const T ov[3],
+// Readers of the grid adjoint lE~ at unwrapped node coordinates: from global
+// memory (periodic wrap), or from a block's LDS copy of the box it needs.
+struct AdjGlobalRd {
+    const double *const *F;
+    int n[3];
+    AP_D double operator()(int c, int x, int y, int z) const {
+        return F[c][((size_t)wrap_idx(z, n[2]) * n[1] + wrap_idx(y, n[1])) * n[0] + wrap_idx(x, n[0])];
+    }
+};
+struct AdjLdsRd {
+    const double *L;
+    int lo[3], ext[3];
+    AP_D double operator()(int c, int x, int y, int z) const {
+        return L[(((size_t)c * ext[2] + (z - lo[2])) * ext[1] + (y - lo[1])) * ext[0] + (x - lo[0])];
+    }
+};
+
+template <typename T, int GD, class RD>
+AP_D void deposit_adjoint(const RD &rd, const int32_t n[3], const int ic[3], const T ov[3],
                           const T dl[3], const T v[3], double qw, double dt, const double dx[3], double gx0[3],
                           double gx1[3], double gv[3]) {
     constexpr int NA = GD == 3 ? 3 : (GD == 2 ? 2 : 1);
@@ -217,7 +234,7 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
         x0[s] = ov[A] - T(up);
         x1[s] = x0[s] + dl[A];
     }
-    const int nx = n[0], ny = n[1], nz = n[2];
+    (void)n;
     // shapes of window node m (0..4) on slot s, and their derivatives in x0, x1
     auto shp = [&](int s, int m, T &a0, T &d0, T &a1, T &d1) {
         tsc_vd(x0[s] - T(m - 2), a0, d0);
@@ -226,25 +243,23 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
     const double T3 = 1.0 / 3.0, T6 = 1.0 / 6.0;
     if constexpr (GD == 1) {
         // a row: J_x from the x shapes; y and z carry q w v times the mean shape
-        const double *ex = lE_t[0] + (size_t)ic[2] * nx;
-        const double *ey = lE_t[1] + (size_t)ic[2] * nx;
-        const double *ez = lE_t[2] + (size_t)ic[2] * nx;
         double suf = 0.0, g0 = 0.0, g1 = 0.0, sy = 0.0, sz = 0.0, y0 = 0.0, y1 = 0.0, z0 = 0.0, z1 = 0.0;
 #pragma unroll
         for (int m = 4; m >= 0; --m) {
             T a0, d0, a1, d1;
             shp(0, m, a0, d0, a1, d1);
-            const int i = wrap_idx(cb[0] + m, nx);
-            suf += ex[i];
+            const double lx = rd(0, cb[0] + m, 0, ic[2]), ly = rd(1, cb[0] + m, 0, ic[2]);
+            const double lz = rd(2, cb[0] + m, 0, ic[2]);
+            suf += lx;
             g0 -= (double)d0 * suf;
             g1 += (double)d1 * suf;
             const double mean = 0.5 * ((double)a0 + (double)a1);
-            sy += mean * ey[i];
-            sz += mean * ez[i];
-            y0 += 0.5 * (double)d0 * ey[i];
-            y1 += 0.5 * (double)d1 * ey[i];
-            z0 += 0.5 * (double)d0 * ez[i];
-            z1 += 0.5 * (double)d1 * ez[i];
+            sy += mean * ly;
+            sz += mean * lz;
+            y0 += 0.5 * (double)d0 * ly;
+            y1 += 0.5 * (double)d1 * ly;
+            z0 += 0.5 * (double)d0 * lz;
+            z1 += 0.5 * (double)d1 * lz;
         }
         const double cj = qw * dx[0], cy = -dt * qw;
         gx0[0] = cj * g0 + cy * ((double)v[1] * y0 + (double)v[2] * z0);
@@ -260,13 +275,12 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
         for (int k = 0; k < 5; ++k) {
             T za0, zd0, za1, zd1;
             shp(1, k, za0, zd0, za1, zd1);
-            const double *row = lE_t[0] + (size_t)wrap_idx(cb[1] + k, nz) * nx;
             double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
 #pragma unroll
             for (int m = 4; m >= 0; --m) {
                 T xa0, xd0, xa1, xd1;
                 shp(0, m, xa0, xd0, xa1, xd1);
-                suf += row[wrap_idx(cb[0] + m, nx)];
+                suf += rd(0, cb[0] + m, 0, cb[1] + k);
                 av += (double)(xa1 - xa0) * suf;
                 a0 -= (double)xd0 * suf;
                 a1 += (double)xd1 * suf;
@@ -282,19 +296,17 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
         for (int m = 0; m < 5; ++m) {
             T xa0, xd0, xa1, xd1;
             shp(0, m, xa0, xd0, xa1, xd1);
-            const int i = wrap_idx(cb[0] + m, nx);
             double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
             double p0 = 0.0, p1 = 0.0, r0 = 0.0, r1 = 0.0;   // sums over z for J_y
 #pragma unroll
             for (int k = 4; k >= 0; --k) {
                 T za0, zd0, za1, zd1;
                 shp(1, k, za0, zd0, za1, zd1);
-                const size_t c = (size_t)wrap_idx(cb[1] + k, nz) * nx + i;
-                suf += lE_t[2][c];
+                suf += rd(2, cb[0] + m, 0, cb[1] + k);
                 av += (double)(za1 - za0) * suf;
                 a0 -= (double)zd0 * suf;
                 a1 += (double)zd1 * suf;
-                const double ly = lE_t[1][c];
+                const double ly = rd(1, cb[0] + m, 0, cb[1] + k);
                 p0 += ly * (T3 * (double)za0 + T6 * (double)za1);   // pairs with X0
                 p1 += ly * (T6 * (double)za0 + T3 * (double)za1);   // pairs with X1
                 r0 += ly * (double)zd0;
@@ -324,15 +336,12 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const int s1 = s == 0 ? 1 : 0, s2 = s == 2 ? 1 : 2;   // the two other axes
-            const int n_s = s == 0 ? nx : (s == 1 ? ny : nz);
-            const int n_1 = s1 == 0 ? nx : (s1 == 1 ? ny : nz);
-            const int n_2 = s2 == 0 ? nx : (s2 == 1 ? ny : nz);
             const double coef = qw * dx[s];
 #pragma unroll 1
             for (int b = 0; b < 5; ++b) {
                 T p0, dp0, p1, dp1;
                 shp(s1, b, p0, dp0, p1, dp1);
-                const int i1 = wrap_idx(cb[s1] + b, n_1);
+                const int i1 = cb[s1] + b;
 #pragma unroll 1
                 for (int c = 0; c < 5; ++c) {
                     T q0, dq0, q1, dq1;
@@ -340,14 +349,14 @@ AP_D void deposit_adjoint(const double *const lE_t[3], const int32_t n[3], const
                     const double tr = T3 * ((double)p0 * q0 + (double)p1 * q1) + T6 * ((double)p1 * q0 + (double)p0 * q1);
                     int id3[3];
                     id3[s1] = i1;
-                    id3[s2] = wrap_idx(cb[s2] + c, n_2);
+                    id3[s2] = cb[s2] + c;
                     double suf = 0.0, av = 0.0, a0 = 0.0, a1 = 0.0;
 #pragma unroll
                     for (int m = 4; m >= 0; --m) {
                         T sa0, sd0, sa1, sd1;
                         shp(s, m, sa0, sd0, sa1, sd1);
-                        id3[s] = wrap_idx(cb[s] + m, n_s);
-                        suf += lE_t[s][((size_t)id3[2] * ny + id3[1]) * nx + id3[0]];
+                        id3[s] = cb[s] + m;
+                        suf += rd(s, id3[0], id3[1], id3[2]);
                         av += (double)(sa1 - sa0) * suf;
                         a0 -= (double)sd0 * suf;
                         a1 += (double)sd1 * suf;
@@ -389,7 +398,10 @@ AP_D void scatter_adjoint(double *F, const AxisStencil<T> &sx, const AxisStencil
 // LDS staging of the gather's adjoint (coupled 2-D/3-D): a block's particles
 // are nearly tile-sorted, so their stencils cover a small box of nodes; the
 // block accumulates there and flushes each node once.
-constexpr int kAdjLdsDoubles = 8192;   // 64 KiB: six components of up to 1365 nodes
+// LDS of a coupled block, in doubles: the gather's adjoint (six components)
+// and the grid adjoint lE~ the current's adjoint reads (three components)
+template <int GD> constexpr int adj_lds_scatter() { return GD == 3 ? 8192 : 3072; }
+template <int GD> constexpr int adj_lds_j() { return GD == 3 ? 6144 : 3072; }
 constexpr int kAdjPpt = 1;             // particles per thread in those blocks (4 measured slower)
 struct AdjRegion {
     int lo[3], ext[3], n[3];
@@ -470,7 +482,8 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
     };
     // coupled 2-D/3-D: the block's bounding box of cells fixes its LDS region
     AdjRegion R{};
-    bool use_lds = false;
+    AdjLdsRd JR{};
+    bool use_lds = false, use_ldsj = false;
     int vol = 0;
     double *lds_adj = nullptr;
     if constexpr (CPL && GD >= 2) {
@@ -512,9 +525,38 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             fits = fits && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
             vol *= R.ext[ax];
         }
-        use_lds = fits && vol <= kAdjLdsDoubles;
+        use_lds = fits && vol <= adj_lds_scatter<GD>();
         if (use_lds)
             for (int i = threadIdx.x; i < vol; i += blockDim.x) lds_adj[i] = 0.0;
+        // the current's window reaches two nodes below the lowest cell and three above the highest
+        JR.L = lds_adj + adj_lds_scatter<GD>();
+        int volj = 3;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (GD == 2 && ax == 1) {
+                JR.lo[1] = 0;
+                JR.ext[1] = 1;
+                continue;
+            }
+            JR.lo[ax] = bbox[ax] - 2;
+            JR.ext[ax] = bbox[3 + ax] - bbox[ax] + 6;
+            volj *= JR.ext[ax];
+        }
+        use_ldsj = bbox[0] <= bbox[3] && volj <= adj_lds_j<GD>();
+        if (use_ldsj) {
+            double *L = lds_adj + adj_lds_scatter<GD>();
+            const int per = JR.ext[0] * JR.ext[1] * JR.ext[2];
+            for (int i = threadIdx.x; i < volj; i += blockDim.x) {
+                const int comp = i / per;
+                int r = i - comp * per;
+                const int l2 = r / (JR.ext[0] * JR.ext[1]);
+                r -= l2 * JR.ext[0] * JR.ext[1];
+                const int l1 = r / JR.ext[0], l0 = r - l1 * JR.ext[0];
+                const int gx = wrap_idx(JR.lo[0] + l0, a.G.n[0]), gy = wrap_idx(JR.lo[1] + l1, a.G.n[1]);
+                const int gz = wrap_idx(JR.lo[2] + l2, a.G.n[2]);
+                L[i] = a.lJ[comp][((size_t)gz * a.G.n[1] + gy) * a.G.n[0] + gx];
+            }
+        }
         __syncthreads();
     }
     for (int kk = 0; kk < PPT; ++kk) {
@@ -567,7 +609,13 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
                     dl[c] = fabs(d) < T(1) ? d : T(0);   // the forward push holds a too-fast move
                 }
             }
-            deposit_adjoint<T, GD>(a.lJ, a.G.n, ic, ov, dl, vt, a.q * (double)a.w[p], a.dt, a.dx, gx0, gx1, gv);
+            const double qw = a.q * (double)a.w[p];
+            if (GD >= 2 && use_ldsj) {
+                deposit_adjoint<T, GD>(JR, a.G.n, ic, ov, dl, vt, qw, a.dt, a.dx, gx0, gx1, gv);
+            } else {
+                const AdjGlobalRd gr{a.lJ, {a.G.n[0], a.G.n[1], a.G.n[2]}};
+                deposit_adjoint<T, GD>(gr, a.G.n, ic, ov, dl, vt, qw, a.dt, a.dx, gx0, gx1, gv);
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (c == 0 || GD == 3 || (GD == 2 && c == 2)) {
