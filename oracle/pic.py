@@ -81,13 +81,16 @@ class Species:
     """Macroparticles: positions (cell units), momenta u = gamma beta, weights;
     ``proxy`` (per particle, or None) accumulates the emission proxy."""
 
-    def __init__(self, q, m, pos, u, w, proxy=None):
+    def __init__(self, q, m, pos, u, w, proxy=None, ids=None, free=None):
         self.q = float(q)
         self.m = float(m)
         self.pos = np.array(pos, dtype=float, copy=True)
         self.u = np.array(u, dtype=float, copy=True)
         self.w = np.array(w, dtype=float, copy=True)
         self.proxy = None if proxy is None else np.array(proxy, dtype=float, copy=True)
+        # particle ids and the ids not in use (moving window bookkeeping)
+        self.ids = None if ids is None else np.array(ids, dtype=np.int64, copy=True)
+        self.free = np.zeros(0, dtype=np.int64) if free is None else np.sort(np.array(free, dtype=np.int64))
 
 
 # ----------------------------------------------------------------------------
@@ -481,6 +484,47 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False, launch=Fa
         yee_step(grid, boundary_source(grid, pulse, grid.t + 0.5 * grid.dt) if launch else None)
     grid.t += grid.dt
     return moved
+
+
+def shift_window(grid, species, injected):
+    """Moving window (Sec. III.C: a window that follows the pulse, e.g. the
+    intensity peak of a flying focus): advance it one cell along +x.
+
+    Lab positions are kept: x_min[0] grows by dx; E2, B2 move down one index
+    along x and the new last column is empty; particles move down one cell
+    index, and those in the first column fall behind the window and are
+    removed (their ids join the free ids).  ``injected`` holds, per species,
+    None or (pos (3, k) in cell units of the new window, u (3, k), w (k)):
+    the particles of the new column, which take the k smallest free ids."""
+    grid.x_min = (grid.x_min[0] + grid.dx[0],) + tuple(grid.x_min[1:])
+    for F in grid.E + grid.B:
+        F[..., :-1] = F[..., 1:].copy()
+        F[..., -1] = 0.0
+    for sp, inj in zip(species, injected):
+        keep = sp.pos[0] >= 1.0
+        if sp.ids is not None:
+            sp.free = np.sort(np.concatenate([sp.free, sp.ids[~keep]]))
+            sp.ids = sp.ids[keep]
+        sp.pos = sp.pos[:, keep]
+        sp.pos[0] -= 1.0
+        sp.u = sp.u[:, keep]
+        sp.w = sp.w[keep]
+        if sp.proxy is not None:
+            sp.proxy = sp.proxy[keep]
+        if inj is None:
+            continue
+        pos, u, w = (np.asarray(a, dtype=float) for a in inj)
+        k = w.shape[0]
+        if sp.ids is not None:
+            if k > sp.free.shape[0]:
+                raise ValueError("not enough free ids for the injected particles")
+            sp.ids = np.concatenate([sp.ids, sp.free[:k]])
+            sp.free = sp.free[k:]
+        sp.pos = np.concatenate([sp.pos, pos], axis=1)
+        sp.u = np.concatenate([sp.u, u], axis=1)
+        sp.w = np.concatenate([sp.w, w])
+        if sp.proxy is not None:
+            sp.proxy = np.concatenate([sp.proxy, np.zeros(k)])
 
 
 def emission_proxy(u0, u1, E, B, dt):

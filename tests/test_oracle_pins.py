@@ -1177,3 +1177,67 @@ def test_open_boundary_lets_the_pulse_leave():
     _, _, grid = _launch_vs_apt(30, tau=20.0, fwhm=6.0, extra=60.0)
     assert grid.t > 85.0 * L
     assert max(np.abs(grid.E[1]).max(), np.abs(grid.B[2]).max(), np.abs(grid.E[2]).max()) < 1e-6
+
+
+# ---- moving window (Sec. III.C)
+
+def test_moving_window_shift_keeps_lab_state():
+    """A shift keeps every lab position and lab field value: x_min grows by
+    dx, E2/B2 move down one index (new column empty), particles move down one
+    cell; those in the first column leave and free their ids, and injected
+    particles take the smallest free ids."""
+    rng = np.random.default_rng(8)
+    n = (12, 1, 6)
+    g = pic.Grid(2, n, (0.3, 0.3, 0.4), 0.1, (1.0, 0.0, -2.0))
+    for F in g.E + g.B:
+        F[...] = rng.standard_normal(F.shape)
+    E0 = [e.copy() for e in g.E]
+    N = 40
+    pos = np.zeros((3, N))
+    pos[0] = rng.uniform(0, n[0], N)
+    pos[2] = rng.uniform(0, n[2], N)
+    pos[0][:3] = [0.2, 0.9, 1.0]
+    sp = pic.Species(-1.0, 1.0, pos, rng.standard_normal((3, N)), np.ones(N), ids=np.arange(N),
+                     free=np.arange(N, N + 10))
+    lab0 = g.x_min[0] + pos[0] * g.dx[0]
+    inj = (np.array([[n[0] - 0.5, n[0] - 0.25], [0.0, 0.0], [1.5, 4.5]]), np.zeros((3, 2)), np.full(2, 0.5))
+    pic.shift_window(g, [sp], [inj])
+    assert g.x_min[0] == 1.0 + 0.3
+    for e, e0 in zip(g.E, E0):
+        assert np.array_equal(e[..., :-1], e0[..., 1:]) and not e[..., -1].any()
+    left = pos[0] < 1.0
+    assert sp.pos.shape[1] == N - left.sum() + 2
+    kept_ids = np.arange(N)[~left]
+    assert np.array_equal(sp.ids[:-2], kept_ids)
+    lab1 = g.x_min[0] + sp.pos[0][:-2] * g.dx[0]
+    assert np.allclose(lab1, lab0[~left], rtol=0, atol=1e-14)
+    # the two injected particles take the two smallest free ids: the first leavers
+    assert np.array_equal(sp.ids[-2:], np.sort(np.concatenate([np.arange(N)[left], np.arange(N, N + 10)]))[:2])
+
+
+def test_moving_window_weightless_run_equals_fixed_window():
+    """Weightless particles in an LG pulse: the same 30 steps with the window
+    shifted every 6 steps (and a box wide enough that none leaves either run)
+    give the same momenta, particle by particle (ids), to round-off."""
+    from tests import cases
+    case = cases.make_case(n=(80, 1, 16), seed=12, u_scale=0.5, ppc=1)
+    runs = []
+    for shift in (False, True):
+        g, sps, P = cases.oracle_state(case)
+        for F in g.E + g.B:
+            F[...] = 0.0                 # APT alone: E2 = B2 = 0 throughout
+        sp = sps[0]
+        sp.w = np.zeros_like(sp.w)
+        # away from the back (5 shifts) and from the front (the pulse pushes forward)
+        keep = (sp.pos[0] >= 10.0) & (sp.pos[0] < 40.0)
+        sp.pos, sp.u, sp.w = sp.pos[:, keep], sp.u[:, keep], sp.w[keep]
+        sp.ids = np.arange(sp.w.size)
+        for k in range(30):
+            if shift and k % 6 == 5:
+                pic.shift_window(g, [sp], [None])
+            pic.step(g, [sp], P)
+        runs.append((sp.ids.copy(), sp.u.copy(), g.x_min[0] + sp.pos[0] * g.dx[0]))
+    (i0, u0, x0), (i1, u1, x1) = runs
+    assert np.array_equal(i0, i1) and i0.size > 400
+    assert np.abs(u1 - u0).max() <= 1e-11 * np.abs(u0).max()
+    assert np.abs(x1 - x0).max() <= 1e-11 * L
