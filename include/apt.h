@@ -78,6 +78,8 @@ typedef int32_t ap_status;
 #define AP_GRID_PULSE_ON_GRID 0x1  /* allow AP_SAMPLE_GRID (reserves workspace)  */
 #define AP_GRID_PROXY         0x2  /* gridded species may carry an emission
                                       proxy (reserves its re-sort workspace)  */
+#define AP_GRID_MOVING_WINDOW 0x8  /* gridded runs: reserves the workspace of
+                                      ap_shift_window                          */
 #define AP_GRID_OPEN_X        0x4  /* dim 1 only: the x ends of every row are
                                       incoming/outgoing-wave boundaries for E2,
                                       B2 (App. B, first order, normal
@@ -389,6 +391,32 @@ ap_status ap_timing_enable(ap_ctx *ctx, int32_t enable);
 ap_status ap_timing_read(ap_ctx *ctx, ap_timing *out, int32_t reset);
 
 /* Release the context (does not free caller buffers). NULL is accepted. */
+/* Moving window (Sec. III.C: a window following the pulse, e.g. the
+ * intensity peak of a flying focus): advance the window one cell along +x.
+ * Needs AP_GRID_MOVING_WINDOW.  Lab positions are kept: x_min[0] grows by
+ * dx[0]; E2, B2 move down one index along x and the new last column is
+ * zero; every particle moves down one cell index.  Particles in the first
+ * column fall behind the window: their slots become free.  A free slot holds
+ * cell -1 and zero offsets, momentum, weight (and proxy); the caller may
+ * pass such slots at ap_init as spare capacity.  Each species' ids must be
+ * a permutation of 0..n-1 (else AP_E_ARG, nothing changed).
+ * inject: NULL, or one ap_inject per species (n = 0 for none): device arrays
+ * in the species layout of the new particles, all in the new last column
+ * (cell index n[0]-1 of its row) with offsets in [0, 1) (else AP_E_ARG,
+ * nothing changed); their momenta and weights are the caller's (the
+ * injected plasma).  They take the free slots in increasing id order, and
+ * the proxy of an injected particle starts at zero.  More injected particles
+ * than free slots: AP_E_ARG, nothing changed.  Drops any adjoint recording;
+ * the next step re-sorts.  Synchronises the stream. */
+typedef struct ap_inject {
+    const int32_t *cell;
+    const void    *off[3];      /* active axes; NULL on the others           */
+    const void    *u[3];
+    const void    *w;
+    int64_t        n;
+} ap_inject;
+ap_status ap_shift_window(ap_ctx *ctx, const ap_inject *inject);
+
 ap_status ap_destroy(ap_ctx *ctx);
 
 /* Message of the last non-OK status on this thread ("" if none). */

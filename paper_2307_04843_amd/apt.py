@@ -23,6 +23,7 @@ AP_PARAM_A0, AP_PARAM_W0, AP_PARAM_XF, AP_PARAM_BETA_F, AP_PARAM_CHIRP = range(5
 AP_GRID_PULSE_ON_GRID = 0x1
 AP_GRID_PROXY = 0x2
 AP_GRID_OPEN_X = 0x4
+AP_GRID_MOVING_WINDOW = 0x8
 AP_ADJ_FROZEN, AP_ADJ_COUPLED = 0, 1
 AP_ENV_SIN2, AP_ENV_SGAUSS = 0, 1
 AP_SAMPLE_PARTICLES, AP_SAMPLE_GRID, AP_SAMPLE_BOUNDARY = 0, 1, 2
@@ -33,7 +34,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
-            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_set_adjoint_mode", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_destroy",
+            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_set_adjoint_mode", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window", "ap_destroy",
             "ap_last_error")
 
 
@@ -51,6 +52,11 @@ class ap_species_desc(C.Structure):
 class ap_particles(C.Structure):
     _fields_ = [("cell", C.c_void_p), ("icell", C.c_void_p * 3), ("off", C.c_void_p * 3),
                 ("u", C.c_void_p * 3), ("w", C.c_void_p), ("id", C.c_void_p), ("proxy", C.c_void_p)]
+
+
+class ap_inject(C.Structure):
+    _fields_ = [("cell", C.c_void_p), ("off", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p),
+                ("n", C.c_int64)]
 
 
 class ap_layout(C.Structure):
@@ -126,6 +132,7 @@ def load():
                                     C.c_int32, P(C.c_double)]),
         "ap_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
         "ap_timing_read": (C.c_int32, [C.c_void_p, P(ap_timing), C.c_int32]),
+        "ap_shift_window": (C.c_int32, [C.c_void_p, C.c_void_p]),
         "ap_destroy": (C.c_int32, [C.c_void_p]),
         "ap_last_error": (C.c_char_p, []),
     }
@@ -224,6 +231,12 @@ def ap_timing_read(ctx, reset=False):
     out = ap_timing()
     _check(load().ap_timing_read(ctx, C.byref(out), 1 if reset else 0), "ap_timing_read")
     return out
+
+
+def ap_shift_window(ctx, inject):
+    """inject: None or a ctypes array of ap_inject, one per species."""
+    _check(load().ap_shift_window(ctx, C.cast(inject, C.c_void_p) if inject is not None else None),
+           "ap_shift_window")
 
 
 def ap_destroy(ctx):

@@ -55,6 +55,7 @@ struct RunShape {
 struct WorkLayout {
     size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, bsrc = 0,
            total = 0;
+    size_t wtmp = 0, wflag = 0, wrank = 0, wpart = 0;   // moving window: field copy, free-slot flags and ranks
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -135,8 +136,9 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         s.dt = g->dt * kTwoPi;
     }
     if (g->sort_every < 0) return fail(AP_E_ARG, "sort_every must be >= 0");
-    if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY | AP_GRID_OPEN_X))
+    if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY | AP_GRID_OPEN_X | AP_GRID_MOVING_WINDOW))
         return fail(AP_E_ARG, "unknown grid option bits");
+    if ((g->options & AP_GRID_MOVING_WINDOW) && s.dim == 0) return fail(AP_E_ARG, "a moving window needs a grid");
     if ((g->options & AP_GRID_OPEN_X) && s.dim != 1) return fail(AP_E_ARG, "AP_GRID_OPEN_X is built for 1-D rows only");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
@@ -193,6 +195,14 @@ WorkLayout make_layout(const RunShape &s) {
         L.scan_part = take((size_t)2 * scan_part_len((int32_t)s.ntiles) * 4);
         // boundary source S_y, S_z per row (incoming-wave x_min of open rows)
         if (s.options & AP_GRID_OPEN_X) L.bsrc = take((size_t)s.n[2] * 2 * s.real);
+        if (s.options & AP_GRID_MOVING_WINDOW) {
+            int64_t nmax = 0;
+            for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
+            L.wtmp = take((size_t)6 * (size_t)s.ncell * s.real);
+            L.wflag = take((size_t)(nmax + 1) * 4);
+            L.wrank = take((size_t)(nmax + 1) * 4);
+            L.wpart = take((size_t)2 * scan_part_len((int32_t)(nmax > 0 ? nmax : 1)) * 4);
+        }
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
             L.count[i] = take((size_t)s.ntiles * 4);
@@ -390,6 +400,7 @@ ap_status hip_fail(hipError_t e, const char *where) {
     } while (0)
 
 template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags);
+template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *inject);
 template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
 template <typename T>
 ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
@@ -934,6 +945,17 @@ ap_status ap_timing_read(ap_ctx *c, ap_timing *out, int32_t reset) {
     return AP_OK;
 }
 
+ap_status ap_shift_window(ap_ctx *c, const ap_inject *inject) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (!(c->s.options & AP_GRID_MOVING_WINDOW))
+        return fail(AP_E_STATE, "the run was not created with AP_GRID_MOVING_WINDOW");
+    try {
+        return c->s.prec == AP_F64 ? shift_window_impl<double>(c, inject) : shift_window_impl<float>(c, inject);
+    } catch (...) {
+        return fail(AP_E_NOMEM, "host allocation failed");
+    }
+}
+
 ap_status ap_destroy(ap_ctx *c) {
     if (!c) return AP_OK;
     (void)hipStreamSynchronize(c->stream);
@@ -1434,6 +1456,105 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     HIPCHK(hipStreamSynchronize(c->stream), "backward");
     const double unit[5] = {1.0, kTwoPi, kTwoPi, 1.0, 1.0};
     for (int k = 0; k < np_; ++k) out[k] = host[ids[k]] * unit[ids[k]];
+    return AP_OK;
+}
+
+template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *inject) {
+    const RunShape &s = c->s;
+    const WorkLayout &L = c->L;
+    unsigned long long *bad = c->counters() + 5;
+    // validate everything before changing anything
+    for (int i = 0; i < s.nsp; ++i) {
+        const int64_t k = inject ? inject[i].n : 0;
+        if (k < 0 || k > s.np[i]) return fail(AP_E_ARG, "species " + std::to_string(i) + ": bad injection count");
+        if (k > 0) {
+            const ap_inject &in = inject[i];
+            bool okp = in.cell && in.u[0] && in.u[1] && in.u[2] && in.w;
+            for (int a = 0; a < 3; ++a) okp = okp && (axis_active(s.dim, a) ? in.off[a] != nullptr : true);
+            if (!okp) return fail(AP_E_ARG, "species " + std::to_string(i) + ": a required injection array is NULL");
+        }
+    }
+    auto args = [&](int i) {
+        const ap_particles &p = c->buf.sp[i];
+        WindowArgs<T> a{};
+        a.cell = p.cell;
+        a.id = p.id;
+        for (int k = 0; k < 3; ++k) {
+            a.off[k] = axis_active(s.dim, k) ? static_cast<T *>(p.off[k]) : nullptr;
+            a.u[k] = static_cast<T *>(p.u[k]);
+        }
+        a.w = static_cast<T *>(p.w);
+        a.proxy = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
+        a.n = (int32_t)s.np[i];
+        a.ncell = (uint32_t)s.ncell;
+        a.nx = s.n[0];
+        a.fnx = FastDiv((uint32_t)s.n[0]);
+        a.flag = c->wp<int32_t>(L.wflag);
+        a.rank = c->wp<int32_t>(L.wrank);
+        a.bad = bad;
+        if (inject && inject[i].n > 0) {
+            const ap_inject &in = inject[i];
+            a.in_cell = in.cell;
+            for (int k = 0; k < 3; ++k) {
+                a.in_off[k] = axis_active(s.dim, k) ? static_cast<const T *>(in.off[k]) : nullptr;
+                a.in_u[k] = static_cast<const T *>(in.u[k]);
+            }
+            a.in_w = static_cast<const T *>(in.w);
+            a.n_inj = (int32_t)in.n;
+        }
+        return a;
+    };
+    auto count = [&](const char *what) -> ap_status {
+        unsigned long long b = 0;
+        HIPCHK(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, c->stream), "shift window");
+        HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+        if (b != 0) return fail(AP_E_ARG, what);
+        return AP_OK;
+    };
+    for (int i = 0; i < s.nsp; ++i) {
+        if (s.np[i] == 0) continue;
+        const WindowArgs<T> a = args(i);
+        HIPCHK(launch_fill_zero<unsigned long long>(bad, 1, c->stream), "shift window");
+        HIPCHK(launch_window_check_inject<T>(a, c->stream), "shift window");
+        ap_status st = count("injected particles must sit in the new last column with offsets in [0, 1)");
+        if (st != AP_OK) return st;
+        HIPCHK(launch_fill_zero<int32_t>(a.flag, (size_t)s.np[i], c->stream), "shift window");
+        HIPCHK(launch_window_mark<T>(a, c->stream), "shift window");
+        st = count("particle ids are not a permutation of 0..n-1");
+        if (st != AP_OK) return st;
+        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank), (int32_t)s.np[i], c->wp<int32_t>(L.wpart), c->stream),
+               "shift window");
+        int32_t nfree = 0;
+        HIPCHK(hipMemcpyAsync(&nfree, c->wp<int32_t>(L.wrank) + s.np[i], 4, hipMemcpyDeviceToHost, c->stream),
+               "shift window");
+        HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+        if (inject && inject[i].n > nfree)
+            return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(inject[i].n) +
+                                      " injected particles but " + std::to_string(nfree) + " free slots");
+    }
+    // apply: fields, then each species (its flags and ranks recomputed: the
+    // workspace holds one species at a time)
+    T *grid = static_cast<T *>(c->buf.grid);
+    const size_t nc = (size_t)s.ncell;
+    T *F[6];
+    for (int k = 0; k < 6; ++k) F[k] = grid + (size_t)k * nc;
+    T *tmp = c->wp<T>(L.wtmp);
+    HIPCHK(hipMemcpyAsync(tmp, grid, 6 * nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "shift window");
+    HIPCHK(launch_window_fields<T>(F, tmp, s.n[0], nc, c->stream), "shift window");
+    for (int i = 0; i < s.nsp; ++i) {
+        if (s.np[i] == 0) continue;
+        const WindowArgs<T> a = args(i);
+        HIPCHK(launch_fill_zero<int32_t>(a.flag, (size_t)s.np[i], c->stream), "shift window");
+        HIPCHK(launch_window_mark<T>(a, c->stream), "shift window");
+        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank), (int32_t)s.np[i], c->wp<int32_t>(L.wpart), c->stream),
+               "shift window");
+        HIPCHK(launch_window_apply<T>(a, c->stream), "shift window");
+    }
+    HIPCHK(launch_fill_zero<unsigned long long>(bad, 1, c->stream), "shift window");
+    HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+    c->s.x_min[0] += s.dx[0];
+    c->need_sort = true;
+    c->rec_n = 0;
     return AP_OK;
 }
 

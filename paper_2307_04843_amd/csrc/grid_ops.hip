@@ -407,6 +407,107 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, in
     return hipGetLastError();
 }
 
+// ---- moving window (Sec. III.C)
+
+// Per particle: the slot becomes free if it is free already or its particle
+// sits in the first column (it falls behind the window); recorded by id, so
+// that free slots rank in id order whatever the tile order.
+template <typename T> __global__ __launch_bounds__(256) void k_window_mark(WindowArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int id = a.id[p];
+    if ((unsigned)id >= (unsigned)a.n) {
+        atomicAdd(a.bad, 1ull);
+        return;
+    }
+    const int cell = a.cell[p];
+    const bool dead = (unsigned)cell >= a.ncell;
+    const bool leaves = !dead && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == 0;
+    a.flag[id] = (dead || leaves) ? 1 : 0;
+}
+
+// Injected particles must sit in the new last column with offsets in [0, 1).
+template <typename T> __global__ __launch_bounds__(256) void k_window_check_inject(WindowArgs<T> a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_inj) return;
+    const int cell = a.in_cell[r];
+    bool ok = (unsigned)cell < a.ncell && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == a.nx - 1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (a.in_off[k]) ok = ok && a.in_off[k][r] >= T(0) && a.in_off[k][r] < T(1);
+    if (!ok) atomicAdd(a.bad, 1ull);
+}
+
+// Apply the shift: particles move down one cell; the free slots (ranked by
+// id) take the injected particles in order, the rest stay free.
+template <typename T> __global__ __launch_bounds__(256) void k_window_apply(WindowArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int cell = a.cell[p];
+    const bool dead = (unsigned)cell >= a.ncell;
+    const bool leaves = !dead && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == 0;
+    if (!(dead || leaves)) {
+        a.cell[p] = cell - 1;
+        return;
+    }
+    const int r = a.rank[a.id[p]];
+    const bool inj = r < a.n_inj;
+    a.cell[p] = inj ? a.in_cell[r] : kDeadCell;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (a.off[k]) a.off[k][p] = inj ? a.in_off[k][r] : T(0);
+        a.u[k][p] = inj ? a.in_u[k][r] : T(0);
+    }
+    a.w[p] = inj ? a.in_w[r] : T(0);
+    if (a.proxy) {
+        a.proxy[2 * p] = T(0);
+        a.proxy[2 * p + 1] = T(0);
+    }
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_window_fields(T *F0, T *F1, T *F2, T *F3, T *F4,
+                                                                             T *F5, const T *tmp, int32_t nx,
+                                                                             FastDiv fnx, size_t ncell) {
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t cc = (uint32_t)c;
+        const int i = (int)(cc - fnx.div(cc) * (uint32_t)nx);
+        const bool last = i == nx - 1;
+        T *F[6] = {F0, F1, F2, F3, F4, F5};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) F[k][c] = last ? T(0) : tmp[(size_t)k * ncell + c + 1];
+    }
+}
+
+template <typename T> hipError_t launch_window_mark(const WindowArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_window_mark<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> &a, hipStream_t s) {
+    if (a.n_inj == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_window_check_inject<T>), dim3((a.n_inj + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_window_apply(const WindowArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_window_apply<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_window_fields(T *const F[6], const T *tmp, int32_t nx, size_t ncell, hipStream_t s) {
+    hipLaunchKernelGGL((k_window_fields<T>), dim3(grid_blocks(ncell)), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4],
+                       F[5], tmp, nx, FastDiv((uint32_t)nx), ncell);
+    return hipGetLastError();
+}
+template hipError_t launch_window_mark<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_mark<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_check_inject<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_check_inject<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_apply<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_apply<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_fields<float>(float *const[6], const float *, int32_t, size_t, hipStream_t);
+template hipError_t launch_window_fields<double>(double *const[6], const double *, int32_t, size_t, hipStream_t);
+
 template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterArgs<T> a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;

@@ -215,6 +215,29 @@ hipError_t launch_tile_count(const SortArgs &a, hipStream_t s);
 int32_t scan_part_len(int32_t n_tiles);
 hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, int32_t *part, hipStream_t s);
 
+// Moving window (Sec. III.C): the window advances one cell along +x.  A free
+// particle slot holds cell kDeadCell, zero weight, momentum and offsets.
+constexpr int32_t kDeadCell = -1;
+template <typename T> struct WindowArgs {
+    int32_t *cell; const int32_t *id; T *off[3]; T *u[3]; T *w; T *proxy;   // one species, in place
+    int32_t n;
+    uint32_t ncell;
+    int32_t nx;
+    FastDiv fnx;
+    int32_t *flag;               // [n], by id: 1 if the slot is free after the shift
+    const int32_t *rank;         // [n + 1]: exclusive scan of flag, rank[n] = free slots
+    const int32_t *in_cell;      // injected particles (device, n_inj): cells in the new last column
+    const T *in_off[3]; const T *in_u[3]; const T *in_w;
+    int32_t n_inj;
+    unsigned long long *bad;     // ids out of range / injected particles outside the new column
+};
+template <typename T> hipError_t launch_window_mark(const WindowArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> &a, hipStream_t s);
+template <typename T> hipError_t launch_window_apply(const WindowArgs<T> &a, hipStream_t s);
+// E2, B2 (six components of ncell) move down one index along x from tmp (a copy); the last column is cleared.
+template <typename T> hipError_t launch_window_fields(T *const F[6], const T *tmp, int32_t nx, size_t ncell,
+                                                      hipStream_t s);
+
 template <typename T> struct ScatterArgs {
     const int32_t *cell_src; const T *off_src[3]; const T *u_src[3]; const T *w_src; const int32_t *id_src;
     int32_t *cell_dst; T *off_dst[3]; T *u_dst[3]; T *w_dst; int32_t *id_dst;

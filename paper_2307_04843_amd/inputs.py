@@ -37,6 +37,33 @@ def density_ramp_x(n0, x_start, length):
     return lambda x, y, z: n0 * np.clip((x - x_start) / length, 0.0, 1.0)
 
 
+def pad_free(state, n_free, first_id):
+    """Append n_free free particle slots (cell -1, zero offsets, momentum and
+    weight) to a gridded state, with ids first_id, first_id + 1, ...; the
+    state's own ids are 0..N-1 (``id`` added when absent)."""
+    N = state["w"].shape[0]
+    out = dict(state)
+    out["id"] = np.concatenate([state.get("id", np.arange(N, dtype=np.int32)).astype(np.int32),
+                                np.arange(first_id, first_id + n_free, dtype=np.int32)])
+    out["cell"] = np.concatenate([state["cell"], np.full(n_free, -1, np.int32)])
+    out["off"] = np.concatenate([state["off"], np.zeros((3, n_free), state["off"].dtype)], axis=1)
+    out["u"] = np.concatenate([state["u"], np.zeros((3, n_free), state["u"].dtype)], axis=1)
+    out["w"] = np.concatenate([state["w"], np.zeros(n_free, state["w"].dtype)])
+    return out
+
+
+def window_column(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed, stream=0):
+    """Particles of the column a moving window adds: ``plasma`` on a grid one
+    cell wide at lab x = x_min[0] + (n_cells[0] - 1) dx[0] (x_min is the new
+    window's origin), with cells renumbered into the last column of the full
+    grid."""
+    nx = n_cells[0]
+    col = plasma(dim, (1,) + tuple(n_cells[1:]), dx, (x_min[0] + (nx - 1) * dx[0],) + tuple(x_min[1:]), ppc,
+                 density, temperature_ev, mass, seed, stream)
+    col["cell"] = (col["cell"].astype(np.int64) * nx + (nx - 1)).astype(np.int32)
+    return col
+
+
 def density_slab_x(n0, x0, x1):
     """n = n0 for x0 <= x < x1, else 0 (lambda units)."""
     return lambda x, y, z: np.where((x >= x0) & (x < x1), n0, 0.0)

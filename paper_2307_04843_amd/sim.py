@@ -26,12 +26,14 @@ class Simulation:
     lambda units.  ``proxy``: every species carries an emission proxy;
     ``pulse_on_grid``: the pulse may be sampled on the grid; ``open_x`` (1-D
     rows): incoming/outgoing-wave x ends, for pulses launched through x_min
-    (``set_pulse(..., sampling="boundary")``).
+    (``set_pulse(..., sampling="boundary")``); ``moving_window``: the window
+    can advance along x (``shift_window``); spare particle slots are passed as
+    free slots (cell -1, zero weight; ``inputs.pad_free``).
     """
 
     def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
                  precision="f32", tile=(0, 0, 0), sort_every=0, species=(), proxy=False,
-                 device="cuda:0", stream=None, pulse_on_grid=False, open_x=False):
+                 device="cuda:0", stream=None, pulse_on_grid=False, open_x=False, moving_window=False):
         if not torch.cuda.is_available():
             raise RuntimeError("the HIP path needs a GPU")
         apt.load()
@@ -52,7 +54,8 @@ class Simulation:
         g.sort_every = int(sort_every)
         g.options = ((apt.AP_GRID_PULSE_ON_GRID if pulse_on_grid else 0)
                      | (apt.AP_GRID_PROXY if (proxy and dim > 0) else 0)
-                     | (apt.AP_GRID_OPEN_X if open_x else 0))
+                     | (apt.AP_GRID_OPEN_X if open_x else 0)
+                     | (apt.AP_GRID_MOVING_WINDOW if moving_window else 0))
         self.grid_desc = g
         self.sp_desc = []
         for sp in species:
@@ -121,6 +124,31 @@ class Simulation:
     def set_pulse(self, kind, **params):
         ptype = apt.PULSE_TYPES[kind]
         apt.ap_set_pulse(self.ctx, ptype, apt.pulse_params(**params) if ptype != apt.AP_PULSE_NONE else None)
+
+    def shift_window(self, inject=None):
+        """Advance the window one cell along +x (ap_shift_window).  inject:
+        None or, per species, None or a state dict (cell, off, u, w) of the new
+        particles, cells in the new last column."""
+        arr = None
+        keep = []
+        if inject is not None:
+            arr = (apt.ap_inject * len(self.sp_desc))()
+            for i, st in enumerate(inject):
+                if st is None or len(st["w"]) == 0:
+                    continue
+                cell = _dev(np.asarray(st["cell"]), np.int32, self.device)
+                off = [_dev(np.asarray(st["off"][k]), self.np_dtype, self.device) for k in range(3)]
+                u = [_dev(np.asarray(st["u"][k]), self.np_dtype, self.device) for k in range(3)]
+                w = _dev(np.asarray(st["w"]), self.np_dtype, self.device)
+                keep += [cell, w] + off + u
+                arr[i].cell = cell.data_ptr()
+                for k in range(3):
+                    arr[i].off[k] = off[k].data_ptr() if self.arrays[i]["off"][k] is not None else None
+                    arr[i].u[k] = u[k].data_ptr()
+                arr[i].w = w.data_ptr()
+                arr[i].n = int(w.numel())
+        apt.ap_shift_window(self.ctx, arr)
+        del keep
 
     def eval_pulse(self, xyz, t):
         """E1, B1 at lab points xyz (3, n) in lambda units, time t; numpy (3, n) arrays."""

@@ -114,11 +114,13 @@ def periodic_diff(a, b, n):
     return d - n * np.round(d / n)
 
 
-def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0, pulse_on_grid=False, proxy=False):
+def sim_from_case(case, precision="f32", tile=(0, 0, 0), sort_every=0, pulse_on_grid=False, proxy=False,
+                  moving_window=False):
     from paper_2307_04843_amd.sim import Simulation
     sim = Simulation(case["dim"], n=case["n"], dx=case["dx"], x_min=case["x_min"], t0=case["t0"],
                      dt=case["dt"], precision=precision, tile=tile, sort_every=sort_every,
-                     species=case["species"], pulse_on_grid=pulse_on_grid, proxy=proxy)
+                     species=case["species"], pulse_on_grid=pulse_on_grid, proxy=proxy,
+                     moving_window=moving_window)
     E, B, _ = sim.field_views()
     import torch
     for k in range(3):

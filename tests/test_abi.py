@@ -62,7 +62,7 @@ def test_query_layout_sizes():
     (lambda g: setattr(g, "dt", 0.2), "stability"),
     (lambda g: setattr(g, "dt", float("nan")), "dt"),
     (lambda g: (g.n.__setitem__(0, 256), g.tile.__setitem__(0, 100)), "tile"),
-    (lambda g: setattr(g, "options", 0x8), "option"),
+    (lambda g: setattr(g, "options", 0x40), "option"),
 ])
 def test_query_layout_rejects_bad_grid(mut, msg):
     g = _grid()
@@ -150,6 +150,20 @@ def test_open_x_option_rows_only():
     base = apt.ap_query_layout(g1, [_sp()]).work_bytes
     g1.options = apt.AP_GRID_OPEN_X
     assert apt.ap_query_layout(g1, [_sp()]).work_bytes >= base
+
+
+def test_moving_window_option():
+    """AP_GRID_MOVING_WINDOW reserves the shift's workspace on grids and is
+    rejected without one."""
+    g = _grid()
+    base = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
+    g.options = apt.AP_GRID_MOVING_WINDOW
+    assert apt.ap_query_layout(g, [_sp(2048)]).work_bytes >= base + 6 * 64 * 32 * 4 + 2 * 2048 * 4
+    g0 = _grid(dim=0)
+    g0.dt = 0.01
+    g0.options = apt.AP_GRID_MOVING_WINDOW
+    with pytest.raises(apt.APTError, match="moving window"):
+        apt.ap_query_layout(g0, [_sp()])
 
 
 def test_pulse_params_struct_matches_header():
