@@ -23,7 +23,7 @@ Particle shape: quadratic B-spline ("second-order", Sec. II.B: the scaling
 runs used second-order current deposition) for both the gather and the
 charge-conserving deposition.
 
-Open x ends (1-D rows, ``Grid(..., open_x=True)``): the traditional
+Open x ends (1-D rows and (x, z) grids, ``Grid(..., open_x=True)``): the traditional
 comparison runs of Fig. demo launch the pulse through an incoming-wave
 boundary at x_min (App. B) and let it leave through x_max.  E nodes 0 and
 nx - 1 are the boundary nodes; the B nodes at nx - 1/2 lie outside and are
@@ -50,14 +50,15 @@ class Grid:
     reduced-dimensionality series of Sec. III.B), row k at lab z = x_min[2] +
     k dx[2] and lab y = the pulse's slice.  An inactive axis has no
     derivative, no motion and no stagger; a particle's coordinate on it is
-    the (integer) index of its row.  ``open_x`` (dim 1 only): the x ends are
-    incoming/outgoing-wave boundaries for E2, B2 (App. B)."""
+    the (integer) index of its row.  ``open_x`` (dim 1, 2): the x ends are
+    incoming/outgoing-wave boundaries for E2, B2 (App. B; on an (x, z) grid
+    the boundary update omits the z derivative of B_x, as App. B does)."""
 
     def __init__(self, dim, n, dx, dt, x_min, t0=0.0, open_x=False):
         if dim not in (1, 2, 3):
             raise ValueError("grid dimension must be 1, 2 or 3")
-        if open_x and dim != 1:
-            raise ValueError("open x boundaries are built for 1-D rows only")
+        if open_x and dim == 3:
+            raise ValueError("open x boundaries are built for 1-D rows and (x, z) grids")
         self.dim = dim
         self.open_x = bool(open_x)
         nx, ny, nz = n

@@ -139,7 +139,8 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
     if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY | AP_GRID_OPEN_X | AP_GRID_MOVING_WINDOW))
         return fail(AP_E_ARG, "unknown grid option bits");
     if ((g->options & AP_GRID_MOVING_WINDOW) && s.dim == 0) return fail(AP_E_ARG, "a moving window needs a grid");
-    if ((g->options & AP_GRID_OPEN_X) && s.dim != 1) return fail(AP_E_ARG, "AP_GRID_OPEN_X is built for 1-D rows only");
+    if ((g->options & AP_GRID_OPEN_X) && s.dim != 1 && s.dim != 2)
+        return fail(AP_E_ARG, "AP_GRID_OPEN_X is built for 1-D rows and (x, z) grids only");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
     if ((g->options & AP_GRID_PROXY) && s.dim == 0)

@@ -139,7 +139,7 @@ hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, 
         hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, 0, (const T *)nullptr, T(1));
         hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, 0);
     } else {
-        const int ox = dim == 1 && a.open_x ? 1 : 0;
+        const int ox = dim <= 2 && a.open_x ? 1 : 0;
         const T *src = static_cast<const T *>(a.src);
         const T r = T(a.dx[0] / a.dt);
         hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);

@@ -140,12 +140,15 @@ def test_proxy_option_reserves_workspace():
 
 
 def test_open_x_option_rows_only():
-    """AP_GRID_OPEN_X is built for 1-D rows: other dims reject it; rows take it
-    and reserve the per-row boundary source."""
-    g = _grid()
+    """AP_GRID_OPEN_X is built for 1-D rows and (x, z) grids: 3-D rejects it;
+    rows take it and reserve the per-row boundary source."""
+    g = _grid(dim=3, n=(16, 8, 8))
     g.options = apt.AP_GRID_OPEN_X
     with pytest.raises(apt.APTError, match="1-D rows"):
         apt.ap_query_layout(g, [_sp()])
+    g2 = _grid()
+    g2.options = apt.AP_GRID_OPEN_X
+    assert apt.ap_query_layout(g2, [_sp()]).work_bytes > 0
     g1 = _grid(dim=1)
     base = apt.ap_query_layout(g1, [_sp()]).work_bytes
     g1.options = apt.AP_GRID_OPEN_X

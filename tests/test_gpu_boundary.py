@@ -6,6 +6,8 @@
   vacuum and reflects from a 2 n_c slab of electrons and protons between 12
   and 16 lambda): fields (FP64 1e-9, FP32 vacuum 1e-5 of the largest) and the
   slab's momenta against the oracle's launched run.
+* The same on an (x, z) grid (12 rows, both polarisations; 8 rows with the
+  slab), the boundary update omitting dB_x/dz as App. B does.
 * Fig. demo(e) on the GPU: the launched pulse against the APT field of the
   same pulse (E1 from ap_eval_pulse at the E nodes; E2 = 0 in vacuum) at
   lambda/dx = 15, 30, 60: the cycle-averaged difference falls at fourth order
@@ -30,8 +32,9 @@ def _pulse(dxl, dtl, tau=10.0, fwhm=3.0, pol=0):
                 dx_prop=dxl, dt_prop=dtl, envelope="sgauss", sg_order=4, fwhm=fwhm)
 
 
-def _slab_species(n, dxl, rows):
-    e = inputs.plasma(1, (n, 1, rows), (dxl, dxl, 0.5), (0.0, 0.0, 0.0), 4, inputs.density_slab_x(2.0, 12.0, 16.0),
+def _slab_species(n, dxl, rows, dim=1):
+    dz = 0.5 if dim == 1 else dxl
+    e = inputs.plasma(dim, (n, 1, rows), (dxl, dxl, dz), (0.0, 0.0, 0.0), 4, inputs.density_slab_x(2.0, 12.0, 16.0),
                       0.0, 1.0, 71)
     keep = e["w"] > 0
     e = {k: (v[..., keep] if v.ndim == 2 else v[keep]) for k, v in e.items()}
@@ -40,31 +43,32 @@ def _slab_species(n, dxl, rows):
     return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=1836.15267343, state=p)]
 
 
-def _oracle_species(sps, n):
+def _oracle_species(sps, n, dim=1):
     out = []
     for sp in sps:
         st = sp["state"]
         cell = st["cell"].astype(np.int64)
         pos = np.zeros((3, cell.size))
         pos[0] = cell % n + st["off"][0].astype(float)
-        pos[2] = cell // n
+        pos[2] = cell // n + (st["off"][2].astype(float) if dim == 2 else 0.0)
         out.append(pic.Species(sp["q"], sp["m"], pos, st["u"].astype(float), st["w"].astype(float)))
     return out
 
 
-def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boundary"):
+def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boundary", dim=1, pol=0):
     from paper_2307_04843_amd.sim import Simulation
     dxl = 1.0 / 20.0
-    dtl = units.default_dt(dxl, 1)
-    pp = _pulse(dxl, dtl)
+    dtl = units.default_dt(dxl, dim)
+    dz = 0.5 if dim == 1 else dxl
+    pp = _pulse(dxl, dtl, pol=pol)
     if with_slab:
-        sps = _slab_species(n, dxl, rows)
+        sps = _slab_species(n, dxl, rows, dim)
     else:
         # one weightless electron: the run needs a species
         st = dict(cell=np.array([n // 2], np.int32), off=np.zeros((3, 1), np.float32),
                   u=np.zeros((3, 1), np.float32), w=np.zeros(1, np.float32))
         sps = [dict(q=-1.0, m=1.0, state=st)]
-    sim = Simulation(1, n=(n, 1, rows), dx=(dxl, dxl, 0.5), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=dtl,
+    sim = Simulation(dim, n=(n, 1, rows), dx=(dxl, dxl, dz), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=dtl,
                      precision=precision, species=sps, open_x=True)
     try:
         sim.set_pulse("plane", **{k: v for k, v in pp.items() if k != "type"}, sampling=sampling)
@@ -75,8 +79,8 @@ def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boun
         d, _ = sim.diag()
     finally:
         sim.close()
-    g = pic.Grid(1, (n, 1, rows), (dxl * L, dxl * L, 0.5 * L), dtl * L, (0.0, 0.0, 0.0), t0=0.0, open_x=True)
-    osp = _oracle_species(sps, n)
+    g = pic.Grid(dim, (n, 1, rows), (dxl * L, dxl * L, dz * L), dtl * L, (0.0, 0.0, 0.0), t0=0.0, open_x=True)
+    osp = _oracle_species(sps, n, dim)
     P = pulses.Pulse(dict(pp, dt=dtl))
     for _ in range(n_steps):
         pic.step(g, osp, P, launch=(sampling == "boundary"))
@@ -95,10 +99,26 @@ def test_launch_vacuum_parity(precision, tol):
     assert d.n_nonfinite == 0
 
 
+@pytest.mark.parametrize("pol", [0, 1])
+def test_launch_xz_grid_parity_fp64(pol):
+    """(x, z) grid with open x ends (dB_x/dz omitted at the boundary nodes), 12
+    rows, the plane pulse launched in either polarisation, vs the oracle."""
+    print("boundary launch, (x, z) grid, pol", pol, flush=True)
+    gf, _, d, g, _ = _run_launch("f64", False, rows=12, dim=2, pol=pol)
+    fmax = max(np.abs(c).max() for c in g.E + g.B)
+    assert fmax > 0.2
+    for k in range(3):
+        assert np.abs(gf[k] - g.E[k]).max() <= 1e-12 * fmax, ("E", k)
+        assert np.abs(gf[3 + k] - g.B[k]).max() <= 1e-12 * fmax, ("B", k)
+
+
 @pytest.mark.timeout(300)
-def test_launch_with_slab_parity_fp64():
-    print("boundary launch, slab", flush=True)
-    gf, out, d, g, osp = _run_launch("f64", True)
+@pytest.mark.parametrize("dim", [1, 2])
+def test_launch_with_slab_parity_fp64(dim):
+    print("boundary launch, slab, dim", dim, flush=True)
+    # the same 21.9 lambda/c in both: the reflection is well under way
+    gf, out, d, g, osp = _run_launch("f64", True, dim=dim, rows=2 if dim == 1 else 8,
+                                     n_steps=460 if dim == 1 else 650)
     fmax = max(np.abs(c).max() for c in g.E + g.B)
     for k in range(3):
         assert np.abs(gf[k] - g.E[k]).max() <= 1e-9 * fmax, ("E", k)
