@@ -540,15 +540,15 @@ METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 
 # launches of the profiled steps.  Valid only for the kernel sources whose
 # digest is recorded here (None once the sources change).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6f8f682f7735d8c451ba079b88b6631e093805602de73a75897b7d990bf889ac",
-    "fetch_bytes_per_launch": 4.12382e9,
-    "write_bytes_per_launch": 3.87974e9,
+    "sources_sha256": "8ef60c6618326b7d14e93695729af8ba8cca9389670ba397df3bc35e7e96346f",
+    "fetch_bytes_per_launch": 4.12096e9,
+    "write_bytes_per_launch": 3.87719e9,
     # SQ_INSTS_VALU x 64 / particles, same runs: VALU lane-ops issued per push
     "valu_lane_ops_per_push": 591.1,
     # SQ_LDS_IDX_ACTIVE / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs), and the bank-conflict share of it
-    "lds_busy_frac": 0.817,
+    "lds_busy_frac": 0.819,
     "lds_bank_conflict_frac": 0.380,
-    "note": "average over the 2000 launches of the default run (calibration copy factors "
+    "note": "average over the 2000 timed launches of the default run (calibration copy factors "
             "0.500 fetch, 1.000 write), profiles/push_deposit_2d_lg_4096x1024_f32.md",
 }
 # Non-packed FP32 VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.

@@ -342,6 +342,10 @@ struct ap_ctx {
     PulseDev P;
     int pulse_type = -1;
     double s0 = 1.0;             // S0/E0 of the incoming-wave boundary (AP_SAMPLE_BOUNDARY)
+    // moving window: free particle slots (all species) and the skipped-particle
+    // count they add to the push's counter, which the diagnostics subtract
+    int64_t n_free = 0;
+    uint64_t free_skips = 0;
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
@@ -490,6 +494,17 @@ ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int3
                 e = launch_fill_zero<double>(static_cast<double *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
             else
                 e = launch_fill_zero<float>(static_cast<float *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
+        }
+        if (e == hipSuccess && (s.options & AP_GRID_MOVING_WINDOW)) {
+            // free slots the caller passes as spare capacity
+            unsigned long long *cnt = c->counters() + 5;
+            for (int i = 0; i < s.nsp && e == hipSuccess; ++i)
+                if (s.np[i] > 0) e = launch_count_free(buffers->sp[i].cell, (int32_t)s.np[i], cnt, c->stream);
+            unsigned long long nf = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess) e = launch_fill_zero<unsigned long long>(cnt, 1, c->stream);
+            c->n_free = (int64_t)nf;
         }
         if (e != hipSuccess) {
             delete c;
@@ -787,7 +802,8 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
     HIPCHK(hipStreamSynchronize(c->stream), "ap_gather_diag");
     d.t = (s.t0 + (double)c->step * s.dt) / kTwoPi;
     d.step = c->step;
-    int64_t nonfinite = (int64_t)cnt[1];
+    // free slots (moving window) are skipped by the push like invalid particles: not an error
+    int64_t nonfinite = (int64_t)(cnt[1] - c->free_skips);
     if (what & AP_DIAG_PARTICLES) {
         for (int i = 0; i < s.nsp; ++i) {
             const double *v = host + (size_t)i * kDiagVals;
@@ -1239,6 +1255,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     const int n = (int)s.np[sp];
     unsigned long long *cnt = c->counters();
     unsigned long long saved[kCounters];
+    const uint64_t saved_skips = c->free_skips;
     {
         // the adjoint state is indexed by particle id: ids must be 0..n-1, each once
         int32_t *seen = c->wp<int32_t>(c->L.rank[sp]);
@@ -1319,6 +1336,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     c->step = c->rec_step0 + c->rec_n;
     c->need_sort = true;
     HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
+    c->free_skips = saved_skips;
     double *sums = c->wp<double>(c->L.sums);
     HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
     double host[5];
@@ -1342,6 +1360,7 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     const size_t nc = (size_t)s.ncell;
     unsigned long long *cnt = c->counters();
     unsigned long long saved[kCounters];
+    const uint64_t saved_skips = c->free_skips;
     HIPCHK(hipMemcpyAsync(saved, cnt, sizeof(saved), hipMemcpyDeviceToHost, c->stream), "backward");
     for (int i = 0; i < s.nsp; ++i) {
         // each adjoint state is indexed by particle id: ids must be 0..n-1, each once
@@ -1450,6 +1469,7 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     c->step = c->rec_step0 + c->rec_n;
     c->need_sort = true;
     HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
+    c->free_skips = saved_skips;
     double *sums = c->wp<double>(c->L.sums);
     HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
     double host[5];
@@ -1465,6 +1485,7 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
     const WorkLayout &L = c->L;
     unsigned long long *bad = c->counters() + 5;
     // validate everything before changing anything
+    int64_t free_after = 0;
     for (int i = 0; i < s.nsp; ++i) {
         const int64_t k = inject ? inject[i].n : 0;
         if (k < 0 || k > s.np[i]) return fail(AP_E_ARG, "species " + std::to_string(i) + ": bad injection count");
@@ -1529,6 +1550,7 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
         HIPCHK(hipMemcpyAsync(&nfree, c->wp<int32_t>(L.wrank) + s.np[i], 4, hipMemcpyDeviceToHost, c->stream),
                "shift window");
         HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+        free_after += nfree - (inject ? inject[i].n : 0);
         if (inject && inject[i].n > nfree)
             return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(inject[i].n) +
                                       " injected particles but " + std::to_string(nfree) + " free slots");
@@ -1556,6 +1578,7 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
     c->s.x_min[0] += s.dx[0];
     c->need_sort = true;
     c->rec_n = 0;
+    c->n_free = free_after;
     return AP_OK;
 }
 
@@ -1761,6 +1784,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
                                   : launch_push_deposit_3d<T>(push_pulse, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
+        c->free_skips += (uint64_t)c->n_free;   // free slots take the push's skipped-particle path
     }
     if (s.prec == AP_F32) {
         // one rounding of the FP64 sum per node keeps continuity at FP32 round-off

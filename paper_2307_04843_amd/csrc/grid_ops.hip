@@ -499,6 +499,17 @@ hipError_t launch_window_fields(T *const F[6], const T *tmp, int32_t nx, size_t 
                        F[5], tmp, nx, FastDiv((uint32_t)nx), ncell);
     return hipGetLastError();
 }
+__global__ __launch_bounds__(256) void k_count_free(const int32_t *cell, int32_t n, unsigned long long *count) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = p < n && cell[p] == kDeadCell;
+    const unsigned long long b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+hipError_t launch_count_free(const int32_t *cell, int32_t n, unsigned long long *count, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_free, dim3((n + 255) / 256), dim3(256), 0, s, cell, n, count);
+    return hipGetLastError();
+}
 template hipError_t launch_window_mark<float>(const WindowArgs<float> &, hipStream_t);
 template hipError_t launch_window_mark<double>(const WindowArgs<double> &, hipStream_t);
 template hipError_t launch_window_check_inject<float>(const WindowArgs<float> &, hipStream_t);

@@ -232,6 +232,8 @@ template <typename T> struct WindowArgs {
     unsigned long long *bad;     // ids out of range / injected particles outside the new column
 };
 template <typename T> hipError_t launch_window_mark(const WindowArgs<T> &a, hipStream_t s);
+// *count += number of free slots (cell == kDeadCell) among n cells.
+hipError_t launch_count_free(const int32_t *cell, int32_t n, unsigned long long *count, hipStream_t s);
 template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_window_apply(const WindowArgs<T> &a, hipStream_t s);
 // E2, B2 (six components of ncell) move down one index along x from tmp (a copy); the last column is cleared.

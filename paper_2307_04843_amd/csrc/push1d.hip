@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
             // a particle belongs to its tile's row; anything else is invalid state
             const bool ok = (unsigned)cell < ncell && prow == row && offx >= T(0) && offx < T(1);
             if (!ok) {
-                if (cell != kDeadCell) atomicAdd(a.n_bad, 1ull);   // a free slot is not an error
+                atomicAdd(a.n_bad, 1ull);
                 S.cell_out[p] = cell;
                 S.off_out[0][p] = offx;
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;

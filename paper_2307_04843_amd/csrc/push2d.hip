@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             const bool ok = (unsigned)cell < ncell && offx >= T(0) && offx < T(1) &&
                             offz >= T(0) && offz < T(1);
             if (!ok) {
-                if (cell != kDeadCell) atomicAdd(a.n_bad, 1ull);   // a free slot is not an error
+                atomicAdd(a.n_bad, 1ull);
                 S.cell_out[p] = cell;
                 S.off_out[0][p] = offx;
                 S.off_out[2][p] = offz;

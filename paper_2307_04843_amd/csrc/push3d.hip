@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_3d(PushArgs<T> a) {
             T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
             const T w = w_in[p];
             if (!ok) {
-                if (cell != kDeadCell) atomicAdd(a.n_bad, 1ull);   // a free slot is not an error
+                atomicAdd(a.n_bad, 1ull);
                 S.cell_out[p] = cell;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) S.off_out[c][p] = off[c];
