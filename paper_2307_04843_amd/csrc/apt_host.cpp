@@ -55,7 +55,8 @@ struct RunShape {
 struct WorkLayout {
     size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, bsrc = 0,
            total = 0;
-    size_t wtmp = 0, wflag = 0, wrank = 0, wpart = 0;   // moving window: field copy, free-slot flags and ranks
+    size_t wtmp = 0, wpart = 0;   // moving window: field copy, scan scratch
+    size_t wflag[kMaxSpecies] = {}, wrank[kMaxSpecies] = {};   // per species: free-slot flags and ranks by id
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -200,8 +201,10 @@ WorkLayout make_layout(const RunShape &s) {
             int64_t nmax = 0;
             for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
             L.wtmp = take((size_t)6 * (size_t)s.ncell * s.real);
-            L.wflag = take((size_t)(nmax + 1) * 4);
-            L.wrank = take((size_t)(nmax + 1) * 4);
+            for (int i = 0; i < s.nsp; ++i) {
+                L.wflag[i] = take((size_t)(s.np[i] + 1) * 4);
+                L.wrank[i] = take((size_t)(s.np[i] + 1) * 4);
+            }
             L.wpart = take((size_t)2 * scan_part_len((int32_t)(nmax > 0 ? nmax : 1)) * 4);
         }
         for (int i = 0; i < s.nsp; ++i) {
@@ -1511,8 +1514,8 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
         a.ncell = (uint32_t)s.ncell;
         a.nx = s.n[0];
         a.fnx = FastDiv((uint32_t)s.n[0]);
-        a.flag = c->wp<int32_t>(L.wflag);
-        a.rank = c->wp<int32_t>(L.wrank);
+        a.flag = c->wp<int32_t>(L.wflag[i]);
+        a.rank = c->wp<int32_t>(L.wrank[i]);
         a.bad = bad;
         if (inject && inject[i].n > 0) {
             const ap_inject &in = inject[i];
@@ -1526,37 +1529,37 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
         }
         return a;
     };
-    auto count = [&](const char *what) -> ap_status {
-        unsigned long long b = 0;
-        HIPCHK(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, c->stream), "shift window");
-        HIPCHK(hipStreamSynchronize(c->stream), "shift window");
-        if (b != 0) return fail(AP_E_ARG, what);
-        return AP_OK;
-    };
+    // every species: injected particles checked (counter bad), ids checked
+    // (counter bad + 1), free slots marked by id and ranked; one synchronisation
+    HIPCHK(launch_fill_zero<unsigned long long>(bad, 2, c->stream), "shift window");
+    int32_t nfree[kMaxSpecies] = {0, 0, 0, 0};
     for (int i = 0; i < s.nsp; ++i) {
         if (s.np[i] == 0) continue;
-        const WindowArgs<T> a = args(i);
-        HIPCHK(launch_fill_zero<unsigned long long>(bad, 1, c->stream), "shift window");
+        WindowArgs<T> a = args(i);
         HIPCHK(launch_window_check_inject<T>(a, c->stream), "shift window");
-        ap_status st = count("injected particles must sit in the new last column with offsets in [0, 1)");
-        if (st != AP_OK) return st;
+        a.bad = bad + 1;
         HIPCHK(launch_fill_zero<int32_t>(a.flag, (size_t)s.np[i], c->stream), "shift window");
         HIPCHK(launch_window_mark<T>(a, c->stream), "shift window");
-        st = count("particle ids are not a permutation of 0..n-1");
-        if (st != AP_OK) return st;
-        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank), (int32_t)s.np[i], c->wp<int32_t>(L.wpart), c->stream),
+        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank[i]), (int32_t)s.np[i], c->wp<int32_t>(L.wpart),
+                           c->stream), "shift window");
+        HIPCHK(hipMemcpyAsync(&nfree[i], c->wp<int32_t>(L.wrank[i]) + s.np[i], 4, hipMemcpyDeviceToHost, c->stream),
                "shift window");
-        int32_t nfree = 0;
-        HIPCHK(hipMemcpyAsync(&nfree, c->wp<int32_t>(L.wrank) + s.np[i], 4, hipMemcpyDeviceToHost, c->stream),
-               "shift window");
-        HIPCHK(hipStreamSynchronize(c->stream), "shift window");
-        free_after += nfree - (inject ? inject[i].n : 0);
-        if (inject && inject[i].n > nfree)
-            return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(inject[i].n) +
-                                      " injected particles but " + std::to_string(nfree) + " free slots");
     }
-    // apply: fields, then each species (its flags and ranks recomputed: the
-    // workspace holds one species at a time)
+    unsigned long long b[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(b, bad, sizeof(b), hipMemcpyDeviceToHost, c->stream), "shift window");
+    HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+    if (b[0] != 0 || b[1] != 0) {
+        HIPCHK(launch_fill_zero<unsigned long long>(bad, 2, c->stream), "shift window");
+        return fail(AP_E_ARG, b[0] != 0 ? "injected particles must sit in the new last column with offsets in [0, 1)"
+                                        : "particle ids are not a permutation of 0..n-1");
+    }
+    for (int i = 0; i < s.nsp; ++i) {
+        if (inject && inject[i].n > nfree[i])
+            return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(inject[i].n) +
+                                      " injected particles but " + std::to_string(nfree[i]) + " free slots");
+        free_after += nfree[i] - (inject ? inject[i].n : 0);
+    }
+    // apply: fields, then each species from its ranks
     T *grid = static_cast<T *>(c->buf.grid);
     const size_t nc = (size_t)s.ncell;
     T *F[6];
@@ -1564,16 +1567,8 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
     T *tmp = c->wp<T>(L.wtmp);
     HIPCHK(hipMemcpyAsync(tmp, grid, 6 * nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "shift window");
     HIPCHK(launch_window_fields<T>(F, tmp, s.n[0], nc, c->stream), "shift window");
-    for (int i = 0; i < s.nsp; ++i) {
-        if (s.np[i] == 0) continue;
-        const WindowArgs<T> a = args(i);
-        HIPCHK(launch_fill_zero<int32_t>(a.flag, (size_t)s.np[i], c->stream), "shift window");
-        HIPCHK(launch_window_mark<T>(a, c->stream), "shift window");
-        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank), (int32_t)s.np[i], c->wp<int32_t>(L.wpart), c->stream),
-               "shift window");
-        HIPCHK(launch_window_apply<T>(a, c->stream), "shift window");
-    }
-    HIPCHK(launch_fill_zero<unsigned long long>(bad, 1, c->stream), "shift window");
+    for (int i = 0; i < s.nsp; ++i)
+        if (s.np[i] > 0) HIPCHK(launch_window_apply<T>(args(i), c->stream), "shift window");
     HIPCHK(hipStreamSynchronize(c->stream), "shift window");
     c->s.x_min[0] += s.dx[0];
     c->need_sort = true;
