@@ -19,7 +19,7 @@ import torch
 
 import bench
 from oracle import pic, pulses, units
-from paper_2307_04843_amd import apt
+from paper_2307_04843_amd import apt, inputs
 from paper_2307_04843_amd.sim import Simulation
 from tests import cases
 
@@ -91,6 +91,46 @@ def _check_one_step(sim, species, ids, P, dt):
     return worst_u, worst_x
 
 
+def _check_window_shift(sim, species, ids):
+    """One moving-window shift at full size (Sec. III.C): the fields move down
+    one index exactly (new column zero); sampled particles outside the first
+    column move down one cell with offsets and momenta unchanged; those in it
+    leave; 1 + 1 particle per cell of the new column are injected; the run
+    steps on with no invalid particle."""
+    nx = bench.N_CELLS[0]
+    E, B, _ = sim.field_views()
+    before = [t.cpu().numpy().copy() for t in E + B]
+    pre = [_select(sim, i, ids[i]) for i in range(len(species))]
+    x_min = (bench.LAMBDA_DX, 0.0, -25.6)
+    dens = inputs.density_ramp_x(0.05, 0.0, 200.0)
+    e = inputs.window_column(2, bench.N_CELLS, (bench.LAMBDA_DX,) * 3, x_min, 1, dens, 1.0, 1.0, 91)
+    p = inputs.window_column(2, bench.N_CELLS, (bench.LAMBDA_DX,) * 3, x_min, 1, dens, 1.0, inputs.PROTON_MASS,
+                             91, stream=1)
+    p["cell"], p["off"] = e["cell"], e["off"]
+    sim.shift_window([e, p])
+    E, B, _ = sim.field_views()
+    for t, b in zip(E + B, before):
+        a = t.cpu().numpy()
+        assert np.array_equal(a[..., :-1], b[..., 1:]) and not a[..., -1].any()
+    for i in range(len(species)):
+        post = _select(sim, i, ids[i])
+        a = pre[i]
+        assert np.array_equal(a["id"], post["id"])
+        stay = (a["cell"] % nx) != 0
+        assert stay.sum() > 0.9 * stay.size
+        assert np.array_equal(post["cell"][stay], a["cell"][stay] - 1)
+        assert np.array_equal(post["off"][:, stay], a["off"][:, stay])
+        assert np.array_equal(post["u"][:, stay], a["u"][:, stay])
+        gone = post["cell"][~stay]
+        assert np.all((gone == -1) | (gone % nx == nx - 1))
+        cells = sim.arrays[i]["cell"]
+        last = int(((cells >= 0) & (cells % nx == nx - 1)).sum())
+        assert last >= e["w"].size
+    sim.step(1)
+    d, _ = sim.diag()
+    assert d.n_nonfinite == 0 and d.n_fast == 0
+
+
 @pytest.mark.timeout(900)
 def test_full_size_lg_run_sampled_pushes_and_continuity():
     species = bench.workload_inputs()
@@ -100,13 +140,14 @@ def test_full_size_lg_run_sampled_pushes_and_continuity():
     P = pulses.Pulse(dict(type="lg", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
     ids = [_sample_ids(n, seed=20 + i) for i, n in enumerate(n_part)]
     sim = Simulation(2, n=bench.N_CELLS, dx=(bench.LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
-                     precision="f32", species=species)
+                     precision="f32", species=species, moving_window=True)
     del species[0]["state"], species[1]["state"]
     try:
         sim.set_pulse("lg", **pp)
         sim.step(399)
         results = [_check_one_step(sim, species, ids, P, dt) for _ in range(2)]   # in-place, then re-sort
         d, _ = sim.diag()
+        _check_window_shift(sim, species, ids)
     finally:
         sim.close()
     for worst_u, worst_x in results:
