@@ -1,7 +1,8 @@
 """Moving window (Sec. III.C) on the HIP path vs the oracle.
 
 A 2-D LG replica (32 x 16 cells, electrons and protons, u x5, spare slots for
-a quarter of the particles) and 1-D LG rows (64 cells x 3 rows) advance 24
+a quarter of the particles), 1-D LG rows (64 cells x 3 rows) and a 3-D
+Gaussian replica (16 x 10 x 8) advance 24
 steps with the window shifted every 4 steps; each shift injects a fresh
 column of plasma (``inputs.window_column``, its own seed).  Fields and, by
 particle id, the live particles' cells, offsets and momenta match the
@@ -25,6 +26,17 @@ N_STEPS, EVERY = 24, 4
 def _setup(dim):
     if dim == 2:
         case = cases.make_case(n=(32, 1, 16), seed=81, u_scale=5.0, ppc=2)
+    elif dim == 3:
+        from oracle import units
+        dxl = 0.0625
+        n = (16, 10, 8)
+        dt = units.default_dt(dxl, 3)
+        box = tuple(nn * dxl for nn in n)
+        pp = dict(type="gauss", a0=3.0, tau=20.0, x_ref=box[0] / 2, t_ref=10.0, x_f=box[0] / 2 + 0.3, w0=1.0,
+                  y_c=box[1] / 2, z_c=box[2] / 2, d_f=3, pol=1, dispersion=units.DISP_PAPER2, dx_prop=dxl,
+                  dt_prop=dt, dt=dt)
+        case = cases.make_case(dim=3, n=n, dxl=dxl, x_min=(0.0, 0.0, 0.0), t0_steps=int(10.0 / dt), ppc=2,
+                               pulse=pp, u_scale=5.0, seed=83)
     else:
         case = cases.make_case(dim=1, n=(64, 1, 3), seed=82, u_scale=5.0, ppc=2, x_min=(48.0, 0.0, 4.4),
                                t0_steps=1343)
@@ -77,7 +89,7 @@ def _col_for_oracle(case, col):
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("dim", [2, 1])
+@pytest.mark.parametrize("dim", [2, 1, 3])
 def test_moving_window_matches_oracle_fp64(dim):
     case = _setup(dim)
     print("moving window, dim", dim, flush=True)
@@ -124,7 +136,7 @@ def test_moving_window_matches_oracle_fp64(dim):
         order = np.argsort(sp.ids)
         o2 = np.argsort(st["id"][live])
         pos = cases.gpu_positions(case, {"cell": st["cell"][live], "off": st["off"][:, live]})
-        for ax in (0, 2):
+        for ax in (0, 1, 2) if dim == 3 else (0, 2):
             assert np.abs(pos[ax][o2] - sp.pos[ax][order]).max() <= 1e-10, ax
         assert np.abs(st["u"][:, live][:, o2] - sp.u[:, order]).max() <= 1e-10 * max(np.abs(sp.u).max(), 1.0)
 
