@@ -540,9 +540,9 @@ METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 
 # launches of the profiled steps.  Valid only for the kernel sources whose
 # digest is recorded here (None once the sources change).
 MEASURED_TRAFFIC = {
-    "sources_sha256": "6c6db1afafda3dd35148c509de0fdb9eb57a96991cfd47151f7bd02a9423e612",
-    "fetch_bytes_per_launch": 4.12349e9,
-    "write_bytes_per_launch": 3.88031e9,
+    "sources_sha256": "1bff5f437f62f4347e035d317f352786d2306d624b42597e48b8d3aa6f97849b",
+    "fetch_bytes_per_launch": 4.12356e9,
+    "write_bytes_per_launch": 3.87995e9,
     # SQ_INSTS_VALU x 64 / particles, same runs: VALU lane-ops issued per push
     "valu_lane_ops_per_push": 591.1,
     # SQ_LDS_IDX_ACTIVE / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs), and the bank-conflict share of it

@@ -80,11 +80,12 @@ typedef int32_t ap_status;
                                       proxy (reserves its re-sort workspace)  */
 #define AP_GRID_MOVING_WINDOW 0x8  /* gridded runs: reserves the workspace of
                                       ap_shift_window                          */
-#define AP_GRID_OPEN_X        0x4  /* dim 1, 2: the x ends of every row are
-                                      incoming/outgoing-wave boundaries for E2,
-                                      B2 (App. B, first order, normal
-                                      incidence; on an (x, z) grid the
-                                      boundary update omits dB_x/dz).  E nodes 0 and n[0]-1 are the
+#define AP_GRID_OPEN_X        0x4  /* gridded runs: the x ends of every row
+                                      are incoming/outgoing-wave boundaries for
+                                      E2, B2 (App. B, first order, normal
+                                      incidence; on 2-D and 3-D grids the
+                                      boundary update omits the transverse
+                                      derivatives of B_x).  E nodes 0 and n[0]-1 are the
                                       boundary nodes; the transverse B nodes at
                                       n[0]-1/2 lie outside and are held at 0;
                                       J is not applied at the boundary nodes.

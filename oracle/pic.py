@@ -23,7 +23,7 @@ Particle shape: quadratic B-spline ("second-order", Sec. II.B: the scaling
 runs used second-order current deposition) for both the gather and the
 charge-conserving deposition.
 
-Open x ends (1-D rows and (x, z) grids, ``Grid(..., open_x=True)``): the traditional
+Open x ends (``Grid(..., open_x=True)``): the traditional
 comparison runs of Fig. demo launch the pulse through an incoming-wave
 boundary at x_min (App. B) and let it leave through x_max.  E nodes 0 and
 nx - 1 are the boundary nodes; the B nodes at nx - 1/2 lie outside and are
@@ -50,15 +50,14 @@ class Grid:
     reduced-dimensionality series of Sec. III.B), row k at lab z = x_min[2] +
     k dx[2] and lab y = the pulse's slice.  An inactive axis has no
     derivative, no motion and no stagger; a particle's coordinate on it is
-    the (integer) index of its row.  ``open_x`` (dim 1, 2): the x ends are
-    incoming/outgoing-wave boundaries for E2, B2 (App. B; on an (x, z) grid
-    the boundary update omits the z derivative of B_x, as App. B does)."""
+    the (integer) index of its row.  ``open_x``: the x ends are
+    incoming/outgoing-wave boundaries for E2, B2 (App. B; on 2-D and 3-D
+    grids the boundary update omits the transverse derivatives of B_x, as
+    App. B does)."""
 
     def __init__(self, dim, n, dx, dt, x_min, t0=0.0, open_x=False):
         if dim not in (1, 2, 3):
             raise ValueError("grid dimension must be 1, 2 or 3")
-        if open_x and dim == 3:
-            raise ValueError("open x boundaries are built for 1-D rows and (x, z) grids")
         self.dim = dim
         self.open_x = bool(open_x)
         nx, ny, nz = n
@@ -291,7 +290,8 @@ def _e_full(grid, source=None):
         x_max: (1 + r) E_y' = 2 B_z(nx - 3/2) + (r - 1) E_y
                (1 + r) E_z' = -2 B_y(nx - 3/2) + (r - 1) E_z
     (B at the half step, as in the bulk update; J is not applied at the
-    boundary nodes).  ``source`` is (S_y, S_z) per row at t^{n+1/2}, or None."""
+    boundary nodes).  ``source`` is (S_y, S_z) per row of x nodes ((z, y)
+    order) at t^{n+1/2}, or None."""
     Bx, By, Bz = grid.B
     dt = grid.dt
     if grid.open_x:
@@ -305,7 +305,8 @@ def _e_full(grid, source=None):
     grid.E[2] = grid.E[2] + dt * (cz - grid.J[2])
     if grid.open_x:
         r = grid.dx[0] / dt
-        sy, sz = (0.0, 0.0) if source is None else (source[0][:, None], source[1][:, None])
+        shape = grid.E[1][..., 0].shape
+        sy, sz = (0.0, 0.0) if source is None else (np.reshape(source[0], shape), np.reshape(source[1], shape))
         grid.E[1][..., 0] = (4.0 * sy - 2.0 * Bz[..., 0] + (r - 1.0) * old_y[..., 0]) / (1.0 + r)
         grid.E[2][..., 0] = (4.0 * sz + 2.0 * By[..., 0] + (r - 1.0) * old_z[..., 0]) / (1.0 + r)
         grid.E[1][..., -1] = (2.0 * Bz[..., -2] + (r - 1.0) * old_y[..., 1]) / (1.0 + r)
@@ -335,10 +336,11 @@ def boundary_source(grid, pulse, t):
     """(S_y, S_z) per row at time t for a pulse launched through the x_min
     boundary: S0/E0 times the pulse's transverse E at (x_min, row) (App. B;
     the source carries the pulse's own envelope and phase at the boundary)."""
-    nz = grid.n[2]
-    X = np.full(nz, grid.x_min[0])
-    Y = np.full(nz, pulse.q_slice)
-    Z = grid.x_min[2] + np.arange(nz) * grid.dx[2]
+    nz, ny = grid.n[2], grid.n[1]
+    kk, jj = np.meshgrid(np.arange(nz), np.arange(ny), indexing="ij")
+    X = np.full(kk.shape, grid.x_min[0])
+    Y = grid.x_min[1] + jj * grid.dx[1] if grid.dim == 3 else np.full(kk.shape, pulse.q_slice)
+    Z = grid.x_min[2] + kk * grid.dx[2]
     E1 = _pulses.analytic_fields(pulse, t, X, Y, Z)[0]
     s0 = incoming_wave_s0(grid.dx[0], grid.dt)
     return s0 * np.asarray(E1[1], dtype=float), s0 * np.asarray(E1[2], dtype=float)

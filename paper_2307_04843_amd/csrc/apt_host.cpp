@@ -140,8 +140,7 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
     if (g->options & ~(AP_GRID_PULSE_ON_GRID | AP_GRID_PROXY | AP_GRID_OPEN_X | AP_GRID_MOVING_WINDOW))
         return fail(AP_E_ARG, "unknown grid option bits");
     if ((g->options & AP_GRID_MOVING_WINDOW) && s.dim == 0) return fail(AP_E_ARG, "a moving window needs a grid");
-    if ((g->options & AP_GRID_OPEN_X) && s.dim != 1 && s.dim != 2)
-        return fail(AP_E_ARG, "AP_GRID_OPEN_X is built for 1-D rows and (x, z) grids only");
+    if ((g->options & AP_GRID_OPEN_X) && s.dim == 0) return fail(AP_E_ARG, "AP_GRID_OPEN_X needs a grid");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
     if ((g->options & AP_GRID_PROXY) && s.dim == 0)
@@ -196,7 +195,7 @@ WorkLayout make_layout(const RunShape &s) {
         if (s.options & AP_GRID_PULSE_ON_GRID) L.esamp = take((size_t)s.ncell * 6 * s.real);
         L.scan_part = take((size_t)2 * scan_part_len((int32_t)s.ntiles) * 4);
         // boundary source S_y, S_z per row (incoming-wave x_min of open rows)
-        if (s.options & AP_GRID_OPEN_X) L.bsrc = take((size_t)s.n[2] * 2 * s.real);
+        if (s.options & AP_GRID_OPEN_X) L.bsrc = take((size_t)s.n[1] * s.n[2] * 2 * s.real);
         if (s.options & AP_GRID_MOVING_WINDOW) {
             int64_t nmax = 0;
             for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
@@ -1823,7 +1822,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         if (launch && !(flags & AP_STEP_NO_YEE)) {
             BoundaryArgs<T> ba{};
             ba.S = c->wp<T>(L.bsrc);
-            ba.rows = s.n[2];
+            ba.rows = s.n[1] * s.n[2];
+            ba.ny = s.n[1];
             for (int k = 0; k < 3; ++k) {
                 ba.x_min[k] = s.x_min[k];
                 ba.dx[k] = s.dx[k];

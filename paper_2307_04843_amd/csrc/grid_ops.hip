@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_yee_b(T *__restrict__ Ex, T *__restrict
         }
         Bx[c] -= cx;
         // open x ends: the transverse B nodes at nx - 1/2 lie outside the domain
-        const bool ghost = DIM == 2 && open_x && i == g.nx - 1;
+        const bool ghost = open_x && i == g.nx - 1;
         By[c] = ghost ? T(0) : By[c] - cy;
         Bz[c] = ghost ? T(0) : Bz[c] - cz;
         (void)j;
@@ -91,14 +91,15 @@ __global__ __launch_bounds__(256) void k_yee_e(T *__restrict__ Ex, T *__restrict
         }
         const T ey = Ey[c], ez = Ez[c];
         T ny = ey + (qy - dt * Jy[c]), nz = ez + (qz - dt * Jz[c]);
-        if (DIM == 2 && open_x && (i == 0 || i == g.nx - 1)) {
+        if (open_x && (i == 0 || i == g.nx - 1)) {
             // App. B: Ampere's law with the outside B node and the step-averaged
             // incoming-wave condition (x_min: E_y + B_z = 2 S_y, E_z - B_y = 2 S_z;
             // x_max: no incoming wave), solved for the new boundary E; J is not
             // applied at the boundary nodes
             const T ir = T(1) / (T(1) + r), rm = r - T(1);
             if (i == 0) {
-                const T sy = src ? src[2 * k] : T(0), sz = src ? src[2 * k + 1] : T(0);
+                // one source pair per row of x nodes (the row index is j + ny k)
+                const T sy = src ? src[2 * row] : T(0), sz = src ? src[2 * row + 1] : T(0);
                 ny = (T(4) * sy - T(2) * bz + rm * ey) * ir;
                 nz = (T(4) * sz + T(2) * by + rm * ez) * ir;
             } else {
@@ -134,14 +135,14 @@ hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &a, int no_yee, 
     const T hz = dim == 1 ? T(0) : T(0.5 * a.dt / a.dx[2]);
     const T cx = T(a.dt / a.dx[0]), cy = T(a.dt / a.dx[1]);
     const T cz = dim == 1 ? T(0) : T(a.dt / a.dx[2]);
+    const int ox = a.open_x ? 1 : 0;
+    const T *src = static_cast<const T *>(a.src);
+    const T r = T(a.dx[0] / a.dt);
     if (dim == 3) {
-        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, 0);
-        hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, 0, (const T *)nullptr, T(1));
-        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, 0);
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);
+        hipLaunchKernelGGL((k_yee_e<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, ox, src, r);
+        hipLaunchKernelGGL((k_yee_b<T, 3>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);
     } else {
-        const int ox = dim <= 2 && a.open_x ? 1 : 0;
-        const T *src = static_cast<const T *>(a.src);
-        const T r = T(a.dx[0] / a.dt);
         hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);
         hipLaunchKernelGGL((k_yee_e<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], F[6], F[7], F[8], g, cx, cy, cz, T(a.dt), ncell, ox, src, r);
         hipLaunchKernelGGL((k_yee_b<T, 2>), dim3(blocks), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4], F[5], g, hx, hy, hz, ncell, ox);

@@ -158,15 +158,16 @@ struct YeeArgsBase {
     int32_t n[3];
     double dx[3];
     double dt;
-    int32_t open_x;              // 1-D rows: incoming/outgoing-wave x ends (App. B)
+    int32_t open_x;              // incoming/outgoing-wave x ends (App. B)
     const void *src;             // open x: [rows][2] boundary source S_y, S_z at t^{n+1/2}, or null
 };
 
 // Incoming-wave boundary source (App. B): per row, S0/E0 times the pulse's
 // transverse E at (x_min, row) and the step's half time.
 template <typename T> struct BoundaryArgs {
-    T *S;                        // [rows][2]
+    T *S;                        // [rows][2], row = j + ny k
     int32_t rows;
+    int32_t ny;                  // rows along y (3-D), else 1
     double x_min[3], dx[3];
     double q_slice;
     double s0;                   // S0 / E0

@@ -136,7 +136,9 @@ template <typename T, int PT> __global__ __launch_bounds__(64) void k_boundary_s
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.rows) return;
     T e[3], b[3];
-    analytic_field<PT, T>(a.W, a.x_min[0], a.q_slice, a.x_min[2] + (double)r * a.dx[2], e, b);
+    const int j = r % a.ny, k = r / a.ny;
+    const double y = a.ny > 1 ? a.x_min[1] + (double)j * a.dx[1] : a.q_slice;
+    analytic_field<PT, T>(a.W, a.x_min[0], y, a.x_min[2] + (double)k * a.dx[2], e, b);
     a.S[2 * r] = T(a.s0) * e[1];
     a.S[2 * r + 1] = T(a.s0) * e[2];
 }

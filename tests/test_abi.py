@@ -140,11 +140,12 @@ def test_proxy_option_reserves_workspace():
 
 
 def test_open_x_option_rows_only():
-    """AP_GRID_OPEN_X is built for 1-D rows and (x, z) grids: 3-D rejects it;
-    rows take it and reserve the per-row boundary source."""
-    g = _grid(dim=3, n=(16, 8, 8))
+    """AP_GRID_OPEN_X needs a grid; gridded runs take it and reserve the
+    per-row boundary source."""
+    g = _grid(dim=0)
+    g.dt = 0.01
     g.options = apt.AP_GRID_OPEN_X
-    with pytest.raises(apt.APTError, match="1-D rows"):
+    with pytest.raises(apt.APTError, match="needs a grid"):
         apt.ap_query_layout(g, [_sp()])
     g2 = _grid()
     g2.options = apt.AP_GRID_OPEN_X

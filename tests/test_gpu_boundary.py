@@ -55,7 +55,7 @@ def _oracle_species(sps, n, dim=1):
     return out
 
 
-def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boundary", dim=1, pol=0):
+def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boundary", dim=1, pol=0, ny=1):
     from paper_2307_04843_amd.sim import Simulation
     dxl = 1.0 / 20.0
     dtl = units.default_dt(dxl, dim)
@@ -68,7 +68,7 @@ def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boun
         st = dict(cell=np.array([n // 2], np.int32), off=np.zeros((3, 1), np.float32),
                   u=np.zeros((3, 1), np.float32), w=np.zeros(1, np.float32))
         sps = [dict(q=-1.0, m=1.0, state=st)]
-    sim = Simulation(dim, n=(n, 1, rows), dx=(dxl, dxl, dz), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=dtl,
+    sim = Simulation(dim, n=(n, ny, rows), dx=(dxl, dxl, dz), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=dtl,
                      precision=precision, species=sps, open_x=True)
     try:
         sim.set_pulse("plane", **{k: v for k, v in pp.items() if k != "type"}, sampling=sampling)
@@ -79,7 +79,7 @@ def _run_launch(precision, with_slab, n=480, rows=2, n_steps=460, sampling="boun
         d, _ = sim.diag()
     finally:
         sim.close()
-    g = pic.Grid(dim, (n, 1, rows), (dxl * L, dxl * L, dz * L), dtl * L, (0.0, 0.0, 0.0), t0=0.0, open_x=True)
+    g = pic.Grid(dim, (n, ny, rows), (dxl * L, dxl * L, dz * L), dtl * L, (0.0, 0.0, 0.0), t0=0.0, open_x=True)
     osp = _oracle_species(sps, n, dim)
     P = pulses.Pulse(dict(pp, dt=dtl))
     for _ in range(n_steps):
@@ -100,11 +100,14 @@ def test_launch_vacuum_parity(precision, tol):
 
 
 @pytest.mark.parametrize("pol", [0, 1])
-def test_launch_xz_grid_parity_fp64(pol):
-    """(x, z) grid with open x ends (dB_x/dz omitted at the boundary nodes), 12
-    rows, the plane pulse launched in either polarisation, vs the oracle."""
-    print("boundary launch, (x, z) grid, pol", pol, flush=True)
-    gf, _, d, g, _ = _run_launch("f64", False, rows=12, dim=2, pol=pol)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_launch_xz_grid_parity_fp64(pol, dim):
+    """(x, z) grid (12 rows) and 3-D grid (6 x 5 rows) with open x ends (the
+    transverse derivatives of B_x omitted at the boundary nodes), the plane
+    pulse launched in either polarisation, vs the oracle."""
+    print("boundary launch, dim", dim, "pol", pol, flush=True)
+    gf, _, d, g, _ = _run_launch("f64", False, rows=12 if dim == 2 else 5, dim=dim, pol=pol,
+                                 ny=1 if dim == 2 else 6, n=480 if dim == 2 else 240, n_steps=460 if dim == 2 else 300)
     fmax = max(np.abs(c).max() for c in g.E + g.B)
     assert fmax > 0.2
     for k in range(3):

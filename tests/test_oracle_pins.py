@@ -1244,22 +1244,25 @@ def test_moving_window_weightless_run_equals_fixed_window():
 
 
 def test_open_boundary_xz_grid_equals_rows():
-    """On an (x, z) grid the open x ends launch a plane pulse exactly as the
-    1-D rows do (the fields do not vary along z, so the omitted dB_x/dz is
-    zero): both polarisations, bit for bit."""
+    """On (x, z) and 3-D grids the open x ends launch a plane pulse exactly as
+    the 1-D rows do (the fields do not vary across x, so the omitted
+    transverse derivatives of B_x are zero): both polarisations, bit for bit."""
     for pol in (0, 1):
-        out = []
-        for dim in (1, 2):
+        out = {}
+        for dim in (1, 2, 3):
             dxl = 1.0 / 20.0
-            dtl = 0.95 / math.sqrt(2) * dxl
-            g = pic.Grid(dim, (200, 1, 4), (dxl * L, dxl * L, 0.5 * L), dtl * L, (0.0, 0.0, 0.0), open_x=True)
+            dtl = 0.95 / math.sqrt(3) * dxl
+            g = pic.Grid(dim, (200, 3, 4), (dxl * L, dxl * L, (0.5 if dim == 1 else dxl) * L), dtl * L,
+                         (0.0, 0.0, 0.0), open_x=True)
             P = pulses.Pulse(dict(type="plane", a0=1.0, tau=6.0, x_ref=0.0, t_ref=3.0, pol=pol,
                                   dispersion=units.DISP_PAPER2, dx_prop=dxl, dt=dtl, envelope="sgauss",
                                   sg_order=4, fwhm=2.0))
             for _ in range(150):
                 pic.yee_step(g, pic.boundary_source(g, P, g.t + 0.5 * g.dt))
                 g.t += g.dt
-            out.append([f.copy() for f in g.E + g.B])
-        assert max(np.abs(f).max() for f in out[0]) > 0.5
-        for a, b in zip(out[0], out[1]):
+            out[dim] = [f.copy() for f in g.E + g.B]
+        assert max(np.abs(f).max() for f in out[1]) > 0.5
+        for a, b, c in zip(out[1], out[2], out[3]):
             assert np.array_equal(a, b)
+            for j in range(3):
+                assert np.array_equal(a[:, 0, :], c[:, j, :])
