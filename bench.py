@@ -348,7 +348,8 @@ def small_leg():
     return out
 
 
-def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_grid=False, window_shifts=0):
+def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_grid=False, window_shifts=0,
+            current=False):
     import torch
     from paper_2307_04843_amd import apt, inputs
     from paper_2307_04843_amd.sim import Simulation
@@ -357,7 +358,11 @@ def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_gri
                      precision=precision, species=species, sort_every=sort_every, pulse_on_grid=on_grid,
                      moving_window=window_shifts > 0)
     try:
-        sim.set_pulse("lg", **workload_pulse(dt), sampling="grid" if on_grid else "particles")
+        pp = workload_pulse(dt)
+        if current:
+            # Sec. IV: the pulse carries the analytic current of a 0.05 n_c plasma (J1 on the grid)
+            pp.update(dispersion=3, wp2=0.05)
+        sim.set_pulse("lg", **pp, sampling="grid" if on_grid else "particles")
         n_part = sum(int(s["state"]["u"].shape[1]) for s in species)
         sim.step(warmup)
         torch.cuda.synchronize()
@@ -663,6 +668,16 @@ def pic_leg(args):
                     "fp32_first_steps_pushes_per_s" % args.fp64_steps,
             "push_ms_per_launch": tg.ms_push / max(1, tg.n_push),
             "sample_and_round_ms_per_step": tg.ms_other / max(1, args.fp64_steps)}
+        log("analytic current: %d steps" % args.fp64_steps)
+        rc = run_gpu(species, "f32", args.fp64_steps, 0, on_grid=True, current=True)
+        tc = rc["timing"]
+        out["analytic_current"] = {
+            "pushes_per_s": n_part * args.fp64_steps / rc["wall"],
+            "note": "the same %d steps with the pulse's analytic current J1 (Sec. IV, AP_DISP_PLASMA, "
+                    "wp2 = 0.05, grid-sampled E1, corrected B1): the J1 kernel and the corrected "
+                    "sampling run per step; compare grid_sampled" % args.fp64_steps,
+            "push_ms_per_launch": tc.ms_push / max(1, tc.n_push),
+            "sample_current_and_round_ms_per_step": tc.ms_other / max(1, args.fp64_steps)}
     del species
     return out
 
