@@ -64,7 +64,11 @@ def _positions(st):
     return pos
 
 
-def _check_one_step(sim, species, ids, P, dt):
+def _check_one_step(sim, species, ids, P, dt, pulse_on_grid=False):
+    """Advance one step; return the worst relative momentum and position
+    differences of the sampled particles from the oracle's push of each from
+    the GPU's state and fields at the start of the step (E1, B1 sampled on
+    the grid once for the step with ``pulse_on_grid``)."""
     E, B, _ = sim.field_views()
     fields = [t.double().cpu().numpy() for t in E + B]
     t_n, _ = sim.time()
@@ -75,12 +79,24 @@ def _check_one_step(sim, species, ids, P, dt):
     for k in range(3):
         g.E[k][...] = fields[k]
         g.B[k][...] = fields[3 + k]
+    sampled = pic.sample_pulse(g, P) if pulse_on_grid else None
     worst_u, worst_x = 0.0, 0.0
     for sp_desc, a, b in zip(species, pre, post):
         assert np.array_equal(a["id"], b["id"])
         sp = pic.Species(sp_desc["q"], sp_desc["m"], _positions(a), a["u"].astype(float), a["w"].astype(float))
         fs = cases.force_scale(g, [sp], P)[0]
-        u_half = pic.push_species(g, sp, P)
+        if sampled is None:
+            u_half = pic.push_species(g, sp, P)
+        else:
+            # the oracle's grid-sampled push (E1 + E2, B1 + B2 gathered), with the
+            # sampled pulse computed once instead of once per species
+            E2, B2 = g.E, g.B
+            g.E = [f + s for f, s in zip(E2, sampled[0])]
+            g.B = [f + s for f, s in zip(B2, sampled[1])]
+            try:
+                u_half = pic.push_species(g, sp, None)
+            finally:
+                g.E, g.B = E2, B2
         x_new = pic.move(g, sp.pos, u_half)
         scale = np.maximum(np.maximum(np.linalg.norm(u_half, axis=0), np.linalg.norm(sp.u, axis=0)), fs)
         du = np.linalg.norm(b["u"].astype(float) - u_half, axis=0) / scale
@@ -226,3 +242,48 @@ def _select_gridless(sim, ids):
             "icell": np.stack([a["icell"][c][k].cpu().numpy() for c in range(3)]),
             "off": np.stack([a["off"][c][k].cpu().numpy() for c in range(3)]),
             "u": np.stack([a["u"][c][k].cpu().numpy() for c in range(3)])}
+
+
+@pytest.mark.timeout(900)
+def test_full_size_analytic_current_sampled_pushes_and_j1():
+    """The same run with the analytic current of a 0.05 n_c plasma (Sec. IV:
+    plasma dispersion constants, grid-sampled E1 and corrected B1, E2, B2
+    driven by J - J1), as the benchmark's analytic-current leg runs it.
+    After 99 steps, step 100's pushes of the sampled particles are recomputed
+    one by one by the oracle's grid-sampled push.  Then every weight is set
+    to zero and one more step is taken: the particles deposit nothing, so J
+    must equal -J1(t^{n+1/2}) at every node of the 4096 x 1024 grid."""
+    species = bench.workload_inputs()
+    n_part = [int(s["state"]["u"].shape[1]) for s in species]
+    dt = 0.95 / math.sqrt(2) * bench.LAMBDA_DX
+    pp = bench.workload_pulse(dt)
+    pp.update(dispersion=units.DISP_PLASMA, wp2=0.05)
+    P = pulses.Pulse(dict(type="lg", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    ids = [_sample_ids(n, seed=40 + i) for i, n in enumerate(n_part)]
+    sim = Simulation(2, n=bench.N_CELLS, dx=(bench.LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
+                     precision="f32", species=species, pulse_on_grid=True)
+    del species[0]["state"], species[1]["state"]
+    try:
+        sim.set_pulse("lg", **pp, sampling="grid")
+        sim.step(99)
+        print("analytic current: step 100 sampled pushes", flush=True)
+        worst_u, worst_x = _check_one_step(sim, species, ids, P, dt, pulse_on_grid=True)
+        for a in sim.arrays:
+            a["w"].zero_()
+        t_n, _ = sim.time()
+        print("analytic current: zero-weight step at t = %.4f" % t_n, flush=True)
+        sim.step(1)
+        _, _, J = sim.field_views()
+        gj = [t.double().cpu().numpy() for t in J]
+        d, _ = sim.diag()
+    finally:
+        sim.close()
+    assert worst_u <= 1e-6, worst_u
+    assert worst_x <= 1e-6, worst_x
+    assert d.n_nonfinite == 0 and d.n_fast == 0
+    g = pic.Grid(2, bench.N_CELLS, (bench.LAMBDA_DX * L,) * 3, dt * L, (0.0, 0.0, -25.6 * L), t0=t_n * L)
+    J1 = pic.sample_current(g, P, g.t + 0.5 * g.dt)
+    jmax = max(np.abs(c).max() for c in J1)
+    assert jmax > 0
+    for k in range(3):
+        assert np.abs(gj[k] + J1[k]).max() <= 1e-6 * jmax, k
