@@ -287,3 +287,93 @@ def test_full_size_analytic_current_sampled_pushes_and_j1():
     assert jmax > 0
     for k in range(3):
         assert np.abs(gj[k] + J1[k]).max() <= 1e-6 * jmax, k
+
+
+def _select3(sim, i, ids):
+    """Host copy (cell, off, u) of the particles with the given ids, ordered by id (3-D)."""
+    a = sim.arrays[i]
+    idt = torch.as_tensor(ids, device=sim.device, dtype=a["id"].dtype)
+    k = torch.isin(a["id"], idt).nonzero().squeeze(1)
+    k = k[torch.argsort(a["id"][k])]
+    return {"id": a["id"][k].cpu().numpy(), "cell": a["cell"][k].cpu().numpy(),
+            "off": np.stack([a["off"][c][k].cpu().numpy() for c in range(3)]),
+            "u": np.stack([a["u"][c][k].cpu().numpy() for c in range(3)]),
+            "w": a["w"][k].cpu().numpy()}
+
+
+def _positions3(st):
+    nx, ny, _ = bench.N3
+    cell = st["cell"].astype(np.int64)
+    pos = np.zeros((3, cell.size))
+    pos[0] = (cell % nx) + st["off"][0].astype(float)
+    pos[1] = ((cell // nx) % ny) + st["off"][1].astype(float)
+    pos[2] = (cell // (nx * ny)) + st["off"][2].astype(float)
+    return pos
+
+
+@pytest.mark.timeout(900)
+def test_full_size_3d_flying_focus_sampled_pushes_and_continuity():
+    """The 3-D flying-focus run of the benchmark at full size (512 x 256 x 256
+    cells at lambda/16, 8 electrons per cell = 268M, 0.001 n_c, beta_f = -1,
+    a0 = 2, w0 = 4, 5% chirp) from step 1800, in the benchmark's launch
+    configuration.  After 5 steps, two single steps are checked: the oracle
+    recomputes the push and move of 4000 sampled electrons (half within
+    4 lambda of the axis, half uniform) one by one from the GPU's state and
+    fields at the start of each step, and the continuity residual of the
+    whole grid is checked."""
+    species = bench.workload3d_inputs()
+    n = int(species[0]["state"]["u"].shape[1])
+    nx, ny, nz = bench.N3
+    dt = 0.95 / math.sqrt(3) * bench.DX3
+    pp = bench.workload3d_pulse(dt)
+    P = pulses.Pulse(dict(type="ff", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    rng = np.random.default_rng(60)
+    cx = rng.integers(0, nx, N_SAMPLE)
+    cy = rng.integers(ny // 4, 3 * ny // 4, N_SAMPLE)
+    cz = rng.integers(nz // 4, 3 * nz // 4, N_SAMPLE)
+    axis = ((cz * ny + cy) * nx + cx) * bench.PPC3 + rng.integers(0, bench.PPC3, N_SAMPLE)
+    ids = np.unique(np.concatenate([axis, rng.choice(n, N_SAMPLE, replace=False)]).astype(np.int64))
+    x_min = (0.0, -8.0, -8.0)
+    sim = Simulation(3, n=bench.N3, dx=(bench.DX3,) * 3, x_min=x_min, t0=bench.T0_STEP3 * dt, dt=dt,
+                     precision="f32", species=species)
+    q, m = species[0]["q"], species[0]["m"]
+    del species[0]["state"]
+    results, diags = [], []
+    try:
+        sim.set_pulse("ff", **pp)
+        sim.step(5)
+        for s in range(2):
+            E, B, _ = sim.field_views()
+            fields = [t.double().cpu().numpy() for t in E + B]
+            t_n, steps = sim.time()
+            print("3-D full size: checking step %d" % steps, flush=True)
+            a = _select3(sim, 0, ids)
+            sim.step(1, flags=apt.AP_STEP_CONTINUITY)
+            b = _select3(sim, 0, ids)
+            diags.append(sim.diag()[0])
+            assert np.array_equal(a["id"], b["id"])
+            g = pic.Grid(3, bench.N3, (bench.DX3 * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=t_n * L)
+            for k in range(3):
+                g.E[k][...] = fields[k]
+                g.B[k][...] = fields[3 + k]
+            del fields
+            sp = pic.Species(q, m, _positions3(a), a["u"].astype(float), a["w"].astype(float))
+            fs = cases.force_scale(g, [sp], P)[0]
+            u_half = pic.push_species(g, sp, P)
+            x_new = pic.move(g, sp.pos, u_half)
+            del g
+            scale = np.maximum(np.maximum(np.linalg.norm(u_half, axis=0), np.linalg.norm(sp.u, axis=0)), fs)
+            du = float((np.linalg.norm(b["u"].astype(float) - u_half, axis=0) / scale).max())
+            pos = _positions3(b)
+            dxm = max(float(np.abs(cases.periodic_diff(pos[ax], x_new[ax], nn)).max())
+                      for ax, nn in ((0, nx), (1, ny), (2, nz)))
+            results.append((du, dxm))
+    finally:
+        sim.close()
+    for du, dxm in results:
+        assert du <= 1e-6, results
+        assert dxm <= 1e-6, results
+    dxi = bench.DX3 * L
+    for d in diags:
+        assert d.j_max > 0 and d.n_nonfinite == 0
+        assert d.continuity_max <= 1e-6 * d.j_max / dxi, (d.continuity_max, d.j_max / dxi)
