@@ -232,6 +232,18 @@ def large3d_inputs(seed=5, slab=32):
     return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
 
 
+T0_STEP5 = 450
+
+
+def large3d_pulse(dt):
+    """Gaussian (D_f = 3, a0 = 3, w0 = 10, tau = 30) focused at the centre of the 1024 x 512 x 512 box."""
+    c2 = (dt / DX3) ** 2
+    vg = 1.0 - (1.0 - c2) * (2 * math.pi * DX3) ** 2 / 8.0
+    xc = N5[0] * DX3 / 2
+    return dict(a0=3.0, tau=30.0, x_ref=xc, t_ref=15.0 + xc / vg, x_f=xc, w0=10.0, y_c=0.0, z_c=0.0, d_f=3, pol=0,
+                dispersion=0, dx_prop=DX3, dt_prop=dt)
+
+
 def large3d_leg(args):
     import torch
     from paper_2307_04843_amd import apt
@@ -239,12 +251,8 @@ def large3d_leg(args):
     species = large3d_inputs()
     n = sum(int(s["state"]["u"].shape[1]) for s in species)
     dt = 0.95 / math.sqrt(3) * DX3
-    c2 = (dt / DX3) ** 2
-    vg = 1.0 - (1.0 - c2) * (2 * math.pi * DX3) ** 2 / 8.0
-    xc = N5[0] * DX3 / 2
-    pp = dict(a0=3.0, tau=30.0, x_ref=xc, t_ref=15.0 + xc / vg, x_f=xc, w0=10.0, y_c=0.0, z_c=0.0, d_f=3, pol=0,
-              dispersion=0, dx_prop=DX3, dt_prop=dt)
-    steps, t_step0 = 100, 450
+    pp = large3d_pulse(dt)
+    steps, t_step0 = 100, T0_STEP5
     out = {"workload": "3-D PIC 1024x512x512 cells lambda/16, 2 e + 2 p per cell (1.07e9), n = 0.01 "
                        "exp(-r^2/(20 lambda)^2), Gaussian D_f=3 a0=3 w0=10 tau=30, steps %d..%d of the "
                        "1000-step run" % (t_step0, t_step0 + steps), "particles": n, "steps": steps, "warmup": 3}

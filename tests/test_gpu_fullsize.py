@@ -301,14 +301,73 @@ def _select3(sim, i, ids):
             "w": a["w"][k].cpu().numpy()}
 
 
-def _positions3(st):
-    nx, ny, _ = bench.N3
+def _positions3(st, n):
+    nx, ny, _ = n
     cell = st["cell"].astype(np.int64)
     pos = np.zeros((3, cell.size))
     pos[0] = (cell % nx) + st["off"][0].astype(float)
     pos[1] = ((cell // nx) % ny) + st["off"][1].astype(float)
     pos[2] = (cell // (nx * ny)) + st["off"][2].astype(float)
     return pos
+
+
+def _sample_ids3(n, ppc, n_part, lo, hi, seed):
+    """Ids with their initial cell in the box [lo, hi) of cell indices, and as
+    many uniform ones; ids follow the generators' cell order (id // ppc = the
+    linear initial cell)."""
+    rng = np.random.default_rng(seed)
+    c = [rng.integers(lo[a], hi[a], N_SAMPLE) for a in range(3)]
+    box = ((c[2] * n[1] + c[1]) * n[0] + c[0]) * ppc + rng.integers(0, ppc, N_SAMPLE)
+    return np.unique(np.concatenate([box, rng.choice(n_part, N_SAMPLE, replace=False)]).astype(np.int64))
+
+
+def _check3(sim, species, ids, P, n, dx, x_min, dt, steps=2):
+    """Take `steps` single steps; for each, the oracle recomputes the push
+    and move of the sampled particles of every species one by one from the
+    GPU's state and fields at the start of the step.  Returns the worst
+    relative momentum and position differences per step, and the
+    diagnostics after each step (continuity tracked)."""
+    g = None
+    results, diags = [], []
+    for s in range(steps):
+        t_n, step = sim.time()
+        print("3-D full size %s: checking step %d" % (tuple(n), step), flush=True)
+        if g is None:
+            g = pic.Grid(3, n, (dx * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=t_n * L)
+        g.t = t_n * L
+        E, B, _ = sim.field_views()
+        for k in range(3):
+            g.E[k][...] = E[k].double().cpu().numpy()
+            g.B[k][...] = B[k].double().cpu().numpy()
+        pre = [_select3(sim, i, ids[i]) for i in range(len(species))]
+        sim.step(1, flags=apt.AP_STEP_CONTINUITY)
+        post = [_select3(sim, i, ids[i]) for i in range(len(species))]
+        diags.append(sim.diag()[0])
+        du, dxm = 0.0, 0.0
+        for sp_desc, a, b in zip(species, pre, post):
+            assert np.array_equal(a["id"], b["id"])
+            sp = pic.Species(sp_desc["q"], sp_desc["m"], _positions3(a, n), a["u"].astype(float),
+                             a["w"].astype(float))
+            fs = cases.force_scale(g, [sp], P)[0]
+            u_half = pic.push_species(g, sp, P)
+            x_new = pic.move(g, sp.pos, u_half)
+            scale = np.maximum(np.maximum(np.linalg.norm(u_half, axis=0), np.linalg.norm(sp.u, axis=0)), fs)
+            du = max(du, float((np.linalg.norm(b["u"].astype(float) - u_half, axis=0) / scale).max()))
+            pos = _positions3(b, n)
+            dxm = max(dxm, max(float(np.abs(cases.periodic_diff(pos[ax], x_new[ax], n[ax])).max())
+                               for ax in range(3)))
+        results.append((du, dxm))
+    return results, diags
+
+
+def _assert3(results, diags, dx):
+    for du, dxm in results:
+        assert du <= 1e-6, results
+        assert dxm <= 1e-6, results
+    dxi = dx * L
+    for d in diags:
+        assert d.j_max > 0 and d.n_nonfinite == 0
+        assert d.continuity_max <= 1e-6 * d.j_max / dxi, (d.continuity_max, d.j_max / dxi)
 
 
 @pytest.mark.timeout(900)
@@ -322,58 +381,48 @@ def test_full_size_3d_flying_focus_sampled_pushes_and_continuity():
     fields at the start of each step, and the continuity residual of the
     whole grid is checked."""
     species = bench.workload3d_inputs()
-    n = int(species[0]["state"]["u"].shape[1])
-    nx, ny, nz = bench.N3
+    n_part = int(species[0]["state"]["u"].shape[1])
+    n = bench.N3
     dt = 0.95 / math.sqrt(3) * bench.DX3
     pp = bench.workload3d_pulse(dt)
     P = pulses.Pulse(dict(type="ff", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
-    rng = np.random.default_rng(60)
-    cx = rng.integers(0, nx, N_SAMPLE)
-    cy = rng.integers(ny // 4, 3 * ny // 4, N_SAMPLE)
-    cz = rng.integers(nz // 4, 3 * nz // 4, N_SAMPLE)
-    axis = ((cz * ny + cy) * nx + cx) * bench.PPC3 + rng.integers(0, bench.PPC3, N_SAMPLE)
-    ids = np.unique(np.concatenate([axis, rng.choice(n, N_SAMPLE, replace=False)]).astype(np.int64))
+    ids = [_sample_ids3(n, bench.PPC3, n_part, (0, n[1] // 4, n[2] // 4), (n[0], 3 * n[1] // 4, 3 * n[2] // 4), 60)]
     x_min = (0.0, -8.0, -8.0)
-    sim = Simulation(3, n=bench.N3, dx=(bench.DX3,) * 3, x_min=x_min, t0=bench.T0_STEP3 * dt, dt=dt,
+    sim = Simulation(3, n=n, dx=(bench.DX3,) * 3, x_min=x_min, t0=bench.T0_STEP3 * dt, dt=dt,
                      precision="f32", species=species)
-    q, m = species[0]["q"], species[0]["m"]
     del species[0]["state"]
-    results, diags = [], []
     try:
         sim.set_pulse("ff", **pp)
         sim.step(5)
-        for s in range(2):
-            E, B, _ = sim.field_views()
-            fields = [t.double().cpu().numpy() for t in E + B]
-            t_n, steps = sim.time()
-            print("3-D full size: checking step %d" % steps, flush=True)
-            a = _select3(sim, 0, ids)
-            sim.step(1, flags=apt.AP_STEP_CONTINUITY)
-            b = _select3(sim, 0, ids)
-            diags.append(sim.diag()[0])
-            assert np.array_equal(a["id"], b["id"])
-            g = pic.Grid(3, bench.N3, (bench.DX3 * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=t_n * L)
-            for k in range(3):
-                g.E[k][...] = fields[k]
-                g.B[k][...] = fields[3 + k]
-            del fields
-            sp = pic.Species(q, m, _positions3(a), a["u"].astype(float), a["w"].astype(float))
-            fs = cases.force_scale(g, [sp], P)[0]
-            u_half = pic.push_species(g, sp, P)
-            x_new = pic.move(g, sp.pos, u_half)
-            del g
-            scale = np.maximum(np.maximum(np.linalg.norm(u_half, axis=0), np.linalg.norm(sp.u, axis=0)), fs)
-            du = float((np.linalg.norm(b["u"].astype(float) - u_half, axis=0) / scale).max())
-            pos = _positions3(b)
-            dxm = max(float(np.abs(cases.periodic_diff(pos[ax], x_new[ax], nn)).max())
-                      for ax, nn in ((0, nx), (1, ny), (2, nz)))
-            results.append((du, dxm))
+        results, diags = _check3(sim, species, ids, P, n, bench.DX3, x_min, dt)
     finally:
         sim.close()
-    for du, dxm in results:
-        assert du <= 1e-6, results
-        assert dxm <= 1e-6, results
-    dxi = bench.DX3 * L
-    for d in diags:
-        assert d.j_max > 0 and d.n_nonfinite == 0
-        assert d.continuity_max <= 1e-6 * d.j_max / dxi, (d.continuity_max, d.j_max / dxi)
+    _assert3(results, diags, bench.DX3)
+
+
+@pytest.mark.timeout(1100)
+def test_full_size_large_3d_sampled_pushes_and_continuity():
+    """The largest 3-D run at full size (1024 x 512 x 512 cells at lambda/16,
+    2 electrons + 2 protons per cell = 1.07e9 particles in a Gaussian density
+    channel, Gaussian pulse D_f = 3, a0 = 3, w0 = 10) from step 450, as the
+    benchmark's large 3-D leg.  After 3 steps, two single steps are checked:
+    per species, 2000 sampled particles (half in the pulse, x < 15 lambda and
+    within 10 lambda of the axis) are recomputed by the oracle one by one,
+    and the continuity residual of the whole grid is checked."""
+    species = bench.large3d_inputs()
+    n = bench.N5
+    n_part = [int(s["state"]["u"].shape[1]) for s in species]
+    dt = 0.95 / math.sqrt(3) * bench.DX3
+    pp = bench.large3d_pulse(dt)
+    P = pulses.Pulse(dict(type="gauss", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    ids = [_sample_ids3(n, 2, n_part[i], (0, 96, 96), (240, 416, 416), 70 + i) for i in range(2)]
+    sim = Simulation(3, n=n, dx=(bench.DX3,) * 3, x_min=bench.X5_MIN, t0=bench.T0_STEP5 * dt, dt=dt,
+                     precision="f32", species=species)
+    del species[0]["state"], species[1]["state"]
+    try:
+        sim.set_pulse("gauss", **pp)
+        sim.step(3)
+        results, diags = _check3(sim, species, ids, P, n, bench.DX3, bench.X5_MIN, dt)
+    finally:
+        sim.close()
+    _assert3(results, diags, bench.DX3)
