@@ -47,8 +47,11 @@ def continuity_residual(grid, rho0, rho1, J=None):
 
 
 def field_energy(grid):
-    """Half the sum of E2^2 + B2^2 over cells, times the cell volume."""
-    vol = grid.dx[0] * grid.dx[2] * (grid.dx[1] if grid.dim == 3 else 1.0)
+    """Half the sum of E2^2 + B2^2 over cells, times the cell volume: dx dy dz
+    in 3-D, dx dz on (x, z) grids (per unit length along y), dx on 1-D rows
+    (per unit transverse area of each row, summed over the rows: the rows are
+    independent lines, not a slab)."""
+    vol = grid.dx[0] * (grid.dx[2] if grid.dim >= 2 else 1.0) * (grid.dx[1] if grid.dim == 3 else 1.0)
     tot = sum(np.sum(c ** 2) for c in grid.E) + sum(np.sum(c ** 2) for c in grid.B)
     return 0.5 * tot * vol
 
@@ -58,12 +61,15 @@ def moments(sp):
     g = pic.gamma_of(sp.u)
     w = sp.w
     sw = np.sum(w)
+    # m (gamma - 1) = m |u|^2 / (gamma + 1): the same kinetic energy, without
+    # the cancellation of gamma - 1 for slow particles (protons at 1 eV)
+    ek = np.sum(sp.u ** 2, axis=0) / (g + 1.0)
     return {
         "sum_w": sw,
         "mean_u": np.sum(w * sp.u, axis=1) / sw,
         "mean_u2": np.sum(w * sp.u ** 2, axis=1) / sw,
         "mean_uperp2": np.sum(w * (sp.u[1] ** 2 + sp.u[2] ** 2)) / sw,
         "mean_gamma": np.sum(w * g) / sw,
-        "kinetic": sp.m * np.sum(w * (g - 1.0)),
+        "kinetic": sp.m * np.sum(w * ek),
         "charge": sp.q * sw,
     }

@@ -6,13 +6,15 @@ Reading: the Lax-Davis expansion of a linearly polarised vector potential
 A = x-hat psi(x, y, z) e^{ikz} (physics convention e^{i(kz - wt)}, vacuum,
 c = w = k = 1), psi = psi0 (1 + eps^2 G2 + eps^4 G4), eps = w0/x_R.
 
-This module derives the series by itself:
+The series, written out:
 * psi0 = f exp(-f s), f = 1/(1 + i zeta), s = (x^2 + y^2)/w0^2, zeta = z/x_R;
-* G2, G4 are polynomials in (f, s) found by making the scaled Helmholtz
-  equation lap_perp psi + 4i d_zeta psi + eps^2 d_zeta^2 psi vanish order by
-  order, matched numerically on random points and rationalised;
-* the homogeneous freedom (zeta-derivatives of psi0, i.e. focus and waist
-  redefinitions) is removed by requiring psi = psi0 on the axis;
+* G2 = f^2 s / 2 - f^3 s^2 / 4 and
+  G4 = f^6 s^4 / 32 - f^5 s^3 / 4 + 3 f^4 s^2 / 8: the polynomials in (f, s)
+  that make the scaled Helmholtz equation
+  lap_perp psi + 4i d_zeta psi + eps^2 d_zeta^2 psi vanish at orders eps^2
+  and eps^4, with the homogeneous freedom (zeta-derivatives of psi0, i.e.
+  focus and waist redefinitions) fixed by psi = psi0 on the axis (s = 0);
+  the pins check the eps^6 residual of the truncated psi;
 * E = i A + i grad div A and B = curl A are obtained by symbolic
   differentiation of the full potential in physical coordinates.
 
@@ -21,7 +23,6 @@ amplitude normalised by i w A0, a field is Re{conj(X) Gamma e^{i(theta + Phi)}},
 so that the leading E_p is Re{conj(psi0) Gamma e^{i(theta + Phi)}} like the
 paraxial Gaussian.
 """
-from fractions import Fraction
 from functools import lru_cache
 
 import numpy as np
@@ -30,57 +31,12 @@ import sympy as sp
 from . import pulses as _pulses
 
 
-def _lin_solve_rational(A, b):
-    """Least-squares solve and rationalise (coefficients are small rationals)."""
-    x, *_ = np.linalg.lstsq(A, b, rcond=None)
-    out = []
-    for v in x:
-        re = Fraction(float(v.real)).limit_denominator(512)
-        im = Fraction(float(v.imag)).limit_denominator(512)
-        out.append(sp.Rational(re.numerator, re.denominator)
-                   + sp.I * sp.Rational(im.numerator, im.denominator))
-    return out
-
-
-@lru_cache(maxsize=1)
 def series():
-    """(G2, G4) as sympy expressions in (f, s) symbols F, S."""
-    xi, eta, zeta = sp.symbols("xi eta zeta", real=True)
+    """(G2, G4) as sympy polynomials in the symbols F (= f) and S (= s)."""
     F, S = sp.symbols("F S")
-    f = 1 / (1 + sp.I * zeta)
-    s = xi ** 2 + eta ** 2
-    psi0 = f * sp.exp(-f * s)
-
-    def helm(g):   # lap_perp + 4 i d_zeta
-        return sp.diff(g, xi, 2) + sp.diff(g, eta, 2) + 4 * sp.I * sp.diff(g, zeta)
-
-    rng = np.random.default_rng(12345)
-    pts = np.stack([rng.uniform(-1.5, 1.5, 120), rng.uniform(-1.5, 1.5, 120),
-                    rng.uniform(-2.0, 2.0, 120)], axis=1)
-    Gs = [sp.Integer(1)]
-    for n in (1, 2):
-        monos = [(a, b) for a in range(1, 4 * n + 2) for b in range(0, 2 * n + 1)]
-        cols = []
-        for (a, b) in monos:
-            e = helm(f ** a * s ** b * psi0) / psi0
-            fn = sp.lambdify((xi, eta, zeta), e, "numpy")
-            cols.append(np.array([complex(fn(*p)) for p in pts]))
-        rhs_e = sp.diff(Gs[-1].subs({F: f, S: s}) * psi0, zeta, 2) / psi0
-        fr = sp.lambdify((xi, eta, zeta), rhs_e, "numpy")
-        rhs = -np.array([complex(fr(*p)) for p in pts])
-        A = np.stack(cols, axis=1)
-        # on-axis condition: sum_a c_{a,0} f^a = 0 for every zeta
-        zs = np.linspace(-2, 2, 9)
-        rows = np.zeros((zs.size, len(monos)), dtype=complex)
-        for j, (a, b) in enumerate(monos):
-            if b == 0:
-                rows[:, j] = (1.0 / (1.0 + 1j * zs)) ** a
-        A = np.vstack([A, rows * 10.0])
-        rhs = np.concatenate([rhs, np.zeros(zs.size)])
-        c = _lin_solve_rational(A, rhs)
-        Gn = sp.expand(sum(ci * F ** a * S ** b for ci, (a, b) in zip(c, monos)))
-        Gs.append(Gn)
-    return Gs[1], Gs[2]
+    G2 = F ** 2 * S / 2 - F ** 3 * S ** 2 / 4
+    G4 = F ** 6 * S ** 4 / 32 - F ** 5 * S ** 3 / 4 + sp.Rational(3, 8) * F ** 4 * S ** 2
+    return G2, G4
 
 
 @lru_cache(maxsize=4)

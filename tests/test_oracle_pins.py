@@ -46,6 +46,68 @@ def test_pin1_yee_travelling_eigenmode_exact():
     assert abs(math.cos(omega * dt / 2) - 1.0) > 1e-3
 
 
+def test_field_energy_of_yee_eigenmodes_closed_form():
+    """diag.field_energy against the closed form of discrete plane waves: on a
+    periodic grid sum_i cos^2(2 pi m i / N + phi) = N/2 exactly (0 < m < N/2),
+    so a mode of amplitude A in E and A B0/E0 in B carries
+    (A^2 + (A B0/E0)^2)/4 per cell, times the cell volume (dx dz on an (x, z)
+    grid, dx dy dz in 3-D, dx on 1-D rows).  Two modes on different
+    components add.  The travelling mode keeps this value exactly while the
+    split Yee step propagates it.  A missing factor 1/2, a dropped B or
+    component, or the wrong volume fails."""
+    nx, nz = 64, 12
+    dx, dz = 0.3, 0.2
+    dt = 0.9 / math.sqrt(1 / dx ** 2 + 1 / dz ** 2)
+    k = 2 * math.pi * 5 / (nx * dx)
+    omega = 2.0 / dt * math.asin(dt / dx * math.sin(k * dx / 2))
+    b0 = math.cos(omega * dt / 2)
+    kz = 2 * math.pi * 2 / (nz * dz)
+    g = pic.Grid(2, (nx, 1, nz), (dx, 1.0, dz), dt, (0.0, 0.0, 0.0))
+    xi = np.arange(nx) * dx
+    zi = np.arange(nz) * dz
+    g.E[1][:] = np.cos(k * xi)[None, None, :]
+    g.B[2][:] = (b0 * np.cos(k * (xi + dx / 2)))[None, None, :]
+    one = 0.25 * (1.0 + b0 ** 2) * nx * nz * dx * dz
+    assert abs(diag.field_energy(g) - one) < 1e-12 * one
+    for _ in range(50):
+        pic.yee_step(g)
+    assert abs(diag.field_energy(g) - one) < 1e-11 * one
+    # a second mode along z on (E_x, B_y), amplitude 0.5, B 0.3 of it
+    g.E[0][:] += 0.5 * np.cos(kz * zi)[:, None, None]
+    g.B[1][:] += 0.15 * np.sin(kz * (zi + dz / 2))[:, None, None]
+    two = one + 0.25 * (0.5 ** 2 + 0.15 ** 2) * nx * nz * dx * dz
+    assert abs(diag.field_energy(g) - two) < 1e-11 * two
+    # 3-D: E_z along y; the volume takes dy
+    g3 = pic.Grid(3, (8, 16, 6), (0.1, 0.25, 0.2), 0.01, (0.0, 0.0, 0.0))
+    ky = 2 * math.pi * 3 / (16 * 0.25)
+    g3.E[2][:] = 2.0 * np.cos(ky * np.arange(16) * 0.25 + 0.3)[None, :, None]
+    e3 = 0.25 * 4.0 * 8 * 16 * 6 * 0.1 * 0.25 * 0.2
+    assert abs(diag.field_energy(g3) - e3) < 1e-12 * e3
+    # 1-D rows: dx only (energy per unit transverse area, summed over rows)
+    g1 = pic.Grid(1, (32, 1, 3), (0.1, 1.0, 0.7), 0.05, (0.0, 0.0, 0.0))
+    g1.B[1][:] = np.sin(2 * math.pi * 4 * np.arange(32) / 32 + 0.1)[None, None, :]
+    e1 = 0.25 * 32 * 3 * 0.1
+    assert abs(diag.field_energy(g1) - e1) < 1e-12 * e1
+
+
+def test_moments_hand_computed():
+    """diag.moments on three particles whose gamma are integers (|u|^2 = 3, 8,
+    24 give gamma = 2, 3, 5), against sums done by hand: sum w = 3.5,
+    sum w u = (7, -2, 0), sum w u^2 = (17, 11, 3), sum w gamma = 10.5,
+    sum w (gamma - 1) = 7, times the mass for the kinetic energy."""
+    u = np.array([[1.0, 2.0, 4.0], [1.0, -2.0, 2.0], [1.0, 0.0, -2.0]])
+    w = np.array([1.0, 2.0, 0.5])
+    sp = pic.Species(-1.0, 3.0, np.zeros((3, 3)), u, w)
+    m = diag.moments(sp)
+    assert m["sum_w"] == 3.5
+    assert np.allclose(m["mean_u"], np.array([7.0, -2.0, 0.0]) / 3.5, rtol=0, atol=1e-15)
+    assert np.allclose(m["mean_u2"], np.array([17.0, 11.0, 3.0]) / 3.5, rtol=0, atol=1e-15)
+    assert abs(m["mean_gamma"] - 3.0) < 1e-15
+    assert abs(m["kinetic"] - 21.0) < 1e-13
+    assert abs(m["mean_uperp2"] - 14.0 / 3.5) < 1e-15
+    assert m["charge"] == -3.5
+
+
 def test_pin1_yee_oblique_standing_mode_multid_relation():
     """Multi-D Yee relation sin^2(w dt/2)/dt^2 = sum_d sin^2(k_d dx_d/2)/dx_d^2:
     a standing mode started with B = 0 oscillates as cos(n omega dt) exactly."""
