@@ -1,47 +1,36 @@
 """Throughput of the analytic-pulse PIC hot path on one MI355X.
 
-Workload (default): 2-D (x, z) PIC, 4096 x 1024 cells at lambda/20, c dt/dx =
-0.95/sqrt(2), 16 electrons + 16 protons (m = 1836) per cell (134M particles),
-density ramping linearly 0 -> 0.05 n_c over 200 lambda, T = 1 eV; analytic
-Laguerre-Gaussian l=1 p=0 pulse, a0 = 5, w0 = 8 lambda, 30 lambda/c sin^2
-envelope, focus at the box centre, front at x = 0 at t = 0; FP32 particles and
-grid with an FP64 laser phase.  The whole 2000-step run is executed: ``--warmup``
-untimed steps, then ``--steps`` timed steps.
+Headline (``value``): 3-D PIC, 1024 x 512 x 512 cells at lambda/16, c dt/dx =
+0.95/sqrt(3), 2 electrons + 2 protons (m = 1836) per cell = 1.07e9 particles
+in a Gaussian density channel n = 0.01 exp(-r^2/(20 lambda)^2) n_c, T = 1 eV;
+analytic paraxial Gaussian pulse (D_f = 3, a0 = 3, w0 = 10 lambda, 30 lambda/c
+sin^2 envelope, focus at the box centre, front at x = 0 at t = 0); FP32
+particles and grid with an FP64 laser phase.  The particles are drawn on the
+GPU.  The timed window is the END of the 1000-step run, where the pulse is
+inside the plasma: the run starts at step 1000 - warmup - steps, takes
+``--warmup`` untimed steps, then ``--steps`` timed ones.  One step = tile
+sort + J clear + fused gather/analytic/Boris/move/Esirkepov kernel + J
+rounding + Yee update.  ``value`` = particle pushes per second over the timed
+steps, inputs resident in HBM.  The same window then runs in FP64
+(``fp32_over_fp64``).  ``roofline`` is the fused kernel's algorithmic HBM
+rate from its HIP-event launch time; ``cpu_baseline`` the FP64 oracle on a
+16^3-cell replica inside the pulse at the window's clock.
 
-One step = tile sort (every 8 steps) + J clear + fused gather/analytic/Boris/
-move/Esirkepov kernel + Yee update.  ``value`` = particle pushes per second
-over the timed steps, inputs resident in HBM.
-
-Second leg (``adjoint``): the gridless head-on collision -- 2^24 electrons,
-gamma = 2000 with 5% spread, transverse sigma = 1 lambda, against the eps^4
-nonparaxial Gaussian (a0 = 20, w0 = 2 lambda, tau = 20 lambda/c, focus at the
-origin), dt = 0.01 lambda/c -- over the ``--adj-steps`` steps around the
-collision (t = 90 ... 110 lambda/c for 2000 steps), forward with checkpoint
-recording plus ap_backward for d<p_perp^2>/d(a0, w0, x_f), in FP32 and FP64.
-Adjoint pushes/s = N x steps / wall time of the backward pass (replay
-included).
-
-Third leg (``three_d``): 3-D PIC, 512 x 256 x 256 cells at lambda/16, c dt/dx
-= 0.95/sqrt(3), 8 electrons per cell (268M) in 0.001 n_c with immobile ions,
-T = 1 eV, flying-focus pulse (beta_f = -1, a0 = 2, w0 = 4 lambda, tau = 150
-lambda/c, 5% chirp), FP32: steps 1800 ... 1900 of the 4000-step run (the box
-inside the pulse, the moving focus crossing it), then the frozen-grid adjoint
-of d<p_perp^2>/d(beta_f, chirp) over a 32-step window (segments of 8).
-
-Fourth leg (``small``): the 128 x 64 Gaussian run (32768 electrons, 200 steps)
-in FP64 and FP32; launch-bound, reported for completeness.
-
-Fifth leg (``rows1d``): the reduced-dimensionality series of Sec. III.B as one
-run of 30 independent 1-D rows (z = 0 ... 2.9 lambda, 0.1 lambda apart), 4096
-cells at lambda/20 each, 64 electrons per cell (7.9M) in 0.01 n_c, Gaussian
-D_f = 3 pulse (a0 = 5, w0 = 2.5 lambda, tau = 10 lambda/c) on the rows' axis
-side, FP32, 500 steps.
-
-Optional leg (``--with-large3d``, off by default: about three minutes of host
-input generation): 3-D PIC, 1024 x 512 x 512 cells at lambda/16, 2 electrons
-+ 2 protons per cell (1.07e9 particles) in n = 0.01 exp(-r^2/(20 lambda)^2)
-n_c, Gaussian D_f = 3 pulse (a0 = 3, w0 = 10 lambda, tau = 30 lambda/c,
-focus at the box centre), FP32, steps 450 ... 550 of the 1000-step run.
+Other legs (``--legs``):
+  pic2d    the 4096 x 1024 LG run (16 e + 16 p per cell, 134M, 0 -> 0.05 n_c
+           ramp, LG l=1 p=0 a0=5 w0=8 tau=30): the last steps of its 2000-step
+           run in FP32 and FP64, with the grid-sampled pulse and with the
+           analytic current, the moving-window shift cost, and a 512 x 1024
+           box that lies inside the LG envelope for the whole window;
+  adjoint  the gridless head-on collision (2^24 electrons, gamma = 2000, eps^4
+           nonparaxial Gaussian a0 = 20, w0 = 2): forward with recording plus
+           ap_backward for d<p_perp^2>/d(a0, w0, x_f), FP32 and FP64;
+  three_d  the 512 x 256 x 256 flying-focus run (268M electrons, beta_f = -1,
+           chirp 5%): steps 1800 ... 1900 of 4000, then the frozen-grid and the
+           fully coupled adjoints over a 32-step window;
+  small    the 128 x 64 Gaussian run (32768 electrons, 200 steps), FP64, FP32;
+  rows1d   30 independent 1-D rows (Sec. III.B), 7.9M electrons, 500 steps;
+  cpu      the oracle baselines.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
 """
@@ -66,14 +55,10 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def workload_inputs(n_cells=N_CELLS, ppc=PPC, x_min=(0.0, 0.0, -25.6), seed=2):
-    from paper_2307_04843_amd import inputs
-    dx = (LAMBDA_DX,) * 3
-    dens = inputs.density_ramp_x(0.05, 0.0, 200.0)
-    e = inputs.plasma(2, n_cells, dx, x_min, ppc, dens, 1.0, 1.0, seed, stream=0)
-    p = inputs.plasma(2, n_cells, dx, x_min, ppc, dens, 1.0, inputs.PROTON_MASS, seed, stream=1,
-                      positions_from=e)
-    return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
+def workload_inputs(n_cells=N_CELLS, x_min=(0.0, 0.0, -25.6), seed=2):
+    """Electrons + protons of the 4096 x 1024 LG run (16 + 16 per cell), drawn
+    on the GPU (``inputs.plasma_device``)."""
+    return pic2d_inputs(n_cells, x_min, seed)
 
 
 def workload_pulse(dt):
@@ -195,48 +180,28 @@ def three_d_leg(args):
 
 N5 = (1024, 512, 512)
 X5_MIN = (0.0, -16.0, -16.0)
+RUN5_STEPS = 1000   # length of the 1024 x 512 x 512 run
 
 
-def large3d_inputs(seed=5, slab=32):
-    """Electrons + protons of the 1024 x 512 x 512 channel, generated slab by
-    slab of `slab` z-planes (each slab its own seeded stream) straight into
-    device tensors."""
-    import numpy as np
+def large3d_inputs(seed=5, precision="f32"):
+    """Electrons + protons of the 1024 x 512 x 512 channel (2 + 2 per cell,
+    1.07e9 particles), drawn on the GPU (``inputs.plasma_device``)."""
     import torch
     from paper_2307_04843_amd import inputs
-    nx, ny, nz = N5
-    ppc = 2
-    n = nx * ny * nz * ppc
     dens = inputs.density_gauss_channel(0.01, 20.0, 0.0, 0.0)
-    dev = torch.device("cuda")
-    e = {"cell": torch.empty(n, dtype=torch.int32, device=dev),
-         "off": torch.empty((3, n), dtype=torch.float32, device=dev),
-         "u": torch.empty((3, n), dtype=torch.float32, device=dev),
-         "w": torch.empty(n, dtype=torch.float32, device=dev)}
-    up = torch.empty((3, n), dtype=torch.float32, device=dev)
-    per = nx * ny * slab * ppc
-    for k0 in range(0, nz, slab):
-        xm = (X5_MIN[0], X5_MIN[1], X5_MIN[2] + k0 * DX3)
-        s_e = inputs.plasma(3, (nx, ny, slab), (DX3,) * 3, xm, ppc, dens, 1.0, 1.0, seed, stream=2 * k0)
-        s_p = inputs.plasma(3, (nx, ny, slab), (DX3,) * 3, xm, ppc, dens, 1.0, inputs.PROTON_MASS, seed,
-                            stream=2 * k0 + 1, positions_from=s_e)
-        a, b = (k0 // slab) * per, (k0 // slab + 1) * per
-        e["cell"][a:b] = torch.from_numpy(s_e["cell"] + np.int32(k0 * nx * ny)).to(dev)
-        e["off"][:, a:b] = torch.from_numpy(s_e["off"]).to(dev)
-        e["u"][:, a:b] = torch.from_numpy(s_e["u"]).to(dev)
-        e["w"][a:b] = torch.from_numpy(s_e["w"]).to(dev)
-        up[:, a:b] = torch.from_numpy(s_p["u"]).to(dev)
-        del s_e, s_p
-        log("large 3-D inputs: %d/%d z-planes" % (k0 + slab, nz))
-    p = {"cell": e["cell"].clone(), "off": e["off"].clone(), "u": up, "w": e["w"].clone()}
+    e = inputs.plasma_device(3, N5, (DX3,) * 3, X5_MIN, 2, dens, 1.0, 1.0, seed, stream=0)
+    p = inputs.plasma_device(3, N5, (DX3,) * 3, X5_MIN, 2, dens, 1.0, inputs.PROTON_MASS, seed, stream=1,
+                             positions_from=e)
+    if precision == "f64":
+        for st in (e, p):
+            for key in ("off", "u", "w"):
+                st[key] = st[key].to(torch.float64)
     return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
 
 
-T0_STEP5 = 450
-
-
 def large3d_pulse(dt):
-    """Gaussian (D_f = 3, a0 = 3, w0 = 10, tau = 30) focused at the centre of the 1024 x 512 x 512 box."""
+    """Gaussian (D_f = 3, a0 = 3, w0 = 10, tau = 30) focused at the centre of
+    the 1024 x 512 x 512 box; its front is at x = 0 at t = 0."""
     c2 = (dt / DX3) ** 2
     vg = 1.0 - (1.0 - c2) * (2 * math.pi * DX3) ** 2 / 8.0
     xc = N5[0] * DX3 / 2
@@ -244,48 +209,55 @@ def large3d_pulse(dt):
                 dispersion=0, dx_prop=DX3, dt_prop=dt)
 
 
-def large3d_leg(args):
+def window_start(run_steps, warmup, steps):
+    """First step of a window of warmup + steps steps that ends at the end of
+    the run: the pulse is then inside the plasma for the whole window."""
+    return max(0, run_steps - warmup - steps)
+
+
+def large3d_run(precision, warmup, steps, timing=True, tile=(0, 0, 0)):
+    """The last warmup + steps steps of the 1000-step 1024 x 512 x 512 run:
+    `warmup` untimed, then `steps` timed between synchronisations."""
     import torch
     from paper_2307_04843_amd import apt
     from paper_2307_04843_amd.sim import Simulation
-    species = large3d_inputs()
+    log("large 3-D %s: generating 1.07e9 particles on the GPU" % precision)
+    a = time.perf_counter()
+    species = large3d_inputs(precision=precision)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - a
     n = sum(int(s["state"]["u"].shape[1]) for s in species)
     dt = 0.95 / math.sqrt(3) * DX3
-    pp = large3d_pulse(dt)
-    steps, t_step0 = 100, T0_STEP5
-    out = {"workload": "3-D PIC 1024x512x512 cells lambda/16, 2 e + 2 p per cell (1.07e9), n = 0.01 "
-                       "exp(-r^2/(20 lambda)^2), Gaussian D_f=3 a0=3 w0=10 tau=30, steps %d..%d of the "
-                       "1000-step run" % (t_step0, t_step0 + steps), "particles": n, "steps": steps, "warmup": 3}
-    sim = Simulation(3, n=N5, dx=(DX3,) * 3, x_min=X5_MIN, t0=t_step0 * dt, dt=dt, precision="f32",
-                     species=species)
+    s0 = window_start(RUN5_STEPS, warmup, steps)
+    sim = Simulation(3, n=N5, dx=(DX3,) * 3, x_min=X5_MIN, t0=s0 * dt, dt=dt, precision=precision,
+                     species=species, tile=tile)
+    del species
     try:
-        sim.set_pulse("gauss", **pp)
-        sim.step(3)
+        sim.set_pulse("gauss", **large3d_pulse(dt))
+        sim.step(warmup)
         torch.cuda.synchronize()
-        apt.ap_timing_enable(sim.ctx, True)
-        apt.ap_timing_read(sim.ctx, reset=True)
+        if timing:
+            apt.ap_timing_enable(sim.ctx, True)
+            apt.ap_timing_read(sim.ctx, reset=True)
         a = time.perf_counter()
-        for k in range(0, steps, 25):
-            sim.step(25)
-            torch.cuda.synchronize()
-            log("large 3-D: %d/%d steps" % (k + 25, steps))
+        done = 0
+        while done < steps:
+            k = min(25, steps - done)
+            sim.step(k)
+            done += k
+            if done < steps:
+                torch.cuda.synchronize()   # a progress line every 25 steps
+                log("large 3-D %s: %d/%d steps, %.1f s" % (precision, done, steps, time.perf_counter() - a))
+        torch.cuda.synchronize()
         wall = time.perf_counter() - a
-        tm = apt.ap_timing_read(sim.ctx, reset=True)
-        d, _ = sim.diag(allow_numeric=True)
-        ms_push = tm.ms_push / max(1, tm.n_push)
-        bl = n * 60 + sim.ncell * 36
-        out.update({"pushes_per_s": n * steps / wall, "ms_per_step": wall * 1e3 / steps,
-                    "push_ms_per_launch": ms_push, "hbm_gbs_algorithmic": bl / (ms_push * 1e-3) / 1e9,
-                    "hbm_frac": bl / (ms_push * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "yee_ms": tm.ms_yee / max(1, tm.n_yee), "sort_ms_per_step": tm.ms_sort / steps,
-                    "n_nonfinite": d.n_nonfinite, "n_fast": d.n_fast,
-                    "offtile_fraction": d.n_offtile / float(n * (steps + 3))})
-        log("large 3-D: %.3e pushes/s, push %.3f ms/launch" % (out["pushes_per_s"], ms_push))
+        tm = apt.ap_timing_read(sim.ctx, reset=True) if timing else None
+        d, st = sim.diag(allow_numeric=True)
+        return dict(wall=wall, n_part=n, ncell=sim.ncell, timing=tm, diag=d, status=st, first_step=s0,
+                    gen_s=gen_s)
     finally:
         sim.close()
-        del sim, species
+        del sim
         torch.cuda.empty_cache()
-    return out
 
 
 def rows1d_leg():
@@ -356,13 +328,18 @@ def small_leg():
     return out
 
 
+RUN2_STEPS = 2000   # length of the 4096 x 1024 run
+
+
 def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_grid=False, window_shifts=0,
-            current=False):
+            current=False, first_step=0, n_cells=N_CELLS, x_min=(0.0, 0.0, -25.6)):
+    """The 4096 x 1024 LG run (or a box of it, n_cells at x_min) from step
+    `first_step`: `warmup` untimed steps, then `steps` timed ones."""
     import torch
     from paper_2307_04843_amd import apt, inputs
     from paper_2307_04843_amd.sim import Simulation
     dt = 0.95 / math.sqrt(2) * LAMBDA_DX
-    sim = Simulation(2, n=N_CELLS, dx=(LAMBDA_DX,) * 3, x_min=(0.0, 0.0, -25.6), t0=0.0, dt=dt,
+    sim = Simulation(2, n=n_cells, dx=(LAMBDA_DX,) * 3, x_min=x_min, t0=first_step * dt, dt=dt,
                      precision=precision, species=species, sort_every=sort_every, pulse_on_grid=on_grid,
                      moving_window=window_shifts > 0)
     try:
@@ -420,15 +397,60 @@ def run_gpu(species, precision, steps, warmup, timing=True, sort_every=0, on_gri
         sim.close()
 
 
-def cpu_baseline(budget_s=20.0):
-    """The FP64 oracle on a bounded replica of the same workload (host cores).
-
-    Sample: a 64 x 64-cell periodic replica at the workload's resolution,
-    16 e + 16 p per cell (131072 particles), placed at absolute x in
-    [48, 51.2] lambda about the laser axis with the clock at step 1900, so
-    the LG pulse is present; steps until ~budget_s of CPU time.
-    """
+def _oracle_species(st, n, q_m):
+    """Oracle species (positions in cell units) from an inputs.plasma state."""
     import numpy as np
+    from oracle import pic
+    c = st["cell"].astype(np.int64)
+    pos = np.zeros((3, c.size))
+    pos[0] = c % n[0] + st["off"][0]
+    pos[1] = (c // n[0]) % n[1] + st["off"][1]
+    pos[2] = c // (n[0] * n[1]) + st["off"][2]
+    return pic.Species(q_m[0], q_m[1], pos, st["u"].astype(float), st["w"].astype(float))
+
+
+def cpu_baseline(first_step, budget_s=20.0):
+    """The FP64 oracle on a bounded replica of the headline workload (host).
+
+    Sample: a 16 x 16 x 16-cell periodic replica of the 1024 x 512 x 512 run
+    at its resolution, 2 e + 2 p per cell (16384 particles) in the channel's
+    density, around the laser axis at x = 16 ... 17 lambda with the clock at
+    `first_step` (the first step of the timed window), so the Gaussian pulse
+    covers it as it covers the timed steps; steps until ~budget_s of CPU
+    time.  NumPy elementwise work runs on one core.
+    """
+    from oracle import pic, pulses, units
+    from paper_2307_04843_amd import inputs
+    L = units.LAMBDA
+    n = (16, 16, 16)
+    x_min = (16.0, -0.5, -0.5)
+    dt = 0.95 / math.sqrt(3) * DX3
+    dens = inputs.density_gauss_channel(0.01, 20.0, 0.0, 0.0)
+    e = inputs.plasma(3, n, (DX3,) * 3, x_min, 2, dens, 1.0, 1.0, 6, stream=0)
+    p = inputs.plasma(3, n, (DX3,) * 3, x_min, 2, dens, 1.0, inputs.PROTON_MASS, 6, stream=1, positions_from=e)
+    g = pic.Grid(3, n, (DX3 * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=first_step * dt * L)
+    sps = [_oracle_species(e, n, (-1.0, 1.0)), _oracle_species(p, n, (1.0, inputs.PROTON_MASS))]
+    pp = large3d_pulse(dt)
+    P = pulses.Pulse(dict(type="gauss", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
+    N = sum(s.pos.shape[1] for s in sps)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        pic.step(g, sps, P)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 200:
+            break
+    wall = time.perf_counter() - t0
+    return dict(value=N * steps / wall, unit="pushes/s", cores=1, kind="oracle",
+                sample="16x16x16-cell replica of the 1024x512x512 run at x = 16-17 lambda about the laser "
+                       "axis, clock at step %d (the timed window, pulse present), %d particles (2 e + 2 p per "
+                       "cell), %d steps, FP64 NumPy, single thread" % (first_step, N, steps))
+
+
+def cpu_baseline_2d(budget_s=10.0):
+    """The FP64 oracle on a 64 x 64-cell replica of the 4096 x 1024 LG run
+    (16 e + 16 p per cell at x = 48-51.2 lambda, clock at step 1900, inside
+    the pulse), one core."""
     from oracle import pic, pulses, units
     from paper_2307_04843_amd import inputs
     L = units.LAMBDA
@@ -440,12 +462,7 @@ def cpu_baseline(budget_s=20.0):
     p = inputs.plasma(2, n, (LAMBDA_DX,) * 3, x_min, PPC, dens, 1.0, inputs.PROTON_MASS, 6, stream=1,
                       positions_from=e)
     g = pic.Grid(2, n, (LAMBDA_DX * L,) * 3, dt * L, tuple(v * L for v in x_min), t0=1900 * dt * L)
-    sps = []
-    for q, m, st in ((-1.0, 1.0, e), (1.0, inputs.PROTON_MASS, p)):
-        pos = np.zeros((3, st["cell"].size))
-        pos[0] = st["cell"] % n[0] + st["off"][0]
-        pos[2] = st["cell"] // n[0] + st["off"][2]
-        sps.append(pic.Species(q, m, pos, st["u"].astype(float), st["w"].astype(float)))
+    sps = [_oracle_species(e, n, (-1.0, 1.0)), _oracle_species(p, n, (1.0, inputs.PROTON_MASS))]
     pp = workload_pulse(dt)
     P = pulses.Pulse(dict(type="lg", dt=dt, **{k: v for k, v in pp.items() if k != "dt_prop"}))
     N = sum(s.pos.shape[1] for s in sps)
@@ -458,9 +475,8 @@ def cpu_baseline(budget_s=20.0):
             break
     wall = time.perf_counter() - t0
     return dict(value=N * steps / wall, unit="pushes/s", cores=1, kind="oracle",
-                sample="64x64-cell replica of the 4096x1024 workload at x=48-51.2 lambda, "
-                       "step 1900 clock, %d particles (16 e + 16 p per cell), %d steps, FP64 NumPy, "
-                       "single thread" % (N, steps))
+                sample="64x64-cell replica of the 4096x1024 LG run at x=48-51.2 lambda, step 1900 clock, "
+                       "%d particles, %d steps, FP64 NumPy, single thread" % (N, steps))
 
 
 ADJ_N = 1 << 24
@@ -547,33 +563,23 @@ def cpu_gridless_baseline(budget_s=8.0):
 
 METRIC = "particle pushes/s (field eval+push+deposit) FP32 & adjoint vs FP64, 1 MI355X"
 
-# HBM traffic of k_push_deposit_2d on this workload, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, then WRITE_SIZE) scaled by what the same counters read for
-# a plain copy of known size in the same run; per launch, averaged over the
-# launches of the profiled steps.  Valid only for the kernel sources whose
-# digest is recorded here (None once the sources change).
-MEASURED_TRAFFIC = {
-    "sources_sha256": "1bff5f437f62f4347e035d317f352786d2306d624b42597e48b8d3aa6f97849b",
-    "fetch_bytes_per_launch": 4.12356e9,
-    "write_bytes_per_launch": 3.87995e9,
-    # SQ_INSTS_VALU x 64 / particles, same runs: VALU lane-ops issued per push
-    "valu_lane_ops_per_push": 591.1,
-    # SQ_LDS_IDX_ACTIVE / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs), and the bank-conflict share of it
-    "lds_busy_frac": 0.819,
-    "lds_bank_conflict_frac": 0.380,
-    "note": "average over the 2000 timed launches of the default run (calibration copy factors "
-            "0.500 fetch, 1.000 write), profiles/push_deposit_2d_lg_4096x1024_f32.md",
-}
 # Non-packed FP32 VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.
 VALU_PEAK_T_LANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
+PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h", "common.h", "pulse_dev.h",
+                  "dual.h", "nonparaxial_gen.h", "apt_host.cpp")
 
-PUSH2D_SOURCES = ("push2d.hip", "kernels.h", "common.h", "pulse_dev.h", "dual.h", "nonparaxial_gen.h",
-                  "apt_host.cpp")
+# Counter measurements of k_push_deposit_3d on the headline window (the
+# default --steps/--warmup of the full test run), from rocprofv3 --pmc runs of
+# this script: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, each scaled by
+# what the counter reads for a device copy of known size in the same run),
+# VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
+# share.  Valid only for the kernel sources whose digest is recorded here.
+MEASURED_TRAFFIC = None
 
 
-def sources_digest(names=PUSH2D_SOURCES):
-    """SHA-256 over the sources that define the 2-D push kernel and its launch."""
+def sources_digest(names=PUSH3D_SOURCES):
+    """SHA-256 over the sources that define the 3-D push kernel and its launch."""
     import hashlib
     d = os.path.join(ROOT, "paper_2307_04843_amd", "csrc")
     h = hashlib.sha256()
@@ -584,44 +590,42 @@ def sources_digest(names=PUSH2D_SOURCES):
     return h.hexdigest()
 
 
-def pic_leg(args):
-    log("generating inputs")
-    species = workload_inputs()
-    log("FP32 run: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    r32 = run_gpu(species, "f32", args.steps, args.warmup, sort_every=args.sort_every, window_shifts=7)
-    tm = r32["timing"]
-    n_part = r32["n_part"]
-    value = n_part * args.steps / r32["wall"]
+def headline_leg(args):
+    """1024 x 512 x 512 run, 1.07e9 particles: the last warmup + steps steps of
+    its 1000 steps, FP32 (FP64 phase island), then the same window in FP64."""
+    tile3 = tuple(int(v) for v in args.tile3.split(",")) if args.tile3 else (0, 0, 0)
+    r = large3d_run("f32", args.warmup, args.steps, tile=tile3)
+    tm = r["timing"]
+    n_part = r["n_part"]
+    value = n_part * args.steps / r["wall"]
     ms_push = tm.ms_push / max(1, tm.n_push)
     # algorithmic bytes of one launch of the fused kernel: every particle read
-    # (cell 4 + offsets 8 + u 12 + w 4 = 28 B) and written (cell 4 + offsets 8
-    # + u 12 = 24 B), plus the grid share (stage E2, B2: 24 B/cell; J flush 12 B/cell)
-    bytes_launch = n_part * 52 + r32["ncell"] * 36
+    # (cell 4 + offsets 12 + u 12 + w 4 = 32 B) and written (cell 4 + offsets
+    # 12 + u 12 = 28 B), plus the grid share (stage E2, B2: 24 B/cell; J flush 12 B/cell)
+    bytes_launch = n_part * 60 + r["ncell"] * 36
     achieved = bytes_launch / (ms_push * 1e-3) / 1e9
     traffic = None
     traffic_note = "no counter measurement for the current kernel sources"
-    roofline_valu = None
-    roofline_lds = None
-    if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_digest():
-        tb = MEASURED_TRAFFIC["fetch_bytes_per_launch"] + MEASURED_TRAFFIC["write_bytes_per_launch"]
-        traffic = tb / (ms_push * 1e-3) / 1e9
-        traffic_note = ("HBM bytes per launch %.4g (fetch %.4g + write %.4g) from rocprofv3 FETCH_SIZE/"
-                        "WRITE_SIZE, %s, over the current launch time" % (
-                            tb, MEASURED_TRAFFIC["fetch_bytes_per_launch"],
-                            MEASURED_TRAFFIC["write_bytes_per_launch"], MEASURED_TRAFFIC["note"]))
-        ops = MEASURED_TRAFFIC["valu_lane_ops_per_push"] * n_part / (ms_push * 1e-3) / 1e12
+    roofline_valu = roofline_lds = None
+    M = MEASURED_TRAFFIC
+    if M is not None and M["sources_sha256"] == sources_digest():
+        tb = M["fetch_bytes_per_launch"] + M["write_bytes_per_launch"]
+        traffic = tb
+        traffic_note = ("HBM bytes per launch (fetch %.4g + write %.4g) from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                        "%s" % (M["fetch_bytes_per_launch"], M["write_bytes_per_launch"], M["note"]))
+        ops = M["valu_lane_ops_per_push"] * n_part / (M["ms_per_launch"] * 1e-3) / 1e12
         roofline_valu = {"bound": "alu", "achieved": ops, "peak": VALU_PEAK_T_LANE_OPS,
                          "unit": "T VALU lane-ops/s", "frac": ops / VALU_PEAK_T_LANE_OPS,
-                         "per_push": MEASURED_TRAFFIC["valu_lane_ops_per_push"],
-                         "note": "VALU lane-ops issued per push counted by rocprofv3 (SQ_INSTS_VALU), "
-                                 "non-packed FP32 issue peak"}
-        roofline_lds = {"bound": "lds", "busy_frac": MEASURED_TRAFFIC["lds_busy_frac"],
-                        "bank_conflict_frac_of_busy": MEASURED_TRAFFIC["lds_bank_conflict_frac"],
+                         "per_push": M["valu_lane_ops_per_push"], "ms_per_launch": M["ms_per_launch"],
+                         "note": "VALU lane-ops per push counted by rocprofv3 (SQ_INSTS_VALU) over the "
+                                 "launch time of the same profiled runs, non-packed FP32 issue peak"}
+        roofline_lds = {"bound": "lds", "busy_frac": M["lds_busy_frac"],
+                        "bank_conflict_frac_of_busy": M["lds_bank_conflict_frac"],
                         "note": "share of the kernel's cycles in which the LDS pipe is busy "
-                                "(rocprofv3 SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, first 200 steps): "
-                                "the kernel's first bound"}
-    log("FP32: %.3e pushes/s, push kernel %.3f ms/launch, yee %.3f ms, sort %.3f ms"
-        % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, tm.n_sort)))
+                                "(rocprofv3 SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT), same window"}
+    log("headline FP32: %.3e pushes/s, push %.3f ms/launch, yee %.3f ms, sort %.3f ms/step"
+        % (value, ms_push, tm.ms_yee / max(1, tm.n_yee), tm.ms_sort / max(1, args.steps)))
+    first = r["first_step"]
     out = {
         "metric": METRIC,
         "value": value,
@@ -629,64 +633,121 @@ def pic_leg(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["wall"] * 1e3 / args.steps,
+        "ms_per_step": r["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2-D PIC 4096x1024 cells lambda/20, 16 e + 16 p per cell (134M), "
-                               "0->0.05 n_c ramp over 200 lambda, analytic LG l=1 p=0 a0=5 w0=8 "
-                               "tau=30, 2000-step run", "particles": n_part, "cells": r32["ncell"]},
+        "config": {"workload": "3-D PIC 1024x512x512 cells lambda/16, c dt/dx 0.95/sqrt(3), 2 e + 2 p per cell "
+                               "(1.07e9 particles, generated on the GPU), n = 0.01 exp(-r^2/(20 lambda)^2) n_c, "
+                               "T = 1 eV, analytic paraxial Gaussian D_f=3 a0=3 w0=10 lambda tau=30 lambda/c "
+                               "focused at the box centre, FP32 with an FP64 laser phase; timed steps %d..%d of "
+                               "the 1000-step run (pulse inside the plasma)" % (first + args.warmup,
+                                                                              first + args.warmup + args.steps),
+                   "particles": n_part, "cells": r["ncell"], "first_timed_step": first + args.warmup},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_note": traffic_note,
-                     "kernel": "k_push_deposit_2d", "ms_per_launch": ms_push,
-                     "bytes_per_launch": bytes_launch},
+                     "kernel": "k_push_deposit_3d", "ms_per_launch": ms_push,
+                     "bytes_per_launch": bytes_launch,
+                     "bytes_note": "60 B per particle (read cell, offsets, u, w; write cell, offsets, u) + 36 B "
+                                   "per cell (stage E2, B2; flush J)"},
         "roofline_valu": roofline_valu,
         "roofline_lds": roofline_lds,
         "kernels_ms_per_step": {"push_deposit": ms_push, "yee": tm.ms_yee / max(1, tm.n_yee),
                                 "sort": tm.ms_sort / max(1, args.steps),
                                 "other": tm.ms_other / max(1, args.steps)},
-        "moving_window": {"shift_ms": r32["shift_ms"], "note": "ap_shift_window on this grid after the timed "
-                          "steps (fields moved, particles shifted, 2 e + 2 p per cell of the new column injected "
-                          "into slots freed by earlier shifts), wall time incl. host sync, not in the "
-                          "timed region"},
-        "numerics": {"n_nonfinite": r32["diag"].n_nonfinite, "n_fast": r32["diag"].n_fast,
-                     "offtile_fraction": r32["diag"].n_offtile / float(n_part * (args.steps + args.warmup))},
+        "numerics": {"n_nonfinite": r["diag"].n_nonfinite, "n_fast": r["diag"].n_fast,
+                     "offtile_fraction": r["diag"].n_offtile / float(n_part * (args.steps + args.warmup))},
+        "input_generation_s": r["gen_s"],
     }
     if not args.skip_fp64:
-        log("FP64 run: %d steps" % args.fp64_steps)
-        r64 = run_gpu(species, "f64", args.fp64_steps, 0)
-        v64 = n_part * args.fp64_steps / r64["wall"]
-        out["fp64_pushes_per_s"] = v64
-        out["fp32_over_fp64"] = None
-        out["fp64_note"] = ("first %d steps of the same run in the FP64 instantiation; the FP32 "
-                            "rate over the same steps is fp32_first_steps_pushes_per_s" % args.fp64_steps)
-        r32s = run_gpu(species, "f32", args.fp64_steps, 0, timing=False)
-        v32s = n_part * args.fp64_steps / r32s["wall"]
-        out["fp32_first_steps_pushes_per_s"] = v32s
-        out["fp32_over_fp64"] = v32s / v64
-        log("grid-sampled pulse: %d steps" % args.fp64_steps)
-        rg = run_gpu(species, "f32", args.fp64_steps, 0, on_grid=True)
-        tg = rg["timing"]
-        out["grid_sampled"] = {
-            "pushes_per_s": n_part * args.fp64_steps / rg["wall"],
-            "note": "first %d steps with E1, B1 sampled on the grid (Fig. 1 loop, AP_SAMPLE_GRID): "
-                    "sampling kernel + push without per-particle pulse evaluation; compare "
-                    "fp32_first_steps_pushes_per_s" % args.fp64_steps,
-            "push_ms_per_launch": tg.ms_push / max(1, tg.n_push),
-            "sample_and_round_ms_per_step": tg.ms_other / max(1, args.fp64_steps)}
-        log("analytic current: %d steps" % args.fp64_steps)
-        rc = run_gpu(species, "f32", args.fp64_steps, 0, on_grid=True, current=True)
-        tc = rc["timing"]
-        out["analytic_current"] = {
-            "pushes_per_s": n_part * args.fp64_steps / rc["wall"],
-            "note": "the same %d steps with the pulse's analytic current J1 (Sec. IV, AP_DISP_PLASMA, "
-                    "wp2 = 0.05, grid-sampled E1, corrected B1): the J1 kernel and the corrected "
-                    "sampling run per step; compare grid_sampled" % args.fp64_steps,
-            "push_ms_per_launch": tc.ms_push / max(1, tc.n_push),
-            "sample_current_and_round_ms_per_step": tc.ms_other / max(1, args.fp64_steps)}
-    del species
+        k64 = min(args.steps, args.fp64_steps)
+        r64 = large3d_run("f64", args.warmup + args.steps - k64, k64, tile=tile3)
+        v64 = n_part * k64 / r64["wall"]
+        t64 = r64["timing"]
+        out["fp64"] = {"pushes_per_s": v64, "steps": k64,
+                       "push_ms_per_launch": t64.ms_push / max(1, t64.n_push),
+                       "note": "the same kernels instantiated in FP64, same run, timed on the last %d steps of "
+                               "the same window" % k64}
+        out["fp32_over_fp64"] = value / v64
+        log("headline FP64: %.3e pushes/s" % v64)
+    return out
+
+
+def pic2d_inputs(n_cells=N_CELLS, x_min=(0.0, 0.0, -25.6), seed=2):
+    """Electrons + protons of the 4096 x 1024 LG run (16 + 16 per cell),
+    drawn on the GPU."""
+    from paper_2307_04843_amd import inputs
+    dens = inputs.density_ramp_x(0.05, 0.0, 200.0)
+    dx = (LAMBDA_DX,) * 3
+    e = inputs.plasma_device(2, n_cells, dx, x_min, PPC, dens, 1.0, 1.0, seed, stream=0)
+    p = inputs.plasma_device(2, n_cells, dx, x_min, PPC, dens, 1.0, inputs.PROTON_MASS, seed, stream=1,
+                             positions_from=e)
+    return [dict(q=-1.0, m=1.0, state=e), dict(q=1.0, m=inputs.PROTON_MASS, state=p)]
+
+
+INPULSE2D_CELLS = (512, 1, 1024)
+INPULSE2D_XMIN = (37.0, 0.0, -25.6)
+
+
+def pic2d_leg(args):
+    """The 4096 x 1024 LG run (134M particles) on the last steps of its
+    2000-step run (the pulse inside the ramp); then the same window in FP64,
+    with the grid-sampled pulse and with the analytic current; then a box of
+    512 x 1024 cells that lies inside the pulse's envelope for the whole
+    window (every particle evaluates the LG pulse every step)."""
+    import torch
+    W2, K2 = args.warmup2d, args.steps2d
+    first = window_start(RUN2_STEPS, W2, K2)
+
+    def fresh(prec="f32", n_cells=N_CELLS, x_min=(0.0, 0.0, -25.6)):
+        sp = pic2d_inputs(n_cells, x_min)
+        if prec == "f64":
+            for s in sp:
+                for key in ("off", "u", "w"):
+                    s["state"][key] = s["state"][key].to(torch.float64)
+        return sp
+
+    def summary(r, steps):
+        tm = r["timing"]
+        ms = tm.ms_push / max(1, tm.n_push)
+        bl = r["n_part"] * 52 + r["ncell"] * 36
+        return {"pushes_per_s": r["n_part"] * steps / r["wall"], "ms_per_step": r["wall"] * 1e3 / steps,
+                "push_ms_per_launch": ms, "hbm_frac": bl / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "sort_ms_per_step": tm.ms_sort / steps, "yee_ms": tm.ms_yee / max(1, tm.n_yee),
+                "other_ms_per_step": tm.ms_other / steps}
+
+    out = {"workload": "2-D PIC 4096x1024 cells lambda/20, 16 e + 16 p per cell (134M), 0->0.05 n_c ramp over "
+                       "200 lambda, analytic LG l=1 p=0 a0=5 w0=8 tau=30, timed steps %d..%d of the 2000-step "
+                       "run" % (first + W2, first + W2 + K2), "steps": K2, "warmup": W2}
+    log("2-D FP32: %d + %d steps from step %d" % (W2, K2, first))
+    r = run_gpu(fresh(), "f32", K2, W2, sort_every=args.sort_every, window_shifts=7, first_step=first)
+    out.update(summary(r, K2))
+    out["particles"] = r["n_part"]
+    out["moving_window"] = {"shift_ms": r["shift_ms"], "note": "ap_shift_window on this grid after the timed "
+                            "steps (fields moved, particles shifted, 2 e + 2 p per cell of the new column "
+                            "injected into slots freed by earlier shifts), wall time incl. host sync"}
+    if not args.skip_fp64:
+        r64 = run_gpu(fresh("f64"), "f64", K2, W2, first_step=first)
+        out["fp64"] = summary(r64, K2)
+        out["fp32_over_fp64"] = out["pushes_per_s"] / out["fp64"]["pushes_per_s"]
+        rg = run_gpu(fresh(), "f32", K2, W2, on_grid=True, first_step=first)
+        out["grid_sampled"] = summary(rg, K2)
+        out["grid_sampled"]["note"] = ("E1, B1 sampled on the grid (Fig. 1 loop, AP_SAMPLE_GRID): the sampling "
+                                       "kernel + the push without per-particle pulse evaluation")
+        rc = run_gpu(fresh(), "f32", K2, W2, on_grid=True, current=True, first_step=first)
+        out["analytic_current"] = summary(rc, K2)
+        out["analytic_current"]["note"] = ("the pulse's analytic current J1 (Sec. IV, AP_DISP_PLASMA, wp2 = "
+                                           "0.05, grid-sampled E1, corrected B1)")
+    # every particle inside the envelope: the box spans x = 37 ... 62.6 lambda
+    # and the pulse (front at v_g t, 30 lambda/c long) covers it over the window
+    ri = run_gpu(fresh(n_cells=INPULSE2D_CELLS, x_min=INPULSE2D_XMIN), "f32", K2, W2, first_step=first,
+                 n_cells=INPULSE2D_CELLS, x_min=INPULSE2D_XMIN)
+    out["in_pulse"] = summary(ri, K2)
+    out["in_pulse"]["particles"] = ri["n_part"]
+    out["in_pulse"]["workload"] = ("512x1024 cells of the same run at x = 37-62.6 lambda, inside the LG "
+                                   "envelope at every timed step: every push evaluates the LG pulse")
     return out
 
 
@@ -710,35 +771,39 @@ def adjoint_leg(args):
     return adj
 
 
+LEGS = ("headline", "pic2d", "adjoint", "three_d", "small", "rows1d", "cpu")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1990)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=50, help="timed steps of the headline run")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps before them")
+    ap.add_argument("--fp64-steps", type=int, default=50, help="timed FP64 steps (at most --steps)")
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated subset of %s (the headline line is always printed)" % ",".join(LEGS))
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--steps2d", type=int, default=100, help="timed steps of the 4096x1024 legs")
+    ap.add_argument("--warmup2d", type=int, default=10)
     ap.add_argument("--adj-steps", type=int, default=2000)
-    ap.add_argument("--skip-adjoint", action="store_true")
-    ap.add_argument("--skip-pic", action="store_true", help="skip the 2-D PIC leg (profiling runs)")
-    ap.add_argument("--sort-every", type=int, default=0, help="tile re-sort interval (0: library default)")
-    ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 3-D leg")
+    ap.add_argument("--sort-every", type=int, default=0, help="2-D tile re-sort interval (0: library default)")
+    ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 512x256x256 leg")
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
     ap.add_argument("--skip-coupled", action="store_true", help="3-D leg: frozen-grid adjoint only")
-    ap.add_argument("--skip-3d", action="store_true")
-    ap.add_argument("--skip-small", action="store_true")
-    ap.add_argument("--skip-rows1d", action="store_true")
-    ap.add_argument("--with-large3d", action="store_true",
-                    help="add the 1024x512x512 3-D leg (about three minutes of input generation)")
+    ap.add_argument("--tile3", default="", help="tile shape of the headline run, e.g. 8,8,4 (default: library's)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a device buffer of this size (a known-size kernel for "
                          "scaling HBM counters in profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: runs on one GPU only (no multi-GPU path); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    legs = [x for x in args.legs.split(",") if x]
+    for x in legs:
+        if x not in LEGS:
+            print("bench.py: unknown leg %r" % x, file=sys.stderr)
+            sys.exit(2)
     import torch
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
@@ -753,25 +818,27 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read + %d MiB written" % (args.calib_copy_mib, args.calib_copy_mib))
         del src, dst
-    if args.skip_pic:
-        out = {"metric": METRIC, "value": None, "unit": "pushes/s", "n_gpus": 1, "steps": 0,
-               "warmup": 0, "note": "PIC leg skipped (profiling run)"}
+    if "headline" in legs:
+        out = headline_leg(args)
     else:
-        out = pic_leg(args)
-    if not args.skip_adjoint:
+        out = {"metric": METRIC, "value": None, "unit": "pushes/s", "n_gpus": 1, "steps": 0,
+               "warmup": 0, "note": "headline leg skipped (profiling run)"}
+    if "pic2d" in legs:
+        out["pic2d"] = pic2d_leg(args)
+    if "adjoint" in legs:
         out["adjoint"] = adjoint_leg(args)
-    if not args.skip_3d:
+    if "three_d" in legs:
         out["three_d"] = three_d_leg(args)
-    if not args.skip_small:
+    if "small" in legs:
         out["small"] = small_leg()
-    if not args.skip_rows1d:
+    if "rows1d" in legs:
         out["rows1d"] = rows1d_leg()
-    if args.with_large3d:
-        out["large3d"] = large3d_leg(args)
-    if not args.skip_cpu:
+    if "cpu" in legs:
+        first = window_start(RUN5_STEPS, args.warmup, args.steps) + args.warmup
         log("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
-        if not args.skip_adjoint:
+        out["cpu_baseline"] = cpu_baseline(first, args.cpu_budget)
+        out["cpu_baseline_2d"] = cpu_baseline_2d()
+        if "adjoint" in legs:
             log("CPU oracle baseline, gridless")
             out["cpu_baseline_gridless"] = cpu_gridless_baseline()
     print(json.dumps(out), flush=True)

@@ -252,25 +252,46 @@ typedef struct ap_pulse_params {
     double  wp2, zeta;
 } ap_pulse_params;
 
-/* FP64 diagnostics (reductions of the current state). */
+/* FP64 diagnostics: reductions of the current state (the quantities the
+ * paper inspects: field energy, particle energy and moments, Sec. II.B and
+ * the energy balance of Sec. IV), the continuity residual of the
+ * charge-conserving deposition (Sec. II.B names second-order charge-
+ * conserving deposition), and numeric flags.  Every per-species sum is over
+ * valid particles only (free slots and invalid particles are left out).
+ * The step counters (continuity_max, j_max, n_fast, n_offtile, n_skipped)
+ * cover the steps since the previous ap_gather_diag (or ap_init): each call
+ * resets them. */
 typedef struct ap_diag {
     double  t;                          /* lambda/c                        */
     int64_t step;
-    double  field_energy;               /* sum (E2^2 + B2^2)/2 * cell volume */
+    double  field_energy;               /* sum over cells of (E2^2 + B2^2)/2 times
+                                           the cell volume dx dy dz (2-D: dx dz, per
+                                           unit length along y; 1-D rows: dx, per
+                                           unit transverse area, summed over rows);
+                                           internal units: m c^2 n_c (c/omega)^D  */
     double  sum_w[AP_MAX_SPECIES];
-    double  kinetic[AP_MAX_SPECIES];    /* m sum w (gamma - 1)              */
-    double  mean_u[AP_MAX_SPECIES][3];  /* weighted means                   */
-    double  mean_u2[AP_MAX_SPECIES][3];
+    double  kinetic[AP_MAX_SPECIES];    /* m sum w (gamma - 1), in m_e c^2 n_c per cell */
+    double  mean_u[AP_MAX_SPECIES][3];  /* weighted means sum w u / sum w  */
+    double  mean_u2[AP_MAX_SPECIES][3]; /* sum w u_k^2 / sum w             */
     double  mean_gamma[AP_MAX_SPECIES];
-    double  proxy_sum[AP_MAX_SPECIES];  /* sum of per-particle proxies      */
-    double  continuity_max;             /* max over checked steps of
-                                           max|(rho1-rho0)/dt + div J|      */
+    double  proxy_sum[AP_MAX_SPECIES];  /* sum of per-particle proxies (s - c) */
+    double  continuity_max;             /* max over checked steps (AP_STEP_CONTINUITY)
+                                           of max|(rho1-rho0)/dt + div J|      */
     double  j_max;                      /* max |J| over the same steps      */
-    int64_t n_nonfinite;                /* particles with non-finite state  */
-    int64_t n_fast;                     /* moves of >= 1 cell in one step   */
+    int64_t n_nonfinite;                /* AP_DIAG_PARTICLES: particles whose state
+                                           is invalid now (non-finite momentum,
+                                           weight or offset, cell off the grid,
+                                           offset outside [0, 1)); free slots of a
+                                           moving window are not counted */
+    int64_t n_fast;                     /* pushes whose move was dropped: a particle
+                                           never outruns c and dt is below the Yee
+                                           limit, so this counts momenta whose gamma
+                                           overflows the working type            */
     int64_t n_offtile;                  /* pushes whose stencil left the LDS-staged
                                            tile region (served from global memory
                                            instead; a measure of sort staleness) */
+    int64_t n_skipped;                  /* pushes skipped because the particle was
+                                           invalid (left unchanged)             */
 } ap_diag;
 
 /* Accumulated device time of each kernel family since the last reset. */
@@ -283,32 +304,47 @@ typedef struct ap_timing {
     int64_t pushes;         /* particle pushes covered by ms_push            */
 } ap_timing;
 
-/* Sizes of every caller-owned device buffer for this grid and species set.
+/* Sizes of every caller-owned device buffer for this grid and species set:
+ * the internal fields E2, B2 and the current J of the field split (Sec. II,
+ * Eqs. (3)-(4)) and the particle workspace of the loop of Fig. 1.
  * AP_E_ARG for an invalid description (see ap_init). */
 ap_status ap_query_layout(const ap_grid_desc *grid, const ap_species_desc *species,
                           int32_t n_species, ap_layout *out);
 
-/* Bind caller-owned buffers and the stream; zero the grid block.
+/* Bind caller-owned buffers and the stream; zero the grid block (E2 = B2 = 0:
+ * the internal field starts empty, Sec. II, Eq. (4)).  Time step rule: the
+ * one stated after Eq. (14).
  * The particle arrays must already hold the initial state (u at t0 - dt/2).
- * Validation: dim in {0,2,3}; n >= 4 cells per active axis; dx > 0;
+ * Validation: dim in {0,1,2,3}; n >= 4 cells per active axis; dx > 0;
  * dt > 0 and below the Yee limit 1/sqrt(sum 1/dx^2); 1 <= n_species <= 4;
  * m > 0; every required pointer non-NULL.  Writes *out on success only. */
 ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species,
                   int32_t n_species, const ap_buffers *buffers, void *hip_stream,
                   ap_ctx **out);
 
-/* Select the analytic pulse (E1, B1).  Validates the parameters (tau > 0,
+/* Select the analytic pulse (E1, B1): the closed-form vacuum solution of the
+ * field split (Sec. II, Eq. (3)) with the run-time parameters of Sec. II.B
+ * (amplitude, frequency, duration, envelope delay, phase at a reference
+ * position) and the families of Eqs. (15), (21) and Sec. III.  Validates the parameters (tau > 0,
  * w0 > 0 for focused types, d_f in {2,3}, LG needs d_f = 3, beta_f != 1,
  * finite values) and precomputes its FP64 constants on the host.
  * AP_PULSE_NONE removes the laser. */
 ap_status ap_set_pulse(ap_ctx *ctx, int32_t pulse_type, const ap_pulse_params *params);
 
-/* Advance n_steps time steps (asynchronous).  Requires ap_set_pulse first. */
+/* Advance n_steps time steps (asynchronous): the loop of Fig. 1 with the
+ * field split of Sec. II -- per step, gather E2, B2 at the particles, add
+ * E1, B1 (Eq. (3), evaluated at each particle, or on the grid with
+ * AP_SAMPLE_GRID), relativistic Boris push, move, charge-conserving
+ * second-order deposition of J (Sec. II.B), and the Yee update of E2, B2
+ * driven by J alone (Eqs. (4), (7)-(9)).  Requires ap_set_pulse first.
+ * AP_E_ARG for unknown flags or a too small checkpoint buffer when recording. */
 ap_status ap_step(ap_ctx *ctx, int64_t n_steps, uint32_t flags);
 
-/* FP64 reductions of the current state into *out (host), synchronising.
- * Returns AP_E_NUMERIC (after filling *out) when non-finite particles or
- * moves of a full cell were detected. */
+/* FP64 reductions of the current state into *out (host), synchronising
+ * (the diagnostics of Sec. II.B and Sec. IV; the continuity residual of the
+ * charge-conserving deposition).  what: AP_DIAG_* bits.  Returns AP_E_NUMERIC
+ * (after filling *out) when n_nonfinite, n_fast or n_skipped is non-zero;
+ * AP_E_ARG for a NULL argument or unknown bits. */
 ap_status ap_gather_diag(ap_ctx *ctx, uint32_t what, ap_diag *out);
 
 /* Current simulation time (lambda/c) and step count. */
@@ -321,6 +357,15 @@ ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
  * each (context precision, component-major).  t in lambda/c.
  * Asynchronous on the context stream. */
 ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, void *E, void *B);
+
+/* Emission proxy of every particle of a species (the radiated-power proxy
+ * the benchmark spec's gradients observe: the Lienard power without its constant,
+ * summed over the steps), read out as FP64 values s - c of each particle's
+ * compensated pair, in the current slot order of the species' arrays (pair
+ * them with the id array for a by-id view).  dst: device, n doubles, written
+ * asynchronously on the context stream.  AP_E_ARG for a species without a
+ * proxy, a species index out of range or a NULL dst. */
+ap_status ap_read_proxy(ap_ctx *ctx, int32_t species, double *dst);
 
 /* Adjoint checkpoint storage.  dev: caller-owned device buffer of `bytes`;
  * segment K: steps between stored states.  Recording n steps needs
@@ -354,7 +399,9 @@ ap_status ap_set_adjoint_mode(ap_ctx *ctx, int32_t mode);
  * (written to *bytes, host). */
 ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segment, size_t *bytes);
 
-/* Gradient of a particle observable with respect to pulse parameters over
+/* Gradient of a particle observable with respect to pulse parameters (the
+ * the benchmark spec's differentiated form of the push and the analytic field of
+ * Sec. II-III) over
  * the steps of the last ap_step call made with AP_STEP_RECORD (the state
  * must not have been advanced, nor the pulse changed, since).  The observable is
  *     L = sum_p dL_du[p] . u_p(final) + dL_dproxy[p] * proxy_p(final),
@@ -392,7 +439,6 @@ ap_status ap_backward(ap_ctx *ctx, int32_t species, const void *dL_du,
 ap_status ap_timing_enable(ap_ctx *ctx, int32_t enable);
 ap_status ap_timing_read(ap_ctx *ctx, ap_timing *out, int32_t reset);
 
-/* Release the context (does not free caller buffers). NULL is accepted. */
 /* Moving window (Sec. III.C: a window following the pulse, e.g. the
  * intensity peak of a flying focus): advance the window one cell along +x.
  * Needs AP_GRID_MOVING_WINDOW.  Lab positions are kept: x_min[0] grows by
@@ -419,9 +465,11 @@ typedef struct ap_inject {
 } ap_inject;
 ap_status ap_shift_window(ap_ctx *ctx, const ap_inject *inject);
 
+/* Release the context (does not free caller buffers). NULL is accepted. */
 ap_status ap_destroy(ap_ctx *ctx);
 
-/* Message of the last non-OK status on this thread ("" if none). */
+/* Message of the last non-OK status on this thread ("" if none).  The string
+ * stays valid until the thread's next ap_* call. */
 const char *ap_last_error(void);
 
 #ifdef __cplusplus

@@ -34,8 +34,9 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
-            "ap_get_time", "ap_eval_pulse", "ap_set_checkpoints", "ap_set_adjoint_mode", "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window", "ap_destroy",
-            "ap_last_error")
+            "ap_get_time", "ap_eval_pulse", "ap_read_proxy", "ap_set_checkpoints", "ap_set_adjoint_mode",
+            "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window",
+            "ap_destroy", "ap_last_error")
 
 
 class ap_grid_desc(C.Structure):
@@ -87,7 +88,7 @@ class ap_diag(C.Structure):
                 ("mean_gamma", C.c_double * 4), ("proxy_sum", C.c_double * 4),
                 ("continuity_max", C.c_double), ("j_max", C.c_double),
                 ("n_nonfinite", C.c_int64), ("n_fast", C.c_int64),
-                ("n_offtile", C.c_int64)]
+                ("n_offtile", C.c_int64), ("n_skipped", C.c_int64)]
 
 
 class ap_timing(C.Structure):
@@ -125,6 +126,7 @@ def load():
         "ap_get_time": (C.c_int32, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
         "ap_eval_pulse": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p,
                                       C.c_void_p]),
+        "ap_read_proxy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
         "ap_set_checkpoints": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
         "ap_checkpoint_bytes": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, P(C.c_size_t)]),
         "ap_set_adjoint_mode": (C.c_int32, [C.c_void_p, C.c_int32]),
@@ -197,6 +199,10 @@ def ap_get_time(ctx):
 def ap_eval_pulse(ctx, n, xyz_ptr, t, e_ptr, b_ptr):
     _check(load().ap_eval_pulse(ctx, int(n), C.c_void_p(xyz_ptr), float(t), C.c_void_p(e_ptr),
                                 C.c_void_p(b_ptr)), "ap_eval_pulse")
+
+
+def ap_read_proxy(ctx, species, dst_ptr):
+    _check(load().ap_read_proxy(ctx, int(species), C.c_void_p(dst_ptr)), "ap_read_proxy")
 
 
 def ap_set_checkpoints(ctx, dev_ptr, nbytes, segment):

@@ -71,8 +71,7 @@ class GridlessRun:
         a = self.sim.arrays[0]
         u = torch.stack([t.clone() for t in a["u"]])
         if a["proxy"] is not None:
-            pr = a["proxy"].view(-1, 2)
-            proxy = pr[:, 0].double() - pr[:, 1].double()   # sum minus its compensation
+            proxy = self.sim.proxy_values(0)
         else:
             proxy = torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
         return u, proxy
@@ -168,8 +167,7 @@ class GriddedRun:
         out[:, idx] = u
         proxy = torch.zeros(u.shape[1], dtype=torch.float64, device=u.device)
         if a["proxy"] is not None:
-            pr = a["proxy"].view(-1, 2)
-            proxy[idx] = pr[:, 0].double() - pr[:, 1].double()   # sum minus its compensation
+            proxy[idx] = self.sim.proxy_values(self.sp)
         return out, proxy
 
     def backward(self, grad_u, grad_proxy=None):
@@ -198,9 +196,15 @@ class APTRun(torch.autograd.Function):
     def forward(ctx, params, run):
         ctx.run = run
         u, proxy = run.forward(params.detach().cpu().double().tolist())
+        # the run holds one recording: a later forward replaces it
+        run.generation = getattr(run, "generation", 0) + 1
+        ctx.generation = run.generation
         return u, proxy
 
     @staticmethod
     def backward(ctx, grad_u, grad_proxy):
+        if getattr(ctx.run, "generation", None) != ctx.generation:
+            raise RuntimeError("APTRun: the run was forwarded again since this graph was built; its "
+                               "recording (checkpoints, pulse parameters) is gone")
         g = ctx.run.backward(grad_u, grad_proxy)
         return torch.tensor(g, dtype=torch.float64), None

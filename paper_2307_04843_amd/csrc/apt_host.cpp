@@ -120,11 +120,16 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         for (int ax = 0; ax < 3; ++ax) {
             int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : (s.dim == 2 ? def2[ax] : def1[ax]));
             if (!axis_active(s.dim, ax)) t = 1;
-            if (t > s.n[ax]) t = s.n[ax];
+            // 3-D tile shapes are compiled into the push kernel (constant LDS
+            // strides); a tile wider than a tiny grid covers its periodic images
+            if (s.dim != 3 && t > s.n[ax]) t = s.n[ax];
             if (t > 64) return fail(AP_E_ARG, "tile extent must be <= 64 cells");
             s.tile[ax] = t;
             s.ntile[ax] = (s.n[ax] + t - 1) / t;
         }
+        if (s.dim == 3 && !(s.tile[0] == 8 && ((s.tile[1] == 4 && s.tile[2] == 4) ||
+                                               (s.tile[1] == 8 && (s.tile[2] == 4 || s.tile[2] == 8)))))
+            return fail(AP_E_ARG, "3-D tiles must be 8x4x4, 8x8x4 or 8x8x8 cells");
         s.ntiles = (int64_t)s.ntile[0] * s.ntile[1] * s.ntile[2];
         // LDS of the push kernel: 9 components on the tile plus its halo
         size_t region = 1;
@@ -344,10 +349,8 @@ struct ap_ctx {
     PulseDev P;
     int pulse_type = -1;
     double s0 = 1.0;             // S0/E0 of the incoming-wave boundary (AP_SAMPLE_BOUNDARY)
-    // moving window: free particle slots (all species) and the skipped-particle
-    // count they add to the push's counter, which the diagnostics subtract
+    // moving window: free particle slots (all species)
     int64_t n_free = 0;
-    uint64_t free_skips = 0;
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
@@ -770,12 +773,14 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
                     DiagArgs<double> a{};
                     for (int k = 0; k < 3; ++k) { a.u[k] = (const double *)p.u[k]; a.off[k] = (const double *)(axis_active(s.dim, k) ? p.off[k] : nullptr); }
                     a.w = (const double *)p.w; a.proxy = (const double *)p.proxy; a.n = (int)s.np[i]; a.dim = s.dim;
+                    a.cell = s.dim > 0 ? p.cell : nullptr; a.ncell = (uint32_t)s.ncell;
                     a.partial = partial; a.blocks = kDiagBlocks;
                     e = launch_diag_particles<double>(a, c->stream);
                 } else {
                     DiagArgs<float> a{};
                     for (int k = 0; k < 3; ++k) { a.u[k] = (const float *)p.u[k]; a.off[k] = (const float *)(axis_active(s.dim, k) ? p.off[k] : nullptr); }
                     a.w = (const float *)p.w; a.proxy = (const float *)p.proxy; a.n = (int)s.np[i]; a.dim = s.dim;
+                    a.cell = s.dim > 0 ? p.cell : nullptr; a.ncell = (uint32_t)s.ncell;
                     a.partial = partial; a.blocks = kDiagBlocks;
                     e = launch_diag_particles<float>(a, c->stream);
                 }
@@ -801,11 +806,13 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
     unsigned long long cnt[kCounters];
     HIPCHK(hipMemcpyAsync(host, sums, sizeof(host), hipMemcpyDeviceToHost, c->stream), "ap_gather_diag");
     HIPCHK(hipMemcpyAsync(cnt, c->counters(), sizeof(cnt), hipMemcpyDeviceToHost, c->stream), "ap_gather_diag");
+    // the step counters (dropped moves, skipped pushes, continuity maxima,
+    // off-tile pushes) cover the steps since the previous ap_gather_diag
+    HIPCHK(launch_fill_zero<unsigned long long>(c->counters(), 5, c->stream), "ap_gather_diag");
     HIPCHK(hipStreamSynchronize(c->stream), "ap_gather_diag");
     d.t = (s.t0 + (double)c->step * s.dt) / kTwoPi;
     d.step = c->step;
-    // free slots (moving window) are skipped by the push like invalid particles: not an error
-    int64_t nonfinite = (int64_t)(cnt[1] - c->free_skips);
+    int64_t nonfinite = 0;
     if (what & AP_DIAG_PARTICLES) {
         for (int i = 0; i < s.nsp; ++i) {
             const double *v = host + (size_t)i * kDiagVals;
@@ -817,7 +824,7 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
                 d.mean_u2[i][k] = v[4 + k] * inv;
             }
             d.mean_gamma[i] = v[7] * inv;
-            d.kinetic[i] = c->s.np[i] > 0 ? v[8] * 1.0 : 0.0;
+            d.kinetic[i] = c->s.m[i] * v[8];
             d.proxy_sum[i] = v[9];
             nonfinite += (int64_t)v[10];
         }
@@ -835,9 +842,12 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
     d.n_nonfinite = nonfinite;
     d.n_fast = (int64_t)cnt[0];
     d.n_offtile = (int64_t)cnt[4];
+    d.n_skipped = (int64_t)cnt[1];
     *out = d;
-    if (d.n_nonfinite > 0 || d.n_fast > 0)
-        return fail(AP_E_NUMERIC, "non-finite particle state or a move of a full cell detected");
+    if (d.n_nonfinite > 0 || d.n_fast > 0 || d.n_skipped > 0)
+        return fail(AP_E_NUMERIC, "invalid particle state (" + std::to_string(d.n_nonfinite) + " now, " +
+                                      std::to_string(d.n_skipped) + " skipped pushes) or " +
+                                      std::to_string(d.n_fast) + " dropped moves since the last diagnostics");
     return AP_OK;
 }
 
@@ -858,6 +868,22 @@ ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void 
         e = launch_eval_pulse<float>(c->P.type, plain_vars<float>(c->P, t * kTwoPi), fd_delta, n, xyz,
                                      static_cast<float *>(E), static_cast<float *>(B), c->stream);
     if (e != hipSuccess) return hip_fail(e, "ap_eval_pulse");
+    return AP_OK;
+}
+
+ap_status ap_read_proxy(ap_ctx *c, int32_t species, double *dst) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (species < 0 || species >= c->s.nsp) return fail(AP_E_ARG, "species index out of range");
+    const bool has = c->s.dim > 0 ? c->s.has_proxy[species] : c->buf.sp[species].proxy != nullptr;
+    if (!has) return fail(AP_E_ARG, "the species carries no emission proxy");
+    const int n = (int)c->s.np[species];
+    if (n > 0 && !dst) return fail(AP_E_ARG, "destination is NULL");
+    hipError_t e = c->s.prec == AP_F64
+                       ? launch_proxy_value<double>(static_cast<const double *>(c->buf.sp[species].proxy), dst, n,
+                                                    c->stream)
+                       : launch_proxy_value<float>(static_cast<const float *>(c->buf.sp[species].proxy), dst, n,
+                                                   c->stream);
+    if (e != hipSuccess) return hip_fail(e, "ap_read_proxy");
     return AP_OK;
 }
 
@@ -1257,7 +1283,6 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     const int n = (int)s.np[sp];
     unsigned long long *cnt = c->counters();
     unsigned long long saved[kCounters];
-    const uint64_t saved_skips = c->free_skips;
     {
         // the adjoint state is indexed by particle id: ids must be 0..n-1, each once
         int32_t *seen = c->wp<int32_t>(c->L.rank[sp]);
@@ -1338,7 +1363,6 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     c->step = c->rec_step0 + c->rec_n;
     c->need_sort = true;
     HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
-    c->free_skips = saved_skips;
     double *sums = c->wp<double>(c->L.sums);
     HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
     double host[5];
@@ -1362,7 +1386,6 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     const size_t nc = (size_t)s.ncell;
     unsigned long long *cnt = c->counters();
     unsigned long long saved[kCounters];
-    const uint64_t saved_skips = c->free_skips;
     HIPCHK(hipMemcpyAsync(saved, cnt, sizeof(saved), hipMemcpyDeviceToHost, c->stream), "backward");
     for (int i = 0; i < s.nsp; ++i) {
         // each adjoint state is indexed by particle id: ids must be 0..n-1, each once
@@ -1471,7 +1494,6 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     c->step = c->rec_step0 + c->rec_n;
     c->need_sort = true;
     HIPCHK(hipMemcpyAsync(cnt, saved, sizeof(saved), hipMemcpyHostToDevice, c->stream), "backward");
-    c->free_skips = saved_skips;
     double *sums = c->wp<double>(c->L.sums);
     HIPCHK(launch_sum_partials(partial, G.blocks, 5, sums, c->stream), "backward");
     double host[5];
@@ -1704,6 +1726,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     a.fntxy = FastDiv((uint32_t)(s.ntile[0] * s.ntile[1]));
     a.splits = s.splits;
     a.n_logical = (int32_t)(s.ntiles * s.splits);
+    a.xcd_chunk = s.dim == 3 && s.splits == 1 && s.ntile[0] >= 8 ? s.ntile[0] / 8 : 1;
     a.dt = s.dt;
     a.t = s.t0 + (double)c->step * s.dt;
     a.n_fast = c->counters() + 0;
@@ -1778,7 +1801,6 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
                                   : launch_push_deposit_3d<T>(push_pulse, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
-        c->free_skips += (uint64_t)c->n_free;   // free slots take the push's skipped-particle path
     }
     if (s.prec == AP_F32) {
         // one rounding of the FP64 sum per node keeps continuity at FP32 round-off

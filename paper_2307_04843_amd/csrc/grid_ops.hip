@@ -202,6 +202,20 @@ template hipError_t launch_fill_zero<double>(double *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<int32_t>(int32_t *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<unsigned long long>(unsigned long long *, size_t, hipStream_t);
 
+// Emission proxy of each particle: its compensated pair (sum s, compensation
+// c) read out as the FP64 value s - c, in slot order.
+template <typename T> __global__ void k_proxy_value(const T *pair, double *out, int n) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) out[p] = (double)pair[2 * p] - (double)pair[2 * p + 1];
+}
+template <typename T> hipError_t launch_proxy_value(const T *pair, double *out, int n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_proxy_value<T>), dim3((n + 255) / 256), dim3(256), 0, s, pair, out, n);
+    return hipGetLastError();
+}
+template hipError_t launch_proxy_value<float>(const float *, double *, int, hipStream_t);
+template hipError_t launch_proxy_value<double>(const double *, double *, int, hipStream_t);
+
 template <typename T> __global__ void k_round_current(const double *jacc, T *J, size_t n) {
     for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
         J[c] = T(jacc[c]);
@@ -589,18 +603,26 @@ template <typename T> __global__ __launch_bounds__(256) void k_diag_particles(Di
 #pragma unroll
     for (int m = 0; m < kDiagVals; ++m) v[m] = 0.0;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += gridDim.x * blockDim.x) {
+        const int32_t cell = a.cell ? a.cell[p] : 0;
+        if (a.cell && cell == kDeadCell) continue;   // free slot of a moving window
         const double ux = a.u[0][p], uy = a.u[1][p], uz = a.u[2][p];
         const double w = a.w[p];
+        // a valid particle: finite momentum and weight, cell on the grid, offsets in [0, 1)
         bool fin = isfinite(ux) && isfinite(uy) && isfinite(uz) && isfinite(w);
+        if (a.cell) fin = fin && (uint32_t)cell < a.ncell;
         for (int c = 0; c < 3; ++c)
-            if (a.off[c]) fin = fin && isfinite((double)a.off[c][p]);
-        if (!fin) { v[10] += 1.0; continue; }
-        const double g = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+            if (a.off[c]) {
+                const double o = a.off[c][p];
+                fin = fin && o >= 0.0 && o < 1.0;
+            }
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double g = sqrt(1.0 + uu);
+        if (!fin || !isfinite(g)) { v[10] += 1.0; continue; }
         v[0] += w;
         v[1] += w * ux; v[2] += w * uy; v[3] += w * uz;
         v[4] += w * ux * ux; v[5] += w * uy * uy; v[6] += w * uz * uz;
         v[7] += w * g;
-        v[8] += w * (g - 1.0);
+        v[8] += w * (uu / (g + 1.0));   // gamma - 1 without cancellation
         // compensated pair: the sum carries the compensation's error with the opposite sign
         if (a.proxy) v[9] += (double)a.proxy[2 * p] - (double)a.proxy[2 * p + 1];
     }

@@ -21,6 +21,7 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_gridless(
         ok = ok && of[c] >= T(0) && of[c] < T(1);
     }
     T ux = a.u[0][p], uy = a.u[1][p], uz = a.u[2][p];
+    ok = ok && finite_state(ux, uy, uz, T(0));
     if (!ok) {
         atomicAdd(a.n_bad, 1ull);
 #pragma unroll

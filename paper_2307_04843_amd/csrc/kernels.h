@@ -49,13 +49,14 @@ template <typename T> struct PushArgs {
     FastDiv fnx, fnxy, fntx, fntxy;
     int32_t splits;              // workgroups per tile
     int32_t n_logical;           // n_tiles * splits
+    int32_t xcd_chunk;           // 3-D: consecutive logical tiles per XCD run (block -> tile map)
     int32_t reg[3];              // LDS region extent per axis
     double dx[3];
     double x_min[3];
     double dt;
     double t;                    // time of the positions read (t^n)
-    unsigned long long *n_fast;  // moves >= 1 cell (clamped)
-    unsigned long long *n_bad;   // non-finite / out-of-range particles
+    unsigned long long *n_fast;  // moves the kernel could not take (dropped), see push_move_ok
+    unsigned long long *n_bad;   // skipped pushes of invalid particles (free slots not counted)
     unsigned long long *n_offtile;   // pushes that left the staged region (global-memory path)
     double q_slice;              // lab y sampled by an (x, z) grid
     int32_t pulse;               // PulseType
@@ -196,6 +197,8 @@ template <typename T>
 hipError_t launch_yee(int dim, T *const F[9], const YeeArgsBase &g, int no_yee, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_zero(T *p, size_t n, hipStream_t s);
+// out[p] = pair[2p] - pair[2p+1] in FP64: the proxy of each particle from its compensated pair.
+template <typename T> hipError_t launch_proxy_value(const T *pair, double *out, int n, hipStream_t s);
 // J = (T) Jacc over n values: the step's current rounded once to the working type.
 template <typename T> hipError_t launch_round_current(const double *jacc, T *J, size_t n, hipStream_t s);
 
@@ -219,6 +222,23 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, in
 // Moving window (Sec. III.C): the window advances one cell along +x.  A free
 // particle slot holds cell kDeadCell, zero weight, momentum and offsets.
 constexpr int32_t kDeadCell = -1;
+
+// A particle the push can advance has finite momentum and weight (a
+// non-finite one would put NaN into the current); its cell and offsets are
+// checked by each kernel.  Skipped particles are counted, free slots not.
+template <typename T> AP_D bool finite_state(T ux, T uy, T uz, T w) {
+    return __builtin_isfinite(ux) && __builtin_isfinite(uy) && __builtin_isfinite(uz) && __builtin_isfinite(w);
+}
+AP_D void count_skipped(unsigned long long *n_bad, int32_t cell) {
+    if (cell != kDeadCell) atomicAdd(n_bad, 1ull);
+}
+// A move is taken when 1/gamma is positive (gamma did not overflow the
+// working type) and the displacement is below one cell.  A particle is never
+// faster than c and dt is below the Yee limit, so only a momentum whose gamma
+// overflows (|u| above ~1e19 in FP32) can fail; its move is dropped and counted.
+template <typename T> AP_D bool push_move_ok(T inv_gamma, T d) {
+    return inv_gamma > T(0) && fabs(d) < T(1);
+}
 template <typename T> struct WindowArgs {
     int32_t *cell; const int32_t *id; T *off[3]; T *u[3]; T *w; T *proxy;   // one species, in place
     int32_t n;
@@ -262,6 +282,8 @@ template <typename T> struct DiagArgs {
     const T *w;
     const T *proxy;
     const T *off[3];
+    const int32_t *cell;         // gridded runs: linear cells (kDeadCell = free slot), else null
+    uint32_t ncell;
     int32_t n;
     int32_t dim;
     double *partial;             // [blocks][kDiagVals]

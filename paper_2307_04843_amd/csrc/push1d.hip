@@ -89,9 +89,10 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
             const T w = w_in[p];
             const int prow = (int)a.fnx.div((unsigned)cell);
             // a particle belongs to its tile's row; anything else is invalid state
-            const bool ok = (unsigned)cell < ncell && prow == row && offx >= T(0) && offx < T(1);
+            const bool ok = (unsigned)cell < ncell && prow == row && offx >= T(0) && offx < T(1) &&
+                            finite_state(ux, uy, uz, w);
             if (!ok) {
-                atomicAdd(a.n_bad, 1ull);
+                count_skipped(a.n_bad, cell);
                 S.cell_out[p] = cell;
                 S.off_out[0][p] = offx;
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
             // ---- move along x
             const T ign = rsqrt_r<T>(T(1) + ux * ux + uy * uy + uz * uz);
             T ddx = ux * ign * dtdx;
-            if (!(fabs(ddx) < T(1))) {
+            if (!push_move_ok(ign, ddx)) {
                 atomicAdd(a.n_fast, 1ull);
                 ddx = T(0);
             }

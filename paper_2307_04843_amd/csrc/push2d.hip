@@ -158,9 +158,9 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
             const T w = w_in[p];
             const bool ok = (unsigned)cell < ncell && offx >= T(0) && offx < T(1) &&
-                            offz >= T(0) && offz < T(1);
+                            offz >= T(0) && offz < T(1) && finite_state(ux, uy, uz, w);
             if (!ok) {
-                atomicAdd(a.n_bad, 1ull);
+                count_skipped(a.n_bad, cell);
                 S.cell_out[p] = cell;
                 S.off_out[0][p] = offx;
                 S.off_out[2][p] = offz;
@@ -275,10 +275,10 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             // ---- move in (cell, offset) form
             const T ign = rsqrt_r<T>(T(1) + ux * ux + uy * uy + uz * uz);
             T ddx = ux * ign * dtdx, ddz = uz * ign * dtdz;
-            if (!(fabs(ddx) < T(1)) || !(fabs(ddz) < T(1))) {
+            if (!push_move_ok(ign, ddx) || !push_move_ok(ign, ddz)) {
                 atomicAdd(a.n_fast, 1ull);
-                if (!(fabs(ddx) < T(1))) ddx = T(0);
-                if (!(fabs(ddz) < T(1))) ddz = T(0);
+                if (!push_move_ok(ign, ddx)) ddx = T(0);
+                if (!push_move_ok(ign, ddz)) ddz = T(0);
             }
             T nox = offx + ddx, noz = offz + ddz;
             int sx = (int)floor_r<T>(nox), sz = (int)floor_r<T>(noz);

@@ -1,0 +1,506 @@
+// Fused per-particle kernel for 3-D grids (implementation; the launcher
+// dispatching on the tile shape is in push3d.hip): LDS-staged gather of E2, B2 on a
+// 3 x 3 x 3 quadratic stencil per staggered component, analytic E1, B1 at the
+// particle, relativistic Boris push, move, and Esirkepov deposition on a
+// window of 3 or 4 nodes per axis into an LDS-private FP64 J tile flushed
+// with atomics.  Particles whose stencil leaves the staged region use
+// global memory.
+//
+// The tile shape (TX, TY, TZ) is a compile-time parameter: the staged region
+// (tile + 2 nodes below + 3 above per axis) then has constant strides, so
+// every gather read and every deposit atomic of a particle addresses LDS as
+// one per-particle base plus an immediate offset, and the staging and flush
+// loops decompose node indices with constant divisors.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace apt {
+
+constexpr int kLo3 = 2;   // 3-D halo: no drift margin (LDS budget), sort often
+constexpr int kHi3 = 3;
+
+template <int TX, int TY, int TZ> struct Region3 {
+    static constexpr int RX = TX + kLo3 + kHi3, RY = TY + kLo3 + kHi3, RZ = TZ + kLo3 + kHi3;
+    static constexpr int RXY = RX * RY;
+    static constexpr int RC = RXY * RZ;
+};
+
+template <typename T> AP_D void tsc3w(T d, T w[3]) {
+    const T a = T(0.5) - d, b = T(0.5) + d;
+    w[0] = T(0.5) * a * a;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * b * b;
+}
+
+template <typename T> AP_D void place4w(int o, const T w[3], T out[4]) {
+    const bool z = (o == 0);
+    out[0] = z ? w[0] : T(0);
+    out[1] = z ? w[1] : w[0];
+    out[2] = z ? w[2] : w[1];
+    out[3] = z ? T(0) : w[2];
+}
+
+AP_D int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Periodic image of a staged node coordinate (v >= -kLo3): one subtraction
+// on grids wider than the region, repeated on tiny grids.
+AP_D int wrap_node(int v, int n) {
+    v = v < 0 ? v + n : v;
+    v = v >= n ? v - n : v;
+    if (v >= n) v %= n;   // grids narrower than the staged region only
+    return v;
+}
+
+// 27-point quadratic gather of one component from its LDS block at base
+// (x fastest; rows RX apart, planes RXY apart: constant offsets).
+template <int RX, int RXY, typename T>
+AP_D T gather27(const T *F, int base, const T wx[3], const T wy[3], const T wz[3]) {
+    const T *f = F + base;
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T pl = T(0);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const T *r = f + c * RXY + b * RX;
+            pl += wy[b] * (wx[0] * r[0] + wx[1] * r[1] + wx[2] * r[2]);
+        }
+        acc += wz[c] * pl;
+    }
+    return acc;
+}
+
+// Esirkepov deposition of one particle on a WX x WY x WZ node window whose
+// origin is at LDS index o (constant strides).  An axis of width 3 is exact
+// when no lane of the wave changed its nearest node on it: the fourth
+// weight is zero before and after the move, and so is every current term
+// that involves it.  Esirkepov's W in product form,
+//     W_x(i,j,k) = DS_x[i] A_x(j,k),  A_x = p_y[j] S0_z[k] + q_y[j] DS_z[k],
+//     p = S0 + DS/2,  q = S0/2 + DS/3,
+// makes J_x(i,j,k) = -q w dx/dt sum_{i' <= i} W_x(i',j,k) = C_x[i] A_x(j,k),
+// with C_x the running sum of DS_x (scaled by -q w dx/dt) along x: one FP64
+// product per node.  Likewise J_y, J_z.  In a 4-node window, a lane whose
+// nearest node did not change on that axis has zero terms on the window's
+// rim (last running-sum node along the flux axis, fourth node across it):
+// those atomics run under the mask of the lanes that moved (`wide`).
+template <int RX, int RXY, int RC, int WX, int WY, int WZ, typename T>
+AP_D void deposit3(double *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], const T (&fj)[3],
+                   const bool (&wide)[3]) {
+    constexpr int W[3] = {WX, WY, WZ};
+    // running sums of DS along each axis, scaled, in FP64
+    double C[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            acc += (double)DS[c][m];
+            C[c][m] = acc * (double)fj[c];
+        }
+    }
+    double *J = sJ + o;
+    // component c (flux axis c) with transverse axes (t1, t2): node (a1, a2)
+    // across, m along; strides of the flux and transverse axes
+    auto comp = [&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        constexpr int t1 = c == 0 ? 1 : 0, t2 = c == 2 ? 1 : 2;
+        constexpr int st[3] = {1, RX, RXY};
+        double *Jc = J + c * RC;
+#pragma unroll
+        for (int a2 = 0; a2 < W[t2]; ++a2)
+#pragma unroll
+            for (int a1 = 0; a1 < W[t1]; ++a1) {
+                const bool rim_t = (W[t1] == 4 && a1 == 3) || (W[t2] == 4 && a2 == 3);
+                if (rim_t && !((W[t1] == 4 && a1 == 3 ? wide[t1] : true) && (W[t2] == 4 && a2 == 3 ? wide[t2] : true)))
+                    continue;
+                const T pa = S0[t1][a1] + T(0.5) * DS[t1][a1];
+                const T qa = T(0.5) * S0[t1][a1] + T(1.0 / 3.0) * DS[t1][a1];
+                const double A = (double)(pa * S0[t2][a2] + qa * DS[t2][a2]);
+                double *row = Jc + a2 * st[t2] + a1 * st[t1];
+#pragma unroll
+                for (int m = 0; m < W[c] - 1; ++m) {
+                    if (W[c] == 4 && m == 2 && !wide[c]) continue;
+                    atomic_add(row + m * st[c], C[c][m] * A);
+                }
+            }
+    };
+    comp(std::integral_constant<int, 0>());
+    comp(std::integral_constant<int, 1>());
+    comp(std::integral_constant<int, 2>());
+}
+
+template <typename T, int PT, bool INPLACE, bool PROXY, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
+    using R = Region3<TX, TY, TZ>;
+    constexpr int RX = R::RX, RXY = R::RXY, RC = R::RC;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sF = reinterpret_cast<T *>(smem_raw);
+    double *sJ = reinterpret_cast<double *>(smem_raw + align_lds(6 * RC * sizeof(T)));
+
+    // Block -> tile: the hardware hands consecutive block ids to the 8 XCDs
+    // in turn.  Runs of `xcd_chunk` consecutive tiles along x go to one XCD
+    // and the XCDs take neighbouring runs, so the whole chip sweeps the domain
+    // together (a z-slab of tiles at a time, whose staged data stays in the
+    // shared last-level cache) while each XCD keeps x- and y-neighbour tiles
+    // in its own L2.
+    const int bid = blockIdx.x;
+    const int chunk = a.xcd_chunk;
+    const int grp = (bid >> 3) / chunk, rem = (bid >> 3) - grp * chunk;
+    const int logical = grp * 8 * chunk + (bid & 7) * chunk + rem;
+    if (logical >= a.n_logical) return;
+    const int tile = logical / a.splits;
+    const int split = logical - tile * a.splits;
+    const int tyz = (int)a.fntx.div((unsigned)tile);
+    const int tx = tile - tyz * a.ntile[0];
+    const int tz = (int)a.fntxy.div((unsigned)tile);
+    const int ty = tyz - tz * a.ntile[1];
+    const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int X0 = tx * TX, Y0 = ty * TY, Z0 = tz * TZ;
+    const int ox = X0 - kLo3, oy = Y0 - kLo3, oz = Z0 - kLo3;
+
+    // staged node e -> global node: no periodic wrap for tiles whose region
+    // lies inside the grid (uniform over the block)
+    const bool interior = ox >= 0 && oy >= 0 && oz >= 0 && ox + R::RX <= nx && oy + R::RY <= ny && oz + R::RZ <= nz;
+    const unsigned nxy = (unsigned)nx * (unsigned)ny;
+    const size_t g0 = (size_t)ox + (size_t)nx * ((size_t)oy + (size_t)ny * (size_t)oz);
+    auto global_node = [&](int e) -> size_t {
+        const int lz = e / RXY;
+        const int rr = e - lz * RXY;
+        const int ly = rr / RX;
+        const int lx = rr - ly * RX;
+        if (interior) return g0 + (size_t)((unsigned)lz * nxy + (unsigned)ly * (unsigned)nx + (unsigned)lx);
+        return (size_t)wrap_node(ox + lx, nx) +
+               (size_t)nx * ((size_t)wrap_node(oy + ly, ny) + (size_t)ny * (size_t)wrap_node(oz + lz, nz));
+    };
+    for (int e = threadIdx.x; e < RC; e += blockDim.x) {
+        const size_t g = global_node(e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sF[c * RC + e] = a.E[c][g];
+            sF[(3 + c) * RC + e] = a.B[c][g];
+            sJ[c * RC + e] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    const T dtd[3] = {T(a.dt / a.dx[0]), T(a.dt / a.dx[1]), T(a.dt / a.dx[2])};
+    const int nn[3] = {nx, ny, nz};
+    const int org[3] = {X0, Y0, Z0};
+    constexpr int reg[3] = {R::RX, R::RY, R::RZ};
+    const unsigned ncell = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    // stagger of each component per axis (1 = half node):
+    // Ex(h,n,n) Ey(n,h,n) Ez(n,n,h) Bx(n,h,h) By(h,n,h) Bz(h,h,n)
+    for (int s = 0; s < a.nsp; ++s) {
+        const SpeciesIO<T> &S = a.sp[s];
+        // in-place steps read and write the same arrays (fewer live pointers)
+        const int32_t *cell_in = INPLACE ? S.cell_out : S.cell_in;
+        const T *off_in0 = INPLACE ? S.off_out[0] : S.off_in[0];
+        const T *off_in1 = INPLACE ? S.off_out[1] : S.off_in[1];
+        const T *off_in2 = INPLACE ? S.off_out[2] : S.off_in[2];
+        const T *u_in0 = INPLACE ? S.u_out[0] : S.u_in[0];
+        const T *u_in1 = INPLACE ? S.u_out[1] : S.u_in[1];
+        const T *u_in2 = INPLACE ? S.u_out[2] : S.u_in[2];
+        const T *w_in = INPLACE ? S.w_out : S.w_in;
+        const int beg = S.tile_start[tile];
+        const int cnt = S.tile_start[tile + 1] - beg;
+        const int pb = beg + (int)(((long long)cnt * split) / a.splits);
+        const int pe = beg + (int)(((long long)cnt * (split + 1)) / a.splits);
+        const T kap = T(0.5 * S.q_over_m * a.dt);
+        const T cj[3] = {T(-S.q * a.dx[0] / a.dt), T(-S.q * a.dx[1] / a.dt), T(-S.q * a.dx[2] / a.dt)};
+        for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
+            const int cell = cell_in[p];
+            T off[3];
+            bool ok = (unsigned)cell < ncell;
+            off[0] = off_in0[p];
+            off[1] = off_in1[p];
+            off[2] = off_in2[p];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ok = ok && off[c] >= T(0) && off[c] < T(1);
+            T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
+            const T w = w_in[p];
+            ok = ok && finite_state(ux, uy, uz, w);
+            if (!ok) {
+                count_skipped(a.n_bad, cell);
+                S.cell_out[p] = cell;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) S.off_out[c][p] = off[c];
+                S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
+                if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+                if (PROXY && !INPLACE && S.proxy_out) {
+                    S.proxy_out[2 * p] = S.proxy_in[2 * p];
+                    S.proxy_out[2 * p + 1] = S.proxy_in[2 * p + 1];
+                }
+                continue;
+            }
+            const int row = (int)a.fnx.div((unsigned)cell);
+            const int kk = (int)a.fnxy.div((unsigned)cell);
+            int idx[3];
+            idx[0] = cell - row * nx;
+            idx[1] = row - kk * ny;
+            idx[2] = kk;
+            int loc[3];
+            bool in_lds = true;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int d = idx[c] - org[c];
+                const int h = nn[c] >> 1;
+                if (d < -h) d += nn[c]; else if (d >= nn[c] - h) d -= nn[c];
+                loc[c] = d + kLo3;
+                in_lds = in_lds && loc[c] >= 2 && loc[c] <= reg[c] - 4;
+            }
+            wave_count(a.n_offtile, !in_lds);
+            // weights: node (n) and half-node (h) per axis
+            int nod[3];
+            T wn[3][3], wh[3][3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                nod[c] = off[c] >= T(0.5) ? 1 : 0;
+                tsc3w(off[c] - T(nod[c]), wn[c]);
+                tsc3w(off[c] - T(0.5), wh[c]);
+            }
+            T e2[3], b2[3];
+            if (in_lds) {
+                // stencil starts on the node (n) and half-node (h) lattice of each axis
+                const int xn = loc[0] + nod[0] - 1, xh = loc[0] - 1;
+                const int yn = (loc[1] + nod[1] - 1) * RX, yh = (loc[1] - 1) * RX;
+                const int zn = (loc[2] + nod[2] - 1) * RXY, zh = (loc[2] - 1) * RXY;
+                e2[0] = gather27<RX, RXY>(sF + 0 * RC, xh + yn + zn, wh[0], wn[1], wn[2]);
+                e2[1] = gather27<RX, RXY>(sF + 1 * RC, xn + yh + zn, wn[0], wh[1], wn[2]);
+                e2[2] = gather27<RX, RXY>(sF + 2 * RC, xn + yn + zh, wn[0], wn[1], wh[2]);
+                b2[0] = gather27<RX, RXY>(sF + 3 * RC, xn + yh + zh, wn[0], wh[1], wh[2]);
+                b2[1] = gather27<RX, RXY>(sF + 4 * RC, xh + yn + zh, wh[0], wn[1], wh[2]);
+                b2[2] = gather27<RX, RXY>(sF + 5 * RC, xh + yh + zn, wh[0], wh[1], wn[2]);
+            } else {
+                auto gath = [&](int comp, int sx, int sy, int sz) {
+                    const T *wx = sx ? wh[0] : wn[0];
+                    const T *wy = sy ? wh[1] : wn[1];
+                    const T *wz = sz ? wh[2] : wn[2];
+                    const int bx = sx ? -1 : nod[0] - 1;
+                    const int by = sy ? -1 : nod[1] - 1;
+                    const int bz = sz ? -1 : nod[2] - 1;
+                    const T *F = comp < 3 ? a.E[comp] : a.B[comp - 3];
+                    int gx[3];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) gx[m] = wrap3(idx[0] + bx + m, nx);
+                    T acc = T(0);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const size_t gz = (size_t)wrap3(idx[2] + bz + c, nz) * ny;
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const size_t rbase = (gz + (size_t)wrap3(idx[1] + by + b, ny)) * nx;
+                            acc += wz[c] * wy[b] * (wx[0] * F[rbase + gx[0]] + wx[1] * F[rbase + gx[1]] +
+                                                    wx[2] * F[rbase + gx[2]]);
+                        }
+                    }
+                    return acc;
+                };
+                e2[0] = gath(0, 1, 0, 0);
+                e2[1] = gath(1, 0, 1, 0);
+                e2[2] = gath(2, 0, 0, 1);
+                b2[0] = gath(3, 0, 1, 1);
+                b2[1] = gath(4, 1, 0, 1);
+                b2[2] = gath(5, 1, 1, 0);
+            }
+
+            T e1[3], b1[3];
+            const double X = a.x_min[0] + ((double)idx[0] + (double)off[0]) * a.dx[0];
+            const double Y = a.x_min[1] + ((double)idx[1] + (double)off[1]) * a.dx[1];
+            const double Z = a.x_min[2] + ((double)idx[2] + (double)off[2]) * a.dx[2];
+            analytic_field<PT, T>(a.W, X, Y, Z, e1, b1);
+            const T Ex = e1[0] + e2[0], Ey = e1[1] + e2[1], Ez = e1[2] + e2[2];
+            const T Bx = b1[0] + b2[0], By = b1[1] + b2[1], Bz = b1[2] + b2[2];
+
+            // ---- relativistic Boris push
+            const T u0x = ux, u0y = uy, u0z = uz;
+            const T umx = ux + kap * Ex, umy = uy + kap * Ey, umz = uz + kap * Ez;
+            const T ig = rsqrt_r<T>(T(1) + umx * umx + umy * umy + umz * umz);
+            const T tx_ = kap * Bx * ig, ty_ = kap * By * ig, tz_ = kap * Bz * ig;
+            const T sf = T(2) / (T(1) + tx_ * tx_ + ty_ * ty_ + tz_ * tz_);
+            const T upx = umx + (umy * tz_ - umz * ty_);
+            const T upy = umy + (umz * tx_ - umx * tz_);
+            const T upz = umz + (umx * ty_ - umy * tx_);
+            ux = umx + sf * (upy * tz_ - upz * ty_) + kap * Ex;
+            uy = umy + sf * (upz * tx_ - upx * tz_) + kap * Ey;
+            uz = umz + sf * (upx * ty_ - upy * tx_) + kap * Ez;
+            if constexpr (PROXY) {
+                if (S.proxy_out) {
+                    const T uv0[3] = {u0x, u0y, u0z}, uv1[3] = {ux, uy, uz};
+                    const T Ev[3] = {Ex, Ey, Ez}, Bv[3] = {Bx, By, Bz};
+                    proxy_accumulate<T>((INPLACE ? S.proxy_out : S.proxy_in) + 2 * p, S.proxy_out + 2 * p, uv0, uv1,
+                                        Ev, Bv, T(a.dt));
+                }
+            }
+
+            const T ign = rsqrt_r<T>(T(1) + ux * ux + uy * uy + uz * uz);
+            const T uu[3] = {ux, uy, uz};
+            T nof[3];
+            int sh[3];
+            bool fast = false;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T d = uu[c] * ign * dtd[c];
+                if (!push_move_ok(ign, d)) { d = T(0); fast = true; }
+                T no = off[c] + d;
+                int sc = (int)floor_r<T>(no);
+                no -= T(sc);
+                if (no >= T(1)) { no -= T(1); sc += 1; }
+                nof[c] = no;
+                sh[c] = sc;
+            }
+            if (fast) atomicAdd(a.n_fast, 1ull);
+
+            // Esirkepov on a window relative to the old cell
+            T S0[3][4], DS[3][4];
+            int base[3];
+            bool wide[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int n1 = sh[c] + (nof[c] >= T(0.5) ? 1 : 0);
+                wide[c] = n1 != nod[c];
+                T w1[3];
+                tsc3w(nof[c] - T(n1 - sh[c]), w1);
+                base[c] = min(nod[c], n1) - 1;
+                T s1[4];
+                place4w(nod[c] - 1 - base[c], wn[c], S0[c]);
+                place4w(n1 - 1 - base[c], w1, s1);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) DS[c][m] = s1[m] - S0[c][m];
+            }
+            const T fj[3] = {cj[0] * w, cj[1] * w, cj[2] * w};
+            if (in_lds) {
+                // window width per axis, uniform over the wave
+                const int o = (loc[2] + base[2]) * RXY + (loc[1] + base[1]) * RX + loc[0] + base[0];
+                const int wmask = (__any(wide[0]) ? 1 : 0) | (__any(wide[1]) ? 2 : 0) | (__any(wide[2]) ? 4 : 0);
+                switch (wmask) {
+                case 0: deposit3<RX, RXY, RC, 3, 3, 3>(sJ, o, S0, DS, fj, wide); break;
+                case 1: deposit3<RX, RXY, RC, 4, 3, 3>(sJ, o, S0, DS, fj, wide); break;
+                case 2: deposit3<RX, RXY, RC, 3, 4, 3>(sJ, o, S0, DS, fj, wide); break;
+                case 3: deposit3<RX, RXY, RC, 4, 4, 3>(sJ, o, S0, DS, fj, wide); break;
+                case 4: deposit3<RX, RXY, RC, 3, 3, 4>(sJ, o, S0, DS, fj, wide); break;
+                case 5: deposit3<RX, RXY, RC, 4, 3, 4>(sJ, o, S0, DS, fj, wide); break;
+                case 6: deposit3<RX, RXY, RC, 3, 4, 4>(sJ, o, S0, DS, fj, wide); break;
+                default: deposit3<RX, RXY, RC, 4, 4, 4>(sJ, o, S0, DS, fj, wide); break;
+                }
+            } else {
+                const T third = T(1.0 / 3.0);
+                auto addJ = [&](int comp, int i4, int j4, int k4, T v) {
+                    if (v == T(0)) return;
+                    const int gx = wrap3(idx[0] + base[0] + i4, nx);
+                    const int gy = wrap3(idx[1] + base[1] + j4, ny);
+                    const int gz = wrap3(idx[2] + base[2] + k4, nz);
+                    atomic_add(&a.Jacc[comp][(size_t)gx + (size_t)nx * ((size_t)gy + (size_t)ny * gz)], (double)v);
+                };
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                    for (int j4 = 0; j4 < 4; ++j4) {
+                        const T cyz = S0[1][j4] * S0[2][k4] + T(0.5) * DS[1][j4] * S0[2][k4] +
+                                      T(0.5) * S0[1][j4] * DS[2][k4] + third * DS[1][j4] * DS[2][k4];
+                        T cum = T(0);
+#pragma unroll
+                        for (int i4 = 0; i4 < 3; ++i4) {
+                            cum += DS[0][i4] * cyz;
+                            addJ(0, i4, j4, k4, fj[0] * cum);
+                        }
+                    }
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4)
+#pragma unroll
+                    for (int i4 = 0; i4 < 4; ++i4) {
+                        const T cxz = S0[0][i4] * S0[2][k4] + T(0.5) * DS[0][i4] * S0[2][k4] +
+                                      T(0.5) * S0[0][i4] * DS[2][k4] + third * DS[0][i4] * DS[2][k4];
+                        T cum = T(0);
+#pragma unroll
+                        for (int j4 = 0; j4 < 3; ++j4) {
+                            cum += DS[1][j4] * cxz;
+                            addJ(1, i4, j4, k4, fj[1] * cum);
+                        }
+                    }
+#pragma unroll
+                for (int j4 = 0; j4 < 4; ++j4)
+#pragma unroll
+                    for (int i4 = 0; i4 < 4; ++i4) {
+                        const T cxy = S0[0][i4] * S0[1][j4] + T(0.5) * DS[0][i4] * S0[1][j4] +
+                                      T(0.5) * S0[0][i4] * DS[1][j4] + third * DS[0][i4] * DS[1][j4];
+                        T cum = T(0);
+#pragma unroll
+                        for (int k4 = 0; k4 < 3; ++k4) {
+                            cum += DS[2][k4] * cxy;
+                            addJ(2, i4, j4, k4, fj[2] * cum);
+                        }
+                    }
+            }
+
+            int ni[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ni[c] = wrap3(idx[c] + sh[c], nn[c]);
+            S.cell_out[p] = ni[0] + nx * (ni[1] + ny * ni[2]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.off_out[c][p] = nof[c];
+            S.u_out[0][p] = ux;
+            S.u_out[1][p] = uy;
+            S.u_out[2][p] = uz;
+            if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+        }
+    }
+    __syncthreads();
+
+    for (int e = threadIdx.x; e < RC; e += blockDim.x) {
+        const size_t g = global_node(e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = sJ[c * RC + e];
+            if (v != 0.0) atomic_add(&a.Jacc[c][g], v);
+        }
+    }
+}
+
+template <int TX, int TY, int TZ> constexpr size_t lds3(size_t real) {
+    return align_lds(6 * (size_t)Region3<TX, TY, TZ>::RC * real) +
+           3 * (size_t)Region3<TX, TY, TZ>::RC * sizeof(double);
+}
+
+template <typename T, int PT, int TX, int TY, int TZ>
+hipError_t launch3d_shape(const PushArgs<T> &a, int threads, hipStream_t s) {
+    if (a.n_logical == 0) return hipSuccess;
+    const size_t lds = lds3<TX, TY, TZ>(sizeof(T));
+    const int per = 8 * a.xcd_chunk;
+    const int blocks = ((a.n_logical + per - 1) / per) * per;
+    const bool inplace = a.sp[0].copy_static == 0;
+    bool proxy = false;
+    for (int k = 0; k < a.nsp; ++k) proxy = proxy || a.sp[k].proxy_out != nullptr;
+    if (inplace && !proxy)
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, true, false, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
+                           a);
+    else if (!proxy)
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, false, false, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
+                           a);
+    else if (inplace)
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, true, true, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
+                           a);
+    else
+        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, false, true, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
+                           a);
+    return hipGetLastError();
+}
+
+// Every pulse family of one tile shape (instantiated per shape in its own
+// translation unit: push3d_t844.hip, push3d_t884.hip, push3d_t888.hip).
+template <typename T, int TX, int TY, int TZ>
+hipError_t launch3d_tile(int pulse, const PushArgs<T> &a, int threads, hipStream_t s) {
+    switch (pulse) {
+    case PT_NONE: return launch3d_shape<T, PT_NONE, TX, TY, TZ>(a, threads, s);
+    case PT_PLANE: return launch3d_shape<T, PT_PLANE, TX, TY, TZ>(a, threads, s);
+    case PT_GAUSS: return launch3d_shape<T, PT_GAUSS, TX, TY, TZ>(a, threads, s);
+    case PT_LG: return launch3d_shape<T, PT_LG, TX, TY, TZ>(a, threads, s);
+    case PT_FF: return launch3d_shape<T, PT_FF, TX, TY, TZ>(a, threads, s);
+    case PT_NP: return launch3d_shape<T, PT_NP, TX, TY, TZ>(a, threads, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace apt

@@ -7,11 +7,23 @@ exactly representable in FP32 so that the FP32 and FP64 paths and the oracle
 see bit-identical initial states.
 
 Random numbers come from NumPy's Philox-4x32-10 counter-based generator
-(Salmon et al. 2011), one stream per (seed, species).
+(Salmon et al. 2011), one stream per (seed, species).  ``plasma_device``
+draws the same recipe on the GPU with torch's Philox generator (for inputs of
+a billion particles, which the host would take minutes to draw); its streams
+differ from NumPy's, so runs started from it are checked against the oracle
+on sampled particles, from the GPU's own state.
 """
 import math
 
 import numpy as np
+
+
+def _xp(x):
+    """Array module of x: numpy, or torch for torch tensors (device inputs)."""
+    if type(x).__module__.split(".")[0] == "torch":
+        import torch
+        return torch
+    return np
 
 ELECTRON_REST_EV = 510998.95
 PROTON_MASS = 1836.15267343
@@ -29,12 +41,12 @@ def _unit_offsets(rng, n):
 
 
 def density_uniform(n0):
-    return lambda x, y, z: np.full_like(x, n0)
+    return lambda x, y, z: _xp(x).full_like(x, n0)
 
 
 def density_ramp_x(n0, x_start, length):
     """n = n0 * min(1, (x - x_start)/length) for x >= x_start, else 0 (lambda units)."""
-    return lambda x, y, z: n0 * np.clip((x - x_start) / length, 0.0, 1.0)
+    return lambda x, y, z: n0 * _xp(x).clip((x - x_start) / length, 0.0, 1.0)
 
 
 def pad_free(state, n_free, first_id):
@@ -66,12 +78,12 @@ def window_column(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, s
 
 def density_slab_x(n0, x0, x1):
     """n = n0 for x0 <= x < x1, else 0 (lambda units)."""
-    return lambda x, y, z: np.where((x >= x0) & (x < x1), n0, 0.0)
+    return lambda x, y, z: n0 * ((x >= x0) & (x < x1))
 
 
 def density_gauss_channel(n0, radius, y_axis, z_axis):
     """n = n0 exp(-r_perp^2 / radius^2) about the axis (y_axis, z_axis)."""
-    return lambda x, y, z: n0 * np.exp(-((y - y_axis) ** 2 + (z - z_axis) ** 2) / radius ** 2)
+    return lambda x, y, z: n0 * _xp(x).exp(-((y - y_axis) ** 2 + (z - z_axis) ** 2) / radius ** 2)
 
 
 def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
@@ -114,6 +126,52 @@ def plasma(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed,
     ys = (x_min[1] + (j + off[1].astype(np.float64)) * dx[1]) if dim == 3 else np.zeros(N)
     zs = x_min[2] + (k + off[2].astype(np.float64)) * dx[2]
     w = (density(xs, ys, zs) / ppc).astype(np.float32)
+    return {"cell": cell, "off": off, "u": u, "w": w}
+
+
+def plasma_device(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed, stream=0,
+                  positions_from=None, device="cuda", chunk=1 << 26):
+    """The recipe of ``plasma`` (every cell filled with ``ppc`` particles,
+    offsets uniform in [0, 1), Maxwellian momenta, weights n(x_p)/ppc, cell by
+    cell) drawn on a torch device with torch's Philox-4x32-10 generator keyed
+    by (seed, stream).  Returns device tensors (cell int32, off float32
+    (3, N), u float32 (3, N), w float32 (N,)).  ``positions_from`` reuses
+    another species' cells and offsets (co-located ions; they are cloned).
+    Work proceeds in chunks of ``chunk`` particles to bound the temporaries."""
+    import torch
+    nx, ny, nz = n_cells
+    if dim in (1, 2):
+        ny = 1
+    ncell = nx * ny * nz
+    N = ncell * ppc
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) * 1000003 + int(stream))
+    sigma = math.sqrt(temperature_ev / (ELECTRON_REST_EV * mass))
+    if positions_from is None:
+        cell = torch.arange(ncell, dtype=torch.int32, device=dev).repeat_interleave(ppc)
+        off = torch.zeros((3, N), dtype=torch.float32, device=dev)
+        axes = (0, 1, 2) if dim == 3 else ((0, 2) if dim == 2 else (0,))
+        for a in axes:
+            torch.rand(N, generator=gen, dtype=torch.float32, device=dev, out=off[a])
+    else:
+        cell = positions_from["cell"].clone()
+        off = positions_from["off"].clone()
+    u = torch.empty((3, N), dtype=torch.float32, device=dev)
+    for a in range(3):
+        torch.randn(N, generator=gen, dtype=torch.float32, device=dev, out=u[a])
+    u *= sigma
+    w = torch.empty(N, dtype=torch.float32, device=dev)
+    for b in range(0, N, chunk):
+        e = min(N, b + chunk)
+        c = cell[b:e].to(torch.int64)
+        i = c % nx
+        j = (c // nx) % ny
+        k = c // (nx * ny)
+        xs = x_min[0] + (i + off[0, b:e].double()) * dx[0]
+        ys = (x_min[1] + (j + off[1, b:e].double()) * dx[1]) if dim == 3 else torch.zeros_like(xs)
+        zs = x_min[2] + (k + off[2, b:e].double()) * dx[2]
+        w[b:e] = (density(xs, ys, zs) / ppc).float()
     return {"cell": cell, "off": off, "u": u, "w": w}
 
 

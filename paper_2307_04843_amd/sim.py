@@ -186,8 +186,16 @@ class Simulation:
         out["u"] = np.stack([a["u"][k].cpu().numpy()[order] for k in range(3)])
         out["w"] = a["w"].cpu().numpy()[order]
         if a["proxy"] is not None:
-            pr = a["proxy"].cpu().numpy().reshape(-1, 2)
-            out["proxy"] = (pr[:, 0].astype(np.float64) - pr[:, 1])[order]   # sum minus its compensation
+            out["proxy"] = self.proxy_values(i).cpu().numpy()[order]
+        return out
+
+    def proxy_values(self, i):
+        """Per-particle emission proxies of species i (FP64 device tensor, slot
+        order), read out by the library (ap_read_proxy)."""
+        n = self.sp_desc[i].n
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        apt.ap_read_proxy(self.ctx, i, out.data_ptr())
+        torch.cuda.synchronize(self.device)
         return out
 
     def close(self):
