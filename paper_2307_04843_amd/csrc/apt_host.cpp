@@ -64,6 +64,9 @@ struct WorkLayout {
     size_t count[kMaxSpecies] = {}, start[kMaxSpecies] = {}, rank[kMaxSpecies] = {};
     size_t alt_cell[kMaxSpecies] = {}, alt_off[kMaxSpecies][3] = {}, alt_u[kMaxSpecies][3] = {};
     size_t alt_w[kMaxSpecies] = {}, alt_id[kMaxSpecies] = {}, alt_proxy[kMaxSpecies] = {};
+    // fused re-sort (3-D): re-sort keys written by the push, the permutation
+    // the next push reads through, entering and staying counts per tile
+    size_t key[kMaxSpecies] = {}, perm[kMaxSpecies] = {}, mcount[kMaxSpecies] = {}, stay[kMaxSpecies] = {};
 };
 
 constexpr int kDiagBlocks = 512;
@@ -174,7 +177,9 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         int sp_ = (int)std::ceil(avg / target);
         if (sp_ < 1) sp_ = 1;
         if (sp_ > 64) sp_ = 64;
-        s.splits = sp_;
+        // 3-D: one workgroup per tile (the fused re-sort counts a tile's
+        // staying particles in its workgroup)
+        s.splits = s.dim == 3 ? 1 : sp_;
     }
     *out = s;
     return AP_OK;
@@ -225,6 +230,12 @@ WorkLayout make_layout(const RunShape &s) {
             L.alt_id[i] = take(N * 4);
             // the proxy's (sum, compensation) pair follows its particle through re-sorts
             if (s.options & AP_GRID_PROXY) L.alt_proxy[i] = take(N * 2 * s.real);
+            if (s.dim == 3) {
+                L.key[i] = take(N * 4);
+                L.perm[i] = take(N * 4);
+                L.mcount[i] = take((size_t)s.ntiles * 4);
+                L.stay[i] = take((size_t)s.ntiles * 4);
+            }
         }
     }
     if (s.dim == 0) {
@@ -354,6 +365,12 @@ struct ap_ctx {
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
+    // fused re-sort (3-D): within an ap_step call the particle state moves
+    // between the caller's arrays and the workspace copy every step; it is
+    // back in the caller's arrays when the call returns
+    bool state_alt = false;      // the current state is in the workspace copy
+    bool keys_valid = false;     // the last push wrote re-sort keys for the current state
+    bool no_fuse = false;        // full re-sorts only (reverse-sweep replays)
     bool timing = false;
     std::vector<TimedPair> pending;
     std::vector<hipEvent_t> pool;
@@ -399,6 +416,14 @@ struct Timer {
     }
 };
 
+// Full re-sorts only while a reverse sweep replays segments (its replay
+// slots copy the caller's arrays at every step).
+struct NoFuse {
+    ap_ctx *c;
+    explicit NoFuse(ap_ctx *c_) : c(c_) { c->no_fuse = true; }
+    ~NoFuse() { c->no_fuse = false; }
+};
+
 ap_status hip_fail(hipError_t e, const char *where) {
     return fail(AP_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
@@ -410,6 +435,7 @@ ap_status hip_fail(hipError_t e, const char *where) {
     } while (0)
 
 template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags);
+template <typename T> ap_status restore_primary(ap_ctx *c);
 template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *inject);
 template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
 template <typename T>
@@ -730,19 +756,21 @@ ap_status ap_step(ap_ctx *c, int64_t n_steps, uint32_t flags) {
         c->rec_n = 0;   // any unrecorded step invalidates the recording
     }
     try {
-        for (int64_t k = 0; k < n_steps; ++k) {
-            ap_status st;
+        ap_status st = AP_OK;
+        for (int64_t k = 0; k < n_steps && st == AP_OK; ++k) {
             if (c->s.dim == 0)
                 st = c->s.prec == AP_F64 ? step_gridless<double>(c, flags) : step_gridless<float>(c, flags);
             else
                 st = c->s.prec == AP_F64 ? step_gridded<double>(c, flags) : step_gridded<float>(c, flags);
-            if (st != AP_OK) return st;
-            c->step++;
+            if (st == AP_OK) c->step++;
         }
+        // the caller's arrays hold the state when the call returns
+        const ap_status sr = c->s.dim == 0 ? AP_OK
+                                           : (c->s.prec == AP_F64 ? restore_primary<double>(c) : restore_primary<float>(c));
+        return st != AP_OK ? st : sr;
     } catch (...) {
         return fail(AP_E_NOMEM, "host allocation failed");
     }
-    return AP_OK;
 }
 
 ap_status ap_get_time(const ap_ctx *c, double *t, int64_t *step) {
@@ -1278,6 +1306,7 @@ template <typename T> ap_status save_replay(ap_ctx *c, unsigned char *slot, int 
 template <typename T>
 ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
                         double *out) {
+    const NoFuse nf(c);
     const RunShape &s = c->s;
     const GridCkpt G = grid_ckpt(s);
     const int n = (int)s.np[sp];
@@ -1381,6 +1410,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
 template <typename T>
 ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
                            double *out) {
+    const NoFuse nf(c);
     const RunShape &s = c->s;
     const GridCkpt G = grid_ckpt(s);
     const size_t nc = (size_t)s.ncell;
@@ -1614,9 +1644,25 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             if (st != AP_OK) return st;
         }
     }
-    const bool do_sort = !c->sorted_once || c->need_sort || (c->step % s.sort_every) == 0;
+    // Re-sort.  1-D and 2-D runs (and recording or replaying steps) sort in
+    // full every sort_every steps and push in place between sorts.  3-D runs
+    // sort in full once; afterwards each push writes, per particle, its rank
+    // in the tile of its new cell, and the next step builds from those ranks
+    // the permutation its push reads through, writing the particles in tile
+    // order into the other buffer (caller's arrays / workspace copy).
+    const bool fuse = s.dim == 3 && !(flags & AP_STEP_RECORD) && !c->no_fuse;
+    if (!fuse && c->state_alt) {
+        const ap_status st = restore_primary<T>(c);
+        if (st != AP_OK) return st;
+    }
+    const bool do_sort = !c->sorted_once || c->need_sort || (fuse ? !c->keys_valid : (c->step % s.sort_every) == 0);
+    const bool from_perm = fuse && !do_sort;
     bool from_alt = false;
     if (do_sort) {
+        if (c->state_alt) {
+            const ap_status st = restore_primary<T>(c);
+            if (st != AP_OK) return st;
+        }
         Timer tm(c, 2);
         for (int i = 0; i < s.nsp; ++i) {
             const ap_particles &p = c->buf.sp[i];
@@ -1681,7 +1727,48 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         c->sorted_once = true;
         c->need_sort = false;
         from_alt = true;
+    } else if (from_perm) {
+        // the permutation from the ranks the last push wrote (into the buffer holding the state)
+        Timer tm(c, 2);
+        for (int i = 0; i < s.nsp; ++i) {
+            int32_t *count = c->wp<int32_t>(L.count[i]);
+            int32_t *start = c->wp<int32_t>(L.start[i]);
+            const int32_t *stay = c->wp<int32_t>(L.stay[i]);
+            HIPCHK(launch_resort_counts(stay, c->wp<int32_t>(L.mcount[i]), count, (int32_t)s.ntiles, c->stream),
+                   "re-sort counts");
+            HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(L.scan_part), c->stream), "tile scan");
+            PermArgs pa{};
+            pa.cell = c->state_alt ? c->wp<int32_t>(L.alt_cell[i]) : c->buf.sp[i].cell;
+            pa.key = c->wp<int32_t>(L.key[i]);
+            pa.start = start;
+            pa.stay = stay;
+            // mover ranks: the entering counts are no longer needed once summed
+            pa.mrank = c->wp<int32_t>(L.mcount[i]);
+            HIPCHK(launch_fill_zero<int32_t>(pa.mrank, (size_t)s.ntiles, c->stream), "re-sort counts");
+            pa.perm = c->wp<int32_t>(L.perm[i]);
+            pa.ncell = (uint32_t)s.ncell;
+            pa.n = (int)s.np[i];
+            pa.dim = s.dim;
+            pa.fnx = fnx;
+            pa.fnxy = fnxy;
+            pa.ftx = FastDiv((uint32_t)s.tile[0]);
+            pa.fty = FastDiv((uint32_t)s.tile[1]);
+            pa.ftz = FastDiv((uint32_t)s.tile[2]);
+            for (int k = 0; k < 3; ++k) pa.ntile[k] = s.ntile[k];
+            HIPCHK(launch_resort_perm(pa, c->stream), "re-sort permutation");
+        }
     }
+    if (fuse) {
+        // this push counts the particles entering each tile
+        Timer tm(c, 2);
+        for (int i = 0; i < s.nsp; ++i)
+            HIPCHK(launch_fill_zero<int32_t>(c->wp<int32_t>(L.mcount[i]), (size_t)s.ntiles, c->stream), "re-sort counts");
+    }
+    // buffers the push reads and writes: after a full sort, the sorted
+    // workspace copy -> caller's arrays; fused 3-D steps, the buffer holding
+    // the state -> the other one; otherwise in place
+    const bool in_alt = from_alt || (from_perm && c->state_alt);
+    const bool out_alt = from_perm && !c->state_alt;
     PushArgs<T> a{};
     a.nsp = s.nsp;
     for (int i = 0; i < s.nsp; ++i) {
@@ -1689,21 +1776,29 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         SpeciesIO<T> &io = a.sp[i];
         for (int k = 0; k < 3; ++k) {
             const bool act = axis_active(s.dim, k);
-            io.off_out[k] = act ? static_cast<T *>(p.off[k]) : nullptr;
-            io.u_out[k] = static_cast<T *>(p.u[k]);
-            io.off_in[k] = from_alt ? (act ? c->wp<T>(L.alt_off[i][k]) : nullptr) : io.off_out[k];
-            io.u_in[k] = from_alt ? c->wp<T>(L.alt_u[i][k]) : io.u_out[k];
+            T *pr_off = act ? static_cast<T *>(p.off[k]) : nullptr;
+            T *al_off = act ? c->wp<T>(L.alt_off[i][k]) : nullptr;
+            io.off_out[k] = out_alt ? al_off : pr_off;
+            io.u_out[k] = out_alt ? c->wp<T>(L.alt_u[i][k]) : static_cast<T *>(p.u[k]);
+            io.off_in[k] = in_alt ? al_off : pr_off;
+            io.u_in[k] = in_alt ? c->wp<T>(L.alt_u[i][k]) : static_cast<T *>(p.u[k]);
         }
-        io.cell_out = p.cell;
-        io.w_out = static_cast<T *>(p.w);
-        io.id_out = p.id;
-        io.cell_in = from_alt ? c->wp<int32_t>(L.alt_cell[i]) : p.cell;
-        io.w_in = from_alt ? c->wp<T>(L.alt_w[i]) : io.w_out;
-        io.id_in = from_alt ? c->wp<int32_t>(L.alt_id[i]) : p.id;
-        io.copy_static = from_alt ? 1 : 0;
-        io.proxy_out = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
-        io.proxy_in = s.has_proxy[i] && from_alt ? c->wp<T>(L.alt_proxy[i]) : io.proxy_out;
+        io.cell_out = out_alt ? c->wp<int32_t>(L.alt_cell[i]) : p.cell;
+        io.w_out = out_alt ? c->wp<T>(L.alt_w[i]) : static_cast<T *>(p.w);
+        io.id_out = out_alt ? c->wp<int32_t>(L.alt_id[i]) : p.id;
+        io.cell_in = in_alt ? c->wp<int32_t>(L.alt_cell[i]) : p.cell;
+        io.w_in = in_alt ? c->wp<T>(L.alt_w[i]) : static_cast<T *>(p.w);
+        io.id_in = in_alt ? c->wp<int32_t>(L.alt_id[i]) : p.id;
+        io.copy_static = (from_alt || from_perm) ? 1 : 0;
+        T *pr_proxy = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
+        T *al_proxy = s.has_proxy[i] ? c->wp<T>(L.alt_proxy[i]) : nullptr;
+        io.proxy_out = out_alt ? al_proxy : pr_proxy;
+        io.proxy_in = in_alt ? al_proxy : pr_proxy;
         io.tile_start = c->wp<int32_t>(L.start[i]);
+        io.perm = from_perm ? c->wp<int32_t>(L.perm[i]) : nullptr;
+        io.key_out = fuse ? c->wp<int32_t>(L.key[i]) : nullptr;
+        io.mcount = fuse ? c->wp<int32_t>(L.mcount[i]) : nullptr;
+        io.stay = fuse ? c->wp<int32_t>(L.stay[i]) : nullptr;
         io.n = (int)s.np[i];
         io.q_over_m = s.q[i] / s.m[i];
         io.q = s.q[i];
@@ -1801,6 +1896,8 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
                                   : launch_push_deposit_3d<T>(push_pulse, a, 256, c->stream);
         if (e != hipSuccess) return hip_fail(e, "push/deposit");
         for (int i = 0; i < s.nsp; ++i) c->push_since_read += s.np[i];
+        c->keys_valid = fuse;
+        c->state_alt = out_alt;
     }
     if (s.prec == AP_F32) {
         // one rounding of the FP64 sum per node keeps continuity at FP32 round-off
@@ -1858,6 +1955,37 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         }
         HIPCHK(launch_yee<T>(s.dim, F, yb, (flags & AP_STEP_NO_YEE) ? 1 : 0, c->stream), "yee");
     }
+    return AP_OK;
+}
+
+// The particle state back from the workspace copy into the caller's arrays
+// (fused 3-D re-sort); the re-sort keys stay valid (same slots).
+template <typename T> ap_status restore_primary(ap_ctx *c) {
+    if (!c->state_alt) return AP_OK;
+    const RunShape &s = c->s;
+    const WorkLayout &L = c->L;
+    for (int i = 0; i < s.nsp; ++i) {
+        const size_t N = (size_t)s.np[i];
+        if (N == 0) continue;
+        const ap_particles &p = c->buf.sp[i];
+        HIPCHK(hipMemcpyAsync(p.cell, c->wp<int32_t>(L.alt_cell[i]), N * 4, hipMemcpyDeviceToDevice, c->stream),
+               "restore state");
+        HIPCHK(hipMemcpyAsync(p.id, c->wp<int32_t>(L.alt_id[i]), N * 4, hipMemcpyDeviceToDevice, c->stream),
+               "restore state");
+        for (int k = 0; k < 3; ++k) {
+            if (axis_active(s.dim, k))
+                HIPCHK(hipMemcpyAsync(p.off[k], c->wp<T>(L.alt_off[i][k]), N * sizeof(T), hipMemcpyDeviceToDevice,
+                                      c->stream), "restore state");
+            HIPCHK(hipMemcpyAsync(p.u[k], c->wp<T>(L.alt_u[i][k]), N * sizeof(T), hipMemcpyDeviceToDevice, c->stream),
+                   "restore state");
+        }
+        HIPCHK(hipMemcpyAsync(p.w, c->wp<T>(L.alt_w[i]), N * sizeof(T), hipMemcpyDeviceToDevice, c->stream),
+               "restore state");
+        if (s.has_proxy[i])
+            HIPCHK(hipMemcpyAsync(p.proxy, c->wp<T>(L.alt_proxy[i]), 2 * N * sizeof(T), hipMemcpyDeviceToDevice,
+                                  c->stream), "restore state");
+    }
+    c->state_alt = false;
     return AP_OK;
 }
 

@@ -578,6 +578,35 @@ template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStre
 template hipError_t launch_scatter<float>(const ScatterArgs<float> &, hipStream_t);
 template hipError_t launch_scatter<double>(const ScatterArgs<double> &, hipStream_t);
 
+__global__ __launch_bounds__(256) void k_resort_counts(const int32_t *stay, const int32_t *mcount, int32_t *count,
+                                                        int32_t n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) count[t] = stay[t] + mcount[t];
+}
+
+hipError_t launch_resort_counts(const int32_t *stay, const int32_t *mcount, int32_t *count, int32_t n_tiles,
+                                hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resort_counts, dim3((n_tiles + 255) / 256), dim3(256), 0, s, stay, mcount, count, n_tiles);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_resort_perm(PermArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int cell = a.cell[p];
+    const int t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+    const int k = a.key[p];
+    const int slot = k >= 0 ? k : a.stay[t] + atomicAdd(&a.mrank[t], 1);
+    a.perm[a.start[t] + slot] = p;
+}
+
+hipError_t launch_resort_perm(const PermArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_resort_perm, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // FP64 diagnostics
 // ---------------------------------------------------------------------------

@@ -31,6 +31,15 @@ template <typename T> struct SpeciesIO {
     T *proxy_out;
     const int32_t *tile_start;   // [n_tiles + 1]
     int32_t copy_static;         // write w and id (source != destination)
+    // fused re-sort (3-D): the particle of output slot j is read from input
+    // slot perm[j] (perm null: j); key_out[j] (null: none) gets its rank in
+    // the tile of its new cell when that is this block's tile, else -1;
+    // mcount[t] counts the particles entering tile t (atomics) and stay[t]
+    // those staying in it (written by tile t's block)
+    const int32_t *perm;
+    int32_t *key_out;
+    int32_t *mcount;
+    int32_t *stay;
     int32_t n;
     double q_over_m;
     double q;
@@ -274,6 +283,27 @@ template <typename T> struct ScatterArgs {
     int32_t ntile[3];
 };
 template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStream_t s);
+
+// Fused re-sort: count[t] = stay[t] + mcount[t] (input of the tile scan).
+hipError_t launch_resort_counts(const int32_t *stay, const int32_t *mcount, int32_t *count, int32_t n_tiles,
+                                hipStream_t s);
+// Fused re-sort: perm[start[t] + rank] = p for every particle p of the
+// buffer the last push wrote (cell, key as written by it), with stayers
+// first in each tile (their key is the rank) and the particles entering it
+// after them (key -1; ranks handed out by atomics on mrank, zeroed).
+struct PermArgs {
+    const int32_t *cell;
+    const int32_t *key;
+    const int32_t *start;
+    const int32_t *stay;
+    int32_t *mrank;
+    int32_t *perm;
+    uint32_t ncell;
+    int32_t n, dim;
+    FastDiv fnx, fnxy, ftx, fty, ftz;
+    int32_t ntile[3];
+};
+hipError_t launch_resort_perm(const PermArgs &a, hipStream_t s);
 
 // diagnostics
 constexpr int kDiagVals = 16;    // per-species partial-sum slots

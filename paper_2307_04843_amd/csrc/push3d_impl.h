@@ -28,6 +28,24 @@ template <int TX, int TY, int TZ> struct Region3 {
     static constexpr int RC = RXY * RZ;
 };
 
+// Accumulator of the LDS current tile.  FP64 runs add FP64.  FP32 runs add
+// int64 fixed point with a power-of-two scale chosen per block (every
+// contribution below 2^50 units, the node sums below 2^62): integer LDS
+// atomics run faster than FP64 ones, and the tile's sums are exact and
+// independent of the order of the atomics; the quantum is 2^-50 of the
+// block's largest |q w| dx/dt, far below FP32 rounding.
+template <typename T> struct JTile { using type = double; };
+template <> struct JTile<float> { using type = unsigned long long; };
+
+AP_D void lds_add(double *p, double c, double a) { atomic_add(p, c * a); }
+AP_D void lds_add(unsigned long long *p, double c, double a) {
+    // |c a| < 2^51: adding 1.5 * 2^52 leaves round(c a) in the low mantissa bits
+    const double t = fma(c, a, 6755399441055744.0);
+    atomicAdd(p, (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL));
+}
+AP_D double lds_value(double v, double) { return v; }
+AP_D double lds_value(unsigned long long v, double inv_scale) { return (double)(long long)v * inv_scale; }
+
 template <typename T> AP_D void tsc3w(T d, T w[3]) {
     const T a = T(0.5) - d, b = T(0.5) + d;
     w[0] = T(0.5) * a * a;
@@ -86,8 +104,8 @@ AP_D T gather27(const T *F, int base, const T wx[3], const T wy[3], const T wz[3
 // nearest node did not change on that axis has zero terms on the window's
 // rim (last running-sum node along the flux axis, fourth node across it):
 // those atomics run under the mask of the lanes that moved (`wide`).
-template <int RX, int RXY, int RC, int WX, int WY, int WZ, typename T>
-AP_D void deposit3(double *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], const T (&fj)[3],
+template <int RX, int RXY, int RC, int WX, int WY, int WZ, typename T, typename JA>
+AP_D void deposit3(JA *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], const T (&fj)[3], double scale,
                    const bool (&wide)[3]) {
     constexpr int W[3] = {WX, WY, WZ};
     // running sums of DS along each axis, scaled, in FP64
@@ -98,17 +116,17 @@ AP_D void deposit3(double *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], 
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             acc += (double)DS[c][m];
-            C[c][m] = acc * (double)fj[c];
+            C[c][m] = acc * ((double)fj[c] * scale);
         }
     }
-    double *J = sJ + o;
+    JA *J = sJ + o;
     // component c (flux axis c) with transverse axes (t1, t2): node (a1, a2)
     // across, m along; strides of the flux and transverse axes
     auto comp = [&](auto cc) {
         constexpr int c = decltype(cc)::value;
         constexpr int t1 = c == 0 ? 1 : 0, t2 = c == 2 ? 1 : 2;
         constexpr int st[3] = {1, RX, RXY};
-        double *Jc = J + c * RC;
+        JA *Jc = J + c * RC;
 #pragma unroll
         for (int a2 = 0; a2 < W[t2]; ++a2)
 #pragma unroll
@@ -119,11 +137,11 @@ AP_D void deposit3(double *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], 
                 const T pa = S0[t1][a1] + T(0.5) * DS[t1][a1];
                 const T qa = T(0.5) * S0[t1][a1] + T(1.0 / 3.0) * DS[t1][a1];
                 const double A = (double)(pa * S0[t2][a2] + qa * DS[t2][a2]);
-                double *row = Jc + a2 * st[t2] + a1 * st[t1];
+                JA *row = Jc + a2 * st[t2] + a1 * st[t1];
 #pragma unroll
                 for (int m = 0; m < W[c] - 1; ++m) {
                     if (W[c] == 4 && m == 2 && !wide[c]) continue;
-                    atomic_add(row + m * st[c], C[c][m] * A);
+                    lds_add(row + m * st[c], C[c][m], A);
                 }
             }
     };
@@ -133,12 +151,15 @@ AP_D void deposit3(double *sJ, int o, const T (&S0)[3][4], const T (&DS)[3][4], 
 }
 
 template <typename T, int PT, bool INPLACE, bool PROXY, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d(PushArgs<T> a) {
     using R = Region3<TX, TY, TZ>;
     constexpr int RX = R::RX, RXY = R::RXY, RC = R::RC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);
-    double *sJ = reinterpret_cast<double *>(smem_raw + align_lds(6 * RC * sizeof(T)));
+    using JA = typename JTile<T>::type;
+    JA *sJ = reinterpret_cast<JA *>(smem_raw + align_lds(6 * RC * sizeof(T)));
+    __shared__ float s_red[4];
+    __shared__ int s_stay[kMaxSpecies];   // fused re-sort: particles of each species staying in the tile
 
     // Block -> tile: the hardware hands consecutive block ids to the 8 XCDs
     // in turn.  Runs of `xcd_chunk` consecutive tiles along x go to one XCD
@@ -175,13 +196,106 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
         return (size_t)wrap_node(ox + lx, nx) +
                (size_t)nx * ((size_t)wrap_node(oy + ly, ny) + (size_t)ny * (size_t)wrap_node(oz + lz, nz));
     };
-    for (int e = threadIdx.x; e < RC; e += blockDim.x) {
-        const size_t g = global_node(e);
+    if (threadIdx.x < kMaxSpecies) s_stay[threadIdx.x] = 0;
+    auto block_range = [&](int s, int &pb, int &pe) {
+        const int beg = a.sp[s].tile_start[tile];
+        const int cnt = a.sp[s].tile_start[tile + 1] - beg;
+        pb = beg + (int)(((long long)cnt * split) / a.splits);
+        pe = beg + (int)(((long long)cnt * (split + 1)) / a.splits);
+    };
+    // Latency: the record (cell, offsets, momenta, weight) of this thread's
+    // first particle of species 0, the permutation entry of its first
+    // particle of species 1 and the staged fields are all loaded before the
+    // first wait -- permutation entries first, then the fields, then the
+    // record -- and only then written to LDS.
+    struct Rec {
+        int q, cell;
+        T off[3], u[3], w;
+    };
+    auto load_rec = [&](const SpeciesIO<T> &S, int q) {
+        Rec r;
+        r.q = q;
+        r.cell = (INPLACE ? S.cell_out : S.cell_in)[q];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            sF[c * RC + e] = a.E[c][g];
-            sF[(3 + c) * RC + e] = a.B[c][g];
-            sJ[c * RC + e] = 0.0;
+            r.off[c] = (INPLACE ? S.off_out[c] : S.off_in[c])[q];
+            r.u[c] = (INPLACE ? S.u_out[c] : S.u_in[c])[q];
+        }
+        r.w = (INPLACE ? S.w_out : S.w_in)[q];
+        return r;
+    };
+    auto first_slot = [&](int s, int &q) {
+        int pb, pe;
+        block_range(s, pb, pe);
+        const int p = pb + (int)threadIdx.x;
+        if (p >= pe) return false;
+        q = (INPLACE || !a.sp[s].perm) ? p : a.sp[s].perm[p];
+        return true;
+    };
+    // (FP32 runs: the FP64 kernels have no registers to spare for it)
+    constexpr bool PREFETCH = std::is_same<T, float>::value;
+    int q0 = 0, q1 = 0;
+    const bool has0 = PREFETCH && a.nsp > 0 && first_slot(0, q0);
+    const bool has1 = PREFETCH && a.nsp > 1 && first_slot(1, q1);
+    constexpr int NIT = (RC + 255) / 256;   // launched with 256 threads
+    T sv[NIT][6];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        if (e < RC) {
+            const size_t g = global_node(e);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                sv[k][c] = a.E[c][g];
+                sv[k][3 + c] = a.B[c][g];
+            }
+        }
+    }
+    Rec pre0{};
+    if (has0) pre0 = load_rec(a.sp[0], q0);
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int e = (int)threadIdx.x + 256 * k;
+        if (e < RC) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sF[c * RC + e] = sv[k][c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sJ[c * RC + e] = JA(0);
+        }
+    }
+    // fixed-point scale of the block's current tile (FP32 runs): from the
+    // largest |q w| of its particles (non-finite weights belong to skipped
+    // particles) and its particle count
+    double scale = 1.0, inv_scale = 1.0;
+    if constexpr (std::is_same<T, float>::value) {
+        float qw = 0.f;
+        int count = 0;
+        for (int s = 0; s < a.nsp; ++s) {
+            int pb, pe;
+            block_range(s, pb, pe);
+            count += pe - pb;
+            const float qa = fabsf((float)a.sp[s].q);
+            const T *w_in = INPLACE ? a.sp[s].w_out : a.sp[s].w_in;
+            const int32_t *perm = INPLACE ? nullptr : a.sp[s].perm;
+            for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
+                const bool first = PREFETCH && p == pb + (int)threadIdx.x;
+                const T wv = first && s == 0 ? pre0.w : w_in[first && s == 1 ? q1 : (perm ? perm[p] : p)];
+                const float v = qa * fabsf((float)wv);
+                if (__builtin_isfinite(v)) qw = fmaxf(qw, v);
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) qw = fmaxf(qw, __shfl_xor(qw, d, 64));
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = qw;
+        __syncthreads();
+        qw = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+        const double fbound = (double)qw * fmax(a.dx[0], fmax(a.dx[1], a.dx[2])) / a.dt;
+        if (fbound > 0.0) {
+            int e, ec;
+            frexp(fbound, &e);                              // fbound < 2^e
+            frexp((double)(count > 0 ? count : 1), &ec);   // count < 2^ec
+            const int k = min(50 - e, 62 - e - ec);
+            scale = ldexp(1.0, k);
+            inv_scale = ldexp(1.0, -k);
         }
     }
     __syncthreads();
@@ -195,32 +309,43 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
     // Ex(h,n,n) Ey(n,h,n) Ez(n,n,h) Bx(n,h,h) By(h,n,h) Bz(h,h,n)
     for (int s = 0; s < a.nsp; ++s) {
         const SpeciesIO<T> &S = a.sp[s];
-        // in-place steps read and write the same arrays (fewer live pointers)
-        const int32_t *cell_in = INPLACE ? S.cell_out : S.cell_in;
-        const T *off_in0 = INPLACE ? S.off_out[0] : S.off_in[0];
-        const T *off_in1 = INPLACE ? S.off_out[1] : S.off_in[1];
-        const T *off_in2 = INPLACE ? S.off_out[2] : S.off_in[2];
-        const T *u_in0 = INPLACE ? S.u_out[0] : S.u_in[0];
-        const T *u_in1 = INPLACE ? S.u_out[1] : S.u_in[1];
-        const T *u_in2 = INPLACE ? S.u_out[2] : S.u_in[2];
-        const T *w_in = INPLACE ? S.w_out : S.w_in;
-        const int beg = S.tile_start[tile];
-        const int cnt = S.tile_start[tile + 1] - beg;
-        const int pb = beg + (int)(((long long)cnt * split) / a.splits);
-        const int pe = beg + (int)(((long long)cnt * (split + 1)) / a.splits);
+        int pb, pe;
+        block_range(s, pb, pe);
         const T kap = T(0.5 * S.q_over_m * a.dt);
         const T cj[3] = {T(-S.q * a.dx[0] / a.dt), T(-S.q * a.dx[1] / a.dt), T(-S.q * a.dx[2] / a.dt)};
+        // fused re-sort: rank of the particle in the tile of its new cell,
+        // stayers of this block counted per wave (their order is kept); the
+        // others are only counted in the tile they enter
+        auto emit_key = [&](int p, int tnew) {
+            const int lane = (int)(threadIdx.x & 63);
+            const bool st = tnew == tile;
+            const unsigned long long act = __ballot(1);
+            const unsigned long long m = __ballot(st);
+            const int leader = __ffsll((long long)act) - 1;
+            int base = 0;
+            if (lane == leader && m != 0ull) base = atomicAdd(&s_stay[s], (int)__popcll(m));
+            base = __shfl(base, leader, 64);
+            int key = -1;   // a particle changing tile takes its rank in the permutation kernel
+            if (st) key = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+            else atomicAdd(&S.mcount[tnew], 1);   // no return value: the wave does not wait for it
+            S.key_out[p] = key;
+        };
+        auto tile_of3 = [&](int i, int j, int k) { return i / TX + a.ntile[0] * (j / TY + a.ntile[1] * (k / TZ)); };
+        // p: output slot; q: input slot (the previous order through perm)
         for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
-            const int cell = cell_in[p];
+            const bool first = PREFETCH && p == pb + (int)threadIdx.x;
+            const Rec r = first && s == 0 ? pre0 : load_rec(S, first && s == 1 ? q1 : (INPLACE || !S.perm ? p : S.perm[p]));
+            const int q = r.q;
+            const int cell = r.cell;
             T off[3];
             bool ok = (unsigned)cell < ncell;
-            off[0] = off_in0[p];
-            off[1] = off_in1[p];
-            off[2] = off_in2[p];
+            off[0] = r.off[0];
+            off[1] = r.off[1];
+            off[2] = r.off[2];
 #pragma unroll
             for (int c = 0; c < 3; ++c) ok = ok && off[c] >= T(0) && off[c] < T(1);
-            T ux = u_in0[p], uy = u_in1[p], uz = u_in2[p];
-            const T w = w_in[p];
+            T ux = r.u[0], uy = r.u[1], uz = r.u[2];
+            const T w = r.w;
             ok = ok && finite_state(ux, uy, uz, w);
             if (!ok) {
                 count_skipped(a.n_bad, cell);
@@ -228,10 +353,18 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) S.off_out[c][p] = off[c];
                 S.u_out[0][p] = ux; S.u_out[1][p] = uy; S.u_out[2][p] = uz;
-                if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+                if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[q]; }
                 if (PROXY && !INPLACE && S.proxy_out) {
-                    S.proxy_out[2 * p] = S.proxy_in[2 * p];
-                    S.proxy_out[2 * p + 1] = S.proxy_in[2 * p + 1];
+                    S.proxy_out[2 * p] = S.proxy_in[2 * q];
+                    S.proxy_out[2 * p + 1] = S.proxy_in[2 * q + 1];
+                }
+                if (!INPLACE && S.key_out) {
+                    int tnew = 0;
+                    if ((unsigned)cell < ncell) {
+                        const int r = (int)a.fnx.div((unsigned)cell), k = (int)a.fnxy.div((unsigned)cell);
+                        tnew = tile_of3(cell - r * nx, r - k * ny, k);
+                    }
+                    emit_key(p, tnew);
                 }
                 continue;
             }
@@ -330,7 +463,7 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
                 if (S.proxy_out) {
                     const T uv0[3] = {u0x, u0y, u0z}, uv1[3] = {ux, uy, uz};
                     const T Ev[3] = {Ex, Ey, Ez}, Bv[3] = {Bx, By, Bz};
-                    proxy_accumulate<T>((INPLACE ? S.proxy_out : S.proxy_in) + 2 * p, S.proxy_out + 2 * p, uv0, uv1,
+                    proxy_accumulate<T>((INPLACE ? S.proxy_out : S.proxy_in) + 2 * q, S.proxy_out + 2 * p, uv0, uv1,
                                         Ev, Bv, T(a.dt));
                 }
             }
@@ -376,14 +509,14 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
                 const int o = (loc[2] + base[2]) * RXY + (loc[1] + base[1]) * RX + loc[0] + base[0];
                 const int wmask = (__any(wide[0]) ? 1 : 0) | (__any(wide[1]) ? 2 : 0) | (__any(wide[2]) ? 4 : 0);
                 switch (wmask) {
-                case 0: deposit3<RX, RXY, RC, 3, 3, 3>(sJ, o, S0, DS, fj, wide); break;
-                case 1: deposit3<RX, RXY, RC, 4, 3, 3>(sJ, o, S0, DS, fj, wide); break;
-                case 2: deposit3<RX, RXY, RC, 3, 4, 3>(sJ, o, S0, DS, fj, wide); break;
-                case 3: deposit3<RX, RXY, RC, 4, 4, 3>(sJ, o, S0, DS, fj, wide); break;
-                case 4: deposit3<RX, RXY, RC, 3, 3, 4>(sJ, o, S0, DS, fj, wide); break;
-                case 5: deposit3<RX, RXY, RC, 4, 3, 4>(sJ, o, S0, DS, fj, wide); break;
-                case 6: deposit3<RX, RXY, RC, 3, 4, 4>(sJ, o, S0, DS, fj, wide); break;
-                default: deposit3<RX, RXY, RC, 4, 4, 4>(sJ, o, S0, DS, fj, wide); break;
+                case 0: deposit3<RX, RXY, RC, 3, 3, 3>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 1: deposit3<RX, RXY, RC, 4, 3, 3>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 2: deposit3<RX, RXY, RC, 3, 4, 3>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 3: deposit3<RX, RXY, RC, 4, 4, 3>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 4: deposit3<RX, RXY, RC, 3, 3, 4>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 5: deposit3<RX, RXY, RC, 4, 3, 4>(sJ, o, S0, DS, fj, scale, wide); break;
+                case 6: deposit3<RX, RXY, RC, 3, 4, 4>(sJ, o, S0, DS, fj, scale, wide); break;
+                default: deposit3<RX, RXY, RC, 4, 4, 4>(sJ, o, S0, DS, fj, scale, wide); break;
                 }
             } else {
                 const T third = T(1.0 / 3.0);
@@ -444,16 +577,18 @@ __global__ __launch_bounds__(256, 3) void k_push_deposit_3d(PushArgs<T> a) {
             S.u_out[0][p] = ux;
             S.u_out[1][p] = uy;
             S.u_out[2][p] = uz;
-            if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[p]; }
+            if (!INPLACE) { S.w_out[p] = w; S.id_out[p] = S.id_in[q]; }
+            if (!INPLACE && S.key_out) emit_key(p, tile_of3(ni[0], ni[1], ni[2]));
         }
     }
     __syncthreads();
+    if (!INPLACE && (int)threadIdx.x < a.nsp && a.sp[threadIdx.x].key_out) a.sp[threadIdx.x].stay[tile] = s_stay[threadIdx.x];
 
     for (int e = threadIdx.x; e < RC; e += blockDim.x) {
         const size_t g = global_node(e);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double v = sJ[c * RC + e];
+            const double v = lds_value(sJ[c * RC + e], inv_scale);
             if (v != 0.0) atomic_add(&a.Jacc[c][g], v);
         }
     }
@@ -467,20 +602,17 @@ template <int TX, int TY, int TZ> constexpr size_t lds3(size_t real) {
 template <typename T, int PT, int TX, int TY, int TZ>
 hipError_t launch3d_shape(const PushArgs<T> &a, int threads, hipStream_t s) {
     if (a.n_logical == 0) return hipSuccess;
+    if (threads != 256) return hipErrorInvalidValue;   // the block reductions assume four waves
     const size_t lds = lds3<TX, TY, TZ>(sizeof(T));
     const int per = 8 * a.xcd_chunk;
     const int blocks = ((a.n_logical + per - 1) / per) * per;
-    const bool inplace = a.sp[0].copy_static == 0;
+    // every 3-D push reads a freshly sorted copy or goes through the
+    // re-sort permutation: the in-place instantiation is not needed (an
+    // in-place call is still correct: each slot is read and written by one thread)
     bool proxy = false;
     for (int k = 0; k < a.nsp; ++k) proxy = proxy || a.sp[k].proxy_out != nullptr;
-    if (inplace && !proxy)
-        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, true, false, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
-                           a);
-    else if (!proxy)
+    if (!proxy)
         hipLaunchKernelGGL((k_push_deposit_3d<T, PT, false, false, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
-                           a);
-    else if (inplace)
-        hipLaunchKernelGGL((k_push_deposit_3d<T, PT, true, true, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
                            a);
     else
         hipLaunchKernelGGL((k_push_deposit_3d<T, PT, false, true, TX, TY, TZ>), dim3(blocks), dim3(threads), lds, s,
