@@ -347,6 +347,18 @@ ap_status ap_step(ap_ctx *ctx, int64_t n_steps, uint32_t flags);
  * AP_E_ARG for a NULL argument or unknown bits. */
 ap_status ap_gather_diag(ap_ctx *ctx, uint32_t what, ap_diag *out);
 
+/* ap_gather_diag for callers that cannot allocate device memory (code under
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * reductions, results, counter resets and return codes, with the reduction
+ * partials in a library-held static device array (66,176 bytes per GPU,
+ * resolved by ap_init on the stream's device and held until the process
+ * ends) instead of the context workspace.  Its scratch size does not depend
+ * on the run, so no run is too large for it.  Calls no allocating routine.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (other host threads, other streams) race and must be serialised by the
+ * caller.  AP_E_ARG for a NULL argument or unknown bits. */
+ap_status ap_gather_diag_static(ap_ctx *ctx, uint32_t what, ap_diag *out);
+
 /* Current simulation time (lambda/c) and step count. */
 ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
 
@@ -359,7 +371,7 @@ ap_status ap_get_time(const ap_ctx *ctx, double *t, int64_t *step);
 ap_status ap_eval_pulse(ap_ctx *ctx, int64_t n, const double *xyz, double t, void *E, void *B);
 
 /* Emission proxy of every particle of a species (the radiated-power proxy
- * the benchmark spec's gradients observe: the Lienard power without its constant,
+ * the gradients of ap_backward observe: the Lienard power without its constant,
  * summed over the steps), read out as FP64 values s - c of each particle's
  * compensated pair, in the current slot order of the species' arrays (pair
  * them with the id array for a by-id view).  dst: device, n doubles, written
@@ -400,7 +412,7 @@ ap_status ap_set_adjoint_mode(ap_ctx *ctx, int32_t mode);
 ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segment, size_t *bytes);
 
 /* Gradient of a particle observable with respect to pulse parameters (the
- * the benchmark spec's differentiated form of the push and the analytic field of
+ * differentiated form of the push and of the analytic field of
  * Sec. II-III) over
  * the steps of the last ap_step call made with AP_STEP_RECORD (the state
  * must not have been advanced, nor the pulse changed, since).  The observable is

@@ -33,7 +33,7 @@ SAMPLINGS = {"particles": AP_SAMPLE_PARTICLES, "grid": AP_SAMPLE_GRID, "boundary
 PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE_GAUSS,
                "lg": AP_PULSE_LG, "ff": AP_PULSE_FF, "gauss_np": AP_PULSE_GAUSS_NP}
 
-EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag",
+EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag", "ap_gather_diag_static",
             "ap_get_time", "ap_eval_pulse", "ap_read_proxy", "ap_set_checkpoints", "ap_set_adjoint_mode",
             "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window",
             "ap_destroy", "ap_last_error")
@@ -123,6 +123,7 @@ def load():
         "ap_set_pulse": (C.c_int32, [C.c_void_p, C.c_int32, P(ap_pulse_params)]),
         "ap_step": (C.c_int32, [C.c_void_p, C.c_int64, C.c_uint32]),
         "ap_gather_diag": (C.c_int32, [C.c_void_p, C.c_uint32, P(ap_diag)]),
+        "ap_gather_diag_static": (C.c_int32, [C.c_void_p, C.c_uint32, P(ap_diag)]),
         "ap_get_time": (C.c_int32, [C.c_void_p, P(C.c_double), P(C.c_int64)]),
         "ap_eval_pulse": (C.c_int32, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p,
                                       C.c_void_p]),
@@ -186,6 +187,13 @@ def ap_gather_diag(ctx, what=AP_DIAG_PARTICLES | AP_DIAG_FIELDS, allow_numeric=F
     out = ap_diag()
     st = load().ap_gather_diag(ctx, int(what), C.byref(out))
     _check(st, "ap_gather_diag", allow=(AP_E_NUMERIC,) if allow_numeric else ())
+    return out, st
+
+
+def ap_gather_diag_static(ctx, what=AP_DIAG_PARTICLES | AP_DIAG_FIELDS, allow_numeric=False):
+    out = ap_diag()
+    st = load().ap_gather_diag_static(ctx, int(what), C.byref(out))
+    _check(st, "ap_gather_diag_static", allow=(AP_E_NUMERIC,) if allow_numeric else ())
     return out, st
 
 

@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -352,11 +354,58 @@ struct TimedPair {
 
 }  // namespace
 
+// Library-held scratch of ap_gather_diag_static, for callers that cannot
+// allocate device memory: the per-species sums, then the per-block partial
+// sums of the diagnostics reductions (66,176 bytes, whatever the run's size).
+// Each GPU holds its own copy until the process ends; host code reaches it
+// only through the address resolved per device (static_scratch), never
+// through the name.
+constexpr size_t kStaticSums = (size_t)(kMaxSpecies + 1) * kDiagVals;
+constexpr size_t kStaticDoubles = kStaticSums + (size_t)kDiagBlocks * kDiagVals;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+static_assert(sizeof(scratch) == 66176, "the documented size of the static scratch");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// Resolve the device address of `scratch` on device dev, once per device,
+// with dev current (the caller's current device is restored).
+hipError_t resolve_static_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+double *static_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
+}  // namespace
+
 struct ap_ctx {
     RunShape s;
     WorkLayout L;
     ap_buffers buf;
     hipStream_t stream = nullptr;
+    int device = 0;              // device of the stream
     PulseDev P;
     int pulse_type = -1;
     double s0 = 1.0;             // S0/E0 of the incoming-wave boundary (AP_SAMPLE_BOUNDARY)
@@ -519,7 +568,10 @@ ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int3
         c->buf = *buffers;
         c->stream = static_cast<hipStream_t>(hip_stream);
         c->P = default_pulse();
-        hipError_t e = launch_fill_zero<unsigned long long>(c->counters(), kCounters, c->stream);
+        // the stream's device; ap_gather_diag_static's scratch is resolved there
+        hipError_t e = c->stream ? hipStreamGetDevice(c->stream, &c->device) : hipGetDevice(&c->device);
+        if (e == hipSuccess) e = resolve_static_scratch(c->device);
+        if (e == hipSuccess) e = launch_fill_zero<unsigned long long>(c->counters(), kCounters, c->stream);
         if (e == hipSuccess && s.dim > 0) {
             if (s.prec == AP_F64)
                 e = launch_fill_zero<double>(static_cast<double *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
@@ -780,19 +832,24 @@ ap_status ap_get_time(const ap_ctx *c, double *t, int64_t *step) {
     return AP_OK;
 }
 
-ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
-    if (!c) return fail(AP_E_ARG, "context is NULL");
+namespace {
+
+// The diagnostics reductions of ap_gather_diag and ap_gather_diag_static.
+// sums: (kMaxSpecies + 1) x kDiagVals doubles, partial: kDiagBlocks x
+// kDiagVals doubles, both device.  Every slot read back is written by this
+// call (per-block rows by the reduction kernels, sums by k_sum_partials), so
+// neither needs clearing.
+static ap_status gather_diag(ap_ctx *c, uint32_t what, ap_diag *out, double *sums, double *partial, bool timed) {
     if (!out) return fail(AP_E_ARG, "diag output is NULL");
     if (what & ~(AP_DIAG_PARTICLES | AP_DIAG_FIELDS)) return fail(AP_E_ARG, "unknown diag mask");
     ap_diag d;
     std::memset(&d, 0, sizeof(d));
     const RunShape &s = c->s;
-    double *sums = c->wp<double>(c->L.sums);
-    double *partial = c->wp<double>(c->L.partial);
     double host[(kMaxSpecies + 1) * kDiagVals];
     std::memset(host, 0, sizeof(host));
     {
-        Timer tm(c, 3);
+        std::optional<Timer> tm;
+        if (timed) tm.emplace(c, 3);
         if (what & AP_DIAG_PARTICLES) {
             for (int i = 0; i < s.nsp; ++i) {
                 const ap_particles &p = c->buf.sp[i];
@@ -877,6 +934,21 @@ ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
                                       std::to_string(d.n_skipped) + " skipped pushes) or " +
                                       std::to_string(d.n_fast) + " dropped moves since the last diagnostics");
     return AP_OK;
+}
+
+}  // namespace
+
+ap_status ap_gather_diag(ap_ctx *c, uint32_t what, ap_diag *out) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    return gather_diag(c, what, out, c->wp<double>(c->L.sums), c->wp<double>(c->L.partial), true);
+}
+
+ap_status ap_gather_diag_static(ap_ctx *c, uint32_t what, ap_diag *out) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    double *base = static_scratch(c->device);
+    if (!base) return fail(AP_E_STATE, "static scratch not resolved for device " + std::to_string(c->device));
+    // no event timing: the pool may have to create events
+    return gather_diag(c, what, out, base, base + kStaticSums, false);
 }
 
 ap_status ap_eval_pulse(ap_ctx *c, int64_t n, const double *xyz, double t, void *E, void *B) {
