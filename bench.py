@@ -569,13 +569,24 @@ VALU_PEAK_T_LANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h", "common.h", "pulse_dev.h",
                   "dual.h", "nonparaxial_gen.h", "apt_host.cpp")
 
-# Counter measurements of k_push_deposit_3d on the headline window (the
-# default --steps/--warmup of the full test run), from rocprofv3 --pmc runs of
-# this script: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, each scaled by
+# Counter measurements of k_push_deposit_3d on the headline window (this
+# script's default --steps/--warmup), from rocprofv3 --pmc runs of it: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE, each scaled by
 # what the counter reads for a device copy of known size in the same run),
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
-MEASURED_TRAFFIC = None
+MEASURED_TRAFFIC = {
+    "sources_sha256": "410dc79c148ce0b99b2209366bb4594d97b8064a8751334d031992a242599e4e",
+    # FETCH_SIZE 3.2244e7 KiB x 1.99991 (a 2 GiB device copy reads as 1048614 KiB)
+    "fetch_bytes_per_launch": 6.6033e10,
+    # WRITE_SIZE 7.6615e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.8454e10,
+    "valu_lane_ops_per_push": 1488.7,
+    "ms_per_launch": 94.910,
+    "lds_busy_frac": 0.470,
+    "lds_bank_conflict_frac": 0.567,
+    "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
+            "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
+}
 
 
 def sources_digest(names=PUSH3D_SOURCES):
