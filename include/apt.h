@@ -79,7 +79,7 @@ typedef int32_t ap_status;
 #define AP_GRID_PROXY         0x2  /* gridded species may carry an emission
                                       proxy (reserves its re-sort workspace)  */
 #define AP_GRID_MOVING_WINDOW 0x8  /* gridded runs: reserves the workspace of
-                                      ap_shift_window                          */
+                                      ap_shift_window (not with AP_GRID_OPEN_X) */
 #define AP_GRID_OPEN_X        0x4  /* gridded runs: the x ends of every row
                                       are incoming/outgoing-wave boundaries for
                                       E2, B2 (App. B, first order, normal
@@ -451,23 +451,33 @@ ap_status ap_backward(ap_ctx *ctx, int32_t species, const void *dL_du,
 ap_status ap_timing_enable(ap_ctx *ctx, int32_t enable);
 ap_status ap_timing_read(ap_ctx *ctx, ap_timing *out, int32_t reset);
 
-/* Moving window (Sec. III.C: a window following the pulse, e.g. the
- * intensity peak of a flying focus): advance the window one cell along +x.
- * Needs AP_GRID_MOVING_WINDOW.  Lab positions are kept: x_min[0] grows by
- * dx[0]; E2, B2 move down one index along x and the new last column is
- * zero; every particle moves down one cell index.  Particles in the first
- * column fall behind the window: their slots become free.  A free slot holds
- * cell -1 and zero offsets, momentum, weight (and proxy); the caller may
- * pass such slots at ap_init as spare capacity.  Each species' ids must be
- * a permutation of 0..n-1 (else AP_E_ARG, nothing changed).
+/* Moving window (Sec. III.C: a window that follows the pulse, e.g. the
+ * intensity peak of a flying focus, which moves at v_f in either direction).
+ * Needs AP_GRID_MOVING_WINDOW.  The grid is a ring along x: window column l
+ * (l = 0 at the window's x_min) is stored in column (l + origin) mod n[0] of
+ * every field array and of the particles' cell indices, so a shift moves the
+ * origin, not the data.  At ap_init origin = 0 (storage = window columns).
+ *
+ * ap_shift_window moves the window by one cell: dir = +1 along +x (x_min
+ * grows by dx[0]; the window's first column leaves and a new last column
+ * enters), dir = -1 along -x (x_min falls by dx[0]; the last column leaves,
+ * a new first column enters).  Lab positions and the lab values of E2, B2
+ * are kept; the entering column's E2, B2 are zero.  Particles in the leaving
+ * column fall out of the window: their slots become free and their ids
+ * free ids.  A free slot holds cell -1 and zero offsets, momentum, weight
+ * (and proxy); the caller may pass such slots at ap_init as spare capacity.
+ * Each species' ids must be a permutation of 0..n-1 (the range is checked
+ * at ap_init: AP_E_ARG).
  * inject: NULL, or one ap_inject per species (n = 0 for none): device arrays
- * in the species layout of the new particles, all in the new last column
- * (cell index n[0]-1 of its row) with offsets in [0, 1) (else AP_E_ARG,
- * nothing changed); their momenta and weights are the caller's (the
- * injected plasma).  They take the free slots in increasing id order, and
- * the proxy of an injected particle starts at zero.  More injected particles
- * than free slots: AP_E_ARG, nothing changed.  Drops any adjoint recording;
- * the next step re-sorts.  Synchronises the stream. */
+ * in the species layout of the new particles, cells given in window columns
+ * (the entering column: n[0]-1 for dir = +1, 0 for dir = -1, any row) with
+ * offsets in [0, 1) (else AP_E_ARG, nothing changed); momenta and weights
+ * are the caller's (the injected plasma).  They take the smallest free ids,
+ * in order, and the slots holding them; the proxy of an injected particle
+ * starts at zero.  More injected particles than free slots: AP_E_ARG,
+ * nothing changed.  Drops any adjoint recording; 1-D and 3-D runs re-sort at
+ * the next step.  One synchronisation of the stream (the checks); the work
+ * is a pass over the particles' cells and one over the free slots. */
 typedef struct ap_inject {
     const int32_t *cell;
     const void    *off[3];      /* active axes; NULL on the others           */
@@ -475,7 +485,18 @@ typedef struct ap_inject {
     const void    *w;
     int64_t        n;
 } ap_inject;
-ap_status ap_shift_window(ap_ctx *ctx, const ap_inject *inject);
+ap_status ap_shift_window(ap_ctx *ctx, int32_t dir, const ap_inject *inject);
+
+/* The window's lab x_min (lambda) and its storage origin (the storage column
+ * of window column 0); either output may be NULL. */
+ap_status ap_get_window(const ap_ctx *ctx, double *x_min, int32_t *origin);
+
+/* Shift schedule of a window moving at beta c (beta = v_f / c of a flying
+ * focus, Sec. III.C, any sign): the window's x_min should be
+ * x_ref + beta (t - t_ref) at the current time t (lambda, lambda/c).  With
+ * d = (that position - x_min) / dx[0]: *dir = +1 if d >= 1/2, -1 if
+ * d < -1/2 (shift once and ask again), else 0. */
+ap_status ap_window_due(const ap_ctx *ctx, double beta, double x_ref, double t_ref, int32_t *dir);
 
 /* Release the context (does not free caller buffers). NULL is accepted. */
 ap_status ap_destroy(ap_ctx *ctx);

@@ -489,27 +489,38 @@ def step(grid, species, pulse, field_update=True, pulse_on_grid=False, launch=Fa
     return moved
 
 
-def shift_window(grid, species, injected):
+def shift_window(grid, species, injected, direction=1):
     """Moving window (Sec. III.C: a window that follows the pulse, e.g. the
-    intensity peak of a flying focus): advance it one cell along +x.
+    intensity peak of a flying focus at v_f of either sign): move it one
+    cell along +x (direction 1) or -x (direction -1).
 
-    Lab positions are kept: x_min[0] grows by dx; E2, B2 move down one index
-    along x and the new last column is empty; particles move down one cell
-    index, and those in the first column fall behind the window and are
-    removed (their ids join the free ids).  ``injected`` holds, per species,
-    None or (pos (3, k) in cell units of the new window, u (3, k), w (k)):
-    the particles of the new column, which take the k smallest free ids."""
-    grid.x_min = (grid.x_min[0] + grid.dx[0],) + tuple(grid.x_min[1:])
+    Lab positions are kept.  Along +x: x_min[0] grows by dx, E2/B2 move down
+    one index along x and the new last column is empty; particles move down
+    one cell index and those in the first column fall behind the window.
+    Along -x: x_min[0] falls by dx, E2/B2 move up one index and the new first
+    column is empty; particles move up one cell index and those in the last
+    column fall out.  Particles that leave are removed (their ids join the
+    free ids).  ``injected`` holds, per species, None or (pos (3, k) in cell
+    units of the new window, u (3, k), w (k)): the particles of the entering
+    column, which take the k smallest free ids."""
+    if direction not in (1, -1):
+        raise ValueError("direction must be +1 or -1")
+    nx = grid.n[0]
+    grid.x_min = (grid.x_min[0] + direction * grid.dx[0],) + tuple(grid.x_min[1:])
     for F in grid.E + grid.B:
-        F[..., :-1] = F[..., 1:].copy()
-        F[..., -1] = 0.0
+        if direction == 1:
+            F[..., :-1] = F[..., 1:].copy()
+            F[..., -1] = 0.0
+        else:
+            F[..., 1:] = F[..., :-1].copy()
+            F[..., 0] = 0.0
     for sp, inj in zip(species, injected):
-        keep = sp.pos[0] >= 1.0
+        keep = sp.pos[0] >= 1.0 if direction == 1 else sp.pos[0] < nx - 1.0
         if sp.ids is not None:
             sp.free = np.sort(np.concatenate([sp.free, sp.ids[~keep]]))
             sp.ids = sp.ids[keep]
         sp.pos = sp.pos[:, keep]
-        sp.pos[0] -= 1.0
+        sp.pos[0] -= direction
         sp.u = sp.u[:, keep]
         sp.w = sp.w[keep]
         if sp.proxy is not None:
@@ -528,6 +539,16 @@ def shift_window(grid, species, injected):
         sp.w = np.concatenate([sp.w, w])
         if sp.proxy is not None:
             sp.proxy = np.concatenate([sp.proxy, np.zeros(k)])
+
+
+def window_due(x_min, dx, t, beta, x_ref, t_ref):
+    """Shift due for a window whose x_min should be x_ref + beta (t - t_ref)
+    (Sec. III.C, a window moving with the flying focus at v_f = beta c):
+    +1 when that position lies half a cell or more ahead, -1 when it lies
+    more than half a cell behind, else 0 (the half-open interval keeps a tie
+    from shifting back and forth)."""
+    d = (x_ref + beta * (t - t_ref) - x_min) / dx
+    return 1 if d >= 0.5 else (-1 if d < -0.5 else 0)
 
 
 def emission_proxy(u0, u1, E, B, dt):

@@ -36,6 +36,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag", "ap_gather_diag_static",
             "ap_get_time", "ap_eval_pulse", "ap_read_proxy", "ap_set_checkpoints", "ap_set_adjoint_mode",
             "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window",
+            "ap_get_window", "ap_window_due",
             "ap_destroy", "ap_last_error")
 
 
@@ -135,7 +136,9 @@ def load():
                                     C.c_int32, P(C.c_double)]),
         "ap_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
         "ap_timing_read": (C.c_int32, [C.c_void_p, P(ap_timing), C.c_int32]),
-        "ap_shift_window": (C.c_int32, [C.c_void_p, C.c_void_p]),
+        "ap_shift_window": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+        "ap_get_window": (C.c_int32, [C.c_void_p, P(C.c_double), P(C.c_int32)]),
+        "ap_window_due": (C.c_int32, [C.c_void_p, C.c_double, C.c_double, C.c_double, P(C.c_int32)]),
         "ap_destroy": (C.c_int32, [C.c_void_p]),
         "ap_last_error": (C.c_char_p, []),
     }
@@ -247,10 +250,25 @@ def ap_timing_read(ctx, reset=False):
     return out
 
 
-def ap_shift_window(ctx, inject):
-    """inject: None or a ctypes array of ap_inject, one per species."""
-    _check(load().ap_shift_window(ctx, C.cast(inject, C.c_void_p) if inject is not None else None),
+def ap_shift_window(ctx, direction, inject):
+    """direction: +1 or -1; inject: None or a ctypes array of ap_inject, one per species."""
+    _check(load().ap_shift_window(ctx, int(direction), C.cast(inject, C.c_void_p) if inject is not None else None),
            "ap_shift_window")
+
+
+def ap_get_window(ctx):
+    """(x_min in lambda, storage origin) of the moving window."""
+    x = C.c_double()
+    o = C.c_int32()
+    _check(load().ap_get_window(ctx, C.byref(x), C.byref(o)), "ap_get_window")
+    return x.value, o.value
+
+
+def ap_window_due(ctx, beta, x_ref, t_ref):
+    """+1 / -1 when the window lags x_ref + beta (t - t_ref) by half a cell or more, else 0."""
+    d = C.c_int32()
+    _check(load().ap_window_due(ctx, float(beta), float(x_ref), float(t_ref), C.byref(d)), "ap_window_due")
+    return d.value
 
 
 def ap_destroy(ctx):

@@ -574,7 +574,7 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
         for (int c = 0; c < 3; ++c) {
             if (GD == 0) Xd[c] = IN(a.x_min[c] + ((double)a.icell[c][p] + (double)a.off[c][p]) * a.dx[c]);
             else if (GD <= 2 && c == 1) Xd[c] = IN(a.G.q_slice);
-            else Xd[c] = IN(a.x_min[c] + ((double)ic[c] + (double)ov[c]) * a.dx[c]);
+            else Xd[c] = IN(a.x_min[c] + ((double)(c == 0 ? win_col(ic[0], a.xo, a.G.n[0]) : ic[c]) + (double)ov[c]) * a.dx[c]);
             Xd[c].d[c] = T(1);
             u0v[c] = a.u[c][p];
         }

@@ -51,14 +51,16 @@ struct RunShape {
     double q[kMaxSpecies] = {0, 0, 0, 0};
     double m[kMaxSpecies] = {1, 1, 1, 1};
     bool has_proxy[kMaxSpecies] = {false, false, false, false};   // gridded: species carries a proxy
+    int xo = 0;                     // moving window: storage column of the window's first column
     int adj_mode = AP_ADJ_FROZEN;   // reading of the gridded adjoint (fixes the checkpoint layout)
 };
 
 struct WorkLayout {
     size_t counters = 0, sums = 0, partial = 0, rho0 = 0, rho1 = 0, jacc = 0, esamp = 0, scan_part = 0, bsrc = 0,
            total = 0;
-    size_t wtmp = 0, wpart = 0;   // moving window: field copy, scan scratch
-    size_t wflag[kMaxSpecies] = {}, wrank[kMaxSpecies] = {};   // per species: free-slot flags and ranks by id
+    // moving window: per species the free-id bit map; popcounts of its words,
+    // their scan, scan scratch and counters, shared by the species
+    size_t wmap[kMaxSpecies] = {}, wslot[kMaxSpecies] = {}, wpop = 0, wfrank = 0, wpart = 0, wcnt = 0;
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -73,6 +75,10 @@ struct WorkLayout {
 
 constexpr int kDiagBlocks = 512;
 constexpr int kCounters = 8;   // n_fast, n_bad, res_max, j_max, n_offtile, ...
+// moving-window counters: [0] bad ids / injected particles, [1 + i] free slots
+// at ap_init and leavers of the last shift, [1 + kMaxSpecies + i] leavers
+// counted ahead, [1 + 2 kMaxSpecies + i] stale slot hints of the last fill
+constexpr int kWinCounters = 1 + 3 * kMaxSpecies;
 
 // Axes with dynamics (derivatives, motion, stagger).  dim 1: rows of
 // independent lines along x; the z index is the row.
@@ -151,6 +157,8 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
         return fail(AP_E_ARG, "unknown grid option bits");
     if ((g->options & AP_GRID_MOVING_WINDOW) && s.dim == 0) return fail(AP_E_ARG, "a moving window needs a grid");
     if ((g->options & AP_GRID_OPEN_X) && s.dim == 0) return fail(AP_E_ARG, "AP_GRID_OPEN_X needs a grid");
+    if ((g->options & AP_GRID_OPEN_X) && (g->options & AP_GRID_MOVING_WINDOW))
+        return fail(AP_E_ARG, "AP_GRID_OPEN_X and AP_GRID_MOVING_WINDOW exclude each other");
     if ((g->options & AP_GRID_PULSE_ON_GRID) && s.dim == 0)
         return fail(AP_E_ARG, "AP_GRID_PULSE_ON_GRID needs a grid");
     if ((g->options & AP_GRID_PROXY) && s.dim == 0)
@@ -209,14 +217,17 @@ WorkLayout make_layout(const RunShape &s) {
         // boundary source S_y, S_z per row (incoming-wave x_min of open rows)
         if (s.options & AP_GRID_OPEN_X) L.bsrc = take((size_t)s.n[1] * s.n[2] * 2 * s.real);
         if (s.options & AP_GRID_MOVING_WINDOW) {
-            int64_t nmax = 0;
-            for (int i = 0; i < s.nsp; ++i) nmax = s.np[i] > nmax ? s.np[i] : nmax;
-            L.wtmp = take((size_t)6 * (size_t)s.ncell * s.real);
+            int64_t wmax = 1;
             for (int i = 0; i < s.nsp; ++i) {
-                L.wflag[i] = take((size_t)(s.np[i] + 1) * 4);
-                L.wrank[i] = take((size_t)(s.np[i] + 1) * 4);
+                const int64_t words = (s.np[i] + 31) / 32;
+                wmax = words > wmax ? words : wmax;
+                L.wmap[i] = take((size_t)words * 4);
+                L.wslot[i] = take((size_t)(s.np[i] > 0 ? s.np[i] : 1) * 4);
             }
-            L.wpart = take((size_t)2 * scan_part_len((int32_t)(nmax > 0 ? nmax : 1)) * 4);
+            L.wpop = take((size_t)wmax * 4);
+            L.wfrank = take((size_t)(wmax + 1) * 4);
+            L.wpart = take((size_t)2 * scan_part_len((int32_t)wmax) * 4);
+            L.wcnt = take((size_t)kWinCounters * 8);
         }
         for (int i = 0; i < s.nsp; ++i) {
             const size_t N = (size_t)s.np[i];
@@ -409,8 +420,9 @@ struct ap_ctx {
     PulseDev P;
     int pulse_type = -1;
     double s0 = 1.0;             // S0/E0 of the incoming-wave boundary (AP_SAMPLE_BOUNDARY)
-    // moving window: free particle slots (all species)
-    int64_t n_free = 0;
+    // moving window: free slots per species, up to the leavers of the last
+    // shift (counted on the device, added at the next shift)
+    int64_t n_free[kMaxSpecies] = {0, 0, 0, 0};
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
@@ -485,7 +497,8 @@ ap_status hip_fail(hipError_t e, const char *where) {
 
 template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags);
 template <typename T> ap_status restore_primary(ap_ctx *c);
-template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *inject);
+template <typename T> ap_status shift_window_impl(ap_ctx *c, int32_t dir, const ap_inject *inject);
+template <typename T> ap_status window_init(ap_ctx *c);
 template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags);
 template <typename T>
 ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dproxy, const int32_t *ids, int np_,
@@ -579,15 +592,11 @@ ap_status ap_init(const ap_grid_desc *grid, const ap_species_desc *species, int3
                 e = launch_fill_zero<float>(static_cast<float *>(buffers->grid), (size_t)9 * s.ncell, c->stream);
         }
         if (e == hipSuccess && (s.options & AP_GRID_MOVING_WINDOW)) {
-            // free slots the caller passes as spare capacity
-            unsigned long long *cnt = c->counters() + 5;
-            for (int i = 0; i < s.nsp && e == hipSuccess; ++i)
-                if (s.np[i] > 0) e = launch_count_free(buffers->sp[i].cell, (int32_t)s.np[i], cnt, c->stream);
-            unsigned long long nf = 0;
-            if (e == hipSuccess) e = hipMemcpyAsync(&nf, cnt, sizeof(nf), hipMemcpyDeviceToHost, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess) e = launch_fill_zero<unsigned long long>(cnt, 1, c->stream);
-            c->n_free = (int64_t)nf;
+            const ap_status st = s.prec == AP_F64 ? window_init<double>(c) : window_init<float>(c);
+            if (st != AP_OK) {
+                delete c;
+                return st;
+            }
         }
         if (e != hipSuccess) {
             delete c;
@@ -1090,15 +1099,39 @@ ap_status ap_timing_read(ap_ctx *c, ap_timing *out, int32_t reset) {
     return AP_OK;
 }
 
-ap_status ap_shift_window(ap_ctx *c, const ap_inject *inject) {
+ap_status ap_shift_window(ap_ctx *c, int32_t dir, const ap_inject *inject) {
     if (!c) return fail(AP_E_ARG, "context is NULL");
     if (!(c->s.options & AP_GRID_MOVING_WINDOW))
         return fail(AP_E_STATE, "the run was not created with AP_GRID_MOVING_WINDOW");
+    if (dir != 1 && dir != -1) return fail(AP_E_ARG, "dir must be +1 or -1");
     try {
-        return c->s.prec == AP_F64 ? shift_window_impl<double>(c, inject) : shift_window_impl<float>(c, inject);
+        return c->s.prec == AP_F64 ? shift_window_impl<double>(c, dir, inject)
+                                   : shift_window_impl<float>(c, dir, inject);
     } catch (...) {
         return fail(AP_E_NOMEM, "host allocation failed");
     }
+}
+
+ap_status ap_get_window(const ap_ctx *c, double *x_min, int32_t *origin) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (x_min) *x_min = c->s.x_min[0] / kTwoPi;
+    if (origin) *origin = c->s.xo;
+    return AP_OK;
+}
+
+ap_status ap_window_due(const ap_ctx *c, double beta, double x_ref, double t_ref, int32_t *dir) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (!dir) return fail(AP_E_ARG, "dir output is NULL");
+    if (!std::isfinite(beta) || !std::isfinite(x_ref) || !std::isfinite(t_ref))
+        return fail(AP_E_ARG, "beta, x_ref and t_ref must be finite");
+    if (c->s.dim == 0) return fail(AP_E_ARG, "a moving window needs a grid");
+    // internal units: lengths in lambda / 2 pi, times in 1 / omega
+    const double t = c->s.t0 + (double)c->step * c->s.dt;
+    const double target = x_ref * kTwoPi + beta * (t - t_ref * kTwoPi);
+    const double d = (target - c->s.x_min[0]) / c->s.dx[0];
+    // half-open interval [-1/2, 1/2): a tie never shifts back and forth
+    *dir = d >= 0.5 ? 1 : (d < -0.5 ? -1 : 0);
+    return AP_OK;
 }
 
 ap_status ap_destroy(ap_ctx *c) {
@@ -1431,6 +1464,7 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
             const SpBlock<T> b = sp_block<T>(slot_j + G.inner_sp, s, sp, false, false);
             const T *F = reinterpret_cast<const T *>(slot_j);
             AdjointArgs<T> a{};
+            a.xo = s.xo;
             for (int k = 0; k < 3; ++k) {
                 a.off[k] = b.off[k];
                 a.u[k] = b.u[k];
@@ -1557,6 +1591,7 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
                 if (s.np[i] == 0) continue;
                 const SpBlock<T> b = sp_block<T>(slot_j + G.inner_off[i], s, i, true, false);
                 AdjointArgs<T> a{};
+                a.xo = s.xo;
                 for (int k = 0; k < 3; ++k) {
                     a.off[k] = b.off[k];
                     a.u[k] = b.u[k];
@@ -1606,12 +1641,76 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     return AP_OK;
 }
 
-template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *inject) {
+// Window arguments of species i: leaving storage column col, injected
+// particles (or none) required in window column in_col.
+template <typename T> WindowArgs<T> window_args(ap_ctx *c, int i, int col, int in_col, const ap_inject *inject) {
     const RunShape &s = c->s;
-    const WorkLayout &L = c->L;
-    unsigned long long *bad = c->counters() + 5;
+    const ap_particles &p = c->buf.sp[i];
+    WindowArgs<T> a{};
+    a.cell = p.cell;
+    a.id = p.id;
+    for (int k = 0; k < 3; ++k) {
+        a.off[k] = axis_active(s.dim, k) ? static_cast<T *>(p.off[k]) : nullptr;
+        a.u[k] = static_cast<T *>(p.u[k]);
+    }
+    a.w = static_cast<T *>(p.w);
+    a.proxy = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
+    a.n = (int32_t)s.np[i];
+    a.ncell = (uint32_t)s.ncell;
+    a.nx = s.n[0];
+    a.fnx = FastDiv((uint32_t)s.n[0]);
+    a.col = col;
+    a.freemap = c->wp<uint32_t>(c->L.wmap[i]);
+    a.free_slot = c->wp<int32_t>(c->L.wslot[i]);
+    a.miss = c->wp<unsigned long long>(c->L.wcnt) + 1 + 2 * kMaxSpecies + i;
+    a.frank = c->wp<int32_t>(c->L.wfrank);
+    a.words = (int32_t)((s.np[i] + 31) / 32);
+    a.in_col = in_col;
+    if (inject && inject[i].n > 0) {
+        const ap_inject &in = inject[i];
+        a.in_cell = in.cell;
+        for (int k = 0; k < 3; ++k) {
+            a.in_off[k] = axis_active(s.dim, k) ? static_cast<const T *>(in.off[k]) : nullptr;
+            a.in_u[k] = static_cast<const T *>(in.u[k]);
+        }
+        a.in_w = static_cast<const T *>(in.w);
+        a.n_inj = (int32_t)in.n;
+    }
+    return a;
+}
+
+// Free-id maps from the free slots passed at ap_init; ids checked for range.
+template <typename T> ap_status window_init(ap_ctx *c) {
+    const RunShape &s = c->s;
+    unsigned long long *cnt = c->wp<unsigned long long>(c->L.wcnt);
+    HIPCHK(launch_fill_zero<unsigned long long>(cnt, kWinCounters, c->stream), "ap_init");
+    for (int i = 0; i < s.nsp; ++i) {
+        WindowArgs<T> a = window_args<T>(c, i, 0, 0, nullptr);
+        HIPCHK(launch_fill_zero<uint32_t>(a.freemap, (size_t)a.words, c->stream), "ap_init");
+        a.count = cnt;
+        a.count_free = cnt + 1 + i;
+        HIPCHK(launch_window_init<T>(a, c->stream), "ap_init");
+    }
+    unsigned long long h[kWinCounters];
+    HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream), "ap_init");
+    HIPCHK(hipStreamSynchronize(c->stream), "ap_init");
+    HIPCHK(launch_fill_zero<unsigned long long>(cnt, kWinCounters, c->stream), "ap_init");
+    if (h[0] != 0) return fail(AP_E_ARG, "particle ids must lie in [0, n) (moving window)");
+    for (int i = 0; i < s.nsp; ++i) c->n_free[i] = (int64_t)h[1 + i];
+    return AP_OK;
+}
+
+// One shift of the ring window: the storage column that leaves (the
+// window's first column for dir = +1, its last for dir = -1) is cleared and
+// becomes the entering column; its particles are freed and the injected ones
+// take the smallest free ids.  One synchronisation, for the checks.
+template <typename T> ap_status shift_window_impl(ap_ctx *c, int32_t dir, const ap_inject *inject) {
+    const RunShape &s = c->s;
+    const int nx = s.n[0];
+    const int col = dir > 0 ? s.xo : (s.xo + nx - 1) % nx;
+    const int in_col = dir > 0 ? nx - 1 : 0;
+    unsigned long long *cnt = c->wp<unsigned long long>(c->L.wcnt);
     // validate everything before changing anything
-    int64_t free_after = 0;
     for (int i = 0; i < s.nsp; ++i) {
         const int64_t k = inject ? inject[i].n : 0;
         if (k < 0 || k > s.np[i]) return fail(AP_E_ARG, "species " + std::to_string(i) + ": bad injection count");
@@ -1622,81 +1721,58 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, const ap_inject *in
             if (!okp) return fail(AP_E_ARG, "species " + std::to_string(i) + ": a required injection array is NULL");
         }
     }
-    auto args = [&](int i) {
-        const ap_particles &p = c->buf.sp[i];
-        WindowArgs<T> a{};
-        a.cell = p.cell;
-        a.id = p.id;
-        for (int k = 0; k < 3; ++k) {
-            a.off[k] = axis_active(s.dim, k) ? static_cast<T *>(p.off[k]) : nullptr;
-            a.u[k] = static_cast<T *>(p.u[k]);
-        }
-        a.w = static_cast<T *>(p.w);
-        a.proxy = s.has_proxy[i] ? static_cast<T *>(p.proxy) : nullptr;
-        a.n = (int32_t)s.np[i];
-        a.ncell = (uint32_t)s.ncell;
-        a.nx = s.n[0];
-        a.fnx = FastDiv((uint32_t)s.n[0]);
-        a.flag = c->wp<int32_t>(L.wflag[i]);
-        a.rank = c->wp<int32_t>(L.wrank[i]);
-        a.bad = bad;
-        if (inject && inject[i].n > 0) {
-            const ap_inject &in = inject[i];
-            a.in_cell = in.cell;
-            for (int k = 0; k < 3; ++k) {
-                a.in_off[k] = axis_active(s.dim, k) ? static_cast<const T *>(in.off[k]) : nullptr;
-                a.in_u[k] = static_cast<const T *>(in.u[k]);
-            }
-            a.in_w = static_cast<const T *>(in.w);
-            a.n_inj = (int32_t)in.n;
-        }
-        return a;
-    };
-    // every species: injected particles checked (counter bad), ids checked
-    // (counter bad + 1), free slots marked by id and ranked; one synchronisation
-    HIPCHK(launch_fill_zero<unsigned long long>(bad, 2, c->stream), "shift window");
-    int32_t nfree[kMaxSpecies] = {0, 0, 0, 0};
+    // injected particles checked; the leavers of the last shift read back;
+    // where the injection exceeds the free slots known so far, this shift's
+    // leavers counted ahead
+    for (int i = 0; i < s.nsp; ++i) {
+        WindowArgs<T> a = window_args<T>(c, i, col, in_col, inject);
+        a.count = cnt;
+        HIPCHK(launch_window_check_inject<T>(a, c->stream), "shift window");
+        a.count = cnt + 1 + kMaxSpecies + i;
+        if (inject && inject[i].n > c->n_free[i]) HIPCHK(launch_window_count_leavers<T>(a, c->stream), "shift window");
+    }
+    unsigned long long h[kWinCounters];
+    HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->stream), "shift window");
+    HIPCHK(hipStreamSynchronize(c->stream), "shift window");
+    HIPCHK(launch_fill_zero<unsigned long long>(cnt, kWinCounters, c->stream), "shift window");
+    for (int i = 0; i < s.nsp; ++i) c->n_free[i] += (int64_t)h[1 + i];
+    if (h[0] != 0)
+        return fail(AP_E_ARG, "injected particles must sit in the entering column (window column " +
+                                  std::to_string(in_col) + ") with offsets in [0, 1)");
+    for (int i = 0; i < s.nsp; ++i) {
+        const int64_t k = inject ? inject[i].n : 0;
+        const int64_t avail = c->n_free[i] + (k > c->n_free[i] ? (int64_t)h[1 + kMaxSpecies + i] : 0);
+        if (k > avail)
+            return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(k) +
+                                      " injected particles but " + std::to_string(avail) + " free slots");
+    }
+    // apply: the column's fields, then per species leavers and injection
+    T *grid = static_cast<T *>(c->buf.grid);
+    T *F[6];
+    for (int k = 0; k < 6; ++k) F[k] = grid + (size_t)k * (size_t)s.ncell;
+    HIPCHK(launch_window_column<T>(F, col, nx, (size_t)s.ncell, c->stream), "shift window");
     for (int i = 0; i < s.nsp; ++i) {
         if (s.np[i] == 0) continue;
-        WindowArgs<T> a = args(i);
-        HIPCHK(launch_window_check_inject<T>(a, c->stream), "shift window");
-        a.bad = bad + 1;
-        HIPCHK(launch_fill_zero<int32_t>(a.flag, (size_t)s.np[i], c->stream), "shift window");
-        HIPCHK(launch_window_mark<T>(a, c->stream), "shift window");
-        HIPCHK(launch_scan(a.flag, c->wp<int32_t>(L.wrank[i]), (int32_t)s.np[i], c->wp<int32_t>(L.wpart),
-                           c->stream), "shift window");
-        HIPCHK(hipMemcpyAsync(&nfree[i], c->wp<int32_t>(L.wrank[i]) + s.np[i], 4, hipMemcpyDeviceToHost, c->stream),
-               "shift window");
+        WindowArgs<T> a = window_args<T>(c, i, col, in_col, inject);
+        a.count = cnt + 1 + i;   // leavers, read back at the next shift
+        HIPCHK(launch_window_leave<T>(a, c->stream), "shift window");
+        if (a.n_inj == 0) continue;
+        int32_t *pop = c->wp<int32_t>(c->L.wpop);
+        int32_t *frank = c->wp<int32_t>(c->L.wfrank);
+        HIPCHK(launch_window_popcount(a.freemap, a.words, pop, c->stream), "shift window");
+        HIPCHK(launch_scan(pop, frank, a.words, c->wp<int32_t>(c->L.wpart), c->stream), "shift window");
+        HIPCHK(launch_window_fill<T>(a, c->stream), "shift window");
+        HIPCHK(launch_window_clear(a.freemap, frank, a.words, a.n_inj, c->stream), "shift window");
+        c->n_free[i] -= a.n_inj;
     }
-    unsigned long long b[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(b, bad, sizeof(b), hipMemcpyDeviceToHost, c->stream), "shift window");
-    HIPCHK(hipStreamSynchronize(c->stream), "shift window");
-    if (b[0] != 0 || b[1] != 0) {
-        HIPCHK(launch_fill_zero<unsigned long long>(bad, 2, c->stream), "shift window");
-        return fail(AP_E_ARG, b[0] != 0 ? "injected particles must sit in the new last column with offsets in [0, 1)"
-                                        : "particle ids are not a permutation of 0..n-1");
-    }
-    for (int i = 0; i < s.nsp; ++i) {
-        if (inject && inject[i].n > nfree[i])
-            return fail(AP_E_ARG, "species " + std::to_string(i) + ": " + std::to_string(inject[i].n) +
-                                      " injected particles but " + std::to_string(nfree[i]) + " free slots");
-        free_after += nfree[i] - (inject ? inject[i].n : 0);
-    }
-    // apply: fields, then each species from its ranks
-    T *grid = static_cast<T *>(c->buf.grid);
-    const size_t nc = (size_t)s.ncell;
-    T *F[6];
-    for (int k = 0; k < 6; ++k) F[k] = grid + (size_t)k * nc;
-    T *tmp = c->wp<T>(L.wtmp);
-    HIPCHK(hipMemcpyAsync(tmp, grid, 6 * nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "shift window");
-    HIPCHK(launch_window_fields<T>(F, tmp, s.n[0], nc, c->stream), "shift window");
-    for (int i = 0; i < s.nsp; ++i)
-        if (s.np[i] > 0) HIPCHK(launch_window_apply<T>(args(i), c->stream), "shift window");
-    HIPCHK(hipStreamSynchronize(c->stream), "shift window");
-    c->s.x_min[0] += s.dx[0];
-    c->need_sort = true;
+    c->s.x_min[0] += dir * s.dx[0];
+    c->s.xo = (s.xo + dir + nx) % nx;
+    // 2-D and 3-D pushes take particles outside their tile; 1-D rows need
+    // every particle in its row's range, and the 3-D re-sort ranks the last
+    // push wrote no longer match the freed and filled slots
+    if (s.dim != 2) c->need_sort = true;
+    c->keys_valid = false;
     c->rec_n = 0;
-    c->n_free = free_after;
     return AP_OK;
 }
 
@@ -1771,6 +1847,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sc.w_dst = c->wp<T>(L.alt_w[i]);
             sc.id_src = p.id;
             sc.id_dst = c->wp<int32_t>(L.alt_id[i]);
+            sc.free_slot = (s.options & AP_GRID_MOVING_WINDOW) ? c->wp<int32_t>(L.wslot[i]) : nullptr;
             sc.proxy_src = s.has_proxy[i] ? static_cast<const T *>(p.proxy) : nullptr;
             sc.proxy_dst = s.has_proxy[i] ? c->wp<T>(L.alt_proxy[i]) : nullptr;
             sc.rank = rank;
@@ -1875,6 +1952,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         io.q_over_m = s.q[i] / s.m[i];
         io.q = s.q[i];
     }
+    a.xo = s.xo;
     for (int k = 0; k < 3; ++k) {
         a.E[k] = F[k];
         a.B[k] = F[3 + k];
@@ -1913,6 +1991,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
             sa.F[k] = F[k];
             sa.S[k] = S + (size_t)k * nc;
         }
+        sa.xo = s.xo;
         for (int k = 0; k < 3; ++k) {
             sa.n[k] = s.n[k];
             sa.dx[k] = s.dx[k];
@@ -1988,6 +2067,7 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         // Sec. IV: E2, B2 are driven by J - J1, J1 at t^{n+1/2}
         Timer tm(c, 3);
         CurrentArgs<T> ca{};
+        ca.xo = s.xo;
         for (int k = 0; k < 3; ++k) {
             ca.J[k] = F[6 + k];
             ca.n[k] = s.n[k];

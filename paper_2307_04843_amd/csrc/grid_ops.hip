@@ -1,6 +1,8 @@
 // Grid-side kernels: Yee update of E2, B2 only, J clear, tile sort,
 // FP64 diagnostics (moments, energies, charge density, continuity residual).
+#include <algorithm>
 #include <climits>
+#include <cstdint>
 
 #include "kernels.h"
 
@@ -201,6 +203,7 @@ template hipError_t launch_fill_zero<float>(float *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<double>(double *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<int32_t>(int32_t *, size_t, hipStream_t);
 template hipError_t launch_fill_zero<unsigned long long>(unsigned long long *, size_t, hipStream_t);
+template hipError_t launch_fill_zero<uint32_t>(uint32_t *, size_t, hipStream_t);
 
 // Emission proxy of each particle: its compensated pair (sum s, compensation
 // c) read out as the FP64 value s - c, in slot order.
@@ -264,7 +267,8 @@ __global__ __launch_bounds__(256) void k_tile_count(SortArgs a) {
     int key = -1;
     if (p < a.n) {
         const int cell = a.cell[p];
-        key = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+        key = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
+                                       : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
     }
     int km = key >= 0 ? key : INT_MAX;
 #pragma unroll
@@ -422,80 +426,175 @@ hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, in
     return hipGetLastError();
 }
 
-// ---- moving window (Sec. III.C)
+// ---- moving window (Sec. III.C): ring along x, a shift moves the origin
 
-// Per particle: the slot becomes free if it is free already or its particle
-// sits in the first column (it falls behind the window); recorded by id, so
-// that free slots rank in id order whatever the tile order.
-template <typename T> __global__ __launch_bounds__(256) void k_window_mark(WindowArgs<T> a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const int id = a.id[p];
-    if ((unsigned)id >= (unsigned)a.n) {
-        atomicAdd(a.bad, 1ull);
-        return;
-    }
-    const int cell = a.cell[p];
-    const bool dead = (unsigned)cell >= a.ncell;
-    const bool leaves = !dead && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == 0;
-    a.flag[id] = (dead || leaves) ? 1 : 0;
+template <typename T> AP_D bool window_leaves(const WindowArgs<T> &a, int cell) {
+    return (unsigned)cell < a.ncell && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == a.col;
 }
 
-// Injected particles must sit in the new last column with offsets in [0, 1).
+// Wave-aggregated count of the lanes where f holds.
+AP_D void wave_count(bool f, unsigned long long *count) {
+    const unsigned long long b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_window_init(WindowArgs<T> a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false, free_slot = false;
+    if (p < a.n) {
+        const int id = a.id[p];
+        bad = (unsigned)id >= (unsigned)a.n;
+        free_slot = !bad && a.cell[p] == kDeadCell;
+        if (free_slot) {
+            atomicOr(&a.freemap[id >> 5], 1u << (id & 31));
+            a.free_slot[id] = p;
+        }
+    }
+    wave_count(bad, a.count);
+    wave_count(free_slot, a.count_free);
+}
+
 template <typename T> __global__ __launch_bounds__(256) void k_window_check_inject(WindowArgs<T> a) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.n_inj) return;
     const int cell = a.in_cell[r];
-    bool ok = (unsigned)cell < a.ncell && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == a.nx - 1;
+    bool ok = (unsigned)cell < a.ncell && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == a.in_col;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         if (a.in_off[k]) ok = ok && a.in_off[k][r] >= T(0) && a.in_off[k][r] < T(1);
-    if (!ok) atomicAdd(a.bad, 1ull);
+    if (!ok) atomicAdd(a.count, 1ull);
 }
 
-// Apply the shift: particles move down one cell; the free slots (ranked by
-// id) take the injected particles in order, the rest stay free.
-template <typename T> __global__ __launch_bounds__(256) void k_window_apply(WindowArgs<T> a) {
+template <typename T> __global__ __launch_bounds__(256) void k_window_count_leavers(WindowArgs<T> a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const int cell = a.cell[p];
-    const bool dead = (unsigned)cell >= a.ncell;
-    const bool leaves = !dead && cell - (int)a.fnx.div((uint32_t)cell) * a.nx == 0;
-    if (!(dead || leaves)) {
-        a.cell[p] = cell - 1;
-        return;
-    }
-    const int r = a.rank[a.id[p]];
-    const bool inj = r < a.n_inj;
-    a.cell[p] = inj ? a.in_cell[r] : kDeadCell;
+    wave_count(p < a.n && window_leaves(a, a.cell[p]), a.count);
+}
+
+// A particle in the leaving column falls behind the window: its slot is
+// freed (state zeroed), its id joins the free ids and records the slot.
+template <typename T> AP_D void window_free(const WindowArgs<T> &a, int p) {
+    a.cell[p] = kDeadCell;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (a.off[k]) a.off[k][p] = inj ? a.in_off[k][r] : T(0);
-        a.u[k][p] = inj ? a.in_u[k][r] : T(0);
+        if (a.off[k]) a.off[k][p] = T(0);
+        a.u[k][p] = T(0);
     }
-    a.w[p] = inj ? a.in_w[r] : T(0);
+    a.w[p] = T(0);
     if (a.proxy) {
         a.proxy[2 * p] = T(0);
         a.proxy[2 * p + 1] = T(0);
     }
+    const int id = a.id[p];
+    atomicOr(&a.freemap[id >> 5], 1u << (id & 31));
+    a.free_slot[id] = p;
 }
 
-template <typename T> __global__ __launch_bounds__(256) void k_window_fields(T *F0, T *F1, T *F2, T *F3, T *F4,
-                                                                             T *F5, const T *tmp, int32_t nx,
-                                                                             FastDiv fnx, size_t ncell) {
-    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < ncell; c += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t cc = (uint32_t)c;
-        const int i = (int)(cc - fnx.div(cc) * (uint32_t)nx);
-        const bool last = i == nx - 1;
-        T *F[6] = {F0, F1, F2, F3, F4, F5};
+// Grid-stride pass over the cells, four per 16-byte load when the array is
+// 16-byte aligned (leavers are rare: one column of the window).
+template <typename T> __global__ __launch_bounds__(256) void k_window_leave(WindowArgs<T> a, int vec) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    int cnt = 0;
+    int done = 0;
+    if (vec) {
+        const int nq = a.n >> 2;
+        const int4 *c4 = reinterpret_cast<const int4 *>(a.cell);
+        for (int q = g; q < nq; q += stride) {
+            const int4 c = c4[q];
+            const int p = q << 2;
+            if (window_leaves(a, c.x)) { window_free(a, p); ++cnt; }
+            if (window_leaves(a, c.y)) { window_free(a, p + 1); ++cnt; }
+            if (window_leaves(a, c.z)) { window_free(a, p + 2); ++cnt; }
+            if (window_leaves(a, c.w)) { window_free(a, p + 3); ++cnt; }
+        }
+        done = nq << 2;
+    }
+    for (int p = done + g; p < a.n; p += stride)
+        if (window_leaves(a, a.cell[p])) { window_free(a, p); ++cnt; }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) F[k][c] = last ? T(0) : tmp[(size_t)k * ncell + c + 1];
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(a.count, (unsigned long long)cnt);
+}
+
+__global__ __launch_bounds__(256) void k_window_popcount(const uint32_t *freemap, int32_t words, int32_t *pop) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < words) pop[w] = __popc(freemap[w]);
+}
+
+template <typename T> AP_D void window_put(const WindowArgs<T> &a, int p, int r) {
+    const int ic = a.in_cell[r];
+    const int row = (int)a.fnx.div((uint32_t)ic);
+    a.cell[p] = row * a.nx + a.col;   // the entering column is the storage column that left
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (a.off[k]) a.off[k][p] = a.in_off[k][r];
+        a.u[k][p] = a.in_u[k][r];
+    }
+    a.w[p] = a.in_w[r];
+}
+
+// Injected particle r takes the r-th smallest free id (the word holding it by
+// binary search of the popcount scan, then the bit) and that id's slot, when
+// the slot hint is still right.
+template <typename T> __global__ __launch_bounds__(256) void k_window_fill_hint(WindowArgs<T> a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_inj) return;
+    int lo = 0, hi = a.words - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.frank[mid] <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    uint32_t bits = a.freemap[lo];
+    for (int k = r - a.frank[lo]; k > 0 && bits; --k) bits &= bits - 1u;
+    const int id = (lo << 5) + __ffs(bits) - 1;
+    const int p = (bits && id < a.n) ? a.free_slot[id] : -1;
+    if ((unsigned)p < (unsigned)a.n && a.cell[p] == kDeadCell && a.id[p] == id) window_put(a, p, r);
+    else atomicAdd(a.miss, 1ull);
+}
+
+// The rest (only when a hint was stale): every free slot whose id ranks
+// below n_inj takes its particle; slots filled above are no longer free.
+template <typename T> __global__ __launch_bounds__(256) void k_window_fill_scan(WindowArgs<T> a) {
+    if (*a.miss == 0) return;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < a.n; p += gridDim.x * blockDim.x) {
+        if (a.cell[p] != kDeadCell) continue;
+        const int id = a.id[p];
+        const uint32_t bits = a.freemap[id >> 5];
+        const int r = a.frank[id >> 5] + __popc(bits & ((1u << (id & 31)) - 1u));
+        if (r < a.n_inj) window_put(a, p, r);
     }
 }
 
-template <typename T> hipError_t launch_window_mark(const WindowArgs<T> &a, hipStream_t s) {
+// Clears the bits of the ids ranked below n_inj: in word w, the first
+// n_inj - frank[w] set bits.
+__global__ __launch_bounds__(256) void k_window_clear(uint32_t *freemap, const int32_t *frank, int32_t words,
+                                                      int32_t n_inj) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= words) return;
+    int take = n_inj - frank[w];
+    if (take <= 0) return;
+    uint32_t bits = freemap[w];
+    while (take > 0 && bits) {
+        bits &= bits - 1u;   // clear the lowest set bit
+        --take;
+    }
+    freemap[w] = bits;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_window_column(T *F0, T *F1, T *F2, T *F3, T *F4, T *F5, int32_t col,
+                                                       int32_t nx, size_t rows) {
+    for (size_t r = blockIdx.x * (size_t)blockDim.x + threadIdx.x; r < rows; r += (size_t)gridDim.x * blockDim.x) {
+        const size_t c = r * (size_t)nx + (size_t)col;
+        F0[c] = T(0); F1[c] = T(0); F2[c] = T(0);
+        F3[c] = T(0); F4[c] = T(0); F5[c] = T(0);
+    }
+}
+
+template <typename T> hipError_t launch_window_init(const WindowArgs<T> &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_window_mark<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_window_init<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> &a, hipStream_t s) {
@@ -503,42 +602,64 @@ template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> 
     hipLaunchKernelGGL((k_window_check_inject<T>), dim3((a.n_inj + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
-template <typename T> hipError_t launch_window_apply(const WindowArgs<T> &a, hipStream_t s) {
+template <typename T> hipError_t launch_window_count_leavers(const WindowArgs<T> &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_window_apply<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_window_count_leavers<T>), dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_window_leave(const WindowArgs<T> &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const int vec = (reinterpret_cast<uintptr_t>(a.cell) & 15u) == 0 ? 1 : 0;
+    const int items = vec ? (a.n + 3) / 4 : a.n;
+    const int blocks = std::min((items + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_window_leave<T>), dim3(blocks), dim3(256), 0, s, a, vec);
+    return hipGetLastError();
+}
+hipError_t launch_window_popcount(const uint32_t *freemap, int32_t words, int32_t *pop, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_window_popcount, dim3((words + 255) / 256), dim3(256), 0, s, freemap, words, pop);
+    return hipGetLastError();
+}
+template <typename T> hipError_t launch_window_fill(const WindowArgs<T> &a, hipStream_t s) {
+    if (a.n == 0 || a.n_inj == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_window_fill_hint<T>), dim3((a.n_inj + 255) / 256), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_window_fill_scan<T>), dim3(std::min((a.n + 255) / 256, 2048)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_window_clear(uint32_t *freemap, const int32_t *frank, int32_t words, int32_t n_inj,
+                               hipStream_t s) {
+    if (words == 0 || n_inj == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_window_clear, dim3((words + 255) / 256), dim3(256), 0, s, freemap, frank, words, n_inj);
     return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_window_fields(T *const F[6], const T *tmp, int32_t nx, size_t ncell, hipStream_t s) {
-    hipLaunchKernelGGL((k_window_fields<T>), dim3(grid_blocks(ncell)), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4],
-                       F[5], tmp, nx, FastDiv((uint32_t)nx), ncell);
+hipError_t launch_window_column(T *const F[6], int32_t col, int32_t nx, size_t ncell, hipStream_t s) {
+    const size_t rows = ncell / (size_t)nx;
+    hipLaunchKernelGGL((k_window_column<T>), dim3(grid_blocks(rows)), dim3(256), 0, s, F[0], F[1], F[2], F[3], F[4],
+                       F[5], col, nx, rows);
     return hipGetLastError();
 }
-__global__ __launch_bounds__(256) void k_count_free(const int32_t *cell, int32_t n, unsigned long long *count) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool f = p < n && cell[p] == kDeadCell;
-    const unsigned long long b = __ballot(f);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
-}
-hipError_t launch_count_free(const int32_t *cell, int32_t n, unsigned long long *count, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_count_free, dim3((n + 255) / 256), dim3(256), 0, s, cell, n, count);
-    return hipGetLastError();
-}
-template hipError_t launch_window_mark<float>(const WindowArgs<float> &, hipStream_t);
-template hipError_t launch_window_mark<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_init<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_init<double>(const WindowArgs<double> &, hipStream_t);
 template hipError_t launch_window_check_inject<float>(const WindowArgs<float> &, hipStream_t);
 template hipError_t launch_window_check_inject<double>(const WindowArgs<double> &, hipStream_t);
-template hipError_t launch_window_apply<float>(const WindowArgs<float> &, hipStream_t);
-template hipError_t launch_window_apply<double>(const WindowArgs<double> &, hipStream_t);
-template hipError_t launch_window_fields<float>(float *const[6], const float *, int32_t, size_t, hipStream_t);
-template hipError_t launch_window_fields<double>(double *const[6], const double *, int32_t, size_t, hipStream_t);
+template hipError_t launch_window_count_leavers<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_count_leavers<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_leave<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_leave<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_fill<float>(const WindowArgs<float> &, hipStream_t);
+template hipError_t launch_window_fill<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_column<float>(float *const[6], int32_t, int32_t, size_t, hipStream_t);
+template hipError_t launch_window_column<double>(double *const[6], int32_t, int32_t, size_t, hipStream_t);
 
 template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterArgs<T> a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     const int cell = a.cell_src[p];
-    const int tile = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+    const int tile = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
+                                              : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
     // Place the particle at its tile slot.  Ranks follow the previous order
     // (a wave's lanes rank in lane order).  When that order is cell-major
     // (about M particles per cell), a ragged transpose of the tile's rank
@@ -564,6 +685,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_scatter(ScatterAr
     }
     a.w_dst[d] = a.w_src[p];
     a.id_dst[d] = a.id_src[p];
+    if (a.free_slot && cell == kDeadCell) a.free_slot[a.id_src[p]] = d;
     if (a.proxy_src) {
         a.proxy_dst[2 * d] = a.proxy_src[2 * p];
         a.proxy_dst[2 * d + 1] = a.proxy_src[2 * p + 1];
@@ -595,7 +717,8 @@ __global__ __launch_bounds__(256) void k_resort_perm(PermArgs a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     const int cell = a.cell[p];
-    const int t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile) : 0;
+    const int t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
+                                           : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
     const int k = a.key[p];
     const int slot = k >= 0 ? k : a.stay[t] + atomicAdd(&a.mrank[t], 1);
     a.perm[a.start[t] + slot] = p;

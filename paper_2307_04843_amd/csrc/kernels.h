@@ -61,7 +61,8 @@ template <typename T> struct PushArgs {
     int32_t xcd_chunk;           // 3-D: consecutive logical tiles per XCD run (block -> tile map)
     int32_t reg[3];              // LDS region extent per axis
     double dx[3];
-    double x_min[3];
+    double x_min[3];             // lab position of the window's first node
+    int32_t xo;                  // moving window: storage column of the window's first column
     double dt;
     double t;                    // time of the positions read (t^n)
     unsigned long long *n_fast;  // moves the kernel could not take (dropped), see push_move_ok
@@ -99,6 +100,7 @@ template <typename T> struct SampleArgs {
     FastDiv fnx, fnxy;
     double dx[3];
     double x_min[3];
+    int32_t xo;                  // moving window origin (storage column of window column 0)
     double q_slice;              // lab y of an (x, z) grid
     PulseVar<T> W;               // pulse constants of this step
     int32_t fd_b;                // B1 with the finite-duration correction of an analytic current
@@ -114,6 +116,7 @@ template <typename T> struct CurrentArgs {
     FastDiv fnx, fnxy;
     double dx[3];
     double x_min[3];
+    int32_t xo;                  // moving window origin
     double q_slice;
     PulseVar<T> W;               // pulse constants at t^{n+1/2}
     double wp2z;                 // omega_p^2 zeta / omega
@@ -144,6 +147,7 @@ template <typename T> struct AdjointArgs {
     double q_over_m;
     double dx[3];
     double x_min[3];
+    int32_t xo;                  // moving window origin (gridded runs)
     double dt;
     double t;
     PulseDev P;
@@ -228,9 +232,22 @@ hipError_t launch_tile_count(const SortArgs &a, hipStream_t s);
 int32_t scan_part_len(int32_t n_tiles);
 hipError_t launch_scan(const int32_t *count, int32_t *start, int32_t n_tiles, int32_t *part, hipStream_t s);
 
-// Moving window (Sec. III.C): the window advances one cell along +x.  A free
-// particle slot holds cell kDeadCell, zero weight, momentum and offsets.
+// Moving window (Sec. III.C).  The grid is a ring along x: window column l
+// lives in storage column (l + xo) mod nx, so a shift moves the origin xo
+// instead of the data.  A free particle slot holds cell kDeadCell and zero
+// offsets, momentum and weight (its id is a free id).
 constexpr int32_t kDeadCell = -1;
+
+// Tile of a free or invalid slot p in the tile sort and the 3-D re-sort:
+// blocks of 256 such slots are spread over the tiles, so that spare capacity
+// does not pile up in one tile (the push skips them at the cost of a load).
+AP_D inline int dead_tile(int p, int ntiles) { return (int)(((unsigned)p >> 8) % (unsigned)ntiles); }
+
+// Window column of storage column i (origin xo, nx columns).
+AP_D inline int win_col(int i, int xo, int nx) {
+    const int l = i - xo;
+    return l < 0 ? l + nx : l;
+}
 
 // A particle the push can advance has finite momentum and weight (a
 // non-finite one would put NaN into the current); its cell and offsets are
@@ -254,20 +271,41 @@ template <typename T> struct WindowArgs {
     uint32_t ncell;
     int32_t nx;
     FastDiv fnx;
-    int32_t *flag;               // [n], by id: 1 if the slot is free after the shift
-    const int32_t *rank;         // [n + 1]: exclusive scan of flag, rank[n] = free slots
-    const int32_t *in_cell;      // injected particles (device, n_inj): cells in the new last column
+    int32_t col;                 // storage column leaving the window (it becomes the entering one)
+    uint32_t *freemap;           // bit id set: the particle id is free (its slot holds no particle)
+    const int32_t *frank;        // [words + 1]: exclusive scan of the popcounts of freemap's words
+    int32_t words;               // ceil(n / 32)
+    const int32_t *in_cell;      // injected particles (device, n_inj): window cells, entering column
     const T *in_off[3]; const T *in_u[3]; const T *in_w;
     int32_t n_inj;
-    unsigned long long *bad;     // ids out of range / injected particles outside the new column
+    int32_t in_col;              // window column the injected particles must sit in
+    unsigned long long *count;   // bad ids / bad injected particles / leavers
+    unsigned long long *count_free;   // free slots (window_init)
+    int32_t *free_slot;          // [n] by id: the slot a free id was last seen in (a hint, verified on use)
+    unsigned long long *miss;    // injected particles whose hint was stale (window_fill)
 };
-template <typename T> hipError_t launch_window_mark(const WindowArgs<T> &a, hipStream_t s);
-// *count += number of free slots (cell == kDeadCell) among n cells.
-hipError_t launch_count_free(const int32_t *cell, int32_t n, unsigned long long *count, hipStream_t s);
+// freemap from the free slots (bits of their ids, the map zeroed first);
+// count[0] += ids out of range, count_free[0] += free slots.
+template <typename T> hipError_t launch_window_init(const WindowArgs<T> &a, hipStream_t s);
+// count[0] += injected particles outside the entering column or with offsets outside [0, 1).
 template <typename T> hipError_t launch_window_check_inject(const WindowArgs<T> &a, hipStream_t s);
-template <typename T> hipError_t launch_window_apply(const WindowArgs<T> &a, hipStream_t s);
-// E2, B2 (six components of ncell) move down one index along x from tmp (a copy); the last column is cleared.
-template <typename T> hipError_t launch_window_fields(T *const F[6], const T *tmp, int32_t nx, size_t ncell,
+// count[0] += particles in the leaving column (no change).
+template <typename T> hipError_t launch_window_count_leavers(const WindowArgs<T> &a, hipStream_t s);
+// Particles in the leaving column: freed (state zeroed, id bit set, slot
+// hint written); count[0] += leavers.
+template <typename T> hipError_t launch_window_leave(const WindowArgs<T> &a, hipStream_t s);
+// pop[w] = popcount(freemap[w]).
+hipError_t launch_window_popcount(const uint32_t *freemap, int32_t words, int32_t *pop, hipStream_t s);
+// The free ids ranked below n_inj take the injected particles in rank order
+// (cells mapped to storage through col): first through the slot hints (a
+// hint is used when its slot is free and holds that id, else *miss counts
+// it), then, only if *miss > 0, by a pass over every slot for the rest.
+template <typename T> hipError_t launch_window_fill(const WindowArgs<T> &a, hipStream_t s);
+// Clears the bits of the n_inj smallest free ids (after launch_window_fill).
+hipError_t launch_window_clear(uint32_t *freemap, const int32_t *frank, int32_t words, int32_t n_inj,
+                               hipStream_t s);
+// Zeroes storage column col of the six fields.
+template <typename T> hipError_t launch_window_column(T *const F[6], int32_t col, int32_t nx, size_t ncell,
                                                       hipStream_t s);
 
 template <typename T> struct ScatterArgs {
@@ -281,6 +319,7 @@ template <typename T> struct ScatterArgs {
     int32_t n, dim;
     FastDiv fnx, fnxy, ftx, fty, ftz;
     int32_t ntile[3];
+    int32_t *free_slot;          // moving window: slot of each free id (a hint), or null
 };
 template <typename T> hipError_t launch_scatter(const ScatterArgs<T> &a, hipStream_t s);
 

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_1d(PushArgs<T> a) {
 
             // ---- analytic E1, B1 at the particle (FP64 position)
             T e1[3], b1[3];
-            const double X = a.x_min[0] + ((double)i + (double)offx) * a.dx[0];
+            const double X = a.x_min[0] + ((double)win_col(i, a.xo, a.n[0]) + (double)offx) * a.dx[0];
             analytic_field<PT, T>(a.W, X, a.q_slice, Zrow, e1, b1);
             const T Ex = e1[0] + f[0], Ey = e1[1] + f[1], Ez = e1[2] + f[2];
             const T Bx = b1[0] + f[3], By = b1[1] + f[4], Bz = b1[2] + f[5];

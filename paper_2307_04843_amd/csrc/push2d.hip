@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 
             // ---- analytic E1, B1 at the particle (FP64 position)
             T e1[3], b1[3];
-            const double X = a.x_min[0] + ((double)i + (double)offx) * a.dx[0];
+            const double X = a.x_min[0] + ((double)win_col(i, a.xo, a.n[0]) + (double)offx) * a.dx[0];
             const double Z = a.x_min[2] + ((double)k + (double)offz) * a.dx[2];
             analytic_field<PT, T>(a.W, X, a.q_slice, Z, e1, b1);
             const T Ex = e1[0] + e2[0], Ey = e1[1] + e2[1], Ez = e1[2] + e2[2];

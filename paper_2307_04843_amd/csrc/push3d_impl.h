@@ -359,7 +359,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
                     S.proxy_out[2 * p + 1] = S.proxy_in[2 * q + 1];
                 }
                 if (!INPLACE && S.key_out) {
-                    int tnew = 0;
+                    int tnew = dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
                     if ((unsigned)cell < ncell) {
                         const int r = (int)a.fnx.div((unsigned)cell), k = (int)a.fnxy.div((unsigned)cell);
                         tnew = tile_of3(cell - r * nx, r - k * ny, k);
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
             }
 
             T e1[3], b1[3];
-            const double X = a.x_min[0] + ((double)idx[0] + (double)off[0]) * a.dx[0];
+            const double X = a.x_min[0] + ((double)win_col(idx[0], a.xo, a.n[0]) + (double)off[0]) * a.dx[0];
             const double Y = a.x_min[1] + ((double)idx[1] + (double)off[1]) * a.dx[1];
             const double Z = a.x_min[2] + ((double)idx[2] + (double)off[2]) * a.dx[2];
             analytic_field<PT, T>(a.W, X, Y, Z, e1, b1);

@@ -23,7 +23,7 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_sample_pu
             j = (int)(row - (uint32_t)k * a.n[1]);
         }
         // node and half-node coordinates per axis (lab, internal units)
-        const double xn = a.x_min[0] + (double)i * a.dx[0], xh = xn + 0.5 * a.dx[0];
+        const double xn = a.x_min[0] + (double)win_col(i, a.xo, a.n[0]) * a.dx[0], xh = xn + 0.5 * a.dx[0];
         // 1-D rows: no stagger across rows (every component sits at the row's z)
         const double zn = a.x_min[2] + (double)k * a.dx[2], zh = a.dim == 1 ? zn : zn + 0.5 * a.dx[2];
         const double yn = a.dim == 3 ? a.x_min[1] + (double)j * a.dx[1] : a.q_slice;
@@ -95,7 +95,7 @@ template <typename T, int PT> __global__ __launch_bounds__(256) void k_analytic_
             k = (int)a.fnxy.div((uint32_t)g);
             j = (int)(row - (uint32_t)k * a.n[1]);
         }
-        const double xn = a.x_min[0] + (double)i * a.dx[0], xh = xn + 0.5 * a.dx[0];
+        const double xn = a.x_min[0] + (double)win_col(i, a.xo, a.n[0]) * a.dx[0], xh = xn + 0.5 * a.dx[0];
         // 1-D rows: no stagger across rows (every component sits at the row's z)
         const double zn = a.x_min[2] + (double)k * a.dx[2], zh = a.dim == 1 ? zn : zn + 0.5 * a.dx[2];
         const double yn = a.dim == 3 ? a.x_min[1] + (double)j * a.dx[1] : a.q_slice;

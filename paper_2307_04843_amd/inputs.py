@@ -64,15 +64,17 @@ def pad_free(state, n_free, first_id):
     return out
 
 
-def window_column(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed, stream=0):
+def window_column(dim, n_cells, dx, x_min, ppc, density, temperature_ev, mass, seed, stream=0, column=None):
     """Particles of the column a moving window adds: ``plasma`` on a grid one
-    cell wide at lab x = x_min[0] + (n_cells[0] - 1) dx[0] (x_min is the new
-    window's origin), with cells renumbered into the last column of the full
-    grid."""
+    cell wide at window column ``column`` (default the last, n_cells[0] - 1;
+    0 for a window moving along -x), i.e. lab x = x_min[0] + column dx[0]
+    (x_min is the new window's origin), with cells renumbered into that
+    column of the full grid."""
     nx = n_cells[0]
-    col = plasma(dim, (1,) + tuple(n_cells[1:]), dx, (x_min[0] + (nx - 1) * dx[0],) + tuple(x_min[1:]), ppc,
+    c = nx - 1 if column is None else int(column)
+    col = plasma(dim, (1,) + tuple(n_cells[1:]), dx, (x_min[0] + c * dx[0],) + tuple(x_min[1:]), ppc,
                  density, temperature_ev, mass, seed, stream)
-    col["cell"] = (col["cell"].astype(np.int64) * nx + (nx - 1)).astype(np.int32)
+    col["cell"] = (col["cell"].astype(np.int64) * nx + c).astype(np.int32)
     return col
 
 

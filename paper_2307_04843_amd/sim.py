@@ -13,7 +13,7 @@ def _dev(x, np_dtype, dev):
     """Device tensor of a host array (converted to np_dtype) or of a tensor."""
     if isinstance(x, torch.Tensor):
         return x.to(device=dev, dtype=torch.from_numpy(np.zeros(0, np_dtype)).dtype).contiguous()
-    return torch.as_tensor(np.ascontiguousarray(x.astype(np_dtype)), device=dev)
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(x).astype(np_dtype)), device=dev)
 
 
 class Simulation:
@@ -27,8 +27,9 @@ class Simulation:
     ``pulse_on_grid``: the pulse may be sampled on the grid; ``open_x`` (1-D
     rows): incoming/outgoing-wave x ends, for pulses launched through x_min
     (``set_pulse(..., sampling="boundary")``); ``moving_window``: the window
-    can advance along x (``shift_window``); spare particle slots are passed as
-    free slots (cell -1, zero weight; ``inputs.pad_free``).
+    can move along +x or -x (``shift_window``, ``step_window``); spare
+    particle slots are passed as free slots (cell -1, zero weight;
+    ``inputs.pad_free``).
     """
 
     def __init__(self, dim, n=(1, 1, 1), dx=(1.0, 1.0, 1.0), x_min=(0.0, 0.0, 0.0), t0=0.0, dt=0.0,
@@ -38,6 +39,9 @@ class Simulation:
             raise RuntimeError("the HIP path needs a GPU")
         apt.load()
         self.dim = dim
+        self.n = tuple(int(v) for v in n)
+        self.dx = tuple(float(v) for v in dx)
+        self.moving_window = bool(moving_window)
         self.device = torch.device(device)
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         self.np_dtype = np.float64 if precision == "f64" else np.float32
@@ -125,10 +129,11 @@ class Simulation:
         ptype = apt.PULSE_TYPES[kind]
         apt.ap_set_pulse(self.ctx, ptype, apt.pulse_params(**params) if ptype != apt.AP_PULSE_NONE else None)
 
-    def shift_window(self, inject=None):
-        """Advance the window one cell along +x (ap_shift_window).  inject:
-        None or, per species, None or a state dict (cell, off, u, w) of the new
-        particles, cells in the new last column."""
+    def shift_window(self, inject=None, direction=1):
+        """Move the window one cell along +x (direction 1) or -x (-1)
+        (ap_shift_window).  inject: None or, per species, None or a state dict
+        (cell, off, u, w) of the new particles, cells in window columns (the
+        entering column: the last for +x, the first for -x)."""
         arr = None
         keep = []
         if inject is not None:
@@ -136,10 +141,10 @@ class Simulation:
             for i, st in enumerate(inject):
                 if st is None or len(st["w"]) == 0:
                     continue
-                cell = _dev(np.asarray(st["cell"]), np.int32, self.device)
-                off = [_dev(np.asarray(st["off"][k]), self.np_dtype, self.device) for k in range(3)]
-                u = [_dev(np.asarray(st["u"][k]), self.np_dtype, self.device) for k in range(3)]
-                w = _dev(np.asarray(st["w"]), self.np_dtype, self.device)
+                cell = _dev(st["cell"], np.int32, self.device)
+                off = [_dev(st["off"][k], self.np_dtype, self.device) for k in range(3)]
+                u = [_dev(st["u"][k], self.np_dtype, self.device) for k in range(3)]
+                w = _dev(st["w"], self.np_dtype, self.device)
                 keep += [cell, w] + off + u
                 arr[i].cell = cell.data_ptr()
                 for k in range(3):
@@ -147,8 +152,38 @@ class Simulation:
                     arr[i].u[k] = u[k].data_ptr()
                 arr[i].w = w.data_ptr()
                 arr[i].n = int(w.numel())
-        apt.ap_shift_window(self.ctx, arr)
+        apt.ap_shift_window(self.ctx, direction, arr)
         del keep
+
+    def window(self):
+        """(x_min in lambda, storage origin): window column l lives in storage
+        column (l + origin) mod n[0] of the fields and of the caller's cells."""
+        return apt.ap_get_window(self.ctx)
+
+    def window_due(self, beta, x_ref, t_ref):
+        return apt.ap_window_due(self.ctx, beta, x_ref, t_ref)
+
+    def step_window(self, n, beta, x_ref, t_ref, inject=None):
+        """n steps with the window following x_ref + beta (t - t_ref): before
+        each step, shift while a shift is due.  inject(direction, x_min_new):
+        None or the per-species injection of the entering column."""
+        shifts = 0
+        for _ in range(n):
+            while True:
+                d = self.window_due(beta, x_ref, t_ref)
+                if d == 0:
+                    break
+                x_new = self.window()[0] + d * self.dx[0]
+                self.shift_window(inject(d, x_new) if inject is not None else None, d)
+                shifts += d
+            self.step(1)
+        return shifts
+
+    def window_fields(self):
+        """Copies of E2, B2 in window column order (ring origin undone)."""
+        E, B, _ = self.field_views()
+        o = self.window()[1]
+        return [torch.roll(f, -o, dims=2).clone() for f in E], [torch.roll(f, -o, dims=2).clone() for f in B]
 
     def eval_pulse(self, xyz, t):
         """E1, B1 at lab points xyz (3, n) in lambda units, time t; numpy (3, n) arrays."""
@@ -180,7 +215,14 @@ class Simulation:
             out["icell"] = np.stack([a["icell"][k].cpu().numpy()[order] for k in range(3)])
             out["off"] = np.stack([a["off"][k].cpu().numpy()[order] for k in range(3)])
         else:
-            out["cell"] = a["cell"].cpu().numpy()[order]
+            cell = a["cell"].cpu().numpy()[order]
+            if self.moving_window:
+                # storage cells -> window cells (free slots keep -1)
+                o = self.window()[1]
+                nx = self.n[0]
+                col = cell % nx
+                cell = np.where(cell >= 0, cell - col + (col - o) % nx, cell)
+            out["cell"] = cell
             out["off"] = np.stack([a["off"][k].cpu().numpy()[order] if a["off"][k] is not None
                                    else np.zeros(len(ids), dtype=self.np_dtype) for k in range(3)])
         out["u"] = np.stack([a["u"][k].cpu().numpy()[order] for k in range(3)])

@@ -157,17 +157,44 @@ def test_open_x_option_rows_only():
 
 
 def test_moving_window_option():
-    """AP_GRID_MOVING_WINDOW reserves the shift's workspace on grids and is
-    rejected without one."""
+    """AP_GRID_MOVING_WINDOW reserves the shift's workspace on grids (the free-id
+    bit map, its word popcounts and their scan: no copy of the fields) and is
+    rejected without a grid or together with AP_GRID_OPEN_X."""
     g = _grid()
     base = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
     g.options = apt.AP_GRID_MOVING_WINDOW
-    assert apt.ap_query_layout(g, [_sp(2048)]).work_bytes >= base + 6 * 64 * 32 * 4 + 2 * 2048 * 4
+    extra = apt.ap_query_layout(g, [_sp(2048)]).work_bytes - base
+    assert 3 * 64 * 4 <= extra < 6 * 64 * 32 * 4
     g0 = _grid(dim=0)
     g0.dt = 0.01
     g0.options = apt.AP_GRID_MOVING_WINDOW
     with pytest.raises(apt.APTError, match="moving window"):
         apt.ap_query_layout(g0, [_sp()])
+    g.options = apt.AP_GRID_MOVING_WINDOW | apt.AP_GRID_OPEN_X
+    with pytest.raises(apt.APTError, match="exclude each other"):
+        apt.ap_query_layout(g, [_sp()])
+
+
+def test_window_calls_on_null_context():
+    lib = apt.load()
+    assert lib.ap_shift_window(None, 1, None) == apt.AP_E_ARG
+    assert lib.ap_get_window(None, None, None) == apt.AP_E_ARG
+    d = C.c_int32()
+    assert lib.ap_window_due(None, 1.0, 0.0, 0.0, C.byref(d)) == apt.AP_E_ARG
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    """Every kernel launcher the library calls is instantiated in it (a
+    missing template instantiation would only fail when loaded)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", apt.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    bad = [ln for ln in out.splitlines() if "_ZN3apt" in ln or " ap_" in ln]
+    assert not bad, bad
 
 
 def test_pulse_params_struct_matches_header():

@@ -1305,6 +1305,118 @@ def test_moving_window_weightless_run_equals_fixed_window():
     assert np.abs(x1 - x0).max() <= 1e-11 * L
 
 
+def test_moving_window_shift_minus_x_keeps_lab_state():
+    """A shift along -x keeps every lab position and lab field value: x_min
+    falls by dx, E2/B2 move up one index (new first column empty), particles
+    move up one cell; those in the last column leave and free their ids, and
+    injected particles (in the new first column) take the smallest free ids."""
+    rng = np.random.default_rng(9)
+    n = (12, 1, 6)
+    g = pic.Grid(2, n, (0.3, 0.3, 0.4), 0.1, (1.0, 0.0, -2.0))
+    for F in g.E + g.B:
+        F[...] = rng.standard_normal(F.shape)
+    E0 = [e.copy() for e in g.E]
+    B0 = [b.copy() for b in g.B]
+    N = 40
+    pos = np.zeros((3, N))
+    pos[0] = rng.uniform(0, n[0], N)
+    pos[2] = rng.uniform(0, n[2], N)
+    pos[0][:3] = [n[0] - 0.2, n[0] - 1.0, n[0] - 1.0 - 1e-9]
+    sp = pic.Species(-1.0, 1.0, pos, rng.standard_normal((3, N)), np.ones(N), ids=np.arange(N),
+                     free=np.arange(N, N + 10))
+    lab0 = g.x_min[0] + pos[0] * g.dx[0]
+    inj = (np.array([[0.5, 0.25], [0.0, 0.0], [1.5, 4.5]]), np.zeros((3, 2)), np.full(2, 0.5))
+    pic.shift_window(g, [sp], [inj], direction=-1)
+    assert g.x_min[0] == 1.0 - 0.3
+    for f, f0 in zip(g.E + g.B, E0 + B0):
+        assert np.array_equal(f[..., 1:], f0[..., :-1]) and not f[..., 0].any()
+    left = pos[0] >= n[0] - 1.0
+    assert left[:2].all() and not left[2]
+    assert sp.pos.shape[1] == N - left.sum() + 2
+    assert np.array_equal(sp.ids[:-2], np.arange(N)[~left])
+    lab1 = g.x_min[0] + sp.pos[0][:-2] * g.dx[0]
+    assert np.allclose(lab1, lab0[~left], rtol=0, atol=1e-14)
+    assert np.array_equal(sp.ids[-2:], np.sort(np.concatenate([np.arange(N)[left], np.arange(N, N + 10)]))[:2])
+    with pytest.raises(ValueError):
+        pic.shift_window(g, [sp], [None], direction=2)
+
+
+def test_moving_window_round_trip():
+    """A shift along +x then one along -x (nothing injected) restores every
+    field value but the first column (which left, and comes back empty) and
+    every particle but those of the first column, at their old positions;
+    the window returns to its x_min."""
+    rng = np.random.default_rng(10)
+    n = (10, 1, 5)
+    g = pic.Grid(2, n, (0.2, 0.2, 0.3), 0.05, (0.7, 0.0, 0.0))
+    for F in g.E + g.B:
+        F[...] = rng.standard_normal(F.shape)
+    F0 = [f.copy() for f in g.E + g.B]
+    N = 60
+    pos = np.stack([rng.uniform(0, n[0], N), np.zeros(N), rng.uniform(0, n[2], N)])
+    sp = pic.Species(1.0, 3.0, pos.copy(), rng.standard_normal((3, N)), rng.uniform(0.5, 1.0, N),
+                     ids=np.arange(N), free=np.arange(N, N))
+    u0 = sp.u.copy()
+    pic.shift_window(g, [sp], [None], direction=1)
+    pic.shift_window(g, [sp], [None], direction=-1)
+    assert g.x_min[0] == 0.7
+    for f, f0 in zip(g.E + g.B, F0):
+        assert np.array_equal(f[..., 1:], f0[..., 1:]) and not f[..., 0].any()
+    kept = pos[0] >= 1.0
+    assert np.array_equal(sp.ids, np.arange(N)[kept])
+    assert np.array_equal(sp.pos, pos[:, kept]) and np.array_equal(sp.u, u0[:, kept])
+    assert np.array_equal(sp.free, np.arange(N)[~kept])
+
+
+def test_window_schedule_follows_the_focus():
+    """window_due keeps x_ref + beta (t - t_ref) - x_min in [-dx/2, dx/2) at
+    every step (an exact tie included: 0.5 cell ahead at t = 0), for windows moving along -x at c, along +x at 1.5 c
+    (two shifts in some steps on a coarse grid) and at rest; the number of
+    shifts after n steps is the rounded displacement in cells."""
+    dx, dt = 1.0, 0.67 * 1.0
+    for beta in (-1.0, 1.5, 0.0, 0.3):
+        x_min, x_ref, t_ref = 5.0, 5.5, 0.0
+        shifts = 0
+        for n in range(200):
+            t = n * dt
+            while True:
+                d = pic.window_due(x_min, dx, t, beta, x_ref, t_ref)
+                if d == 0:
+                    break
+                x_min += d * dx
+                shifts += d
+            target = x_ref + beta * (t - t_ref)
+            assert -0.5 * dx <= target - x_min < 0.5 * dx
+        assert shifts == math.floor((x_ref + beta * 199 * dt - 5.0) / dx + 0.5)
+
+
+def test_moving_window_backward_weightless_run_equals_fixed_window():
+    """Weightless particles in an LG pulse: the same 30 steps with a window
+    moving along -x (shifted every 6 steps) and with the window at rest give
+    the same momenta and lab positions, particle by particle (ids)."""
+    from tests import cases
+    case = cases.make_case(n=(80, 1, 16), seed=13, u_scale=0.5, ppc=1)
+    runs = []
+    for shift in (False, True):
+        g, sps, P = cases.oracle_state(case)
+        for F in g.E + g.B:
+            F[...] = 0.0
+        sp = sps[0]
+        sp.w = np.zeros_like(sp.w)
+        keep = (sp.pos[0] >= 10.0) & (sp.pos[0] < 60.0)
+        sp.pos, sp.u, sp.w = sp.pos[:, keep], sp.u[:, keep], sp.w[keep]
+        sp.ids = np.arange(sp.w.size)
+        for k in range(30):
+            if shift and k % 6 == 5:
+                pic.shift_window(g, [sp], [None], direction=-1)
+            pic.step(g, [sp], P)
+        runs.append((sp.ids.copy(), sp.u.copy(), g.x_min[0] + sp.pos[0] * g.dx[0]))
+    (i0, u0, x0), (i1, u1, x1) = runs
+    assert np.array_equal(i0, i1) and i0.size > 400
+    assert np.abs(u1 - u0).max() <= 1e-11 * np.abs(u0).max()
+    assert np.abs(x1 - x0).max() <= 1e-11 * L
+
+
 def test_open_boundary_xz_grid_equals_rows():
     """On (x, z) and 3-D grids the open x ends launch a plane pulse exactly as
     the 1-D rows do (the fields do not vary across x, so the omitted
