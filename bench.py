@@ -496,13 +496,14 @@ def adjoint_pulse():
                 dispersion=2, pol=0)
 
 
-def run_adjoint(beam, precision, steps):
+def run_adjoint(beam, precision, steps, t0=ADJ_T0, revolve=None):
     """Forward (recording) + backward of the collision run; wall times and gradient."""
     import torch
     from paper_2307_04843_amd.autograd import APTRun, GridlessRun
     names = ["a0", "w0", "x_f"]
     vals = [20.0, 2.0, 0.0]
-    run = GridlessRun(beam, "gauss_np", adjoint_pulse(), names, steps, ADJ_DT, t0=ADJ_T0, precision=precision)
+    run = GridlessRun(beam, "gauss_np", adjoint_pulse(), names, steps, ADJ_DT, t0=t0, precision=precision,
+                      revolve=revolve)
     try:
         n = int(beam["u"].shape[1])
         p = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
@@ -515,9 +516,14 @@ def run_adjoint(beam, precision, steps):
         obs.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        return dict(forward_s=t1 - t0, backward_s=t2 - t1, grad=p.grad.tolist(), observable=float(obs.detach()),
-                    forward_pushes_per_s=n * steps / (t1 - t0), adjoint_pushes_per_s=n * steps / (t2 - t1),
-                    segment=run.segment, checkpoint_gb=run.ckpt.numel() / 1e9)
+        out = dict(forward_s=t1 - t0, backward_s=t2 - t1, grad=p.grad.tolist(), observable=float(obs.detach()),
+                   forward_pushes_per_s=n * steps / (t1 - t0), adjoint_pushes_per_s=n * steps / (t2 - t1),
+                   checkpoint_gb=run.ckpt.numel() / 1e9)
+        if revolve:
+            out["revolve_slots"] = revolve
+        else:
+            out["segment"] = run.segment
+        return out
     finally:
         run.close()
         del run
@@ -786,7 +792,75 @@ def adjoint_leg(args):
     return adj
 
 
-LEGS = ("headline", "pic2d", "adjoint", "three_d", "small", "rows1d", "cpu")
+ADJ_FULL_STEPS = 20000   # the collision run's length (t = 0 ... 200 lambda/c)
+ADJ_FULL_SLOTS = 64
+
+
+def adjoint_full_leg(args):
+    """The whole 20000-step collision run in FP32 (beam starting 100 lambda
+    ahead of the focus, so that it meets the pulse at t = 100 lambda/c),
+    differentiated with the binomial checkpoint schedule over 64 slots."""
+    from paper_2307_04843_amd import apt, inputs
+    steps = args.adj_full_steps
+    beam = inputs.beam(ADJ_N, 2000.0, 0.05, 1.0, 1.0, 100.0, 1.0, seed=3)
+    log("adjoint, whole run: %d steps, %d slots" % (steps, ADJ_FULL_SLOTS))
+    r = run_adjoint(beam, "f32", steps, t0=0.0, revolve=ADJ_FULL_SLOTS)
+    t, f = apt.ap_revolve_plan(steps, ADJ_FULL_SLOTS)
+    r.update({"workload": "gridless head-on collision, the whole run: 2^24 electrons, gamma 2000 (5%% spread), "
+                          "eps^4 nonparaxial Gaussian a0=20 w0=2 tau=20, dt=0.01, %d steps (t=0..%.0f), FP32, "
+                          "gradient of <p_perp^2> wrt (a0, w0, x_f)" % (steps, steps * ADJ_DT),
+              "particles": ADJ_N, "steps": steps, "revolve_repeats": t, "revolve_forward_steps": f,
+              "note": "binomial checkpointing: %d whole states (%.1f GB), the recording sweep plus %d re-advanced "
+                      "steps, then the reverse steps; backward_s covers re-advancing and reverse steps"
+                      % (ADJ_FULL_SLOTS, r["checkpoint_gb"], f)})
+    log("adjoint, whole run: forward %.1f s, backward %.1f s" % (r["forward_s"], r["backward_s"]))
+    return r
+
+
+def adjoint3d_long_leg(args):
+    """The 512 x 256 x 256 flying-focus run's frozen-grid adjoint over a long
+    window, binomial schedule over 16 whole states."""
+    import torch
+    from paper_2307_04843_amd import apt
+    from paper_2307_04843_amd.autograd import APTRun, GriddedRun
+    species = workload3d_inputs()
+    n = int(species[0]["state"]["u"].shape[1])
+    dt = 0.95 / math.sqrt(3) * DX3
+    pp = workload3d_pulse(dt)
+    steps, slots = args.adj3d_long_steps, 16
+    names = ["beta_f", "chirp"]
+    log("3-D adjoint, %d steps, %d slots" % (steps, slots))
+    run = GriddedRun(3, N3, (DX3,) * 3, (0.0, -8.0, -8.0), species, "ff", pp, names, steps,
+                     t0=T0_STEP3 * dt, dt=dt, precision="f32", revolve=slots)
+    try:
+        p = torch.tensor([pp["beta_f"], pp["chirp"]], dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        u, _ = APTRun.apply(p, run)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        obs = (u[1].double() ** 2 + u[2].double() ** 2).sum() / n
+        obs.backward()
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        t, f = apt.ap_revolve_plan(steps, slots)
+        out = {"workload": "3-D PIC 512x256x256, 268M electrons, flying focus beta_f=-1 chirp 5%%, steps "
+                           "%d..%d, frozen-grid adjoint of <p_perp^2> wrt (beta_f, chirp)"
+                           % (T0_STEP3, T0_STEP3 + steps),
+               "steps": steps, "revolve_slots": slots, "checkpoint_gb": run.ckpt.numel() / 1e9,
+               "revolve_repeats": t, "revolve_forward_steps": f, "grad": p.grad.tolist(),
+               "forward_s": b - a, "backward_s": c - b, "forward_pushes_per_s": n * steps / (b - a),
+               "adjoint_pushes_per_s": n * steps / (c - b)}
+        log("3-D adjoint: forward %.1f s, backward %.1f s" % (b - a, c - b))
+        return out
+    finally:
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
+
+LEGS = ("headline", "pic2d", "adjoint", "adjoint_full", "three_d", "small", "rows1d", "cpu")
+OPTIONAL_LEGS = ("adjoint3d_long",)
 
 
 def main():
@@ -797,11 +871,14 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=50, help="timed FP64 steps (at most --steps)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--legs", default=",".join(LEGS),
-                    help="comma-separated subset of %s (the headline line is always printed)" % ",".join(LEGS))
+                    help="comma-separated subset of %s, or the optional %s (the headline line is always "
+                         "printed)" % (",".join(LEGS), ",".join(OPTIONAL_LEGS)))
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--steps2d", type=int, default=100, help="timed steps of the 4096x1024 legs")
     ap.add_argument("--warmup2d", type=int, default=10)
     ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--adj-full-steps", type=int, default=ADJ_FULL_STEPS, help="whole-run adjoint length")
+    ap.add_argument("--adj3d-long-steps", type=int, default=1000, help="optional 3-D long adjoint window")
     ap.add_argument("--sort-every", type=int, default=0, help="2-D tile re-sort interval (0: library default)")
     ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 512x256x256 leg")
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
@@ -816,7 +893,7 @@ def main():
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x]
     for x in legs:
-        if x not in LEGS:
+        if x not in LEGS + OPTIONAL_LEGS:
             print("bench.py: unknown leg %r" % x, file=sys.stderr)
             sys.exit(2)
     import torch
@@ -842,6 +919,10 @@ def main():
         out["pic2d"] = pic2d_leg(args)
     if "adjoint" in legs:
         out["adjoint"] = adjoint_leg(args)
+    if "adjoint_full" in legs:
+        out["adjoint_full"] = adjoint_full_leg(args)
+    if "adjoint3d_long" in legs:
+        out["adjoint3d_long"] = adjoint3d_long_leg(args)
     if "three_d" in legs:
         out["three_d"] = three_d_leg(args)
     if "small" in legs:

@@ -411,6 +411,27 @@ ap_status ap_set_adjoint_mode(ap_ctx *ctx, int32_t mode);
  * (written to *bytes, host). */
 ap_status ap_checkpoint_bytes(const ap_ctx *ctx, int64_t n_steps, int32_t segment, size_t *bytes);
 
+/* Binomial checkpointing (the schedule of Griewank's revolve, restated): a
+ * fixed budget of `slots` whole states, whatever the number of recorded
+ * steps, at the cost of re-advancing.  With the state of step l stored and s
+ * slots free, C(s + t + 1, s + 1) steps are reversed when every step is
+ * advanced at most t times beyond the recording sweep; the recording sweep
+ * stores step 0 and the states of the recursion's first descent, and
+ * ap_backward runs the recursion (each reverse step reads its state from a
+ * slot: no replay buffer).  Gridless runs: slots + 1 slots of
+ * ap_layout.ckpt_slot_bytes; gridded runs: the whole state (every species,
+ * E2, B2) per slot, a copy of the final state and the FP64 adjoint state.
+ * Gradients equal those of ap_set_checkpoints' segments: bit for bit in
+ * gridless runs, up to the deposit's summation order in gridded ones.
+ * ap_set_revolve selects it (replacing segments; AP_E_ARG if slots < 1 or the
+ * buffer is smaller than ap_revolve_bytes); ap_set_checkpoints selects
+ * segments again.  ap_revolve_plan (no context) gives, for n_steps and
+ * slots, the repetitions t and the forward steps the reverse sweep takes
+ * (the recording sweep excluded). */
+ap_status ap_set_revolve(ap_ctx *ctx, void *dev, size_t bytes, int32_t slots);
+ap_status ap_revolve_bytes(const ap_ctx *ctx, int32_t slots, size_t *bytes);
+ap_status ap_revolve_plan(int64_t n_steps, int32_t slots, int64_t *repeats, int64_t *forward_steps);
+
 /* Gradient of a particle observable with respect to pulse parameters (the
  * differentiated form of the push and of the analytic field of
  * Sec. II-III) over

@@ -36,7 +36,7 @@ PULSE_TYPES = {"none": AP_PULSE_NONE, "plane": AP_PULSE_PLANE, "gauss": AP_PULSE
 EXPORTED = ("ap_query_layout", "ap_init", "ap_set_pulse", "ap_step", "ap_gather_diag", "ap_gather_diag_static",
             "ap_get_time", "ap_eval_pulse", "ap_read_proxy", "ap_set_checkpoints", "ap_set_adjoint_mode",
             "ap_checkpoint_bytes", "ap_backward", "ap_timing_enable", "ap_timing_read", "ap_shift_window",
-            "ap_get_window", "ap_window_due",
+            "ap_get_window", "ap_window_due", "ap_set_revolve", "ap_revolve_bytes", "ap_revolve_plan",
             "ap_destroy", "ap_last_error")
 
 
@@ -131,6 +131,9 @@ def load():
         "ap_read_proxy": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
         "ap_set_checkpoints": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
         "ap_checkpoint_bytes": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, P(C.c_size_t)]),
+        "ap_set_revolve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
+        "ap_revolve_bytes": (C.c_int32, [C.c_void_p, C.c_int32, P(C.c_size_t)]),
+        "ap_revolve_plan": (C.c_int32, [C.c_int64, C.c_int32, P(C.c_int64), P(C.c_int64)]),
         "ap_set_adjoint_mode": (C.c_int32, [C.c_void_p, C.c_int32]),
         "ap_backward": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(C.c_int32),
                                     C.c_int32, P(C.c_double)]),
@@ -229,6 +232,24 @@ def ap_checkpoint_bytes(ctx, n_steps, segment):
     out = C.c_size_t(0)
     _check(load().ap_checkpoint_bytes(ctx, int(n_steps), int(segment), C.byref(out)), "ap_checkpoint_bytes")
     return int(out.value)
+
+
+def ap_set_revolve(ctx, dev_ptr, nbytes, slots):
+    _check(load().ap_set_revolve(ctx, C.c_void_p(dev_ptr), int(nbytes), int(slots)), "ap_set_revolve")
+
+
+def ap_revolve_bytes(ctx, slots):
+    out = C.c_size_t(0)
+    _check(load().ap_revolve_bytes(ctx, int(slots), C.byref(out)), "ap_revolve_bytes")
+    return int(out.value)
+
+
+def ap_revolve_plan(n_steps, slots):
+    """(repetitions t, forward steps of the reverse sweep) of the binomial schedule."""
+    t = C.c_int64(0)
+    f = C.c_int64(0)
+    _check(load().ap_revolve_plan(int(n_steps), int(slots), C.byref(t), C.byref(f)), "ap_revolve_plan")
+    return int(t.value), int(f.value)
 
 
 def ap_backward(ctx, species, dl_du_ptr, dl_dproxy_ptr, param_ids):

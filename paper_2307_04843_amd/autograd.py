@@ -14,6 +14,10 @@ By default in the frozen-grid reading (the gradient treats the E2, B2 each
 push gathered as a recorded external field); with ``coupled=True`` through
 the whole loop (every species' current, the Yee update and the gather).
 Without ``proxy=True`` its proxy output is identically zero.
+
+Both store their checkpoints in segments of ``segment`` steps (default
+sqrt(n_steps): memory grows with n_steps) or, with ``revolve=S``, in the
+binomial schedule over S whole states (fixed memory, steps re-advanced).
 """
 import math
 
@@ -27,9 +31,16 @@ PARAM_IDS = {"a0": apt.AP_PARAM_A0, "w0": apt.AP_PARAM_W0, "x_f": apt.AP_PARAM_X
              "beta_f": apt.AP_PARAM_BETA_F, "chirp": apt.AP_PARAM_CHIRP}
 
 
+def _set_checkpoints(run):
+    if run.revolve:
+        apt.ap_set_revolve(run.sim.ctx, run.ckpt.data_ptr(), run.ckpt.numel(), run.revolve)
+    else:
+        apt.ap_set_checkpoints(run.sim.ctx, run.ckpt.data_ptr(), run.ckpt.numel(), run.segment)
+
+
 class GridlessRun:
     def __init__(self, state, pulse_kind, pulse_params, param_names, n_steps, dt, t0=0.0,
-                 vcell=1.0, precision="f32", q=-1.0, m=1.0, segment=None, proxy=True):
+                 vcell=1.0, precision="f32", q=-1.0, m=1.0, segment=None, proxy=True, revolve=None):
         self.sim = Simulation(0, dx=(vcell,) * 3, x_min=(0.0, 0.0, 0.0), t0=t0, dt=dt, precision=precision,
                               species=[dict(q=q, m=m, state=state)], proxy=proxy)
         self.kind = pulse_kind
@@ -40,10 +51,13 @@ class GridlessRun:
                 raise ValueError("unknown parameter %r" % nm)
         self.n_steps = int(n_steps)
         self.segment = int(segment or max(1, int(math.sqrt(self.n_steps))))
-        nseg = -(-self.n_steps // self.segment)
-        slot = int(self.sim.layout.ckpt_slot_bytes)
-        self.ckpt = torch.empty(max(2, nseg + self.segment) * slot, dtype=torch.uint8, device=self.sim.device)
-        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        self.revolve = int(revolve) if revolve else 0
+        if self.revolve:
+            nbytes = apt.ap_revolve_bytes(self.sim.ctx, self.revolve)
+        else:
+            nbytes = apt.ap_checkpoint_bytes(self.sim.ctx, self.n_steps, self.segment)
+        self.ckpt = torch.empty(nbytes, dtype=torch.uint8, device=self.sim.device)
+        _set_checkpoints(self)
         a = self.sim.arrays[0]
         self._init = {k: [t.clone() for t in a[k]] for k in ("icell", "off", "u")}
         self._t0 = t0
@@ -59,7 +73,7 @@ class GridlessRun:
         apt.ap_destroy(self.sim.ctx)
         self.sim.ctx = apt.ap_init(self.sim.grid_desc, self.sim.sp_desc, self.sim.buffers,
                                    self.sim.stream.cuda_stream)
-        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        _set_checkpoints(self)
 
     def forward(self, values):
         self._reset()
@@ -105,7 +119,7 @@ class GriddedRun:
 
     def __init__(self, dim, n, dx, x_min, species, pulse_kind, pulse_params, param_names, n_steps, t0=0.0,
                  dt=0.0, precision="f32", fields=None, species_index=0, segment=None, tile=(0, 0, 0),
-                 sort_every=0, proxy=False, coupled=False):
+                 sort_every=0, proxy=False, coupled=False, revolve=None):
         self.sim = Simulation(dim, n=n, dx=dx, x_min=x_min, t0=t0, dt=dt, precision=precision, tile=tile,
                               sort_every=sort_every, species=species, proxy=proxy)
         self.proxy = bool(proxy)
@@ -120,9 +134,13 @@ class GriddedRun:
         self.n_steps = int(n_steps)
         self.sp = int(species_index)
         self.segment = int(segment or max(1, int(math.sqrt(self.n_steps))))
-        nbytes = apt.ap_checkpoint_bytes(self.sim.ctx, self.n_steps, self.segment)
+        self.revolve = int(revolve) if revolve else 0
+        if self.revolve:
+            nbytes = apt.ap_revolve_bytes(self.sim.ctx, self.revolve)
+        else:
+            nbytes = apt.ap_checkpoint_bytes(self.sim.ctx, self.n_steps, self.segment)
         self.ckpt = torch.empty(nbytes, dtype=torch.uint8, device=self.sim.device)
-        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        _set_checkpoints(self)
         self._fields = None if fields is None else [torch.as_tensor(np.asarray(f)) for f in fields]
         self._init = []
         for a in self.sim.arrays:
@@ -151,7 +169,7 @@ class GriddedRun:
             for k in range(3):
                 E[k].copy_(self._fields[k].to(E[k].dtype))
                 B[k].copy_(self._fields[3 + k].to(B[k].dtype))
-        apt.ap_set_checkpoints(self.sim.ctx, self.ckpt.data_ptr(), self.ckpt.numel(), self.segment)
+        _set_checkpoints(self)
 
     def forward(self, values):
         self._reset()

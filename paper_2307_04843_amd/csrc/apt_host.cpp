@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <optional>
@@ -345,6 +346,100 @@ size_t ckpt_need(const RunShape &s, const WorkLayout &L, int64_t n, int64_t K) {
     return G.fixed + (size_t)(1 + nseg) * G.outer + (size_t)K * G.inner;
 }
 
+// Bytes of the binomial schedule with S slots, whatever the number of steps:
+// gridless, S slots plus a work slot; gridded, the fixed part, a copy of the
+// final state and S whole states.
+size_t revolve_need(const RunShape &s, const WorkLayout &L, int64_t S) {
+    if (s.dim == 0) return (size_t)(S + 1) * L.slot_bytes;
+    const GridCkpt G = grid_ckpt(s);
+    return G.fixed + (size_t)(1 + S) * G.outer;
+}
+
+// Binomial checkpointing.  With the state at step l held in a slot and s
+// further slots free, R(s, t) = C(s + t + 1, s + 1) steps can be reversed
+// when every step is advanced at most t times: R(0, t) = t + 1 (re-advance
+// from l for each step) and R(s, t) = R(s, t - 1) + R(s - 1, t) (a state
+// stored d steps ahead splits the range into a left part reversed again from
+// l and a right part with one slot less).  R(s, t) = 0 for t < 0.
+int64_t revolve_capacity(int64_t s, int64_t t) {
+    if (t < 0) return 0;
+    unsigned __int128 v = 1;   // C(s + 1 + k, k) for k = 1..t
+    for (int64_t k = 1; k <= t; ++k) {
+        v = v * (unsigned __int128)(s + 1 + k) / (unsigned __int128)k;
+        if (v > (unsigned __int128)INT64_MAX) return INT64_MAX;
+    }
+    return (int64_t)v;
+}
+
+// Fewest repetitions t with R(s, t) >= n.
+int64_t revolve_repeats(int64_t n, int64_t s) {
+    int64_t t = 0;
+    while (revolve_capacity(s, t) < n) ++t;
+    return t;
+}
+
+// Forward steps of reversing n steps with s free slots when every advance
+// counts: t n - R(s + 1, t - 1) with t = revolve_repeats(n, s); the k-th step
+// of the range costs revolve_repeats(k, s).
+int64_t revolve_cost(int64_t n, int64_t s) {
+    if (n <= 1) return 0;
+    const int64_t t = revolve_repeats(n, s);
+    return t * n - revolve_capacity(s + 1, t - 1);
+}
+
+// Split of n >= 2 steps with s >= 1 free slots that reaches revolve_cost:
+// the smallest d with d <= R(s, t - 1) (left part, one repetition less) and
+// n - d <= R(s - 1, t) (right part, one slot less) that is not below
+// R(s, t - 2).
+int64_t revolve_split(int64_t n, int64_t s) {
+    const int64_t t = revolve_repeats(n, s);
+    int64_t d = revolve_capacity(s, t - 2);
+    const int64_t r = n - revolve_capacity(s - 1, t);
+    if (r > d) d = r;
+    if (d > n - 1) d = n - 1;
+    return d < 1 ? 1 : d;
+}
+
+// States the recording sweep stores (relative steps, increasing), the
+// recording being free: n steps fall into segments i = 0.. s with s - i free
+// slots each, the k-th step of segment i costing revolve_repeats(k, s - i);
+// filling every segment up to a common cost level tau minimises the total.
+std::vector<int64_t> revolve_spine(int64_t n, int64_t s, int64_t *cost = nullptr) {
+    int64_t tau = 0;
+    for (;;) {
+        int64_t cap = 0;
+        for (int64_t i = 0; i <= s && cap < n; ++i) {
+            const int64_t c = revolve_capacity(s - i, tau);
+            cap = c > n ? n : cap + c;
+        }
+        if (cap >= n) break;
+        ++tau;
+    }
+    std::vector<int64_t> size((size_t)s + 1, 0);
+    int64_t left = n;
+    for (int64_t i = 0; i <= s; ++i) {
+        int64_t d = revolve_capacity(s - i, tau - 1);
+        if (d > left) d = left;
+        size[(size_t)i] = d;
+        left -= d;
+    }
+    for (int64_t i = 0; i <= s && left > 0; ++i) {
+        int64_t more = revolve_capacity(s - i, tau) - size[(size_t)i];
+        if (more > left) more = left;
+        size[(size_t)i] += more;
+        left -= more;
+    }
+    std::vector<int64_t> pos;
+    int64_t at = 0, total = 0;
+    for (int64_t i = 0; i <= s; ++i) {
+        total += revolve_cost(size[(size_t)i], s - i);
+        at += size[(size_t)i];
+        if (i < s && at < n && size[(size_t)i] > 0) pos.push_back(at);
+    }
+    if (cost) *cost = total;
+    return pos;
+}
+
 PulseDev default_pulse() {
     PulseDev P;
     std::memset(&P, 0, sizeof(P));
@@ -439,11 +534,15 @@ struct ap_ctx {
     int64_t acc_n[4] = {0, 0, 0, 0};
     int64_t acc_pushes = 0;
     int64_t push_since_read = 0;
-    // adjoint checkpoints (gridless)
+    // adjoint checkpoints
     unsigned char *ckpt = nullptr;
     size_t ckpt_bytes = 0;
     int64_t segment = 0;
     int64_t rec_n = 0, rec_step0 = 0;
+    // binomial schedule: slots of whole states (0: none, segments instead);
+    // the recorded states besides step 0, as (relative step, slot)
+    int32_t revolve = 0;
+    std::vector<std::pair<int64_t, int32_t>> spine;
 
     unsigned char *work() const { return static_cast<unsigned char *>(buf.work); }
     template <typename X> X *wp(size_t off) const { return reinterpret_cast<X *>(work() + off); }
@@ -808,11 +907,18 @@ ap_status ap_step(ap_ctx *c, int64_t n_steps, uint32_t flags) {
         return fail(AP_E_ARG, "grid flags on a gridless run");
     if (flags & AP_STEP_RECORD) {
         if (!c->ckpt) return fail(AP_E_STATE, "ap_set_checkpoints must be called before recording");
-        const size_t need = ckpt_need(c->s, c->L, n_steps, c->segment);
+        const size_t need = c->revolve > 0 ? revolve_need(c->s, c->L, c->revolve)
+                                           : ckpt_need(c->s, c->L, n_steps, c->segment);
         if (need > c->ckpt_bytes)
             return fail(AP_E_ARG, "checkpoint buffer too small: need " + std::to_string(need) + " bytes");
         c->rec_n = n_steps;
         c->rec_step0 = c->step;
+        // binomial schedule: the states its first descent stores (slot 0 holds step 0)
+        c->spine.clear();
+        if (c->revolve > 0) {
+            int32_t next = 1;
+            for (int64_t m : revolve_spine(n_steps, c->revolve - 1)) c->spine.push_back({m, next++});
+        }
     } else {
         c->rec_n = 0;   // any unrecorded step invalidates the recording
     }
@@ -1004,7 +1110,53 @@ ap_status ap_set_checkpoints(ap_ctx *c, void *dev, size_t bytes, int32_t segment
     c->ckpt = static_cast<unsigned char *>(dev);
     c->ckpt_bytes = bytes;
     c->segment = segment;
+    c->revolve = 0;
+    c->spine.clear();
     c->rec_n = 0;
+    return AP_OK;
+}
+
+ap_status ap_set_revolve(ap_ctx *c, void *dev, size_t bytes, int32_t slots) {
+    if (!c) return fail(AP_E_ARG, "context is NULL");
+    if (slots < 1) return fail(AP_E_ARG, "slots must be >= 1");
+    const size_t need = revolve_need(c->s, c->L, slots);
+    if (!dev || bytes < need)
+        return fail(AP_E_ARG, "checkpoint buffer NULL or smaller than " + std::to_string(need) + " bytes");
+    c->ckpt = static_cast<unsigned char *>(dev);
+    c->ckpt_bytes = bytes;
+    c->segment = 1;
+    c->revolve = slots;
+    c->spine.clear();
+    c->rec_n = 0;
+    return AP_OK;
+}
+
+ap_status ap_revolve_bytes(const ap_ctx *c, int32_t slots, size_t *bytes) {
+    if (!c || !bytes) return fail(AP_E_ARG, "NULL argument");
+    if (slots < 1) return fail(AP_E_ARG, "slots must be >= 1");
+    *bytes = revolve_need(c->s, c->L, slots);
+    return AP_OK;
+}
+
+ap_status ap_revolve_plan(int64_t n_steps, int32_t slots, int64_t *repeats, int64_t *forward_steps) {
+    if (n_steps < 1 || slots < 1) return fail(AP_E_ARG, "n_steps and slots must be >= 1");
+    if (!repeats && !forward_steps) return fail(AP_E_ARG, "NULL argument");
+    if (slots == 1 && n_steps > (int64_t)1 << 31)
+        return fail(AP_E_ARG, "one slot: n_steps too large (quadratic re-advancing)");
+    int64_t cost = 0;
+    const std::vector<int64_t> pos = revolve_spine(n_steps, slots - 1, &cost);
+    if (repeats) {
+        // the most any step is re-advanced: the cost of each segment's last step
+        int64_t t = 0, at = 0;
+        for (size_t i = 0; i <= pos.size(); ++i) {
+            const int64_t end = i < pos.size() ? pos[i] : n_steps;
+            const int64_t ti = revolve_repeats(end - at, slots - 1 - (int64_t)i);
+            t = ti > t ? ti : t;
+            at = end;
+        }
+        *repeats = t;
+    }
+    if (forward_steps) *forward_steps = cost;
     return AP_OK;
 }
 
@@ -1019,6 +1171,8 @@ ap_status ap_set_adjoint_mode(ap_ctx *c, int32_t mode) {
     c->ckpt = nullptr;
     c->ckpt_bytes = 0;
     c->segment = 0;
+    c->revolve = 0;
+    c->spine.clear();
     c->rec_n = 0;
     return AP_OK;
 }
@@ -1186,6 +1340,75 @@ template <typename T> void slot_ptrs(ap_ctx *c, int64_t k, int i, int32_t *icell
     }
 }
 
+// Reverse sweep of the binomial schedule over relative steps [l, r), the
+// state of step l in slot_l and sfree slots free below it.  advance(from, l,
+// d, to) leaves the state of step l + d in slot `to` (-1: the working state);
+// leaf(j, slot) runs reverse step j from the state in `slot` (-1: working).
+// The states the recording sweep stored (stored) are used where the
+// recursion asks for them.
+struct Revolve {
+    std::function<ap_status(int32_t, int64_t, int64_t, int32_t)> advance;
+    std::function<ap_status(int64_t, int32_t)> leaf;
+    std::vector<std::pair<int64_t, int32_t>> stored;
+    std::vector<int32_t> pool;
+
+    ap_status run(int64_t l, int64_t r, int32_t slot_l, int64_t sfree) {
+        const int64_t n = r - l;
+        if (n == 1) return leaf(l, slot_l);
+        if (sfree == 0) {
+            // no slot left: each step again from l
+            for (int64_t j = r - 1; j > l; --j) {
+                ap_status st = advance(slot_l, l, j - l, -1);
+                if (st != AP_OK) return st;
+                st = leaf(j, -1);
+                if (st != AP_OK) return st;
+            }
+            return leaf(l, slot_l);
+        }
+        // the next state of the recording's first descent, if it lies in (l, r), else the split
+        int64_t m = l + revolve_split(n, sfree);
+        int32_t slot_m = -1;
+        for (size_t k = 0; k < stored.size(); ++k)
+            if (stored[k].first > l && stored[k].first < r) {
+                m = stored[k].first;
+                slot_m = stored[k].second;
+                stored.erase(stored.begin() + (std::ptrdiff_t)k);
+                break;
+            }
+        if (slot_m < 0) {
+            if (pool.empty()) return fail(AP_E_STATE, "binomial schedule ran out of slots");
+            slot_m = pool.back();
+            pool.pop_back();
+            const ap_status st = advance(slot_l, l, m - l, slot_m);
+            if (st != AP_OK) return st;
+        }
+        ap_status st = run(m, r, slot_m, sfree - 1);
+        if (st != AP_OK) return st;
+        pool.push_back(slot_m);
+        return run(l, m, slot_l, sfree);
+    }
+};
+
+// A Revolve over the context's recording: slot 0 holds step 0, the spine
+// its stored states, the other slots start free.
+Revolve make_revolve(const ap_ctx *c) {
+    Revolve R;
+    R.stored = c->spine;
+    for (int32_t k = c->revolve - 1; k > (int32_t)c->spine.size(); --k) R.pool.push_back(k);
+    return R;
+}
+
+// Slot that the recording sweep stores the state of relative step k in, or
+// -1: every segment's first step (segments), or step 0 and the first
+// descent of the binomial schedule.
+int64_t record_slot(const ap_ctx *c, int64_t k) {
+    if (c->revolve == 0) return k % c->segment == 0 ? k / c->segment : -1;
+    if (k == 0) return 0;
+    for (const auto &e : c->spine)
+        if (e.first == k) return e.second;
+    return -1;
+}
+
 template <typename T> ap_status copy_state_to_slot(ap_ctx *c, int64_t k) {
     for (int i = 0; i < c->s.nsp; ++i) {
         const size_t N = (size_t)c->s.np[i];
@@ -1207,8 +1430,9 @@ template <typename T> ap_status step_gridless(ap_ctx *c, uint32_t flags) {
     const RunShape &s = c->s;
     if (flags & AP_STEP_RECORD) {
         const int64_t k = c->step - c->rec_step0;
-        if (k % c->segment == 0) {
-            const ap_status st = copy_state_to_slot<T>(c, k / c->segment);
+        const int64_t slot = record_slot(c, k);
+        if (slot >= 0) {
+            const ap_status st = copy_state_to_slot<T>(c, slot);
             if (st != AP_OK) return st;
         }
     }
@@ -1242,46 +1466,71 @@ ap_status backward_impl(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
         if (ids[k] != AP_PARAM_A0) slot[nslot++] = ids[k];
     HIPCHK(launch_fill_zero<double>(partial, (size_t)L.adj_blocks * 5, c->stream), "backward");
     HIPCHK(launch_adjoint_init<T>(lam, static_cast<const T *>(dl_du), n, c->stream), "backward");
-    const int64_t K = c->segment;
-    const int64_t nseg = (c->rec_n + K - 1) / K;
-    const int64_t inner0 = nseg;   // first inner slot
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t s0 = seg * K;
-        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
-        // replay the segment forward from its checkpoint into the inner slots
-        for (int64_t j = 0; j + 1 < len; ++j) {
+    // reverse step j (relative) from the state in slot k
+    auto leaf = [&](int64_t j, int64_t k) -> ap_status {
+        int32_t *ic[3];
+        T *of[3], *u[3];
+        slot_ptrs<T>(c, k, sp, ic, of, u);
+        AdjointArgs<T> a{};
+        for (int q = 0; q < 3; ++q) {
+            a.icell[q] = ic[q];
+            a.off[q] = of[q];
+            a.u[q] = u[q];
+            a.dx[q] = s.dx[q];
+            a.x_min[q] = s.x_min[q];
+        }
+        for (int q = 0; q < 6; ++q) a.lam[q] = lam[q];
+        a.lam_proxy = static_cast<const T *>(dl_dproxy);
+        a.partial = partial;
+        for (int q = 0; q < 4; ++q) a.slot[q] = slot[q];
+        a.n = n;
+        a.q_over_m = s.q[sp] / s.m[sp];
+        a.dt = s.dt;
+        a.t = s.t0 + (double)(c->rec_step0 + j) * s.dt;
+        a.P = c->P;
+        a.dim = 0;
+        HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+        return AP_OK;
+    };
+    // d forward steps of the species from slot `from` (relative step l) into slot `to`
+    auto advance = [&](int64_t from, int64_t l, int64_t d, int64_t to) -> ap_status {
+        for (int64_t k = 0; k < d; ++k) {
             int32_t *ic_i[3], *ic_o[3];
             T *of_i[3], *u_i[3], *of_o[3], *u_o[3];
-            if (j == 0) slot_ptrs<T>(c, seg, sp, ic_i, of_i, u_i);
-            else slot_ptrs<T>(c, inner0 + j, sp, ic_i, of_i, u_i);
-            slot_ptrs<T>(c, inner0 + j + 1, sp, ic_o, of_o, u_o);
-            const double t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
+            slot_ptrs<T>(c, k == 0 ? from : to, sp, ic_i, of_i, u_i);
+            slot_ptrs<T>(c, to, sp, ic_o, of_o, u_o);
+            const double t = s.t0 + (double)(c->rec_step0 + l + k) * s.dt;
             GridlessArgs<T> a = gridless_args<T>(c, sp, ic_i, of_i, u_i, ic_o, of_o, u_o, nullptr, t);
             HIPCHK(launch_gridless<T>(c->P.type, a, c->stream), "backward replay");
         }
-        for (int64_t j = len - 1; j >= 0; --j) {
-            int32_t *ic[3];
-            T *of[3], *u[3];
-            slot_ptrs<T>(c, j == 0 ? seg : inner0 + j, sp, ic, of, u);
-            AdjointArgs<T> a{};
-            for (int k = 0; k < 3; ++k) {
-                a.icell[k] = ic[k];
-                a.off[k] = of[k];
-                a.u[k] = u[k];
-                a.dx[k] = s.dx[k];
-                a.x_min[k] = s.x_min[k];
+        return AP_OK;
+    };
+    if (c->revolve > 0) {
+        // binomial schedule; slot c->revolve is the working state
+        const int64_t work = c->revolve;
+        Revolve R = make_revolve(c);
+        R.advance = [&](int32_t from, int64_t l, int64_t d, int32_t to) {
+            return advance(from, l, d, to >= 0 ? to : work);
+        };
+        R.leaf = [&](int64_t j, int32_t k) { return leaf(j, k >= 0 ? k : work); };
+        const ap_status st = R.run(0, c->rec_n, 0, c->revolve - 1);
+        if (st != AP_OK) return st;
+    } else {
+        const int64_t K = c->segment;
+        const int64_t nseg = (c->rec_n + K - 1) / K;
+        const int64_t inner0 = nseg;   // first inner slot
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t s0 = seg * K;
+            const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+            // replay the segment forward from its checkpoint into the inner slots
+            for (int64_t j = 0; j + 1 < len; ++j) {
+                const ap_status st = advance(j == 0 ? seg : inner0 + j, s0 + j, 1, inner0 + j + 1);
+                if (st != AP_OK) return st;
             }
-            for (int k = 0; k < 6; ++k) a.lam[k] = lam[k];
-            a.lam_proxy = static_cast<const T *>(dl_dproxy);
-            a.partial = partial;
-            for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
-            a.n = n;
-            a.q_over_m = s.q[sp] / s.m[sp];
-            a.dt = s.dt;
-            a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
-            a.P = c->P;
-            a.dim = 0;
-            HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+            for (int64_t j = len - 1; j >= 0; --j) {
+                const ap_status st = leaf(s0 + j, j == 0 ? seg : inner0 + j);
+                if (st != AP_OK) return st;
+            }
         }
     }
     double *sums = c->wp<double>(L.sums);
@@ -1403,6 +1652,22 @@ template <typename T> ap_status save_replay(ap_ctx *c, unsigned char *slot, int 
                          (size_t)s.np[sp], false);
 }
 
+// Binomial schedule, gridded runs: the whole state of relative step l from
+// slot `from` into the caller's arrays and the grid, d steps of the full
+// loop, then (to >= 0) the state into slot `to`.
+template <typename T> ap_status revolve_advance_grid(ap_ctx *c, int32_t from, int64_t l, int64_t d, int32_t to) {
+    ap_status st = save_ckpt<T>(c, ckpt_outer(c, from), true);
+    if (st != AP_OK) return st;
+    c->step = c->rec_step0 + l;
+    c->need_sort = true;
+    for (int64_t k = 0; k < d; ++k) {
+        st = step_gridded<T>(c, 0);
+        if (st != AP_OK) return st;
+        c->step++;
+    }
+    return to >= 0 ? save_ckpt<T>(c, ckpt_outer(c, to)) : AP_OK;
+}
+
 // Reverse sweep of a recorded gridded run (frozen-grid reading).  Each
 // segment is restored from its checkpoint and replayed with the full loop
 // (push, deposit, field update), storing E2, B2 and the species at the start
@@ -1440,57 +1705,77 @@ ap_status backward_grid(ap_ctx *c, int sp, const void *dl_du, const void *dl_dpr
     if (st != AP_OK) return st;
     HIPCHK(launch_fill_zero<double>(partial, (size_t)G.blocks * 5, c->stream), "backward");
     HIPCHK(launch_adjoint_init<T>(lam, static_cast<const T *>(dl_du), n, c->stream), "backward");
-    const int64_t K = c->segment;
-    const int64_t nseg = (c->rec_n + K - 1) / K;
     const FastDiv fnx((uint32_t)s.n[0]), fnxy((uint32_t)(s.n[0] * s.n[1]));
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t s0 = seg * K;
-        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
-        st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
-        if (st != AP_OK) return st;
-        c->step = c->rec_step0 + s0;
-        c->need_sort = true;
-        for (int64_t j = 0; j < len; ++j) {
-            st = save_replay<T>(c, ckpt_inner(c, j), sp);
-            if (st != AP_OK) return st;
-            if (j + 1 < len) {
-                st = step_gridded<T>(c, 0);
-                if (st != AP_OK) return st;
-                c->step++;
-            }
+    // reverse step j (relative) from E2, B2 at F and the species' block b
+    auto leaf = [&](int64_t j, const T *F, const SpBlock<T> &b) -> ap_status {
+        AdjointArgs<T> a{};
+        a.xo = s.xo;
+        for (int k = 0; k < 3; ++k) {
+            a.off[k] = b.off[k];
+            a.u[k] = b.u[k];
+            a.dx[k] = s.dx[k];
+            a.x_min[k] = s.x_min[k];
+            a.G.n[k] = s.n[k];
         }
-        for (int64_t j = len - 1; j >= 0; --j) {
-            unsigned char *slot_j = ckpt_inner(c, j);
-            const SpBlock<T> b = sp_block<T>(slot_j + G.inner_sp, s, sp, false, false);
-            const T *F = reinterpret_cast<const T *>(slot_j);
-            AdjointArgs<T> a{};
-            a.xo = s.xo;
-            for (int k = 0; k < 3; ++k) {
-                a.off[k] = b.off[k];
-                a.u[k] = b.u[k];
-                a.dx[k] = s.dx[k];
-                a.x_min[k] = s.x_min[k];
-                a.G.n[k] = s.n[k];
+        for (int k = 0; k < 6; ++k) {
+            a.lam[k] = lam[k];
+            a.G.F[k] = F + (size_t)k * (size_t)s.ncell;
+        }
+        a.G.cell = b.cell;
+        a.G.id = b.id;
+        a.G.fnx = fnx;
+        a.G.fnxy = fnxy;
+        a.G.q_slice = c->P.q_slice;
+        a.dim = s.dim;
+        a.lam_proxy = static_cast<const T *>(dl_dproxy);   // by particle id, like dl_du
+        a.partial = partial;
+        for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
+        a.n = n;
+        a.q_over_m = s.q[sp] / s.m[sp];
+        a.dt = s.dt;
+        a.t = s.t0 + (double)(c->rec_step0 + j) * s.dt;
+        a.P = c->P;
+        HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+        return AP_OK;
+    };
+    if (c->revolve > 0) {
+        Revolve R = make_revolve(c);
+        R.advance = [&](int32_t from, int64_t l, int64_t d, int32_t to) {
+            return revolve_advance_grid<T>(c, from, l, d, to);
+        };
+        R.leaf = [&](int64_t j, int32_t k) -> ap_status {
+            if (k < 0) return leaf(j, static_cast<const T *>(c->buf.grid), live_block<T>(c, sp));
+            unsigned char *slot_k = ckpt_outer(c, k);
+            return leaf(j, reinterpret_cast<const T *>(slot_k + G.fields),
+                        sp_block<T>(slot_k + G.sp_off[sp], s, sp, true, true));
+        };
+        st = R.run(0, c->rec_n, 0, c->revolve - 1);
+        if (st != AP_OK) return st;
+    } else {
+        const int64_t K = c->segment;
+        const int64_t nseg = (c->rec_n + K - 1) / K;
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t s0 = seg * K;
+            const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+            st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
+            if (st != AP_OK) return st;
+            c->step = c->rec_step0 + s0;
+            c->need_sort = true;
+            for (int64_t j = 0; j < len; ++j) {
+                st = save_replay<T>(c, ckpt_inner(c, j), sp);
+                if (st != AP_OK) return st;
+                if (j + 1 < len) {
+                    st = step_gridded<T>(c, 0);
+                    if (st != AP_OK) return st;
+                    c->step++;
+                }
             }
-            for (int k = 0; k < 6; ++k) {
-                a.lam[k] = lam[k];
-                a.G.F[k] = F + (size_t)k * (size_t)s.ncell;
+            for (int64_t j = len - 1; j >= 0; --j) {
+                unsigned char *slot_j = ckpt_inner(c, j);
+                st = leaf(s0 + j, reinterpret_cast<const T *>(slot_j),
+                          sp_block<T>(slot_j + G.inner_sp, s, sp, false, false));
+                if (st != AP_OK) return st;
             }
-            a.G.cell = b.cell;
-            a.G.id = b.id;
-            a.G.fnx = fnx;
-            a.G.fnxy = fnxy;
-            a.G.q_slice = c->P.q_slice;
-            a.dim = s.dim;
-            a.lam_proxy = static_cast<const T *>(dl_dproxy);   // by particle id, like dl_du
-            a.partial = partial;
-            for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
-            a.n = n;
-            a.q_over_m = s.q[sp] / s.m[sp];
-            a.dt = s.dt;
-            a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
-            a.P = c->P;
-            HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
         }
     }
     st = save_ckpt<T>(c, ckpt_final(c), true);
@@ -1564,65 +1849,90 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
         yb.dx[k] = s.dx[k];
     }
     yb.dt = s.dt;
-    const int64_t K = c->segment;
-    const int64_t nseg = (c->rec_n + K - 1) / K;
     const FastDiv fnx((uint32_t)s.n[0]), fnxy((uint32_t)(s.n[0] * s.n[1]));
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t s0 = seg * K;
-        const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
-        st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
-        if (st != AP_OK) return st;
-        c->step = c->rec_step0 + s0;
-        c->need_sort = true;
-        for (int64_t j = 0; j < len; ++j) {
-            st = save_replay<T>(c, ckpt_inner(c, j), sp);
-            if (st != AP_OK) return st;
-            if (j + 1 < len) {
-                st = step_gridded<T>(c, 0);
-                if (st != AP_OK) return st;
-                c->step++;
+    // reverse step j (relative) from E2, B2 at F and every species' block
+    auto leaf = [&](int64_t j, const T *F, const SpBlock<T> *blk) -> ap_status {
+        HIPCHK(launch_yee_adjoint(s.dim, lE, lB, lJt, yb, c->stream), "backward yee");
+        for (int i = 0; i < s.nsp; ++i) {
+            if (s.np[i] == 0) continue;
+            const SpBlock<T> &b = blk[i];
+            AdjointArgs<T> a{};
+            a.xo = s.xo;
+            for (int k = 0; k < 3; ++k) {
+                a.off[k] = b.off[k];
+                a.u[k] = b.u[k];
+                a.dx[k] = s.dx[k];
+                a.x_min[k] = s.x_min[k];
+                a.G.n[k] = s.n[k];
+                a.lJ[k] = lJt + (size_t)k * nc;
+                a.lEg[k] = lE + (size_t)k * nc;
+                a.lBg[k] = lB + (size_t)k * nc;
             }
+            for (int k = 0; k < 6; ++k) {
+                a.lam[k] = lam[i][k];
+                a.G.F[k] = F + (size_t)k * nc;
+            }
+            a.G.cell = b.cell;
+            a.G.id = b.id;
+            a.G.fnx = fnx;
+            a.G.fnxy = fnxy;
+            a.G.q_slice = c->P.q_slice;
+            a.w = b.w;
+            a.q = s.q[i];
+            a.dim = s.dim;
+            a.lam_proxy = i == sp ? static_cast<const T *>(dl_dproxy) : nullptr;
+            a.partial = partial;
+            for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
+            a.n = (int)s.np[i];
+            a.q_over_m = s.q[i] / s.m[i];
+            a.dt = s.dt;
+            a.t = s.t0 + (double)(c->rec_step0 + j) * s.dt;
+            a.P = c->P;
+            HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
         }
-        for (int64_t j = len - 1; j >= 0; --j) {
-            unsigned char *slot_j = ckpt_inner(c, j);
-            const T *F = reinterpret_cast<const T *>(slot_j);
-            HIPCHK(launch_yee_adjoint(s.dim, lE, lB, lJt, yb, c->stream), "backward yee");
-            for (int i = 0; i < s.nsp; ++i) {
-                if (s.np[i] == 0) continue;
-                const SpBlock<T> b = sp_block<T>(slot_j + G.inner_off[i], s, i, true, false);
-                AdjointArgs<T> a{};
-                a.xo = s.xo;
-                for (int k = 0; k < 3; ++k) {
-                    a.off[k] = b.off[k];
-                    a.u[k] = b.u[k];
-                    a.dx[k] = s.dx[k];
-                    a.x_min[k] = s.x_min[k];
-                    a.G.n[k] = s.n[k];
-                    a.lJ[k] = lJt + (size_t)k * nc;
-                    a.lEg[k] = lE + (size_t)k * nc;
-                    a.lBg[k] = lB + (size_t)k * nc;
+        return AP_OK;
+    };
+    SpBlock<T> blk[kMaxSpecies];
+    if (c->revolve > 0) {
+        Revolve R = make_revolve(c);
+        R.advance = [&](int32_t from, int64_t l, int64_t d, int32_t to) {
+            return revolve_advance_grid<T>(c, from, l, d, to);
+        };
+        R.leaf = [&](int64_t j, int32_t k) -> ap_status {
+            if (k < 0) {
+                for (int i = 0; i < s.nsp; ++i) blk[i] = live_block<T>(c, i);
+                return leaf(j, static_cast<const T *>(c->buf.grid), blk);
+            }
+            unsigned char *slot_k = ckpt_outer(c, k);
+            for (int i = 0; i < s.nsp; ++i) blk[i] = sp_block<T>(slot_k + G.sp_off[i], s, i, true, true);
+            return leaf(j, reinterpret_cast<const T *>(slot_k + G.fields), blk);
+        };
+        st = R.run(0, c->rec_n, 0, c->revolve - 1);
+        if (st != AP_OK) return st;
+    } else {
+        const int64_t K = c->segment;
+        const int64_t nseg = (c->rec_n + K - 1) / K;
+        for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+            const int64_t s0 = seg * K;
+            const int64_t len = (c->rec_n - s0) < K ? (c->rec_n - s0) : K;
+            st = save_ckpt<T>(c, ckpt_outer(c, seg), true);
+            if (st != AP_OK) return st;
+            c->step = c->rec_step0 + s0;
+            c->need_sort = true;
+            for (int64_t j = 0; j < len; ++j) {
+                st = save_replay<T>(c, ckpt_inner(c, j), sp);
+                if (st != AP_OK) return st;
+                if (j + 1 < len) {
+                    st = step_gridded<T>(c, 0);
+                    if (st != AP_OK) return st;
+                    c->step++;
                 }
-                for (int k = 0; k < 6; ++k) {
-                    a.lam[k] = lam[i][k];
-                    a.G.F[k] = F + (size_t)k * nc;
-                }
-                a.G.cell = b.cell;
-                a.G.id = b.id;
-                a.G.fnx = fnx;
-                a.G.fnxy = fnxy;
-                a.G.q_slice = c->P.q_slice;
-                a.w = b.w;
-                a.q = s.q[i];
-                a.dim = s.dim;
-                a.lam_proxy = i == sp ? static_cast<const T *>(dl_dproxy) : nullptr;
-                a.partial = partial;
-                for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];
-                a.n = (int)s.np[i];
-                a.q_over_m = s.q[i] / s.m[i];
-                a.dt = s.dt;
-                a.t = s.t0 + (double)(c->rec_step0 + s0 + j) * s.dt;
-                a.P = c->P;
-                HIPCHK(launch_adjoint_step<T>(c->P.type, a, c->stream), "backward step");
+            }
+            for (int64_t j = len - 1; j >= 0; --j) {
+                unsigned char *slot_j = ckpt_inner(c, j);
+                for (int i = 0; i < s.nsp; ++i) blk[i] = sp_block<T>(slot_j + G.inner_off[i], s, i, true, false);
+                st = leaf(s0 + j, reinterpret_cast<const T *>(slot_j), blk);
+                if (st != AP_OK) return st;
             }
         }
     }
@@ -1787,8 +2097,9 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
     const FastDiv fnxy((uint32_t)(s.n[0] * s.n[1]));
     if (flags & AP_STEP_RECORD) {
         const int64_t k = c->step - c->rec_step0;
-        if (k % c->segment == 0) {
-            const ap_status st = save_ckpt<T>(c, ckpt_outer(c, k / c->segment));
+        const int64_t slot = record_slot(c, k);
+        if (slot >= 0) {
+            const ap_status st = save_ckpt<T>(c, ckpt_outer(c, slot));
             if (st != AP_OK) return st;
         }
     }

@@ -219,3 +219,43 @@ def test_rows1d_layout():
     assert lay.n_cells == 300
     assert lay.n_tiles == 4 * 3                  # default 32-cell tiles
     assert lay.grid_bytes == 9 * 300 * lay.real_bytes
+
+
+def test_revolve_plan_is_the_optimal_binomial_schedule():
+    """ap_revolve_plan's forward steps equal the optimum over every split,
+    found by dynamic programming: C(n, s) = min_d d + C(n - d, s - 1) + C(d, s)
+    (store the state d steps ahead, reverse the right part with one slot
+    less, then the left part again from the start), C(1, s) = 0,
+    C(n, 0) = n (n - 1) / 2; the recording sweep's first descent is free:
+    F(n, s) = min_d F(n - d, s - 1) + C(d, s).  The repetitions bound the
+    re-advancing: forward steps <= repetitions x n."""
+    import functools
+
+    @functools.lru_cache(maxsize=None)
+    def cost(n, s):
+        if n <= 1:
+            return 0
+        if s == 0:
+            return n * (n - 1) // 2
+        return min(d + cost(n - d, s - 1) + cost(d, s) for d in range(1, n))
+
+    @functools.lru_cache(maxsize=None)
+    def first(n, s):
+        if n <= 1:
+            return 0
+        if s == 0:
+            return cost(n, 0)
+        return min(first(n - d, s - 1) + cost(d, s) for d in range(1, n))
+
+    for slots in range(1, 7):
+        for n in range(1, 61):
+            t, f = apt.ap_revolve_plan(n, slots)
+            assert f == first(n, slots - 1), (n, slots, f, first(n, slots - 1))
+            assert f <= t * n and (t == 0) == (f == 0)
+    # one slot: every step re-advanced from the start
+    assert apt.ap_revolve_plan(10, 1) == (9, 45)
+    # at scale: 20000 steps with 64 slots re-advance each step at most twice
+    t, f = apt.ap_revolve_plan(20000, 64)
+    assert t == 2 and f <= 2 * 20000
+    with pytest.raises(apt.APTError):
+        apt.ap_revolve_plan(0, 4)
