@@ -63,6 +63,24 @@ template <typename T> AP_HD Cx<T> operator*(T s, Cx<T> a) { return Cx<T>(s * a.r
 AP_D void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 AP_D void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// Accumulator of the LDS current tile.  FP64 runs add FP64.  FP32 runs add
+// int64 fixed point with a power-of-two scale chosen per block (every
+// contribution below 2^50 units, the node sums below 2^62): integer LDS
+// atomics run faster than FP64 ones, and the tile's sums are exact and
+// independent of the order of the atomics; the quantum is 2^-50 of the
+// block's largest |q w| dx/dt, far below FP32 rounding.
+template <typename T> struct JTile { using type = double; };
+template <> struct JTile<float> { using type = unsigned long long; };
+
+AP_D void lds_add(double *p, double c, double a) { atomic_add(p, c * a); }
+AP_D void lds_add(unsigned long long *p, double c, double a) {
+    // |c a| < 2^51: adding 1.5 * 2^52 leaves round(c a) in the low mantissa bits
+    const double t = fma(c, a, 6755399441055744.0);
+    atomicAdd(p, (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL));
+}
+AP_D double lds_value(double v, double) { return v; }
+AP_D double lds_value(unsigned long long v, double inv_scale) { return (double)(long long)v * inv_scale; }
+
 // LDS sub-buffer offsets are kept 16-byte aligned.
 AP_HD size_t align_lds(size_t bytes) { return (bytes + 15) / 16 * 16; }
 

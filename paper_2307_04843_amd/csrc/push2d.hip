@@ -38,13 +38,13 @@ AP_D int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 // weight is then zero before and after the move, and so is every current
 // term that involves it.  In a 4-node window the lanes that kept their node
 // skip those zero terms (fewer active lanes per LDS atomic).
-template <int WX, int WZ, typename T>
-AP_D void deposit_window(double *sJ, int RC, int RX, int x0, int z0, const T S0x[4], const T DSx[4],
-                         const T S0z[4], const T DSz[4], T fx, T fy, T fz) {
-    double *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
+template <int WX, int WZ, typename T, typename JA>
+AP_D void deposit_window(JA *sJ, int RC, int RX, int x0, int z0, const T S0x[4], const T DSx[4],
+                         const T S0z[4], const T DSz[4], T fx, T fy, T fz, double scale) {
+    JA *Jx = sJ, *Jy = sJ + RC, *Jz = sJ + 2 * RC;
     const T third = T(1.0 / 3.0);
-    auto atomic_add = [](double *p, double v) {
-        if ((WX == 3 && WZ == 3) || v != 0.0) apt::atomic_add(p, v);
+    auto atomic_add = [scale](JA *p, double v) {
+        if ((WX == 3 && WZ == 3) || v != 0.0) lds_add(p, v, scale);
     };
 #pragma unroll
     for (int b = 0; b < WZ; ++b) {
@@ -88,10 +88,12 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     using T2 = typename Vec2<T>::type;
     T2 *sP = reinterpret_cast<T2 *>(smem_raw);               // [2][RC] pairs
     T *sS = reinterpret_cast<T *>(sP + 2 * RC);              // [2][RC] Ey, By
-    // The current tile accumulates in FP64 for both working types: ds_add_f64
-    // measured several times faster than ds_add_f32 for this access pattern.
-    using A = double;
+    // The current tile: FP64 in FP64 runs, int64 fixed point in FP32 runs
+    // (JTile; ds_add_f64 measured several times faster than ds_add_f32 here,
+    // ds_add_u64 faster again).
+    using A = typename JTile<T>::type;
     A *sJ = reinterpret_cast<A *>(smem_raw + align_lds(6 * RC * sizeof(T)));   // Jx Jy Jz
+    __shared__ float s_red[4];
 
     // XCD-aware mapping: consecutive hardware block ids go round-robin to
     // the 8 XCDs; give each XCD a contiguous run of logical tiles so that
@@ -124,6 +126,43 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
         sJ[0 * RC + e] = A(0);
         sJ[1 * RC + e] = A(0);
         sJ[2 * RC + e] = A(0);
+    }
+    // fixed-point scale of the block's current tile (FP32 runs): every
+    // contribution is below |q w| max(dx, dz) / dt (the running sums and
+    // shape factors are at most 1, |v_y| < c < dx / dt); from the largest
+    // |q w| of the block's particles (non-finite weights belong to skipped
+    // particles) and their count
+    double scale = 1.0, inv_scale = 1.0;
+    if constexpr (std::is_same<T, float>::value) {
+        float qw = 0.f;
+        int count = 0;
+        for (int s = 0; s < a.nsp; ++s) {
+            const SpeciesIO<T> &S = a.sp[s];
+            const int beg = S.tile_start[tile];
+            const int cnt = S.tile_start[tile + 1] - beg;
+            const int pb = beg + (int)(((long long)cnt * split) / a.splits);
+            const int pe = beg + (int)(((long long)cnt * (split + 1)) / a.splits);
+            count += pe - pb;
+            const float qa = fabsf((float)S.q);
+            const T *w_in = INPLACE ? S.w_out : S.w_in;
+            for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
+                const float v = qa * fabsf((float)w_in[p]);
+                if (__builtin_isfinite(v)) qw = fmaxf(qw, v);
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) qw = fmaxf(qw, __shfl_xor(qw, d, 64));
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = qw;
+        __syncthreads();
+        qw = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+        const double fbound = (double)qw * fmax(a.dx[0], a.dx[2]) / a.dt;
+        if (fbound > 0.0) {
+            int e, ec;
+            frexp(fbound, &e);                              // fbound < 2^e
+            frexp((double)(count > 0 ? count : 1), &ec);   // count < 2^ec
+            const int k = min(50 - e, 62 - e - ec);
+            scale = ldexp(1.0, k);
+            inv_scale = ldexp(1.0, -k);
+        }
     }
     __syncthreads();
 
@@ -306,10 +345,10 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                 // window width per axis, uniform over the wave
                 const bool wx4 = __any(nxn != n1x), wz4 = __any(nzn != n1z);
                 const int x0 = la + bx, z0 = lb + bz;
-                if (wx4 && wz4) deposit_window<4, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
-                else if (wx4) deposit_window<4, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
-                else if (wz4) deposit_window<3, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
-                else deposit_window<3, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz);
+                if (wx4 && wz4) deposit_window<4, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz, scale);
+                else if (wx4) deposit_window<4, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz, scale);
+                else if (wz4) deposit_window<3, 4>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz, scale);
+                else deposit_window<3, 3>(sJ, RC, RX, x0, z0, S0x, DSx, S0z, DSz, fx, fy, fz, scale);
             } else {
                 int gx[4];
                 size_t gz[4];
@@ -370,7 +409,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const A v = sJ[c * RC + e];
-            if (v != A(0)) atomic_add(&a.Jacc[c][g], (double)v);
+            if (v != A(0)) atomic_add(&a.Jacc[c][g], lds_value(v, inv_scale));
         }
     }
 }

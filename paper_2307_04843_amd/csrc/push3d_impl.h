@@ -28,23 +28,6 @@ template <int TX, int TY, int TZ> struct Region3 {
     static constexpr int RC = RXY * RZ;
 };
 
-// Accumulator of the LDS current tile.  FP64 runs add FP64.  FP32 runs add
-// int64 fixed point with a power-of-two scale chosen per block (every
-// contribution below 2^50 units, the node sums below 2^62): integer LDS
-// atomics run faster than FP64 ones, and the tile's sums are exact and
-// independent of the order of the atomics; the quantum is 2^-50 of the
-// block's largest |q w| dx/dt, far below FP32 rounding.
-template <typename T> struct JTile { using type = double; };
-template <> struct JTile<float> { using type = unsigned long long; };
-
-AP_D void lds_add(double *p, double c, double a) { atomic_add(p, c * a); }
-AP_D void lds_add(unsigned long long *p, double c, double a) {
-    // |c a| < 2^51: adding 1.5 * 2^52 leaves round(c a) in the low mantissa bits
-    const double t = fma(c, a, 6755399441055744.0);
-    atomicAdd(p, (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000LL));
-}
-AP_D double lds_value(double v, double) { return v; }
-AP_D double lds_value(unsigned long long v, double inv_scale) { return (double)(long long)v * inv_scale; }
 
 template <typename T> AP_D void tsc3w(T d, T w[3]) {
     const T a = T(0.5) - d, b = T(0.5) + d;
