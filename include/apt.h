@@ -129,8 +129,10 @@ typedef struct ap_ctx ap_ctx;    /* opaque */
  *              k*dx[2] (dx[2] >= 0) and at the pulse's y slice; particles
  *              keep their row (cell = k*n[0] + i, an x offset only).
  *              The grid is periodic: a field component has n nodes per axis.
- *   tile[3]    particle tile shape in cells (0 = default); the push kernel
- *              stages each tile's fields plus a halo in LDS.
+ *   tile[3]    particle tile shape in cells (0 = default: 32 x 8 on (x, z)
+ *              grids, 8 x 4 x 4 in 3-D, 32 cells on 1-D rows); the push
+ *              kernel stages each tile's fields plus a halo in LDS.  3-D
+ *              tiles must be 8x4x4, 8x8x4 or 8x8x8 (AP_E_ARG otherwise).
  *   dx[3]      cell size per axis (lambda).  For dim 0 it is the size of
  *              the virtual cells that hold positions as (cell, offset).
  *   x_min[3]   grid origin (lambda).  Node i of axis a is at

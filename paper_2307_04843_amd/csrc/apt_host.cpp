@@ -128,12 +128,13 @@ ap_status make_shape(const ap_grid_desc *g, const ap_species_desc *sp, int32_t n
             if (axis_active(s.dim, ax)) { inv2 += 1.0 / (s.dx[ax] * s.dx[ax]); dmin = std::fmin(dmin, s.dx[ax]); }
         s.dt = g->dt > 0.0 ? g->dt * kTwoPi : 0.95 / std::sqrt((double)s.dim) * dmin;
         if (!(s.dt < 1.0 / std::sqrt(inv2))) return fail(AP_E_ARG, "dt exceeds the Yee stability limit");
-        const int def1[3] = {32, 1, 1}, def2[3] = {16, 1, 8}, def3[3] = {8, 4, 4};
+        const int def1[3] = {32, 1, 1}, def2[3] = {32, 1, 8}, def3[3] = {8, 4, 4};
         for (int ax = 0; ax < 3; ++ax) {
             int t = g->tile[ax] > 0 ? g->tile[ax] : (s.dim == 3 ? def3[ax] : (s.dim == 2 ? def2[ax] : def1[ax]));
             if (!axis_active(s.dim, ax)) t = 1;
             // 3-D tile shapes are compiled into the push kernel (constant LDS
-            // strides); a tile wider than a tiny grid covers its periodic images
+            // strides; 2-D: 16x8, 32x8 and 16x16 are, others read at run
+            // time); a tile wider than a tiny grid covers its periodic images
             if (s.dim != 3 && t > s.n[ax]) t = s.n[ax];
             if (t > 64) return fail(AP_E_ARG, "tile extent must be <= 64 cells");
             s.tile[ax] = t;

@@ -1,0 +1,9 @@
+// 2-D push/deposit kernels with 32 x 8 tiles fixed at compile time.
+#include "push2d_impl.h"
+
+namespace apt {
+
+template hipError_t launch2d_tile<float, 32, 8>(int, const PushArgs<float> &, int, hipStream_t);
+template hipError_t launch2d_tile<double, 32, 8>(int, const PushArgs<double> &, int, hipStream_t);
+
+}  // namespace apt

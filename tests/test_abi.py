@@ -46,7 +46,7 @@ def test_query_layout_sizes():
     lay = apt.ap_query_layout(g, [_sp(2048)])
     assert lay.grid_bytes == 9 * 64 * 32 * 4
     assert lay.n_cells == 64 * 32
-    assert lay.n_tiles == 4 * 4           # default 16 x 8 tiles
+    assert lay.n_tiles == 2 * 4           # default 32 x 8 tiles
     assert lay.work_bytes > 2048 * 4 * 8
     g64 = _grid(prec=apt.AP_F64)
     assert apt.ap_query_layout(g64, [_sp(2048)]).grid_bytes == 9 * 64 * 32 * 8

@@ -40,10 +40,11 @@ def _run_one_step(case, precision, tile=(0, 0, 0), pulse_on_grid=False):
 
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
 @pytest.mark.parametrize("pulse", ["cfg2", "cfg1"])
-@pytest.mark.parametrize("tile", [(0, 0, 0), (32, 1, 16)])
+@pytest.mark.parametrize("tile", [(0, 0, 0), (16, 1, 8), (32, 1, 16)])
 def test_one_step_2d_parity(precision, tol, pulse, tile):
     """One full step (gather + LG/Gaussian field + Boris + move + Esirkepov + Yee) on a
-    70x40 grid (several tiles, default 16x8 or 32x16, plus ragged tails), electrons and
+    70x40 grid (several tiles: the default 32x8, 16x8 or 32x16 -- compiled-in shapes and
+    one read at run time -- plus ragged tails), electrons and
     protons."""
     if pulse == "cfg1":
         case = cases.make_case(n=(70, 1, 40), x_min=(0.0, 0.0, 0.0), t0_steps=150, pulse="cfg1",
