@@ -10,24 +10,36 @@ template <typename T, int PT, int GD> static void launch_cpl_gd(const AdjointArg
     const int per_block = 256 * (GD >= 2 ? kAdjPpt : 1);
     const dim3 grid((a.n + per_block - 1) / per_block), block(256);
     const bool px = a.lam_proxy != nullptr;
-    // 2-D and 3-D stage the gather's adjoint and the grid adjoint the current reads in LDS
-    const size_t sh = GD >= 2 ? (size_t)(adj_lds_scatter<GD>() + adj_lds_j<GD>()) * sizeof(double) : 0;
-    if constexpr (GD == 3) {
+    if constexpr (GD == 1) {
         if (np <= 2) {
-            if (px) hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 5, true, T>), grid, block, sh, s, a);
-            else hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 5, false, T>), grid, block, sh, s, a);
+            if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, false, true>), grid, block, 0, s, a);
         } else {
-            if (px) hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 7, true, T>), grid, block, sh, s, a);
-            else hipLaunchKernelGGL((k_adjoint_step_cpl3<PT, 7, false, T>), grid, block, sh, s, a);
+            if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, false, true>), grid, block, 0, s, a);
         }
     } else {
-        if (np <= 2) {
-            if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, true, true>), grid, block, sh, s, a);
-            else hipLaunchKernelGGL((k_adjoint_step<PT, 5, GD, false, true>), grid, block, sh, s, a);
+        // 2-D and 3-D: the current's adjoint (LDS copy of the grid adjoint it
+        // reads), the rest, then the gather's adjoint (LDS accumulation)
+        const size_t shj = (size_t)adj_lds_j<GD>() * sizeof(double);
+        const size_t shs = (size_t)adj_lds_scatter<GD>() * sizeof(double);
+        hipLaunchKernelGGL((k_adjoint_current<PT, GD, T>), grid, block, shj, s, a);
+        if constexpr (GD == 3) {
+            if (np <= 2) {
+                if (px) hipLaunchKernelGGL((k_adjoint_step_rest3<PT, 5, true, T>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_adjoint_step_rest3<PT, 5, false, T>), grid, block, 0, s, a);
+            } else {
+                if (px) hipLaunchKernelGGL((k_adjoint_step_rest3<PT, 7, true, T>), grid, block, 0, s, a);
+                else hipLaunchKernelGGL((k_adjoint_step_rest3<PT, 7, false, T>), grid, block, 0, s, a);
+            }
+        } else if (np <= 2) {
+            if (px) hipLaunchKernelGGL((k_adjoint_step_rest<PT, 5, GD, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step_rest<PT, 5, GD, false>), grid, block, 0, s, a);
         } else {
-            if (px) hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, true, true>), grid, block, sh, s, a);
-            else hipLaunchKernelGGL((k_adjoint_step<PT, 7, GD, false, true>), grid, block, sh, s, a);
+            if (px) hipLaunchKernelGGL((k_adjoint_step_rest<PT, 7, GD, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_adjoint_step_rest<PT, 7, GD, false>), grid, block, 0, s, a);
         }
+        hipLaunchKernelGGL((k_adjoint_gather_scatter<T, GD>), dim3((a.n + 255) / 256), block, shs, s, a);
     }
 }
 

@@ -449,8 +449,16 @@ template <typename T, int GD> AP_D void grid_stencils(const int ic[3], const T o
     }
 }
 
-template <typename T, int PT, int NT, int GD, bool PX, bool CPL>
+// PASS (coupled reading): 0 = the whole reverse step; 1 = the current's
+// adjoint only (a value-only forward pass, then d/dx^{n+1} and the
+// out-of-plane d/dv folded into the particle's adjoint state, d/dx^n kept in
+// a.gx0[0..3)); 2 = the rest but the gather's adjoint, reading d/dx^n and
+// leaving the adjoints of the gathered E, B in a.gx0[0..6); the gather's
+// adjoint is then k_adjoint_gather_scatter.  The passes split the working
+// set of one fused kernel (and its two LDS boxes) over three launches.
+template <typename T, int PT, int NT, int GD, bool PX, bool CPL, int PASS = 0>
 AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
+    static_assert(PASS == 0 || (CPL && GD > 0), "the passes split the coupled reverse step");
     // particles per thread: the coupled 2-D/3-D blocks take a tile's worth, so
     // that their LDS region is flushed once for more particles
     constexpr int PPT = (CPL && GD >= 2) ? kAdjPpt : 1;
@@ -486,7 +494,7 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
     bool use_lds = false, use_ldsj = false;
     int vol = 0;
     double *lds_adj = nullptr;
-    if constexpr (CPL && GD >= 2) {
+    if constexpr (CPL && GD >= 2 && PASS != 2) {
         extern __shared__ double adj_dyn[];
         lds_adj = adj_dyn;
         __shared__ int bbox[6];
@@ -525,11 +533,12 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             fits = fits && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
             vol *= R.ext[ax];
         }
-        use_lds = fits && vol <= adj_lds_scatter<GD>();
+        use_lds = PASS != 1 && fits && vol <= adj_lds_scatter<GD>();
         if (use_lds)
             for (int i = threadIdx.x; i < vol; i += blockDim.x) lds_adj[i] = 0.0;
         // the current's window reaches two nodes below the lowest cell and three above the highest
-        JR.L = lds_adj + adj_lds_scatter<GD>();
+        constexpr int joff = PASS == 1 ? 0 : adj_lds_scatter<GD>();
+        JR.L = lds_adj + joff;
         int volj = 3;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -542,9 +551,9 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             JR.ext[ax] = bbox[3 + ax] - bbox[ax] + 6;
             volj *= JR.ext[ax];
         }
-        use_ldsj = bbox[0] <= bbox[3] && volj <= adj_lds_j<GD>();
+        use_ldsj = PASS != 2 && bbox[0] <= bbox[3] && volj <= adj_lds_j<GD>();
         if (use_ldsj) {
-            double *L = lds_adj + adj_lds_scatter<GD>();
+            double *L = lds_adj + joff;
             const int per = JR.ext[0] * JR.ext[1] * JR.ext[2];
             for (int i = threadIdx.x; i < volj; i += blockDim.x) {
                 const int comp = i / per;
@@ -582,7 +591,11 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
         // (push and move as the forward step takes them), so that its working
         // set does not overlap the dual-number one below
         double gx0[3] = {0.0, 0.0, 0.0}, gx1[3] = {0.0, 0.0, 0.0}, gv[3] = {0.0, 0.0, 0.0};
-        if constexpr (CPL && GD > 0) {
+        if constexpr (PASS == 2) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gx0[c] = a.gx0[(size_t)c * a.n + p];
+        }
+        if constexpr (CPL && GD > 0 && PASS != 2) {
             T ev[3], bv[3];
             analytic_field<PT, T>(plain_vars<T>(a.P, a.t), Xd[0].v, Xd[1].v, Xd[2].v, ev, bv);
             {
@@ -622,6 +635,18 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
                     gx1[c] /= a.dx[c];
                     gx0[c] /= a.dx[c];
                 }
+            }
+            if constexpr (PASS == 1) {
+                // d/dx^{n+1} joins the adjoint of x^{n+1}; the move takes d/dv
+                // to the adjoint of u^{n+1/2} (velocity v = u ig, gamma = 1/ig)
+                const double vg = (double)vt[0] * gv[0] + (double)vt[1] * gv[1] + (double)vt[2] * gv[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (c == 0 || GD == 3 || (GD == 2 && c == 2)) a.lam[c][lid] += gx1[c];
+                    if (gv[c] != 0.0 || vg != 0.0) a.lam[3 + c][lid] += (gv[c] - (double)vt[c] * vg) * (double)ig;
+                    a.gx0[(size_t)c * a.n + p] = gx0[c];
+                }
+                continue;
             }
         }
         const double a0_eff = a.P.a0 != 0.0 ? a.P.a0 : 1.0;
@@ -731,7 +756,15 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
                 lB[c] += lu1[r] * (double)u1[r].d[6 + c];
             }
         }
-        if constexpr (CPL && GD > 0) {
+        if constexpr (PASS == 2) {
+            // the adjoints of the gathered E, B for the scatter pass
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a.gx0[(size_t)c * a.n + p] = lE[c];
+                a.gx0[(size_t)(3 + c) * a.n + p] = lB[c];
+            }
+        }
+        if constexpr (CPL && GD > 0 && PASS != 2) {
             // the gather's adjoint into the grid adjoints of E2^n, B2^n
             AxisStencil<T> sn[3], sh[3];
             grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
@@ -775,7 +808,7 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
         }
     }
     }   // particles of this thread
-    if constexpr (CPL && GD >= 2) {
+    if constexpr (CPL && GD >= 2 && PASS != 2) {
         if (use_lds) {
             // flush: each node of the region once (zero sums skipped)
             __syncthreads();
@@ -796,6 +829,7 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
             }
         }
     }
+    if constexpr (PASS == 1) return;
     // per-block FP64 sum, accumulated into this block's slot (no atomics)
     __shared__ double red[5][4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -809,6 +843,110 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
         double s = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[threadIdx.x][w];
         a.partial[(size_t)blockIdx.x * 5 + threadIdx.x] += s;
+    }
+}
+
+// The gather's adjoint of the coupled reverse step (after PASS 2): each
+// particle's adjoints of its gathered E, B (a.gx0, [6][n]) spread to the
+// grid adjoints lEg, lBg with the gather's weights, accumulated in LDS over
+// the bounding box of the block's cells and flushed once per node (global
+// FP64 atomics when the box does not fit).
+template <typename T, int GD> __global__ __launch_bounds__(256) void k_adjoint_gather_scatter(AdjointArgs<T> a) {
+    extern __shared__ double adj_dyn[];
+    __shared__ int bbox[6];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = a.G.n[0], ny = a.G.n[1], nxy = a.G.n[0] * a.G.n[1];
+    int ic[3] = {0, 0, 0};
+    T ov[3] = {T(0), T(0), T(0)};
+    bool ok = p < a.n;
+    if (ok) {
+        const int cell = a.G.cell[p];
+        ov[0] = a.off[0][p];
+        if (GD >= 2) ov[2] = a.off[2][p];
+        if (GD == 3) ov[1] = a.off[1][p];
+        ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
+             ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)a.G.id[p] < (unsigned)a.n;
+        const int k = (int)a.G.fnxy.div((unsigned)cell);
+        const int r = cell - k * nxy;
+        const int j = (int)a.G.fnx.div((unsigned)r);
+        ic[0] = r - j * nx;
+        ic[1] = j;
+        ic[2] = k;
+    }
+    if (threadIdx.x < 3) {
+        bbox[threadIdx.x] = 0x7fffffff;
+        bbox[3 + threadIdx.x] = -0x7fffffff;
+    }
+    __syncthreads();
+    if (ok) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            atomicMin(&bbox[ax], ic[ax]);
+            atomicMax(&bbox[3 + ax], ic[ax]);
+        }
+    }
+    __syncthreads();
+    AdjRegion R{};
+    bool fits = true;
+    int vol = 6;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        R.n[ax] = a.G.n[ax];
+        if (GD == 2 && ax == 1) {
+            R.lo[1] = 0;
+            R.ext[1] = 1;
+            continue;
+        }
+        R.lo[ax] = bbox[ax] - 1;
+        R.ext[ax] = bbox[3 + ax] - bbox[ax] + 4;
+        fits = fits && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
+        vol *= R.ext[ax];
+    }
+    const bool use_lds = fits && vol <= adj_lds_scatter<GD>();
+    if (use_lds)
+        for (int i = threadIdx.x; i < vol; i += blockDim.x) adj_dyn[i] = 0.0;
+    __syncthreads();
+    if (ok) {
+        double lE[3], lB[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lE[c] = a.gx0[(size_t)c * a.n + p];
+            lB[c] = a.gx0[(size_t)(3 + c) * a.n + p];
+        }
+        AxisStencil<T> sn[3], sh[3];
+        grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
+        if (use_lds) {
+            scatter_adjoint_lds<T, GD>(adj_dyn, 0, R, sh[0], sn[1], sn[2], lE[0]);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 1, R, sn[0], sh[1], sn[2], lE[1]);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 2, R, sn[0], sn[1], sh[2], lE[2]);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 3, R, sn[0], sh[1], sh[2], lB[0]);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 4, R, sh[0], sn[1], sh[2], lB[1]);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 5, R, sh[0], sh[1], sn[2], lB[2]);
+        } else {
+            scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
+            scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
+            scatter_adjoint<T, GD>(a.lEg[2], sn[0], sn[1], sh[2], nx, ny, lE[2]);
+            scatter_adjoint<T, GD>(a.lBg[0], sn[0], sh[1], sh[2], nx, ny, lB[0]);
+            scatter_adjoint<T, GD>(a.lBg[1], sh[0], sn[1], sh[2], nx, ny, lB[1]);
+            scatter_adjoint<T, GD>(a.lBg[2], sh[0], sh[1], sn[2], nx, ny, lB[2]);
+        }
+    }
+    if (!use_lds) return;
+    __syncthreads();
+    const int per = R.ext[0] * R.ext[1] * R.ext[2];
+    for (int i = threadIdx.x; i < vol; i += blockDim.x) {
+        const double v = adj_dyn[i];
+        if (v == 0.0) continue;
+        const int comp = i / per;
+        int r = i - comp * per;
+        const int l2 = r / (R.ext[0] * R.ext[1]);
+        r -= l2 * R.ext[0] * R.ext[1];
+        const int l1 = r / R.ext[0], l0 = r - l1 * R.ext[0];
+        int g[3] = {R.lo[0] + l0, R.lo[1] + l1, R.lo[2] + l2};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) g[ax] = wrap_idx(g[ax], R.n[ax]);
+        const size_t node = ((size_t)g[2] * R.n[1] + g[1]) * R.n[0] + g[0];
+        atomicAdd(comp < 3 ? a.lEg[comp] + node : a.lBg[comp - 3] + node, v);
     }
 }
 
@@ -827,10 +965,27 @@ __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
 }
 // The coupled 3-D step carries the current's and the gather's adjoints as
 // well: one wave per SIMD, so that its working set stays in registers.
+// The coupled reverse step in two launches (see adjoint_step_body's PASS).
+template <int PT, int GD, typename T>
+__global__ __launch_bounds__(256) void k_adjoint_current(AdjointArgs<T> a) {
+    adjoint_step_body<T, PT, 5, GD, false, true, 1>(a);
+}
+// The rest: (x, z) grids at two waves per SIMD (FP32); in 3-D the dual-number
+// working set, the 27-point gather gradients and the gather's adjoint need
+// the whole register file (one wave per SIMD; at two it spilled ~500 words).
+template <int PT, int NT, int GD, bool PX>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step_rest(
+    AdjointArgs<float> a) {
+    adjoint_step_body<float, PT, NT, GD, PX, true, 2>(a);
+}
+template <int PT, int NT, int GD, bool PX>
+__global__ __launch_bounds__(256) void k_adjoint_step_rest(AdjointArgs<double> a) {
+    adjoint_step_body<double, PT, NT, GD, PX, true, 2>(a);
+}
 template <int PT, int NT, bool PX, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_step_cpl3(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_step_rest3(
     AdjointArgs<T> a) {
-    adjoint_step_body<T, PT, NT, 3, PX, true>(a);
+    adjoint_step_body<T, PT, NT, 3, PX, true, 2>(a);
 }
 
 }  // namespace apt

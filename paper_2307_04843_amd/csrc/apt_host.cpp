@@ -282,6 +282,7 @@ struct GridCkpt {
     size_t lam[6] = {}, partial = 0, fixed = 0;
     size_t lam_sp[kMaxSpecies][6] = {};   // coupled: adjoint state of every species
     size_t lgrid = 0;                     // coupled: FP64 adjoints lE, lB, lJt (3 x ncell each)
+    size_t gx0 = 0;                       // coupled: [6][n] per-particle values between the reverse passes
     int blocks = 0;
     size_t outer = 0, inner = 0;
     size_t sp_off[kMaxSpecies] = {};   // species blocks inside a checkpoint slot
@@ -312,6 +313,7 @@ GridCkpt grid_ckpt(const RunShape &s) {
         for (int i = 0; i < s.nsp; ++i)
             for (int c = 0; c < 6; ++c) G.lam_sp[i][c] = take((size_t)s.np[i] * 8);
         G.lgrid = take((size_t)9 * (size_t)s.ncell * 8);
+        G.gx0 = take((size_t)6 * (size_t)(nmax > 0 ? nmax : 1) * 8);
     } else {
         for (int c = 0; c < 6; ++c) G.lam[c] = take((size_t)nmax * 8);
     }
@@ -1881,6 +1883,7 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
             a.w = b.w;
             a.q = s.q[i];
             a.dim = s.dim;
+            a.gx0 = reinterpret_cast<double *>(c->ckpt + G.gx0);
             a.lam_proxy = i == sp ? static_cast<const T *>(dl_dproxy) : nullptr;
             a.partial = partial;
             for (int k = 0; k < 4; ++k) a.slot[k] = slot[k];

@@ -159,6 +159,7 @@ template <typename T> struct AdjointArgs {
     double q;                    // species charge
     const double *lJ[3];         // E adjoint after the first half of the reverse Yee step (E nodes)
     double *lEg[3], *lBg[3];     // grid adjoints of E2^n, B2^n: the gather's adjoint is added here
+    double *gx0;                 // coupled 2-D/3-D: [6][n] per-particle values between the reverse passes
 };
 template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_adjoint_step_coupled(int pulse, const AdjointArgs<T> &a, hipStream_t s);
