@@ -412,18 +412,19 @@ struct AdjRegion {
         return l;
     }
 };
-template <typename T, int GD>
-AP_D void scatter_adjoint_lds(double *L, int comp, const AdjRegion &R, const AxisStencil<T> &sx,
-                              const AxisStencil<T> &sy, const AxisStencil<T> &sz, double val) {
+// LDS accumulator L: FP64, or int64 fixed point with scale `scale` (lds_add).
+template <typename T, int GD, typename JA>
+AP_D void scatter_adjoint_lds(JA *L, int comp, const AdjRegion &R, const AxisStencil<T> &sx,
+                              const AxisStencil<T> &sy, const AxisStencil<T> &sz, double val, double scale = 1.0) {
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
 #pragma unroll
         for (int q = 0; q < (GD == 3 ? 3 : 1); ++q) {
             const double wzy = (double)sz.w[b] * (GD == 3 ? (double)sy.w[q] : 1.0) * val;
             const int l2 = R.local(2, sz.idx[b]), l1 = GD == 3 ? R.local(1, sy.idx[q]) : 0;
-            double *row = L + (((size_t)comp * R.ext[2] + l2) * R.ext[1] + l1) * R.ext[0];
+            JA *row = L + (((size_t)comp * R.ext[2] + l2) * R.ext[1] + l1) * R.ext[0];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) atomicAdd(row + R.local(0, sx.idx[m]), (double)sx.w[m] * wzy);
+            for (int m = 0; m < 3; ++m) lds_add(row + R.local(0, sx.idx[m]), (double)sx.w[m] * wzy, scale);
         }
     }
 }
@@ -852,8 +853,16 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
 // the bounding box of the block's cells and flushed once per node (global
 // FP64 atomics when the box does not fit).
 template <typename T, int GD> __global__ __launch_bounds__(256) void k_adjoint_gather_scatter(AdjointArgs<T> a) {
-    extern __shared__ double adj_dyn[];
+    // FP32 runs accumulate in int64 fixed point (JTile) with a power-of-two
+    // scale from the block's largest |value|: every term lies below 2^50
+    // units and a node takes at most one term per particle of the block, so
+    // its sum stays below 2^58.  Integer LDS atomics run faster than FP64
+    // ones, and the sums do not depend on the order of the atomics
+    using JA = typename JTile<T>::type;
+    extern __shared__ double adj_dyn_raw[];
+    JA *adj_dyn = reinterpret_cast<JA *>(adj_dyn_raw);
     __shared__ int bbox[6];
+    __shared__ double s_max[4];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = a.G.n[0], ny = a.G.n[1], nxy = a.G.n[0] * a.G.n[1];
     int ic[3] = {0, 0, 0};
@@ -904,24 +913,47 @@ template <typename T, int GD> __global__ __launch_bounds__(256) void k_adjoint_g
     }
     const bool use_lds = fits && vol <= adj_lds_scatter<GD>();
     if (use_lds)
-        for (int i = threadIdx.x; i < vol; i += blockDim.x) adj_dyn[i] = 0.0;
-    __syncthreads();
+        for (int i = threadIdx.x; i < vol; i += blockDim.x) adj_dyn[i] = JA(0);
+    double lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
     if (ok) {
-        double lE[3], lB[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             lE[c] = a.gx0[(size_t)c * a.n + p];
             lB[c] = a.gx0[(size_t)(3 + c) * a.n + p];
         }
+    }
+    double scale = 1.0, inv_scale = 1.0;
+    if constexpr (std::is_same<T, float>::value) {
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m = fmax(m, fmax(fabs(lE[c]), fabs(lB[c])));
+        if (!__builtin_isfinite(m)) m = 0.0;   // a non-finite value goes to the global path below
+        for (int d = 32; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+        if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+        __syncthreads();
+        m = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+        if (m > 0.0) {
+            int e;
+            frexp(m, &e);   // every term (a value times stencil weights <= 1) lies below 2^e
+            e = e < -960 ? -960 : e;   // keeps the scale finite; smaller terms round to zero
+            scale = ldexp(1.0, 50 - e);
+            inv_scale = ldexp(1.0, e - 50);
+        }
+    }
+    __syncthreads();
+    if (ok) {
         AxisStencil<T> sn[3], sh[3];
         grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
-        if (use_lds) {
-            scatter_adjoint_lds<T, GD>(adj_dyn, 0, R, sh[0], sn[1], sn[2], lE[0]);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 1, R, sn[0], sh[1], sn[2], lE[1]);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 2, R, sn[0], sn[1], sh[2], lE[2]);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 3, R, sn[0], sh[1], sh[2], lB[0]);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 4, R, sh[0], sn[1], sh[2], lB[1]);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 5, R, sh[0], sh[1], sn[2], lB[2]);
+        bool fin = true;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fin = fin && __builtin_isfinite(lE[c]) && __builtin_isfinite(lB[c]);
+        if (use_lds && fin) {
+            scatter_adjoint_lds<T, GD>(adj_dyn, 0, R, sh[0], sn[1], sn[2], lE[0], scale);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 1, R, sn[0], sh[1], sn[2], lE[1], scale);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 2, R, sn[0], sn[1], sh[2], lE[2], scale);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 3, R, sn[0], sh[1], sh[2], lB[0], scale);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 4, R, sh[0], sn[1], sh[2], lB[1], scale);
+            scatter_adjoint_lds<T, GD>(adj_dyn, 5, R, sh[0], sh[1], sn[2], lB[2], scale);
         } else {
             scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
             scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
@@ -935,8 +967,9 @@ template <typename T, int GD> __global__ __launch_bounds__(256) void k_adjoint_g
     __syncthreads();
     const int per = R.ext[0] * R.ext[1] * R.ext[2];
     for (int i = threadIdx.x; i < vol; i += blockDim.x) {
-        const double v = adj_dyn[i];
-        if (v == 0.0) continue;
+        const JA raw = adj_dyn[i];
+        if (raw == JA(0)) continue;
+        const double v = lds_value(raw, inv_scale);
         const int comp = i / per;
         int r = i - comp * per;
         const int l2 = r / (R.ext[0] * R.ext[1]);
