@@ -153,6 +153,7 @@ def three_d_leg(args):
             try:
                 p = torch.tensor([pp["beta_f"], pp["chirp"]], dtype=torch.float64, requires_grad=True)
                 torch.cuda.synchronize()
+                free_gb = torch.cuda.mem_get_info()[0] / 1e9
                 a = time.perf_counter()
                 u, _ = APTRun.apply(p, run)
                 torch.cuda.synchronize()
@@ -168,7 +169,8 @@ def three_d_leg(args):
                             "grad": p.grad.tolist(), "observable": float(obs.detach()),
                             "forward_pushes_per_s": n * args.adj3d_steps / (b - a),
                             "adjoint_pushes_per_s": n * args.adj3d_steps / (c - b),
-                            "checkpoint_gb": run.ckpt.numel() / 1e9, "note": note}
+                            "checkpoint_gb": run.ckpt.numel() / 1e9, "hbm_free_gb_at_forward": free_gb,
+                            "note": note}
                 log("3-D %s: %.3e pushes/s" % (key, out[key]["adjoint_pushes_per_s"]))
             finally:
                 run.close()
@@ -583,14 +585,14 @@ PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h",
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "410dc79c148ce0b99b2209366bb4594d97b8064a8751334d031992a242599e4e",
-    # FETCH_SIZE 3.2244e7 KiB x 1.99991 (a 2 GiB device copy reads as 1048614 KiB)
-    "fetch_bytes_per_launch": 6.6033e10,
-    # WRITE_SIZE 7.6615e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
-    "write_bytes_per_launch": 7.8454e10,
-    "valu_lane_ops_per_push": 1488.7,
-    "ms_per_launch": 94.910,
-    "lds_busy_frac": 0.470,
+    "sources_sha256": "f80d4e0002dd69d99bc929197a9e4d7cb4805f56abf343396b5885e645413a57",
+    # FETCH_SIZE 3.2335e7 KiB x 2.00005 (a 2 GiB device copy reads as 1048587.5 KiB)
+    "fetch_bytes_per_launch": 6.6221e10,
+    # WRITE_SIZE 7.6548e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.8385e10,
+    "valu_lane_ops_per_push": 1492.0,
+    "ms_per_launch": 95.119,
+    "lds_busy_frac": 0.472,
     "lds_bank_conflict_frac": 0.567,
     "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
             "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
