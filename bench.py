@@ -25,12 +25,16 @@ Other legs (``--legs``):
   adjoint  the gridless head-on collision (2^24 electrons, gamma = 2000, eps^4
            nonparaxial Gaussian a0 = 20, w0 = 2): forward with recording plus
            ap_backward for d<p_perp^2>/d(a0, w0, x_f), FP32 and FP64;
+  adjoint_full  the same collision's whole 20000-step run under binomial
+           checkpointing (64 whole states);
   three_d  the 512 x 256 x 256 flying-focus run (268M electrons, beta_f = -1,
            chirp 5%): steps 1800 ... 1900 of 4000, then the frozen-grid and the
            fully coupled adjoints over a 32-step window;
   small    the 128 x 64 Gaussian run (32768 electrons, 200 steps), FP64, FP32;
   rows1d   30 independent 1-D rows (Sec. III.B), 7.9M electrons, 500 steps;
   cpu      the oracle baselines.
+Optional leg: adjoint3d_long, the 3-D run's frozen-grid adjoint over a
+1000-step window under binomial checkpointing (16 whole states).
 
 Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
 """
