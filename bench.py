@@ -119,7 +119,8 @@ def three_d_leg(args):
                        "ions, flying focus beta_f=-1 a0=2 w0=4 tau=150 chirp 5%%, steps %d..%d of the "
                        "4000-step run" % (T0_STEP3, T0_STEP3 + args.steps3d), "particles": n,
            "steps": args.steps3d, "warmup": 5}
-    sim = Simulation(3, precision="f32", species=species, **geo)
+    tile3 = tuple(int(v) for v in args.tile3.split(",")) if args.tile3 else (0, 0, 0)
+    sim = Simulation(3, precision="f32", species=species, tile=tile3, **geo)
     try:
         sim.set_pulse("ff", **pp)
         sim.step(5)
@@ -889,7 +890,7 @@ def main():
     ap.add_argument("--steps3d", type=int, default=100, help="timed steps of the 512x256x256 leg")
     ap.add_argument("--adj3d-steps", type=int, default=32, help="adjoint window of the 3-D leg (0: none)")
     ap.add_argument("--skip-coupled", action="store_true", help="3-D leg: frozen-grid adjoint only")
-    ap.add_argument("--tile3", default="", help="tile shape of the headline run, e.g. 8,8,4 (default: library's)")
+    ap.add_argument("--tile3", default="", help="tile shape of the 3-D runs, e.g. 8,8,4 (default: library's)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy a device buffer of this size (a known-size kernel for "
                          "scaling HBM counters in profiling runs)")

@@ -713,15 +713,33 @@ hipError_t launch_resort_counts(const int32_t *stay, const int32_t *mcount, int3
     return hipGetLastError();
 }
 
+// Particles changing tile take their ranks after the tile's stayers.  The
+// lanes of a wave (consecutive slots of one old tile) enter few distinct
+// tiles: one counter atomic per distinct tile, its lanes ranked in lane order.
 __global__ __launch_bounds__(256) void k_resort_perm(PermArgs a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const int cell = a.cell[p];
-    const int t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
-                                           : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
-    const int k = a.key[p];
-    const int slot = k >= 0 ? k : a.stay[t] + atomicAdd(&a.mrank[t], 1);
-    a.perm[a.start[t] + slot] = p;
+    const bool live = p < a.n;
+    int t = 0, k = 0;
+    if (live) {
+        const int cell = a.cell[p];
+        t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
+                                     : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
+        k = a.key[p];
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long todo = __ballot(live && k < 0);
+    int slot = k;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int tl = __shfl(t, leader, 64);
+        const unsigned long long m = __ballot(live && k < 0 && t == tl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&a.mrank[tl], (int)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if ((m >> lane) & 1ull) slot = a.stay[tl] + base + (int)__popcll(m & ((1ull << lane) - 1ull));
+        todo &= ~m;
+    }
+    if (live) a.perm[a.start[t] + slot] = p;
 }
 
 hipError_t launch_resort_perm(const PermArgs &a, hipStream_t s) {

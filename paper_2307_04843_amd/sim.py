@@ -9,10 +9,18 @@ import torch
 from . import apt
 
 
+_TORCH_DTYPE = {np.dtype(np.float32): torch.float32, np.dtype(np.float64): torch.float64,
+                np.dtype(np.int32): torch.int32}
+
+
 def _dev(x, np_dtype, dev):
-    """Device tensor of a host array (converted to np_dtype) or of a tensor."""
+    """Device tensor of a host array (converted to np_dtype) or of a tensor
+    (returned as it is when it already is a contiguous one of that type on dev)."""
     if isinstance(x, torch.Tensor):
-        return x.to(device=dev, dtype=torch.from_numpy(np.zeros(0, np_dtype)).dtype).contiguous()
+        td = _TORCH_DTYPE[np.dtype(np_dtype)]
+        if x.dtype == td and x.device == dev and x.is_contiguous():
+            return x
+        return x.to(device=dev, dtype=td).contiguous()
     return torch.as_tensor(np.ascontiguousarray(np.asarray(x).astype(np_dtype)), device=dev)
 
 
