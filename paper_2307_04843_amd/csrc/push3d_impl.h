@@ -220,13 +220,24 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     int q0 = 0, q1 = 0;
     const bool has0 = PREFETCH && a.nsp > 0 && first_slot(0, q0);
     const bool has1 = PREFETCH && a.nsp > 1 && first_slot(1, q1);
-    constexpr int NIT = (RC + 255) / 256;   // launched with 256 threads
+    // E2, B2 are staged on the region's inner box only (nodes 1 .. R - 2 per
+    // axis): the gather of a particle in the tile reads one node below its
+    // cell and two above, while the deposit's window (the J tile, the whole
+    // region) reaches one further on each side
+    constexpr int IX = RX - 2, IXY = IX * (R::RY - 2), IC = IXY * (R::RZ - 2);
+    constexpr int NIT = (IC + 255) / 256;   // launched with 256 threads
+    auto inner_node = [&](int f) {
+        const int fz = f / IXY;
+        const int fr = f - fz * IXY;
+        const int fy = fr / IX;
+        return (fz + 1) * RXY + (fy + 1) * RX + (fr - fy * IX + 1);
+    };
     T sv[NIT][6];
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
-        const int e = (int)threadIdx.x + 256 * k;
-        if (e < RC) {
-            const size_t g = global_node(e);
+        const int f = (int)threadIdx.x + 256 * k;
+        if (f < IC) {
+            const size_t g = global_node(inner_node(f));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 sv[k][c] = a.E[c][g];
@@ -236,15 +247,21 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     }
     Rec pre0{};
     if (has0) pre0 = load_rec(a.sp[0], q0);
+    // the weight of the first particle of species 1, for the scale pass below
+    T w1 = T(0);
+    if (has1) w1 = (INPLACE ? a.sp[1].w_out : a.sp[1].w_in)[q1];
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
-        const int e = (int)threadIdx.x + 256 * k;
-        if (e < RC) {
+        const int f = (int)threadIdx.x + 256 * k;
+        if (f < IC) {
+            const int e = inner_node(f);
 #pragma unroll
             for (int c = 0; c < 6; ++c) sF[c * RC + e] = sv[k][c];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sJ[c * RC + e] = JA(0);
         }
+    }
+    for (int e = (int)threadIdx.x; e < RC; e += 256) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sJ[c * RC + e] = JA(0);
     }
     // fixed-point scale of the block's current tile (FP32 runs): from the
     // largest |q w| of its particles (non-finite weights belong to skipped
@@ -262,7 +279,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
             const int32_t *perm = INPLACE ? nullptr : a.sp[s].perm;
             for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
                 const bool first = PREFETCH && p == pb + (int)threadIdx.x;
-                const T wv = first && s == 0 ? pre0.w : w_in[first && s == 1 ? q1 : (perm ? perm[p] : p)];
+                const T wv = first && s == 0 ? pre0.w : (first && s == 1 ? w1 : w_in[perm ? perm[p] : p]);
                 const float v = qa * fabsf((float)wv);
                 if (__builtin_isfinite(v)) qw = fmaxf(qw, v);
             }
