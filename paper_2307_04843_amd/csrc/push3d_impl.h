@@ -247,9 +247,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     }
     Rec pre0{};
     if (has0) pre0 = load_rec(a.sp[0], q0);
-    // the weight of the first particle of species 1, for the scale pass below
-    T w1 = T(0);
-    if (has1) w1 = (INPLACE ? a.sp[1].w_out : a.sp[1].w_in)[q1];
+    Rec pre1{};
+    if (has1) pre1 = load_rec(a.sp[1], q1);
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
         const int f = (int)threadIdx.x + 256 * k;
@@ -279,7 +278,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
             const int32_t *perm = INPLACE ? nullptr : a.sp[s].perm;
             for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
                 const bool first = PREFETCH && p == pb + (int)threadIdx.x;
-                const T wv = first && s == 0 ? pre0.w : (first && s == 1 ? w1 : w_in[perm ? perm[p] : p]);
+                const T wv = first && s == 0 ? pre0.w : (first && s == 1 ? pre1.w : w_in[perm ? perm[p] : p]);
                 const float v = qa * fabsf((float)wv);
                 if (__builtin_isfinite(v)) qw = fmaxf(qw, v);
             }
@@ -334,7 +333,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
         // p: output slot; q: input slot (the previous order through perm)
         for (int p = pb + (int)threadIdx.x; p < pe; p += blockDim.x) {
             const bool first = PREFETCH && p == pb + (int)threadIdx.x;
-            const Rec r = first && s == 0 ? pre0 : load_rec(S, first && s == 1 ? q1 : (INPLACE || !S.perm ? p : S.perm[p]));
+            const Rec r = first && s == 0 ? pre0 : (first && s == 1 ? pre1 : load_rec(S, INPLACE || !S.perm ? p : S.perm[p]));
             const int q = r.q;
             const int cell = r.cell;
             T off[3];
