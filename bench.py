@@ -590,15 +590,15 @@ PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h",
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f80d4e0002dd69d99bc929197a9e4d7cb4805f56abf343396b5885e645413a57",
-    # FETCH_SIZE 3.2335e7 KiB x 2.00005 (a 2 GiB device copy reads as 1048587.5 KiB)
-    "fetch_bytes_per_launch": 6.6221e10,
-    # WRITE_SIZE 7.6548e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
-    "write_bytes_per_launch": 7.8385e10,
-    "valu_lane_ops_per_push": 1492.0,
-    "ms_per_launch": 95.119,
-    "lds_busy_frac": 0.472,
-    "lds_bank_conflict_frac": 0.567,
+    "sources_sha256": "65579bb7e290bd7f5eb1e78039cfad83346b686aa10c0417af1e1d80b0082531",
+    # FETCH_SIZE 2.984e7 KiB x 1.99996 (a 2 GiB device copy reads as 1048606.8 KiB)
+    "fetch_bytes_per_launch": 6.111e10,
+    # WRITE_SIZE 7.632e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.815e10,
+    "valu_lane_ops_per_push": 1503.9,
+    "ms_per_launch": 90.214,
+    "lds_busy_frac": 0.494,
+    "lds_bank_conflict_frac": 0.575,
     "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
             "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
 }
