@@ -500,7 +500,14 @@ ap_status ap_timing_read(ap_ctx *ctx, ap_timing *out, int32_t reset);
  * starts at zero.  More injected particles than free slots: AP_E_ARG,
  * nothing changed.  Drops any adjoint recording; 1-D and 3-D runs re-sort at
  * the next step.  One synchronisation of the stream (the checks); the work
- * is a pass over the particles' cells and one over the free slots. */
+ * is a pass over the particles' cells and one over the free slots.  In 2-D
+ * runs, once the particles have been sorted by ap_step and while no re-sort
+ * is pending, the leaving particles are looked up instead in the slot
+ * ranges of the tile columns they can have reached since that sort (a
+ * particle moves less than a cell per step) and among the particles
+ * injected since: this relies on the particle arrays being changed only by
+ * ap_step and ap_shift_window between the two (a caller that edits cells
+ * there calls ap_step first, or passes the particles anew to ap_init). */
 typedef struct ap_inject {
     const int32_t *cell;
     const void    *off[3];      /* active axes; NULL on the others           */

@@ -62,6 +62,9 @@ struct WorkLayout {
     // moving window: per species the free-id bit map; popcounts of its words,
     // their scan, scan scratch and counters, shared by the species
     size_t wmap[kMaxSpecies] = {}, wslot[kMaxSpecies] = {}, wpop = 0, wfrank = 0, wpart = 0, wcnt = 0;
+    // slots of the particles injected since the last full sort (2-D windows)
+    size_t winj[kMaxSpecies] = {};
+    int64_t winj_cap[kMaxSpecies] = {};
     size_t lam[6] = {}, adj_partial = 0;   // gridless adjoint state and gradient partials
     int adj_blocks = 0;
     size_t slot_bytes = 0;                 // one checkpoint slot (all species), gridless
@@ -225,6 +228,10 @@ WorkLayout make_layout(const RunShape &s) {
                 wmax = words > wmax ? words : wmax;
                 L.wmap[i] = take((size_t)words * 4);
                 L.wslot[i] = take((size_t)(s.np[i] > 0 ? s.np[i] : 1) * 4);
+                if (s.dim == 2) {
+                    L.winj_cap[i] = s.np[i] / 16 > 4096 ? s.np[i] / 16 : 4096;
+                    L.winj[i] = take((size_t)L.winj_cap[i] * 4);
+                }
             }
             L.wpop = take((size_t)wmax * 4);
             L.wfrank = take((size_t)(wmax + 1) * 4);
@@ -521,6 +528,11 @@ struct ap_ctx {
     // moving window: free slots per species, up to the leavers of the last
     // shift (counted on the device, added at the next shift)
     int64_t n_free[kMaxSpecies] = {0, 0, 0, 0};
+    // 2-D moving window: the step of the last full sort, and the particles
+    // injected since (their slots listed while the list holds them)
+    int64_t sort_step = 0;
+    int64_t inj_n[kMaxSpecies] = {0, 0, 0, 0};
+    bool inj_overflow = false;
     int64_t step = 0;
     bool sorted_once = false;
     bool need_sort = false;      // re-sort before the next push (state restored from a checkpoint)
@@ -2065,17 +2077,51 @@ template <typename T> ap_status shift_window_impl(ap_ctx *c, int32_t dir, const 
     T *F[6];
     for (int k = 0; k < 6; ++k) F[k] = grid + (size_t)k * (size_t)s.ncell;
     HIPCHK(launch_window_column<T>(F, col, nx, (size_t)s.ncell, c->stream), "shift window");
+    // 2-D runs push in place between full sorts, moving a particle less than
+    // a cell per step: a particle now in the leaving column sat, at the last
+    // sort, within S = (steps since) cells of it, so its slot lies in the
+    // range of a tile column meeting [col - S, col + S] -- unless it was
+    // injected since, and then it is listed.  Otherwise (3-D, 1-D rows, a
+    // pending re-sort, an overflowed list) every cell is read.
+    LeaveTiles lt{};
+    bool by_tiles = false;
+    if (s.dim == 2 && c->sorted_once && !c->need_sort && !c->inj_overflow) {
+        const int64_t S = c->step - c->sort_step;
+        const int TX = s.tile[0], ntx = s.ntile[0];
+        if (S >= 0 && 2 * S + 1 < nx) {
+            const int lo = (int)(((col - S) % nx + nx) % nx), hi = (int)((col + S) % nx);
+            const int tlo = lo / TX, thi = hi / TX;
+            lt.tx0 = tlo;
+            // tile columns from lo's to hi's; an interval that crosses the ring's
+            // end and comes back into lo's tile column meets all of them
+            lt.ncols = lo <= hi ? thi - tlo + 1 : (thi >= tlo ? ntx : ntx - tlo + thi + 1);
+            lt.ntile_x = ntx;
+            lt.ntile_z = s.ntile[2];
+            by_tiles = lt.ncols < ntx;
+        }
+    }
     for (int i = 0; i < s.nsp; ++i) {
         if (s.np[i] == 0) continue;
         WindowArgs<T> a = window_args<T>(c, i, col, in_col, inject);
         a.count = cnt + 1 + i;   // leavers, read back at the next shift
-        HIPCHK(launch_window_leave<T>(a, c->stream), "shift window");
+        if (by_tiles) {
+            lt.start = c->wp<int32_t>(c->L.start[i]);
+            lt.list = c->wp<int32_t>(c->L.winj[i]);
+            lt.list_n = (int32_t)c->inj_n[i];
+            HIPCHK(launch_window_leave_tiles<T>(a, lt, c->stream), "shift window");
+        } else {
+            HIPCHK(launch_window_leave<T>(a, c->stream), "shift window");
+        }
         if (a.n_inj == 0) continue;
         int32_t *pop = c->wp<int32_t>(c->L.wpop);
         int32_t *frank = c->wp<int32_t>(c->L.wfrank);
         HIPCHK(launch_window_popcount(a.freemap, a.words, pop, c->stream), "shift window");
         HIPCHK(launch_scan(pop, frank, a.words, c->wp<int32_t>(c->L.wpart), c->stream), "shift window");
+        if (s.dim == 2 && !c->inj_overflow && c->inj_n[i] + a.n_inj <= c->L.winj_cap[i])
+            a.inj_list = c->wp<int32_t>(c->L.winj[i]) + c->inj_n[i];
         HIPCHK(launch_window_fill<T>(a, c->stream), "shift window");
+        if (a.inj_list) c->inj_n[i] += a.n_inj;
+        else if (s.dim == 2) c->inj_overflow = true;
         HIPCHK(launch_window_clear(a.freemap, frank, a.words, a.n_inj, c->stream), "shift window");
         c->n_free[i] -= a.n_inj;
     }
@@ -2190,6 +2236,9 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         }
         c->sorted_once = true;
         c->need_sort = false;
+        c->sort_step = c->step;
+        for (int i = 0; i < kMaxSpecies; ++i) c->inj_n[i] = 0;
+        c->inj_overflow = false;
         from_alt = true;
     } else if (from_perm) {
         // the permutation from the ranks the last push wrote (into the buffer holding the state)

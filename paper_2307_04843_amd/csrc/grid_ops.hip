@@ -521,7 +521,58 @@ __global__ __launch_bounds__(256) void k_window_popcount(const uint32_t *freemap
     if (w < words) pop[w] = __popc(freemap[w]);
 }
 
+// One slot reached twice (a listed slot inside a scanned tile, or listed
+// twice) is freed once: the thread that swaps its cell to the dead value.
+template <typename T> AP_D bool window_free_once(const WindowArgs<T> &a, int p, int cell) {
+    if (atomicCAS(&a.cell[p], cell, kDeadCell) != cell) return false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (a.off[k]) a.off[k][p] = T(0);
+        a.u[k][p] = T(0);
+    }
+    a.w[p] = T(0);
+    if (a.proxy) {
+        a.proxy[2 * p] = T(0);
+        a.proxy[2 * p + 1] = T(0);
+    }
+    const int id = a.id[p];
+    atomicOr(&a.freemap[id >> 5], 1u << (id & 31));
+    a.free_slot[id] = p;
+    return true;
+}
+
+// Blocks [0, ncols * ntile_z): one tile each, a pass over its slot range;
+// the remaining blocks: the listed slots, 256 each.
+template <typename T> __global__ __launch_bounds__(256) void k_window_leave_tiles(WindowArgs<T> a, LeaveTiles lt) {
+    const int b = blockIdx.x;
+    const int ntb = lt.ncols * lt.ntile_z;
+    int cnt = 0;
+    if (b < ntb) {
+        const int tz = b / lt.ncols;
+        const int tx = (lt.tx0 + (b - tz * lt.ncols)) % lt.ntile_x;
+        const int t = tx + lt.ntile_x * tz;
+        const int end = lt.start[t + 1];
+        for (int p = lt.start[t] + (int)threadIdx.x; p < end; p += blockDim.x) {
+            const int c = a.cell[p];
+            if (window_leaves(a, c) && window_free_once(a, p, c)) ++cnt;
+        }
+    } else {
+        const int j = (b - ntb) * (int)blockDim.x + (int)threadIdx.x;
+        if (j < lt.list_n) {
+            const int p = lt.list[j];
+            if ((unsigned)p < (unsigned)a.n) {
+                const int c = a.cell[p];
+                if (window_leaves(a, c) && window_free_once(a, p, c)) ++cnt;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(a.count, (unsigned long long)cnt);
+}
+
 template <typename T> AP_D void window_put(const WindowArgs<T> &a, int p, int r) {
+    if (a.inj_list) a.inj_list[r] = p;
     const int ic = a.in_cell[r];
     const int row = (int)a.fnx.div((uint32_t)ic);
     a.cell[p] = row * a.nx + a.col;   // the entering column is the storage column that left
@@ -615,6 +666,12 @@ template <typename T> hipError_t launch_window_leave(const WindowArgs<T> &a, hip
     hipLaunchKernelGGL((k_window_leave<T>), dim3(blocks), dim3(256), 0, s, a, vec);
     return hipGetLastError();
 }
+template <typename T> hipError_t launch_window_leave_tiles(const WindowArgs<T> &a, const LeaveTiles &lt, hipStream_t s) {
+    const int blocks = lt.ncols * lt.ntile_z + (lt.list_n + 255) / 256;
+    if (a.n == 0 || blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_window_leave_tiles<T>), dim3(blocks), dim3(256), 0, s, a, lt);
+    return hipGetLastError();
+}
 hipError_t launch_window_popcount(const uint32_t *freemap, int32_t words, int32_t *pop, hipStream_t s) {
     if (words == 0) return hipSuccess;
     hipLaunchKernelGGL(k_window_popcount, dim3((words + 255) / 256), dim3(256), 0, s, freemap, words, pop);
@@ -649,6 +706,8 @@ template hipError_t launch_window_count_leavers<float>(const WindowArgs<float> &
 template hipError_t launch_window_count_leavers<double>(const WindowArgs<double> &, hipStream_t);
 template hipError_t launch_window_leave<float>(const WindowArgs<float> &, hipStream_t);
 template hipError_t launch_window_leave<double>(const WindowArgs<double> &, hipStream_t);
+template hipError_t launch_window_leave_tiles<float>(const WindowArgs<float> &, const LeaveTiles &, hipStream_t);
+template hipError_t launch_window_leave_tiles<double>(const WindowArgs<double> &, const LeaveTiles &, hipStream_t);
 template hipError_t launch_window_fill<float>(const WindowArgs<float> &, hipStream_t);
 template hipError_t launch_window_fill<double>(const WindowArgs<double> &, hipStream_t);
 template hipError_t launch_window_column<float>(float *const[6], int32_t, int32_t, size_t, hipStream_t);

@@ -284,7 +284,20 @@ template <typename T> struct WindowArgs {
     unsigned long long *count_free;   // free slots (window_init)
     int32_t *free_slot;          // [n] by id: the slot a free id was last seen in (a hint, verified on use)
     unsigned long long *miss;    // injected particles whose hint was stale (window_fill)
+    int32_t *inj_list;           // or null: slot of injected particle r written to inj_list[r] (window_fill)
 };
+// The leaving column's particles found through the tile ranges of the last
+// full sort (2-D runs, particles in place since): tile columns tx0 ..
+// tx0 + ncols - 1 (mod ntile_x), every tile row, plus the slots listed in
+// list[0 .. list_n) (particles injected since that sort).  Each leaver is
+// freed once (compare-and-swap of its cell); count[0] += leavers.
+struct LeaveTiles {
+    const int32_t *start;        // [n_tiles + 1] slot ranges of the last full sort
+    int32_t tx0, ncols, ntile_x, ntile_z;
+    const int32_t *list;
+    int32_t list_n;
+};
+template <typename T> hipError_t launch_window_leave_tiles(const WindowArgs<T> &a, const LeaveTiles &lt, hipStream_t s);
 // freemap from the free slots (bits of their ids, the map zeroed first);
 // count[0] += ids out of range, count_free[0] += free slots.
 template <typename T> hipError_t launch_window_init(const WindowArgs<T> &a, hipStream_t s);

@@ -158,8 +158,9 @@ def test_open_x_option_rows_only():
 
 def test_moving_window_option():
     """AP_GRID_MOVING_WINDOW reserves the shift's workspace on grids (the free-id
-    bit map, its word popcounts and their scan: no copy of the fields) and is
-    rejected without a grid or together with AP_GRID_OPEN_X."""
+    bit map, its word popcounts and their scan, in 2-D the list of slots
+    injected since the last sort: no copy of the fields) and is rejected
+    without a grid or together with AP_GRID_OPEN_X."""
     g = _grid()
     base = apt.ap_query_layout(g, [_sp(2048)]).work_bytes
     g.options = apt.AP_GRID_MOVING_WINDOW

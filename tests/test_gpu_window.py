@@ -162,6 +162,40 @@ def test_moving_window_matches_oracle_fp64(dim, direction):
     assert origin == (direction * shift) % case["n"][0]
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("pattern", ["forward", "alternate"])
+def test_window_2d_leavers_by_tile_ranges_fp64(pattern):
+    """2-D run with 8 x 8 tiles (four tile columns) and a re-sort every 3
+    steps: between sorts each shift finds its leavers in the slot ranges of
+    the tile columns within reach since the sort, plus the particles injected
+    since.  "alternate" shifts +x then -x in turn, so each shift's injected
+    particles leave at the next one; those are found only through the list
+    of injected slots.  Matches the oracle as above."""
+    case = _setup(2)
+    print("moving window, tile ranges,", pattern, flush=True)
+    g = _oracle_grid(case)
+    sps = _oracle_species(case)
+    P = pulses.Pulse(case["pulse"])
+    sim = cases.sim_from_case(case, precision="f64", sort_every=3, moving_window=True, tile=(8, 1, 8))
+    try:
+        x_min = list(case["x_min"])
+        shift = 0
+        for k in range(N_STEPS):
+            if k % 2 == 1:
+                direction = 1 if (pattern == "forward" or shift % 2 == 0) else -1
+                x_min[0] += direction * case["dx"][0]
+                cols = _column(case, shift, x_min, direction)
+                sim.shift_window(cols, direction)
+                pic.shift_window(g, sps, [_col_for_oracle(case, c) for c in cols], direction)
+                shift += 1
+            sim.step(1)
+            pic.step(g, sps, P)
+        _compare(case, sim, g, sps, x_min[0])
+    finally:
+        sim.close()
+    assert shift == N_STEPS // 2
+
+
 def _ff_window_case(beta_f):
     dxl = 0.05
     n = (40, 1, 20)
