@@ -26,6 +26,8 @@ template <int TX, int TY, int TZ> struct Region3 {
     static constexpr int RX = TX + kLo3 + kHi3, RY = TY + kLo3 + kHi3, RZ = TZ + kLo3 + kHi3;
     static constexpr int RXY = RX * RY;
     static constexpr int RC = RXY * RZ;
+    // the gather's inner box (nodes 1 .. R - 2 per axis), where E2, B2 are staged
+    static constexpr int IX = RX - 2, IXY = IX * (RY - 2), IC = IXY * (RZ - 2);
 };
 
 
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);
     using JA = typename JTile<T>::type;
-    JA *sJ = reinterpret_cast<JA *>(smem_raw + align_lds(6 * RC * sizeof(T)));
+    JA *sJ = reinterpret_cast<JA *>(smem_raw + align_lds(6 * R::IC * sizeof(T)));
     __shared__ float s_red[4];
     __shared__ int s_stay[kMaxSpecies];   // fused re-sort: particles of each species staying in the tile
 
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     // axis): the gather of a particle in the tile reads one node below its
     // cell and two above, while the deposit's window (the J tile, the whole
     // region) reaches one further on each side
-    constexpr int IX = RX - 2, IXY = IX * (R::RY - 2), IC = IXY * (R::RZ - 2);
+    constexpr int IX = R::IX, IXY = R::IXY, IC = R::IC;
     constexpr int NIT = (IC + 255) / 256;   // launched with 256 threads
     auto inner_node = [&](int f) {
         const int fz = f / IXY;
@@ -253,9 +255,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
     for (int k = 0; k < NIT; ++k) {
         const int f = (int)threadIdx.x + 256 * k;
         if (f < IC) {
-            const int e = inner_node(f);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sF[c * RC + e] = sv[k][c];
+            for (int c = 0; c < 6; ++c) sF[c * IC + f] = sv[k][c];
         }
     }
     for (int e = (int)threadIdx.x; e < RC; e += 256) {
@@ -396,15 +397,16 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
             T e2[3], b2[3];
             if (in_lds) {
                 // stencil starts on the node (n) and half-node (h) lattice of each axis
-                const int xn = loc[0] + nod[0] - 1, xh = loc[0] - 1;
-                const int yn = (loc[1] + nod[1] - 1) * RX, yh = (loc[1] - 1) * RX;
-                const int zn = (loc[2] + nod[2] - 1) * RXY, zh = (loc[2] - 1) * RXY;
-                e2[0] = gather27<RX, RXY>(sF + 0 * RC, xh + yn + zn, wh[0], wn[1], wn[2]);
-                e2[1] = gather27<RX, RXY>(sF + 1 * RC, xn + yh + zn, wn[0], wh[1], wn[2]);
-                e2[2] = gather27<RX, RXY>(sF + 2 * RC, xn + yn + zh, wn[0], wn[1], wh[2]);
-                b2[0] = gather27<RX, RXY>(sF + 3 * RC, xn + yh + zh, wn[0], wh[1], wh[2]);
-                b2[1] = gather27<RX, RXY>(sF + 4 * RC, xh + yn + zh, wh[0], wn[1], wh[2]);
-                b2[2] = gather27<RX, RXY>(sF + 5 * RC, xh + yh + zn, wh[0], wh[1], wn[2]);
+                // stencil starts in the inner box (region node - 1 per axis)
+                const int xn = loc[0] + nod[0] - 2, xh = loc[0] - 2;
+                const int yn = (loc[1] + nod[1] - 2) * IX, yh = (loc[1] - 2) * IX;
+                const int zn = (loc[2] + nod[2] - 2) * IXY, zh = (loc[2] - 2) * IXY;
+                e2[0] = gather27<IX, IXY>(sF + 0 * IC, xh + yn + zn, wh[0], wn[1], wn[2]);
+                e2[1] = gather27<IX, IXY>(sF + 1 * IC, xn + yh + zn, wn[0], wh[1], wn[2]);
+                e2[2] = gather27<IX, IXY>(sF + 2 * IC, xn + yn + zh, wn[0], wn[1], wh[2]);
+                b2[0] = gather27<IX, IXY>(sF + 3 * IC, xn + yh + zh, wn[0], wh[1], wh[2]);
+                b2[1] = gather27<IX, IXY>(sF + 4 * IC, xh + yn + zh, wh[0], wn[1], wh[2]);
+                b2[2] = gather27<IX, IXY>(sF + 5 * IC, xh + yh + zn, wh[0], wh[1], wn[2]);
             } else {
                 auto gath = [&](int comp, int sx, int sy, int sz) {
                     const T *wx = sx ? wh[0] : wn[0];
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) void k_push_deposit_3d
 }
 
 template <int TX, int TY, int TZ> constexpr size_t lds3(size_t real) {
-    return align_lds(6 * (size_t)Region3<TX, TY, TZ>::RC * real) +
+    return align_lds(6 * (size_t)Region3<TX, TY, TZ>::IC * real) +
            3 * (size_t)Region3<TX, TY, TZ>::RC * sizeof(double);
 }
 
