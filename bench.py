@@ -590,15 +590,15 @@ PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h",
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "65579bb7e290bd7f5eb1e78039cfad83346b686aa10c0417af1e1d80b0082531",
-    # FETCH_SIZE 2.984e7 KiB x 1.99996 (a 2 GiB device copy reads as 1048606.8 KiB)
-    "fetch_bytes_per_launch": 6.111e10,
-    # WRITE_SIZE 7.632e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
-    "write_bytes_per_launch": 7.815e10,
-    "valu_lane_ops_per_push": 1503.9,
-    "ms_per_launch": 90.214,
-    "lds_busy_frac": 0.494,
-    "lds_bank_conflict_frac": 0.575,
+    "sources_sha256": "b0a0af5d0613de502aa393d66ce2ca3e4e1801bc997d4d3d6b1712a1307ef218",
+    # FETCH_SIZE 2.984e7 KiB x 1.99993 (a 2 GiB device copy reads as 1048613.5 KiB)
+    "fetch_bytes_per_launch": 6.112e10,
+    # WRITE_SIZE 7.653e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.837e10,
+    "valu_lane_ops_per_push": 1491.2,
+    "ms_per_launch": 89.797,
+    "lds_busy_frac": 0.505,
+    "lds_bank_conflict_frac": 0.578,
     "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
             "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
 }
