@@ -782,35 +782,47 @@ hipError_t launch_resort_counts(const int32_t *stay, const int32_t *mcount, int3
 // Particles changing tile take their ranks after the tile's stayers.  The
 // lanes of a wave (consecutive slots of one old tile) enter few distinct
 // tiles: one counter atomic per distinct tile, its lanes ranked in lane order.
+constexpr int kPermPpt = 8;   // particles per thread: independent load chains in flight
 __global__ __launch_bounds__(256) void k_resort_perm(PermArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = p < a.n;
-    int t = 0, k = 0;
-    if (live) {
-        const int cell = a.cell[p];
-        t = (unsigned)cell < a.ncell ? tile_of(cell, a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
-                                     : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
-        k = a.key[p];
+    const int p0 = blockIdx.x * blockDim.x * kPermPpt + threadIdx.x;
+    int t[kPermPpt], k[kPermPpt], cell[kPermPpt];
+#pragma unroll
+    for (int u = 0; u < kPermPpt; ++u) {
+        const int p = p0 + u * (int)blockDim.x;
+        cell[u] = p < a.n ? a.cell[p] : -1;
+        k[u] = p < a.n ? a.key[p] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPermPpt; ++u) {
+        const int p = p0 + u * (int)blockDim.x;
+        t[u] = (unsigned)cell[u] < a.ncell ? tile_of(cell[u], a.dim, a.fnx, a.fnxy, a.ftx, a.fty, a.ftz, a.ntile)
+                                           : dead_tile(p, a.ntile[0] * a.ntile[1] * a.ntile[2]);
     }
     const int lane = (int)(threadIdx.x & 63);
-    unsigned long long todo = __ballot(live && k < 0);
-    int slot = k;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int tl = __shfl(t, leader, 64);
-        const unsigned long long m = __ballot(live && k < 0 && t == tl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&a.mrank[tl], (int)__popcll(m));
-        base = __shfl(base, leader, 64);
-        if ((m >> lane) & 1ull) slot = a.stay[tl] + base + (int)__popcll(m & ((1ull << lane) - 1ull));
-        todo &= ~m;
+#pragma unroll
+    for (int u = 0; u < kPermPpt; ++u) {
+        const int p = p0 + u * (int)blockDim.x;
+        const bool live = p < a.n;
+        unsigned long long todo = __ballot(live && k[u] < 0);
+        int slot = k[u];
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const int tl = __shfl(t[u], leader, 64);
+            const unsigned long long m = __ballot(live && k[u] < 0 && t[u] == tl);
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&a.mrank[tl], (int)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if ((m >> lane) & 1ull) slot = a.stay[tl] + base + (int)__popcll(m & ((1ull << lane) - 1ull));
+            todo &= ~m;
+        }
+        if (live) a.perm[a.start[t[u]] + slot] = p;
     }
-    if (live) a.perm[a.start[t] + slot] = p;
 }
 
 hipError_t launch_resort_perm(const PermArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resort_perm, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    const int per = 256 * kPermPpt;
+    hipLaunchKernelGGL(k_resort_perm, dim3((a.n + per - 1) / per), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
