@@ -36,7 +36,7 @@ Other legs (``--legs``):
 Optional leg: adjoint3d_long, the 3-D run's frozen-grid adjoint over a
 1000-step window under binomial checkpointing (16 whole states).
 
-Prints one JSON line.  ``--gpus`` above 1 is refused (single-GPU build).
+Prints one JSON line.  ``--gpus`` above 1 is refused (one GPU only).
 """
 import argparse
 import json
@@ -896,7 +896,7 @@ def main():
                          "scaling HBM counters in profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: one GPU only (the library has no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x]
     for x in legs:
