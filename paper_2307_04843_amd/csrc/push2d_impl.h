@@ -79,24 +79,32 @@ AP_D void deposit_window(JA *sJ, int RC, int RX, int x0, int z0, const T S0x[4],
 
 // CTX, CTZ: the tile shape at compile time (LDS offsets become immediates),
 // or 0, 0: the run's tile shape at run time.
+// Blocks per CU the registers are budgeted for: five in FP32 runs (LDS holds
+// five 32 x 8 tile blocks), three in FP64 runs (two with the eps^4 pulse,
+// which would spill at three).
 template <typename T, int PT, bool INPLACE, bool PROXY, int CTX, int CTZ>
-__global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : (PT == PT_NP ? 2 : 3)) void k_push_deposit_2d(PushArgs<T> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int TXv = CTX ? CTX : a.tile[0], TZv = CTZ ? CTZ : a.tile[2];
     const int RX = CTX ? CTX + kHaloLo + kHaloHi : a.reg[0];
     const int RZ = CTZ ? CTZ + kHaloLo + kHaloHi : a.reg[2];
     const int RC = RX * RZ;
-    // Staged fields: components that share a stencil window are stored as
-    // pairs, (Ex, Bz) on (half, node) and (Ez, Bx) on (node, half), so one
-    // LDS read serves both; Ey (node, node) and By (half, half) alone.
+    // Staged fields, on the region's inner box (nodes 1 .. R - 2 per axis:
+    // the gather of a particle within the drift margin reads one node below
+    // its cell and two above; the J tile keeps the whole region): 30.8 KB
+    // per 32 x 8 tile block in FP32 runs, so five blocks share a CU.
+    // Components that share a stencil window are stored as pairs, (Ex, Bz) on
+    // (half, node) and (Ez, Bx) on (node, half), so one LDS read serves both;
+    // Ey (node, node) and By (half, half) alone.
+    const int IX = RX - 2, IC = IX * (RZ - 2);
     using T2 = typename Vec2<T>::type;
-    T2 *sP = reinterpret_cast<T2 *>(smem_raw);               // [2][RC] pairs
-    T *sS = reinterpret_cast<T *>(sP + 2 * RC);              // [2][RC] Ey, By
+    T2 *sP = reinterpret_cast<T2 *>(smem_raw);               // [2][IC] pairs
+    T *sS = reinterpret_cast<T *>(sP + 2 * IC);              // [2][IC] Ey, By
     // The current tile: FP64 in FP64 runs, int64 fixed point in FP32 runs
     // (JTile; ds_add_f64 measured several times faster than ds_add_f32 here,
     // ds_add_u64 faster again).
     using A = typename JTile<T>::type;
-    A *sJ = reinterpret_cast<A *>(smem_raw + align_lds(6 * RC * sizeof(T)));   // Jx Jy Jz
+    A *sJ = reinterpret_cast<A *>(smem_raw + align_lds(6 * IC * sizeof(T)));   // Jx Jy Jz
     __shared__ float s_red[4];
 
     // XCD-aware mapping: consecutive hardware block ids go round-robin to
@@ -114,19 +122,21 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
     const int X0 = tx * TXv, Z0 = tz * TZv;
     const int ox = X0 - kHaloLo, oz = Z0 - kHaloLo;
 
-    for (int e = threadIdx.x; e < RC; e += blockDim.x) {
-        const int lz = e / RX;
-        const int lx = e - lz * RX;
-        const int gx = ((ox + lx) % nx + nx) % nx;
-        const int gz = ((oz + lz) % nz + nz) % nz;
+    for (int f = threadIdx.x; f < IC; f += blockDim.x) {
+        const int lz = f / IX;
+        const int lx = f - lz * IX;
+        const int gx = ((ox + lx + 1) % nx + nx) % nx;
+        const int gz = ((oz + lz + 1) % nz + nz) % nz;
         const size_t g = (size_t)gz * nx + gx;
         T2 p0, p1;
         p0.x = a.E[0][g]; p0.y = a.B[2][g];
         p1.x = a.E[2][g]; p1.y = a.B[0][g];
-        sP[e] = p0;
-        sP[RC + e] = p1;
-        sS[e] = a.E[1][g];
-        sS[RC + e] = a.B[1][g];
+        sP[f] = p0;
+        sP[IC + f] = p1;
+        sS[f] = a.E[1][g];
+        sS[IC + f] = a.B[1][g];
+    }
+    for (int e = threadIdx.x; e < RC; e += blockDim.x) {
         sJ[0 * RC + e] = A(0);
         sJ[1 * RC + e] = A(0);
         sJ[2 * RC + e] = A(0);
@@ -234,12 +244,13 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
             tsc3(offz - T(0.5), wzh);
             T e2[3], b2[3];
             if (in_lds) {
-                const int xn = la + nxn - 1, xh = la - 1, zn = lb + nzn - 1, zh = lb - 1;
+                // stencil starts in the inner box (region node - 1 per axis)
+                const int xn = la + nxn - 2, xh = la - 2, zn = lb + nzn - 2, zh = lb - 2;
                 auto G = [&](const T *F, int bx, const T *wx, int bz, const T *wz) {
                     T acc = T(0);
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
-                        const T *row = F + (bz + b) * RX + bx;
+                        const T *row = F + (bz + b) * IX + bx;
                         acc += wz[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2]);
                     }
                     return acc;
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     T a0 = T(0), a1 = T(0);
 #pragma unroll
                     for (int b = 0; b < 3; ++b) {
-                        const T2 *row = F + (bz + b) * RX + bx;
+                        const T2 *row = F + (bz + b) * IX + bx;
                         const T2 r0 = row[0], r1 = row[1], r2 = row[2];
                         a0 += wz[b] * (wx[0] * r0.x + wx[1] * r1.x + wx[2] * r2.x);
                         a1 += wz[b] * (wx[0] * r0.y + wx[1] * r1.y + wx[2] * r2.y);
@@ -257,9 +268,9 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
                     o1 = a1;
                 };
                 G2(sP, xh, wxh, zn, wzn, e2[0], b2[2]);
-                G2(sP + RC, xn, wxn, zh, wzh, e2[2], b2[0]);
+                G2(sP + IC, xn, wxn, zh, wzh, e2[2], b2[0]);
                 e2[1] = G(sS, xn, wxn, zn, wzn);
-                b2[1] = G(sS + RC, xh, wxh, zh, wzh);
+                b2[1] = G(sS + IC, xh, wxh, zh, wzh);
             } else {
                 int gxn[3], gxh[3];
                 size_t gzn[3], gzh[3];
@@ -421,7 +432,8 @@ __global__ __launch_bounds__(256) void k_push_deposit_2d(PushArgs<T> a) {
 template <typename T, int PT, int CTX, int CTZ>
 hipError_t launch2d(const PushArgs<T> &a, int threads, hipStream_t s) {
     const size_t rc = (size_t)a.reg[0] * a.reg[2];
-    const size_t lds = align_lds(6 * rc * sizeof(T)) + 3 * rc * sizeof(double);
+    const size_t ic = (size_t)(a.reg[0] - 2) * (a.reg[2] - 2);
+    const size_t lds = align_lds(6 * ic * sizeof(T)) + 3 * rc * sizeof(double);
     const int blocks = ((a.n_logical + 7) / 8) * 8;
     if (blocks == 0) return hipSuccess;
     bool proxy = false;
