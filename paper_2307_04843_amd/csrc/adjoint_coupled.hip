@@ -22,7 +22,8 @@ template <typename T, int PT, int GD> static void launch_cpl_gd(const AdjointArg
         // 2-D and 3-D: the current's adjoint (LDS copy of the grid adjoint it
         // reads), the rest, then the gather's adjoint (LDS accumulation)
         const size_t shj = (size_t)adj_lds_j<GD>() * sizeof(double);
-        const size_t shs = (size_t)adj_lds_scatter<GD>() * sizeof(double);
+        const int cap = a.scatter_cap > 0 ? a.scatter_cap : adj_lds_scatter<GD>();
+        const size_t shs = (size_t)cap * sizeof(double);
         hipLaunchKernelGGL((k_adjoint_current<PT, GD, T>), grid, block, shj, s, a);
         if constexpr (GD == 3) {
             if (np <= 2) {
@@ -39,7 +40,8 @@ template <typename T, int PT, int GD> static void launch_cpl_gd(const AdjointArg
             if (px) hipLaunchKernelGGL((k_adjoint_step_rest<PT, 7, GD, true>), grid, block, 0, s, a);
             else hipLaunchKernelGGL((k_adjoint_step_rest<PT, 7, GD, false>), grid, block, 0, s, a);
         }
-        hipLaunchKernelGGL((k_adjoint_gather_scatter<T, GD>), dim3((a.n + 255) / 256), block, shs, s, a);
+        const dim3 grid3(a.tile_start ? (unsigned)a.ntile : (unsigned)((a.n + 255) / 256));
+        hipLaunchKernelGGL((k_adjoint_gather_scatter<GD>), grid3, block, shs, s, a);
     }
 }
 
@@ -66,6 +68,8 @@ template <typename T> hipError_t launch_adjoint_step_coupled(int pulse, const Ad
     default: return hipErrorInvalidValue;
     }
 }
+int adjoint_scatter_lds_entries(int dim) { return dim == 3 ? adj_lds_scatter<3>() : adj_lds_scatter<2>(); }
+
 template hipError_t launch_adjoint_step_coupled<float>(int, const AdjointArgs<float> &, hipStream_t);
 template hipError_t launch_adjoint_step_coupled<double>(int, const AdjointArgs<double> &, hipStream_t);
 

@@ -849,138 +849,228 @@ AP_D __forceinline__ void adjoint_step_body(const AdjointArgs<T> &a) {
 
 // The gather's adjoint of the coupled reverse step (after PASS 2): each
 // particle's adjoints of its gathered E, B (a.gx0, [6][n]) spread to the
-// grid adjoints lEg, lBg with the gather's weights, accumulated in LDS over
-// the bounding box of the block's cells and flushed once per node (global
-// FP64 atomics when the box does not fit).
-template <typename T, int GD> __global__ __launch_bounds__(256) void k_adjoint_gather_scatter(AdjointArgs<T> a) {
+// grid adjoints lEg, lBg with the gather's weights, accumulated in an LDS
+// box and flushed once per node.  With a.tile_start a block takes the slots
+// of one tile and its box is the tile's, widened by a.tile_margin cells (a
+// tile-sorted state that has moved by up to that many cells since its sort
+// stays inside); a particle whose stencil leaves the box adds its terms
+// with global FP64 atomics.  Without it a block takes 256 consecutive slots
+// and the box is their cells' bounding box (global atomics for the whole
+// block when that box does not fit).  A block works through its slots in
+// runs of at most kScatterRun, each with its own scale and flush.  The
+// sums do not depend on the order of the state.
+constexpr int kScatterRun = 4096;
+template <typename T, int GD> AP_D __forceinline__ void adjoint_gather_scatter_body(const AdjointArgs<T> &a) {
     // FP32 runs accumulate in int64 fixed point (JTile) with a power-of-two
-    // scale from the block's largest |value|: every term lies below 2^50
-    // units and a node takes at most one term per particle of the block, so
-    // its sum stays below 2^58.  Integer LDS atomics run faster than FP64
-    // ones, and the sums do not depend on the order of the atomics
+    // scale from the run's largest |value|: every term lies below 2^B units,
+    // B = min(50, 58 - ceil(log2(run length))), and a node takes at most one
+    // term per particle of the run, so its sum stays below 2^58.  Integer LDS
+    // atomics run faster than FP64 ones, and the sums do not depend on the
+    // order of the atomics
     using JA = typename JTile<T>::type;
     extern __shared__ double adj_dyn_raw[];
     JA *adj_dyn = reinterpret_cast<JA *>(adj_dyn_raw);
     __shared__ int bbox[6];
     __shared__ double s_max[4];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = a.G.n[0], ny = a.G.n[1], nxy = a.G.n[0] * a.G.n[1];
-    int ic[3] = {0, 0, 0};
-    T ov[3] = {T(0), T(0), T(0)};
-    bool ok = p < a.n;
-    if (ok) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool by_tile = a.tile_start != nullptr;
+    const int cap = a.scatter_cap > 0 ? a.scatter_cap : adj_lds_scatter<GD>();
+    int r0, r1;
+    AdjRegion R{};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) R.n[ax] = a.G.n[ax];
+    if (by_tile) {
+        r0 = a.tile_start[blockIdx.x];
+        r1 = a.tile_start[blockIdx.x + 1];
+        const int t[3] = {(int)blockIdx.x % a.tile_n[0], ((int)blockIdx.x / a.tile_n[0]) % a.tile_n[1],
+                          (int)blockIdx.x / (a.tile_n[0] * a.tile_n[1])};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const int ext = a.tile_dim[ax] + 3 + 2 * a.tile_margin;
+            if ((GD == 2 && ax == 1) || ext >= R.n[ax]) {
+                R.lo[ax] = 0;   // the whole axis
+                R.ext[ax] = R.n[ax];
+            } else {
+                R.lo[ax] = wrap_idx(t[ax] * a.tile_dim[ax] - 1 - a.tile_margin, R.n[ax]);
+                R.ext[ax] = ext;
+            }
+        }
+    } else {
+        r0 = blockIdx.x * 256;
+        r1 = min(r0 + 256, a.n);
+    }
+    r0 = max(r0, 0);
+    r1 = min(r1, a.n);
+    // slot p: its cell (ic) and offsets (ov), false for a particle outside
+    // the grid or with an id out of range (it adds nothing)
+    auto load = [&](int p, int ic[3], T ov[3]) -> bool {
         const int cell = a.G.cell[p];
         ov[0] = a.off[0][p];
-        if (GD >= 2) ov[2] = a.off[2][p];
-        if (GD == 3) ov[1] = a.off[1][p];
-        ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
-             ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) && (unsigned)a.G.id[p] < (unsigned)a.n;
+        ov[1] = GD == 3 ? a.off[1][p] : T(0);
+        ov[2] = a.off[2][p];
+        const bool ok = (unsigned)cell < (unsigned)nxy * (unsigned)a.G.n[2] && ov[0] >= T(0) && ov[0] < T(1) &&
+                        ov[1] >= T(0) && ov[1] < T(1) && ov[2] >= T(0) && ov[2] < T(1) &&
+                        (unsigned)a.G.id[p] < (unsigned)a.n;
         const int k = (int)a.G.fnxy.div((unsigned)cell);
         const int r = cell - k * nxy;
         const int j = (int)a.G.fnx.div((unsigned)r);
         ic[0] = r - j * nx;
         ic[1] = j;
         ic[2] = k;
-    }
-    if (threadIdx.x < 3) {
-        bbox[threadIdx.x] = 0x7fffffff;
-        bbox[3 + threadIdx.x] = -0x7fffffff;
-    }
-    __syncthreads();
-    if (ok) {
+        return ok;
+    };
+    // the stencil of a particle in cell ic covers nodes ic - 1 .. ic + 2 per axis
+    auto in_box = [&](const int ic[3]) -> bool {
+        bool in = true;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            atomicMin(&bbox[ax], ic[ax]);
-            atomicMax(&bbox[3 + ax], ic[ax]);
+            if (R.ext[ax] == R.n[ax]) continue;
+            int d = ic[ax] - (R.lo[ax] + 1);
+            if (d < 0) d += R.n[ax];
+            else if (d >= R.n[ax]) d -= R.n[ax];
+            in = in && d <= R.ext[ax] - 4;
         }
-    }
-    __syncthreads();
-    AdjRegion R{};
-    bool fits = true;
-    int vol = 6;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        R.n[ax] = a.G.n[ax];
-        if (GD == 2 && ax == 1) {
-            R.lo[1] = 0;
-            R.ext[1] = 1;
-            continue;
+        return in;
+    };
+    for (int c0 = r0; c0 < r1; c0 += kScatterRun) {
+        const int c1 = min(c0 + kScatterRun, r1);
+        if (threadIdx.x < 3) {
+            bbox[threadIdx.x] = 0x7fffffff;
+            bbox[3 + threadIdx.x] = -0x7fffffff;
         }
-        R.lo[ax] = bbox[ax] - 1;
-        R.ext[ax] = bbox[3 + ax] - bbox[ax] + 4;
-        fits = fits && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
-        vol *= R.ext[ax];
-    }
-    const bool use_lds = fits && vol <= adj_lds_scatter<GD>();
-    if (use_lds)
-        for (int i = threadIdx.x; i < vol; i += blockDim.x) adj_dyn[i] = JA(0);
-    double lE[3] = {0.0, 0.0, 0.0}, lB[3] = {0.0, 0.0, 0.0};
-    if (ok) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            lE[c] = a.gx0[(size_t)c * a.n + p];
-            lB[c] = a.gx0[(size_t)(3 + c) * a.n + p];
-        }
-    }
-    double scale = 1.0, inv_scale = 1.0;
-    if constexpr (std::is_same<T, float>::value) {
+        // the run's box of cells (256-slot blocks) and (FP32) its largest |value|
+        int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
         double m = 0.0;
+        if (!by_tile || std::is_same<T, float>::value) {
+            for (int p = c0 + (int)threadIdx.x; p < c1; p += blockDim.x) {
+                int ic[3];
+                T ov[3];
+                if (!load(p, ic, ov)) continue;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m = fmax(m, fmax(fabs(lE[c]), fabs(lB[c])));
-        if (!__builtin_isfinite(m)) m = 0.0;   // a non-finite value goes to the global path below
+                for (int ax = 0; ax < 3; ++ax) {
+                    mn[ax] = min(mn[ax], ic[ax]);
+                    mx[ax] = max(mx[ax], ic[ax]);
+                }
+                if constexpr (std::is_same<T, float>::value) {
+                    double mp = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) mp = fmax(mp, fabs(a.gx0[(size_t)c * a.n + p]));
+                    if (__builtin_isfinite(mp)) m = fmax(m, mp);   // a non-finite value goes to the global path
+                }
+            }
+        }
         for (int d = 32; d > 0; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
-        if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+        if (lane == 0) s_max[wid] = m;
+        if (!by_tile) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                for (int d = 32; d > 0; d >>= 1) {
+                    mn[ax] = min(mn[ax], __shfl_xor(mn[ax], d, 64));
+                    mx[ax] = max(mx[ax], __shfl_xor(mx[ax], d, 64));
+                }
+        }
         __syncthreads();
-        m = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
-        if (m > 0.0) {
-            int e;
-            frexp(m, &e);   // every term (a value times stencil weights <= 1) lies below 2^e
-            e = e < -960 ? -960 : e;   // keeps the scale finite; smaller terms round to zero
-            scale = ldexp(1.0, 50 - e);
-            inv_scale = ldexp(1.0, e - 50);
-        }
-    }
-    __syncthreads();
-    if (ok) {
-        AxisStencil<T> sn[3], sh[3];
-        grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
-        bool fin = true;
+        if (!by_tile && lane == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fin = fin && __builtin_isfinite(lE[c]) && __builtin_isfinite(lB[c]);
-        if (use_lds && fin) {
-            scatter_adjoint_lds<T, GD>(adj_dyn, 0, R, sh[0], sn[1], sn[2], lE[0], scale);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 1, R, sn[0], sh[1], sn[2], lE[1], scale);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 2, R, sn[0], sn[1], sh[2], lE[2], scale);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 3, R, sn[0], sh[1], sh[2], lB[0], scale);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 4, R, sh[0], sn[1], sh[2], lB[1], scale);
-            scatter_adjoint_lds<T, GD>(adj_dyn, 5, R, sh[0], sh[1], sn[2], lB[2], scale);
-        } else {
-            scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
-            scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
-            scatter_adjoint<T, GD>(a.lEg[2], sn[0], sn[1], sh[2], nx, ny, lE[2]);
-            scatter_adjoint<T, GD>(a.lBg[0], sn[0], sh[1], sh[2], nx, ny, lB[0]);
-            scatter_adjoint<T, GD>(a.lBg[1], sh[0], sn[1], sh[2], nx, ny, lB[1]);
-            scatter_adjoint<T, GD>(a.lBg[2], sh[0], sh[1], sn[2], nx, ny, lB[2]);
+            for (int ax = 0; ax < 3; ++ax) {
+                atomicMin(&bbox[ax], mn[ax]);
+                atomicMax(&bbox[3 + ax], mx[ax]);
+            }
         }
-    }
-    if (!use_lds) return;
-    __syncthreads();
-    const int per = R.ext[0] * R.ext[1] * R.ext[2];
-    for (int i = threadIdx.x; i < vol; i += blockDim.x) {
-        const JA raw = adj_dyn[i];
-        if (raw == JA(0)) continue;
-        const double v = lds_value(raw, inv_scale);
-        const int comp = i / per;
-        int r = i - comp * per;
-        const int l2 = r / (R.ext[0] * R.ext[1]);
-        r -= l2 * R.ext[0] * R.ext[1];
-        const int l1 = r / R.ext[0], l0 = r - l1 * R.ext[0];
-        int g[3] = {R.lo[0] + l0, R.lo[1] + l1, R.lo[2] + l2};
+        __syncthreads();
+        bool use_lds = true;
+        if (!by_tile) {
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) g[ax] = wrap_idx(g[ax], R.n[ax]);
-        const size_t node = ((size_t)g[2] * R.n[1] + g[1]) * R.n[0] + g[0];
-        atomicAdd(comp < 3 ? a.lEg[comp] + node : a.lBg[comp - 3] + node, v);
+            for (int ax = 0; ax < 3; ++ax) {
+                if (GD == 2 && ax == 1) {
+                    R.lo[1] = 0;
+                    R.ext[1] = 1;
+                    continue;
+                }
+                R.lo[ax] = bbox[ax] - 1;
+                R.ext[ax] = bbox[3 + ax] - bbox[ax] + 4;
+                use_lds = use_lds && bbox[ax] <= bbox[3 + ax] && R.ext[ax] <= R.n[ax];
+            }
+        }
+        const int per = R.ext[0] * R.ext[1] * R.ext[2], vol = 6 * per;
+        use_lds = use_lds && vol <= cap;
+        if (use_lds)
+            for (int i = threadIdx.x; i < vol; i += blockDim.x) adj_dyn[i] = JA(0);
+        double scale = 1.0, inv_scale = 1.0;
+        if constexpr (std::is_same<T, float>::value) {
+            m = fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
+            if (m > 0.0) {
+                int e, lb = 0;
+                frexp(m, &e);   // every term (a value times stencil weights <= 1) lies below 2^e
+                e = e < -960 ? -960 : e;   // keeps the scale finite; smaller terms round to zero
+                while ((1 << lb) < c1 - c0) ++lb;
+                const int bits = min(50, 58 - lb);
+                scale = ldexp(1.0, bits - e);
+                inv_scale = ldexp(1.0, e - bits);
+            }
+        }
+        __syncthreads();
+        for (int p = c0 + (int)threadIdx.x; p < c1; p += blockDim.x) {
+            int ic[3];
+            T ov[3];
+            if (!load(p, ic, ov)) continue;
+            double lE[3], lB[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lE[c] = a.gx0[(size_t)c * a.n + p];
+                lB[c] = a.gx0[(size_t)(3 + c) * a.n + p];
+            }
+            AxisStencil<T> sn[3], sh[3];
+            grid_stencils<T, GD>(ic, ov, a.G.n, sn, sh);
+            bool fin = true;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fin = fin && __builtin_isfinite(lE[c]) && __builtin_isfinite(lB[c]);
+            if (use_lds && fin && (!by_tile || in_box(ic))) {
+                scatter_adjoint_lds<T, GD>(adj_dyn, 0, R, sh[0], sn[1], sn[2], lE[0], scale);
+                scatter_adjoint_lds<T, GD>(adj_dyn, 1, R, sn[0], sh[1], sn[2], lE[1], scale);
+                scatter_adjoint_lds<T, GD>(adj_dyn, 2, R, sn[0], sn[1], sh[2], lE[2], scale);
+                scatter_adjoint_lds<T, GD>(adj_dyn, 3, R, sn[0], sh[1], sh[2], lB[0], scale);
+                scatter_adjoint_lds<T, GD>(adj_dyn, 4, R, sh[0], sn[1], sh[2], lB[1], scale);
+                scatter_adjoint_lds<T, GD>(adj_dyn, 5, R, sh[0], sh[1], sn[2], lB[2], scale);
+            } else {
+                scatter_adjoint<T, GD>(a.lEg[0], sh[0], sn[1], sn[2], nx, ny, lE[0]);
+                scatter_adjoint<T, GD>(a.lEg[1], sn[0], sh[1], sn[2], nx, ny, lE[1]);
+                scatter_adjoint<T, GD>(a.lEg[2], sn[0], sn[1], sh[2], nx, ny, lE[2]);
+                scatter_adjoint<T, GD>(a.lBg[0], sn[0], sh[1], sh[2], nx, ny, lB[0]);
+                scatter_adjoint<T, GD>(a.lBg[1], sh[0], sn[1], sh[2], nx, ny, lB[1]);
+                scatter_adjoint<T, GD>(a.lBg[2], sh[0], sh[1], sn[2], nx, ny, lB[2]);
+            }
+        }
+        if (!use_lds) continue;   // uniform over the block
+        __syncthreads();
+        for (int i = threadIdx.x; i < vol; i += blockDim.x) {
+            const JA raw = adj_dyn[i];
+            if (raw == JA(0)) continue;
+            const double v = lds_value(raw, inv_scale);
+            const int comp = i / per;
+            int r = i - comp * per;
+            const int l2 = r / (R.ext[0] * R.ext[1]);
+            r -= l2 * R.ext[0] * R.ext[1];
+            const int l1 = r / R.ext[0], l0 = r - l1 * R.ext[0];
+            int g[3] = {R.lo[0] + l0, R.lo[1] + l1, R.lo[2] + l2};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) g[ax] = wrap_idx(g[ax], R.n[ax]);
+            const size_t node = ((size_t)g[2] * R.n[1] + g[1]) * R.n[0] + g[0];
+            atomicAdd(comp < 3 ? a.lEg[comp] + node : a.lBg[comp - 3] + node, v);
+        }
+        __syncthreads();   // the next run reuses bbox, s_max and the LDS box
     }
+}
+// FP32 (int64 LDS sums): three waves per SIMD, with a few spills, measured
+// faster than two; FP64 at three would spill some 45 registers.
+template <int GD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_adjoint_gather_scatter(
+    AdjointArgs<float> a) {
+    adjoint_gather_scatter_body<float, GD>(a);
+}
+template <int GD> __global__ __launch_bounds__(256) void k_adjoint_gather_scatter(AdjointArgs<double> a) {
+    adjoint_gather_scatter_body<double, GD>(a);
 }
 
 // FP32: two waves per SIMD (the compiler keeps the dual-number working set

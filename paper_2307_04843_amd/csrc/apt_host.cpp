@@ -1865,6 +1865,19 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
     }
     yb.dt = s.dt;
     const FastDiv fnx((uint32_t)s.n[0]), fnxy((uint32_t)(s.n[0] * s.n[1]));
+    // Each reverse step tile-sorts its state into the sort's workspace copy
+    // (free here: every replay starts with a full sort) when a tile's box
+    // (the tile plus the stencil margin, or the whole axis where that would
+    // cover it) fits the LDS of the gather's adjoint and the tiles hold 2048
+    // particles or fewer on average.  The three passes then take the sorted
+    // copy, and the gather's adjoint runs one block per tile with its LDS
+    // sized to that box.
+    bool tile_ranges = s.dim >= 2;
+    int64_t tile_box = 6;
+    for (int ax = 0; ax < 3; ++ax)
+        if (axis_active(s.dim, ax)) tile_box *= std::min<int64_t>(s.tile[ax] + 3, s.n[ax]);
+    tile_ranges = tile_ranges && tile_box <= adjoint_scatter_lds_entries(s.dim);
+    for (int i = 0; i < s.nsp; ++i) tile_ranges = tile_ranges && s.np[i] <= 2048 * s.ntiles;
     // reverse step j (relative) from E2, B2 at F and every species' block
     auto leaf = [&](int64_t j, const T *F, const SpBlock<T> *blk) -> ap_status {
         HIPCHK(launch_yee_adjoint(s.dim, lE, lB, lJt, yb, c->stream), "backward yee");
@@ -1872,10 +1885,77 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
             if (s.np[i] == 0) continue;
             const SpBlock<T> &b = blk[i];
             AdjointArgs<T> a{};
+            // the state, tile-sorted into the sort's workspace copy when the
+            // tile ranges are in use (the adjoint state is indexed by particle
+            // id, so the passes may take the particles in any order)
+            SpBlock<T> sb = b;
+            if (tile_ranges && b.cell != c->wp<int32_t>(c->L.alt_cell[i])) {
+                int32_t *count = c->wp<int32_t>(c->L.count[i]);
+                int32_t *start = c->wp<int32_t>(c->L.start[i]);
+                int32_t *rank = c->wp<int32_t>(c->L.rank[i]);
+                HIPCHK(launch_fill_zero<int32_t>(count, (size_t)s.ntiles, c->stream), "backward");
+                SortArgs sa{};
+                sa.cell = b.cell;
+                sa.ncell = (uint32_t)s.ncell;
+                sa.n = (int)s.np[i];
+                sa.dim = s.dim;
+                sa.fnx = fnx;
+                sa.fnxy = fnxy;
+                sa.ftx = FastDiv((uint32_t)s.tile[0]);
+                sa.fty = FastDiv((uint32_t)s.tile[1]);
+                sa.ftz = FastDiv((uint32_t)s.tile[2]);
+                for (int k = 0; k < 3; ++k) sa.ntile[k] = s.ntile[k];
+                sa.count = count;
+                sa.rank = rank;
+                HIPCHK(launch_tile_count(sa, c->stream), "backward tile count");
+                HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(c->L.scan_part), c->stream),
+                       "backward tile scan");
+                sb.cell = c->wp<int32_t>(c->L.alt_cell[i]);
+                sb.id = c->wp<int32_t>(c->L.alt_id[i]);
+                sb.w = c->wp<T>(c->L.alt_w[i]);
+                sb.proxy = nullptr;
+                ScatterArgs<T> sc{};
+                sc.cell_src = b.cell;
+                sc.cell_dst = sb.cell;
+                for (int k = 0; k < 3; ++k) {
+                    const bool act = axis_active(s.dim, k);
+                    sb.off[k] = act ? c->wp<T>(c->L.alt_off[i][k]) : nullptr;
+                    sb.u[k] = c->wp<T>(c->L.alt_u[i][k]);
+                    sc.off_src[k] = act ? b.off[k] : nullptr;
+                    sc.off_dst[k] = sb.off[k];
+                    sc.u_src[k] = b.u[k];
+                    sc.u_dst[k] = sb.u[k];
+                }
+                sc.w_src = b.w;
+                sc.w_dst = sb.w;
+                sc.id_src = b.id;
+                sc.id_dst = sb.id;
+                sc.rank = rank;
+                sc.start = start;
+                sc.ncell = (uint32_t)s.ncell;
+                sc.interleave = 1;
+                sc.n = (int)s.np[i];
+                sc.dim = s.dim;
+                sc.fnx = fnx;
+                sc.fnxy = fnxy;
+                sc.ftx = sa.ftx;
+                sc.fty = sa.fty;
+                sc.ftz = sa.ftz;
+                for (int k = 0; k < 3; ++k) sc.ntile[k] = s.ntile[k];
+                HIPCHK(launch_scatter<T>(sc, c->stream), "backward tile scatter");
+                a.tile_start = start;
+                a.ntile = (int32_t)s.ntiles;
+                for (int k = 0; k < 3; ++k) {
+                    a.tile_dim[k] = s.tile[k];
+                    a.tile_n[k] = s.ntile[k];
+                }
+                a.tile_margin = 0;
+                a.scatter_cap = (int32_t)tile_box;
+            }
             a.xo = s.xo;
             for (int k = 0; k < 3; ++k) {
-                a.off[k] = b.off[k];
-                a.u[k] = b.u[k];
+                a.off[k] = sb.off[k];
+                a.u[k] = sb.u[k];
                 a.dx[k] = s.dx[k];
                 a.x_min[k] = s.x_min[k];
                 a.G.n[k] = s.n[k];
@@ -1887,12 +1967,12 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
                 a.lam[k] = lam[i][k];
                 a.G.F[k] = F + (size_t)k * nc;
             }
-            a.G.cell = b.cell;
-            a.G.id = b.id;
+            a.G.cell = sb.cell;
+            a.G.id = sb.id;
             a.G.fnx = fnx;
             a.G.fnxy = fnxy;
             a.G.q_slice = c->P.q_slice;
-            a.w = b.w;
+            a.w = sb.w;
             a.q = s.q[i];
             a.dim = s.dim;
             a.gx0 = reinterpret_cast<double *>(c->ckpt + G.gx0);

@@ -160,9 +160,18 @@ template <typename T> struct AdjointArgs {
     const double *lJ[3];         // E adjoint after the first half of the reverse Yee step (E nodes)
     double *lEg[3], *lBg[3];     // grid adjoints of E2^n, B2^n: the gather's adjoint is added here
     double *gx0;                 // coupled 2-D/3-D: [6][n] per-particle values between the reverse passes
+    // coupled 2-D/3-D, or null: [ntile + 1] slot ranges of the tiles; the
+    // gather's adjoint then runs one block per tile, over the tile's box
+    // widened by tile_margin cells (whole axes where that box would cover
+    // the axis)
+    const int32_t *tile_start;
+    int32_t ntile, tile_dim[3], tile_n[3], tile_margin;
+    int32_t scatter_cap;         // LDS entries of the gather's adjoint box (0: the default budget)
 };
 template <typename T> hipError_t launch_adjoint_step(int pulse, const AdjointArgs<T> &a, hipStream_t s);
 template <typename T> hipError_t launch_adjoint_step_coupled(int pulse, const AdjointArgs<T> &a, hipStream_t s);
+// LDS entries (doubles) of the coupled gather's adjoint box in dim-D runs
+int adjoint_scatter_lds_entries(int dim);
 
 // Checks that id[0..n) is a permutation of 0..n-1: seen[] (n ints, zeroed by
 // the caller) counts each id; *bad counts ids out of range or repeated.
