@@ -590,14 +590,14 @@ PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h",
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "b0a0af5d0613de502aa393d66ce2ca3e4e1801bc997d4d3d6b1712a1307ef218",
-    # FETCH_SIZE 2.984e7 KiB x 1.99993 (a 2 GiB device copy reads as 1048613.5 KiB)
-    "fetch_bytes_per_launch": 6.112e10,
-    # WRITE_SIZE 7.653e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
-    "write_bytes_per_launch": 7.837e10,
+    "sources_sha256": "1966b3ead5b7618731a292803a82e8611b68b3cf17c0e746bdc105e10a37baec",
+    # FETCH_SIZE 2.977e7 KiB x 1.99993 (a 2 GiB device copy reads as 1048613.7 KiB)
+    "fetch_bytes_per_launch": 6.096e10,
+    # WRITE_SIZE 7.649e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.832e10,
     "valu_lane_ops_per_push": 1491.2,
-    "ms_per_launch": 89.797,
-    "lds_busy_frac": 0.505,
+    "ms_per_launch": 89.834,
+    "lds_busy_frac": 0.502,
     "lds_bank_conflict_frac": 0.578,
     "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
             "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
