@@ -1093,9 +1093,11 @@ template <int PT, int GD, typename T>
 __global__ __launch_bounds__(256) void k_adjoint_current(AdjointArgs<T> a) {
     adjoint_step_body<T, PT, 5, GD, false, true, 1>(a);
 }
-// The rest: (x, z) grids at two waves per SIMD (FP32); in 3-D the dual-number
-// working set, the 27-point gather gradients and the gather's adjoint need
-// the whole register file (one wave per SIMD; at two it spilled ~500 words).
+// The rest: (x, z) grids at two waves per SIMD (FP32).  In 3-D the
+// dual-number working set and the 27-point gather gradients take 161-203
+// VGPRs in FP32 without the proxy term (two waves); the proxy term, the
+// nonparaxial pulse and FP64 need more (one wave: at two they spilled up to
+// ~1000 words).
 template <int PT, int NT, int GD, bool PX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step_rest(
     AdjointArgs<float> a) {
@@ -1105,9 +1107,15 @@ template <int PT, int NT, int GD, bool PX>
 __global__ __launch_bounds__(256) void k_adjoint_step_rest(AdjointArgs<double> a) {
     adjoint_step_body<double, PT, NT, GD, PX, true, 2>(a);
 }
+// Waves per SIMD of the 3-D pass 2: two where its working set fits 256
+// registers without spills (FP32 without the proxy term, pulses but the
+// nonparaxial one: 161-203 VGPRs), else one.
+template <int PT, bool PX, typename T> struct Rest3Waves {
+    static constexpr int v = (std::is_same<T, float>::value && !PX && PT != PT_NP) ? 2 : 1;
+};
 template <int PT, int NT, bool PX, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_step_rest3(
-    AdjointArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((
+    amdgpu_waves_per_eu(Rest3Waves<PT, PX, T>::v, Rest3Waves<PT, PX, T>::v))) void k_adjoint_step_rest3(AdjointArgs<T> a) {
     adjoint_step_body<T, PT, NT, 3, PX, true, 2>(a);
 }
 
