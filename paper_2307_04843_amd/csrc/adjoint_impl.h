@@ -1078,6 +1078,8 @@ template <int GD> __global__ __launch_bounds__(256) void k_adjoint_gather_scatte
 // spills.  FP64 needs twice the registers and runs best at one wave.  The
 // proxy term (PX) is a kernel of its own: its 12-tangent Jacobian would
 // otherwise raise the register demand of every launch.
+// (3-D with 5 tangents also fits three waves without spills, 158 VGPRs for
+// the flying focus, but ran 57 ms against 47 at two.)
 template <int PT, int NT, int GD, bool PX, bool CPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_step(AdjointArgs<float> a) {
     adjoint_step_body<float, PT, NT, GD, PX, CPL>(a);
@@ -1086,9 +1088,9 @@ template <int PT, int NT, int GD, bool PX, bool CPL>
 __global__ __launch_bounds__(256) void k_adjoint_step(AdjointArgs<double> a) {
     adjoint_step_body<double, PT, NT, GD, PX, CPL>(a);
 }
-// The coupled 3-D step carries the current's and the gather's adjoints as
-// well: one wave per SIMD, so that its working set stays in registers.
-// The coupled reverse step in two launches (see adjoint_step_body's PASS).
+// The coupled 2-D/3-D reverse step in three launches (see adjoint_step_body's
+// PASS): the current's adjoint (159 VGPRs in 3-D FP32, three waves per
+// SIMD), the rest, then k_adjoint_gather_scatter.
 template <int PT, int GD, typename T>
 __global__ __launch_bounds__(256) void k_adjoint_current(AdjointArgs<T> a) {
     adjoint_step_body<T, PT, 5, GD, false, true, 1>(a);
