@@ -1602,6 +1602,82 @@ template <typename T> SpBlock<T> live_block(ap_ctx *c, int i) {
     return b;
 }
 
+// The sort's workspace copy of species i, as a block.
+template <typename T> SpBlock<T> alt_block(ap_ctx *c, int i) {
+    const WorkLayout &L = c->L;
+    SpBlock<T> b{};
+    b.cell = c->wp<int32_t>(L.alt_cell[i]);
+    b.id = c->wp<int32_t>(L.alt_id[i]);
+    for (int a = 0; a < 3; ++a) {
+        b.off[a] = axis_active(c->s.dim, a) ? c->wp<T>(L.alt_off[i][a]) : nullptr;
+        b.u[a] = c->wp<T>(L.alt_u[i][a]);
+    }
+    b.w = c->wp<T>(L.alt_w[i]);
+    b.proxy = c->s.has_proxy[i] ? c->wp<T>(L.alt_proxy[i]) : nullptr;
+    return b;
+}
+
+// Counting sort of species i's records in src by tile into its workspace
+// copy: tile histogram and ranks, exclusive scan into the tile starts
+// (L.start[i]), scatter.  interleave: the within-tile transpose stride (1
+// keeps the order); free_slot: moving-window slot hints to update, or null.
+// src.proxy null leaves the proxies out.
+template <typename T>
+ap_status tile_sort_to_alt(ap_ctx *c, int i, const SpBlock<T> &src, int32_t interleave, int32_t *free_slot) {
+    const RunShape &s = c->s;
+    const WorkLayout &L = c->L;
+    int32_t *count = c->wp<int32_t>(L.count[i]);
+    int32_t *start = c->wp<int32_t>(L.start[i]);
+    int32_t *rank = c->wp<int32_t>(L.rank[i]);
+    HIPCHK(launch_fill_zero<int32_t>(count, (size_t)s.ntiles, c->stream), "sort");
+    SortArgs sa{};
+    sa.cell = src.cell;
+    sa.ncell = (uint32_t)s.ncell;
+    sa.n = (int)s.np[i];
+    sa.dim = s.dim;
+    sa.fnx = FastDiv((uint32_t)s.n[0]);
+    sa.fnxy = FastDiv((uint32_t)(s.n[0] * s.n[1]));
+    sa.ftx = FastDiv((uint32_t)s.tile[0]);
+    sa.fty = FastDiv((uint32_t)s.tile[1]);
+    sa.ftz = FastDiv((uint32_t)s.tile[2]);
+    for (int k = 0; k < 3; ++k) sa.ntile[k] = s.ntile[k];
+    sa.count = count;
+    sa.rank = rank;
+    if (s.np[i] > 0) HIPCHK(launch_tile_count(sa, c->stream), "tile count");
+    HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(L.scan_part), c->stream), "tile scan");
+    const SpBlock<T> dst = alt_block<T>(c, i);
+    ScatterArgs<T> sc{};
+    sc.cell_src = src.cell;
+    sc.cell_dst = dst.cell;
+    for (int k = 0; k < 3; ++k) {
+        sc.off_src[k] = dst.off[k] ? src.off[k] : nullptr;
+        sc.off_dst[k] = dst.off[k];
+        sc.u_src[k] = src.u[k];
+        sc.u_dst[k] = dst.u[k];
+    }
+    sc.w_src = src.w;
+    sc.w_dst = dst.w;
+    sc.id_src = src.id;
+    sc.id_dst = dst.id;
+    sc.free_slot = free_slot;
+    sc.proxy_src = src.proxy && dst.proxy ? src.proxy : nullptr;
+    sc.proxy_dst = src.proxy && dst.proxy ? dst.proxy : nullptr;
+    sc.rank = rank;
+    sc.start = start;
+    sc.ncell = (uint32_t)s.ncell;
+    sc.interleave = interleave;
+    sc.n = (int)s.np[i];
+    sc.dim = s.dim;
+    sc.fnx = sa.fnx;
+    sc.fnxy = sa.fnxy;
+    sc.ftx = sa.ftx;
+    sc.fty = sa.fty;
+    sc.ftz = sa.ftz;
+    for (int k = 0; k < 3; ++k) sc.ntile[k] = s.ntile[k];
+    HIPCHK(launch_scatter<T>(sc, c->stream), "tile scatter");
+    return AP_OK;
+}
+
 template <typename T> ap_status copy_block(ap_ctx *c, const SpBlock<T> &dst, const SpBlock<T> &src, size_t N, bool w) {
     if (N == 0) return AP_OK;
     HIPCHK(hipMemcpyAsync(dst.cell, src.cell, N * 4, hipMemcpyDeviceToDevice, c->stream), "checkpoint copy");
@@ -1890,60 +1966,13 @@ ap_status backward_coupled(ap_ctx *c, int sp, const void *dl_du, const void *dl_
             // id, so the passes may take the particles in any order)
             SpBlock<T> sb = b;
             if (tile_ranges && b.cell != c->wp<int32_t>(c->L.alt_cell[i])) {
-                int32_t *count = c->wp<int32_t>(c->L.count[i]);
-                int32_t *start = c->wp<int32_t>(c->L.start[i]);
-                int32_t *rank = c->wp<int32_t>(c->L.rank[i]);
-                HIPCHK(launch_fill_zero<int32_t>(count, (size_t)s.ntiles, c->stream), "backward");
-                SortArgs sa{};
-                sa.cell = b.cell;
-                sa.ncell = (uint32_t)s.ncell;
-                sa.n = (int)s.np[i];
-                sa.dim = s.dim;
-                sa.fnx = fnx;
-                sa.fnxy = fnxy;
-                sa.ftx = FastDiv((uint32_t)s.tile[0]);
-                sa.fty = FastDiv((uint32_t)s.tile[1]);
-                sa.ftz = FastDiv((uint32_t)s.tile[2]);
-                for (int k = 0; k < 3; ++k) sa.ntile[k] = s.ntile[k];
-                sa.count = count;
-                sa.rank = rank;
-                HIPCHK(launch_tile_count(sa, c->stream), "backward tile count");
-                HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(c->L.scan_part), c->stream),
-                       "backward tile scan");
-                sb.cell = c->wp<int32_t>(c->L.alt_cell[i]);
-                sb.id = c->wp<int32_t>(c->L.alt_id[i]);
-                sb.w = c->wp<T>(c->L.alt_w[i]);
+                SpBlock<T> src = b;
+                src.proxy = nullptr;
+                const ap_status sst = tile_sort_to_alt<T>(c, i, src, 1, nullptr);
+                if (sst != AP_OK) return sst;
+                sb = alt_block<T>(c, i);
                 sb.proxy = nullptr;
-                ScatterArgs<T> sc{};
-                sc.cell_src = b.cell;
-                sc.cell_dst = sb.cell;
-                for (int k = 0; k < 3; ++k) {
-                    const bool act = axis_active(s.dim, k);
-                    sb.off[k] = act ? c->wp<T>(c->L.alt_off[i][k]) : nullptr;
-                    sb.u[k] = c->wp<T>(c->L.alt_u[i][k]);
-                    sc.off_src[k] = act ? b.off[k] : nullptr;
-                    sc.off_dst[k] = sb.off[k];
-                    sc.u_src[k] = b.u[k];
-                    sc.u_dst[k] = sb.u[k];
-                }
-                sc.w_src = b.w;
-                sc.w_dst = sb.w;
-                sc.id_src = b.id;
-                sc.id_dst = sb.id;
-                sc.rank = rank;
-                sc.start = start;
-                sc.ncell = (uint32_t)s.ncell;
-                sc.interleave = 1;
-                sc.n = (int)s.np[i];
-                sc.dim = s.dim;
-                sc.fnx = fnx;
-                sc.fnxy = fnxy;
-                sc.ftx = sa.ftx;
-                sc.fty = sa.fty;
-                sc.ftz = sa.ftz;
-                for (int k = 0; k < 3; ++k) sc.ntile[k] = s.ntile[k];
-                HIPCHK(launch_scatter<T>(sc, c->stream), "backward tile scatter");
-                a.tile_start = start;
+                a.tile_start = c->wp<int32_t>(c->L.start[i]);
                 a.ntile = (int32_t)s.ntiles;
                 for (int k = 0; k < 3; ++k) {
                     a.tile_dim[k] = s.tile[k];
@@ -2254,65 +2283,16 @@ template <typename T> ap_status step_gridded(ap_ctx *c, uint32_t flags) {
         }
         Timer tm(c, 2);
         for (int i = 0; i < s.nsp; ++i) {
-            const ap_particles &p = c->buf.sp[i];
-            int32_t *count = c->wp<int32_t>(L.count[i]);
-            int32_t *start = c->wp<int32_t>(L.start[i]);
-            int32_t *rank = c->wp<int32_t>(L.rank[i]);
-            HIPCHK(launch_fill_zero<int32_t>(count, (size_t)s.ntiles, c->stream), "sort");
-            SortArgs sa{};
-            sa.cell = p.cell;
-            sa.ncell = (uint32_t)s.ncell;
-            sa.n = (int)s.np[i];
-            sa.dim = s.dim;
-            sa.fnx = fnx;
-            sa.fnxy = fnxy;
-            sa.ftx = FastDiv((uint32_t)s.tile[0]);
-            sa.fty = FastDiv((uint32_t)s.tile[1]);
-            sa.ftz = FastDiv((uint32_t)s.tile[2]);
-            for (int k = 0; k < 3; ++k) sa.ntile[k] = s.ntile[k];
-            sa.count = count;
-            sa.rank = rank;
-            if (s.np[i] > 0) HIPCHK(launch_tile_count(sa, c->stream), "tile count");
-            HIPCHK(launch_scan(count, start, (int32_t)s.ntiles, c->wp<int32_t>(L.scan_part), c->stream), "tile scan");
-            ScatterArgs<T> sc{};
-            sc.cell_src = p.cell;
-            sc.cell_dst = c->wp<int32_t>(L.alt_cell[i]);
-            for (int k = 0; k < 3; ++k) {
-                const bool act = axis_active(s.dim, k);
-                sc.off_src[k] = act ? static_cast<const T *>(p.off[k]) : nullptr;
-                sc.off_dst[k] = act ? c->wp<T>(L.alt_off[i][k]) : nullptr;
-                sc.u_src[k] = static_cast<const T *>(p.u[k]);
-                sc.u_dst[k] = c->wp<T>(L.alt_u[i][k]);
-            }
-            sc.w_src = static_cast<const T *>(p.w);
-            sc.w_dst = c->wp<T>(L.alt_w[i]);
-            sc.id_src = p.id;
-            sc.id_dst = c->wp<int32_t>(L.alt_id[i]);
-            sc.free_slot = (s.options & AP_GRID_MOVING_WINDOW) ? c->wp<int32_t>(L.wslot[i]) : nullptr;
-            sc.proxy_src = s.has_proxy[i] ? static_cast<const T *>(p.proxy) : nullptr;
-            sc.proxy_dst = s.has_proxy[i] ? c->wp<T>(L.alt_proxy[i]) : nullptr;
-            sc.rank = rank;
-            sc.start = start;
-            sc.ncell = (uint32_t)s.ncell;
-            {
-                // The first sort starts from the caller's order (typically cell
-                // by cell) and interleaves it; later sorts start from an
-                // interleaved order, which ranks within a tile preserve, so
-                // they keep it (and write their slots contiguously).
-                const double ppc = (double)s.np[i] / (double)s.ncell;
-                int M = (int)std::lround(ppc);
-                M = M < 1 ? 1 : (M > 64 ? 64 : M);
-                sc.interleave = c->sorted_once ? 1 : M;
-            }
-            sc.n = (int)s.np[i];
-            sc.dim = s.dim;
-            sc.fnx = fnx;
-            sc.fnxy = fnxy;
-            sc.ftx = sa.ftx;
-            sc.fty = sa.fty;
-            sc.ftz = sa.ftz;
-            for (int k = 0; k < 3; ++k) sc.ntile[k] = s.ntile[k];
-            HIPCHK(launch_scatter<T>(sc, c->stream), "tile scatter");
+            // The first sort starts from the caller's order (typically cell
+            // by cell) and interleaves it; later sorts start from an
+            // interleaved order, which ranks within a tile preserve, so they
+            // keep it (and write their slots contiguously).
+            const double ppc = (double)s.np[i] / (double)s.ncell;
+            int M = (int)std::lround(ppc);
+            M = M < 1 ? 1 : (M > 64 ? 64 : M);
+            int32_t *free_slot = (s.options & AP_GRID_MOVING_WINDOW) ? c->wp<int32_t>(L.wslot[i]) : nullptr;
+            const ap_status st = tile_sort_to_alt<T>(c, i, live_block<T>(c, i), c->sorted_once ? 1 : M, free_slot);
+            if (st != AP_OK) return st;
         }
         c->sorted_once = true;
         c->need_sort = false;
