@@ -590,14 +590,14 @@ PUSH3D_SOURCES = ("push3d.hip", "push3d_impl.h", "push3d_t844.hip", "kernels.h",
 # VALU lane-ops per push (SQ_INSTS_VALU x 64 / pushes) and the LDS pipe's busy
 # share.  Valid only for the kernel sources whose digest is recorded here.
 MEASURED_TRAFFIC = {
-    "sources_sha256": "1966b3ead5b7618731a292803a82e8611b68b3cf17c0e746bdc105e10a37baec",
-    # FETCH_SIZE 2.977e7 KiB x 1.99993 (a 2 GiB device copy reads as 1048613.7 KiB)
-    "fetch_bytes_per_launch": 6.096e10,
-    # WRITE_SIZE 7.649e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
-    "write_bytes_per_launch": 7.832e10,
+    "sources_sha256": "5ee2c2cd7d37705b160ef32eab7d15f71fdf732db7b92eacf888cf2401ac31e1",
+    # FETCH_SIZE 2.981e7 KiB x 1.99993 (a 2 GiB device copy reads as 1048610.8 KiB)
+    "fetch_bytes_per_launch": 6.104e10,
+    # WRITE_SIZE 7.640e7 KiB x 1.0 (the same copy writes as 2097152 KiB)
+    "write_bytes_per_launch": 7.823e10,
     "valu_lane_ops_per_push": 1491.2,
-    "ms_per_launch": 89.834,
-    "lds_busy_frac": 0.502,
+    "ms_per_launch": 89.871,
+    "lds_busy_frac": 0.503,
     "lds_bank_conflict_frac": 0.578,
     "note": "means over the 55 launches of the window, 2 GiB copy calibration in the same runs "
             "(profiles/push_deposit_3d_gauss_1024x512x512_f32.md)",
