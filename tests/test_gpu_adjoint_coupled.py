@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 N_STEPS = 12
 
 
-def _case(dim):
+def _case(dim, ppc=2):
     if dim == 2:
         return cases.make_case(n=(24, 1, 16), seed=4, u_scale=10.0, ppc=2)
     if dim == 1:
@@ -37,7 +37,7 @@ def _case(dim):
     pp = dict(type="gauss", a0=3.0, tau=20.0, x_ref=box[0] / 2, t_ref=10.0, x_f=box[0] / 2 + 0.3, w0=1.0,
               y_c=box[1] / 2, z_c=box[2] / 2, d_f=3, pol=1, dispersion=units.DISP_PAPER2, dx_prop=dxl,
               dt_prop=dt, dt=dt)
-    return cases.make_case(dim=3, n=n, dxl=dxl, x_min=(0.0, 0.0, 0.0), t0_steps=int(10.0 / dt), ppc=2,
+    return cases.make_case(dim=3, n=n, dxl=dxl, x_min=(0.0, 0.0, 0.0), t0_steps=int(10.0 / dt), ppc=ppc,
                            pulse=pp, u_scale=10.0, seed=23)
 
 
@@ -165,6 +165,29 @@ def test_coupled_tile_blocks_match_slot_blocks(precision):
     assert np.all(np.isfinite(a)) and np.abs(b).max() > 0
     tol = 1e-10 if precision == "f64" else 1e-4
     assert np.all(np.abs(a - b) <= tol * np.linalg.norm(b)), (a, b)
+
+
+@pytest.mark.timeout(600)
+def test_coupled_3d_tile_blocks_match_slot_blocks_and_fp32():
+    """3-D: the gather's adjoint by 8x4x4 tiles against runs of 256 slots
+    (8x8x8 tiles holding more than 2048 particles per species on average)
+    in FP64, 1e-10 of the norm; and the FP32 gradient by tiles (int64
+    fixed-point LDS sums) against the FP64 one, 1e-4 of the norm."""
+    case = _case(3, ppc=10)
+    names = ["a0", "w0", "x_f"]
+    vals = [case["pulse"][k] for k in names]
+    out = {}
+    for prec, tile in (("f64", (8, 4, 4)), ("f64", (8, 8, 8)), ("f32", (8, 4, 4))):
+        print("coupled adjoint 3-D", prec, "tile", tile, flush=True)
+        run = _run(case, names, prec, tile=tile)
+        try:
+            out[(prec, tile)] = _grad(run, vals)[0]
+        finally:
+            run.close()
+    a, b, f = out[("f64", (8, 4, 4))], out[("f64", (8, 8, 8))], out[("f32", (8, 4, 4))]
+    assert np.all(np.isfinite(a)) and np.abs(a).max() > 0
+    assert np.all(np.abs(a - b) <= 1e-10 * np.linalg.norm(a)), (a, b)
+    assert np.all(np.abs(f - a) <= 1e-4 * np.linalg.norm(a)), (f, a)
 
 
 def test_coupled_mode_errors():
