@@ -942,8 +942,14 @@ template <typename T, int GD> AP_D __forceinline__ void adjoint_gather_scatter_b
         // the run's box of cells (256-slot blocks) and (FP32) its largest |value|
         int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
         double m = 0.0;
+        // thread t takes the run's slots t*k .. t*k + k - 1: a wave's lanes
+        // then lie k slots apart, in distinct cells also where the state
+        // holds a cell's particles next to each other (their LDS adds do not
+        // collide), and each thread's reads stay contiguous
+        const int k_per = (c1 - c0 + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int t0 = c0 + (int)threadIdx.x * k_per, t1 = min(t0 + k_per, c1);
         if (!by_tile || std::is_same<T, float>::value) {
-            for (int p = c0 + (int)threadIdx.x; p < c1; p += blockDim.x) {
+            for (int p = t0; p < t1; ++p) {
                 int ic[3];
                 T ov[3];
                 if (!load(p, ic, ov)) continue;
@@ -1011,7 +1017,7 @@ template <typename T, int GD> AP_D __forceinline__ void adjoint_gather_scatter_b
             }
         }
         __syncthreads();
-        for (int p = c0 + (int)threadIdx.x; p < c1; p += blockDim.x) {
+        for (int p = t0; p < t1; ++p) {
             int ic[3];
             T ov[3];
             if (!load(p, ic, ov)) continue;
